@@ -1,0 +1,140 @@
+/*
+ * ldpcci.h -- C ABI of the MI355X (gfx950) dynamic-schedule LDPC belief-propagation decoder.
+ *
+ * The decoder computes, for each frame of channel LLRs, the message-passing schedules of
+ * Chang, Wang, Weng, Lee, Su, "Belief-Propagation Decoding of LDPC Codes with Variable
+ * Node-Centric Dynamic Schedules" (arXiv 2102.11089):
+ *   - residual BP (RBP): Sec. II-A, steps 1)-4), argmax of eq. (5) over all edges;
+ *   - conditional-innovation RBP (CIRBP): Algorithm 1 (Sec. III-B) with the CI metric eq. (9);
+ *   - multi-edge CIRBP (ME-CIRBP): Algorithm 5 with the VN selection of Algorithm 4 (Sec. VI);
+ *   - flooding and layered BP baselines (Sec. I);
+ *   - replay of a recorded edge order (the schedule held fixed).
+ * Messages follow eqs. (1)-(3) (Sec. II-A): V2C, C2V by the tanh rule (sum-product), total LLR
+ * and hard decision bsgn(L) (bit 0 iff L >= 0).  An iteration is E C2V propagations (Sec. II-A),
+ * and `max_updates` always counts C2V propagations.
+ *
+ * Conventions
+ *   - Every function returns 0 on success or a negative LDPC_E* code; nothing is thrown across
+ *     the ABI and nothing is enqueued when an error is returned.  ldpc_strerror() names a code.
+ *   - Device buffers are allocated and owned by the caller (e.g. PyTorch); the library reads
+ *     inputs and writes outputs on the caller's HIP stream (`stream` is a hipStream_t, NULL =
+ *     the default stream).  Calls are enqueue-only: outputs are valid once the stream is
+ *     synchronised.
+ *   - The library owns only ldpc_code handles.  A handle is immutable after creation and may be
+ *     shared by concurrent calls on different streams; decode calls are reentrant.  Scratch
+ *     memory needed by a call is allocated and freed by the library inside the call.
+ *   - Layouts are row-major and frame-contiguous: [B][N] for per-VN arrays, [B][E] for per-edge
+ *     arrays, [B] for per-frame scalars.  Edge ids are canonical: the position of the nonzero
+ *     (m, n) in the row-major (check-major, VN-ascending) enumeration of H.
+ */
+#ifndef LDPCCI_H
+#define LDPCCI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define LDPC_OK 0
+#define LDPC_EINVAL (-1)       /* malformed argument (shape, range, null pointer)            */
+#define LDPC_ENOMEM (-2)       /* host or device allocation failed                            */
+#define LDPC_EHIP (-3)         /* a HIP runtime call failed; see ldpc_last_hip_error()        */
+#define LDPC_ECAPACITY (-4)    /* the frame state does not fit the device's on-chip memory    */
+#define LDPC_EUNSUPPORTED (-5) /* schedule/arithmetic combination or code shape not supported */
+
+/* schedules */
+#define LDPC_FLOODING 0
+#define LDPC_LAYERED 1
+#define LDPC_RBP 2
+#define LDPC_CIRBP 3
+#define LDPC_ME_CIRBP 4
+#define LDPC_REPLAY 5
+
+/* arithmetic */
+#define LDPC_SPA_F32 0  /* sum-product, FP32 messages                                          */
+#define LDPC_MS_FIX 1   /* fixed-point min-sum (Sec. V), q_bits <= 8, frac_bits fractional bits */
+
+/* Algorithm 4 fill of the partially selected CI group */
+#define LDPC_FILL_LOWEST 0 /* lowest VN indices                                                */
+#define LDPC_FILL_HASH 1   /* smallest keys splitmix64(splitmix64(splitmix64(seed^frame)^step)^n) */
+
+typedef struct ldpc_code ldpc_code; /* opaque, library-owned */
+
+typedef struct {
+  int32_t kind;        /* LDPC_FLOODING .. LDPC_REPLAY                                          */
+  int32_t arith;       /* LDPC_SPA_F32 or LDPC_MS_FIX                                            */
+  int32_t q_bits;      /* LDPC_MS_FIX: message width, 2..8 (saturation at +-(2^(q-1)-1))         */
+  int32_t frac_bits;   /* LDPC_MS_FIX: channel quantisation llr * 2^frac_bits, 0..6              */
+  float gamma;         /* CIRBP threshold: fall back to the global residual search if D_{n*} < gamma
+                          (Algorithm 1 line 5); MS_FIX compares D_q with round(gamma * 65534)    */
+  int32_t n_p;         /* ME-CIRBP: VNs updated per step (N_P, Sec. VI), 1..64                   */
+  int32_t n_g;         /* ME-CIRBP: CI groups (N_G, Algorithm 4), 1..65535                       */
+  int32_t fill;        /* ME-CIRBP: LDPC_FILL_LOWEST or LDPC_FILL_HASH                           */
+  uint64_t seed;       /* ME-CIRBP: key of the hashed fill                                       */
+  int64_t check_every; /* syndrome test at t = 0 and whenever t passes a multiple of check_every
+                          (1 = after every update; E = end of each iteration as in Sec. II-A;
+                          0 = never stop early).  Flooding/layered test after every iteration. */
+} ldpc_schedule;
+
+typedef struct {
+  uint8_t* bits;         /* device [B][N], required: hard decisions bsgn(L_n)                    */
+  float* llr_out;        /* device [B][N], nullable: total LLRs L_n (MS_FIX: L_q / 2^frac_bits)  */
+  int64_t* updates_used; /* device [B], required: C2V propagations performed                     */
+  int64_t* steps_used;   /* device [B], nullable: update steps (ME: VN sets; flooding/layered:
+                            iterations; single-edge: = updates)                                  */
+  int64_t* fallbacks;    /* device [B], nullable: CIRBP updates that used the RBP fallback       */
+  int32_t* trace;        /* device [B][max_updates], nullable: edge id of every propagation     */
+  float* dump_c2v;       /* device [B][E], nullable: final C2V messages                          */
+  float* dump_pre;       /* device [B][E], nullable: final precomputed C2V messages (dynamic)    */
+  float* dump_L;         /* device [B][N], nullable: final L (MS_FIX: integer units)             */
+  float* dump_Lt;        /* device [B][N], nullable: final precomputed total LLRs (dynamic)      */
+  float* dump_D;         /* device [B][N], nullable: final CI values (MS_FIX: D_q in [0,65534])  */
+} ldpc_outputs;
+
+typedef struct {
+  int32_t M, N, E;
+  int32_t max_dv, max_dc, n_layers;
+  int32_t max_touch;         /* max over VNs of the summed degrees of its checks               */
+  int64_t lds_bytes_f32;     /* LDS bytes per frame of the single-edge decoder, FP32 mode       */
+  int64_t lds_bytes_fix;     /* same, fixed-point mode                                          */
+} ldpc_code_stats;
+
+/* Create a code handle from H in CSR form (host pointers; Sec. II-A: M x N parity-check matrix,
+   N(m) = row m).  Column indices must be strictly ascending inside each row, every row must have
+   at least 2 entries and every column at least 1.  layer_ptr (nullable) lists n_layers + 1 row
+   offsets of consecutive layers whose rows share no VN (layered baseline); NULL = one row per
+   layer.  The library copies the arrays; the caller keeps ownership of its buffers.
+   Errors: LDPC_EINVAL on a malformed matrix or layer partition, LDPC_ENOMEM, LDPC_EHIP. */
+int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32_t* col_idx,
+                       const int32_t* layer_ptr, int32_t n_layers, ldpc_code** out);
+
+/* Fill *out with the sizes and per-frame on-chip memory needs of a code. */
+int ldpc_code_info(const ldpc_code* code, ldpc_code_stats* out);
+
+/* Release a handle (and its device copy).  NULL is ignored. */
+void ldpc_code_free(ldpc_code* code);
+
+/* Decode B frames of channel LLRs llr_in (device [B][N], FP32: 2 y_n / sigma^2, Sec. II-A).
+   replay (device [B][replay_len] edge ids, nullable) is used by LDPC_REPLAY only: update t
+   propagates edge replay[f][t], with no selection and no early stop, for min(max_updates,
+   replay_len) updates; an id outside [0, E) ends that frame early (updates_used tells where).
+   Outputs as described in ldpc_outputs.
+   Errors: LDPC_EINVAL (null required pointer, B < 0, max_updates < 0, bad schedule field),
+   LDPC_EUNSUPPORTED (combination not implemented, a VN of degree > 63), LDPC_ECAPACITY (frame
+   state exceeds on-chip memory), LDPC_EHIP (launch failure). */
+int ldpc_decode(const ldpc_code* code, const ldpc_schedule* schedule, const float* llr_in, int32_t B,
+                int64_t max_updates, const int32_t* replay, int64_t replay_len,
+                const ldpc_outputs* out, void* stream);
+
+/* Human-readable name of an error code (static string). */
+const char* ldpc_strerror(int code);
+
+/* The last hipError_t recorded by a failing call on this thread (0 if none). */
+int ldpc_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDPCCI_H */

@@ -348,6 +348,7 @@ uint64_t oc_fill_key(uint64_t seed, uint64_t frame, uint64_t step, uint64_t n) {
    Fills sel[] in ascending VN order and returns |P|. */
 int32_t oc_alg4_select_keyed(int32_t N, const int32_t *bins, int32_t ng, int32_t np,
                              const uint64_t *keys, int32_t *sel) {
+  if (N <= 0 || ng <= 0) return 0;
   int32_t *count = (int32_t *)calloc((size_t)ng, sizeof(int32_t));
   for (int32_t n = 0; n < N; ++n) count[bins[n]] += 1;
   int32_t kstar = 0, q = 0;

@@ -1,0 +1,375 @@
+// Host runtime behind include/ldpcci.h: argument validation, code upload, LDS layout and
+// kernel selection.  Every step of decoding runs in the HIP kernels; this file only prepares
+// their parameters and launches them on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/ldpcci.h"
+#include "kernels.hpp"
+
+using namespace ldpc;
+
+struct ldpc_code {
+  int device;
+  int M, N, E;
+  int max_dv, max_dc, max_touch, n_layers, max_layer_edges;
+  std::vector<int> h_row_ptr, h_col, h_layer_ptr;
+  int* d_buf;       // one device allocation holding every index array
+  int* d_lut;       // 7 p0 tables (frac_bits 0..6), 257 entries each
+  DevCode dev;
+};
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return LDPC_EHIP;
+}
+
+int align16(int x) { return (x + 15) & ~15; }
+
+int device_lds_limit(int dev) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+  }
+  return v;
+}
+
+int device_cu_count(int dev) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+  return v;
+}
+
+double round_half_away(double x) { return x < 0 ? -std::floor(-x + 0.5) : std::floor(x + 0.5); }
+
+// LDS layout of the single-edge / multi-edge dynamic decoders
+struct DynLayout {
+  int off_c2v, off_pre, off_L, off_Lt, off_D, off_ckey, off_dblk, off_cblk, off_dmask, off_cmask, off_syn;
+  int off_v, off_kbuf, off_slot, off_trow, off_lut, off_extra, total;
+  int nbd, nbc, nbd_words, nbc_words;
+};
+
+DynLayout dyn_layout(const ldpc_code* c, bool fixed, bool pre_global, int extra_bytes) {
+  DynLayout L{};
+  const int msg = fixed ? 1 : 4, llr = 4, val = 4;
+  L.nbd = (c->N + WAVE - 1) / WAVE;
+  L.nbc = (c->M + WAVE - 1) / WAVE;
+  L.nbd_words = (L.nbd + 31) / 32;
+  L.nbc_words = (L.nbc + 31) / 32;
+  int o = 0;
+  L.off_c2v = o; o = align16(o + c->E * msg);
+  L.off_pre = o; if (!pre_global) o = align16(o + c->E * msg);
+  L.off_L = o; o = align16(o + c->N * llr);
+  L.off_Lt = o; o = align16(o + c->N * llr);
+  L.off_D = o; o = align16(o + c->N * 4);
+  L.off_ckey = o; o = align16(o + c->M * 8);
+  L.off_dblk = o; o = align16(o + L.nbd * 8);
+  L.off_cblk = o; o = align16(o + L.nbc * 8);
+  L.off_dmask = o; o = align16(o + L.nbd_words * 4);
+  L.off_cmask = o; o = align16(o + L.nbc_words * 4);
+  L.off_syn = o; o = align16(o + c->M);
+  L.off_v = o; o = align16(o + c->max_touch * val);
+  L.off_kbuf = o; o = align16(o + c->max_touch * 8);
+  L.off_slot = o; o = align16(o + c->max_touch);
+  L.off_trow = o; o = align16(o + 3 * WAVE * 4);
+  L.off_lut = o; if (fixed) o = align16(o + 257 * 4);
+  L.off_extra = o; o = align16(o + extra_bytes);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ldpc_strerror(int code) {
+  switch (code) {
+    case LDPC_OK: return "ok";
+    case LDPC_EINVAL: return "invalid argument";
+    case LDPC_ENOMEM: return "out of memory";
+    case LDPC_EHIP: return "HIP runtime error";
+    case LDPC_ECAPACITY: return "frame state exceeds on-chip memory";
+    case LDPC_EUNSUPPORTED: return "unsupported schedule, arithmetic or code shape";
+    default: return "unknown error";
+  }
+}
+
+int ldpc_last_hip_error(void) { return g_last_hip; }
+
+int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32_t* col_idx,
+                       const int32_t* layer_ptr, int32_t n_layers, ldpc_code** out) {
+  if (!out) return LDPC_EINVAL;
+  *out = nullptr;
+  if (M <= 0 || N <= 0 || !row_ptr || !col_idx) return LDPC_EINVAL;
+  if (row_ptr[0] != 0) return LDPC_EINVAL;
+  for (int m = 0; m < M; ++m)
+    if (row_ptr[m + 1] - row_ptr[m] < 2) return LDPC_EINVAL;
+  const long long E64 = row_ptr[M];
+  if (E64 <= 0 || E64 > (1 << 28)) return LDPC_EINVAL;
+  const int E = (int)E64;
+  std::vector<int> vdeg(N, 0);
+  for (int m = 0; m < M; ++m) {
+    for (int e = row_ptr[m]; e < row_ptr[m + 1]; ++e) {
+      int n = col_idx[e];
+      if (n < 0 || n >= N) return LDPC_EINVAL;
+      if (e > row_ptr[m] && col_idx[e - 1] >= n) return LDPC_EINVAL;
+      vdeg[n] += 1;
+    }
+  }
+  for (int n = 0; n < N; ++n)
+    if (vdeg[n] < 1) return LDPC_EINVAL;
+  std::vector<int> lp;
+  if (layer_ptr) {
+    if (n_layers < 1 || layer_ptr[0] != 0 || layer_ptr[n_layers] != M) return LDPC_EINVAL;
+    std::vector<int> mark(N, -1);
+    for (int l = 0; l < n_layers; ++l) {
+      if (layer_ptr[l + 1] <= layer_ptr[l]) return LDPC_EINVAL;
+      for (int e = row_ptr[layer_ptr[l]]; e < row_ptr[layer_ptr[l + 1]]; ++e) {
+        if (mark[col_idx[e]] == l) return LDPC_EINVAL;  // two rows of one layer share a VN
+        mark[col_idx[e]] = l;
+      }
+    }
+    lp.assign(layer_ptr, layer_ptr + n_layers + 1);
+  } else {
+    lp.resize(M + 1);
+    for (int m = 0; m <= M; ++m) lp[m] = m;
+  }
+  ldpc_code* c = new (std::nothrow) ldpc_code();
+  if (!c) return LDPC_ENOMEM;
+  c->M = M;
+  c->N = N;
+  c->E = E;
+  c->n_layers = (int)lp.size() - 1;
+  c->h_row_ptr.assign(row_ptr, row_ptr + M + 1);
+  c->h_col.assign(col_idx, col_idx + E);
+  c->h_layer_ptr = lp;
+  // derived host arrays: row of edge, CSC (checks ascending inside a column)
+  std::vector<int> row_of(E), col_ptr(N + 1, 0), col_row(E), col_eid(E);
+  for (int m = 0; m < M; ++m)
+    for (int e = row_ptr[m]; e < row_ptr[m + 1]; ++e) row_of[e] = m;
+  for (int n = 0; n < N; ++n) col_ptr[n + 1] = col_ptr[n] + vdeg[n];
+  std::vector<int> fill(col_ptr.begin(), col_ptr.end() - 1);
+  for (int e = 0; e < E; ++e) {  // row-major traversal keeps checks ascending per column
+    int n = col_idx[e];
+    col_row[fill[n]] = row_of[e];
+    col_eid[fill[n]] = e;
+    fill[n] += 1;
+  }
+  c->max_dv = *std::max_element(vdeg.begin(), vdeg.end());
+  c->max_dc = 0;
+  for (int m = 0; m < M; ++m) c->max_dc = std::max(c->max_dc, row_ptr[m + 1] - row_ptr[m]);
+  c->max_touch = 0;
+  for (int n = 0; n < N; ++n) {
+    int s = 0;
+    for (int k = col_ptr[n]; k < col_ptr[n + 1]; ++k) s += row_ptr[col_row[k] + 1] - row_ptr[col_row[k]];
+    c->max_touch = std::max(c->max_touch, s);
+  }
+  c->max_layer_edges = 0;
+  for (int l = 0; l < c->n_layers; ++l)
+    c->max_layer_edges = std::max(c->max_layer_edges, row_ptr[lp[l + 1]] - row_ptr[lp[l]]);
+  // one device buffer: row_ptr, col, row_of, col_ptr, col_row, col_eid, layer_ptr, 7 LUTs
+  std::vector<int> blob;
+  auto put = [&](const std::vector<int>& v) {
+    size_t o = blob.size();
+    blob.insert(blob.end(), v.begin(), v.end());
+    while (blob.size() % 4) blob.push_back(0);
+    return o;
+  };
+  size_t o_rp = put(c->h_row_ptr), o_col = put(c->h_col), o_ro = put(row_of), o_cp = put(col_ptr);
+  size_t o_cr = put(col_row), o_ce = put(col_eid), o_lp = put(lp);
+  std::vector<int> luts(7 * 257);
+  for (int f = 0; f <= 6; ++f)
+    for (int x = -128; x <= 128; ++x)
+      luts[f * 257 + x + 128] = (int)round_half_away(32767.0 * std::tanh(0.5 * std::ldexp((double)x, -f)));
+  size_t o_lut = put(luts);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return LDPC_EHIP;
+  }
+  hipError_t he = hipMalloc((void**)&c->d_buf, blob.size() * sizeof(int));
+  if (he != hipSuccess) {
+    delete c;
+    g_last_hip = (int)he;
+    return he == hipErrorOutOfMemory ? LDPC_ENOMEM : LDPC_EHIP;
+  }
+  he = hipMemcpy(c->d_buf, blob.data(), blob.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    (void)hipFree(c->d_buf);
+    delete c;
+    return hip_fail(he);
+  }
+  DevCode& d = c->dev;
+  d.M = M;
+  d.N = N;
+  d.E = E;
+  d.max_dc = c->max_dc;
+  d.max_dv = c->max_dv;
+  d.max_touch = c->max_touch;
+  d.n_layers = c->n_layers;
+  d.row_ptr = c->d_buf + o_rp;
+  d.col = c->d_buf + o_col;
+  d.row_of = c->d_buf + o_ro;
+  d.col_ptr = c->d_buf + o_cp;
+  d.col_row = c->d_buf + o_cr;
+  d.col_eid = c->d_buf + o_ce;
+  d.layer_ptr = c->d_buf + o_lp;
+  c->d_lut = c->d_buf + o_lut;
+  *out = c;
+  return LDPC_OK;
+}
+
+int ldpc_code_info(const ldpc_code* c, ldpc_code_stats* out) {
+  if (!c || !out) return LDPC_EINVAL;
+  out->M = c->M;
+  out->N = c->N;
+  out->E = c->E;
+  out->max_dv = c->max_dv;
+  out->max_dc = c->max_dc;
+  out->n_layers = c->n_layers;
+  out->max_touch = c->max_touch;
+  out->lds_bytes_f32 = dyn_layout(c, false, false, 0).total;
+  out->lds_bytes_fix = dyn_layout(c, true, false, 0).total;
+  return LDPC_OK;
+}
+
+void ldpc_code_free(ldpc_code* c) {
+  if (!c) return;
+  if (c->d_buf) (void)hipFree(c->d_buf);
+  delete c;
+}
+
+int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B, int64_t max_updates,
+                const int32_t* replay, int64_t replay_len, const ldpc_outputs* out, void* stream) {
+  if (!c || !s || !out || B < 0 || max_updates < 0) return LDPC_EINVAL;
+  if (B == 0) return LDPC_OK;
+  if (!llr_in || !out->bits || !out->updates_used) return LDPC_EINVAL;
+  if (s->kind < LDPC_FLOODING || s->kind > LDPC_REPLAY) return LDPC_EINVAL;
+  if (s->arith != LDPC_SPA_F32 && s->arith != LDPC_MS_FIX) return LDPC_EINVAL;
+  const bool fixed = s->arith == LDPC_MS_FIX;
+  if (fixed && (s->q_bits < 2 || s->q_bits > 8 || s->frac_bits < 0 || s->frac_bits > 6)) return LDPC_EINVAL;
+  if (s->check_every < 0) return LDPC_EINVAL;
+  if (!(s->gamma >= 0.0f) || !std::isfinite(s->gamma)) return LDPC_EINVAL;
+  if (s->kind == LDPC_REPLAY && (!replay || replay_len < 0)) return LDPC_EINVAL;
+  if (s->kind == LDPC_ME_CIRBP && (s->n_p < 1 || s->n_p > 64 || s->n_g < 1 || s->n_g > 65535 ||
+                                   (s->fill != LDPC_FILL_LOWEST && s->fill != LDPC_FILL_HASH)))
+    return LDPC_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LDPC_EHIP;
+  if (dev != c->device) return LDPC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
+  const int ncu = device_cu_count(dev);
+  const int qmax = (1 << (std::max(s->q_bits, 2) - 1)) - 1;
+  const float scale = std::ldexp(1.0f, fixed ? s->frac_bits : 0);
+
+  DecOut o;
+  o.bits = out->bits;
+  o.llr_out = out->llr_out;
+  o.updates_used = out->updates_used;
+  o.steps_used = out->steps_used;
+  o.fallbacks = out->fallbacks;
+  o.trace = out->trace;
+  o.dump_c2v = out->dump_c2v;
+  o.dump_pre = out->dump_pre;
+  o.dump_L = out->dump_L;
+  o.dump_Lt = out->dump_Lt;
+  o.dump_D = out->dump_D;
+
+  if (s->kind == LDPC_FLOODING || s->kind == LDPC_LAYERED) {
+    BaseParams P{};
+    P.kind = s->kind;
+    P.B = B;
+    P.max_updates = max_updates;
+    P.check_every = s->check_every;
+    P.llr = llr_in;
+    P.out = o;
+    P.qmax = qmax;
+    P.scale = scale;
+    const int msg = fixed ? 1 : 4;
+    const int vbuf_n = s->kind == LDPC_FLOODING ? c->E : c->max_layer_edges;
+    int off = 0;
+    P.off_c2v = off; off = align16(off + c->E * msg);
+    P.off_L = off; off = align16(off + c->N * 4);
+    P.off_ch = off; off = align16(off + vbuf_n * 4);
+    P.off_syn = off; off = align16(off + ((c->M + 31) / 32) * 4);
+    P.off_misc = off; off = align16(off + 16);
+    P.lds_bytes = off;
+    if (P.lds_bytes > lds_limit) return LDPC_ECAPACITY;
+    hipError_t he = set_baseline_lds_limit(lds_limit);
+    if (he != hipSuccess) return hip_fail(he);
+    int work = s->kind == LDPC_FLOODING ? c->E : c->max_layer_edges;
+    int block = work >= 4096 ? 1024 : (work >= 1024 ? 256 : (work >= 256 ? 128 : 64));
+    he = launch_baseline(c->dev, P, fixed, B, block, st);
+    return he == hipSuccess ? LDPC_OK : hip_fail(he);
+  }
+
+  if (c->max_dv > WAVE - 1) return LDPC_EUNSUPPORTED;
+  if (c->max_touch > 255 * 64) return LDPC_EUNSUPPORTED;
+
+  DynParams P{};
+  P.kind = s->kind;
+  P.B = B;
+  P.max_updates = max_updates;
+  P.check_every = s->check_every;
+  P.llr = llr_in;
+  P.replay = replay;
+  P.replay_len = replay_len;
+  P.out = o;
+  P.qmax = qmax;
+  P.scale = scale;
+  P.lut_global = c->d_lut + 257 * (fixed ? s->frac_bits : 0);
+  P.n_p = s->n_p;
+  P.n_g = s->n_g;
+  P.fill = s->fill;
+  P.seed = s->seed;
+  if (fixed) {
+    double g = round_half_away((double)s->gamma * 65534.0);
+    P.gamma_bits = (uint32_t)std::min(g, 4294967295.0);
+  } else {
+    float g = s->gamma;
+    std::memcpy(&P.gamma_bits, &g, 4);
+  }
+  if (s->kind == LDPC_ME_CIRBP) return LDPC_EUNSUPPORTED;
+
+  bool pre_global = false;
+  DynLayout Ly = dyn_layout(c, fixed, false, 0);
+  if (Ly.total > lds_limit) {
+    pre_global = true;
+    Ly = dyn_layout(c, fixed, true, 0);
+    if (Ly.total > lds_limit) return LDPC_ECAPACITY;
+  }
+  P.off_c2v = Ly.off_c2v; P.off_pre = Ly.off_pre; P.off_L = Ly.off_L; P.off_Lt = Ly.off_Lt;
+  P.off_D = Ly.off_D; P.off_ckey = Ly.off_ckey; P.off_dblk = Ly.off_dblk; P.off_cblk = Ly.off_cblk;
+  P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
+  P.off_kbuf = Ly.off_kbuf; P.off_slot = Ly.off_slot; P.off_trow = Ly.off_trow; P.off_lut = Ly.off_lut;
+  P.off_extra = Ly.off_extra;
+  P.lds_bytes = Ly.total;
+  P.nbd = Ly.nbd; P.nbc = Ly.nbc; P.nbd_words = Ly.nbd_words; P.nbc_words = Ly.nbc_words;
+
+  hipError_t he = set_dynamic_lds_limit(lds_limit);
+  if (he != hipSuccess) return hip_fail(he);
+  int grid = B;
+  void* scratch = nullptr;
+  if (pre_global) {
+    const int per_cu = std::max(1, (160 * 1024) / std::max(P.lds_bytes, 1));
+    grid = std::min<long long>(B, (long long)ncu * per_cu);
+    he = hipMallocAsync(&scratch, (size_t)grid * c->E * (fixed ? 1 : 4), st);
+    if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
+    P.pre_global = scratch;
+  }
+  he = launch_dynamic(c->dev, P, fixed, pre_global, grid, st);
+  if (scratch) (void)hipFreeAsync(scratch, st);
+  return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+"""Python binding of the C ABI in ``include/ldpcci.h`` (ctypes; argument marshalling only).
+
+The functions ``ldpc_code_from_csr``, ``ldpc_code_info``, ``ldpc_code_free``, ``ldpc_decode`` and
+``ldpc_strerror`` mirror the C entry points one to one.  PyTorch supplies device memory and the
+stream; every decoding step runs in the HIP kernels of ``libldpcci.so``.  There is no fallback:
+if the library is missing or no GPU is present, loading raises.
+
+``decode`` is a convenience wrapper that allocates the output tensors and returns them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libldpcci.so")
+
+# schedules / arithmetic / fill (values of include/ldpcci.h)
+FLOODING, LAYERED, RBP, CIRBP, ME_CIRBP, REPLAY = range(6)
+SPA_F32, MS_FIX = 0, 1
+FILL_LOWEST, FILL_HASH = 0, 1
+ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -4: "LDPC_ECAPACITY",
+          -5: "LDPC_EUNSUPPORTED"}
+
+EXPORTS = ("ldpc_code_from_csr", "ldpc_code_info", "ldpc_code_free", "ldpc_decode", "ldpc_strerror",
+           "ldpc_last_hip_error")
+
+
+class ldpc_schedule(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("arith", C.c_int32), ("q_bits", C.c_int32), ("frac_bits", C.c_int32),
+                ("gamma", C.c_float), ("n_p", C.c_int32), ("n_g", C.c_int32), ("fill", C.c_int32),
+                ("seed", C.c_uint64), ("check_every", C.c_int64)]
+
+
+class ldpc_outputs(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in
+                ("bits", "llr_out", "updates_used", "steps_used", "fallbacks", "trace", "dump_c2v",
+                 "dump_pre", "dump_L", "dump_Lt", "dump_D")]
+
+
+class ldpc_code_stats(C.Structure):
+    _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("E", C.c_int32), ("max_dv", C.c_int32),
+                ("max_dc", C.c_int32), ("n_layers", C.c_int32), ("max_touch", C.c_int32),
+                ("lds_bytes_f32", C.c_int64), ("lds_bytes_fix", C.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libldpcci.so (built by ``paper_2102_11089_amd.build``); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing: run `python -m paper_2102_11089_amd.build`")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.ldpc_code_from_csr.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_int32, C.POINTER(C.c_void_p)]
+    lib.ldpc_code_from_csr.restype = C.c_int
+    lib.ldpc_code_info.argtypes = [P, C.POINTER(ldpc_code_stats)]
+    lib.ldpc_code_info.restype = C.c_int
+    lib.ldpc_code_free.argtypes = [P]
+    lib.ldpc_code_free.restype = None
+    lib.ldpc_decode.argtypes = [P, C.POINTER(ldpc_schedule), P, C.c_int32, C.c_int64, P, C.c_int64,
+                                C.POINTER(ldpc_outputs), P]
+    lib.ldpc_decode.restype = C.c_int
+    lib.ldpc_strerror.argtypes = [C.c_int]
+    lib.ldpc_strerror.restype = C.c_char_p
+    lib.ldpc_last_hip_error.argtypes = []
+    lib.ldpc_last_hip_error.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def ldpc_strerror(rc: int) -> str:
+    return load().ldpc_strerror(rc).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"{what}: {ERRORS.get(rc, rc)} ({ldpc_strerror(rc)}), hip={load().ldpc_last_hip_error()}")
+
+
+def ldpc_code_from_csr(M: int, N: int, row_ptr: np.ndarray, col_idx: np.ndarray,
+                       layer_ptr: Optional[np.ndarray] = None) -> int:
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    lp = None if layer_ptr is None else np.ascontiguousarray(layer_ptr, dtype=np.int32)
+    h = C.c_void_p()
+    rc = load().ldpc_code_from_csr(M, N, rp.ctypes.data, ci.ctypes.data, None if lp is None else lp.ctypes.data,
+                                   0 if lp is None else len(lp) - 1, C.byref(h))
+    _check(rc, "ldpc_code_from_csr")
+    return h.value
+
+
+def ldpc_code_info(handle: int) -> ldpc_code_stats:
+    st = ldpc_code_stats()
+    _check(load().ldpc_code_info(handle, C.byref(st)), "ldpc_code_info")
+    return st
+
+
+def ldpc_code_free(handle: int) -> None:
+    load().ldpc_code_free(handle)
+
+
+def ldpc_decode(handle: int, schedule: ldpc_schedule, llr_ptr: int, B: int, max_updates: int,
+                replay_ptr: Optional[int], replay_len: int, outputs: ldpc_outputs, stream: int) -> None:
+    rc = load().ldpc_decode(handle, C.byref(schedule), llr_ptr, B, max_updates, replay_ptr, replay_len,
+                            C.byref(outputs), stream)
+    _check(rc, "ldpc_decode")
+
+
+# ----------------------------------------------------------------------------------------------
+# convenience layer over torch tensors
+# ----------------------------------------------------------------------------------------------
+class Code:
+    """Owns a library code handle built from a ``synth.Code`` (or any object with M, N, row_ptr,
+    col and optional layer_ptr)."""
+
+    def __init__(self, code):
+        self.M, self.N, self.E = int(code.M), int(code.N), int(code.row_ptr[-1])
+        self.handle = ldpc_code_from_csr(self.M, self.N, code.row_ptr, code.col, getattr(code, "layer_ptr", None))
+        self.stats = ldpc_code_info(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            ldpc_code_free(h)
+            self.handle = None
+
+
+@dataclass
+class Decoded:
+    bits: "object"
+    llr_out: "object"
+    updates_used: "object"
+    steps_used: "object"
+    fallbacks: "object"
+    trace: Optional[object] = None
+    c2v: Optional[object] = None
+    pre: Optional[object] = None
+    L: Optional[object] = None
+    Lt: Optional[object] = None
+    D: Optional[object] = None
+
+
+def schedule(kind: int, arith: int = SPA_F32, gamma: float = 0.1, q_bits: int = 6, frac_bits: int = 1,
+             n_p: int = 1, n_g: int = 16, fill: int = FILL_LOWEST, seed: int = 0, check_every: int = 1):
+    return ldpc_schedule(kind, arith, q_bits, frac_bits, gamma, n_p, n_g, fill, seed & (2**64 - 1), check_every)
+
+
+def decode(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int = 0, gamma: float = 0.1,
+           q_bits: int = 6, frac_bits: int = 1, n_p: int = 1, n_g: int = 16, fill: int = FILL_LOWEST,
+           seed: int = 0, check_every: int = 1, replay=None, trace: bool = False, dump: bool = False,
+           stream=None) -> Decoded:
+    """Decode a (B, N) float32 CUDA tensor of channel LLRs; returns device tensors."""
+    import torch
+    assert llr.is_cuda and llr.dtype == torch.float32 and llr.dim() == 2 and llr.shape[1] == code.N
+    llr = llr.contiguous()
+    B = llr.shape[0]
+    dev = llr.device
+    bits = torch.empty((B, code.N), dtype=torch.uint8, device=dev)
+    llr_out = torch.empty((B, code.N), dtype=torch.float32, device=dev)
+    upd = torch.empty(B, dtype=torch.int64, device=dev)
+    steps = torch.empty(B, dtype=torch.int64, device=dev)
+    fall = torch.empty(B, dtype=torch.int64, device=dev)
+    tr = torch.full((B, max(max_updates, 1)), -1, dtype=torch.int32, device=dev) if trace else None
+    d = {}
+    if dump:
+        d = dict(c2v=torch.zeros((B, code.E), device=dev), pre=torch.zeros((B, code.E), device=dev),
+                 L=torch.zeros((B, code.N), device=dev), Lt=torch.zeros((B, code.N), device=dev),
+                 D=torch.zeros((B, code.N), device=dev))
+    rep = None
+    rep_len = 0
+    if replay is not None:
+        rep = replay.to(device=dev, dtype=torch.int32).contiguous()
+        rep_len = rep.shape[1]
+    ptr = lambda t: None if t is None else t.data_ptr()
+    outs = ldpc_outputs(ptr(bits), ptr(llr_out), ptr(upd), ptr(steps), ptr(fall), ptr(tr), ptr(d.get("c2v")),
+                        ptr(d.get("pre")), ptr(d.get("L")), ptr(d.get("Lt")), ptr(d.get("D")))
+    s = schedule(kind, arith, gamma, q_bits, frac_bits, n_p, n_g, fill, seed, check_every)
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    ldpc_decode(code.handle, s, llr.data_ptr(), B, max_updates, ptr(rep), rep_len, outs, st)
+    return Decoded(bits, llr_out, upd, steps, fall, tr, d.get("c2v"), d.get("pre"), d.get("L"), d.get("Lt"),
+                   d.get("D"))

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every function the
+header declares, and rejects malformed input before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2102_11089_amd import ldpc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ldpcci.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ldpc_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ldpc.load()
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(ldpc.EXPORTS)
+
+
+def test_header_constants_match_binding():
+    src = open(HEADER).read()
+    consts = dict(re.findall(r"#define (LDPC_[A-Z_0-9]+) \(?(-?\d+)\)?", src))
+    assert int(consts["LDPC_FLOODING"]) == ldpc.FLOODING
+    assert int(consts["LDPC_LAYERED"]) == ldpc.LAYERED
+    assert int(consts["LDPC_RBP"]) == ldpc.RBP
+    assert int(consts["LDPC_CIRBP"]) == ldpc.CIRBP
+    assert int(consts["LDPC_ME_CIRBP"]) == ldpc.ME_CIRBP
+    assert int(consts["LDPC_REPLAY"]) == ldpc.REPLAY
+    assert int(consts["LDPC_SPA_F32"]) == ldpc.SPA_F32
+    assert int(consts["LDPC_MS_FIX"]) == ldpc.MS_FIX
+    for k, v in ldpc.ERRORS.items():
+        assert int(consts[v]) == k
+
+
+def test_struct_sizes():
+    assert C.sizeof(ldpc.ldpc_schedule) == 48
+    assert C.sizeof(ldpc.ldpc_outputs) == 11 * 8
+
+
+def test_strerror():
+    for rc in ldpc.ERRORS:
+        assert isinstance(ldpc.ldpc_strerror(rc), str) and ldpc.ldpc_strerror(rc)
+
+
+@pytest.mark.parametrize("case", ["unsorted", "dup", "range", "short_row", "empty_col", "layer_overlap"])
+def test_code_validation_rejects_malformed(case):
+    rp = np.array([0, 3, 6], dtype=np.int32)
+    col = np.array([0, 1, 2, 1, 2, 3], dtype=np.int32)
+    lp = None
+    M, N = 2, 4
+    if case == "unsorted":
+        col = np.array([1, 0, 2, 1, 2, 3], dtype=np.int32)
+    elif case == "dup":
+        col = np.array([0, 1, 1, 1, 2, 3], dtype=np.int32)
+    elif case == "range":
+        col = np.array([0, 1, 2, 1, 2, 4], dtype=np.int32)
+    elif case == "short_row":
+        rp = np.array([0, 1, 6], dtype=np.int32)
+    elif case == "empty_col":
+        N = 5
+    elif case == "layer_overlap":
+        lp = np.array([0, 2], dtype=np.int32)
+    with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+        ldpc.ldpc_code_from_csr(M, N, rp, col, lp)
+
+
+def test_decode_rejects_null_arguments():
+    lib = ldpc.load()
+    s = ldpc.schedule(ldpc.CIRBP)
+    out = ldpc.ldpc_outputs()
+    assert lib.ldpc_decode(None, C.byref(s), None, 1, 10, None, 0, C.byref(out), None) == -1

@@ -1,0 +1,231 @@
+"""GPU parity: the HIP decoder (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+* fixed-point min-sum: bit-exact (decoded bits, recorded schedule, updates used, fallbacks, and the
+  final c2v / pre / L / Lt / D state);
+* FP32 sum-product: replay of the oracle's recorded schedule, every message within
+  |gpu - oracle| <= 1e-4 max(|oracle|, 1) (CI within 1e-4 absolute), and free-running frame
+  error rates within the oracle's 95% Clopper-Pearson interval.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy.stats import beta
+
+from oracle import oracle as O
+from paper_2102_11089_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"flooding": (O.FLOODING, 0), "layered": (O.LAYERED, 1), "rbp": (O.RBP, 2), "cirbp": (O.CIRBP, 3),
+        "me": (O.MECIRBP, 4), "replay": (O.REPLAY, 5)}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gpu_decode(ldpc, code_h, llr, kind, arith, **kw):
+    t = torch.from_numpy(np.ascontiguousarray(llr, dtype=np.float32)).cuda()
+    r = ldpc.decode(code_h, t, KIND[kind][1], arith, **kw)
+    torch.cuda.synchronize()
+    return r
+
+
+def np_(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def cp_interval(k, n, a=0.05):
+    lo = 0.0 if k == 0 else beta.ppf(a / 2, k, n - k + 1)
+    hi = 1.0 if k == n else beta.ppf(1 - a / 2, k + 1, n - k)
+    return lo, hi
+
+
+@pytest.fixture(scope="module")
+def c0(gpu):
+    code = S.workload_code("c0")
+    return code, gpu.Code(code)
+
+
+# ------------------------------------------------------------------------------------------
+# fixed point: bit-exact
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["rbp", "cirbp"])
+def test_fixed_dynamic_bit_exact_c0(gpu, c0, kind):
+    code, ch = c0
+    cw, llr = S.frames(code, 1000, 2.0, 100)
+    mu = 2400
+    say(f"[fixed {kind}] c0 1000 frames, cap {mu}")
+    ref = O.decode(code, llr, KIND[kind][0], O.MSFIX, max_updates=mu, gamma=0.1, q_bits=6, frac_bits=1,
+                   trace=True, dump=True, threads=8)
+    g = gpu_decode(gpu, ch, llr, kind, gpu.MS_FIX, max_updates=mu, gamma=0.1, q_bits=6, frac_bits=1,
+                   trace=True, dump=True)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+    np.testing.assert_array_equal(np_(g.llr_out), ref.llr_out.astype(np.float32))
+    np.testing.assert_array_equal(np_(g.c2v), ref.c2v)
+    np.testing.assert_array_equal(np_(g.pre), ref.pre)
+    np.testing.assert_array_equal(np_(g.L), ref.L)
+    if kind == "cirbp":
+        np.testing.assert_array_equal(np_(g.Lt), ref.Lt)
+        np.testing.assert_array_equal(np_(g.D), ref.D)
+        np.testing.assert_array_equal(np_(g.fallbacks), ref.counter("fallback"))
+
+
+@pytest.mark.parametrize("kind", ["flooding", "layered"])
+def test_fixed_baselines_bit_exact_c0(gpu, c0, kind):
+    code, ch = c0
+    cw, llr = S.frames(code, 1000, 2.0, 101)
+    mu = 50 * code.E
+    say(f"[fixed {kind}] c0 1000 frames")
+    ref = O.decode(code, llr, KIND[kind][0], O.MSFIX, max_updates=mu, q_bits=6, frac_bits=1, threads=8)
+    g = gpu_decode(gpu, ch, llr, kind, gpu.MS_FIX, max_updates=mu, q_bits=6, frac_bits=1)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+    np.testing.assert_array_equal(np_(g.llr_out), ref.llr_out.astype(np.float32))
+
+
+def test_fixed_tie_heavy_inputs(gpu):
+    """Many exact ties: integer channel values from a tiny alphabet, exact zeros included; ragged
+    code size (N = 200: four VN blocks, the last one partial)."""
+    code = S.peg_regular(200, 3, 6, seed=3)
+    ch = gpu.Code(code)
+    rng = np.random.default_rng(5)
+    llr = rng.choice([-1.0, -0.5, 0.0, 0.5, 1.0, 1.5], size=(300, code.N)).astype(np.float32)
+    for kind in ("cirbp", "rbp"):
+        say(f"[fixed ties {kind}] N=200")
+        ref = O.decode(code, llr, KIND[kind][0], O.MSFIX, max_updates=700, gamma=0.05, trace=True, threads=8)
+        g = gpu_decode(gpu, ch, llr, kind, gpu.MS_FIX, max_updates=700, gamma=0.05, trace=True)
+        np.testing.assert_array_equal(np_(g.trace), ref.trace)
+        np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+        np.testing.assert_array_equal(np_(g.bits), ref.bits)
+
+
+def test_fixed_8bit_and_check_every(gpu, c0):
+    code, ch = c0
+    cw, llr = S.frames(code, 400, 1.5, 102)
+    for ce in (0, code.E):
+        say(f"[fixed q8 f2 check_every={ce}]")
+        ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=1000, q_bits=8, frac_bits=2, check_every=ce,
+                       trace=True, threads=8)
+        g = gpu_decode(gpu, ch, llr, "cirbp", gpu.MS_FIX, max_updates=1000, q_bits=8, frac_bits=2,
+                       check_every=ce, trace=True)
+        np.testing.assert_array_equal(np_(g.trace), ref.trace)
+        np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+        np.testing.assert_array_equal(np_(g.bits), ref.bits)
+
+
+def test_fixed_bg1_shaped_full_size_sampled(gpu):
+    """The Z=52 BG1-shaped code at full size (state larger than one workgroup's LDS in FP32, here
+    fixed point): a few frames, bit-exact."""
+    code = S.workload_code("c1")
+    ch = gpu.Code(code)
+    cw, llr = S.frames(code, 4, 1.25, 103)
+    say("[fixed cirbp] c1 4 frames, cap 3000")
+    ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=3000, q_bits=8, frac_bits=2, trace=True, threads=4)
+    g = gpu_decode(gpu, ch, llr, "cirbp", gpu.MS_FIX, max_updates=3000, q_bits=8, frac_bits=2, trace=True)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+    say("[fixed layered] c1 16 frames")
+    ref = O.decode(code, llr, O.LAYERED, O.MSFIX, max_updates=20 * code.E, q_bits=8, frac_bits=2, threads=4)
+    g = gpu_decode(gpu, ch, llr, "layered", gpu.MS_FIX, max_updates=20 * code.E, q_bits=8, frac_bits=2)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+
+
+# ------------------------------------------------------------------------------------------
+# FP32: replay tolerance and frame-error-rate interval
+# ------------------------------------------------------------------------------------------
+def assert_close_msgs(g, ref, what):
+    a, b = np_(g), ref
+    tol = 1e-4 * np.maximum(np.abs(b), 1.0)
+    bad = np.abs(a - b) > tol
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond tolerance, max err {np.abs(a - b).max()}"
+
+
+@pytest.mark.parametrize("name,ntr", [("c0", 400), ("c4", 600)])
+def test_f32_replay_within_tolerance(gpu, name, ntr):
+    code = S.workload_code(name)
+    ch = gpu.Code(code)
+    cw, llr = S.frames(code, 64, 2.0, 104)
+    say(f"[f32 replay] {name} 64 frames, {ntr} updates")
+    rec = O.decode(code, llr, O.CIRBP, O.SPA, max_updates=ntr, check_every=0, trace=True, threads=8)
+    ref = O.decode(code, llr, O.REPLAY, O.SPA, max_updates=ntr, replay=rec.trace, dump=True, threads=8)
+    g = gpu_decode(gpu, ch, llr, "replay", gpu.SPA_F32, max_updates=ntr, replay=torch.from_numpy(rec.trace),
+                   dump=True)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    assert_close_msgs(g.c2v, ref.c2v, "c2v")
+    assert_close_msgs(g.pre, ref.pre, "pre")
+    assert_close_msgs(g.L, ref.L, "L")
+    assert_close_msgs(g.Lt, ref.Lt, "Lt")
+    assert np.abs(np_(g.D) - ref.D).max() <= 1e-4
+
+
+@pytest.mark.parametrize("kind", ["cirbp", "rbp", "flooding", "layered"])
+def test_f32_fer_within_interval_c0(gpu, c0, kind):
+    code, ch = c0
+    cw, llr = S.frames(code, 1000, 2.0, 105)
+    mu = 50 * code.E if kind in ("flooding", "layered") else 2400
+    say(f"[f32 FER {kind}] c0 1000 frames")
+    ref = O.decode(code, llr, KIND[kind][0], O.SPA, max_updates=mu, threads=8)
+    g = gpu_decode(gpu, ch, llr, kind, gpu.SPA_F32, max_updates=mu)
+    k_ref = int(np.any(ref.bits != cw, axis=1).sum())
+    k_gpu = int(np.any(np_(g.bits) != cw, axis=1).sum())
+    lo, hi = cp_interval(k_ref, 1000)
+    assert lo <= k_gpu / 1000 <= hi, (k_gpu, k_ref, lo, hi)
+    # most frames take exactly the same number of updates
+    assert np.mean(np_(g.updates_used) == ref.updates_used) > 0.8
+
+
+def test_f32_bg1_shaped_full_size_replay(gpu):
+    """Z=52 BG1-shaped code at full size (pre[] kept outside LDS): replay of 1500 oracle updates."""
+    code = S.workload_code("c1")
+    ch = gpu.Code(code)
+    cw, llr = S.frames(code, 3, 1.25, 106)
+    say("[f32 replay] c1 3 frames, 1500 updates")
+    rec = O.decode(code, llr, O.CIRBP, O.SPA, max_updates=1500, check_every=0, trace=True, threads=3)
+    ref = O.decode(code, llr, O.REPLAY, O.SPA, max_updates=1500, replay=rec.trace, dump=True, threads=3)
+    g = gpu_decode(gpu, ch, llr, "replay", gpu.SPA_F32, max_updates=1500, replay=torch.from_numpy(rec.trace),
+                   dump=True)
+    assert_close_msgs(g.c2v, ref.c2v, "c2v")
+    assert_close_msgs(g.L, ref.L, "L")
+    assert_close_msgs(g.Lt, ref.Lt, "Lt")
+    assert np.abs(np_(g.D) - ref.D).max() <= 1e-4
+
+
+# ------------------------------------------------------------------------------------------
+# edge cases
+# ------------------------------------------------------------------------------------------
+def test_edge_cases(gpu, c0):
+    code, ch = c0
+    # empty batch
+    t = torch.zeros((0, code.N), device="cuda")
+    r = gpu.decode(ch, t, gpu.CIRBP, gpu.SPA_F32, max_updates=10)
+    assert r.bits.shape == (0, code.N)
+    # max_updates = 0, and an already-valid word (strong all-zero channel): 0 updates
+    llr = np.full((3, code.N), 5.0, dtype=np.float32)
+    for kind in ("cirbp", "rbp", "flooding", "layered"):
+        g = gpu_decode(gpu, ch, llr, kind, gpu.SPA_F32, max_updates=100 * code.E)
+        assert np.all(np_(g.updates_used) == 0) and not np_(g.bits).any()
+    cw, llr = S.frames(code, 8, 1.0, 107)
+    g = gpu_decode(gpu, ch, llr, "cirbp", gpu.MS_FIX, max_updates=0)
+    assert np.all(np_(g.updates_used) == 0)
+    # all-zero channel (every value tied)
+    llr = np.zeros((4, code.N), dtype=np.float32)
+    ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=200, trace=True)
+    g = gpu_decode(gpu, ch, llr, "cirbp", gpu.MS_FIX, max_updates=200, trace=True)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    # single parity check of length 3 (smallest code), FP32 against the oracle
+    spc = S.spc_code(3)
+    sh = gpu.Code(spc)
+    llr = np.array([[1.0, -0.5, 2.0], [0.2, 0.3, -0.1]], dtype=np.float32)
+    ref = O.decode(spc, llr, O.CIRBP, O.SPA, max_updates=10, check_every=0, trace=True)
+    g = gpu_decode(gpu, sh, llr, "cirbp", gpu.SPA_F32, max_updates=10, check_every=0, trace=True)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_allclose(np_(g.llr_out), ref.llr_out, rtol=1e-5, atol=1e-5)
+    # replay with an invalid edge id stops that frame where the id appears
+    rep = torch.tensor([[0, 1, code.E + 5, 2]], dtype=torch.int32)
+    cw, llr = S.frames(code, 1, 2.0, 108)
+    g = gpu_decode(gpu, ch, llr, "replay", gpu.SPA_F32, max_updates=4, replay=rep)
+    assert int(np_(g.updates_used)[0]) == 2
