@@ -110,6 +110,14 @@ typedef struct {
 int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32_t* col_idx,
                        const int32_t* layer_ptr, int32_t n_layers, ldpc_code** out);
 
+/* Create a code handle from a quasi-cyclic base matrix (host pointer shift[mb][nb], row-major;
+   -1 = zero block, s in [0, Z) = circulant): check i Z + r meets VN j Z + ((r + s) mod Z) (the
+   lifting used by the paper's Sec. V codes).  The expanded H uses canonical edge ids; the block
+   rows form the layers.  Kernels use the base tables instead of per-edge index arrays.
+   Errors: LDPC_EINVAL (shift out of range, a base row with < 2 blocks, an empty base column),
+   LDPC_ENOMEM, LDPC_EHIP. */
+int ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t* shift, ldpc_code** out);
+
 /* Fill *out with the sizes and per-frame on-chip memory needs of a code. */
 int ldpc_code_info(const ldpc_code* code, ldpc_code_stats* out);
 

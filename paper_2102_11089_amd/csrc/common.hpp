@@ -19,6 +19,7 @@
 namespace ldpc {
 
 constexpr int WAVE = 64;
+constexpr int NBR_PMAX = 8;  // two-hop neighbourhood of one VN: at most 8 passes of 64 lanes
 
 // ------------------------------------------------------------------------------------------
 // keys and wave reductions
@@ -31,30 +32,154 @@ __device__ __forceinline__ uint32_t key_val(uint64_t k) { return (uint32_t)(k >>
 
 __device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
-// maximum over the 64 lanes, returned wave-uniform (scalar registers)
+// Cross-lane primitives built on DPP (data-parallel primitives: a VALU source operand taken from
+// another lane of the same 16-lane row) and v_readlane for the four row results.  They must be
+// called with all 64 lanes active.
+//   quad_perm [1,0,3,2] / [2,3,0,1], row_half_mirror and row_mirror pair every lane of a row with a
+//   distinct partner, so four steps leave the row's total in all 16 lanes;
+//   row_shr:1,2,4,8 (identity fill) give an inclusive scan inside each row, row_bcast:15 and
+//   row_bcast:31 carry the row totals forward.
+#define LDPC_DPP_QXOR1 0xB1
+#define LDPC_DPP_QXOR2 0x4E
+#define LDPC_DPP_HALF_MIRROR 0x141
+#define LDPC_DPP_MIRROR 0x140
+#define LDPC_DPP_SHR(n) (0x110 + (n))
+#define LDPC_DPP_BCAST15 0x142
+#define LDPC_DPP_BCAST31 0x143
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  x = max(x, dpp_u32<LDPC_DPP_QXOR1>(x));
+  x = max(x, dpp_u32<LDPC_DPP_QXOR2>(x));
+  x = max(x, dpp_u32<LDPC_DPP_HALF_MIRROR>(x));
+  x = max(x, dpp_u32<LDPC_DPP_MIRROR>(x));
+  const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
+  const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
+  const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+  return max(max(a, b), max(c, d));
+}
+
+// maximum of u64 keys over the 64 lanes, returned wave-uniform: the high words first, then the
+// low words of the lanes holding the maximal high word
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t k) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) k = umax64(k, __shfl_xor(k, off));
-  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(k & 0xFFFFFFFFull));
-  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(k >> 32));
-  return ((uint64_t)hi << 32) | lo;
+  const uint32_t hi = (uint32_t)(k >> 32), lo = (uint32_t)(k & 0xFFFFFFFFull);
+  const uint32_t mh = wave_max_u32(hi);
+  const uint32_t ml = wave_max_u32(hi == mh ? lo : 0u);
+  return ((uint64_t)mh << 32) | ml;
 }
 
 __device__ __forceinline__ int wave_sum_i32(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return __builtin_amdgcn_readfirstlane(v);
+  uint32_t x = (uint32_t)v;
+  x += dpp_u32<LDPC_DPP_QXOR1>(x);
+  x += dpp_u32<LDPC_DPP_QXOR2>(x);
+  x += dpp_u32<LDPC_DPP_HALF_MIRROR>(x);
+  x += dpp_u32<LDPC_DPP_MIRROR>(x);
+  return __builtin_amdgcn_readlane((int)x, 0) + __builtin_amdgcn_readlane((int)x, 16) +
+         __builtin_amdgcn_readlane((int)x, 32) + __builtin_amdgcn_readlane((int)x, 48);
 }
 
-// exclusive prefix sum across the wave
-__device__ __forceinline__ int wave_excl_scan(int v, int lane) {
-  int x = v;
-#pragma unroll
-  for (int off = 1; off < WAVE; off <<= 1) {
-    int y = __shfl_up(x, off);
-    if (lane >= off) x += y;
+// exclusive prefix sum across the wave (lane order)
+__device__ __forceinline__ int wave_excl_scan(int v, int) {
+  uint32_t x = (uint32_t)v;
+  x += dpp_u32<LDPC_DPP_SHR(1)>(x);
+  x += dpp_u32<LDPC_DPP_SHR(2)>(x);
+  x += dpp_u32<LDPC_DPP_SHR(4)>(x);
+  x += dpp_u32<LDPC_DPP_SHR(8)>(x);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, LDPC_DPP_BCAST15, 0xA, 0xF, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, LDPC_DPP_BCAST31, 0xC, 0xF, false);
+  return (int)x - v;
+}
+
+// Butterfly exchange inside aligned lane blocks of 2^L lanes: level 1..4 use DPP inside 16-lane
+// rows (quad_perm xor 1, xor 2, row_half_mirror, row_mirror); level 5 pairs the two 16-lane rows
+// of a 32-lane half with a ds_swizzle xor 16.  After level k every lane holds the result of its
+// aligned 2^k group.
+template <int LEVEL>
+__device__ __forceinline__ uint32_t bfly(uint32_t x) {
+  if constexpr (LEVEL == 1) return dpp_u32<LDPC_DPP_QXOR1>(x);
+  else if constexpr (LEVEL == 2) return dpp_u32<LDPC_DPP_QXOR2>(x);
+  else if constexpr (LEVEL == 3) return dpp_u32<LDPC_DPP_HALF_MIRROR>(x);
+  else if constexpr (LEVEL == 4) return dpp_u32<LDPC_DPP_MIRROR>(x);
+  else return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);
+}
+template <int LEVEL>
+__device__ __forceinline__ float bflyf(float x) { return __uint_as_float(bfly<LEVEL>(__float_as_uint(x))); }
+
+// Per-lane state of a whole-row reduction: sum of phi (S), the same sum without the row's
+// smallest input (Sx), smallest magnitude (m1) with its edge id, second smallest (m2), sign
+// parity (bit 31 of ap, the edge id in bits 0..30).  Merging two groups keeps the smaller
+// minimum (lower edge id on ties); the merged Sx is the winner's Sx plus the other group's S.
+struct RowRed {
+  float S, Sx, m1, m2;
+  uint32_t ap;  // edge id of m1 | parity << 31
+};
+
+template <int LEVEL, bool SUM>
+__device__ __forceinline__ void rowred_step(RowRed& r, bool on) {
+  const float pm1 = bflyf<LEVEL>(r.m1), pm2 = bflyf<LEVEL>(r.m2);
+  const uint32_t pap = bfly<LEVEL>(r.ap);
+  float pS = 0.0f, pSx = 0.0f;
+  if constexpr (SUM) {
+    pS = bflyf<LEVEL>(r.S);
+    pSx = bflyf<LEVEL>(r.Sx);
   }
-  return x - v;
+  if (on) {
+    const uint32_t par = (r.ap ^ pap) & 0x80000000u;
+    const uint32_t a = r.ap & 0x7FFFFFFFu, pa = pap & 0x7FFFFFFFu;
+    if (pm1 < r.m1 || (pm1 == r.m1 && pa < a)) {
+      r.m2 = fminf(r.m1, pm2);
+      r.m1 = pm1;
+      r.ap = pa | par;
+      if constexpr (SUM) r.Sx = pSx + r.S;
+    } else {
+      r.m2 = fminf(r.m2, pm1);
+      r.ap = a | par;
+      if constexpr (SUM) r.Sx = r.Sx + pS;
+    }
+    if constexpr (SUM) r.S += pS;
+  }
+}
+
+// all butterfly levels up to the largest block of the pass (maxL2 is wave-uniform)
+template <bool SUM>
+__device__ __forceinline__ void rowred_all(RowRed& r, int L2, int maxL2) {
+  if (maxL2 >= 1) rowred_step<1, SUM>(r, L2 >= 1);
+  if (maxL2 >= 2) rowred_step<2, SUM>(r, L2 >= 2);
+  if (maxL2 >= 3) rowred_step<3, SUM>(r, L2 >= 3);
+  if (maxL2 >= 4) rowred_step<4, SUM>(r, L2 >= 4);
+  if (maxL2 >= 5) rowred_step<5, SUM>(r, L2 >= 5);
+}
+
+// maximum of (hi, lo) pairs inside the block
+template <int LEVEL>
+__device__ __forceinline__ void keymax_step(uint32_t& hi, uint32_t& lo, bool on) {
+  const uint32_t ph = bfly<LEVEL>(hi), pl = bfly<LEVEL>(lo);
+  if (on && (ph > hi || (ph == hi && pl > lo))) {
+    hi = ph;
+    lo = pl;
+  }
+}
+__device__ __forceinline__ uint64_t keymax_all(uint64_t k, int L2, int maxL2) {
+  uint32_t hi = (uint32_t)(k >> 32), lo = (uint32_t)(k & 0xFFFFFFFFull);
+  if (maxL2 >= 1) keymax_step<1>(hi, lo, L2 >= 1);
+  if (maxL2 >= 2) keymax_step<2>(hi, lo, L2 >= 2);
+  if (maxL2 >= 3) keymax_step<3>(hi, lo, L2 >= 3);
+  if (maxL2 >= 4) keymax_step<4>(hi, lo, L2 >= 4);
+  if (maxL2 >= 5) keymax_step<5>(hi, lo, L2 >= 5);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Ordering point for a workgroup that is exactly one wavefront: LDS operations of one wavefront
+// execute in order, so only the compiler has to be kept from moving memory accesses across it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -146,8 +271,102 @@ struct ArithFix {
 };
 
 // ------------------------------------------------------------------------------------------
+// whole-row check update (eq. (2) for every edge of one check at once)
+//
+// Sum-product, FP32, Gallager's form of eq. (2):
+//   |C2V_{m->j}| = phi( sum_{k != j} phi(|V2C_k|) ),  phi(x) = -log tanh(x/2) = phi^{-1}(x),
+//   sign = product of the other signs (sign of 0 is +).
+// Every lane of a row reads the row's (V2C, phi) pairs once; the sum leaving out the row's
+// smallest input is accumulated separately so that no large term is ever subtracted from itself,
+// and the result is clamped by the smallest other magnitude (|a [+] b| <= min(|a|, |b|)).
+// Min-sum (fixed point): sign product times the smallest other magnitude, from (min1, argmin,
+// min2, parity) of the row -- exactly the oracle's leave-one-out fold.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float phi_f32(float x) {  // -log(tanh(x/2)) = log((1 + t) / (1 - t)), t = e^-x
+  const float t = __expf(-x);
+  // 1 - e^-x: Taylor series below 0.25 (the subtraction would lose the low bits)
+  const float ser = x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f)))));
+  const float y = x < 0.25f ? ser : 1.0f - t;
+  const float lg = __logf(__fdividef(1.0f + t, y));
+  // above 4 the quotient is 1 + w, w = 2t/(1-t) < 0.04: log(1 + w) by its series
+  const float w = __fdividef(2.0f * t, y);
+  const float lp = w * (1.0f - w * (0.5f - w * (1.0f / 3.0f - w * 0.25f)));
+  return x > 4.0f ? lp : lg;
+}
+
+struct RowAccF32 {
+  float S = 0.0f, Sx = 0.0f, min1 = __builtin_inff(), min2 = __builtin_inff();
+  int arg = -1;
+  uint32_t par = 0;
+  __device__ __forceinline__ void add(int k, float v, float ph) {
+    const float a = fabsf(v);
+    par ^= v < 0.0f ? 1u : 0u;
+    const float before = S;
+    S += ph;
+    if (a < min1) {
+      Sx = before;
+      min2 = min1;
+      min1 = a;
+      arg = k;
+    } else {
+      Sx += ph;
+      if (a < min2) min2 = a;
+    }
+  }
+  __device__ __forceinline__ float out(int j, float vj, float phj) const {
+    const bool self = j == arg;
+    const float mo = self ? min2 : min1;
+    const float Sj = self ? Sx : (phj == __builtin_inff() ? __builtin_inff() : S - phj);
+    const float mag = fminf(phi_f32(fmaxf(Sj, 0.0f)), mo);
+    return ((par ^ (vj < 0.0f ? 1u : 0u)) & 1u) ? -mag : mag;
+  }
+};
+
+struct RowAccFix {
+  int min1 = 0x7fffffff, min2 = 0x7fffffff, arg = -1;
+  uint32_t par = 0;
+  __device__ __forceinline__ void add(int k, int v, float) {
+    const int a = abs(v);
+    par ^= v < 0 ? 1u : 0u;
+    if (a < min1) {
+      min2 = min1;
+      min1 = a;
+      arg = k;
+    } else if (a < min2) {
+      min2 = a;
+    }
+  }
+  __device__ __forceinline__ int out(int j, int vj, float) const {
+    const int mag = j == arg ? min2 : min1;
+    return ((par ^ (vj < 0 ? 1u : 0u)) & 1u) ? -mag : mag;
+  }
+};
+
+template <class A> struct RowAccOf;
+template <> struct RowAccOf<ArithF32> { using type = RowAccF32; };
+template <> struct RowAccOf<ArithFix> { using type = RowAccFix; };
+
+// per-input auxiliary value stored next to each V2C (phi for sum-product, unused for min-sum)
+__device__ __forceinline__ float row_aux(const ArithF32&, float v) { return phi_f32(fabsf(v)); }
+__device__ __forceinline__ float row_aux(const ArithFix&, int) { return 0.0f; }
+
+// ------------------------------------------------------------------------------------------
 // code topology as seen by a kernel
 // ------------------------------------------------------------------------------------------
+// Quasi-cyclic description (Sec. V codes are lifted base graphs): base row i has deg[i] blocks
+// (j, shift) with ascending j; check m = i Z + r meets VN j Z + ((r + shift) mod Z).  Edge ids stay
+// canonical: e = Z bptr[i] + r deg[i] + rank of j in row i.
+struct DevQC {
+  int Z, mb, nb, nblk;  // nblk = bptr[mb] = number of nonzero blocks
+  const int* bdeg;      // [mb]
+  const int* bptr;      // [mb+1]
+  const int* brow;      // [nblk][2]  (j, shift) per row, ascending j
+  const int* bcol_ptr;  // [nb+1]
+  const int* bcol;      // [nblk][4]  (i, shift, rank in row i, 0) per column, ascending i
+  const int* rowmap;    // [nblk]     base row of edge block e / Z
+  int words;            // total ints of the tables (for copying into LDS)
+};
+
 struct DevCode {
   int M, N, E;
   int max_dc, max_dv, max_touch;  // max_touch = max over VNs of sum of degrees of its checks
@@ -159,6 +378,93 @@ struct DevCode {
   const int* col_row;    // [E]   checks of VN n, ascending
   const int* col_eid;    // [E]   edge ids of VN n, ascending
   const int* layer_ptr;  // [n_layers+1]
+  DevQC qc;              // valid when qc.Z > 0
+  // two-hop neighbourhood table: for VN n, nbr[off(n) .. off(n) + cnt(n)) lists every edge of every
+  // check of n, each check in an aligned block of 2^L lanes (largest blocks first, padding entries
+  // have e = -1).  Entry = (edge id, VN | L << 24 | leader << 27).
+  const int2* nbr;
+  const int2* nbr_idx;   // [N] (off, cnt)
+  const int2* nbr_col;   // quasi-cyclic codes: [nb] (off of VN j Z, cnt) -- off(n) = off + (n mod Z) cnt
+  int nbr_max_cnt;
+};
+
+// Topology over CSR/CSC arrays (global memory or LDS copies)
+struct TopoCSR {
+  const int* row_ptr;
+  const int* col;
+  const int* row_of;
+  const int* col_ptr;
+  const int* col_row;
+  const int* col_eid;
+  __device__ __forceinline__ int vn_deg(int n) const { return col_ptr[n + 1] - col_ptr[n]; }
+  __device__ __forceinline__ void vn_edge(int n, int k, int& m, int& e) const {
+    const int x = col_ptr[n] + k;
+    m = col_row[x];
+    e = col_eid[x];
+  }
+  __device__ __forceinline__ int row_start(int m) const { return row_ptr[m]; }
+  __device__ __forceinline__ int row_deg(int m) const { return row_ptr[m + 1] - row_ptr[m]; }
+  __device__ __forceinline__ int row_vn(int m, int rs, int p) const { return col[rs + p]; }
+  __device__ __forceinline__ int edge_vn(int e) const { return col[e]; }
+  __device__ __forceinline__ int edge_row(int e) const { return row_of[e]; }
+  const int2* nbr_idx;
+  __device__ __forceinline__ int2 nbr(int n) const { return nbr_idx[n]; }
+};
+
+// Topology of a quasi-cyclic code from its base tables (in LDS): no per-edge index arrays
+struct TopoQC {
+  int Z;
+  const int* bdeg;
+  const int* bptr;
+  const int* brow;
+  const int* bcol_ptr;
+  const int* bcol;
+  const int* rowmap;
+  __device__ __forceinline__ int vn_deg(int n) const {
+    const int j = n / Z;
+    return bcol_ptr[j + 1] - bcol_ptr[j];
+  }
+  __device__ __forceinline__ void vn_edge(int n, int k, int& m, int& e) const {
+    const int j = n / Z, c = n - j * Z;
+    const int x = (bcol_ptr[j] + k) * 4;
+    const int i = bcol[x], sh = bcol[x + 1], rank = bcol[x + 2];
+    int r = c - sh;
+    if (r < 0) r += Z;
+    m = i * Z + r;
+    e = Z * bptr[i] + r * bdeg[i] + rank;
+  }
+  __device__ __forceinline__ int row_start(int m) const {
+    const int i = m / Z, r = m - i * Z;
+    return Z * bptr[i] + r * bdeg[i];
+  }
+  __device__ __forceinline__ int row_deg(int m) const { return bdeg[m / Z]; }
+  __device__ __forceinline__ int row_vn(int m, int, int p) const {
+    const int i = m / Z, r = m - i * Z;
+    const int x = (bptr[i] + p) * 2;
+    int c = r + brow[x + 1];
+    if (c >= Z) c -= Z;
+    return brow[x] * Z + c;
+  }
+  __device__ __forceinline__ int edge_row(int e) const {
+    const int i = rowmap[e / Z];
+    const int r = (e - Z * bptr[i]) / bdeg[i];
+    return i * Z + r;
+  }
+  __device__ __forceinline__ int edge_vn(int e) const {
+    const int i = rowmap[e / Z];
+    const int loc = e - Z * bptr[i];
+    const int r = loc / bdeg[i], p = loc - r * bdeg[i];
+    const int x = (bptr[i] + p) * 2;
+    int c = r + brow[x + 1];
+    if (c >= Z) c -= Z;
+    return brow[x] * Z + c;
+  }
+  const int* nbr_col;  // [nb][2] in LDS
+  __device__ __forceinline__ int2 nbr(int n) const {
+    const int j = n / Z, c = n - j * Z;
+    const int cnt = nbr_col[2 * j + 1];
+    return make_int2(nbr_col[2 * j] + c * cnt, cnt);
+  }
 };
 
 // splitmix64 output function (Steele, Lea, Flood, 2014): golden-gamma increment + finaliser

@@ -2,20 +2,22 @@
 // (Algorithm 1, Sec. III-B) and forced-order replay of a recorded schedule.
 //
 // One wavefront (64 lanes, one workgroup) decodes one codeword at a time; workgroups loop over
-// frames.  The frame's whole state lives in LDS:
+// frames.  The frame's state lives in LDS:
 //   c2v[E], pre[E]      current and precomputed C2V messages (pre may live in a global scratch
 //                        slot per workgroup when it does not fit),
 //   L[N], Lt[N]         total and precomputed total LLRs,
 //   D[N]                CI of every VN as key bits,
 //   ckey[M]             per check: max over its edges of (residual, lowest edge id),
 //   dblk[], cblk[]      max over blocks of 64 VNs / 64 checks (two-level max trees),
-//   syn[M]              syndrome bits of the current hard decisions.
-// Per update only the touched part of the state is rewritten:
+//   syn[M]              syndrome bits of the current hard decisions,
+//   topology            CSR/CSC copies (small codes) or quasi-cyclic base tables.
+// Per update (chain of dependent steps kept short; every row computed in registers):
 //   selection      argmax over the block maxima (one wave reduction), or over the checks of n*,
-//   propagation    c2v[e*] <- pre[e*], L_{n*} += delta, syndrome toggles if the hard bit flips,
-//   touched checks every i in M(n*) \ m*: new V2C from n*, new precomputed messages of its
-//                  other edges (one lane per edge, leave-one-out fold), residual keys,
-//   CI             Lt_j += pre_new - pre_old, D_j for the VNs of the touched checks and D_{n*},
+//   propagation    c2v[e*] <- pre[e*], L_{n*} += delta, D_{n*} refresh, syndrome toggles,
+//   touched checks the two-hop table of n* places every edge of every check of n* in an aligned
+//                  block of lanes; one load brings V2C inputs, a butterfly inside each block gives
+//                  the whole row's precomputed messages (eq. (2)) and its residual key,
+//   CI             Lt_j += pre_new - pre_old, then D_j for the VNs of the touched checks,
 //   max trees      block maxima raised with LDS atomic max; a block whose maximum leaf
 //                  decreased is recomputed by one wave reduction.
 #include "common.hpp"
@@ -23,12 +25,78 @@
 
 namespace ldpc {
 
-template <class A, bool PRE_GLOBAL>
+#ifdef LDPC_PROFILE
+// phase timing for development builds only: per-phase clock64() deltas summed over updates
+#define PROF_DECL long long prof_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}; long long prof_t = clock64();
+#define PROF_MARK(i) { long long now_ = clock64(); prof_acc[i] += now_ - prof_t; prof_t = now_; }
+#define PROF_FLUSH { if (lane == 0 && P.prof) for (int i_ = 0; i_ < 8; ++i_) atomicAdd((unsigned long long*)&P.prof[i_], (unsigned long long)prof_acc[i_]); }
+#else
+#define PROF_DECL
+#define PROF_MARK(i)
+#define PROF_FLUSH
+#endif
+
+// Copy the topology into LDS when requested and return the accessor.
+template <int TOPO>
+struct TopoSel;
+template <>
+struct TopoSel<TOPO_GLOBAL> {
+  using type = TopoCSR;
+  __device__ static type make(const DevCode& H, unsigned char*, int, int) {
+    TopoCSR t{H.row_ptr, H.col, H.row_of, H.col_ptr, H.col_row, H.col_eid};
+    t.nbr_idx = H.nbr_idx;
+    return t;
+  }
+};
+template <>
+struct TopoSel<TOPO_LDS> {
+  using type = TopoCSR;
+  __device__ static type make(const DevCode& H, unsigned char* base, int tid, int nthr) {
+    int* p = reinterpret_cast<int*>(base);
+    const int M = H.M, N = H.N, E = H.E;
+    int* row_ptr = p;
+    int* col = row_ptr + (M + 1);
+    int* row_of = col + E;
+    int* col_ptr = row_of + E;
+    int* col_row = col_ptr + (N + 1);
+    int* col_eid = col_row + E;
+    int2* nidx = reinterpret_cast<int2*>(col_eid + E + (((M + 1) + (N + 1)) & 1));
+    for (int x = tid; x <= M; x += nthr) row_ptr[x] = H.row_ptr[x];
+    for (int x = tid; x <= N; x += nthr) col_ptr[x] = H.col_ptr[x];
+    for (int x = tid; x < E; x += nthr) {
+      col[x] = H.col[x];
+      row_of[x] = H.row_of[x];
+      col_row[x] = H.col_row[x];
+      col_eid[x] = H.col_eid[x];
+    }
+    for (int x = tid; x < N; x += nthr) nidx[x] = H.nbr_idx[x];
+    TopoCSR t{row_ptr, col, row_of, col_ptr, col_row, col_eid};
+    t.nbr_idx = nidx;
+    return t;
+  }
+};
+template <>
+struct TopoSel<TOPO_QC> {
+  using type = TopoQC;
+  __device__ static type make(const DevCode& H, unsigned char* base, int tid, int nthr) {
+    int* p = reinterpret_cast<int*>(base);
+    const DevQC& q = H.qc;
+    for (int x = tid; x < q.words; x += nthr) p[x] = q.bdeg[x];  // tables are contiguous from bdeg
+    const int o_bptr = (int)(q.bptr - q.bdeg), o_brow = (int)(q.brow - q.bdeg);
+    const int o_bcp = (int)(q.bcol_ptr - q.bdeg), o_bcol = (int)(q.bcol - q.bdeg), o_rm = (int)(q.rowmap - q.bdeg);
+    TopoQC t{q.Z, p, p + o_bptr, p + o_brow, p + o_bcp, p + o_bcol, p + o_rm};
+    t.nbr_col = p + (int)(reinterpret_cast<const int*>(H.nbr_col) - q.bdeg);
+    return t;
+  }
+};
+
+template <class A, bool PRE_GLOBAL, int TOPO>
 __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
   extern __shared__ __align__(16) unsigned char lds[];
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   using val_t = typename A::val_t;
+  using Acc = typename RowAccOf<A>::type;
   const int lane = threadIdx.x;
 
   msg_t* c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
@@ -44,10 +112,8 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
   uint32_t* dmask = reinterpret_cast<uint32_t*>(lds + P.off_dmask);
   uint32_t* cmask = reinterpret_cast<uint32_t*>(lds + P.off_cmask);
   uint8_t* syn = reinterpret_cast<uint8_t*>(lds + P.off_syn);
-  val_t* vbuf = reinterpret_cast<val_t*>(lds + P.off_v);
-  uint8_t* slot = reinterpret_cast<uint8_t*>(lds + P.off_slot);
-  int* trow = reinterpret_cast<int*>(lds + P.off_trow);  // [3][WAVE]: row, row start, slot offset
   int* lut = reinterpret_cast<int*>(lds + P.off_lut);
+  int* tj = reinterpret_cast<int*>(lds + P.off_v);  // touched VN of each table lane, per pass
 
   A ar;
   ar.qmax = P.qmax;
@@ -56,8 +122,10 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
   if constexpr (A::kFixed) {
     for (int x = lane; x < 257; x += WAVE) lut[x] = P.lut_global[x];
   }
+  const auto G = TopoSel<TOPO>::make(H, lds + P.off_topo, lane, WAVE);
   const int N = H.N, M = H.M, E = H.E;
   const bool with_ci = P.kind != KIND_RBP;
+  wave_sync();
 
   for (int f = blockIdx.x; f < P.B; f += gridDim.x) {
     // ---------------- Algorithm 1 lines 1-3: initial state --------------------------------
@@ -66,76 +134,82 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
     for (int e = lane; e < E; e += WAVE) c2v[e] = (msg_t)0;
     for (int w = lane; w < P.nbd_words; w += WAVE) dmask[w] = 0u;
     for (int w = lane; w < P.nbc_words; w += WAVE) cmask[w] = 0u;
-    __syncthreads();
-    for (int e = lane; e < E; e += WAVE) {  // every precomputed C2V message from V2C = channel
-      int m = H.row_of[e];
-      int rs = H.row_ptr[m], re = H.row_ptr[m + 1];
-      bool first = true;
-      val_t acc = 0;
-      for (int k = rs; k < re; ++k) {
-        if (k == e) continue;
-        val_t v = ar.vin((val_t)L[H.col[k]]);
-        acc = first ? v : ar.op(acc, v);
-        first = false;
-      }
-      pre[e] = (msg_t)acc;
-    }
-    __syncthreads();
-    for (int n = lane; n < N; n += WAVE) {
-      val_t lt = (val_t)L[n];
-      for (int k = H.col_ptr[n]; k < H.col_ptr[n + 1]; ++k) lt += (val_t)pre[H.col_eid[k]];
-      Lt[n] = (llr_t)lt;
-      D[n] = with_ci ? ar.ci((val_t)L[n], lt) : 0u;
-    }
+    wave_sync();
+    // every precomputed C2V message from V2C = channel value: one lane per check row
     int unsat_local = 0;
     for (int m = lane; m < M; m += WAVE) {
-      uint64_t k = 0;
+      const int rs = G.row_start(m), dc = G.row_deg(m);
+      Acc acc;
       int par = 0;
-      for (int e = H.row_ptr[m]; e < H.row_ptr[m + 1]; ++e) {
-        k = umax64(k, mkkey(ar.res((val_t)pre[e], (val_t)c2v[e]), (uint32_t)e));
-        par ^= ((val_t)L[H.col[e]] < 0) ? 1 : 0;
+      for (int p = 0; p < dc; ++p) {
+        const val_t l = (val_t)L[G.row_vn(m, rs, p)];
+        const val_t v = ar.vin(l);
+        acc.add(p, v, row_aux(ar, v));
+        par ^= l < 0 ? 1 : 0;
+      }
+      uint64_t k = 0;
+      for (int p = 0; p < dc; ++p) {
+        const val_t v = ar.vin((val_t)L[G.row_vn(m, rs, p)]);
+        const val_t o = acc.out(p, v, row_aux(ar, v));
+        pre[rs + p] = (msg_t)o;
+        k = umax64(k, mkkey(ar.res(o, (val_t)0), (uint32_t)(rs + p)));
       }
       ckey[m] = k;
       syn[m] = (uint8_t)par;
       unsat_local += par;
     }
     int unsat = wave_sum_i32(unsat_local);
-    __syncthreads();
+    if constexpr (PRE_GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // pre[] stores done
+    wave_sync();
+    for (int n = lane; n < N; n += WAVE) {
+      val_t lt = (val_t)L[n];
+      const int dv = G.vn_deg(n);
+      for (int k = 0; k < dv; ++k) {
+        int m, e;
+        G.vn_edge(n, k, m, e);
+        lt += (val_t)pre[e];
+      }
+      Lt[n] = (llr_t)lt;
+      D[n] = with_ci ? ar.ci((val_t)L[n], lt) : 0u;
+    }
+    wave_sync();
     for (int b = 0; b < P.nbd; ++b) {
-      int n = b * WAVE + lane;
+      const int n = b * WAVE + lane;
       uint64_t k = n < N ? mkkey(D[n], (uint32_t)n) : 0ull;
       k = wave_max_u64(k);
       if (lane == 0) dblk[b] = k;
     }
     for (int b = 0; b < P.nbc; ++b) {
-      int m = b * WAVE + lane;
+      const int m = b * WAVE + lane;
       uint64_t k = m < M ? ckey[m] : 0ull;
       k = wave_max_u64(k);
       if (lane == 0) cblk[b] = k;
     }
-    __syncthreads();
+    wave_sync();
 
     // ---------------- update loop -------------------------------------------------------
     long long t = 0, nfall = 0;
     long long limit = P.max_updates;
     if (P.kind == KIND_REPLAY && P.replay_len < limit) limit = P.replay_len;
     const long long ce = P.kind == KIND_REPLAY ? 0 : P.check_every;
+    long long until_check = ce;  // updates left until the next syndrome test
     bool done = ce > 0 && unsat == 0;
+    PROF_DECL
     while (!done && t < limit) {
-      const long long tprev = t;
+      PROF_MARK(7)
       // ---- selection (Algorithm 1 lines 4-8; RBP eq. (5)) ----
-      int estar;
+      int estar, mstar = -1, nstar = -1;
       if (P.kind == KIND_REPLAY) {
         estar = uni(P.replay[(size_t)f * P.replay_len + t]);
         if (estar < 0 || estar >= E) break;  // invalid edge id ends the frame's replay
       } else {
         bool global_res = P.kind == KIND_RBP;
-        int nstar_sel = -1;
+        int nsel = -1;
         if (!global_res) {
           uint64_t k = 0;
           for (int b = lane; b < P.nbd; b += WAVE) k = umax64(k, dblk[b]);
           k = wave_max_u64(k);
-          nstar_sel = (int)key_idx(k);
+          nsel = (int)key_idx(k);
           if (key_val(k) < P.gamma_bits) {  // D_{n*} < gamma: RBP fallback
             global_res = true;
             nfall += 1;
@@ -146,181 +220,173 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
           for (int b = lane; b < P.nbc; b += WAVE) k = umax64(k, cblk[b]);
           estar = (int)key_idx(wave_max_u64(k));
         } else {
-          const int cb = H.col_ptr[nstar_sel], dv = H.col_ptr[nstar_sel + 1] - cb;
+          const int dvs = uni(G.vn_deg(nsel));
           uint64_t k = 0;
-          for (int q = lane; q < dv; q += WAVE) {
-            int e = H.col_eid[cb + q];
-            k = umax64(k, mkkey(ar.res((val_t)pre[e], (val_t)c2v[e]), (uint32_t)e));
+          int mk = -1;
+          if (lane < dvs) {
+            int e;
+            G.vn_edge(nsel, lane, mk, e);
+            k = mkkey(ar.res((val_t)pre[e], (val_t)c2v[e]), (uint32_t)e);
           }
-          estar = (int)key_idx(wave_max_u64(k));
+          const uint64_t kmax = wave_max_u64(k);
+          estar = (int)key_idx(kmax);
+          const unsigned long long win = __ballot(lane < dvs && k == kmax);
+          mstar = __builtin_amdgcn_readlane(mk, (int)__builtin_ctzll(win));
+          nstar = nsel;
         }
       }
-      const int mstar = uni(H.row_of[estar]);
-      const int nstar = uni(H.col[estar]);
-      const int cb = uni(H.col_ptr[nstar]);
-      const int dv = uni(H.col_ptr[nstar + 1]) - cb;
+      if (mstar < 0) {
+        mstar = uni(G.edge_row(estar));
+        nstar = uni(G.edge_vn(estar));
+      }
+      PROF_MARK(0)
+      const int dv = uni(G.vn_deg(nstar));
+      int my_m = -1;
+      if (lane < dv) {
+        int e;
+        G.vn_edge(nstar, lane, my_m, e);
+      }
+      const int2 nb = G.nbr(nstar);
+      const int noff = uni(nb.x), ncnt = uni(nb.y);
+      const int npass = (ncnt + WAVE - 1) / WAVE;
+      const int rs_m = uni(G.row_start(mstar));
+      const int re_m = rs_m + uni(G.row_deg(mstar));
+      int2 ent0 = make_int2(-1, 0);
+      if (lane < ncnt) ent0 = H.nbr[noff + lane];  // first pass of the two-hop table, early
 
-      // ---- propagation (Algorithm 1 line 9) ----
+      // ---- propagation (Algorithm 1 line 9) and D_{n*} ----
       const val_t newv = (val_t)pre[estar];
       const val_t oldv = (val_t)c2v[estar];
       const val_t Lold = (val_t)L[nstar];
       const val_t Lnew = Lold + (newv - oldv);
-      __syncthreads();
+      const uint32_t dn_old = D[nstar];
+      const uint32_t dn_new = with_ci ? ar.ci(Lnew, (val_t)Lt[nstar]) : 0u;
+      wave_sync();
       if (lane == 0) {
         c2v[estar] = (msg_t)newv;
         L[nstar] = (llr_t)Lnew;
+        if (with_ci) {
+          D[nstar] = dn_new;
+          const uint64_t nk = mkkey(dn_new, (uint32_t)nstar), ok = mkkey(dn_old, (uint32_t)nstar);
+          if (nk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&dblk[nstar >> 6]), (unsigned long long)nk);
+          else if (nk < ok && dblk[nstar >> 6] == ok) atomicOr(&dmask[(nstar >> 6) >> 5], 1u << ((nstar >> 6) & 31));
+        }
       }
       if ((Lold < 0) != (Lnew < 0)) {  // hard decision flipped: toggle the checks of n*
         int d = 0;
-        for (int q = lane; q < dv; q += WAVE) {
-          int m = H.col_row[cb + q];
-          int s = syn[m];
-          syn[m] = (uint8_t)(s ^ 1);
-          d += s ? -1 : 1;
+        if (lane < dv) {
+          const int s = syn[my_m];
+          syn[my_m] = (uint8_t)(s ^ 1);
+          d = s ? -1 : 1;
         }
         unsat += wave_sum_i32(d);
       }
-      // ---- touched checks M(n*) \ m*: slot layout ----
-      int my_row = -1, my_rs = 0, my_dc = 0;
-      if (lane < dv) {
-        my_row = H.col_row[cb + lane];
-        my_rs = H.row_ptr[my_row];
-        my_dc = my_row == mstar ? 0 : H.row_ptr[my_row + 1] - my_rs;
-      }
-      const int my_off = wave_excl_scan(my_dc, lane);
-      const int T = wave_sum_i32(my_dc);
-      if (lane < dv) {
-        trow[lane] = my_row;
-        trow[WAVE + lane] = my_rs;
-        trow[2 * WAVE + lane] = my_off;
-        for (int p = 0; p < my_dc; ++p) slot[my_off + p] = (uint8_t)lane;
-      }
-      __syncthreads();
-      // new V2C messages of every edge of the touched checks (only n*'s changed)
-      for (int s = lane; s < T; s += WAVE) {
-        int q = slot[s];
-        int e = trow[WAVE + q] + (s - trow[2 * WAVE + q]);
-        vbuf[s] = ar.v2c((val_t)L[H.col[e]], (val_t)c2v[e]);
-      }
-      __syncthreads();
-      // precomputed C2V messages (eq. (2) over the other inputs), residual keys, Lt deltas
-      for (int s = lane; s < T; s += WAVE) {
-        int q = slot[s];
-        int off = trow[2 * WAVE + q];
-        int rs = trow[WAVE + q];
-        int dcq = H.row_ptr[trow[q] + 1] - rs;
-        int e = rs + (s - off);
-        int j = H.col[e];
-        val_t pv;
-        if (j == nstar) {
-          pv = (val_t)pre[e];  // inputs unchanged: same value as before
+      wave_sync();
+      PROF_MARK(1)
+
+      // ---- touched checks: V2C inputs, whole-row update, residual keys (one pass per 64 lanes) ----
+      for (int ps = 0; ps < npass; ++ps) {
+        int2 ent = ent0;
+        if (ps > 0) {
+          const int idx = ps * WAVE + lane;
+          ent = idx < ncnt ? H.nbr[noff + idx] : make_int2(-1, 0);
+        }
+        const int e = ent.x;
+        const bool valid = e >= 0;
+        const int j = ent.y & 0xFFFFFF;
+        const int L2 = (ent.y >> 24) & 7;
+        const bool leader = valid && ((ent.y >> 27) & 1);
+        const bool in_m = valid && e >= rs_m && e < re_m;
+        const bool self = valid && j == nstar;
+        val_t cv = 0, po = 0, lv = 0;
+        if (valid) {
+          cv = (val_t)c2v[e];
+          po = (val_t)pre[e];
+          lv = self ? Lnew : (val_t)L[j];
+        }
+        const val_t v = ar.vin(ar.v2c(lv, cv));
+        const int maxL2 = uni(L2);  // lane 0 starts the pass's largest block
+        RowRed r;
+        r.m1 = valid ? fabsf((float)v) : __builtin_inff();
+        r.m2 = __builtin_inff();
+        r.ap = (valid ? (uint32_t)e : 0x7FFFFFFFu) | (valid && v < 0 ? 0x80000000u : 0u);
+        const bool upd = valid && !in_m && !self;
+        val_t pv = po;
+        if constexpr (A::kFixed) {
+          rowred_all<false>(r, L2, maxL2);
+          const bool me = (uint32_t)e == (r.ap & 0x7FFFFFFFu);
+          const int mag = (int)(me ? r.m2 : r.m1);
+          const int o = (((r.ap >> 31) ^ (v < 0 ? 1u : 0u)) & 1u) ? -mag : mag;
+          if (upd) pv = o;
         } else {
-          bool first = true;
-          val_t acc = 0;
-          for (int k = 0; k < dcq; ++k) {
-            if (k == s - off) continue;
-            val_t v = ar.vin(vbuf[off + k]);
-            acc = first ? v : ar.op(acc, v);
-            first = false;
-          }
-          pv = acc;
-          val_t old = (val_t)pre[e];
+          const float ph = valid ? row_aux(ar, v) : 0.0f;
+          r.S = ph;
+          r.Sx = 0.0f;
+          rowred_all<true>(r, L2, maxL2);
+          const bool me = (uint32_t)e == (r.ap & 0x7FFFFFFFu);
+          const float mo = me ? r.m2 : r.m1;
+          const float Sj = me ? r.Sx : (ph == __builtin_inff() ? __builtin_inff() : r.S - ph);
+          const float mag = fminf(phi_f32(fmaxf(Sj, 0.0f)), mo);
+          const float o = (((r.ap >> 31) ^ (v < 0.0f ? 1u : 0u)) & 1u) ? -mag : mag;
+          if (upd) pv = o;
+        }
+        if (upd) {
           pre[e] = (msg_t)pv;
-          if (with_ci) {
-            if constexpr (A::kFixed) atomicAdd(&Lt[j], pv - old);
-            else atomicAdd(&Lt[j], pv - old);
-          }
+          if (with_ci) atomicAdd(&Lt[j], (llr_t)(pv - po));
         }
-        // residual key of this edge, kept in vbuf's companion region
-        reinterpret_cast<uint64_t*>(lds + P.off_kbuf)[s] = mkkey(ar.res(pv, (val_t)c2v[e]), (uint32_t)e);
-      }
-      __syncthreads();
-      // ---- check keys of the touched checks and of m* ----
-      {
-        // lanes q < dv: serial max over the row's slot keys (touched checks)
-        uint64_t* kbuf = reinterpret_cast<uint64_t*>(lds + P.off_kbuf);
-        uint64_t newk = 0, oldk = 0;
-        int myc = -1;
-        if (lane < dv && my_dc > 0) {
-          for (int p = 0; p < my_dc; ++p) newk = umax64(newk, kbuf[my_off + p]);
-          myc = my_row;
-        }
-        // m*: its residual at e* is now zero, others unchanged
-        const int rs_m = uni(H.row_ptr[mstar]);
-        const int dc_m = uni(H.row_ptr[mstar + 1]) - rs_m;
-        uint64_t km = 0;
-        for (int p = lane; p < dc_m; p += WAVE) {
-          int e = rs_m + p;
-          km = umax64(km, mkkey(ar.res((val_t)pre[e], (val_t)c2v[e]), (uint32_t)e));
-        }
-        km = wave_max_u64(km);
-        if (lane == dv) {  // one spare lane handles m* (dv < WAVE)
-          myc = mstar;
-          newk = km;
-        }
-        if (myc >= 0) {
-          oldk = ckey[myc];
-          ckey[myc] = newk;
-          int b = myc >> 6;
-          if (newk > oldk) {
-            atomicMax(reinterpret_cast<unsigned long long*>(&cblk[b]), (unsigned long long)newk);
-          }
-        }
-        __syncthreads();
-        if (myc >= 0 && newk < oldk && cblk[myc >> 6] == oldk) atomicOr(&cmask[(myc >> 6) >> 5], 1u << ((myc >> 6) & 31));
-        __syncthreads();
-        for (int w = 0; w < P.nbc_words; ++w) {
-          uint32_t bits = (uint32_t)uni((int)cmask[w]);
-          while (bits) {
-            int b = w * 32 + __builtin_ctz(bits);
-            bits &= bits - 1;
-            int m = b * WAVE + lane;
-            uint64_t k = m < M ? ckey[m] : 0ull;
-            k = wave_max_u64(k);
-            if (lane == 0) cblk[b] = k;
-          }
-          if (lane == 0) cmask[w] = 0u;
+        tj[ps * WAVE + lane] = upd ? j : -1;
+        const uint64_t rk = keymax_all(valid ? mkkey(ar.res(pv, cv), (uint32_t)e) : 0ull, L2, maxL2);
+        if (leader) {  // one lane per check: new residual key, block maximum
+          const int m = G.edge_row(e);
+          const uint64_t ok = ckey[m];
+          ckey[m] = rk;
+          if (rk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&cblk[m >> 6]), (unsigned long long)rk);
+          else if (rk < ok && cblk[m >> 6] == ok) atomicOr(&cmask[(m >> 6) >> 5], 1u << ((m >> 6) & 31));
         }
       }
-      // ---- CI of the VNs of the touched checks and of n* (Algorithm 1 line 12) ----
+      if constexpr (PRE_GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // pre[] stores done
+      wave_sync();
+      PROF_MARK(3)
+      // ---- CI of the VNs of the touched checks (Algorithm 1 line 12) ----
       if (with_ci) {
-        uint32_t newd = 0, oldd = 0;
-        int myj = -1;
-        // slots first, then n* on an extra pass lane
-        for (int s0 = 0; s0 < T + 1; s0 += WAVE) {
-          int s = s0 + lane;
-          myj = -1;
-          if (s < T) {
-            int q = slot[s];
-            int e = trow[WAVE + q] + (s - trow[2 * WAVE + q]);
-            int j = H.col[e];
-            if (j != nstar) myj = j;
-          } else if (s == T) {
-            myj = nstar;
+        for (int ps = 0; ps < npass; ++ps) {
+          const int j = tj[ps * WAVE + lane];
+          uint32_t nd = 0, od = 0;
+          if (j >= 0) {
+            nd = ar.ci((val_t)L[j], (val_t)Lt[j]);
+            od = D[j];
           }
-          if (myj >= 0) {
-            newd = ar.ci((val_t)L[myj], (val_t)Lt[myj]);
-            oldd = D[myj];
+          wave_sync();
+          if (j >= 0) {
+            D[j] = nd;
+            const uint64_t nk = mkkey(nd, (uint32_t)j), ok = mkkey(od, (uint32_t)j);
+            if (nk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&dblk[j >> 6]), (unsigned long long)nk);
+            else if (nk < ok && dblk[j >> 6] == ok) atomicOr(&dmask[(j >> 6) >> 5], 1u << ((j >> 6) & 31));
           }
-          __syncthreads();
-          if (myj >= 0) {
-            D[myj] = newd;
-            uint64_t nk = mkkey(newd, (uint32_t)myj), ok = mkkey(oldd, (uint32_t)myj);
-            if (nk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&dblk[myj >> 6]), (unsigned long long)nk);
-          }
-          __syncthreads();
-          if (myj >= 0) {
-            uint64_t nk = mkkey(newd, (uint32_t)myj), ok = mkkey(oldd, (uint32_t)myj);
-            if (nk < ok && dblk[myj >> 6] == ok) atomicOr(&dmask[(myj >> 6) >> 5], 1u << ((myj >> 6) & 31));
-          }
+          wave_sync();
         }
-        __syncthreads();
+      }
+      PROF_MARK(5)
+      // ---- blocks whose maximum leaf decreased ----
+      for (int w = 0; w < P.nbc_words; ++w) {
+        uint32_t bits = (uint32_t)uni((int)cmask[w]);
+        while (bits) {
+          const int b = w * 32 + __builtin_ctz(bits);
+          bits &= bits - 1;
+          const int m = b * WAVE + lane;
+          uint64_t k = m < M ? ckey[m] : 0ull;
+          k = wave_max_u64(k);
+          if (lane == 0) cblk[b] = k;
+        }
+        if (lane == 0) cmask[w] = 0u;
+      }
+      if (with_ci) {
         for (int w = 0; w < P.nbd_words; ++w) {
           uint32_t bits = (uint32_t)uni((int)dmask[w]);
           while (bits) {
-            int b = w * 32 + __builtin_ctz(bits);
+            const int b = w * 32 + __builtin_ctz(bits);
             bits &= bits - 1;
-            int n = b * WAVE + lane;
+            const int n = b * WAVE + lane;
             uint64_t k = n < N ? mkkey(D[n], (uint32_t)n) : 0ull;
             k = wave_max_u64(k);
             if (lane == 0) dblk[b] = k;
@@ -328,15 +394,23 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
           if (lane == 0) dmask[w] = 0u;
         }
       }
-      __syncthreads();
+      wave_sync();
+      PROF_MARK(6)
       if (P.out.trace && lane == 0) P.out.trace[(size_t)f * P.max_updates + t] = estar;
       t += 1;
-      if (ce > 0 && (t / ce) != (tprev / ce) && unsat == 0) done = true;
+      if (ce > 0) {
+        until_check -= 1;
+        if (until_check == 0) {
+          until_check = ce;
+          if (unsat == 0) done = true;
+        }
+      }
     }
+    PROF_FLUSH
 
-    // ---------------- outputs (a8) -----------------------------------------------------
+    // ---------------- outputs -----------------------------------------------------------
     for (int n = lane; n < N; n += WAVE) {
-      val_t l = (val_t)L[n];
+      const val_t l = (val_t)L[n];
       P.out.bits[(size_t)f * N + n] = l < 0 ? 1 : 0;
       if (P.out.llr_out) P.out.llr_out[(size_t)f * N + n] = ar.out_llr(l);
       if (P.out.dump_L) P.out.dump_L[(size_t)f * N + n] = ar.as_float(l);
@@ -352,31 +426,47 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
       if (P.out.steps_used) P.out.steps_used[f] = t;
       if (P.out.fallbacks) P.out.fallbacks[f] = nfall;
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
-template <class A, bool PG>
+template <class A, bool PG, int TP>
 static hipError_t launch_dyn(const DevCode& H, const DynParams& P, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_dynamic<A, PG>), dim3(grid), dim3(WAVE), P.lds_bytes, st, H, P);
+  hipLaunchKernelGGL((k_dynamic<A, PG, TP>), dim3(grid), dim3(WAVE), P.lds_bytes, st, H, P);
   return hipGetLastError();
 }
 
-hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, bool pre_global, int grid,
+template <class A, bool PG>
+static hipError_t launch_dyn_t(const DevCode& H, const DynParams& P, int topo, int grid, hipStream_t st) {
+  if (topo == TOPO_QC) return launch_dyn<A, PG, TOPO_QC>(H, P, grid, st);
+  if (topo == TOPO_LDS) return launch_dyn<A, PG, TOPO_LDS>(H, P, grid, st);
+  return launch_dyn<A, PG, TOPO_GLOBAL>(H, P, grid, st);
+}
+
+hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, bool pre_global, int topo, int grid,
                           hipStream_t st) {
-  if (fixed) return pre_global ? launch_dyn<ArithFix, true>(H, P, grid, st) : launch_dyn<ArithFix, false>(H, P, grid, st);
-  return pre_global ? launch_dyn<ArithF32, true>(H, P, grid, st) : launch_dyn<ArithF32, false>(H, P, grid, st);
+  if (fixed)
+    return pre_global ? launch_dyn_t<ArithFix, true>(H, P, topo, grid, st)
+                      : launch_dyn_t<ArithFix, false>(H, P, topo, grid, st);
+  return pre_global ? launch_dyn_t<ArithF32, true>(H, P, topo, grid, st)
+                    : launch_dyn_t<ArithF32, false>(H, P, topo, grid, st);
+}
+
+template <class A, bool PG, int TP>
+static hipError_t set_one(int bytes) {
+  return hipFuncSetAttribute((const void*)k_dynamic<A, PG, TP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t set_dynamic_lds_limit(int bytes) {
-  hipError_t e;
-  e = hipFuncSetAttribute((const void*)k_dynamic<ArithF32, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_dynamic<ArithF32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_dynamic<ArithFix, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_dynamic<ArithFix, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  hipError_t e = hipSuccess;
+#define LDPC_SET(A, PG, TP) \
+  if ((e = set_one<A, PG, TP>(bytes)) != hipSuccess) return e;
+  LDPC_SET(ArithF32, false, TOPO_GLOBAL) LDPC_SET(ArithF32, false, TOPO_LDS) LDPC_SET(ArithF32, false, TOPO_QC)
+  LDPC_SET(ArithF32, true, TOPO_GLOBAL) LDPC_SET(ArithF32, true, TOPO_LDS) LDPC_SET(ArithF32, true, TOPO_QC)
+  LDPC_SET(ArithFix, false, TOPO_GLOBAL) LDPC_SET(ArithFix, false, TOPO_LDS) LDPC_SET(ArithFix, false, TOPO_QC)
+  LDPC_SET(ArithFix, true, TOPO_GLOBAL) LDPC_SET(ArithFix, true, TOPO_LDS) LDPC_SET(ArithFix, true, TOPO_QC)
+#undef LDPC_SET
+  return e;
 }
 
 }  // namespace ldpc

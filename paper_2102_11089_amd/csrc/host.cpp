@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -20,6 +21,9 @@ struct ldpc_code {
   int M, N, E;
   int max_dv, max_dc, max_touch, n_layers, max_layer_edges;
   std::vector<int> h_row_ptr, h_col, h_layer_ptr;
+  std::vector<int> h_qc;  // quasi-cyclic base tables (empty for a plain CSR code)
+  int nbr_max_cnt;
+  int qc_Z, qc_mb, qc_nb, qc_nblk;
   int* d_buf;       // one device allocation holding every index array
   int* d_lut;       // 7 p0 tables (frac_bits 0..6), 257 entries each
   DevCode dev;
@@ -55,11 +59,21 @@ double round_half_away(double x) { return x < 0 ? -std::floor(-x + 0.5) : std::f
 // LDS layout of the single-edge / multi-edge dynamic decoders
 struct DynLayout {
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_ckey, off_dblk, off_cblk, off_dmask, off_cmask, off_syn;
-  int off_v, off_kbuf, off_slot, off_trow, off_lut, off_extra, total;
+  int off_v, off_pbuf, off_jbuf, off_kbuf, off_slot, off_trow, off_lut, off_topo, off_extra, total;
   int nbd, nbc, nbd_words, nbc_words;
 };
 
-DynLayout dyn_layout(const ldpc_code* c, bool fixed, bool pre_global, int extra_bytes) {
+// LDS bytes of a topology variant
+long long topo_bytes(const ldpc_code* c, int topo) {
+  if (topo == TOPO_QC) return c->h_qc.empty() ? -1 : (long long)c->h_qc.size() * 4;
+  if (topo == TOPO_LDS) {
+    const long long ints = (c->M + 1) + (c->N + 1) + 4LL * c->E;
+    return 4LL * (ints + (ints & 1)) + 8LL * c->N;
+  }
+  return 0;
+}
+
+DynLayout dyn_layout(const ldpc_code* c, bool fixed, bool pre_global, int topo, int extra_bytes) {
   DynLayout L{};
   const int msg = fixed ? 1 : 4, llr = 4, val = 4;
   L.nbd = (c->N + WAVE - 1) / WAVE;
@@ -78,11 +92,11 @@ DynLayout dyn_layout(const ldpc_code* c, bool fixed, bool pre_global, int extra_
   L.off_dmask = o; o = align16(o + L.nbd_words * 4);
   L.off_cmask = o; o = align16(o + L.nbc_words * 4);
   L.off_syn = o; o = align16(o + c->M);
-  L.off_v = o; o = align16(o + c->max_touch * val);
-  L.off_kbuf = o; o = align16(o + c->max_touch * 8);
-  L.off_slot = o; o = align16(o + c->max_touch);
-  L.off_trow = o; o = align16(o + 3 * WAVE * 4);
+  (void)val;
+  L.off_v = o; o = align16(o + NBR_PMAX * WAVE * 4);  // touched VN per two-hop table lane
+  L.off_pbuf = L.off_jbuf = L.off_kbuf = L.off_slot = L.off_trow = o;
   L.off_lut = o; if (fixed) o = align16(o + 257 * 4);
+  L.off_topo = o; o = align16(o + (int)std::max(0LL, topo_bytes(c, topo)));
   L.off_extra = o; o = align16(o + extra_bytes);
   L.total = o;
   return L;
@@ -106,8 +120,9 @@ const char* ldpc_strerror(int code) {
 
 int ldpc_last_hip_error(void) { return g_last_hip; }
 
-int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32_t* col_idx,
-                       const int32_t* layer_ptr, int32_t n_layers, ldpc_code** out) {
+static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32_t* col_idx,
+                       const int32_t* layer_ptr, int32_t n_layers, const std::vector<int>* qc, int qZ, int qmb,
+                       int qnb, int qnblk, ldpc_code** out) {
   if (!out) return LDPC_EINVAL;
   *out = nullptr;
   if (M <= 0 || N <= 0 || !row_ptr || !col_idx) return LDPC_EINVAL;
@@ -177,6 +192,41 @@ int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32
   c->max_layer_edges = 0;
   for (int l = 0; l < c->n_layers; ++l)
     c->max_layer_edges = std::max(c->max_layer_edges, row_ptr[lp[l + 1]] - row_ptr[lp[l]]);
+  // two-hop neighbourhood table: per VN, every check of the VN as an aligned power-of-two block
+  // of lanes (largest first, so every block starts at a multiple of its size), in VN order
+  std::vector<int> nbr, nbr_idx(2 * (size_t)N);
+  c->nbr_max_cnt = 0;
+  for (int n = 0; n < N; ++n) {
+    std::vector<std::pair<int, int>> blocks;  // (log2 size, check)
+    for (int k = col_ptr[n]; k < col_ptr[n + 1]; ++k) {
+      const int m = col_row[k], dc = row_ptr[m + 1] - row_ptr[m];
+      int l2 = 0;
+      while ((1 << l2) < dc) ++l2;
+      blocks.push_back({l2, m});
+    }
+    std::stable_sort(blocks.begin(), blocks.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    const int off = (int)(nbr.size() / 2);
+    for (auto& bk : blocks) {
+      const int l2 = bk.first, m = bk.second, rs = row_ptr[m], dc = row_ptr[m + 1] - rs;
+      if (l2 > 5) {
+        delete c;
+        return LDPC_EUNSUPPORTED;  // a check of degree > 32
+      }
+      for (int p = 0; p < (1 << l2); ++p) {
+        const bool valid = p < dc;
+        nbr.push_back(valid ? rs + p : -1);
+        nbr.push_back((valid ? col_idx[rs + p] : 0) | (l2 << 24) | ((p == 0 ? 1 : 0) << 27));
+      }
+    }
+    const int cnt = (int)(nbr.size() / 2) - off;
+    nbr_idx[2 * n] = off;
+    nbr_idx[2 * n + 1] = cnt;
+    c->nbr_max_cnt = std::max(c->nbr_max_cnt, cnt);
+  }
+  if (N >= (1 << 24)) {
+    delete c;
+    return LDPC_EUNSUPPORTED;
+  }
   // one device buffer: row_ptr, col, row_of, col_ptr, col_row, col_eid, layer_ptr, 7 LUTs
   std::vector<int> blob;
   auto put = [&](const std::vector<int>& v) {
@@ -192,6 +242,23 @@ int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32
     for (int x = -128; x <= 128; ++x)
       luts[f * 257 + x + 128] = (int)round_half_away(32767.0 * std::tanh(0.5 * std::ldexp((double)x, -f)));
   size_t o_lut = put(luts);
+  size_t o_nbr = put(nbr), o_nidx = put(nbr_idx);
+  size_t o_qc = 0;
+  if (qc) {
+    // per base column: (offset of the column's first VN, entries per VN); VNs of one column
+    // have equal check degrees, so off(j Z + c) = off(j Z) + c cnt
+    std::vector<int> q2 = *qc;
+    for (int j = 0; j < qnb; ++j) {
+      q2.push_back(nbr_idx[2 * ((size_t)j * qZ)]);
+      q2.push_back(nbr_idx[2 * ((size_t)j * qZ) + 1]);
+    }
+    c->h_qc = q2;
+    c->qc_Z = qZ;
+    c->qc_mb = qmb;
+    c->qc_nb = qnb;
+    c->qc_nblk = qnblk;
+    o_qc = put(c->h_qc);
+  }
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return LDPC_EHIP;
@@ -224,8 +291,96 @@ int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32
   d.col_eid = c->d_buf + o_ce;
   d.layer_ptr = c->d_buf + o_lp;
   c->d_lut = c->d_buf + o_lut;
+  d.nbr = reinterpret_cast<const int2*>(c->d_buf + o_nbr);
+  d.nbr_idx = reinterpret_cast<const int2*>(c->d_buf + o_nidx);
+  d.nbr_col = nullptr;
+  d.nbr_max_cnt = c->nbr_max_cnt;
+  d.qc = DevQC{};
+  if (qc) {
+    // table order: bdeg[mb], bptr[mb+1], brow[2 nblk], bcol_ptr[nb+1], bcol[4 nblk], rowmap[nblk]
+    const int* q0 = c->d_buf + o_qc;
+    d.qc.Z = qZ;
+    d.qc.mb = qmb;
+    d.qc.nb = qnb;
+    d.qc.nblk = qnblk;
+    d.qc.bdeg = q0;
+    d.qc.bptr = q0 + qmb;
+    d.qc.brow = d.qc.bptr + (qmb + 1);
+    d.qc.bcol_ptr = d.qc.brow + 2 * qnblk;
+    d.qc.bcol = d.qc.bcol_ptr + (qnb + 1);
+    d.qc.rowmap = d.qc.bcol + 4 * qnblk;
+    d.qc.words = (int)c->h_qc.size();
+    d.nbr_col = reinterpret_cast<const int2*>(d.qc.rowmap + qnblk);
+  }
   *out = c;
   return LDPC_OK;
+}
+
+int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32_t* col_idx,
+                       const int32_t* layer_ptr, int32_t n_layers, ldpc_code** out) {
+  return create_code(M, N, row_ptr, col_idx, layer_ptr, n_layers, nullptr, 0, 0, 0, 0, out);
+}
+
+int ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t* shift, ldpc_code** out) {
+  if (!out) return LDPC_EINVAL;
+  *out = nullptr;
+  if (mb <= 0 || nb <= 0 || Z <= 0 || !shift) return LDPC_EINVAL;
+  if ((long long)nb * Z > (1 << 26) || (long long)mb * Z > (1 << 26)) return LDPC_EINVAL;
+  std::vector<int> bdeg(mb, 0), bptr(mb + 1, 0), brow, bcol_ptr(nb + 1, 0), bcol, rowmap;
+  for (int i = 0; i < mb; ++i) {
+    for (int j = 0; j < nb; ++j) {
+      const int sh = shift[(size_t)i * nb + j];
+      if (sh < -1 || sh >= Z) return LDPC_EINVAL;
+      if (sh >= 0) {
+        brow.push_back(j);
+        brow.push_back(sh);
+        rowmap.push_back(i);
+        bdeg[i] += 1;
+        bcol_ptr[j + 1] += 1;
+      }
+    }
+    if (bdeg[i] < 2) return LDPC_EINVAL;
+    bptr[i + 1] = bptr[i] + bdeg[i];
+  }
+  const int nblk = bptr[mb];
+  for (int j = 0; j < nb; ++j) {
+    if (bcol_ptr[j + 1] < 1) return LDPC_EINVAL;
+    bcol_ptr[j + 1] += bcol_ptr[j];
+  }
+  bcol.assign(4 * (size_t)nblk, 0);
+  std::vector<int> fillc(bcol_ptr.begin(), bcol_ptr.end() - 1);
+  for (int i = 0; i < mb; ++i) {
+    for (int k = 0; k < bdeg[i]; ++k) {  // ascending i per column by construction
+      const int j = brow[2 * (bptr[i] + k)], sh = brow[2 * (bptr[i] + k) + 1];
+      const int x = fillc[j]++;
+      bcol[4 * x] = i;
+      bcol[4 * x + 1] = sh;
+      bcol[4 * x + 2] = k;
+    }
+  }
+  std::vector<int> qc;
+  qc.insert(qc.end(), bdeg.begin(), bdeg.end());
+  qc.insert(qc.end(), bptr.begin(), bptr.end());
+  qc.insert(qc.end(), brow.begin(), brow.end());
+  qc.insert(qc.end(), bcol_ptr.begin(), bcol_ptr.end());
+  qc.insert(qc.end(), bcol.begin(), bcol.end());
+  qc.insert(qc.end(), rowmap.begin(), rowmap.end());
+  // expanded CSR: check i Z + r meets VN j Z + ((r + shift) mod Z), VNs ascending (j ascending)
+  const int M = mb * Z, N = nb * Z;
+  std::vector<int> row_ptr(M + 1, 0), col((size_t)nblk * Z), layer(mb + 1);
+  for (int i = 0; i < mb; ++i) {
+    layer[i] = i * Z;
+    for (int r = 0; r < Z; ++r) {
+      const int m = i * Z + r;
+      row_ptr[m + 1] = row_ptr[m] + bdeg[i];
+      for (int k = 0; k < bdeg[i]; ++k) {
+        const int j = brow[2 * (bptr[i] + k)], sh = brow[2 * (bptr[i] + k) + 1];
+        col[row_ptr[m] + k] = j * Z + (r + sh) % Z;
+      }
+    }
+  }
+  layer[mb] = M;
+  return create_code(M, N, row_ptr.data(), col.data(), layer.data(), mb, &qc, Z, mb, nb, nblk, out);
 }
 
 int ldpc_code_info(const ldpc_code* c, ldpc_code_stats* out) {
@@ -237,8 +392,9 @@ int ldpc_code_info(const ldpc_code* c, ldpc_code_stats* out) {
   out->max_dc = c->max_dc;
   out->n_layers = c->n_layers;
   out->max_touch = c->max_touch;
-  out->lds_bytes_f32 = dyn_layout(c, false, false, 0).total;
-  out->lds_bytes_fix = dyn_layout(c, true, false, 0).total;
+  const int topo = c->h_qc.empty() ? TOPO_LDS : TOPO_QC;
+  out->lds_bytes_f32 = dyn_layout(c, false, false, topo, 0).total;
+  out->lds_bytes_fix = dyn_layout(c, true, false, topo, 0).total;
   return LDPC_OK;
 }
 
@@ -314,7 +470,7 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   }
 
   if (c->max_dv > WAVE - 1) return LDPC_EUNSUPPORTED;
-  if (c->max_touch > 255 * 64) return LDPC_EUNSUPPORTED;
+  if (c->nbr_max_cnt > NBR_PMAX * WAVE) return LDPC_EUNSUPPORTED;
 
   DynParams P{};
   P.kind = s->kind;
@@ -341,21 +497,51 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   }
   if (s->kind == LDPC_ME_CIRBP) return LDPC_EUNSUPPORTED;
 
+  // storage plan: pre[] in LDS if possible; topology as quasi-cyclic tables, LDS copies or
+  // global arrays, in that order of preference (overridable for tests through the environment)
   bool pre_global = false;
-  DynLayout Ly = dyn_layout(c, fixed, false, 0);
-  if (Ly.total > lds_limit) {
-    pre_global = true;
-    Ly = dyn_layout(c, fixed, true, 0);
-    if (Ly.total > lds_limit) return LDPC_ECAPACITY;
+  int topo = TOPO_GLOBAL;
+  DynLayout Ly{};
+  {
+    const char* ft = std::getenv("LDPCCI_TOPO");
+    const char* fp = std::getenv("LDPCCI_PRE");
+    std::vector<int> topos;
+    if (ft && !std::strcmp(ft, "global")) topos = {TOPO_GLOBAL};
+    else if (ft && !std::strcmp(ft, "lds")) topos = {TOPO_LDS};
+    else if (ft && !std::strcmp(ft, "qc") && !c->h_qc.empty()) topos = {TOPO_QC};
+    else topos = c->h_qc.empty() ? std::vector<int>{TOPO_LDS, TOPO_GLOBAL} : std::vector<int>{TOPO_QC, TOPO_GLOBAL};
+    std::vector<bool> pres = {false, true};
+    if (fp && !std::strcmp(fp, "global")) pres = {true};
+    if (fp && !std::strcmp(fp, "lds")) pres = {false};
+    bool found = false;
+    for (bool pg : pres) {
+      for (int tp : topos) {
+        DynLayout cand = dyn_layout(c, fixed, pg, tp, 0);
+        if (cand.total <= lds_limit) {
+          Ly = cand;
+          pre_global = pg;
+          topo = tp;
+          found = true;
+          break;
+        }
+      }
+      if (found) break;
+    }
+    if (!found) return LDPC_ECAPACITY;
   }
   P.off_c2v = Ly.off_c2v; P.off_pre = Ly.off_pre; P.off_L = Ly.off_L; P.off_Lt = Ly.off_Lt;
   P.off_D = Ly.off_D; P.off_ckey = Ly.off_ckey; P.off_dblk = Ly.off_dblk; P.off_cblk = Ly.off_cblk;
   P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
   P.off_kbuf = Ly.off_kbuf; P.off_slot = Ly.off_slot; P.off_trow = Ly.off_trow; P.off_lut = Ly.off_lut;
+  P.off_pbuf = Ly.off_pbuf; P.off_jbuf = Ly.off_jbuf; P.off_topo = Ly.off_topo;
   P.off_extra = Ly.off_extra;
   P.lds_bytes = Ly.total;
   P.nbd = Ly.nbd; P.nbc = Ly.nbc; P.nbd_words = Ly.nbd_words; P.nbc_words = Ly.nbc_words;
 
+  P.prof = nullptr;
+#ifdef LDPC_PROFILE
+  if (const char* pp = std::getenv("LDPCCI_PROF")) P.prof = (long long*)std::strtoull(pp, nullptr, 10);
+#endif
   hipError_t he = set_dynamic_lds_limit(lds_limit);
   if (he != hipSuccess) return hip_fail(he);
   int grid = B;
@@ -367,7 +553,7 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
     P.pre_global = scratch;
   }
-  he = launch_dynamic(c->dev, P, fixed, pre_global, grid, st);
+  he = launch_dynamic(c->dev, P, fixed, pre_global, topo, grid, st);
   if (scratch) (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
 }

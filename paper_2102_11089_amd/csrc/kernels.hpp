@@ -8,6 +8,7 @@
 namespace ldpc {
 
 enum Kind { KIND_FLOODING = 0, KIND_LAYERED = 1, KIND_RBP = 2, KIND_CIRBP = 3, KIND_ME_CIRBP = 4, KIND_REPLAY = 5 };
+enum Topo { TOPO_GLOBAL = 0, TOPO_LDS = 1, TOPO_QC = 2 };
 
 struct DecOut {
   uint8_t* bits;            // [B][N]
@@ -41,9 +42,10 @@ struct DynParams {
   unsigned long long seed;
   // LDS layout (byte offsets)
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_ckey, off_dblk, off_cblk, off_dmask, off_cmask;
-  int off_syn, off_v, off_kbuf, off_slot, off_trow, off_lut, off_extra;
+  int off_syn, off_v, off_pbuf, off_jbuf, off_kbuf, off_slot, off_trow, off_lut, off_topo, off_extra;
   int lds_bytes;
   int nbd, nbc, nbd_words, nbc_words;
+  long long* prof;          // development builds only: per-phase cycle sums (null otherwise)
 };
 
 struct BaseParams {
@@ -58,14 +60,14 @@ struct BaseParams {
   int lds_bytes;
 };
 
-hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, bool pre_global, int grid,
+hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, bool pre_global, int topo, int grid,
                           hipStream_t st);
 hipError_t set_dynamic_lds_limit(int bytes);
 hipError_t launch_baseline(const DevCode& H, const BaseParams& P, bool fixed, int grid, int block,
                            hipStream_t st);
 hipError_t set_baseline_lds_limit(int bytes);
-hipError_t launch_me(const DevCode& H, const DynParams& P, bool fixed, bool pre_global, int grid, int block,
-                     hipStream_t st);
+hipError_t launch_me(const DevCode& H, const DynParams& P, bool fixed, bool pre_global, int topo, int grid,
+                     int block, hipStream_t st);
 hipError_t set_me_lds_limit(int bytes);
 
 }  // namespace ldpc

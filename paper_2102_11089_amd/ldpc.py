@@ -26,7 +26,7 @@ FILL_LOWEST, FILL_HASH = 0, 1
 ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -4: "LDPC_ECAPACITY",
           -5: "LDPC_EUNSUPPORTED"}
 
-EXPORTS = ("ldpc_code_from_csr", "ldpc_code_info", "ldpc_code_free", "ldpc_decode", "ldpc_strerror",
+EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode", "ldpc_strerror",
            "ldpc_last_hip_error")
 
 
@@ -62,6 +62,8 @@ def load(path: str = LIB_PATH):
     P = C.c_void_p
     lib.ldpc_code_from_csr.argtypes = [C.c_int32, C.c_int32, P, P, P, C.c_int32, C.POINTER(C.c_void_p)]
     lib.ldpc_code_from_csr.restype = C.c_int
+    lib.ldpc_code_from_qc.argtypes = [C.c_int32, C.c_int32, C.c_int32, P, C.POINTER(C.c_void_p)]
+    lib.ldpc_code_from_qc.restype = C.c_int
     lib.ldpc_code_info.argtypes = [P, C.POINTER(ldpc_code_stats)]
     lib.ldpc_code_info.restype = C.c_int
     lib.ldpc_code_free.argtypes = [P]
@@ -98,6 +100,14 @@ def ldpc_code_from_csr(M: int, N: int, row_ptr: np.ndarray, col_idx: np.ndarray,
     return h.value
 
 
+def ldpc_code_from_qc(mb: int, nb: int, Z: int, shift: np.ndarray) -> int:
+    sh = np.ascontiguousarray(shift, dtype=np.int32)
+    assert sh.shape == (mb, nb)
+    h = C.c_void_p()
+    _check(load().ldpc_code_from_qc(mb, nb, Z, sh.ctypes.data, C.byref(h)), "ldpc_code_from_qc")
+    return h.value
+
+
 def ldpc_code_info(handle: int) -> ldpc_code_stats:
     st = ldpc_code_stats()
     _check(load().ldpc_code_info(handle, C.byref(st)), "ldpc_code_info")
@@ -120,11 +130,18 @@ def ldpc_decode(handle: int, schedule: ldpc_schedule, llr_ptr: int, B: int, max_
 # ----------------------------------------------------------------------------------------------
 class Code:
     """Owns a library code handle built from a ``synth.Code`` (or any object with M, N, row_ptr,
-    col and optional layer_ptr)."""
+    col and optional layer_ptr).  Quasi-cyclic codes (``qc_shift`` set) go through
+    ``ldpc_code_from_qc`` unless ``csr=True``."""
 
-    def __init__(self, code):
+    def __init__(self, code, csr: bool = False):
         self.M, self.N, self.E = int(code.M), int(code.N), int(code.row_ptr[-1])
-        self.handle = ldpc_code_from_csr(self.M, self.N, code.row_ptr, code.col, getattr(code, "layer_ptr", None))
+        sh = getattr(code, "qc_shift", None)
+        if sh is not None and not csr:
+            mb, nb = sh.shape
+            self.handle = ldpc_code_from_qc(mb, nb, int(code.qc_Z), sh)
+        else:
+            self.handle = ldpc_code_from_csr(self.M, self.N, code.row_ptr, code.col,
+                                             getattr(code, "layer_ptr", None))
         self.stats = ldpc_code_info(self.handle)
 
     def __del__(self):

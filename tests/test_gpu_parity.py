@@ -229,3 +229,27 @@ def test_edge_cases(gpu, c0):
     cw, llr = S.frames(code, 1, 2.0, 108)
     g = gpu_decode(gpu, ch, llr, "replay", gpu.SPA_F32, max_updates=4, replay=rep)
     assert int(np_(g.updates_used)[0]) == 2
+
+
+# ------------------------------------------------------------------------------------------
+# storage variants: every (pre location, topology source) combination is bit-exact
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("pre", ["lds", "global"])
+@pytest.mark.parametrize("topo", ["global", "lds", "qc"])
+def test_fixed_storage_variants(gpu, monkeypatch, pre, topo):
+    code = S.qc_24col(24, 12, seed=4)  # N = 576, quasi-cyclic
+    cw, llr = S.frames(code, 200, 2.0, 109)
+    ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True, dump=True,
+                   threads=8)
+    monkeypatch.setenv("LDPCCI_PRE", pre)
+    monkeypatch.setenv("LDPCCI_TOPO", topo)
+    handles = [gpu.Code(code)] if topo == "qc" else [gpu.Code(code), gpu.Code(code, csr=True)]
+    for h in handles:
+        say(f"[variant pre={pre} topo={topo}] qc24 Z=24")
+        g = gpu_decode(gpu, h, llr, "cirbp", gpu.MS_FIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True,
+                       dump=True)
+        np.testing.assert_array_equal(np_(g.trace), ref.trace)
+        np.testing.assert_array_equal(np_(g.bits), ref.bits)
+        np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+        np.testing.assert_array_equal(np_(g.c2v), ref.c2v)
+        np.testing.assert_array_equal(np_(g.D), ref.D)
