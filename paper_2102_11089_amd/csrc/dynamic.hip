@@ -36,60 +36,6 @@ namespace ldpc {
 #define PROF_FLUSH
 #endif
 
-// Copy the topology into LDS when requested and return the accessor.
-template <int TOPO>
-struct TopoSel;
-template <>
-struct TopoSel<TOPO_GLOBAL> {
-  using type = TopoCSR;
-  __device__ static type make(const DevCode& H, unsigned char*, int, int) {
-    TopoCSR t{H.row_ptr, H.col, H.row_of, H.col_ptr, H.col_row, H.col_eid};
-    t.nbr_idx = H.nbr_idx;
-    return t;
-  }
-};
-template <>
-struct TopoSel<TOPO_LDS> {
-  using type = TopoCSR;
-  __device__ static type make(const DevCode& H, unsigned char* base, int tid, int nthr) {
-    int* p = reinterpret_cast<int*>(base);
-    const int M = H.M, N = H.N, E = H.E;
-    int* row_ptr = p;
-    int* col = row_ptr + (M + 1);
-    int* row_of = col + E;
-    int* col_ptr = row_of + E;
-    int* col_row = col_ptr + (N + 1);
-    int* col_eid = col_row + E;
-    int2* nidx = reinterpret_cast<int2*>(col_eid + E + (((M + 1) + (N + 1)) & 1));
-    for (int x = tid; x <= M; x += nthr) row_ptr[x] = H.row_ptr[x];
-    for (int x = tid; x <= N; x += nthr) col_ptr[x] = H.col_ptr[x];
-    for (int x = tid; x < E; x += nthr) {
-      col[x] = H.col[x];
-      row_of[x] = H.row_of[x];
-      col_row[x] = H.col_row[x];
-      col_eid[x] = H.col_eid[x];
-    }
-    for (int x = tid; x < N; x += nthr) nidx[x] = H.nbr_idx[x];
-    TopoCSR t{row_ptr, col, row_of, col_ptr, col_row, col_eid};
-    t.nbr_idx = nidx;
-    return t;
-  }
-};
-template <>
-struct TopoSel<TOPO_QC> {
-  using type = TopoQC;
-  __device__ static type make(const DevCode& H, unsigned char* base, int tid, int nthr) {
-    int* p = reinterpret_cast<int*>(base);
-    const DevQC& q = H.qc;
-    for (int x = tid; x < q.words; x += nthr) p[x] = q.bdeg[x];  // tables are contiguous from bdeg
-    const int o_bptr = (int)(q.bptr - q.bdeg), o_brow = (int)(q.brow - q.bdeg);
-    const int o_bcp = (int)(q.bcol_ptr - q.bdeg), o_bcol = (int)(q.bcol - q.bdeg), o_rm = (int)(q.rowmap - q.bdeg);
-    TopoQC t{q.Z, p, p + o_bptr, p + o_brow, p + o_bcp, p + o_bcol, p + o_rm};
-    t.nbr_col = p + (int)(reinterpret_cast<const int*>(H.nbr_col) - q.bdeg);
-    return t;
-  }
-};
-
 template <class A, bool PRE_GLOBAL, int TOPO>
 __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
   extern __shared__ __align__(16) unsigned char lds[];

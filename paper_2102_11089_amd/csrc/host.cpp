@@ -102,6 +102,39 @@ DynLayout dyn_layout(const ldpc_code* c, bool fixed, bool pre_global, int topo, 
   return L;
 }
 
+
+// LDS layout of the multi-edge decoder; returns the total bytes
+struct MeLayout {
+  int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;
+  int off_cand, off_misc, off_lut, off_topo, total, rows_cap, cand_cap;
+};
+
+MeLayout me_layout(const ldpc_code* c, bool fixed, bool msg_global, int topo, int n_p, int n_g, int fill) {
+  MeLayout L{};
+  const int msg = fixed ? 1 : 4;
+  const int nsw = (c->M + 31) / 32, nvw = (c->N + 31) / 32;
+  L.rows_cap = n_p * c->max_dv;
+  L.cand_cap = fill == LDPC_FILL_HASH ? 512 : 0;
+  int o = 0;
+  L.off_c2v = o; if (!msg_global) o = align16(o + c->E * msg);
+  L.off_pre = o; if (!msg_global) o = align16(o + c->E * msg);
+  L.off_L = o; o = align16(o + c->N * 4);
+  L.off_Lt = o; o = align16(o + c->N * 4);
+  L.off_D = o; o = align16(o + c->N * 4);
+  L.off_hist = o; o = align16(o + n_g * 4);
+  L.off_synw = o; o = align16(o + nsw * 4);
+  L.off_rowmark = o; o = align16(o + nsw * 4);
+  L.off_vnmark = o; o = align16(o + nvw * 4);
+  L.off_rows = o; o = align16(o + L.rows_cap * 4);
+  L.off_sel = o; o = align16(o + 3 * 64 * 4);
+  L.off_cand = o; o = align16(o + L.cand_cap * 12);
+  L.off_misc = o; o = align16(o + 32 * 4);
+  L.off_lut = o; if (fixed) o = align16(o + 257 * 4);
+  L.off_topo = o; o = align16(o + (int)std::max(0LL, topo_bytes(c, topo)));
+  L.total = o;
+  return L;
+}
+
 }  // namespace
 
 extern "C" {
@@ -495,7 +528,65 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     float g = s->gamma;
     std::memcpy(&P.gamma_bits, &g, 4);
   }
-  if (s->kind == LDPC_ME_CIRBP) return LDPC_EUNSUPPORTED;
+  if (s->kind == LDPC_ME_CIRBP) {
+    MeParams Q{};
+    Q.B = B;
+    Q.max_updates = max_updates;
+    Q.check_every = s->check_every;
+    Q.llr = llr_in;
+    Q.out = o;
+    Q.qmax = qmax;
+    Q.scale = scale;
+    Q.lut_global = P.lut_global;
+    Q.n_p = s->n_p;
+    Q.n_g = s->n_g;
+    Q.fill = s->fill;
+    Q.seed = s->seed;
+    std::vector<int> topos = c->h_qc.empty() ? std::vector<int>{TOPO_LDS, TOPO_GLOBAL}
+                                             : std::vector<int>{TOPO_QC, TOPO_GLOBAL};
+    if (const char* ft = std::getenv("LDPCCI_TOPO")) {
+      if (!std::strcmp(ft, "global")) topos = {TOPO_GLOBAL};
+      else if (!std::strcmp(ft, "lds")) topos = {TOPO_LDS};
+    }
+    bool found = false, mg = false;
+    int topo = TOPO_GLOBAL;
+    MeLayout Ly{};
+    for (bool g : {false, true}) {
+      for (int tp : topos) {
+        MeLayout cand = me_layout(c, fixed, g, tp, s->n_p, s->n_g, s->fill);
+        if (cand.total <= lds_limit) {
+          Ly = cand;
+          mg = g;
+          topo = tp;
+          found = true;
+          break;
+        }
+      }
+      if (found) break;
+    }
+    if (!found) return LDPC_ECAPACITY;
+    Q.off_c2v = Ly.off_c2v; Q.off_pre = Ly.off_pre; Q.off_L = Ly.off_L; Q.off_Lt = Ly.off_Lt; Q.off_D = Ly.off_D;
+    Q.off_hist = Ly.off_hist; Q.off_synw = Ly.off_synw; Q.off_rowmark = Ly.off_rowmark; Q.off_vnmark = Ly.off_vnmark;
+    Q.off_rows = Ly.off_rows; Q.off_sel = Ly.off_sel; Q.off_cand = Ly.off_cand; Q.off_misc = Ly.off_misc;
+    Q.off_lut = Ly.off_lut; Q.off_topo = Ly.off_topo; Q.lds_bytes = Ly.total;
+    Q.rows_cap = Ly.rows_cap;
+    Q.cand_cap = Ly.cand_cap;
+    const int block = c->N <= 256 ? 64 : (c->N <= 2048 ? 256 : 1024);
+    hipError_t he = set_me_lds_limit(lds_limit);
+    if (he != hipSuccess) return hip_fail(he);
+    int grid = B;
+    void* scratch = nullptr;
+    if (mg) {
+      const int per_cu = std::max(1, (160 * 1024) / std::max(Q.lds_bytes, 1));
+      grid = (int)std::min<long long>(B, (long long)ncu * per_cu);
+      he = hipMallocAsync(&scratch, (size_t)grid * 2 * c->E * (fixed ? 1 : 4), st);
+      if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
+      Q.msg_global = scratch;
+    }
+    he = launch_me(c->dev, Q, fixed, mg, topo, grid, block, st);
+    if (scratch) (void)hipFreeAsync(scratch, st);
+    return he == hipSuccess ? LDPC_OK : hip_fail(he);
+  }
 
   // storage plan: pre[] in LDS if possible; topology as quasi-cyclic tables, LDS copies or
   // global arrays, in that order of preference (overridable for tests through the environment)

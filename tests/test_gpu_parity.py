@@ -253,3 +253,52 @@ def test_fixed_storage_variants(gpu, monkeypatch, pre, topo):
         np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
         np.testing.assert_array_equal(np_(g.c2v), ref.c2v)
         np.testing.assert_array_equal(np_(g.D), ref.D)
+
+
+# ------------------------------------------------------------------------------------------
+# ME-CIRBP (Algorithms 4 and 5)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("fill", [0, 1])
+@pytest.mark.parametrize("n_p,n_g", [(1, 16), (4, 4), (8, 16), (24, 8)])
+def test_fixed_me_bit_exact_c0(gpu, c0, n_p, n_g, fill):
+    code, ch = c0
+    cw, llr = S.frames(code, 300, 2.0, 110)
+    say(f"[fixed me] c0 n_p={n_p} n_g={n_g} fill={fill}")
+    kw = dict(max_updates=2400, n_p=n_p, n_g=n_g, fill=fill, seed=77, trace=True, dump=True)
+    ref = O.decode(code, llr, O.MECIRBP, O.MSFIX, q_bits=6, frac_bits=1, threads=8, **kw)
+    g = gpu_decode(gpu, ch, llr, "me", gpu.MS_FIX, q_bits=6, frac_bits=1, **kw)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    np.testing.assert_array_equal(np_(g.steps_used), ref.steps_used)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+    np.testing.assert_array_equal(np_(g.c2v), ref.c2v)
+    np.testing.assert_array_equal(np_(g.pre), ref.pre)
+    np.testing.assert_array_equal(np_(g.Lt), ref.Lt)
+    np.testing.assert_array_equal(np_(g.D), ref.D)
+
+
+def test_fixed_me_qc_and_bg1_z128(gpu):
+    for code, B, eb, n_p, mu in ((S.qc_24col(24, 8, seed=2), 64, 2.5, 16, 3000),
+                                 (S.workload_code("c3"), 2, 1.25, 32, 4000)):
+        h = gpu.Code(code)
+        cw, llr = S.frames(code, B, eb, 111)
+        say(f"[fixed me hash] {code.name} n_p={n_p}")
+        kw = dict(max_updates=mu, n_p=n_p, n_g=16, fill=1, seed=5, trace=True)
+        ref = O.decode(code, llr, O.MECIRBP, O.MSFIX, q_bits=8, frac_bits=2, threads=4, **kw)
+        g = gpu_decode(gpu, h, llr, "me", gpu.MS_FIX, q_bits=8, frac_bits=2, **kw)
+        np.testing.assert_array_equal(np_(g.trace), ref.trace)
+        np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+        np.testing.assert_array_equal(np_(g.bits), ref.bits)
+
+
+def test_f32_me_fer_within_interval_c0(gpu, c0):
+    code, ch = c0
+    cw, llr = S.frames(code, 1000, 2.0, 112)
+    say("[f32 me] c0 1000 frames n_p=8 hash fill")
+    kw = dict(max_updates=2400, n_p=8, n_g=16, fill=1, seed=9)
+    ref = O.decode(code, llr, O.MECIRBP, O.SPA, threads=8, **kw)
+    g = gpu_decode(gpu, ch, llr, "me", gpu.SPA_F32, **kw)
+    k_ref = int(np.any(ref.bits != cw, axis=1).sum())
+    k_gpu = int(np.any(np_(g.bits) != cw, axis=1).sum())
+    lo, hi = cp_interval(k_ref, 1000)
+    assert lo <= k_gpu / 1000 <= hi, (k_gpu, k_ref, lo, hi)
