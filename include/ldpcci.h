@@ -136,6 +136,33 @@ int ldpc_decode(const ldpc_code* code, const ldpc_schedule* schedule, const floa
                 int64_t max_updates, const int32_t* replay, int64_t replay_len,
                 const ldpc_outputs* out, void* stream);
 
+/* One frame of a batched launch (device memory, 40 bytes). */
+typedef struct {
+  int32_t code;        /* index into the codes array of ldpc_decode_batch                         */
+  int32_t kind;        /* LDPC_FLOODING, LDPC_LAYERED, LDPC_RBP or LDPC_CIRBP                     */
+  float gamma;         /* CIRBP threshold (>= 0)                                                   */
+  int32_t reserved;
+  int64_t max_updates; /* cap in C2V propagations                                                  */
+  int64_t llr_off;     /* element offset of the frame's N channel LLRs in llr_pool                 */
+  int64_t out_off;     /* element offset of the frame's N outputs in bits_pool and llr_out_pool    */
+} ldpc_frame_desc;
+
+/* Decode F frames of uneven codes and schedules in one persistent launch (the batched form of
+   ldpc_decode; the schedules are those of Sec. I, II-A and Algorithm 1).  codes: host array of
+   n_codes handles (1..64, all created on the current device).  s supplies the arithmetic (arith,
+   q_bits, frac_bits) and check_every for every frame; frames (device [F]) the rest.  Workers pull
+   frames from a device work queue in descriptor order (put the longest decodes first for the
+   best balance).  llr_pool (device, llr_len floats), bits_pool (device, out_len bytes),
+   llr_out_pool (device, out_len floats, nullable), updates_used / steps_used / fallbacks (device
+   [F], the latter two nullable).  A descriptor with an unknown code or schedule, a negative gamma
+   or cap, or an offset that does not leave room for N values in its pool is not decoded and gets
+   updates_used = -1.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (a code with VN degree > 63 or a
+   check of degree > 32), LDPC_ECAPACITY, LDPC_ENOMEM, LDPC_EHIP. */
+int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
+                      const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
+                      uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
+                      int64_t* steps_used, int64_t* fallbacks, void* stream);
+
 /* Human-readable name of an error code (static string). */
 const char* ldpc_strerror(int code);
 

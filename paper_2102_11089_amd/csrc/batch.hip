@@ -1,0 +1,219 @@
+// Persistent batched decoding of uneven frames on gfx950: one launch, many codes (lengths, rates)
+// and schedules (flooding, layered, RBP, CIRBP).
+//
+// Workers are single wavefronts.  Each pulls the next frame index from a device work queue
+// (atomic counter), reads the frame's descriptor {code, schedule, gamma, cap, LLR offset, output
+// offset}, loads the code's topology when it differs from the previous frame's, and decodes:
+//   RBP / CIRBP     the single-edge per-frame body shared with the per-code kernel,
+//   flooding        one lane per check: whole-row update from the previous V2C messages, then
+//                   L_n = channel + sum of C2V (one lane per VN), syndrome from scratch,
+//   layered         block rows in order, one lane per check of the layer (VN-disjoint rows).
+// LDS is laid out for the largest code of the launch.  Descriptors are checked on the device:
+// an unknown code or schedule or an offset outside the pools marks the frame with
+// updates_used = -1 and skips it.
+#include "dyn_frame.hpp"
+
+namespace ldpc {
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+// flooding / layered for one wavefront, state in the dynamic layout's c2v and L regions
+template <class A, class Topo>
+__device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
+                                                    const FrameJob& J) {
+  using msg_t = typename A::msg_t;
+  using llr_t = typename A::llr_t;
+  using val_t = typename A::val_t;
+  using Acc = typename RowAccOf<A>::type;
+  const int lane = threadIdx.x & (WAVE - 1);
+  unsigned char* lds = dyn_lds();
+  msg_t* c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
+  llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
+  const int N = H.N, M = H.M, E = H.E;
+  for (int n = lane; n < N; n += WAVE) L[n] = (llr_t)ar.channel(J.llr[n]);
+  for (int e = lane; e < E; e += WAVE) c2v[e] = (msg_t)0;
+  wave_sync();
+  auto syndrome = [&]() {
+    int u = 0;
+    for (int m = lane; m < M; m += WAVE) {
+      const int rs = G.row_start(m), dc = G.row_deg(m);
+      int par = 0;
+      for (int p = 0; p < dc; ++p) par ^= (val_t)L[G.row_vn(m, rs, p)] < 0 ? 1 : 0;
+      u += par;
+    }
+    return wave_sum_i32(u);
+  };
+  int unsat = syndrome();
+  long long t = 0, it = 0;
+  while (!(unsat == 0 && J.check_every > 0) && t + E <= J.max_updates) {
+    if (J.kind == KIND_FLOODING) {
+      for (int m = lane; m < M; m += WAVE) {
+        const int rs = G.row_start(m), dc = G.row_deg(m);
+        Acc acc;
+        for (int p = 0; p < dc; ++p) {
+          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)c2v[rs + p]));
+          acc.add(p, v, row_aux(ar, v));
+        }
+        for (int p = 0; p < dc; ++p) {
+          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)c2v[rs + p]));
+          c2v[rs + p] = (msg_t)acc.out(p, v, row_aux(ar, v));
+        }
+      }
+      wave_sync();
+      for (int n = lane; n < N; n += WAVE) {
+        val_t l = ar.channel(J.llr[n]);
+        const int dv = G.vn_deg(n);
+        for (int k = 0; k < dv; ++k) {
+          int m, e;
+          G.vn_edge(n, k, m, e);
+          l += (val_t)c2v[e];
+        }
+        L[n] = (llr_t)l;
+      }
+      wave_sync();
+    } else {
+      for (int l = 0; l < H.n_layers; ++l) {
+        const int r0 = H.layer_ptr[l], r1 = H.layer_ptr[l + 1];
+        for (int m = r0 + lane; m < r1; m += WAVE) {
+          const int rs = G.row_start(m), dc = G.row_deg(m);
+          Acc acc;
+          for (int p = 0; p < dc; ++p) {
+            const int j = G.row_vn(m, rs, p);
+            const val_t v = ar.vin((val_t)L[j] - (val_t)c2v[rs + p]);
+            acc.add(p, v, row_aux(ar, v));
+          }
+          for (int p = 0; p < dc; ++p) {
+            const int j = G.row_vn(m, rs, p);
+            const val_t vr = (val_t)L[j] - (val_t)c2v[rs + p];
+            const val_t v = ar.vin(vr);
+            const val_t o = acc.out(p, v, row_aux(ar, v));
+            c2v[rs + p] = (msg_t)o;
+            L[j] = (llr_t)(vr + o);
+          }
+        }
+        wave_sync();
+      }
+    }
+    t += E;
+    it += 1;
+    unsat = syndrome();
+  }
+  for (int n = lane; n < N; n += WAVE) {
+    const val_t l = (val_t)L[n];
+    J.bits[n] = l < 0 ? 1 : 0;
+    if (J.llr_out) J.llr_out[n] = ar.out_llr(l);
+  }
+  if (lane == 0) {
+    *J.updates_used = t;
+    if (J.steps_used) *J.steps_used = it;
+    if (J.fallbacks) *J.fallbacks = 0;
+  }
+  wave_sync();
+}
+
+template <class A, bool PRE_GLOBAL, int TOPO>
+__global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
+  using msg_t = typename A::msg_t;
+  const DynParams& P = B.P;
+  unsigned char* lds = dyn_lds();
+  const int lane = threadIdx.x;
+  msg_t* pre;
+  if constexpr (PRE_GLOBAL) pre = reinterpret_cast<msg_t*>(P.pre_global) + (size_t)blockIdx.x * B.max_E;
+  else pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
+  int* lut = reinterpret_cast<int*>(lds + P.off_lut);
+  A ar;
+  ar.qmax = P.qmax;
+  ar.scale = P.scale;
+  ar.lut = lut;
+  if constexpr (A::kFixed) {
+    for (int x = lane; x < 257; x += WAVE) lut[x] = P.lut_global[x];
+  }
+  int cur = -1;
+  typename TopoSel<TOPO>::type G{};
+  while (true) {
+    int f = 0;
+    if (lane == 0) f = atomicAdd(B.queue, 1);
+    f = uni(f);
+    if (f >= B.F) break;
+    const BatchFrame d = B.frames[f];
+    const bool kind_ok = d.kind == KIND_FLOODING || d.kind == KIND_LAYERED || d.kind == KIND_RBP || d.kind == KIND_CIRBP;
+    bool ok = d.code >= 0 && d.code < B.n_codes && kind_ok && d.max_updates >= 0 && d.llr_off >= 0 &&
+              d.out_off >= 0 && d.gamma >= 0.0f;
+    const DevCode& H = *B.codes[ok ? d.code : 0];
+    ok = ok && d.llr_off + H.N <= B.llr_len && d.out_off + H.N <= B.out_len;
+    if (!ok) {
+      if (lane == 0) {
+        B.updates_used[f] = -1;
+        if (B.steps_used) B.steps_used[f] = 0;
+      }
+      continue;
+    }
+    if (d.code != cur) {  // topology of a new code
+      wave_sync();
+      G = TopoSel<TOPO>::make(H, lds + P.off_topo, lane, WAVE);
+      cur = d.code;
+      wave_sync();
+    }
+    FrameJob J;
+    J.kind = d.kind;
+    if constexpr (A::kFixed) {
+      const float g = roundf(d.gamma * 65534.0f);
+      J.gamma_bits = g >= 4294967295.0f ? 0xFFFFFFFFu : (uint32_t)g;
+    } else {
+      J.gamma_bits = __float_as_uint(d.gamma);
+    }
+    J.max_updates = d.max_updates;
+    J.check_every = P.check_every;
+    J.llr = B.llr_pool + d.llr_off;
+    J.replay = nullptr;
+    J.replay_len = 0;
+    J.bits = B.bits_pool + d.out_off;
+    J.llr_out = B.llr_out_pool ? B.llr_out_pool + d.out_off : nullptr;
+    J.updates_used = B.updates_used + f;
+    J.steps_used = B.steps_used ? B.steps_used + f : nullptr;
+    J.fallbacks = B.fallbacks ? B.fallbacks + f : nullptr;
+    J.trace = nullptr;
+    J.dump_c2v = J.dump_pre = J.dump_L = J.dump_Lt = J.dump_D = nullptr;
+    if (d.kind == KIND_FLOODING || d.kind == KIND_LAYERED) wave_baseline_frame<A>(H, G, ar, P, J);
+    else dyn_decode_frame<A, PRE_GLOBAL>(H, G, ar, P, pre, J);
+  }
+}
+
+template <class A, bool PG, int TP>
+static hipError_t launch_batch_k(const BatchParams& B, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, B.queue);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_batch<A, PG, TP>), dim3(grid), dim3(WAVE), B.P.lds_bytes, st, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchParams& B, bool fixed, bool pre_global, int topo, int grid, hipStream_t st) {
+  if (fixed) {
+    if (topo == TOPO_QC) return pre_global ? launch_batch_k<ArithFix, true, TOPO_QC>(B, grid, st) : launch_batch_k<ArithFix, false, TOPO_QC>(B, grid, st);
+    return pre_global ? launch_batch_k<ArithFix, true, TOPO_GLOBAL>(B, grid, st) : launch_batch_k<ArithFix, false, TOPO_GLOBAL>(B, grid, st);
+  }
+  if (topo == TOPO_QC) return pre_global ? launch_batch_k<ArithF32, true, TOPO_QC>(B, grid, st) : launch_batch_k<ArithF32, false, TOPO_QC>(B, grid, st);
+  return pre_global ? launch_batch_k<ArithF32, true, TOPO_GLOBAL>(B, grid, st) : launch_batch_k<ArithF32, false, TOPO_GLOBAL>(B, grid, st);
+}
+
+template <class A, bool PG, int TP>
+static hipError_t set_batch_one(int bytes) {
+  return hipFuncSetAttribute((const void*)k_batch<A, PG, TP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t set_batch_lds_limit(int bytes) {
+  hipError_t e = hipSuccess;
+#define LDPC_SET(A, PG, TP) \
+  if ((e = set_batch_one<A, PG, TP>(bytes)) != hipSuccess) return e;
+  LDPC_SET(ArithF32, false, TOPO_GLOBAL) LDPC_SET(ArithF32, false, TOPO_QC)
+  LDPC_SET(ArithF32, true, TOPO_GLOBAL) LDPC_SET(ArithF32, true, TOPO_QC)
+  LDPC_SET(ArithFix, false, TOPO_GLOBAL) LDPC_SET(ArithFix, false, TOPO_QC)
+  LDPC_SET(ArithFix, true, TOPO_GLOBAL) LDPC_SET(ArithFix, true, TOPO_QC)
+#undef LDPC_SET
+  return e;
+}
+
+}  // namespace ldpc

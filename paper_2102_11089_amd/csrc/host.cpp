@@ -27,6 +27,7 @@ struct ldpc_code {
   int* d_buf;       // one device allocation holding every index array
   int* d_lut;       // 7 p0 tables (frac_bits 0..6), 257 entries each
   DevCode dev;
+  DevCode* d_self;  // device copy of dev (batched launches)
 };
 
 namespace {
@@ -73,33 +74,42 @@ long long topo_bytes(const ldpc_code* c, int topo) {
   return 0;
 }
 
-DynLayout dyn_layout(const ldpc_code* c, bool fixed, bool pre_global, int topo, int extra_bytes) {
+struct Dims {
+  int E, N, M;
+  long long topo_bytes;
+};
+
+DynLayout dyn_layout_dims(const Dims& c, bool fixed, bool pre_global, int extra_bytes) {
   DynLayout L{};
   const int msg = fixed ? 1 : 4, llr = 4, val = 4;
-  L.nbd = (c->N + WAVE - 1) / WAVE;
-  L.nbc = (c->M + WAVE - 1) / WAVE;
+  L.nbd = (c.N + WAVE - 1) / WAVE;
+  L.nbc = (c.M + WAVE - 1) / WAVE;
   L.nbd_words = (L.nbd + 31) / 32;
   L.nbc_words = (L.nbc + 31) / 32;
   int o = 0;
-  L.off_c2v = o; o = align16(o + c->E * msg);
-  L.off_pre = o; if (!pre_global) o = align16(o + c->E * msg);
-  L.off_L = o; o = align16(o + c->N * llr);
-  L.off_Lt = o; o = align16(o + c->N * llr);
-  L.off_D = o; o = align16(o + c->N * 4);
-  L.off_ckey = o; o = align16(o + c->M * 8);
+  L.off_c2v = o; o = align16(o + c.E * msg);
+  L.off_pre = o; if (!pre_global) o = align16(o + c.E * msg);
+  L.off_L = o; o = align16(o + c.N * llr);
+  L.off_Lt = o; o = align16(o + c.N * llr);
+  L.off_D = o; o = align16(o + c.N * 4);
+  L.off_ckey = o; o = align16(o + c.M * 8);
   L.off_dblk = o; o = align16(o + L.nbd * 8);
   L.off_cblk = o; o = align16(o + L.nbc * 8);
   L.off_dmask = o; o = align16(o + L.nbd_words * 4);
   L.off_cmask = o; o = align16(o + L.nbc_words * 4);
-  L.off_syn = o; o = align16(o + c->M);
+  L.off_syn = o; o = align16(o + c.M);
   (void)val;
   L.off_v = o; o = align16(o + NBR_PMAX * WAVE * 4);  // touched VN per two-hop table lane
   L.off_pbuf = L.off_jbuf = L.off_kbuf = L.off_slot = L.off_trow = o;
   L.off_lut = o; if (fixed) o = align16(o + 257 * 4);
-  L.off_topo = o; o = align16(o + (int)std::max(0LL, topo_bytes(c, topo)));
+  L.off_topo = o; o = align16(o + (int)std::max(0LL, c.topo_bytes));
   L.off_extra = o; o = align16(o + extra_bytes);
   L.total = o;
   return L;
+}
+
+DynLayout dyn_layout(const ldpc_code* c, bool fixed, bool pre_global, int topo, int extra_bytes) {
+  return dyn_layout_dims(Dims{c->E, c->N, c->M, topo_bytes(c, topo)}, fixed, pre_global, extra_bytes);
 }
 
 
@@ -345,6 +355,13 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
     d.qc.words = (int)c->h_qc.size();
     d.nbr_col = reinterpret_cast<const int2*>(d.qc.rowmap + qnblk);
   }
+  he = hipMalloc((void**)&c->d_self, sizeof(DevCode));
+  if (he == hipSuccess) he = hipMemcpy(c->d_self, &c->dev, sizeof(DevCode), hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    (void)hipFree(c->d_buf);
+    delete c;
+    return hip_fail(he);
+  }
   *out = c;
   return LDPC_OK;
 }
@@ -434,6 +451,7 @@ int ldpc_code_info(const ldpc_code* c, ldpc_code_stats* out) {
 void ldpc_code_free(ldpc_code* c) {
   if (!c) return;
   if (c->d_buf) (void)hipFree(c->d_buf);
+  if (c->d_self) (void)hipFree(c->d_self);
   delete c;
 }
 
@@ -646,6 +664,82 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   }
   he = launch_dynamic(c->dev, P, fixed, pre_global, topo, grid, st);
   if (scratch) (void)hipFreeAsync(scratch, st);
+  return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
+                      const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
+                      uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
+                      int64_t* steps_used, int64_t* fallbacks, void* stream) {
+  static_assert(sizeof(ldpc_frame_desc) == sizeof(BatchFrame), "descriptor layout");
+  if (!codes || n_codes < 1 || n_codes > 64 || !s || F < 0 || llr_len < 0 || out_len < 0) return LDPC_EINVAL;
+  if (F == 0) return LDPC_OK;
+  if (!frames || !llr_pool || !bits_pool || !updates_used) return LDPC_EINVAL;
+  if (s->arith != LDPC_SPA_F32 && s->arith != LDPC_MS_FIX) return LDPC_EINVAL;
+  const bool fixed = s->arith == LDPC_MS_FIX;
+  if (fixed && (s->q_bits < 2 || s->q_bits > 8 || s->frac_bits < 0 || s->frac_bits > 6)) return LDPC_EINVAL;
+  if (s->check_every < 0) return LDPC_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LDPC_EHIP;
+  bool all_qc = true;
+  Dims mx{0, 0, 0, 0};
+  for (int i = 0; i < n_codes; ++i) {
+    const ldpc_code* c = codes[i];
+    if (!c || c->device != dev) return LDPC_EINVAL;
+    if (c->max_dv > WAVE - 1 || c->nbr_max_cnt > NBR_PMAX * WAVE) return LDPC_EUNSUPPORTED;
+    all_qc = all_qc && !c->h_qc.empty();
+    mx.E = std::max(mx.E, c->E);
+    mx.N = std::max(mx.N, c->N);
+    mx.M = std::max(mx.M, c->M);
+  }
+  const int topo = all_qc ? TOPO_QC : TOPO_GLOBAL;
+  for (int i = 0; i < n_codes; ++i) mx.topo_bytes = std::max(mx.topo_bytes, topo_bytes(codes[i], topo));
+  const int lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
+  const int ncu = device_cu_count(dev);
+  bool pre_global = false;
+  DynLayout Ly = dyn_layout_dims(mx, fixed, false, 0);
+  if (Ly.total > lds_limit) {
+    pre_global = true;
+    Ly = dyn_layout_dims(mx, fixed, true, 0);
+    if (Ly.total > lds_limit) return LDPC_ECAPACITY;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  BatchParams B{};
+  DynParams& P = B.P;
+  P.check_every = s->check_every;
+  P.qmax = (1 << (std::max(s->q_bits, 2) - 1)) - 1;
+  P.scale = std::ldexp(1.0f, fixed ? s->frac_bits : 0);
+  P.lut_global = codes[0]->d_lut + 257 * (fixed ? s->frac_bits : 0);
+  P.off_c2v = Ly.off_c2v; P.off_pre = Ly.off_pre; P.off_L = Ly.off_L; P.off_Lt = Ly.off_Lt;
+  P.off_D = Ly.off_D; P.off_ckey = Ly.off_ckey; P.off_dblk = Ly.off_dblk; P.off_cblk = Ly.off_cblk;
+  P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
+  P.off_lut = Ly.off_lut; P.off_topo = Ly.off_topo;
+  P.lds_bytes = Ly.total;
+  B.n_codes = n_codes;
+  B.frames = reinterpret_cast<const BatchFrame*>(frames);
+  B.F = F;
+  B.llr_pool = llr_pool;
+  B.llr_len = llr_len;
+  B.bits_pool = bits_pool;
+  B.llr_out_pool = llr_out_pool;
+  B.out_len = out_len;
+  B.updates_used = updates_used;
+  B.steps_used = steps_used;
+  B.fallbacks = fallbacks;
+  B.max_E = mx.E;
+  const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(Ly.total, 1)));
+  const int grid = (int)std::min<long long>(F, (long long)ncu * per_cu);
+  // scratch: the work-queue counter and pre[] slots if needed
+  const size_t pre_bytes = pre_global ? (size_t)grid * mx.E * (fixed ? 1 : 4) : 0;
+  void* scratch = nullptr;
+  hipError_t he = hipMallocAsync(&scratch, 256 + pre_bytes, st);
+  if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
+  for (int i = 0; i < n_codes; ++i) B.codes[i] = codes[i]->d_self;
+  B.queue = reinterpret_cast<int*>(scratch);
+  P.pre_global = pre_global ? (char*)scratch + 256 : nullptr;
+  he = set_batch_lds_limit(lds_limit);
+  if (he == hipSuccess) he = launch_batch(B, fixed, pre_global, topo, grid, st);
+  (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
 }
 

@@ -48,6 +48,23 @@ struct DynParams {
   long long* prof;          // development builds only: per-phase cycle sums (null otherwise)
 };
 
+// one frame of a dynamic-schedule decode: limits and frame-local input/output pointers
+struct FrameJob {
+  int kind;
+  uint32_t gamma_bits;
+  long long max_updates, check_every;
+  const float* llr;         // N channel LLRs
+  const int32_t* replay;    // replay row (KIND_REPLAY)
+  long long replay_len;
+  uint8_t* bits;
+  float* llr_out;
+  int64_t* updates_used;
+  int64_t* steps_used;
+  int64_t* fallbacks;
+  int32_t* trace;           // trace row (max_updates entries)
+  float *dump_c2v, *dump_pre, *dump_L, *dump_Lt, *dump_D;
+};
+
 struct BaseParams {
   int kind;                 // KIND_FLOODING or KIND_LAYERED
   int B;
@@ -136,6 +153,35 @@ struct MeParams {
   int lds_bytes;
   int rows_cap, cand_cap;
 };
+
+// batched launch: one descriptor per frame (layout of ldpc_frame_desc)
+struct BatchFrame {
+  int32_t code, kind;
+  float gamma;
+  int32_t reserved;
+  int64_t max_updates, llr_off, out_off;
+};
+
+struct BatchParams {
+  DynParams P;              // arithmetic, LDS layout for the largest code, pre scratch
+  const DevCode* codes[64]; // device copies of the code descriptors
+  int n_codes;
+  const BatchFrame* frames; // [F] in device memory
+  int F;
+  const float* llr_pool;
+  long long llr_len;
+  uint8_t* bits_pool;
+  float* llr_out_pool;
+  long long out_len;
+  int64_t* updates_used;
+  int64_t* steps_used;
+  int64_t* fallbacks;
+  int* queue;               // work-queue counter
+  int max_E;
+};
+
+hipError_t launch_batch(const BatchParams& B, bool fixed, bool pre_global, int topo, int grid, hipStream_t st);
+hipError_t set_batch_lds_limit(int bytes);
 
 hipError_t launch_me(const DevCode& H, const MeParams& P, bool fixed, bool msg_global, int topo, int grid,
                      int block, hipStream_t st);

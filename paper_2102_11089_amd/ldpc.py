@@ -26,8 +26,12 @@ FILL_LOWEST, FILL_HASH = 0, 1
 ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -4: "LDPC_ECAPACITY",
           -5: "LDPC_EUNSUPPORTED"}
 
-EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode", "ldpc_strerror",
-           "ldpc_last_hip_error")
+EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode",
+           "ldpc_decode_batch", "ldpc_strerror", "ldpc_last_hip_error")
+
+# layout of ldpc_frame_desc (40 bytes)
+FRAME_DESC = np.dtype([("code", "<i4"), ("kind", "<i4"), ("gamma", "<f4"), ("reserved", "<i4"),
+                       ("max_updates", "<i8"), ("llr_off", "<i8"), ("out_off", "<i8")])
 
 
 class ldpc_schedule(C.Structure):
@@ -71,6 +75,9 @@ def load(path: str = LIB_PATH):
     lib.ldpc_decode.argtypes = [P, C.POINTER(ldpc_schedule), P, C.c_int32, C.c_int64, P, C.c_int64,
                                 C.POINTER(ldpc_outputs), P]
     lib.ldpc_decode.restype = C.c_int
+    lib.ldpc_decode_batch.argtypes = [P, C.c_int32, C.POINTER(ldpc_schedule), P, C.c_int32, P, C.c_int64, P, P,
+                                      C.c_int64, P, P, P, P]
+    lib.ldpc_decode_batch.restype = C.c_int
     lib.ldpc_strerror.argtypes = [C.c_int]
     lib.ldpc_strerror.restype = C.c_char_p
     lib.ldpc_last_hip_error.argtypes = []
@@ -123,6 +130,15 @@ def ldpc_decode(handle: int, schedule: ldpc_schedule, llr_ptr: int, B: int, max_
     rc = load().ldpc_decode(handle, C.byref(schedule), llr_ptr, B, max_updates, replay_ptr, replay_len,
                             C.byref(outputs), stream)
     _check(rc, "ldpc_decode")
+
+
+def ldpc_decode_batch(handles, schedule: ldpc_schedule, frames_ptr: int, F: int, llr_ptr: int, llr_len: int,
+                      bits_ptr: int, llr_out_ptr: Optional[int], out_len: int, upd_ptr: int, steps_ptr: Optional[int],
+                      fall_ptr: Optional[int], stream: int) -> None:
+    arr = (C.c_void_p * len(handles))(*handles)
+    rc = load().ldpc_decode_batch(arr, len(handles), C.byref(schedule), frames_ptr, F, llr_ptr, llr_len, bits_ptr,
+                                  llr_out_ptr, out_len, upd_ptr, steps_ptr, fall_ptr, stream)
+    _check(rc, "ldpc_decode_batch")
 
 
 # ----------------------------------------------------------------------------------------------
@@ -205,3 +221,25 @@ def decode(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int = 
     ldpc_decode(code.handle, s, llr.data_ptr(), B, max_updates, ptr(rep), rep_len, outs, st)
     return Decoded(bits, llr_out, upd, steps, fall, tr, d.get("c2v"), d.get("pre"), d.get("L"), d.get("Lt"),
                    d.get("D"))
+
+
+def decode_batch(codes, frames: np.ndarray, llr_pool, out_len: int, arith: int = SPA_F32, q_bits: int = 6,
+                 frac_bits: int = 1, check_every: int = 1, stream=None):
+    """Batched decode: ``codes`` is a list of ``Code``; ``frames`` a numpy array of FRAME_DESC;
+    ``llr_pool`` a float32 CUDA tensor.  Returns (bits_pool, llr_out_pool, updates_used,
+    steps_used, fallbacks) as device tensors."""
+    import torch
+    assert frames.dtype == FRAME_DESC
+    dev = llr_pool.device
+    F = len(frames)
+    fr = torch.from_numpy(np.ascontiguousarray(frames).view(np.uint8).copy()).to(dev)
+    bits = torch.zeros(out_len, dtype=torch.uint8, device=dev)
+    llr_out = torch.zeros(out_len, dtype=torch.float32, device=dev)
+    upd = torch.zeros(F, dtype=torch.int64, device=dev)
+    steps = torch.zeros(F, dtype=torch.int64, device=dev)
+    fall = torch.zeros(F, dtype=torch.int64, device=dev)
+    s = schedule(0, arith, 0.0, q_bits, frac_bits, 1, 16, 0, 0, check_every)
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    ldpc_decode_batch([c.handle for c in codes], s, fr.data_ptr(), F, llr_pool.data_ptr(), llr_pool.numel(),
+                      bits.data_ptr(), llr_out.data_ptr(), out_len, upd.data_ptr(), steps.data_ptr(), fall.data_ptr(), st)
+    return bits, llr_out, upd, steps, fall

@@ -302,3 +302,71 @@ def test_f32_me_fer_within_interval_c0(gpu, c0):
     k_gpu = int(np.any(np_(g.bits) != cw, axis=1).sum())
     lo, hi = cp_interval(k_ref, 1000)
     assert lo <= k_gpu / 1000 <= hi, (k_gpu, k_ref, lo, hi)
+
+
+# ------------------------------------------------------------------------------------------
+# persistent batched launch over uneven codes and schedules
+# ------------------------------------------------------------------------------------------
+def _mixed_batch(codes, F, seed, ebn0s=(1.5, 2.5, 3.5)):
+    from paper_2102_11089_amd import ldpc as L
+    rng = np.random.default_rng(seed)
+    frames = np.zeros(F, dtype=L.FRAME_DESC)
+    llrs, cws, per = [], [], []
+    off = 0
+    kinds = [L.FLOODING, L.LAYERED, L.RBP, L.CIRBP]
+    for f in range(F):
+        ci = int(rng.integers(len(codes)))
+        c = codes[ci]
+        kind = kinds[int(rng.integers(4))]
+        cw, llr = S.frames(c, 1, float(rng.choice(ebn0s)), seed * 1000 + f)
+        frames[f] = (ci, kind, 0.1, 0, (20 if kind in (L.FLOODING, L.LAYERED) else 3) * c.E, off, off)
+        llrs.append(llr[0]); cws.append(cw[0]); per.append((ci, kind, off))
+        off += c.N
+    return frames, np.concatenate(llrs).astype(np.float32), cws, per, off
+
+
+@pytest.mark.parametrize("arith", ["fix", "f32"])
+def test_batch_uneven_codes_and_schedules(gpu, arith):
+    codes = [S.qc_24col(24, 12, seed=1), S.qc_24col(48, 8, seed=1), S.qc_24col(24, 4, seed=1)]
+    hs = [gpu.Code(c) for c in codes]
+    frames, pool, cws, per, out_len = _mixed_batch(codes, 240, 3)
+    a = gpu.MS_FIX if arith == "fix" else gpu.SPA_F32
+    say(f"[batch {arith}] 240 frames over 3 codes and 4 schedules")
+    bits, llr_out, upd, steps, fall = gpu.decode_batch(hs, frames, torch.from_numpy(pool).cuda(), out_len, arith=a,
+                                                       q_bits=8, frac_bits=2)
+    torch.cuda.synchronize()
+    bits, upd = np_(bits), np_(upd)
+    kmap = {gpu.FLOODING: O.FLOODING, gpu.LAYERED: O.LAYERED, gpu.RBP: O.RBP, gpu.CIRBP: O.CIRBP}
+    errs_gpu = errs_ref = 0
+    for f, (ci, kind, off) in enumerate(per):
+        c = codes[ci]
+        llr = pool[off:off + c.N][None]
+        mu = int(frames[f]["max_updates"])
+        if arith == "fix":
+            ref = O.decode(c, llr, kmap[kind], O.MSFIX, max_updates=mu, q_bits=8, frac_bits=2)
+            assert int(upd[f]) == int(ref.updates_used[0]), (f, kind)
+            np.testing.assert_array_equal(bits[off:off + c.N], ref.bits[0])
+        elif kind in (gpu.RBP, gpu.CIRBP):  # same per-frame code path as the per-code kernel
+            g = gpu_decode(gpu, hs[ci], llr, "rbp" if kind == gpu.RBP else "cirbp", gpu.SPA_F32, max_updates=mu)
+            assert int(upd[f]) == int(np_(g.updates_used)[0])
+            np.testing.assert_array_equal(bits[off:off + c.N], np_(g.bits)[0])
+        else:
+            ref = O.decode(c, llr, kmap[kind], O.SPA, max_updates=mu)
+            errs_ref += int(np.any(ref.bits[0] != cws[f]))
+            errs_gpu += int(np.any(bits[off:off + c.N] != cws[f]))
+    assert abs(errs_gpu - errs_ref) <= 2
+
+
+def test_batch_rejects_bad_descriptors(gpu):
+    codes = [S.qc_24col(24, 12, seed=1)]
+    hs = [gpu.Code(codes[0])]
+    frames, pool, cws, per, out_len = _mixed_batch(codes, 6, 4)
+    frames[1]["code"] = 7          # unknown code
+    frames[2]["kind"] = 9          # unknown schedule
+    frames[3]["llr_off"] = len(pool) - 10   # LLRs past the end of the pool
+    frames[4]["gamma"] = -1.0      # negative threshold
+    bits, llr_out, upd, steps, fall = gpu.decode_batch(hs, frames, torch.from_numpy(pool).cuda(), out_len)
+    torch.cuda.synchronize()
+    u = np_(upd)
+    assert list(u[1:5]) == [-1, -1, -1, -1]
+    assert u[0] >= 0 and u[5] >= 0
