@@ -1,4 +1,4 @@
-"""Python access to the plain C oracle (``ldpc_oracle.c``).
+"""Python access to the plain C oracle (``ldpc_oracle.c``, ``unrolled_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline leg of the
 benchmark use it; the GPU library never does.  The oracle shares no code with the GPU path.
@@ -17,7 +17,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "ldpc_oracle.c")
+_SRCS = [os.path.join(_HERE, "ldpc_oracle.c"), os.path.join(_HERE, "unrolled_oracle.c")]
 _LIB = os.path.join(_HERE, "libldpc_oracle.so")
 
 FLOODING, LAYERED, RBP, CIRBP, MECIRBP, REPLAY = range(6)
@@ -28,9 +28,10 @@ COUNTERS = ("prop", "v2c", "pre", "ci", "ci_self", "fallback", "cmp", "steps")
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C, -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, _SRC,
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC", "-o", tmp, *_SRCS,
                                "-lm", "-lpthread"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -74,6 +75,12 @@ def lib():
         _lib.oc_alg4_select_keyed.restype = C.c_int32
         _lib.oc_alg4_select_keyed.argtypes = [C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                               C.c_void_p]
+        _lib.ou_forward.restype = C.c_int
+        _lib.ou_forward.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P, C.c_int32]
+        _lib.ou_backward.restype = C.c_int
+        _lib.ou_backward.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P, P, C.c_int32]
+        _lib.ou_boxplus_grad.restype = C.c_double
+        _lib.ou_boxplus_grad.argtypes = [C.c_double, C.c_double]
         _lib.oc_alg4_select.restype = C.c_int32
         _lib.oc_alg4_select.argtypes = [C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
     return _lib
@@ -101,6 +108,18 @@ class Result:
         return self.counters[:, COUNTERS.index(name)]
 
 
+def _code_struct(code):
+    """ctypes view of a ``synth.Code`` (the arrays in ``keep`` must outlive the call)."""
+    col_ptr, col_row, col_eid = code.csc()
+    keep = [np.ascontiguousarray(a, dtype=np.int32) for a in
+            (code.row_ptr, code.col, col_ptr, col_row, col_eid)]
+    lp = None if code.layer_ptr is None else np.ascontiguousarray(code.layer_ptr, dtype=np.int32)
+    keep.append(lp)
+    H = _Code(code.M, code.N, code.E, *[a.ctypes.data for a in keep[:5]],
+              0 if lp is None else len(lp) - 1, _ptr(lp))
+    return H, keep
+
+
 def decode(code, llr, kind: int, arith: int = SPA, max_updates: int = 0, gamma: float = 0.1,
            q_bits: int = 6, frac_bits: int = 1, n_p: int = 1, n_g: int = 16, check_every: int = 1,
            replay: Optional[np.ndarray] = None, trace: bool = False, dump: bool = False,
@@ -111,12 +130,7 @@ def decode(code, llr, kind: int, arith: int = SPA, max_updates: int = 0, gamma: 
         llr = llr[None]
     B, N = llr.shape
     assert N == code.N
-    col_ptr, col_row, col_eid = code.csc()
-    keep = [np.ascontiguousarray(a, dtype=np.int32) for a in
-            (code.row_ptr, code.col, col_ptr, col_row, col_eid)]
-    lp = None if code.layer_ptr is None else np.ascontiguousarray(code.layer_ptr, dtype=np.int32)
-    H = _Code(code.M, code.N, code.E, *[a.ctypes.data for a in keep],
-              0 if lp is None else len(lp) - 1, _ptr(lp))
+    H, keep = _code_struct(code)
     s = _Sched(kind, arith, q_bits, frac_bits, gamma, n_p, n_g, check_every, int(selfcheck), fill,
                seed & (2**64 - 1))
     bits = np.zeros((B, N), dtype=np.uint8)
@@ -180,3 +194,51 @@ def alg4_select_keyed(bins, n_g: int, n_p: int, keys) -> np.ndarray:
     out = np.zeros(len(bins), dtype=np.int32)
     k = lib().oc_alg4_select_keyed(len(bins), bins.ctypes.data, n_g, n_p, keys.ctypes.data, out.ctypes.data)
     return out[:k]
+
+
+# ----------------------------------------------------------------------------------------------
+# damped replay of a fixed schedule and its gradient (unrolled_oracle.c)
+# ----------------------------------------------------------------------------------------------
+def _unrolled_args(code, llr, w, trace):
+    llr = np.ascontiguousarray(np.asarray(llr, dtype=np.float64))
+    if llr.ndim == 1:
+        llr = llr[None]
+    tr = np.ascontiguousarray(trace, dtype=np.int32)
+    if tr.ndim == 1:
+        tr = tr[None]
+    w = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.float64), (code.E,)))
+    assert llr.shape[1] == code.N and tr.shape[0] == llr.shape[0]
+    return llr, w, tr
+
+
+def unrolled_forward(code, llr, w, trace, threads: int = 1):
+    """Damped replay of ``trace`` (B, T) from c2v = 0, L = llr: returns (L (B, N), c2v (B, E))."""
+    llr, w, tr = _unrolled_args(code, llr, w, trace)
+    B, T = tr.shape
+    H, keep = _code_struct(code)
+    L = np.zeros((B, code.N))
+    c2v = np.zeros((B, code.E))
+    rc = lib().ou_forward(C.byref(H), B, llr.ctypes.data, w.ctypes.data, tr.ctypes.data, T, L.ctypes.data,
+                          c2v.ctypes.data, threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle error {rc}")
+    return L, c2v
+
+
+def unrolled_backward(code, llr, w, trace, grad_L, threads: int = 1):
+    """Gradient through the damped replay: returns (d/d llr (B, N), per-frame d/d w (B, E))."""
+    llr, w, tr = _unrolled_args(code, llr, w, trace)
+    B, T = tr.shape
+    gL = np.ascontiguousarray(np.asarray(grad_L, dtype=np.float64).reshape(B, code.N))
+    H, keep = _code_struct(code)
+    g_llr = np.zeros((B, code.N))
+    g_w = np.zeros((B, code.E))
+    rc = lib().ou_backward(C.byref(H), B, llr.ctypes.data, w.ctypes.data, tr.ctypes.data, T, gL.ctypes.data,
+                           g_llr.ctypes.data, g_w.ctypes.data, threads)
+    if rc != 0:
+        raise RuntimeError(f"oracle error {rc}")
+    return g_llr, g_w
+
+
+def boxplus_grad(a: float, b: float) -> float:
+    return lib().ou_boxplus_grad(a, b)
