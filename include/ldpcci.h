@@ -163,6 +163,44 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
                       uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
                       int64_t* steps_used, int64_t* fallbacks, void* stream);
 
+/* ---- differentiable unrolled decoder ------------------------------------------------------
+   A schedule recorded by a single-edge decode (ldpc_outputs.trace of LDPC_RBP / LDPC_CIRBP with
+   check_every = 0, so that every frame runs exactly T updates) is replayed with a weight w_e per
+   edge.  From c2v = 0 and L = llr, step t on edge e = trace[f][t] (check m, VN n) does
+       c2v_e += w_e (pre_e - c2v_e),   L_n += the same amount,
+   where pre_e is the C2V rule of eq. (2) over the V2C messages L_k - c2v_{m->k}, k != n (the
+   propagation step of Sec. II-A, steps 3-4, which it equals for w_e = 1).  FP32 sum-product.
+   The schedule is held fixed: gradients do not flow through the selection. */
+
+#define LDPC_UNROLL_MAX_CKPT_EVERY 128
+
+/* Floats of checkpoint storage per frame: ceil(T / ckpt_every) * (E + N); negative on bad
+   arguments. */
+int64_t ldpc_unrolled_ckpt_floats(const ldpc_code* code, int32_t T, int32_t ckpt_every);
+
+/* Forward pass of B frames.  llr (device [B][N]), w (device [E]), trace (device [B][T] edge ids),
+   soft_out (device [B][N]): the final L; c2v_out (device [B][E], nullable): the final messages;
+   ckpt (device, B * ldpc_unrolled_ckpt_floats(code, T, ckpt_every) floats, nullable): the state
+   (c2v then L) at t = 0, ckpt_every, 2 ckpt_every, ... for ldpc_unrolled_backward.
+   ckpt_every in 1..LDPC_UNROLL_MAX_CKPT_EVERY.  A frame whose trace holds an id outside [0, E)
+   gets NaN outputs.  Enqueue-only on stream; the caller owns every buffer.
+   Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (a check of degree < 2 or > 32), LDPC_ECAPACITY,
+   LDPC_EHIP. */
+int ldpc_unrolled_forward(const ldpc_code* code, const float* llr, const float* w, const int32_t* trace,
+                          int32_t B, int32_t T, int32_t ckpt_every, float* ckpt, float* soft_out,
+                          float* c2v_out, void* stream);
+
+/* Adjoint of ldpc_unrolled_forward: given grad_soft = d loss / d soft_out (device [B][N]) and the
+   checkpoints the forward wrote with the same trace, w, T and ckpt_every, writes
+   grad_llr = d loss / d llr (device [B][N]) and grad_w = d loss / d w (device [E], the sum over
+   frames in a fixed order: bitwise reproducible).  Each segment of ckpt_every steps is recomputed
+   from its checkpoint.  A frame with an invalid trace id gets NaN in grad_llr and contributes NaN
+   to grad_w.  Allocates B * E + 64 * E floats of stream-ordered scratch.  Errors as above, plus
+   LDPC_ENOMEM. */
+int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t* trace, int32_t B, int32_t T,
+                           int32_t ckpt_every, const float* ckpt, const float* grad_soft, float* grad_llr,
+                           float* grad_w, void* stream);
+
 /* Human-readable name of an error code (static string). */
 const char* ldpc_strerror(int code);
 

@@ -19,7 +19,7 @@ using namespace ldpc;
 struct ldpc_code {
   int device;
   int M, N, E;
-  int max_dv, max_dc, max_touch, n_layers, max_layer_edges;
+  int max_dv, max_dc, min_dc, max_touch, n_layers, max_layer_edges;
   std::vector<int> h_row_ptr, h_col, h_layer_ptr;
   std::vector<int> h_qc;  // quasi-cyclic base tables (empty for a plain CSR code)
   int nbr_max_cnt;
@@ -118,6 +118,24 @@ struct MeLayout {
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;
   int off_cand, off_misc, off_lut, off_topo, total, rows_cap, cand_cap;
 };
+
+// LDS of the unrolled kernels: forward (c2v, L); backward adds the adjoints, the weight-gradient
+// row and the segment tape
+void unroll_layout(const ldpc_code* c, int K, UnrollParams& U) {
+  int o = 0;
+  U.off_c2v = o; o = align16(o + c->E * 4);
+  U.off_L = o; o = align16(o + c->N * 4);
+  U.lds_fwd = o;
+  U.off_ch = o; o = align16(o + c->E * 4);
+  U.off_Lh = o; o = align16(o + c->N * 4);
+  U.off_gw = o; o = align16(o + c->E * 4);
+  int ts = 1;
+  while (ts < c->max_dc) ts <<= 1;
+  U.tstride = ts;
+  U.off_tape = o; o = align16(o + K * ts * 8);
+  U.off_tape_hdr = o; o = align16(o + K * 32);
+  U.lds_bwd = o;
+}
 
 MeLayout me_layout(const ldpc_code* c, bool fixed, bool msg_global, int topo, int n_p, int n_g, int fill) {
   MeLayout L{};
@@ -225,7 +243,11 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
   }
   c->max_dv = *std::max_element(vdeg.begin(), vdeg.end());
   c->max_dc = 0;
-  for (int m = 0; m < M; ++m) c->max_dc = std::max(c->max_dc, row_ptr[m + 1] - row_ptr[m]);
+  c->min_dc = M > 0 ? row_ptr[1] - row_ptr[0] : 0;
+  for (int m = 0; m < M; ++m) {
+    c->max_dc = std::max(c->max_dc, row_ptr[m + 1] - row_ptr[m]);
+    c->min_dc = std::min(c->min_dc, row_ptr[m + 1] - row_ptr[m]);
+  }
   c->max_touch = 0;
   for (int n = 0; n < N; ++n) {
     int s = 0;
@@ -739,6 +761,74 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   P.pre_global = pre_global ? (char*)scratch + 256 : nullptr;
   he = set_batch_lds_limit(lds_limit);
   if (he == hipSuccess) he = launch_batch(B, fixed, pre_global, topo, grid, st);
+  (void)hipFreeAsync(scratch, st);
+  return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+// ------------------------------------------------------------------------------------------
+// differentiable unrolled decoder
+// ------------------------------------------------------------------------------------------
+static int unroll_check(const ldpc_code* c, int32_t B, int32_t T, int32_t K, int* dev) {
+  if (!c || B < 0 || T < 0 || K < 1 || K > LDPC_UNROLL_MAX_CKPT_EVERY) return LDPC_EINVAL;
+  if (hipGetDevice(dev) != hipSuccess) return LDPC_EHIP;
+  if (c->device != *dev) return LDPC_EINVAL;
+  if (c->min_dc < 2 || c->max_dc > 32) return LDPC_EUNSUPPORTED;
+  return LDPC_OK;
+}
+
+int64_t ldpc_unrolled_ckpt_floats(const ldpc_code* c, int32_t T, int32_t ckpt_every) {
+  if (!c || T < 0 || ckpt_every < 1 || ckpt_every > LDPC_UNROLL_MAX_CKPT_EVERY) return LDPC_EINVAL;
+  return (int64_t)((T + ckpt_every - 1) / ckpt_every) * (int64_t)(c->E + c->N);
+}
+
+int ldpc_unrolled_forward(const ldpc_code* c, const float* llr, const float* w, const int32_t* trace, int32_t B,
+                          int32_t T, int32_t ckpt_every, float* ckpt, float* soft_out, float* c2v_out,
+                          void* stream) {
+  int dev = 0;
+  int rc = unroll_check(c, B, T, ckpt_every, &dev);
+  if (rc != LDPC_OK) return rc;
+  if (B == 0) return LDPC_OK;
+  if (!llr || !w || !soft_out || (T > 0 && !trace)) return LDPC_EINVAL;
+  UnrollParams U{};
+  unroll_layout(c, ckpt_every, U);
+  const int lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
+  if (U.lds_fwd > lds_limit) return LDPC_ECAPACITY;
+  U.B = B; U.T = T; U.ckpt_every = ckpt_every; U.n_ckpt = (T + ckpt_every - 1) / ckpt_every;
+  U.llr = llr; U.w = w; U.trace = trace; U.ckpt = ckpt; U.soft_out = soft_out; U.c2v_out = c2v_out;
+  const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(U.lds_fwd, 1)));
+  const int grid = (int)std::min<long long>(B, (long long)device_cu_count(dev) * per_cu);
+  hipError_t he = set_unroll_lds_limit(lds_limit);
+  if (he == hipSuccess) he = launch_unroll_fwd(c->dev, U, grid, (hipStream_t)stream);
+  return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+int ldpc_unrolled_backward(const ldpc_code* c, const float* w, const int32_t* trace, int32_t B, int32_t T,
+                           int32_t ckpt_every, const float* ckpt, const float* grad_soft, float* grad_llr,
+                           float* grad_w, void* stream) {
+  int dev = 0;
+  int rc = unroll_check(c, B, T, ckpt_every, &dev);
+  if (rc != LDPC_OK) return rc;
+  if (!grad_w) return LDPC_EINVAL;
+  if (B > 0 && (!w || !grad_soft || !grad_llr || (T > 0 && (!trace || !ckpt)))) return LDPC_EINVAL;
+  UnrollParams U{};
+  unroll_layout(c, ckpt_every, U);
+  const int lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
+  if (U.lds_bwd > lds_limit) return LDPC_ECAPACITY;
+  U.B = B; U.T = T; U.ckpt_every = ckpt_every; U.n_ckpt = (T + ckpt_every - 1) / ckpt_every;
+  U.w = w; U.trace = trace; U.ckpt = const_cast<float*>(ckpt); U.grad_soft = grad_soft; U.grad_llr = grad_llr;
+  hipStream_t st = (hipStream_t)stream;
+  const int nch = std::max(1, std::min(64, (int)B));
+  const int chunk = B > 0 ? (B + nch - 1) / nch : 1;
+  const size_t part_bytes = (size_t)B * c->E * 4, chunk_bytes = (size_t)nch * c->E * 4;
+  void* scratch = nullptr;
+  hipError_t he = hipMallocAsync(&scratch, part_bytes + chunk_bytes, st);
+  if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
+  U.gw_part = reinterpret_cast<float*>(scratch);
+  float* chunks = reinterpret_cast<float*>((char*)scratch + part_bytes);
+  const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(U.lds_bwd, 1)));
+  const int grid = (int)std::max<long long>(1, std::min<long long>(B, (long long)device_cu_count(dev) * per_cu));
+  he = set_unroll_lds_limit(lds_limit);
+  if (he == hipSuccess) he = launch_unroll_bwd(c->dev, U, grid, chunks, nch, chunk, grad_w, st);
   (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
 }

@@ -180,6 +180,26 @@ struct BatchParams {
   int max_E;
 };
 
+// damped replay of a fixed schedule (forward with checkpoints) and its adjoint
+struct UnrollParams {
+  int B, T, ckpt_every, n_ckpt, tstride;
+  const float* llr;        // [B][N]
+  const float* w;          // [E]
+  const int* trace;        // [B][T]
+  float* ckpt;             // [B][n_ckpt][E + N] (c2v then L at t = 0, K, 2K, ...)
+  float* soft_out;         // [B][N]
+  float* c2v_out;          // [B][E] or null
+  const float* grad_soft;  // [B][N]
+  float* grad_llr;         // [B][N]
+  float* gw_part;          // [B][E] per-frame weight gradients (scratch)
+  int off_c2v, off_L, off_ch, off_Lh, off_gw, off_tape, off_tape_hdr;
+  int lds_fwd, lds_bwd;
+};
+hipError_t launch_unroll_fwd(const DevCode& H, const UnrollParams& U, int grid, hipStream_t st);
+hipError_t launch_unroll_bwd(const DevCode& H, const UnrollParams& U, int grid, float* chunks, int nch, int chunk,
+                             float* grad_w, hipStream_t st);
+hipError_t set_unroll_lds_limit(int bytes);
+
 hipError_t launch_batch(const BatchParams& B, bool fixed, bool pre_global, int topo, int grid, hipStream_t st);
 hipError_t set_batch_lds_limit(int bytes);
 

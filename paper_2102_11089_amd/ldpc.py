@@ -27,7 +27,9 @@ ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -
           -5: "LDPC_EUNSUPPORTED"}
 
 EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode",
-           "ldpc_decode_batch", "ldpc_strerror", "ldpc_last_hip_error")
+           "ldpc_decode_batch", "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
+           "ldpc_strerror", "ldpc_last_hip_error")
+UNROLL_MAX_CKPT_EVERY = 128
 
 # layout of ldpc_frame_desc (40 bytes)
 FRAME_DESC = np.dtype([("code", "<i4"), ("kind", "<i4"), ("gamma", "<f4"), ("reserved", "<i4"),
@@ -78,6 +80,12 @@ def load(path: str = LIB_PATH):
     lib.ldpc_decode_batch.argtypes = [P, C.c_int32, C.POINTER(ldpc_schedule), P, C.c_int32, P, C.c_int64, P, P,
                                       C.c_int64, P, P, P, P]
     lib.ldpc_decode_batch.restype = C.c_int
+    lib.ldpc_unrolled_ckpt_floats.argtypes = [P, C.c_int32, C.c_int32]
+    lib.ldpc_unrolled_ckpt_floats.restype = C.c_int64
+    lib.ldpc_unrolled_forward.argtypes = [P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P]
+    lib.ldpc_unrolled_forward.restype = C.c_int
+    lib.ldpc_unrolled_backward.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P]
+    lib.ldpc_unrolled_backward.restype = C.c_int
     lib.ldpc_strerror.argtypes = [C.c_int]
     lib.ldpc_strerror.restype = C.c_char_p
     lib.ldpc_last_hip_error.argtypes = []
@@ -139,6 +147,26 @@ def ldpc_decode_batch(handles, schedule: ldpc_schedule, frames_ptr: int, F: int,
     rc = load().ldpc_decode_batch(arr, len(handles), C.byref(schedule), frames_ptr, F, llr_ptr, llr_len, bits_ptr,
                                   llr_out_ptr, out_len, upd_ptr, steps_ptr, fall_ptr, stream)
     _check(rc, "ldpc_decode_batch")
+
+
+def ldpc_unrolled_ckpt_floats(handle, T: int, ckpt_every: int) -> int:
+    n = load().ldpc_unrolled_ckpt_floats(handle, T, ckpt_every)
+    _check(int(n) if n < 0 else 0, "ldpc_unrolled_ckpt_floats")
+    return int(n)
+
+
+def ldpc_unrolled_forward(handle, llr_ptr, w_ptr, trace_ptr, B, T, ckpt_every, ckpt_ptr, soft_ptr, c2v_ptr,
+                          stream) -> None:
+    rc = load().ldpc_unrolled_forward(handle, llr_ptr, w_ptr, trace_ptr, B, T, ckpt_every, ckpt_ptr, soft_ptr,
+                                      c2v_ptr, stream)
+    _check(rc, "ldpc_unrolled_forward")
+
+
+def ldpc_unrolled_backward(handle, w_ptr, trace_ptr, B, T, ckpt_every, ckpt_ptr, grad_soft_ptr, grad_llr_ptr,
+                           grad_w_ptr, stream) -> None:
+    rc = load().ldpc_unrolled_backward(handle, w_ptr, trace_ptr, B, T, ckpt_every, ckpt_ptr, grad_soft_ptr,
+                                       grad_llr_ptr, grad_w_ptr, stream)
+    _check(rc, "ldpc_unrolled_backward")
 
 
 # ----------------------------------------------------------------------------------------------
@@ -243,3 +271,87 @@ def decode_batch(codes, frames: np.ndarray, llr_pool, out_len: int, arith: int =
     ldpc_decode_batch([c.handle for c in codes], s, fr.data_ptr(), F, llr_pool.data_ptr(), llr_pool.numel(),
                       bits.data_ptr(), llr_out.data_ptr(), out_len, upd.data_ptr(), steps.data_ptr(), fall.data_ptr(), st)
     return bits, llr_out, upd, steps, fall
+
+
+# ----------------------------------------------------------------------------------------------
+# differentiable unrolled decoder
+# ----------------------------------------------------------------------------------------------
+def record_schedule(code: Code, llr, T: int, kind: int = CIRBP, gamma: float = 0.1, stream=None):
+    """Record T single-edge updates per frame (no early stop): an int32 (B, T) CUDA tensor."""
+    assert kind in (RBP, CIRBP)
+    return decode(code, llr, kind, SPA_F32, max_updates=T, gamma=gamma, check_every=0, trace=True,
+                  stream=stream).trace
+
+
+def unrolled_forward(code: Code, llr, w, trace, ckpt_every: int = 32, checkpoints: bool = True,
+                     c2v: bool = False, stream=None):
+    """Damped replay of ``trace`` (B, T): returns (soft L (B, N), checkpoints or None, c2v or None)."""
+    import torch
+    assert llr.is_cuda and llr.dtype == torch.float32 and llr.dim() == 2 and llr.shape[1] == code.N
+    llr = llr.contiguous()
+    w = w.to(device=llr.device, dtype=torch.float32).contiguous()
+    tr = trace.to(device=llr.device, dtype=torch.int32).contiguous()
+    B, T = int(tr.shape[0]), int(tr.shape[1])
+    assert B == llr.shape[0] and w.numel() == code.E
+    soft = torch.empty((B, code.N), dtype=torch.float32, device=llr.device)
+    ck = None
+    if checkpoints:
+        ck = torch.empty(max(1, B * ldpc_unrolled_ckpt_floats(code.handle, T, ckpt_every)), dtype=torch.float32,
+                         device=llr.device)
+    c2v_out = torch.empty((B, code.E), dtype=torch.float32, device=llr.device) if c2v else None
+    st = (stream if stream is not None else torch.cuda.current_stream(llr.device)).cuda_stream
+    ptr = lambda t: None if t is None else t.data_ptr()
+    ldpc_unrolled_forward(code.handle, llr.data_ptr(), w.data_ptr(), tr.data_ptr(), B, T, ckpt_every, ptr(ck),
+                          soft.data_ptr(), ptr(c2v_out), st)
+    return soft, ck, c2v_out
+
+
+def unrolled_backward(code: Code, w, trace, ckpt, grad_soft, ckpt_every: int = 32, stream=None):
+    """Adjoint of ``unrolled_forward``: returns (d/d llr (B, N), d/d w (E,))."""
+    import torch
+    dev = grad_soft.device
+    w = w.to(device=dev, dtype=torch.float32).contiguous()
+    tr = trace.to(device=dev, dtype=torch.int32).contiguous()
+    gs = grad_soft.to(dtype=torch.float32).contiguous()
+    B, T = int(tr.shape[0]), int(tr.shape[1])
+    g_llr = torch.empty((B, code.N), dtype=torch.float32, device=dev)
+    g_w = torch.empty(code.E, dtype=torch.float32, device=dev)
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    ldpc_unrolled_backward(code.handle, w.data_ptr(), tr.data_ptr(), B, T, ckpt_every, ckpt.data_ptr(),
+                           gs.data_ptr(), g_llr.data_ptr(), g_w.data_ptr(), st)
+    return g_llr, g_w
+
+
+_unrolled_fn = None
+
+
+def _unrolled_function():
+    global _unrolled_fn
+    if _unrolled_fn is None:
+        import torch
+
+        class UnrolledDecode(torch.autograd.Function):
+            """soft = replay(llr, w; fixed trace); gradients by the hand-written adjoint kernel."""
+
+            @staticmethod
+            def forward(ctx, llr, w, code, trace, ckpt_every):
+                soft, ck, _ = unrolled_forward(code, llr.detach(), w.detach(), trace, ckpt_every)
+                ctx.code = code
+                ctx.ckpt_every = ckpt_every
+                ctx.save_for_backward(w.detach(), trace, ck)
+                return soft
+
+            @staticmethod
+            def backward(ctx, grad_soft):
+                w, trace, ck = ctx.saved_tensors
+                g_llr, g_w = unrolled_backward(ctx.code, w, trace, ck, grad_soft, ctx.ckpt_every)
+                return (g_llr if ctx.needs_input_grad[0] else None, g_w if ctx.needs_input_grad[1] else None,
+                        None, None, None)
+
+        _unrolled_fn = UnrolledDecode
+    return _unrolled_fn
+
+
+def unrolled_decode(code: Code, llr, w, trace, ckpt_every: int = 32):
+    """Differentiable soft output of the damped replay (torch.autograd.Function)."""
+    return _unrolled_function().apply(llr, w, code, trace, ckpt_every)

@@ -80,3 +80,13 @@ def test_decode_rejects_null_arguments():
     s = ldpc.schedule(ldpc.CIRBP)
     out = ldpc.ldpc_outputs()
     assert lib.ldpc_decode(None, C.byref(s), None, 1, 10, None, 0, C.byref(out), None) == -1
+
+
+def test_unrolled_entry_points_reject_bad_arguments():
+    lib = ldpc.load()
+    assert lib.ldpc_unrolled_ckpt_floats(None, 300, 32) == -1
+    assert lib.ldpc_unrolled_forward(None, None, None, None, 1, 10, 32, None, None, None, None) == -1
+    assert lib.ldpc_unrolled_backward(None, None, None, 1, 10, 32, None, None, None, None, None) == -1
+    assert ldpc.UNROLL_MAX_CKPT_EVERY == 128
+    hdr = open(HEADER).read()
+    assert "#define LDPC_UNROLL_MAX_CKPT_EVERY 128" in hdr
