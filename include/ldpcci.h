@@ -201,6 +201,49 @@ int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t*
                            int32_t ckpt_every, const float* ckpt, const float* grad_soft, float* grad_llr,
                            float* grad_w, void* stream);
 
+/* ---- launch tuning --------------------------------------------------------------------------
+   The arithmetic of a decode does not depend on these knobs (outputs are identical for every
+   setting); they only choose where state lives and how the launch is shaped.  Zero = default. */
+#define LDPC_STORE_AUTO 0   /* precomputed messages in LDS when they fit, else global scratch */
+#define LDPC_STORE_LDS 1
+#define LDPC_STORE_GLOBAL 2
+#define LDPC_TOPO_AUTO 0    /* quasi-cyclic tables, else LDS copies, else global arrays       */
+#define LDPC_TOPO_GLOBAL 1
+#define LDPC_TOPO_LDS 2
+#define LDPC_TOPO_QC 3
+
+typedef struct {
+  int32_t block;         /* threads per frame: flooding / layered / ME-CIRBP (64..1024, step 64)   */
+  int32_t frames_per_cu; /* single-edge and ME: resident frames per CU of a persistent grid (1..32) */
+  int32_t storage;       /* LDPC_STORE_*: precomputed (single-edge) or all (ME) messages            */
+  int32_t topology;      /* LDPC_TOPO_*: where the kernels read H from                              */
+} ldpc_tuning;
+
+/* Set (t non-null) or clear (t null) the tuning that ldpc_decode uses for this code (any handle
+   with the same H), schedule kind and arithmetic.  Process-wide, thread-safe.  A knob that does
+   not fit a later call (e.g. LDS storage that does not fit) makes that call fail with
+   LDPC_ECAPACITY / LDPC_EUNSUPPORTED.  Errors: LDPC_EINVAL (bad kind, arith or knob value). */
+int ldpc_set_tuning(const ldpc_code* code, int32_t kind, int32_t arith, const ldpc_tuning* t);
+
+/* The stored tuning (all zero if none): returns 1 if an entry exists, 0 if not, <0 on error. */
+int ldpc_get_tuning(const ldpc_code* code, int32_t kind, int32_t arith, ldpc_tuning* out);
+
+/* Project autotuner: times every distinct launch plan the knobs give for this schedule on the
+   caller's frames (llr_in: device [B][N]; best of reps timed runs after one warm-up, HIP events on
+   stream), stores the fastest with ldpc_set_tuning and returns it (best, best_ms nullable).
+   Blocking: synchronizes stream.  Candidates: block in {64..1024} for flooding / layered;
+   storage x topology x frames_per_cu in {auto, 1, 2, 4, 8, 16} (and block in {64, 256, 1024}
+   for ME-CIRBP) for the dynamic schedules.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),
+   LDPC_ECAPACITY (no candidate fits), LDPC_EHIP. */
+int ldpc_autotune(const ldpc_code* code, const ldpc_schedule* s, const float* llr_in, int32_t B,
+                  int64_t max_updates, int32_t reps, ldpc_tuning* best, float* best_ms, void* stream);
+
+/* Write every stored tuning to a JSON file, tagged with the current device's architecture and CU
+   count; ldpc_tuning_load reads such a file back (entries of another device are ignored) and
+   returns the number loaded.  Errors: LDPC_EINVAL (path), LDPC_EHIP. */
+int ldpc_tuning_save(const char* path);
+int ldpc_tuning_load(const char* path);
+
 /* Human-readable name of an error code (static string). */
 const char* ldpc_strerror(int code);
 

@@ -6,9 +6,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/ldpcci.h"
@@ -20,6 +23,7 @@ struct ldpc_code {
   int device;
   int M, N, E;
   int max_dv, max_dc, min_dc, max_touch, n_layers, max_layer_edges;
+  uint64_t sig;  // hash of H (tuning key)
   std::vector<int> h_row_ptr, h_col, h_layer_ptr;
   std::vector<int> h_qc;  // quasi-cyclic base tables (empty for a plain CSR code)
   int nbr_max_cnt;
@@ -53,6 +57,34 @@ int device_cu_count(int dev) {
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
   return v;
+}
+
+// architecture name and CU count: the key under which tuning results are stored
+std::string device_tag(int dev) {
+  hipDeviceProp_t p{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&p, dev) == hipSuccess) {
+    arch = p.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  }
+  return arch + "/" + std::to_string(device_cu_count(dev));
+}
+
+// FNV-1a over the parity-check matrix: equal codes share tuning entries
+uint64_t code_signature(int M, int N, const int* row_ptr, const int* col, int E) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint32_t v) {
+    for (int b = 0; b < 4; ++b) {
+      h ^= (v >> (8 * b)) & 0xFFu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint32_t)M);
+  mix((uint32_t)N);
+  for (int m = 0; m <= M; ++m) mix((uint32_t)row_ptr[m]);
+  for (int e = 0; e < E; ++e) mix((uint32_t)col[e]);
+  return h;
 }
 
 double round_half_away(double x) { return x < 0 ? -std::floor(-x + 0.5) : std::floor(x + 0.5); }
@@ -227,6 +259,7 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
   c->E = E;
   c->n_layers = (int)lp.size() - 1;
   c->h_row_ptr.assign(row_ptr, row_ptr + M + 1);
+  c->sig = code_signature(M, N, row_ptr, col_idx, E);
   c->h_col.assign(col_idx, col_idx + E);
   c->h_layer_ptr = lp;
   // derived host arrays: row of edge, CSC (checks ascending inside a column)
@@ -477,11 +510,52 @@ void ldpc_code_free(ldpc_code* c) {
   delete c;
 }
 
-int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B, int64_t max_updates,
-                const int32_t* replay, int64_t replay_len, const ldpc_outputs* out, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// A decode call resolved to one kernel launch: parameters, launch shape and scratch size.
+struct DecodePlan {
+  int which = 0;  // 0 flooding/layered, 1 single-edge (RBP, CIRBP, replay), 2 ME-CIRBP
+  bool fixed = false;
+  BaseParams base{};
+  DynParams dyn{};
+  MeParams me{};
+  int grid = 0, block = WAVE, topo = TOPO_GLOBAL;
+  bool store_global = false;  // single-edge: pre[] in global scratch; ME: c2v and pre in global scratch
+  size_t scratch_bytes = 0;
+  int lds_limit = 0;
+};
+
+bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
+
+// tuning knob -> candidate topologies (empty: the knob does not apply to this code)
+std::vector<int> topo_choices(const ldpc_code* c, int knob) {
+  switch (knob) {
+    case LDPC_TOPO_GLOBAL: return {TOPO_GLOBAL};
+    case LDPC_TOPO_LDS: return {TOPO_LDS};
+    case LDPC_TOPO_QC: return c->h_qc.empty() ? std::vector<int>{} : std::vector<int>{TOPO_QC};
+    default:
+      return c->h_qc.empty() ? std::vector<int>{TOPO_LDS, TOPO_GLOBAL} : std::vector<int>{TOPO_QC, TOPO_GLOBAL};
+  }
+}
+
+int check_tuning(const ldpc_tuning* t) {
+  if (!t) return LDPC_OK;
+  if (t->block != 0 && !valid_block(t->block)) return LDPC_EINVAL;
+  if (t->frames_per_cu < 0 || t->frames_per_cu > 32) return LDPC_EINVAL;
+  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL) return LDPC_EINVAL;
+  if (t->topology < LDPC_TOPO_AUTO || t->topology > LDPC_TOPO_QC) return LDPC_EINVAL;
+  return LDPC_OK;
+}
+
+// Validate a decode request and resolve it to a launch plan.  tune (nullable) overrides the
+// default storage / topology / launch-shape policy.
+int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B, int64_t max_updates,
+                const int32_t* replay, int64_t replay_len, const ldpc_outputs* out, const ldpc_tuning* tune,
+                DecodePlan& pl) {
   if (!c || !s || !out || B < 0 || max_updates < 0) return LDPC_EINVAL;
-  if (B == 0) return LDPC_OK;
-  if (!llr_in || !out->bits || !out->updates_used) return LDPC_EINVAL;
+  if (B > 0 && (!llr_in || !out->bits || !out->updates_used)) return LDPC_EINVAL;
   if (s->kind < LDPC_FLOODING || s->kind > LDPC_REPLAY) return LDPC_EINVAL;
   if (s->arith != LDPC_SPA_F32 && s->arith != LDPC_MS_FIX) return LDPC_EINVAL;
   const bool fixed = s->arith == LDPC_MS_FIX;
@@ -492,11 +566,15 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (s->kind == LDPC_ME_CIRBP && (s->n_p < 1 || s->n_p > 64 || s->n_g < 1 || s->n_g > 65535 ||
                                    (s->fill != LDPC_FILL_LOWEST && s->fill != LDPC_FILL_HASH)))
     return LDPC_EINVAL;
+  if (int rc = check_tuning(tune)) return rc;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return LDPC_EHIP;
   if (dev != c->device) return LDPC_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
-  const int lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
+  const ldpc_tuning none{};
+  const ldpc_tuning& T = tune ? *tune : none;
+  pl = DecodePlan{};
+  pl.fixed = fixed;
+  pl.lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
   const int ncu = device_cu_count(dev);
   const int qmax = (1 << (std::max(s->q_bits, 2) - 1)) - 1;
   const float scale = std::ldexp(1.0f, fixed ? s->frac_bits : 0);
@@ -515,7 +593,7 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   o.dump_D = out->dump_D;
 
   if (s->kind == LDPC_FLOODING || s->kind == LDPC_LAYERED) {
-    BaseParams P{};
+    BaseParams& P = pl.base;
     P.kind = s->kind;
     P.B = B;
     P.max_updates = max_updates;
@@ -533,43 +611,25 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     P.off_syn = off; off = align16(off + ((c->M + 31) / 32) * 4);
     P.off_misc = off; off = align16(off + 16);
     P.lds_bytes = off;
-    if (P.lds_bytes > lds_limit) return LDPC_ECAPACITY;
-    hipError_t he = set_baseline_lds_limit(lds_limit);
-    if (he != hipSuccess) return hip_fail(he);
-    int work = s->kind == LDPC_FLOODING ? c->E : c->max_layer_edges;
-    int block = work >= 4096 ? 1024 : (work >= 1024 ? 256 : (work >= 256 ? 128 : 64));
-    he = launch_baseline(c->dev, P, fixed, B, block, st);
-    return he == hipSuccess ? LDPC_OK : hip_fail(he);
+    if (P.lds_bytes > pl.lds_limit) return LDPC_ECAPACITY;
+    const int work = vbuf_n;
+    pl.which = 0;
+    pl.block = T.block ? T.block : (work >= 4096 ? 1024 : (work >= 1024 ? 256 : (work >= 256 ? 128 : 64)));
+    pl.grid = B;
+    return LDPC_OK;
   }
 
   if (c->max_dv > WAVE - 1) return LDPC_EUNSUPPORTED;
   if (c->nbr_max_cnt > NBR_PMAX * WAVE) return LDPC_EUNSUPPORTED;
+  const std::vector<int> topos = topo_choices(c, T.topology);
+  if (topos.empty()) return LDPC_EUNSUPPORTED;
+  std::vector<bool> stores = {false, true};
+  if (T.storage == LDPC_STORE_LDS) stores = {false};
+  if (T.storage == LDPC_STORE_GLOBAL) stores = {true};
+  const int lut_off = 257 * (fixed ? s->frac_bits : 0);
 
-  DynParams P{};
-  P.kind = s->kind;
-  P.B = B;
-  P.max_updates = max_updates;
-  P.check_every = s->check_every;
-  P.llr = llr_in;
-  P.replay = replay;
-  P.replay_len = replay_len;
-  P.out = o;
-  P.qmax = qmax;
-  P.scale = scale;
-  P.lut_global = c->d_lut + 257 * (fixed ? s->frac_bits : 0);
-  P.n_p = s->n_p;
-  P.n_g = s->n_g;
-  P.fill = s->fill;
-  P.seed = s->seed;
-  if (fixed) {
-    double g = round_half_away((double)s->gamma * 65534.0);
-    P.gamma_bits = (uint32_t)std::min(g, 4294967295.0);
-  } else {
-    float g = s->gamma;
-    std::memcpy(&P.gamma_bits, &g, 4);
-  }
   if (s->kind == LDPC_ME_CIRBP) {
-    MeParams Q{};
+    MeParams& Q = pl.me;
     Q.B = B;
     Q.max_updates = max_updates;
     Q.check_every = s->check_every;
@@ -577,27 +637,20 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     Q.out = o;
     Q.qmax = qmax;
     Q.scale = scale;
-    Q.lut_global = P.lut_global;
+    Q.lut_global = c->d_lut + lut_off;
     Q.n_p = s->n_p;
     Q.n_g = s->n_g;
     Q.fill = s->fill;
     Q.seed = s->seed;
-    std::vector<int> topos = c->h_qc.empty() ? std::vector<int>{TOPO_LDS, TOPO_GLOBAL}
-                                             : std::vector<int>{TOPO_QC, TOPO_GLOBAL};
-    if (const char* ft = std::getenv("LDPCCI_TOPO")) {
-      if (!std::strcmp(ft, "global")) topos = {TOPO_GLOBAL};
-      else if (!std::strcmp(ft, "lds")) topos = {TOPO_LDS};
-    }
-    bool found = false, mg = false;
-    int topo = TOPO_GLOBAL;
+    bool found = false;
     MeLayout Ly{};
-    for (bool g : {false, true}) {
+    for (bool g : stores) {
       for (int tp : topos) {
         MeLayout cand = me_layout(c, fixed, g, tp, s->n_p, s->n_g, s->fill);
-        if (cand.total <= lds_limit) {
+        if (cand.total <= pl.lds_limit) {
           Ly = cand;
-          mg = g;
-          topo = tp;
+          pl.store_global = g;
+          pl.topo = tp;
           found = true;
           break;
         }
@@ -611,55 +664,61 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     Q.off_lut = Ly.off_lut; Q.off_topo = Ly.off_topo; Q.lds_bytes = Ly.total;
     Q.rows_cap = Ly.rows_cap;
     Q.cand_cap = Ly.cand_cap;
-    const int block = c->N <= 256 ? 64 : (c->N <= 2048 ? 256 : 1024);
-    hipError_t he = set_me_lds_limit(lds_limit);
-    if (he != hipSuccess) return hip_fail(he);
-    int grid = B;
-    void* scratch = nullptr;
-    if (mg) {
-      const int per_cu = std::max(1, (160 * 1024) / std::max(Q.lds_bytes, 1));
-      grid = (int)std::min<long long>(B, (long long)ncu * per_cu);
-      he = hipMallocAsync(&scratch, (size_t)grid * 2 * c->E * (fixed ? 1 : 4), st);
-      if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
-      Q.msg_global = scratch;
+    pl.which = 2;
+    pl.block = T.block ? T.block : (c->N <= 256 ? 64 : (c->N <= 2048 ? 256 : 1024));
+    const int lds_per_cu = 160 * 1024;
+    if (pl.store_global || T.frames_per_cu) {
+      const int fit = std::max(1, lds_per_cu / std::max(Q.lds_bytes, 1));
+      const int per_cu = T.frames_per_cu ? std::min(T.frames_per_cu, fit) : fit;
+      pl.grid = (int)std::min<long long>(B, (long long)ncu * per_cu);
+    } else {
+      pl.grid = B;
     }
-    he = launch_me(c->dev, Q, fixed, mg, topo, grid, block, st);
-    if (scratch) (void)hipFreeAsync(scratch, st);
-    return he == hipSuccess ? LDPC_OK : hip_fail(he);
+    if (pl.store_global) pl.scratch_bytes = (size_t)std::max(pl.grid, 1) * 2 * c->E * (fixed ? 1 : 4);
+    return LDPC_OK;
   }
 
-  // storage plan: pre[] in LDS if possible; topology as quasi-cyclic tables, LDS copies or
-  // global arrays, in that order of preference (overridable for tests through the environment)
-  bool pre_global = false;
-  int topo = TOPO_GLOBAL;
-  DynLayout Ly{};
-  {
-    const char* ft = std::getenv("LDPCCI_TOPO");
-    const char* fp = std::getenv("LDPCCI_PRE");
-    std::vector<int> topos;
-    if (ft && !std::strcmp(ft, "global")) topos = {TOPO_GLOBAL};
-    else if (ft && !std::strcmp(ft, "lds")) topos = {TOPO_LDS};
-    else if (ft && !std::strcmp(ft, "qc") && !c->h_qc.empty()) topos = {TOPO_QC};
-    else topos = c->h_qc.empty() ? std::vector<int>{TOPO_LDS, TOPO_GLOBAL} : std::vector<int>{TOPO_QC, TOPO_GLOBAL};
-    std::vector<bool> pres = {false, true};
-    if (fp && !std::strcmp(fp, "global")) pres = {true};
-    if (fp && !std::strcmp(fp, "lds")) pres = {false};
-    bool found = false;
-    for (bool pg : pres) {
-      for (int tp : topos) {
-        DynLayout cand = dyn_layout(c, fixed, pg, tp, 0);
-        if (cand.total <= lds_limit) {
-          Ly = cand;
-          pre_global = pg;
-          topo = tp;
-          found = true;
-          break;
-        }
-      }
-      if (found) break;
-    }
-    if (!found) return LDPC_ECAPACITY;
+  DynParams& P = pl.dyn;
+  P.kind = s->kind;
+  P.B = B;
+  P.max_updates = max_updates;
+  P.check_every = s->check_every;
+  P.llr = llr_in;
+  P.replay = replay;
+  P.replay_len = replay_len;
+  P.out = o;
+  P.qmax = qmax;
+  P.scale = scale;
+  P.lut_global = c->d_lut + lut_off;
+  P.n_p = s->n_p;
+  P.n_g = s->n_g;
+  P.fill = s->fill;
+  P.seed = s->seed;
+  if (fixed) {
+    double g = round_half_away((double)s->gamma * 65534.0);
+    P.gamma_bits = (uint32_t)std::min(g, 4294967295.0);
+  } else {
+    float g = s->gamma;
+    std::memcpy(&P.gamma_bits, &g, 4);
   }
+  // storage plan: pre[] in LDS if possible; topology as quasi-cyclic tables, LDS copies or global
+  // arrays, in that order of preference
+  DynLayout Ly{};
+  bool found = false;
+  for (bool pg : stores) {
+    for (int tp : topos) {
+      DynLayout cand = dyn_layout(c, fixed, pg, tp, 0);
+      if (cand.total <= pl.lds_limit) {
+        Ly = cand;
+        pl.store_global = pg;
+        pl.topo = tp;
+        found = true;
+        break;
+      }
+    }
+    if (found) break;
+  }
+  if (!found) return LDPC_ECAPACITY;
   P.off_c2v = Ly.off_c2v; P.off_pre = Ly.off_pre; P.off_L = Ly.off_L; P.off_Lt = Ly.off_Lt;
   P.off_D = Ly.off_D; P.off_ckey = Ly.off_ckey; P.off_dblk = Ly.off_dblk; P.off_cblk = Ly.off_cblk;
   P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
@@ -668,25 +727,244 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   P.off_extra = Ly.off_extra;
   P.lds_bytes = Ly.total;
   P.nbd = Ly.nbd; P.nbc = Ly.nbc; P.nbd_words = Ly.nbd_words; P.nbc_words = Ly.nbc_words;
-
   P.prof = nullptr;
 #ifdef LDPC_PROFILE
   if (const char* pp = std::getenv("LDPCCI_PROF")) P.prof = (long long*)std::strtoull(pp, nullptr, 10);
 #endif
-  hipError_t he = set_dynamic_lds_limit(lds_limit);
-  if (he != hipSuccess) return hip_fail(he);
-  int grid = B;
-  void* scratch = nullptr;
-  if (pre_global) {
-    const int per_cu = std::max(1, (160 * 1024) / std::max(P.lds_bytes, 1));
-    grid = std::min<long long>(B, (long long)ncu * per_cu);
-    he = hipMallocAsync(&scratch, (size_t)grid * c->E * (fixed ? 1 : 4), st);
-    if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
-    P.pre_global = scratch;
+  pl.which = 1;
+  pl.block = WAVE;
+  if (pl.store_global || T.frames_per_cu) {
+    const int fit = std::max(1, (160 * 1024) / std::max(P.lds_bytes, 1));
+    const int per_cu = T.frames_per_cu ? std::min(T.frames_per_cu, fit) : fit;
+    pl.grid = (int)std::min<long long>(B, (long long)ncu * per_cu);
+  } else {
+    pl.grid = B;
   }
-  he = launch_dynamic(c->dev, P, fixed, pre_global, topo, grid, st);
+  if (pl.store_global) pl.scratch_bytes = (size_t)std::max(pl.grid, 1) * c->E * (fixed ? 1 : 4);
+  return LDPC_OK;
+}
+
+// Enqueue a planned decode; scratch must hold pl.scratch_bytes (may be null when that is 0).
+hipError_t enqueue_decode(const ldpc_code* c, DecodePlan& pl, void* scratch, hipStream_t st) {
+  if (pl.grid <= 0) return hipSuccess;
+  hipError_t he = hipSuccess;
+  if (pl.which == 0) {
+    if ((he = set_baseline_lds_limit(pl.lds_limit)) != hipSuccess) return he;
+    return launch_baseline(c->dev, pl.base, pl.fixed, pl.grid, pl.block, st);
+  }
+  if (pl.which == 2) {
+    pl.me.msg_global = pl.store_global ? scratch : nullptr;
+    if ((he = set_me_lds_limit(pl.lds_limit)) != hipSuccess) return he;
+    return launch_me(c->dev, pl.me, pl.fixed, pl.store_global, pl.topo, pl.grid, pl.block, st);
+  }
+  pl.dyn.pre_global = pl.store_global ? scratch : nullptr;
+  if ((he = set_dynamic_lds_limit(pl.lds_limit)) != hipSuccess) return he;
+  return launch_dynamic(c->dev, pl.dyn, pl.fixed, pl.store_global, pl.topo, pl.grid, st);
+}
+
+// ------------------------------------------------------------------------------------------
+// tuning table: process-wide, keyed by (code signature, schedule kind, arithmetic)
+// ------------------------------------------------------------------------------------------
+struct TuneKey {
+  uint64_t sig;
+  int kind, arith;
+  bool operator<(const TuneKey& o) const {
+    if (sig != o.sig) return sig < o.sig;
+    if (kind != o.kind) return kind < o.kind;
+    return arith < o.arith;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, ldpc_tuning> g_tune;
+
+bool lookup_tuning(const ldpc_code* c, int kind, int arith, ldpc_tuning& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(TuneKey{c->sig, kind, arith});
+  if (it == g_tune.end()) return false;
+  t = it->second;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B, int64_t max_updates,
+                const int32_t* replay, int64_t replay_len, const ldpc_outputs* out, void* stream) {
+  if (!c || !s || !out || B < 0 || max_updates < 0) return LDPC_EINVAL;
+  if (B == 0) return LDPC_OK;
+  ldpc_tuning t{};
+  const bool tuned = lookup_tuning(c, s->kind, s->arith, t);
+  DecodePlan pl;
+  int rc = plan_decode(c, s, llr_in, B, max_updates, replay, replay_len, out, tuned ? &t : nullptr, pl);
+  if (rc != LDPC_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  void* scratch = nullptr;
+  if (pl.scratch_bytes) {
+    hipError_t he = hipMallocAsync(&scratch, pl.scratch_bytes, st);
+    if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
+  }
+  hipError_t he = enqueue_decode(c, pl, scratch, st);
   if (scratch) (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+int ldpc_set_tuning(const ldpc_code* c, int32_t kind, int32_t arith, const ldpc_tuning* t) {
+  if (!c || kind < LDPC_FLOODING || kind > LDPC_REPLAY || (arith != LDPC_SPA_F32 && arith != LDPC_MS_FIX))
+    return LDPC_EINVAL;
+  if (int rc = check_tuning(t)) return rc;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (t) g_tune[TuneKey{c->sig, kind, arith}] = *t;
+  else g_tune.erase(TuneKey{c->sig, kind, arith});
+  return LDPC_OK;
+}
+
+int ldpc_get_tuning(const ldpc_code* c, int32_t kind, int32_t arith, ldpc_tuning* out) {
+  if (!c || !out) return LDPC_EINVAL;
+  ldpc_tuning t{};
+  const bool found = lookup_tuning(c, kind, arith, t);
+  *out = t;
+  return found ? 1 : 0;
+}
+
+int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B, int64_t max_updates,
+                  int32_t reps, ldpc_tuning* best, float* best_ms, void* stream) {
+  if (!c || !s || !llr_in || B < 1 || max_updates < 0 || reps < 1 || reps > 100) return LDPC_EINVAL;
+  if (s->kind == LDPC_REPLAY) return LDPC_EUNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  // candidate knobs of the kernel family this schedule runs on
+  std::vector<ldpc_tuning> cands;
+  if (s->kind == LDPC_FLOODING || s->kind == LDPC_LAYERED) {
+    for (int b : {64, 128, 256, 512, 1024}) cands.push_back(ldpc_tuning{b, 0, 0, 0});
+  } else {
+    std::vector<int> tps = {LDPC_TOPO_GLOBAL, LDPC_TOPO_LDS};
+    if (!c->h_qc.empty()) tps.push_back(LDPC_TOPO_QC);
+    const std::vector<int> blocks = s->kind == LDPC_ME_CIRBP ? std::vector<int>{64, 256, 1024} : std::vector<int>{0};
+    for (int b : blocks)
+      for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL})
+        for (int tp : tps)
+          for (int fpc : {0, 1, 2, 4, 8, 16})
+            cands.push_back(ldpc_tuning{b, fpc, store, tp});
+  }
+  // outputs for the trial decodes (discarded)
+  uint8_t* bits = nullptr;
+  int64_t* upd = nullptr;
+  hipError_t he = hipMalloc((void**)&bits, (size_t)B * c->N);
+  if (he == hipSuccess) he = hipMalloc((void**)&upd, (size_t)B * sizeof(int64_t));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  int rc = LDPC_OK;
+  float best_t = -1.0f;
+  ldpc_tuning best_c{};
+  for (size_t i = 0; i < cands.size() && he == hipSuccess && rc == LDPC_OK; ++i) {
+    ldpc_outputs out{};
+    out.bits = bits;
+    out.updates_used = upd;
+    DecodePlan pl;
+    if (plan_decode(c, s, llr_in, B, max_updates, nullptr, 0, &out, &cands[i], pl) != LDPC_OK) continue;
+    // skip knobs that resolve to a plan already timed
+    bool dup = false;
+    for (size_t j = 0; j < i && !dup; ++j) {
+      DecodePlan q;
+      if (plan_decode(c, s, llr_in, B, max_updates, nullptr, 0, &out, &cands[j], q) != LDPC_OK) continue;
+      dup = q.which == pl.which && q.grid == pl.grid && q.block == pl.block && q.topo == pl.topo &&
+            q.store_global == pl.store_global;
+    }
+    if (dup) continue;
+    void* scratch = nullptr;
+    if (pl.scratch_bytes && (he = hipMalloc(&scratch, pl.scratch_bytes)) != hipSuccess) break;
+    float tmin = -1.0f;
+    he = enqueue_decode(c, pl, scratch, st);  // warm-up
+    for (int r = 0; r < reps && he == hipSuccess; ++r) {
+      he = hipEventRecord(e0, st);
+      if (he == hipSuccess) he = enqueue_decode(c, pl, scratch, st);
+      if (he == hipSuccess) he = hipEventRecord(e1, st);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he == hipSuccess && (tmin < 0.0f || ms < tmin)) tmin = ms;
+    }
+    if (scratch) (void)hipFree(scratch);
+    if (he == hipSuccess && tmin >= 0.0f && (best_t < 0.0f || tmin < best_t)) {
+      best_t = tmin;
+      best_c = cands[i];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (bits) (void)hipFree(bits);
+  if (upd) (void)hipFree(upd);
+  if (he != hipSuccess) return hip_fail(he);
+  if (best_t < 0.0f) return LDPC_ECAPACITY;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[TuneKey{c->sig, s->kind, s->arith}] = best_c;
+  }
+  if (best) *best = best_c;
+  if (best_ms) *best_ms = best_t;
+  return rc;
+}
+
+int ldpc_tuning_save(const char* path) {
+  if (!path) return LDPC_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LDPC_EHIP;
+  const std::string tag = device_tag(dev);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return LDPC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::fprintf(f, "{\"device\": \"%s\", \"entries\": [\n", tag.c_str());
+  size_t i = 0;
+  for (const auto& kv : g_tune) {
+    const ldpc_tuning& t = kv.second;
+    std::fprintf(f,
+                 "{\"sig\": \"%016llx\", \"kind\": %d, \"arith\": %d, \"block\": %d, \"frames_per_cu\": %d, "
+                 "\"storage\": %d, \"topology\": %d}%s\n",
+                 (unsigned long long)kv.first.sig, kv.first.kind, kv.first.arith, t.block, t.frames_per_cu, t.storage,
+                 t.topology, ++i < g_tune.size() ? "," : "");
+  }
+  std::fprintf(f, "]}\n");
+  return std::fclose(f) == 0 ? LDPC_OK : LDPC_EINVAL;
+}
+
+int ldpc_tuning_load(const char* path) {
+  if (!path) return LDPC_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LDPC_EHIP;
+  const std::string tag = device_tag(dev);
+  FILE* f = std::fopen(path, "r");
+  if (!f) return LDPC_EINVAL;
+  char line[512];
+  int loaded = 0;
+  bool same_device = false;
+  std::vector<std::pair<TuneKey, ldpc_tuning>> rows;
+  while (std::fgets(line, sizeof line, f)) {
+    char dtag[128];
+    if (std::sscanf(line, " {\"device\": \"%127[^\"]\"", dtag) == 1) {
+      same_device = tag == dtag;
+      continue;
+    }
+    unsigned long long sig = 0;
+    TuneKey k{};
+    ldpc_tuning t{};
+    if (std::sscanf(line,
+                    " {\"sig\": \"%llx\", \"kind\": %d, \"arith\": %d, \"block\": %d, \"frames_per_cu\": %d, "
+                    "\"storage\": %d, \"topology\": %d}",
+                    &sig, &k.kind, &k.arith, &t.block, &t.frames_per_cu, &t.storage, &t.topology) == 7) {
+      k.sig = sig;
+      if (check_tuning(&t) != LDPC_OK || k.kind < LDPC_FLOODING || k.kind > LDPC_REPLAY) continue;
+      rows.push_back({k, t});
+    }
+  }
+  std::fclose(f);
+  if (!same_device) return 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& r : rows) {
+    g_tune[r.first] = r.second;
+    ++loaded;
+  }
+  return loaded;
 }
 
 int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,

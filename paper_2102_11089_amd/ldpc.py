@@ -27,9 +27,12 @@ ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -
           -5: "LDPC_EUNSUPPORTED"}
 
 EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode",
-           "ldpc_decode_batch", "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
+           "ldpc_decode_batch", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune", "ldpc_tuning_save",
+           "ldpc_tuning_load", "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
            "ldpc_strerror", "ldpc_last_hip_error")
 UNROLL_MAX_CKPT_EVERY = 128
+STORE_AUTO, STORE_LDS, STORE_GLOBAL = 0, 1, 2
+TOPO_AUTO, TOPO_GLOBAL, TOPO_LDS, TOPO_QC = 0, 1, 2, 3
 
 # layout of ldpc_frame_desc (40 bytes)
 FRAME_DESC = np.dtype([("code", "<i4"), ("kind", "<i4"), ("gamma", "<f4"), ("reserved", "<i4"),
@@ -46,6 +49,14 @@ class ldpc_outputs(C.Structure):
     _fields_ = [(name, C.c_void_p) for name in
                 ("bits", "llr_out", "updates_used", "steps_used", "fallbacks", "trace", "dump_c2v",
                  "dump_pre", "dump_L", "dump_Lt", "dump_D")]
+
+
+class ldpc_tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("frames_per_cu", C.c_int32), ("storage", C.c_int32),
+                ("topology", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class ldpc_code_stats(C.Structure):
@@ -80,6 +91,17 @@ def load(path: str = LIB_PATH):
     lib.ldpc_decode_batch.argtypes = [P, C.c_int32, C.POINTER(ldpc_schedule), P, C.c_int32, P, C.c_int64, P, P,
                                       C.c_int64, P, P, P, P]
     lib.ldpc_decode_batch.restype = C.c_int
+    lib.ldpc_set_tuning.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(ldpc_tuning)]
+    lib.ldpc_set_tuning.restype = C.c_int
+    lib.ldpc_get_tuning.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(ldpc_tuning)]
+    lib.ldpc_get_tuning.restype = C.c_int
+    lib.ldpc_autotune.argtypes = [P, C.POINTER(ldpc_schedule), P, C.c_int32, C.c_int64, C.c_int32,
+                                  C.POINTER(ldpc_tuning), C.POINTER(C.c_float), P]
+    lib.ldpc_autotune.restype = C.c_int
+    lib.ldpc_tuning_save.argtypes = [C.c_char_p]
+    lib.ldpc_tuning_save.restype = C.c_int
+    lib.ldpc_tuning_load.argtypes = [C.c_char_p]
+    lib.ldpc_tuning_load.restype = C.c_int
     lib.ldpc_unrolled_ckpt_floats.argtypes = [P, C.c_int32, C.c_int32]
     lib.ldpc_unrolled_ckpt_floats.restype = C.c_int64
     lib.ldpc_unrolled_forward.argtypes = [P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P]
@@ -147,6 +169,37 @@ def ldpc_decode_batch(handles, schedule: ldpc_schedule, frames_ptr: int, F: int,
     rc = load().ldpc_decode_batch(arr, len(handles), C.byref(schedule), frames_ptr, F, llr_ptr, llr_len, bits_ptr,
                                   llr_out_ptr, out_len, upd_ptr, steps_ptr, fall_ptr, stream)
     _check(rc, "ldpc_decode_batch")
+
+
+def ldpc_set_tuning(handle, kind: int, arith: int, t: Optional[ldpc_tuning]) -> None:
+    _check(load().ldpc_set_tuning(handle, kind, arith, None if t is None else C.byref(t)), "ldpc_set_tuning")
+
+
+def ldpc_get_tuning(handle, kind: int, arith: int) -> Optional[ldpc_tuning]:
+    t = ldpc_tuning()
+    rc = load().ldpc_get_tuning(handle, kind, arith, C.byref(t))
+    if rc < 0:
+        _check(rc, "ldpc_get_tuning")
+    return t if rc == 1 else None
+
+
+def ldpc_autotune(handle, s: ldpc_schedule, llr_ptr: int, B: int, max_updates: int, reps: int, stream: int):
+    t = ldpc_tuning()
+    ms = C.c_float(0.0)
+    _check(load().ldpc_autotune(handle, C.byref(s), llr_ptr, B, max_updates, reps, C.byref(t), C.byref(ms), stream),
+           "ldpc_autotune")
+    return t, float(ms.value)
+
+
+def ldpc_tuning_save(path: str) -> None:
+    _check(load().ldpc_tuning_save(path.encode()), "ldpc_tuning_save")
+
+
+def ldpc_tuning_load(path: str) -> int:
+    n = load().ldpc_tuning_load(path.encode())
+    if n < 0:
+        _check(n, "ldpc_tuning_load")
+    return int(n)
 
 
 def ldpc_unrolled_ckpt_floats(handle, T: int, ckpt_every: int) -> int:
@@ -355,3 +408,24 @@ def _unrolled_function():
 def unrolled_decode(code: Code, llr, w, trace, ckpt_every: int = 32):
     """Differentiable soft output of the damped replay (torch.autograd.Function)."""
     return _unrolled_function().apply(llr, w, code, trace, ckpt_every)
+
+
+# ----------------------------------------------------------------------------------------------
+# launch tuning
+# ----------------------------------------------------------------------------------------------
+def set_tuning(code: Code, kind: int, arith: int, block: int = 0, frames_per_cu: int = 0, storage: int = 0,
+               topology: int = 0, clear: bool = False) -> None:
+    ldpc_set_tuning(code.handle, kind, arith, None if clear else ldpc_tuning(block, frames_per_cu, storage, topology))
+
+
+def autotune(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int = 0, gamma: float = 0.1,
+             q_bits: int = 6, frac_bits: int = 1, n_p: int = 1, n_g: int = 16, fill: int = FILL_LOWEST,
+             check_every: int = 1, reps: int = 2, stream=None):
+    """Tune the launch of one schedule on sample frames (a (B, N) float32 CUDA tensor); returns
+    (knobs as a dict, best milliseconds).  The result is kept for later decodes of this code."""
+    import torch
+    llr = llr.contiguous()
+    s = schedule(kind, arith, gamma, q_bits, frac_bits, n_p, n_g, fill, 0, check_every)
+    st = (stream if stream is not None else torch.cuda.current_stream(llr.device)).cuda_stream
+    t, ms = ldpc_autotune(code.handle, s, llr.data_ptr(), llr.shape[0], max_updates, reps, st)
+    return t.as_dict(), ms

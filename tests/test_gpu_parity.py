@@ -236,18 +236,24 @@ def test_edge_cases(gpu, c0):
 # ------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("pre", ["lds", "global"])
 @pytest.mark.parametrize("topo", ["global", "lds", "qc"])
-def test_fixed_storage_variants(gpu, monkeypatch, pre, topo):
+@pytest.mark.parametrize("fpc", [0, 3])
+def test_fixed_storage_variants(gpu, pre, topo, fpc):
+    """Every storage / topology / launch-shape knob gives the oracle's results bit for bit."""
     code = S.qc_24col(24, 12, seed=4)  # N = 576, quasi-cyclic
     cw, llr = S.frames(code, 200, 2.0, 109)
     ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True, dump=True,
                    threads=8)
-    monkeypatch.setenv("LDPCCI_PRE", pre)
-    monkeypatch.setenv("LDPCCI_TOPO", topo)
+    store = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL}[pre]
+    tp = {"global": gpu.TOPO_GLOBAL, "lds": gpu.TOPO_LDS, "qc": gpu.TOPO_QC}[topo]
     handles = [gpu.Code(code)] if topo == "qc" else [gpu.Code(code), gpu.Code(code, csr=True)]
     for h in handles:
-        say(f"[variant pre={pre} topo={topo}] qc24 Z=24")
-        g = gpu_decode(gpu, h, llr, "cirbp", gpu.MS_FIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True,
-                       dump=True)
+        say(f"[variant pre={pre} topo={topo} frames/CU={fpc}] qc24 Z=24")
+        gpu.set_tuning(h, gpu.CIRBP, gpu.MS_FIX, frames_per_cu=fpc, storage=store, topology=tp)
+        try:
+            g = gpu_decode(gpu, h, llr, "cirbp", gpu.MS_FIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True,
+                           dump=True)
+        finally:
+            gpu.set_tuning(h, gpu.CIRBP, gpu.MS_FIX, clear=True)
         np.testing.assert_array_equal(np_(g.trace), ref.trace)
         np.testing.assert_array_equal(np_(g.bits), ref.bits)
         np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)

@@ -1,0 +1,101 @@
+"""GPU tests of the launch autotuner: tuned launches give the same outputs as the default ones
+(the knobs move state and reshape the launch, never the arithmetic), and the JSON cache
+round-trips."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2102_11089_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def outputs(gpu, h, llr, kind, arith, **kw):
+    r = gpu.decode(h, llr, kind, arith, **kw)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in (r.bits, r.llr_out, r.updates_used)]
+
+
+@pytest.mark.parametrize("kind,arith", [("flooding", "f32"), ("layered", "fix"), ("cirbp", "f32"), ("cirbp", "fix"),
+                                        ("rbp", "f32"), ("me", "fix")])
+def test_autotuned_launch_gives_identical_outputs(gpu, kind, arith):
+    code = S.qc_24col(48, 8, seed=2)  # N = 1152, rate 2/3
+    h = gpu.Code(code)
+    k = {"flooding": gpu.FLOODING, "layered": gpu.LAYERED, "cirbp": gpu.CIRBP, "rbp": gpu.RBP,
+         "me": gpu.ME_CIRBP}[kind]
+    a = gpu.SPA_F32 if arith == "f32" else gpu.MS_FIX
+    cw, llr_np = S.frames(code, 384, 3.0, 7)
+    llr = torch.from_numpy(llr_np).cuda()
+    cap = 20 * code.E if kind in ("flooding", "layered") else 2 * code.E
+    kw = dict(max_updates=cap, q_bits=8, frac_bits=2, n_p=8, n_g=16)
+    gpu.set_tuning(h, k, a, clear=True)
+    base = outputs(gpu, h, llr, k, a, **kw)
+    say(f"[tune {kind} {arith}] N=1152, 384 frames")
+    knobs, ms = gpu.autotune(h, llr, k, a, **kw, reps=1)
+    say(f"  best {knobs} {ms:.3f} ms")
+    got = gpu.ldpc_get_tuning(h.handle, k, a)
+    assert got is not None and got.as_dict() == knobs
+    tuned = outputs(gpu, h, llr, k, a, **kw)
+    for x, y in zip(base, tuned):
+        np.testing.assert_array_equal(x, y)
+    if arith == "fix":  # and both equal the oracle
+        ok = {"flooding": O.FLOODING, "layered": O.LAYERED, "cirbp": O.CIRBP, "rbp": O.RBP, "me": O.MECIRBP}[kind]
+        ref = O.decode(code, llr_np[:64], ok, O.MSFIX, max_updates=cap, q_bits=8, frac_bits=2, n_p=8, n_g=16,
+                       threads=16)
+        np.testing.assert_array_equal(tuned[0][:64], ref.bits)
+        np.testing.assert_array_equal(tuned[2][:64], ref.updates_used)
+    gpu.set_tuning(h, k, a, clear=True)
+
+
+@pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
+def test_every_flooding_block_size_is_exact(gpu, block):
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    cw, llr_np = S.frames(code, 200, 2.0, 8)
+    llr = torch.from_numpy(llr_np).cuda()
+    ref = O.decode(code, llr_np, O.FLOODING, O.MSFIX, max_updates=20 * code.E, threads=16)
+    gpu.set_tuning(h, gpu.FLOODING, gpu.MS_FIX, block=block)
+    try:
+        bits, _, upd = outputs(gpu, h, llr, gpu.FLOODING, gpu.MS_FIX, max_updates=20 * code.E)
+    finally:
+        gpu.set_tuning(h, gpu.FLOODING, gpu.MS_FIX, clear=True)
+    np.testing.assert_array_equal(bits, ref.bits)
+    np.testing.assert_array_equal(upd, ref.updates_used)
+
+
+def test_tuning_cache_round_trip(gpu, tmp_path):
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, frames_per_cu=4, storage=gpu.STORE_GLOBAL, topology=gpu.TOPO_LDS)
+    gpu.set_tuning(h, gpu.FLOODING, gpu.MS_FIX, block=128)
+    path = str(tmp_path / "tune.json")
+    gpu.ldpc_tuning_save(path)
+    doc = json.load(open(path))
+    assert doc["device"].startswith("gfx") and len(doc["entries"]) >= 2
+    gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, clear=True)
+    gpu.set_tuning(h, gpu.FLOODING, gpu.MS_FIX, clear=True)
+    assert gpu.ldpc_get_tuning(h.handle, gpu.CIRBP, gpu.SPA_F32) is None
+    assert gpu.ldpc_tuning_load(path) >= 2
+    t = gpu.ldpc_get_tuning(h.handle, gpu.CIRBP, gpu.SPA_F32)
+    assert t.as_dict() == {"block": 0, "frames_per_cu": 4, "storage": gpu.STORE_GLOBAL, "topology": gpu.TOPO_LDS}
+    assert gpu.ldpc_get_tuning(h.handle, gpu.FLOODING, gpu.MS_FIX).block == 128
+    # a tuned decode still matches the oracle
+    cw, llr_np = S.frames(code, 100, 2.0, 9)
+    r = gpu.decode(h, torch.from_numpy(llr_np).cuda(), gpu.CIRBP, gpu.MS_FIX, max_updates=2400)
+    ref = O.decode(code, llr_np, O.CIRBP, O.MSFIX, max_updates=2400, threads=16)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r.bits.cpu().numpy(), ref.bits)
+    for k, a in ((gpu.CIRBP, gpu.SPA_F32), (gpu.FLOODING, gpu.MS_FIX)):
+        gpu.set_tuning(h, k, a, clear=True)
+    # bad knobs are rejected
+    with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+        gpu.set_tuning(h, gpu.FLOODING, gpu.SPA_F32, block=100)
+    with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+        gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, frames_per_cu=33)
