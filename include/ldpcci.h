@@ -244,6 +244,36 @@ int ldpc_autotune(const ldpc_code* code, const ldpc_schedule* s, const float* ll
 int ldpc_tuning_save(const char* path);
 int ldpc_tuning_load(const char* path);
 
+/* ---- SNR sweeps -----------------------------------------------------------------------------
+   Channel frames on the device: frame f of sweep point p carries codeword f mod P of a pool
+   (device [P][N] bytes 0/1); bit n gets x = 1 - 2c plus noise sigma z, z one Box-Muller normal
+   from Philox4x32-10 (Salmon et al., SC 2011) with counter (n, f, p, 0) and key (seed mod 2^32,
+   seed >> 32): u1 = (x0 + 1) 2^-32, u2 = x1 2^-32, z = sqrt(-2 ln u1) cos(2 pi u2).  The LLR is
+   (2 / sigma^2)(x + sigma z), the channel LLR of Sec. II-A. */
+
+/* Write B frames of point `point` to llr_out (device [B][N]).  Errors: LDPC_EINVAL, LDPC_EHIP. */
+int ldpc_awgn_frames(const uint8_t* codewords, int32_t P, int32_t N, int32_t B, float sigma2, uint64_t seed,
+                     int32_t point, float* llr_out, void* stream);
+
+typedef struct ldpc_sweep ldpc_sweep;
+
+/* Capture an SNR sweep into one hipGraph: for each of the S points (Eb/N0 in dB, host array,
+   sigma^2 = 1 / (2 rate 10^(EbN0/10))) generate B frames from the codeword pool, decode them with
+   schedule s (cap max_updates, the tuning stored for this code if any), and count per point
+   {frames, frame errors, bit errors, sum of updates_used}.  The library allocates the frame
+   buffers and decode scratch once; the pool (device [P][N]) must stay valid for the sweep's life.
+   Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay), LDPC_ECAPACITY, LDPC_ENOMEM, LDPC_EHIP. */
+int ldpc_sweep_create(const ldpc_code* code, const ldpc_schedule* s, int64_t max_updates, const uint8_t* codewords,
+                      int32_t P, const float* ebn0_db, int32_t S, float rate, int32_t B, ldpc_sweep** out);
+
+/* Launch the captured sweep with a seed on stream and copy its counters to `counters` (device
+   [S][4] int64).  Enqueue-only.  Runs of one sweep object must not overlap (they share buffers).
+   Errors: LDPC_EINVAL, LDPC_EHIP. */
+int ldpc_sweep_run(ldpc_sweep* sweep, uint64_t seed, int64_t* counters, void* stream);
+
+/* Destroy a sweep (waits for the device first).  NULL is ignored. */
+void ldpc_sweep_free(ldpc_sweep* sweep);
+
 /* Human-readable name of an error code (static string). */
 const char* ldpc_strerror(int code);
 

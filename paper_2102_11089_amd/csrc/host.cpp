@@ -744,21 +744,27 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   return LDPC_OK;
 }
 
+// Raise the kernels' dynamic-LDS limit for a plan (not a stream operation: done before capture).
+hipError_t plan_lds_limits(const DecodePlan& pl) {
+  if (pl.which == 0) return set_baseline_lds_limit(pl.lds_limit);
+  if (pl.which == 2) return set_me_lds_limit(pl.lds_limit);
+  return set_dynamic_lds_limit(pl.lds_limit);
+}
+
 // Enqueue a planned decode; scratch must hold pl.scratch_bytes (may be null when that is 0).
-hipError_t enqueue_decode(const ldpc_code* c, DecodePlan& pl, void* scratch, hipStream_t st) {
+// With set_attr false the caller has applied plan_lds_limits already (stream capture).
+hipError_t enqueue_decode(const ldpc_code* c, DecodePlan& pl, void* scratch, hipStream_t st, bool set_attr = true) {
   if (pl.grid <= 0) return hipSuccess;
-  hipError_t he = hipSuccess;
-  if (pl.which == 0) {
-    if ((he = set_baseline_lds_limit(pl.lds_limit)) != hipSuccess) return he;
-    return launch_baseline(c->dev, pl.base, pl.fixed, pl.grid, pl.block, st);
+  if (set_attr) {
+    hipError_t he = plan_lds_limits(pl);
+    if (he != hipSuccess) return he;
   }
+  if (pl.which == 0) return launch_baseline(c->dev, pl.base, pl.fixed, pl.grid, pl.block, st);
   if (pl.which == 2) {
     pl.me.msg_global = pl.store_global ? scratch : nullptr;
-    if ((he = set_me_lds_limit(pl.lds_limit)) != hipSuccess) return he;
     return launch_me(c->dev, pl.me, pl.fixed, pl.store_global, pl.topo, pl.grid, pl.block, st);
   }
   pl.dyn.pre_global = pl.store_global ? scratch : nullptr;
-  if ((he = set_dynamic_lds_limit(pl.lds_limit)) != hipSuccess) return he;
   return launch_dynamic(c->dev, pl.dyn, pl.fixed, pl.store_global, pl.topo, pl.grid, st);
 }
 
@@ -1109,6 +1115,130 @@ int ldpc_unrolled_backward(const ldpc_code* c, const float* w, const int32_t* tr
   if (he == hipSuccess) he = launch_unroll_bwd(c->dev, U, grid, chunks, nch, chunk, grad_w, st);
   (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+// ------------------------------------------------------------------------------------------
+// SNR sweeps captured into a hipGraph
+// ------------------------------------------------------------------------------------------
+int ldpc_awgn_frames(const uint8_t* codewords, int32_t P, int32_t N, int32_t B, float sigma2, uint64_t seed,
+                     int32_t point, float* llr_out, void* stream) {
+  if (P < 1 || N < 1 || B < 0 || point < 0 || !(sigma2 > 0.0f) || !std::isfinite(sigma2)) return LDPC_EINVAL;
+  if (B == 0) return LDPC_OK;
+  if (!codewords || !llr_out) return LDPC_EINVAL;
+  hipError_t he = launch_awgn_frames(codewords, P, N, B, sigma2, nullptr, seed, point, llr_out, (hipStream_t)stream);
+  return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+}  // extern "C"
+
+struct ldpc_sweep {
+  const ldpc_code* code = nullptr;
+  int S = 0, B = 0, P = 0;
+  float* llr = nullptr;
+  uint8_t* bits = nullptr;
+  int64_t* upd = nullptr;
+  int64_t* counters = nullptr;  // [S][4]
+  uint64_t* seed = nullptr;
+  void* scratch = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void sweep_release(ldpc_sweep* w) {
+  if (!w) return;
+  if (w->exec) (void)hipGraphExecDestroy(w->exec);
+  if (w->graph) (void)hipGraphDestroy(w->graph);
+  if (w->cap) (void)hipStreamDestroy(w->cap);
+  for (void* p : {(void*)w->llr, (void*)w->bits, (void*)w->upd, (void*)w->counters, (void*)w->seed, w->scratch})
+    if (p) (void)hipFree(p);
+  delete w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldpc_sweep_create(const ldpc_code* c, const ldpc_schedule* s, int64_t max_updates, const uint8_t* codewords,
+                      int32_t P, const float* ebn0_db, int32_t S, float rate, int32_t B, ldpc_sweep** out) {
+  if (!out) return LDPC_EINVAL;
+  *out = nullptr;
+  if (!c || !s || !codewords || P < 1 || !ebn0_db || S < 1 || S > 4096 || B < 1 || !(rate > 0.0f && rate <= 1.0f))
+    return LDPC_EINVAL;
+  if (s->kind == LDPC_REPLAY) return LDPC_EUNSUPPORTED;
+  std::vector<float> sigma2(S);
+  for (int p = 0; p < S; ++p) {
+    if (!std::isfinite(ebn0_db[p])) return LDPC_EINVAL;
+    sigma2[p] = (float)(1.0 / (2.0 * rate * std::pow(10.0, ebn0_db[p] / 10.0)));
+  }
+  ldpc_sweep* w = new (std::nothrow) ldpc_sweep();
+  if (!w) return LDPC_ENOMEM;
+  w->code = c;
+  w->S = S;
+  w->B = B;
+  w->P = P;
+  hipError_t he = hipMalloc((void**)&w->llr, (size_t)B * c->N * sizeof(float));
+  if (he == hipSuccess) he = hipMalloc((void**)&w->bits, (size_t)B * c->N);
+  if (he == hipSuccess) he = hipMalloc((void**)&w->upd, (size_t)B * sizeof(int64_t));
+  if (he == hipSuccess) he = hipMalloc((void**)&w->counters, (size_t)S * 4 * sizeof(int64_t));
+  if (he == hipSuccess) he = hipMalloc((void**)&w->seed, sizeof(uint64_t));
+  if (he != hipSuccess) {
+    sweep_release(w);
+    return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
+  }
+  ldpc_outputs o{};
+  o.bits = w->bits;
+  o.updates_used = w->upd;
+  ldpc_tuning t{};
+  const bool tuned = lookup_tuning(c, s->kind, s->arith, t);
+  DecodePlan pl;
+  int rc = plan_decode(c, s, w->llr, B, max_updates, nullptr, 0, &o, tuned ? &t : nullptr, pl);
+  if (rc != LDPC_OK) {
+    sweep_release(w);
+    return rc;
+  }
+  if (pl.scratch_bytes && (he = hipMalloc(&w->scratch, pl.scratch_bytes)) != hipSuccess) {
+    sweep_release(w);
+    return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
+  }
+  if ((he = plan_lds_limits(pl)) == hipSuccess) he = hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking);
+  // graph: zero the counters, then per point generate -> decode -> count
+  if (he == hipSuccess) he = hipStreamBeginCapture(w->cap, hipStreamCaptureModeRelaxed);
+  if (he == hipSuccess) {
+    hipError_t ce = launch_fill_u64(w->counters, 4 * S, 0, w->cap);
+    for (int p = 0; p < S && ce == hipSuccess; ++p) {
+      ce = launch_awgn_frames(codewords, P, c->N, B, sigma2[p], w->seed, 0, p, w->llr, w->cap);
+      if (ce == hipSuccess) ce = enqueue_decode(c, pl, w->scratch, w->cap, false);
+      if (ce == hipSuccess) ce = launch_count_errors(w->bits, codewords, P, c->N, B, w->upd, w->counters + 4 * p, w->cap);
+    }
+    he = hipStreamEndCapture(w->cap, &w->graph);
+    if (ce != hipSuccess) he = ce;
+  }
+  if (he == hipSuccess) he = hipGraphInstantiate(&w->exec, w->graph, nullptr, nullptr, 0);
+  if (he != hipSuccess) {
+    sweep_release(w);
+    return hip_fail(he);
+  }
+  *out = w;
+  return LDPC_OK;
+}
+
+int ldpc_sweep_run(ldpc_sweep* w, uint64_t seed, int64_t* counters, void* stream) {
+  if (!w || !counters) return LDPC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t he = launch_fill_u64(reinterpret_cast<int64_t*>(w->seed), 1, seed, st);
+  if (he == hipSuccess) he = hipGraphLaunch(w->exec, st);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(counters, w->counters, (size_t)w->S * 4 * sizeof(int64_t), hipMemcpyDeviceToDevice, st);
+  return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+void ldpc_sweep_free(ldpc_sweep* w) {
+  if (!w) return;
+  (void)hipDeviceSynchronize();
+  sweep_release(w);
 }
 
 }  // extern "C"

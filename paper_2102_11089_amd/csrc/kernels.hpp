@@ -200,6 +200,13 @@ hipError_t launch_unroll_bwd(const DevCode& H, const UnrollParams& U, int grid, 
                              float* grad_w, hipStream_t st);
 hipError_t set_unroll_lds_limit(int bytes);
 
+// channel frames and error counters of SNR sweeps
+hipError_t launch_awgn_frames(const uint8_t* cw, int P, int N, int B, float sigma2, const uint64_t* seed_dev,
+                              uint64_t seed_val, int point, float* llr, hipStream_t st);
+hipError_t launch_count_errors(const uint8_t* bits, const uint8_t* cw, int P, int N, int B, const int64_t* upd,
+                               int64_t* counters, hipStream_t st);
+hipError_t launch_fill_u64(int64_t* p, int n, uint64_t v, hipStream_t st);
+
 hipError_t launch_batch(const BatchParams& B, bool fixed, bool pre_global, int topo, int grid, hipStream_t st);
 hipError_t set_batch_lds_limit(int bytes);
 

@@ -28,7 +28,8 @@ ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -
 
 EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode",
            "ldpc_decode_batch", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune", "ldpc_tuning_save",
-           "ldpc_tuning_load", "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
+           "ldpc_tuning_load", "ldpc_awgn_frames", "ldpc_sweep_create", "ldpc_sweep_run", "ldpc_sweep_free",
+           "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
            "ldpc_strerror", "ldpc_last_hip_error")
 UNROLL_MAX_CKPT_EVERY = 128
 STORE_AUTO, STORE_LDS, STORE_GLOBAL = 0, 1, 2
@@ -102,6 +103,15 @@ def load(path: str = LIB_PATH):
     lib.ldpc_tuning_save.restype = C.c_int
     lib.ldpc_tuning_load.argtypes = [C.c_char_p]
     lib.ldpc_tuning_load.restype = C.c_int
+    lib.ldpc_awgn_frames.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_uint64, C.c_int32, P, P]
+    lib.ldpc_awgn_frames.restype = C.c_int
+    lib.ldpc_sweep_create.argtypes = [P, C.POINTER(ldpc_schedule), C.c_int64, P, C.c_int32, P, C.c_int32, C.c_float,
+                                      C.c_int32, C.POINTER(C.c_void_p)]
+    lib.ldpc_sweep_create.restype = C.c_int
+    lib.ldpc_sweep_run.argtypes = [P, C.c_uint64, P, P]
+    lib.ldpc_sweep_run.restype = C.c_int
+    lib.ldpc_sweep_free.argtypes = [P]
+    lib.ldpc_sweep_free.restype = None
     lib.ldpc_unrolled_ckpt_floats.argtypes = [P, C.c_int32, C.c_int32]
     lib.ldpc_unrolled_ckpt_floats.restype = C.c_int64
     lib.ldpc_unrolled_forward.argtypes = [P, P, P, P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P]
@@ -200,6 +210,29 @@ def ldpc_tuning_load(path: str) -> int:
     if n < 0:
         _check(n, "ldpc_tuning_load")
     return int(n)
+
+
+def ldpc_awgn_frames(cw_ptr: int, P: int, N: int, B: int, sigma2: float, seed: int, point: int, llr_ptr: int,
+                     stream: int) -> None:
+    _check(load().ldpc_awgn_frames(cw_ptr, P, N, B, sigma2, seed & (2**64 - 1), point, llr_ptr, stream),
+           "ldpc_awgn_frames")
+
+
+def ldpc_sweep_create(handle, s: ldpc_schedule, max_updates: int, cw_ptr: int, P: int, ebn0_db, rate: float,
+                      B: int) -> int:
+    arr = (C.c_float * len(ebn0_db))(*[float(x) for x in ebn0_db])
+    out = C.c_void_p()
+    _check(load().ldpc_sweep_create(handle, C.byref(s), max_updates, cw_ptr, P, arr, len(ebn0_db), rate, B,
+                                    C.byref(out)), "ldpc_sweep_create")
+    return out.value
+
+
+def ldpc_sweep_run(sweep: int, seed: int, counters_ptr: int, stream: int) -> None:
+    _check(load().ldpc_sweep_run(sweep, seed & (2**64 - 1), counters_ptr, stream), "ldpc_sweep_run")
+
+
+def ldpc_sweep_free(sweep: int) -> None:
+    load().ldpc_sweep_free(sweep)
 
 
 def ldpc_unrolled_ckpt_floats(handle, T: int, ckpt_every: int) -> int:
@@ -429,3 +462,49 @@ def autotune(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int 
     st = (stream if stream is not None else torch.cuda.current_stream(llr.device)).cuda_stream
     t, ms = ldpc_autotune(code.handle, s, llr.data_ptr(), llr.shape[0], max_updates, reps, st)
     return t.as_dict(), ms
+
+
+# ----------------------------------------------------------------------------------------------
+# SNR sweeps (one captured hipGraph per sweep)
+# ----------------------------------------------------------------------------------------------
+def awgn_frames(codewords, B: int, sigma2: float, seed: int, point: int = 0, stream=None):
+    """(B, N) float32 channel LLRs on the device from a (P, N) uint8 CUDA codeword pool."""
+    import torch
+    cw = codewords.contiguous()
+    P, N = cw.shape
+    llr = torch.empty((B, N), dtype=torch.float32, device=cw.device)
+    st = (stream if stream is not None else torch.cuda.current_stream(cw.device)).cuda_stream
+    ldpc_awgn_frames(cw.data_ptr(), P, N, B, sigma2, seed, point, llr.data_ptr(), st)
+    return llr
+
+
+class Sweep:
+    """A captured sweep: ``run(seed)`` returns an int64 (S, 4) CUDA tensor of per-point
+    (frames, frame errors, bit errors, sum of updates)."""
+
+    def __init__(self, code: Code, codewords, ebn0_db, rate: float, B: int, kind: int, arith: int = SPA_F32,
+                 max_updates: int = 0, gamma: float = 0.1, q_bits: int = 6, frac_bits: int = 1, n_p: int = 1,
+                 n_g: int = 16, fill: int = FILL_LOWEST, check_every: int = 1):
+        self.code = code
+        self.codewords = codewords.contiguous()  # referenced by the graph
+        self.S = len(ebn0_db)
+        s = schedule(kind, arith, gamma, q_bits, frac_bits, n_p, n_g, fill, 0, check_every)
+        self.handle = ldpc_sweep_create(code.handle, s, max_updates, self.codewords.data_ptr(),
+                                        self.codewords.shape[0], ebn0_db, rate, B)
+
+    def run(self, seed: int, stream=None):
+        import torch
+        dev = self.codewords.device
+        out = torch.empty((self.S, 4), dtype=torch.int64, device=dev)
+        st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+        ldpc_sweep_run(self.handle, seed, out.data_ptr(), st)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ldpc_sweep_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if _lib is not None:
+            self.close()

@@ -367,6 +367,52 @@ def frames(code: Code, B: int, ebn0_db: float, seed: int, zero_codeword: bool = 
 
 
 # ----------------------------------------------------------------------------------------------
+# Counter-based channel noise (the recipe of the on-device sweep generator)
+# ----------------------------------------------------------------------------------------------
+_PHILOX_M0, _PHILOX_M1 = 0xD2511F53, 0xCD9E8D57   # round multipliers
+_PHILOX_W0, _PHILOX_W1 = 0x9E3779B9, 0xBB67AE85   # key increments (Weyl sequence)
+
+
+def philox4x32_10(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
+    """Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+    as 1, 2, 3", SC 2011): ctr (..., 4) and key (..., 2) uint32 arrays -> (..., 4) uint32."""
+    c = [np.asarray(ctr[..., i], dtype=np.uint64) for i in range(4)]
+    k0 = np.asarray(key[..., 0], dtype=np.uint64) + np.zeros_like(c[0])
+    k1 = np.asarray(key[..., 1], dtype=np.uint64) + np.zeros_like(c[0])
+    mask = np.uint64(0xFFFFFFFF)
+    for r in range(10):
+        p0 = np.uint64(_PHILOX_M0) * c[0]
+        p1 = np.uint64(_PHILOX_M1) * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c = [(hi1 ^ c[1] ^ k0) & mask, lo1, (hi0 ^ c[3] ^ k1) & mask, lo0]
+        k0 = (k0 + np.uint64(_PHILOX_W0)) & mask
+        k1 = (k1 + np.uint64(_PHILOX_W1)) & mask
+    return np.stack(c, axis=-1).astype(np.uint32)
+
+
+def philox_awgn_llr(codewords: np.ndarray, B: int, sigma2: float, seed: int, point: int) -> np.ndarray:
+    """B frames of channel LLRs for sweep point ``point``: frame f carries codeword f mod P of the
+    (P, N) pool; the noise of bit n is one Box-Muller normal from Philox4x32-10 with counter
+    (n, f, point, 0) and key (seed mod 2^32, seed >> 32):  u1 = (x0 + 1) 2^-32, u2 = x1 2^-32,
+    z = sqrt(-2 ln u1) cos(2 pi u2),  llr = 2 (1 - 2c + sigma z) / sigma^2.  float64 result."""
+    P, N = codewords.shape
+    f = np.arange(B, dtype=np.uint64)[:, None]
+    n = np.arange(N, dtype=np.uint64)[None, :]
+    ctr = np.zeros((B, N, 4), dtype=np.uint64)
+    ctr[..., 0] = n
+    ctr[..., 1] = f
+    ctr[..., 2] = point
+    key = np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], dtype=np.uint64)
+    x = philox4x32_10(ctr, key).astype(np.float64)
+    u1 = (x[..., 0] + 1.0) * 2.0 ** -32
+    u2 = x[..., 1] * 2.0 ** -32
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    c = codewords[np.arange(B) % P].astype(np.float64)
+    return 2.0 * ((1.0 - 2.0 * c) + np.sqrt(sigma2) * z) / sigma2
+
+
+# ----------------------------------------------------------------------------------------------
 # Named workloads
 # ----------------------------------------------------------------------------------------------
 def workload_code(name: str) -> Code:

@@ -1,0 +1,114 @@
+"""GPU tests of on-device channel frames and the hipGraph-captured SNR sweep.
+
+* the device generator equals the numpy recipe (Philox4x32-10 + Box-Muller, pinned to its
+  known-answer vectors on the CPU) within FP32 rounding;
+* every replay of a captured sweep equals the same work done eagerly (generate, decode, count),
+  with eager work and synchronisations between replays, and a repeated seed repeats exactly;
+* the error rates of a sweep agree with the oracle decoding frames drawn by the numpy recipe.
+"""
+import numpy as np
+import pytest
+import torch
+from scipy.stats import beta
+
+from oracle import oracle as O
+from paper_2102_11089_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def test_device_frames_match_numpy_recipe(gpu):
+    code = S.workload_code("c0")
+    cw = S.random_codewords(code, 7, 3)
+    t_cw = torch.from_numpy(cw).cuda()
+    for seed, point, ebn0 in ((1, 0, 2.0), (2**40 + 17, 5, 0.5)):
+        s2 = S.sigma2_from_ebn0(ebn0, 0.5)
+        g = gpu.awgn_frames(t_cw, 300, s2, seed, point)
+        torch.cuda.synchronize()
+        ref = S.philox_awgn_llr(cw, 300, s2, seed, point)
+        np.testing.assert_allclose(g.cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
+
+
+def eager_counts(gpu, h, t_cw, ebn0s, rate, B, seed, kind, arith, cap, **kw):
+    P = t_cw.shape[0]
+    rows = []
+    for p, e in enumerate(ebn0s):
+        s2 = S.sigma2_from_ebn0(e, rate)
+        llr = gpu.awgn_frames(t_cw, B, s2, seed, p)
+        r = gpu.decode(h, llr, kind, arith, max_updates=cap, **kw)
+        ref_cw = t_cw[torch.arange(B, device="cuda") % P]
+        err = (r.bits != ref_cw).sum(dim=1)
+        rows.append([B, int((err > 0).sum()), int(err.sum()), int(r.updates_used.sum())])
+    torch.cuda.synchronize()
+    return np.array(rows, dtype=np.int64)
+
+
+@pytest.mark.parametrize("kind,arith", [("cirbp", "f32"), ("flooding", "f32"), ("layered", "fix"), ("me", "fix")])
+def test_sweep_replays_equal_eager(gpu, kind, arith):
+    code = S.qc_24col(24, 12, seed=5)  # N = 576, rate 1/2
+    h = gpu.Code(code)
+    k = {"cirbp": gpu.CIRBP, "flooding": gpu.FLOODING, "layered": gpu.LAYERED, "me": gpu.ME_CIRBP}[kind]
+    a = gpu.SPA_F32 if arith == "f32" else gpu.MS_FIX
+    cap = 20 * code.E if kind in ("flooding", "layered") else 2 * code.E
+    kw = dict(q_bits=8, frac_bits=2, n_p=8, n_g=16)
+    t_cw = torch.from_numpy(S.random_codewords(code, 64, 11)).cuda()
+    ebn0s = [1.0, 1.75, 2.5]
+    B = 512
+    say(f"[sweep {kind} {arith}] N=576, 3 points x {B} frames")
+    sw = gpu.Sweep(h, t_cw, ebn0s, code.design_rate, B, k, a, max_updates=cap, **kw)
+    try:
+        seen = {}
+        for seed in (7, 99, 7):
+            got = sw.run(seed).cpu().numpy()          # graph replay (synchronising copy)
+            exp = eager_counts(gpu, h, t_cw, ebn0s, code.design_rate, B, seed, k, a, cap, **kw)
+            np.testing.assert_array_equal(got, exp)
+            if seed in seen:
+                np.testing.assert_array_equal(got, seen[seed])
+            seen[seed] = got
+            assert np.all(got[:, 0] == B)
+        assert not np.array_equal(seen[7], seen[99])
+    finally:
+        sw.close()
+
+
+def cp(k, n, a=0.05):
+    lo = 0.0 if k == 0 else beta.ppf(a / 2, k, n - k + 1)
+    hi = 1.0 if k == n else beta.ppf(1 - a / 2, k + 1, n - k)
+    return lo, hi
+
+
+def test_sweep_error_rates_agree_with_oracle(gpu):
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    cw = S.random_codewords(code, 50, 12)
+    t_cw = torch.from_numpy(cw).cuda()
+    ebn0s = [1.5, 2.5]
+    B = 3000
+    sw = gpu.Sweep(h, t_cw, ebn0s, 0.5, B, gpu.CIRBP, gpu.SPA_F32, max_updates=2400)
+    try:
+        got = sw.run(2024).cpu().numpy()
+    finally:
+        sw.close()
+    for p, e in enumerate(ebn0s):
+        llr = S.philox_awgn_llr(cw, B, S.sigma2_from_ebn0(e, 0.5), 2024, p)
+        ref = O.decode(code, llr, O.CIRBP, O.SPA, max_updates=2400, threads=16)
+        ref_fe = int(np.any(ref.bits != cw[np.arange(B) % 50], axis=1).sum())
+        lo, hi = cp(ref_fe, B)
+        say(f"  {e} dB: sweep {got[p, 1]} frame errors, oracle {ref_fe} (95% [{lo * B:.1f}, {hi * B:.1f}])")
+        assert lo * B - 2 <= got[p, 1] <= hi * B + 2
+
+
+def test_sweep_rejects_bad_arguments(gpu):
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    t_cw = torch.zeros((1, code.N), dtype=torch.uint8, device="cuda")
+    with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+        gpu.Sweep(h, t_cw, [], 0.5, 10, gpu.CIRBP)
+    with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+        gpu.Sweep(h, t_cw, [1.0], 0.0, 10, gpu.CIRBP)
+    with pytest.raises(RuntimeError, match="LDPC_EUNSUPPORTED"):
+        gpu.Sweep(h, t_cw, [1.0], 0.5, 10, gpu.REPLAY)
