@@ -11,6 +11,15 @@ A step decodes one batch of frames; the value is CIRBP decoded frames per second
 steps.  The same batches are then decoded by flooding and layered BP and reported alongside.
 
 Prints one JSON line.  ``--sweep`` instead prints one JSON line per Eb/N0 point (FER curves).
+``--workload`` measures the other workloads, one JSON line each:
+  c2  one persistent batched launch over 12 quasi-cyclic codes (24-column family, Z in {24, 48, 96},
+      rates 1/2, 2/3, 3/4, 5/6), schedule drawn per frame from {flooding, RBP, CIRBP}, Eb/N0 drawn
+      from {1.0, 1.5, ..., 4.0} dB, FP32 and 8-bit fixed point;
+  c3  ME-CIRBP (Algorithms 4-5) on the BG1-shaped code with Z = 128 (n = 8704), N_P in
+      {8, 16, 32, 64}, N_G = 16, random (keyed) fill, Eb/N0 in {1.0, 1.25, 1.5} dB: update steps
+      against FER;
+  c4  the differentiable unrolled decoder: (3,6)-regular n = 576, 4096 frames, 300 recorded CIRBP
+      updates, damped replay forward with checkpoints every 32 and the adjoint.
 """
 from __future__ import annotations
 
@@ -135,6 +144,200 @@ def cpu_baseline(code, llr_host, cw_host, max_updates, seconds, threads):
     return done, upd, dt
 
 
+def ev_time(stream, fn):
+    """Milliseconds of fn's GPU work on stream (HIP events) and wall seconds."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    r = fn()
+    e1.record(stream)
+    e1.synchronize()
+    return r, e0.elapsed_time(e1), time.perf_counter() - t0
+
+
+def bench_batched(args, ldpc, S, dev):
+    """Workload c2: one persistent launch over uneven codes, schedules and SNRs."""
+    import torch
+    F = args.frames if args.frames != 8192 else 262144
+    rng = np.random.default_rng(args.seed)
+    codes = [S.qc_24col(Z, mb, seed=1) for Z in (24, 48, 96) for mb in (12, 8, 6, 4)]
+    hs = [ldpc.Code(c) for c in codes]
+    snrs = np.arange(1.0, 4.01, 0.5)
+    kinds = [ldpc.FLOODING, ldpc.RBP, ldpc.CIRBP]
+    ci = rng.integers(len(codes), size=F)
+    si = rng.integers(len(snrs), size=F)
+    ki = rng.integers(len(kinds), size=F)
+    # LLR / codeword pools laid out by (code, snr) group, frames contiguous inside a group
+    order = np.lexsort((si, ci))
+    llr_parts, cw_parts, offs = [], [], np.zeros(F, dtype=np.int64)
+    groups = []
+    off = 0
+    for c in range(len(codes)):
+        pool = torch.from_numpy(S.random_codewords(codes[c], 256, args.seed + c)).to(dev)
+        for sidx in range(len(snrs)):
+            fr = order[(ci[order] == c) & (si[order] == sidx)]
+            if len(fr) == 0:
+                continue
+            n = codes[c].N
+            s2 = S.sigma2_from_ebn0(float(snrs[sidx]), codes[c].design_rate)
+            llr_parts.append(ldpc.awgn_frames(pool, len(fr), s2, args.seed, c * 16 + sidx).reshape(-1))
+            cw_parts.append(pool[torch.arange(len(fr), device=dev) % 256].reshape(-1))
+            offs[fr] = off + np.arange(len(fr)) * n
+            groups.append((c, sidx, fr, off, n))
+            off += len(fr) * n
+    llr_pool = torch.cat(llr_parts)
+    cw_pool = torch.cat(cw_parts)
+    print(f"[c2] {F} frames in {len(groups)} (code, Eb/N0) groups ready", file=sys.stderr, flush=True)
+    del llr_parts, cw_parts
+    E = np.array([c.E for c in codes])
+    frames = np.zeros(F, dtype=ldpc.FRAME_DESC)
+    frames["code"] = ci
+    frames["kind"] = np.array(kinds)[ki]
+    frames["gamma"] = 0.1
+    frames["max_updates"] = np.where(np.array(kinds)[ki] == ldpc.FLOODING, 20 * E[ci], 3 * E[ci])
+    frames["llr_off"] = offs
+    frames["out_off"] = offs
+    # longest decodes first: dynamic schedules, larger codes, lower SNR
+    dyn = (np.array(kinds)[ki] != ldpc.FLOODING).astype(np.int64)
+    frames = frames[np.lexsort((si, -E[ci], -dyn))]
+    stream = torch.cuda.Stream(device=dev)
+    for name, arith, q, f in (("f32", ldpc.SPA_F32, 6, 1), ("int8", ldpc.MS_FIX, 8, 2)):
+        for _ in range(args.warmup):
+            with torch.cuda.stream(stream):
+                ldpc.decode_batch(hs, frames, llr_pool, off, arith=arith, q_bits=q, frac_bits=f, stream=stream)
+        kms = []
+        wall = 0.0
+        for _ in range(args.steps):
+            def go():
+                with torch.cuda.stream(stream):
+                    return ldpc.decode_batch(hs, frames, llr_pool, off, arith=arith, q_bits=q, frac_bits=f,
+                                             stream=stream)
+            res, ms, w = ev_time(stream, go)
+            kms.append(ms)
+            wall += w
+            print(f"[c2] {name} batch decoded in {ms:.1f} ms", file=sys.stderr, flush=True)
+        bits, _, upd, _, _ = res
+        assert int((upd < 0).sum()) == 0
+        # frame errors per schedule, from the groups' contiguous blocks
+        frame_err = torch.zeros(F, dtype=torch.bool, device=dev)
+        fr_of = {}
+        for (c, sidx, fr, o, n) in groups:
+            blk = (bits[o:o + len(fr) * n] != cw_pool[o:o + len(fr) * n]).reshape(len(fr), n).any(dim=1)
+            fr_of[(c, sidx)] = (fr, blk)
+        per_kind = {}
+        upd_np = upd.cpu().numpy()
+        # map descriptor order back to frame ids through the offsets
+        desc_off = frames["llr_off"]
+        upd_by_off = dict(zip(desc_off.tolist(), upd_np.tolist()))
+        for (c, sidx), (fr, blk) in fr_of.items():
+            b = blk.cpu().numpy()
+            for kname, kv in (("flooding", ldpc.FLOODING), ("rbp", ldpc.RBP), ("cirbp", ldpc.CIRBP)):
+                sel = np.array(kinds)[ki[fr]] == kv
+                d = per_kind.setdefault(kname, [0, 0, 0])
+                d[0] += int(sel.sum())
+                d[1] += int(b[sel].sum())
+                d[2] += int(sum(upd_by_off[int(x)] for x in offs[fr][sel]))
+        tot_upd = int(upd_np.sum())
+        kern_s = float(np.mean(kms)) / 1e3
+        out = {"metric": "decoded frames/s, one persistent launch over uneven codes and schedules",
+               "value": round(F / kern_s, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32" if name == "f32" else "i8",
+               "data": "synthetic",
+               "config": {"workload": "batched mix: 12 24-column QC codes (Z 24/48/96, rates 1/2..5/6), "
+                                      "per-frame schedule flooding(20 it)/RBP(3E)/CIRBP(3E, gamma 0.1), "
+                                      "Eb/N0 1.0..4.0 dB", "frames": F,
+                          "arith": "sum-product FP32" if name == "f32" else "min-sum 8-bit (q=8, f=2)"},
+               "edge_updates_per_s": round(tot_upd / kern_s, 1), "kernel_ms": [round(x, 3) for x in kms],
+               "per_schedule": {k: {"frames": v[0], "fer": v[1] / max(v[0], 1), "mean_updates": v[2] / max(v[0], 1)}
+                                for k, v in per_kind.items()}}
+        print(json.dumps(out), flush=True)
+
+
+def bench_multi_edge(args, ldpc, S, dev):
+    """Workload c3: ME-CIRBP, update steps against FER."""
+    import torch
+    code = S.workload_code("c3")
+    h = ldpc.Code(code)
+    B = args.frames if args.frames != 8192 else 2048
+    stream = torch.cuda.Stream(device=dev)
+    rows = []
+    total_ms = 0.0
+    total_frames = 0
+    total_upd = 0
+    for eb in (1.0, 1.25, 1.5):
+        batch = make_batches(code, 1, B, eb, args.seed + int(eb * 100), dev)[0]
+        cw, llr = batch
+        for n_p in (8, 16, 32, 64):
+            def go():
+                with torch.cuda.stream(stream):
+                    return ldpc.decode(h, llr, ldpc.ME_CIRBP, ldpc.SPA_F32, max_updates=3 * code.E, gamma=0.1,
+                                       n_p=n_p, n_g=16, fill=ldpc.FILL_HASH, seed=args.seed, stream=stream)
+            r, ms, _ = ev_time(stream, go)
+            print(f"[c3] Eb/N0 {eb} N_P {n_p}: {ms:.1f} ms", file=sys.stderr, flush=True)
+            fe = int(torch.any(r.bits != cw, dim=1).sum())
+            upd = int(r.updates_used.sum())
+            steps = int(r.steps_used.sum())
+            total_ms += ms
+            total_frames += B
+            total_upd += upd
+            rows.append({"ebn0": eb, "n_p": n_p, "fer": fe / B, "frame_errors": fe, "mean_steps": steps / B,
+                         "mean_updates": upd / B, "frames_per_s": round(B / (ms / 1e3), 2),
+                         "edge_updates_per_s": round(upd / (ms / 1e3), 1), "kernel_ms": round(ms, 3)})
+    out = {"metric": "ME-CIRBP decoded frames/s and update steps vs FER", "value": round(total_frames / (total_ms / 1e3), 3),
+           "unit": "frames/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(total_ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "BG1-shaped QC 46x68, Z=128 (n=8704, m=5888, E=40448); ME-CIRBP N_G=16, random "
+                                  "(keyed) fill, gamma 0.1, cap 3E; Eb/N0 1.0/1.25/1.5 dB", "frames_per_point": B},
+           "edge_updates_per_s": round(total_upd / (total_ms / 1e3), 1), "points": rows}
+    print(json.dumps(out), flush=True)
+
+
+def bench_unrolled(args, ldpc, S, dev):
+    """Workload c4: differentiable unrolled decoder, forward + adjoint per training step."""
+    import torch
+    code = S.workload_code("c4")
+    h = ldpc.Code(code)
+    B, T, K = 4096, 300, 32
+    cw, llr = make_batches(code, 1, B, 2.0, args.seed, dev)[0]
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        trace = ldpc.record_schedule(code=h, llr=llr, T=T, stream=stream)
+    x = 1.0 - 2.0 * cw.to(torch.float32)
+    w = torch.ones(code.E, device=dev)
+    fwd_ms, bwd_ms = [], []
+    for it in range(args.warmup + args.steps):
+        def f():
+            with torch.cuda.stream(stream):
+                return ldpc.unrolled_forward(h, llr, w, trace, K, stream=stream)
+        (soft, ck, _), ms_f, _ = ev_time(stream, f)
+        with torch.cuda.stream(stream):
+            gs = -(x * torch.sigmoid(-x * soft)) / soft.numel()
+
+        def b():
+            with torch.cuda.stream(stream):
+                return ldpc.unrolled_backward(h, w, trace, ck, gs, K, stream=stream)
+        (g_llr, g_w), ms_b, _ = ev_time(stream, b)
+        if it >= args.warmup:
+            fwd_ms.append(ms_f)
+            bwd_ms.append(ms_b)
+    step_ms = float(np.mean(fwd_ms)) + float(np.mean(bwd_ms))
+    out = {"metric": "differentiable decoder training steps/s (forward + adjoint)", "value": round(1e3 / step_ms, 3),
+           "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(step_ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "(3,6)-regular PEG n=576 (E=1728), 4096 frames at Eb/N0 2 dB, 300 recorded CIRBP "
+                                  "updates, damped replay, checkpoints every 32, BCE loss", "batch": B, "T": T},
+           "forward_ms": round(float(np.mean(fwd_ms)), 3), "backward_ms": round(float(np.mean(bwd_ms)), 3),
+           "replay_steps_per_s_forward": round(B * T / (np.mean(fwd_ms) / 1e3), 1),
+           "replay_steps_per_s_backward": round(B * T / (np.mean(bwd_ms) / 1e3), 1),
+           "checkpoint_bytes": int(ck.numel() * 4)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +350,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--sweep", type=str, default="", help="comma list of Eb/N0 points: FER curves")
+    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -162,6 +366,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload != "c1":
+        {"c2": bench_batched, "c3": bench_multi_edge, "c4": bench_unrolled}[args.workload](args, ldpc, S, dev)
+        return
+
     code = S.workload_code("c1")
     h = ldpc.Code(code)
     E = code.E
