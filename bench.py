@@ -456,7 +456,7 @@ def main():
                "fallback_fraction": fall / max(upd, 1), "kernel_ms_per_step": [round(x, 3) for x in kms]},
         "roofline": {"bound": "lds", "achieved": round(achieved_gbs, 2), "peak": LDS_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved_gbs / LDS_PEAK_GBS, 6), "traffic": None,
-                     "kernel": "k_dynamic<ArithF32, pre in global scratch>",
+                     "kernel": "k_dynamic<ArithF32, STORE_ALL_GLOBAL, TOPO_QC> (2 frames per CU, work queue)",
                      "bytes_per_update": round(bytes_per_update, 2),
                      "kernel_ms_avg": round(float(np.mean(kms)), 3)},
     }

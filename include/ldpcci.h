@@ -204,9 +204,11 @@ int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t*
 /* ---- launch tuning --------------------------------------------------------------------------
    The arithmetic of a decode does not depend on these knobs (outputs are identical for every
    setting); they only choose where state lives and how the launch is shaped.  Zero = default. */
-#define LDPC_STORE_AUTO 0   /* precomputed messages in LDS when they fit, else global scratch */
-#define LDPC_STORE_LDS 1
-#define LDPC_STORE_GLOBAL 2
+#define LDPC_STORE_AUTO 0        /* messages in LDS when they fit, else the next mode that fits   */
+#define LDPC_STORE_LDS 1         /* C2V and precomputed messages in LDS                           */
+#define LDPC_STORE_GLOBAL 2      /* precomputed messages in a global scratch slot (ME: all)       */
+#define LDPC_STORE_GLOBAL_ALL 3  /* C2V and precomputed messages as interleaved pairs in a global
+                                    slot: the least LDS per frame, so the most frames per CU     */
 #define LDPC_TOPO_AUTO 0    /* quasi-cyclic tables, else LDS copies, else global arrays       */
 #define LDPC_TOPO_GLOBAL 1
 #define LDPC_TOPO_LDS 2
@@ -215,7 +217,7 @@ int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t*
 typedef struct {
   int32_t block;         /* threads per frame: flooding / layered / ME-CIRBP (64..1024, step 64)   */
   int32_t frames_per_cu; /* single-edge and ME: resident frames per CU of a persistent grid (1..32) */
-  int32_t storage;       /* LDPC_STORE_*: precomputed (single-edge) or all (ME) messages            */
+  int32_t storage;       /* LDPC_STORE_*: where the messages of a frame live                        */
   int32_t topology;      /* LDPC_TOPO_*: where the kernels read H from                              */
 } ldpc_tuning;
 
@@ -232,8 +234,8 @@ int ldpc_get_tuning(const ldpc_code* code, int32_t kind, int32_t arith, ldpc_tun
    caller's frames (llr_in: device [B][N]; best of reps timed runs after one warm-up, HIP events on
    stream), stores the fastest with ldpc_set_tuning and returns it (best, best_ms nullable).
    Blocking: synchronizes stream.  Candidates: block in {64..1024} for flooding / layered;
-   storage x topology x frames_per_cu in {auto, 1, 2, 4, 8, 16} (and block in {64, 256, 1024}
-   for ME-CIRBP) for the dynamic schedules.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),
+   storage (LDS, pre global, all global) x topology x frames_per_cu in {auto, 1, 2, 4, 8, 16}
+   (and block in {64, 256, 1024} for ME-CIRBP) for the dynamic schedules.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),
    LDPC_ECAPACITY (no candidate fits), LDPC_EHIP. */
 int ldpc_autotune(const ldpc_code* code, const ldpc_schedule* s, const float* llr_in, int32_t B,
                   int64_t max_updates, int32_t reps, ldpc_tuning* best, float* best_ms, void* stream);

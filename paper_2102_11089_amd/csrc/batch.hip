@@ -19,22 +19,29 @@ __global__ void k_zero_int(int* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
-// flooding / layered for one wavefront, state in the dynamic layout's c2v and L regions
-template <class A, class Topo>
+// lanes of the wave exchange values through the frame's message store (LDS, or global memory)
+template <int STORE>
+__device__ __forceinline__ void store_sync() {
+  if constexpr (STORE == STORE_ALL_GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  wave_sync();
+}
+
+// flooding / layered for one wavefront: L in the dynamic layout's L region, the C2V messages in
+// the frame's message store
+template <class A, int STORE, class Topo>
 __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
-                                                    const FrameJob& J) {
+                                                    const MsgStore<typename A::msg_t, STORE>& ms, const FrameJob& J) {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   using val_t = typename A::val_t;
   using Acc = typename RowAccOf<A>::type;
   const int lane = threadIdx.x & (WAVE - 1);
   unsigned char* lds = dyn_lds();
-  msg_t* c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
   llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
   const int N = H.N, M = H.M, E = H.E;
   for (int n = lane; n < N; n += WAVE) L[n] = (llr_t)ar.channel(J.llr[n]);
-  for (int e = lane; e < E; e += WAVE) c2v[e] = (msg_t)0;
-  wave_sync();
+  for (int e = lane; e < E; e += WAVE) ms.set_c(e, (msg_t)0);
+  store_sync<STORE>();
   auto syndrome = [&]() {
     int u = 0;
     for (int m = lane; m < M; m += WAVE) {
@@ -53,22 +60,22 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
         const int rs = G.row_start(m), dc = G.row_deg(m);
         Acc acc;
         for (int p = 0; p < dc; ++p) {
-          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)c2v[rs + p]));
+          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)ms.c(rs + p)));
           acc.add(p, v, row_aux(ar, v));
         }
         for (int p = 0; p < dc; ++p) {
-          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)c2v[rs + p]));
-          c2v[rs + p] = (msg_t)acc.out(p, v, row_aux(ar, v));
+          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)ms.c(rs + p)));
+          ms.set_c(rs + p, (msg_t)acc.out(p, v, row_aux(ar, v)));
         }
       }
-      wave_sync();
+      store_sync<STORE>();
       for (int n = lane; n < N; n += WAVE) {
         val_t l = ar.channel(J.llr[n]);
         const int dv = G.vn_deg(n);
         for (int k = 0; k < dv; ++k) {
           int m, e;
           G.vn_edge(n, k, m, e);
-          l += (val_t)c2v[e];
+          l += (val_t)ms.c(e);
         }
         L[n] = (llr_t)l;
       }
@@ -81,19 +88,19 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
           Acc acc;
           for (int p = 0; p < dc; ++p) {
             const int j = G.row_vn(m, rs, p);
-            const val_t v = ar.vin((val_t)L[j] - (val_t)c2v[rs + p]);
+            const val_t v = ar.vin((val_t)L[j] - (val_t)ms.c(rs + p));
             acc.add(p, v, row_aux(ar, v));
           }
           for (int p = 0; p < dc; ++p) {
             const int j = G.row_vn(m, rs, p);
-            const val_t vr = (val_t)L[j] - (val_t)c2v[rs + p];
+            const val_t vr = (val_t)L[j] - (val_t)ms.c(rs + p);
             const val_t v = ar.vin(vr);
             const val_t o = acc.out(p, v, row_aux(ar, v));
-            c2v[rs + p] = (msg_t)o;
+            ms.set_c(rs + p, (msg_t)o);
             L[j] = (llr_t)(vr + o);
           }
         }
-        wave_sync();
+        store_sync<STORE>();
       }
     }
     t += E;
@@ -110,18 +117,16 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
     if (J.steps_used) *J.steps_used = it;
     if (J.fallbacks) *J.fallbacks = 0;
   }
-  wave_sync();
+  store_sync<STORE>();
 }
 
-template <class A, bool PRE_GLOBAL, int TOPO>
+template <class A, int STORE, int TOPO>
 __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
   using msg_t = typename A::msg_t;
   const DynParams& P = B.P;
   unsigned char* lds = dyn_lds();
   const int lane = threadIdx.x;
-  msg_t* pre;
-  if constexpr (PRE_GLOBAL) pre = reinterpret_cast<msg_t*>(P.pre_global) + (size_t)blockIdx.x * B.max_E;
-  else pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
+  const auto ms = make_store<msg_t, STORE>(P, (size_t)B.max_E);
   int* lut = reinterpret_cast<int*>(lds + P.off_lut);
   A ar;
   ar.qmax = P.qmax;
@@ -176,43 +181,55 @@ __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
     J.fallbacks = B.fallbacks ? B.fallbacks + f : nullptr;
     J.trace = nullptr;
     J.dump_c2v = J.dump_pre = J.dump_L = J.dump_Lt = J.dump_D = nullptr;
-    if (d.kind == KIND_FLOODING || d.kind == KIND_LAYERED) wave_baseline_frame<A>(H, G, ar, P, J);
-    else dyn_decode_frame<A, PRE_GLOBAL>(H, G, ar, P, pre, J);
+    if (d.kind == KIND_FLOODING || d.kind == KIND_LAYERED) wave_baseline_frame<A, STORE>(H, G, ar, P, ms, J);
+    else dyn_decode_frame<A, STORE>(H, G, ar, P, ms, J);
   }
 }
 
-template <class A, bool PG, int TP>
+template <class A, int ST, int TP>
 static hipError_t launch_batch_k(const BatchParams& B, int grid, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, B.queue);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_batch<A, PG, TP>), dim3(grid), dim3(WAVE), B.P.lds_bytes, st, B);
+  hipLaunchKernelGGL((k_batch<A, ST, TP>), dim3(grid), dim3(WAVE), B.P.lds_bytes, st, B);
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchParams& B, bool fixed, bool pre_global, int topo, int grid, hipStream_t st) {
-  if (fixed) {
-    if (topo == TOPO_QC) return pre_global ? launch_batch_k<ArithFix, true, TOPO_QC>(B, grid, st) : launch_batch_k<ArithFix, false, TOPO_QC>(B, grid, st);
-    return pre_global ? launch_batch_k<ArithFix, true, TOPO_GLOBAL>(B, grid, st) : launch_batch_k<ArithFix, false, TOPO_GLOBAL>(B, grid, st);
-  }
-  if (topo == TOPO_QC) return pre_global ? launch_batch_k<ArithF32, true, TOPO_QC>(B, grid, st) : launch_batch_k<ArithF32, false, TOPO_QC>(B, grid, st);
-  return pre_global ? launch_batch_k<ArithF32, true, TOPO_GLOBAL>(B, grid, st) : launch_batch_k<ArithF32, false, TOPO_GLOBAL>(B, grid, st);
+template <class A, int ST>
+static hipError_t launch_batch_t(const BatchParams& B, int topo, int grid, hipStream_t st) {
+  return topo == TOPO_QC ? launch_batch_k<A, ST, TOPO_QC>(B, grid, st) : launch_batch_k<A, ST, TOPO_GLOBAL>(B, grid, st);
 }
 
-template <class A, bool PG, int TP>
+template <class A>
+static hipError_t launch_batch_s(const BatchParams& B, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_ALL_GLOBAL) return launch_batch_t<A, STORE_ALL_GLOBAL>(B, topo, grid, st);
+  if (store == STORE_PRE_GLOBAL) return launch_batch_t<A, STORE_PRE_GLOBAL>(B, topo, grid, st);
+  return launch_batch_t<A, STORE_LDS>(B, topo, grid, st);
+}
+
+hipError_t launch_batch(const BatchParams& B, bool fixed, int store, int topo, int grid, hipStream_t st) {
+  return fixed ? launch_batch_s<ArithFix>(B, store, topo, grid, st) : launch_batch_s<ArithF32>(B, store, topo, grid, st);
+}
+
+template <class A, int ST, int TP>
 static hipError_t set_batch_one(int bytes) {
-  return hipFuncSetAttribute((const void*)k_batch<A, PG, TP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return hipFuncSetAttribute((const void*)k_batch<A, ST, TP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <class A, int ST>
+static hipError_t set_batch_store(int bytes) {
+  hipError_t e = set_batch_one<A, ST, TOPO_GLOBAL>(bytes);
+  if (e == hipSuccess) e = set_batch_one<A, ST, TOPO_QC>(bytes);
+  return e;
 }
 
 hipError_t set_batch_lds_limit(int bytes) {
   hipError_t e = hipSuccess;
-#define LDPC_SET(A, PG, TP) \
-  if ((e = set_batch_one<A, PG, TP>(bytes)) != hipSuccess) return e;
-  LDPC_SET(ArithF32, false, TOPO_GLOBAL) LDPC_SET(ArithF32, false, TOPO_QC)
-  LDPC_SET(ArithF32, true, TOPO_GLOBAL) LDPC_SET(ArithF32, true, TOPO_QC)
-  LDPC_SET(ArithFix, false, TOPO_GLOBAL) LDPC_SET(ArithFix, false, TOPO_QC)
-  LDPC_SET(ArithFix, true, TOPO_GLOBAL) LDPC_SET(ArithFix, true, TOPO_QC)
-#undef LDPC_SET
+  for (hipError_t r : {set_batch_store<ArithF32, STORE_LDS>(bytes), set_batch_store<ArithF32, STORE_PRE_GLOBAL>(bytes),
+                       set_batch_store<ArithF32, STORE_ALL_GLOBAL>(bytes), set_batch_store<ArithFix, STORE_LDS>(bytes),
+                       set_batch_store<ArithFix, STORE_PRE_GLOBAL>(bytes),
+                       set_batch_store<ArithFix, STORE_ALL_GLOBAL>(bytes)})
+    if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }
 

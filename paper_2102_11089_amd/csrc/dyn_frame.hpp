@@ -22,16 +22,68 @@ __device__ __forceinline__ unsigned char* dyn_lds() {
   return lds_dyn;
 }
 
-template <class A, bool PRE_GLOBAL, class Topo>
+// Where a frame's C2V messages (c2v) and precomputed messages (pre) live: both in LDS, pre in a
+// global scratch slot, or both in a global slot as interleaved (c2v, pre) pairs so that one load
+// brings the two values of an edge.
+template <class msg_t, int STORE>
+struct MsgStore {
+  msg_t* c2v;  // LDS
+  msg_t* pre;  // LDS (STORE_LDS) or global (STORE_PRE_GLOBAL)
+  static constexpr bool kGlobal = STORE != STORE_LDS;
+  __device__ __forceinline__ msg_t c(int e) const { return c2v[e]; }
+  __device__ __forceinline__ msg_t p(int e) const { return pre[e]; }
+  __device__ __forceinline__ void set_c(int e, msg_t v) const { c2v[e] = v; }
+  __device__ __forceinline__ void set_p(int e, msg_t v) const { pre[e] = v; }
+  __device__ __forceinline__ void cp(int e, msg_t& cv, msg_t& pv) const {
+    cv = c2v[e];
+    pv = pre[e];
+  }
+};
+
+template <class msg_t>
+struct alignas(2 * sizeof(msg_t)) MsgPair {
+  msg_t c, p;
+};
+
+template <class msg_t>
+struct MsgStore<msg_t, STORE_ALL_GLOBAL> {
+  MsgPair<msg_t>* m;  // global, [E]
+  static constexpr bool kGlobal = true;
+  __device__ __forceinline__ msg_t c(int e) const { return m[e].c; }
+  __device__ __forceinline__ msg_t p(int e) const { return m[e].p; }
+  __device__ __forceinline__ void set_c(int e, msg_t v) const { m[e].c = v; }
+  __device__ __forceinline__ void set_p(int e, msg_t v) const { m[e].p = v; }
+  __device__ __forceinline__ void cp(int e, msg_t& cv, msg_t& pv) const {
+    const MsgPair<msg_t> x = m[e];
+    cv = x.c;
+    pv = x.p;
+  }
+};
+
+// message store of the workgroup's frame slot (slot_edges = edges reserved per workgroup)
+template <class msg_t, int STORE>
+__device__ __forceinline__ MsgStore<msg_t, STORE> make_store(const DynParams& P, size_t slot_edges) {
+  unsigned char* lds = dyn_lds();
+  MsgStore<msg_t, STORE> ms;
+  if constexpr (STORE == STORE_ALL_GLOBAL) {
+    ms.m = reinterpret_cast<MsgPair<msg_t>*>(P.pre_global) + (size_t)blockIdx.x * slot_edges;
+  } else {
+    ms.c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
+    if constexpr (STORE == STORE_PRE_GLOBAL) ms.pre = reinterpret_cast<msg_t*>(P.pre_global) + (size_t)blockIdx.x * slot_edges;
+    else ms.pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
+  }
+  return ms;
+}
+
+template <class A, int STORE, class Topo>
 __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
-                                                 typename A::msg_t* pre, const FrameJob& J) {
+                                                 const MsgStore<typename A::msg_t, STORE>& ms, const FrameJob& J) {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   using val_t = typename A::val_t;
   using Acc = typename RowAccOf<A>::type;
   const int lane = threadIdx.x & (WAVE - 1);
   unsigned char* lds = dyn_lds();
-  msg_t* c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
   llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
   llr_t* Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
   uint32_t* D = reinterpret_cast<uint32_t*>(lds + P.off_D);
@@ -49,7 +101,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   // ---------------- Algorithm 1 lines 1-3: initial state --------------------------------
   const float* llr = J.llr;
   for (int n = lane; n < N; n += WAVE) L[n] = (llr_t)ar.channel(llr[n]);
-  for (int e = lane; e < E; e += WAVE) c2v[e] = (msg_t)0;
+  for (int e = lane; e < E; e += WAVE) ms.set_c(e, (msg_t)0);
   for (int w = lane; w < nbd_words; w += WAVE) dmask[w] = 0u;
   for (int w = lane; w < nbc_words; w += WAVE) cmask[w] = 0u;
   wave_sync();
@@ -69,7 +121,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     for (int p = 0; p < dc; ++p) {
       const val_t v = ar.vin((val_t)L[G.row_vn(m, rs, p)]);
       const val_t o = acc.out(p, v, row_aux(ar, v));
-      pre[rs + p] = (msg_t)o;
+      ms.set_p(rs + p, (msg_t)o);
       k = umax64(k, mkkey(ar.res(o, (val_t)0), (uint32_t)(rs + p)));
     }
     ckey[m] = k;
@@ -77,7 +129,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     unsat_local += par;
   }
   int unsat = wave_sum_i32(unsat_local);
-  if constexpr (PRE_GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // pre[] stores done
+  if constexpr (STORE != STORE_LDS) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // message stores done
   wave_sync();
   for (int n = lane; n < N; n += WAVE) {
     val_t lt = (val_t)L[n];
@@ -85,7 +137,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     for (int k = 0; k < dv; ++k) {
       int m, e;
       G.vn_edge(n, k, m, e);
-      lt += (val_t)pre[e];
+      lt += (val_t)ms.p(e);
     }
     Lt[n] = (llr_t)lt;
     D[n] = with_ci ? ar.ci((val_t)L[n], lt) : 0u;
@@ -144,7 +196,9 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         if (lane < dvs) {
           int e;
           G.vn_edge(nsel, lane, mk, e);
-          k = mkkey(ar.res((val_t)pre[e], (val_t)c2v[e]), (uint32_t)e);
+          msg_t cm, pm;
+          ms.cp(e, cm, pm);
+          k = mkkey(ar.res((val_t)pm, (val_t)cm), (uint32_t)e);
         }
         const uint64_t kmax = wave_max_u64(k);
         estar = (int)key_idx(kmax);
@@ -173,15 +227,17 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     if (lane < ncnt) ent0 = H.nbr[noff + lane];  // first pass of the two-hop table, early
 
     // ---- propagation (Algorithm 1 line 9) and D_{n*} ----
-    const val_t newv = (val_t)pre[estar];
-    const val_t oldv = (val_t)c2v[estar];
+    msg_t c_star, p_star;
+    ms.cp(estar, c_star, p_star);
+    const val_t newv = (val_t)p_star;
+    const val_t oldv = (val_t)c_star;
     const val_t Lold = (val_t)L[nstar];
     const val_t Lnew = Lold + (newv - oldv);
     const uint32_t dn_old = D[nstar];
     const uint32_t dn_new = with_ci ? ar.ci(Lnew, (val_t)Lt[nstar]) : 0u;
     wave_sync();
     if (lane == 0) {
-      c2v[estar] = (msg_t)newv;
+      ms.set_c(estar, (msg_t)newv);
       L[nstar] = (llr_t)Lnew;
       if (with_ci) {
         D[nstar] = dn_new;
@@ -218,8 +274,10 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       const bool self = valid && j == nstar;
       val_t cv = 0, po = 0, lv = 0;
       if (valid) {
-        cv = (val_t)c2v[e];
-        po = (val_t)pre[e];
+        msg_t cm, pm;
+        ms.cp(e, cm, pm);
+        cv = e == estar ? newv : (val_t)cm;  // this update's propagation (its store may be in flight)
+        po = (val_t)pm;
         lv = self ? Lnew : (val_t)L[j];
       }
       const val_t v = ar.vin(ar.v2c(lv, cv));
@@ -249,7 +307,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         if (upd) pv = o;
       }
       if (upd) {
-        pre[e] = (msg_t)pv;
+        ms.set_p(e, (msg_t)pv);
         if (with_ci) atomicAdd(&Lt[j], (llr_t)(pv - po));
       }
       tj[ps * WAVE + lane] = upd ? j : -1;
@@ -262,7 +320,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         else if (rk < ok && cblk[m >> 6] == ok) atomicOr(&cmask[(m >> 6) >> 5], 1u << ((m >> 6) & 31));
       }
     }
-    if constexpr (PRE_GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // pre[] stores done
+    if constexpr (STORE != STORE_LDS) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // message stores done
     wave_sync();
     PROF_MARK(3)
     // ---- CI of the VNs of the touched checks (Algorithm 1 line 12) ----
@@ -336,8 +394,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     if (J.dump_D) J.dump_D[n] = ar.d_float(D[n]);
   }
   for (int e = lane; e < E; e += WAVE) {
-    if (J.dump_c2v) J.dump_c2v[e] = ar.as_float((val_t)c2v[e]);
-    if (J.dump_pre) J.dump_pre[e] = ar.as_float((val_t)pre[e]);
+    if (J.dump_c2v) J.dump_c2v[e] = ar.as_float((val_t)ms.c(e));
+    if (J.dump_pre) J.dump_pre[e] = ar.as_float((val_t)ms.p(e));
   }
   if (lane == 0) {
     *J.updates_used = t;

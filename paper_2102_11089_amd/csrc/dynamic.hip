@@ -1,10 +1,11 @@
 // Single-edge dynamic schedules on gfx950: residual BP (RBP, Sec. II-A steps 1-4), CIRBP
 // (Algorithm 1, Sec. III-B) and forced-order replay of a recorded schedule.
 //
-// One wavefront (64 lanes, one workgroup) decodes one codeword at a time; workgroups loop over
-// frames.  The frame's state lives in LDS:
-//   c2v[E], pre[E]      current and precomputed C2V messages (pre may live in a global scratch
-//                        slot per workgroup when it does not fit),
+// One wavefront (64 lanes, one workgroup) decodes one codeword at a time.  A persistent grid pulls
+// frames from a device counter (frames differ widely in length, so fixed striding would leave a
+// long tail); otherwise there is one workgroup per frame.  The frame's state lives in LDS:
+//   c2v[E], pre[E]      current and precomputed C2V messages (pre, or both as interleaved pairs,
+//                        may live in a global scratch slot per workgroup instead),
 //   L[N], Lt[N]         total and precomputed total LLRs,
 //   D[N]                CI of every VN as key bits,
 //   ckey[M]             per check: max over its edges of (residual, lowest edge id),
@@ -26,14 +27,12 @@ namespace ldpc {
 
 
 
-template <class A, bool PRE_GLOBAL, int TOPO>
+template <class A, int STORE, int TOPO>
 __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
   using msg_t = typename A::msg_t;
   unsigned char* lds = dyn_lds();
   const int lane = threadIdx.x;
-  msg_t* pre;
-  if constexpr (PRE_GLOBAL) pre = reinterpret_cast<msg_t*>(P.pre_global) + (size_t)blockIdx.x * H.E;
-  else pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
+  const auto ms = make_store<msg_t, STORE>(P, (size_t)H.E);
   int* lut = reinterpret_cast<int*>(lds + P.off_lut);
   A ar;
   ar.qmax = P.qmax;
@@ -44,7 +43,9 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
   }
   const auto G = TopoSel<TOPO>::make(H, lds + P.off_topo, lane, WAVE);
   wave_sync();
-  for (int f = blockIdx.x; f < P.B; f += gridDim.x) {
+  int f = blockIdx.x;
+  if (P.queue) f = uni(lane == 0 ? atomicAdd(P.queue, 1) : 0);
+  while (f < P.B) {
     FrameJob J;
     J.kind = P.kind;
     J.gamma_bits = P.gamma_bits;
@@ -64,46 +65,56 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
     J.dump_L = P.out.dump_L ? P.out.dump_L + (size_t)f * H.N : nullptr;
     J.dump_Lt = P.out.dump_Lt ? P.out.dump_Lt + (size_t)f * H.N : nullptr;
     J.dump_D = P.out.dump_D ? P.out.dump_D + (size_t)f * H.N : nullptr;
-    dyn_decode_frame<A, PRE_GLOBAL>(H, G, ar, P, pre, J);
+    dyn_decode_frame<A, STORE>(H, G, ar, P, ms, J);
+    if (P.queue) f = uni(lane == 0 ? atomicAdd(P.queue, 1) : 0);
+    else f += gridDim.x;
   }
 }
 
-template <class A, bool PG, int TP>
+template <class A, int ST, int TP>
 static hipError_t launch_dyn(const DevCode& H, const DynParams& P, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_dynamic<A, PG, TP>), dim3(grid), dim3(WAVE), P.lds_bytes, st, H, P);
+  hipLaunchKernelGGL((k_dynamic<A, ST, TP>), dim3(grid), dim3(WAVE), P.lds_bytes, st, H, P);
   return hipGetLastError();
 }
 
-template <class A, bool PG>
+template <class A, int ST>
 static hipError_t launch_dyn_t(const DevCode& H, const DynParams& P, int topo, int grid, hipStream_t st) {
-  if (topo == TOPO_QC) return launch_dyn<A, PG, TOPO_QC>(H, P, grid, st);
-  if (topo == TOPO_LDS) return launch_dyn<A, PG, TOPO_LDS>(H, P, grid, st);
-  return launch_dyn<A, PG, TOPO_GLOBAL>(H, P, grid, st);
+  if (topo == TOPO_QC) return launch_dyn<A, ST, TOPO_QC>(H, P, grid, st);
+  if (topo == TOPO_LDS) return launch_dyn<A, ST, TOPO_LDS>(H, P, grid, st);
+  return launch_dyn<A, ST, TOPO_GLOBAL>(H, P, grid, st);
 }
 
-hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, bool pre_global, int topo, int grid,
+template <class A>
+static hipError_t launch_dyn_s(const DevCode& H, const DynParams& P, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_ALL_GLOBAL) return launch_dyn_t<A, STORE_ALL_GLOBAL>(H, P, topo, grid, st);
+  if (store == STORE_PRE_GLOBAL) return launch_dyn_t<A, STORE_PRE_GLOBAL>(H, P, topo, grid, st);
+  return launch_dyn_t<A, STORE_LDS>(H, P, topo, grid, st);
+}
+
+hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, int store, int topo, int grid,
                           hipStream_t st) {
-  if (fixed)
-    return pre_global ? launch_dyn_t<ArithFix, true>(H, P, topo, grid, st)
-                      : launch_dyn_t<ArithFix, false>(H, P, topo, grid, st);
-  return pre_global ? launch_dyn_t<ArithF32, true>(H, P, topo, grid, st)
-                    : launch_dyn_t<ArithF32, false>(H, P, topo, grid, st);
+  return fixed ? launch_dyn_s<ArithFix>(H, P, store, topo, grid, st) : launch_dyn_s<ArithF32>(H, P, store, topo, grid, st);
 }
 
-template <class A, bool PG, int TP>
+template <class A, int ST, int TP>
 static hipError_t set_one(int bytes) {
-  return hipFuncSetAttribute((const void*)k_dynamic<A, PG, TP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return hipFuncSetAttribute((const void*)k_dynamic<A, ST, TP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <class A, int ST>
+static hipError_t set_store(int bytes) {
+  hipError_t e = set_one<A, ST, TOPO_GLOBAL>(bytes);
+  if (e == hipSuccess) e = set_one<A, ST, TOPO_LDS>(bytes);
+  if (e == hipSuccess) e = set_one<A, ST, TOPO_QC>(bytes);
+  return e;
 }
 
 hipError_t set_dynamic_lds_limit(int bytes) {
   hipError_t e = hipSuccess;
-#define LDPC_SET(A, PG, TP) \
-  if ((e = set_one<A, PG, TP>(bytes)) != hipSuccess) return e;
-  LDPC_SET(ArithF32, false, TOPO_GLOBAL) LDPC_SET(ArithF32, false, TOPO_LDS) LDPC_SET(ArithF32, false, TOPO_QC)
-  LDPC_SET(ArithF32, true, TOPO_GLOBAL) LDPC_SET(ArithF32, true, TOPO_LDS) LDPC_SET(ArithF32, true, TOPO_QC)
-  LDPC_SET(ArithFix, false, TOPO_GLOBAL) LDPC_SET(ArithFix, false, TOPO_LDS) LDPC_SET(ArithFix, false, TOPO_QC)
-  LDPC_SET(ArithFix, true, TOPO_GLOBAL) LDPC_SET(ArithFix, true, TOPO_LDS) LDPC_SET(ArithFix, true, TOPO_QC)
-#undef LDPC_SET
+  for (hipError_t r : {set_store<ArithF32, STORE_LDS>(bytes), set_store<ArithF32, STORE_PRE_GLOBAL>(bytes),
+                       set_store<ArithF32, STORE_ALL_GLOBAL>(bytes), set_store<ArithFix, STORE_LDS>(bytes),
+                       set_store<ArithFix, STORE_PRE_GLOBAL>(bytes), set_store<ArithFix, STORE_ALL_GLOBAL>(bytes)})
+    if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }
 

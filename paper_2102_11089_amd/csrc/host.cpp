@@ -111,7 +111,8 @@ struct Dims {
   long long topo_bytes;
 };
 
-DynLayout dyn_layout_dims(const Dims& c, bool fixed, bool pre_global, int extra_bytes) {
+// store: STORE_LDS (c2v and pre in LDS), STORE_PRE_GLOBAL (c2v only), STORE_ALL_GLOBAL (neither)
+DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int extra_bytes) {
   DynLayout L{};
   const int msg = fixed ? 1 : 4, llr = 4, val = 4;
   L.nbd = (c.N + WAVE - 1) / WAVE;
@@ -119,8 +120,8 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, bool pre_global, int extra_
   L.nbd_words = (L.nbd + 31) / 32;
   L.nbc_words = (L.nbc + 31) / 32;
   int o = 0;
-  L.off_c2v = o; o = align16(o + c.E * msg);
-  L.off_pre = o; if (!pre_global) o = align16(o + c.E * msg);
+  L.off_c2v = o; if (store != STORE_ALL_GLOBAL) o = align16(o + c.E * msg);
+  L.off_pre = o; if (store == STORE_LDS) o = align16(o + c.E * msg);
   L.off_L = o; o = align16(o + c.N * llr);
   L.off_Lt = o; o = align16(o + c.N * llr);
   L.off_D = o; o = align16(o + c.N * 4);
@@ -140,8 +141,8 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, bool pre_global, int extra_
   return L;
 }
 
-DynLayout dyn_layout(const ldpc_code* c, bool fixed, bool pre_global, int topo, int extra_bytes) {
-  return dyn_layout_dims(Dims{c->E, c->N, c->M, topo_bytes(c, topo)}, fixed, pre_global, extra_bytes);
+DynLayout dyn_layout(const ldpc_code* c, bool fixed, int store, int topo, int extra_bytes) {
+  return dyn_layout_dims(Dims{c->E, c->N, c->M, topo_bytes(c, topo)}, fixed, store, extra_bytes);
 }
 
 
@@ -498,8 +499,8 @@ int ldpc_code_info(const ldpc_code* c, ldpc_code_stats* out) {
   out->n_layers = c->n_layers;
   out->max_touch = c->max_touch;
   const int topo = c->h_qc.empty() ? TOPO_LDS : TOPO_QC;
-  out->lds_bytes_f32 = dyn_layout(c, false, false, topo, 0).total;
-  out->lds_bytes_fix = dyn_layout(c, true, false, topo, 0).total;
+  out->lds_bytes_f32 = dyn_layout(c, false, STORE_LDS, topo, 0).total;
+  out->lds_bytes_fix = dyn_layout(c, true, STORE_LDS, topo, 0).total;
   return LDPC_OK;
 }
 
@@ -522,12 +523,15 @@ struct DecodePlan {
   DynParams dyn{};
   MeParams me{};
   int grid = 0, block = WAVE, topo = TOPO_GLOBAL;
-  bool store_global = false;  // single-edge: pre[] in global scratch; ME: c2v and pre in global scratch
+  int store = STORE_LDS;      // single-edge: Store; ME: STORE_LDS or STORE_ALL_GLOBAL (c2v and pre in global)
+  bool persistent = false;    // single-edge: persistent grid fed by a work queue at the front of scratch
   size_t scratch_bytes = 0;
   int lds_limit = 0;
 };
 
 bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
+
+constexpr size_t kQueueBytes = 256;  // work-queue counter at the front of a persistent launch's scratch
 
 // tuning knob -> candidate topologies (empty: the knob does not apply to this code)
 std::vector<int> topo_choices(const ldpc_code* c, int knob) {
@@ -544,7 +548,7 @@ int check_tuning(const ldpc_tuning* t) {
   if (!t) return LDPC_OK;
   if (t->block != 0 && !valid_block(t->block)) return LDPC_EINVAL;
   if (t->frames_per_cu < 0 || t->frames_per_cu > 32) return LDPC_EINVAL;
-  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL) return LDPC_EINVAL;
+  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_ALL) return LDPC_EINVAL;
   if (t->topology < LDPC_TOPO_AUTO || t->topology > LDPC_TOPO_QC) return LDPC_EINVAL;
   return LDPC_OK;
 }
@@ -623,9 +627,10 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (c->nbr_max_cnt > NBR_PMAX * WAVE) return LDPC_EUNSUPPORTED;
   const std::vector<int> topos = topo_choices(c, T.topology);
   if (topos.empty()) return LDPC_EUNSUPPORTED;
-  std::vector<bool> stores = {false, true};
-  if (T.storage == LDPC_STORE_LDS) stores = {false};
-  if (T.storage == LDPC_STORE_GLOBAL) stores = {true};
+  std::vector<int> stores = {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL};
+  if (T.storage == LDPC_STORE_LDS) stores = {STORE_LDS};
+  if (T.storage == LDPC_STORE_GLOBAL) stores = {STORE_PRE_GLOBAL};
+  if (T.storage == LDPC_STORE_GLOBAL_ALL) stores = {STORE_ALL_GLOBAL};
   const int lut_off = 257 * (fixed ? s->frac_bits : 0);
 
   if (s->kind == LDPC_ME_CIRBP) {
@@ -644,12 +649,15 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     Q.seed = s->seed;
     bool found = false;
     MeLayout Ly{};
-    for (bool g : stores) {
+    std::vector<bool> me_stores = {false, true};
+    if (T.storage == LDPC_STORE_LDS) me_stores = {false};
+    if (T.storage == LDPC_STORE_GLOBAL || T.storage == LDPC_STORE_GLOBAL_ALL) me_stores = {true};
+    for (bool g : me_stores) {
       for (int tp : topos) {
         MeLayout cand = me_layout(c, fixed, g, tp, s->n_p, s->n_g, s->fill);
         if (cand.total <= pl.lds_limit) {
           Ly = cand;
-          pl.store_global = g;
+          pl.store = g ? STORE_ALL_GLOBAL : STORE_LDS;
           pl.topo = tp;
           found = true;
           break;
@@ -667,14 +675,14 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     pl.which = 2;
     pl.block = T.block ? T.block : (c->N <= 256 ? 64 : (c->N <= 2048 ? 256 : 1024));
     const int lds_per_cu = 160 * 1024;
-    if (pl.store_global || T.frames_per_cu) {
+    if (pl.store != STORE_LDS || T.frames_per_cu) {
       const int fit = std::max(1, lds_per_cu / std::max(Q.lds_bytes, 1));
       const int per_cu = T.frames_per_cu ? std::min(T.frames_per_cu, fit) : fit;
       pl.grid = (int)std::min<long long>(B, (long long)ncu * per_cu);
     } else {
       pl.grid = B;
     }
-    if (pl.store_global) pl.scratch_bytes = (size_t)std::max(pl.grid, 1) * 2 * c->E * (fixed ? 1 : 4);
+    if (pl.store != STORE_LDS) pl.scratch_bytes = (size_t)std::max(pl.grid, 1) * 2 * c->E * (fixed ? 1 : 4);
     return LDPC_OK;
   }
 
@@ -701,24 +709,37 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     float g = s->gamma;
     std::memcpy(&P.gamma_bits, &g, 4);
   }
-  // storage plan: pre[] in LDS if possible; topology as quasi-cyclic tables, LDS copies or global
-  // arrays, in that order of preference
+  // storage plan.  Every (message storage, topology source) pair that fits is scored by the frames
+  // per CU it lets the batch keep resident (at most 32, the wave slots of a CU).  More resident
+  // frames win: one update is a chain of dependent steps, so throughput comes from overlapping
+  // frames, and moving messages to global memory adds little latency (both values of an edge come
+  // in the load round trips the update makes anyway).  Ties: for a batch that fits in one round
+  // on the chip, the most state in LDS (lowest latency); otherwise all messages in global memory.
+  // Topology ties: quasi-cyclic tables, then LDS copies, then global arrays.
   DynLayout Ly{};
   bool found = false;
-  for (bool pg : stores) {
+  int best_eff = 0, best_pref = -1;
+  const long long need = std::max<long long>(1, (B + ncu - 1) / ncu);
+  const int cap_fpc = T.frames_per_cu ? T.frames_per_cu : 32;
+  for (int st : stores) {
     for (int tp : topos) {
-      DynLayout cand = dyn_layout(c, fixed, pg, tp, 0);
-      if (cand.total <= pl.lds_limit) {
+      DynLayout cand = dyn_layout(c, fixed, st, tp, 0);
+      if (cand.total > pl.lds_limit) continue;
+      const int fit = std::max(1, (160 * 1024) / std::max(cand.total, 1));
+      const int eff = (int)std::min<long long>(std::min(fit, cap_fpc), need);
+      const int st_pref = need <= 1 ? 2 - st : st;  // Store values: LDS 0, PRE_GLOBAL 1, ALL_GLOBAL 2
+      const int tp_pref = tp == TOPO_QC ? 2 : (tp == TOPO_LDS ? 1 : 0);
+      const int pref = st_pref * 4 + tp_pref;
+      if (!found || eff > best_eff || (eff == best_eff && pref > best_pref)) {
         Ly = cand;
-        pl.store_global = pg;
+        pl.store = st;
         pl.topo = tp;
+        best_eff = eff;
+        best_pref = pref;
         found = true;
-        break;
       }
     }
-    if (found) break;
-  }
-  if (!found) return LDPC_ECAPACITY;
+  }  if (!found) return LDPC_ECAPACITY;
   P.off_c2v = Ly.off_c2v; P.off_pre = Ly.off_pre; P.off_L = Ly.off_L; P.off_Lt = Ly.off_Lt;
   P.off_D = Ly.off_D; P.off_ckey = Ly.off_ckey; P.off_dblk = Ly.off_dblk; P.off_cblk = Ly.off_cblk;
   P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
@@ -733,14 +754,20 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
 #endif
   pl.which = 1;
   pl.block = WAVE;
-  if (pl.store_global || T.frames_per_cu) {
+  // persistent grid (workers pull frames from a queue) unless one workgroup per frame fills the
+  // chip in a single round and the messages stay in LDS
+  pl.persistent = pl.store != STORE_LDS || T.frames_per_cu || need > 1;
+  if (pl.persistent) {
     const int fit = std::max(1, (160 * 1024) / std::max(P.lds_bytes, 1));
-    const int per_cu = T.frames_per_cu ? std::min(T.frames_per_cu, fit) : fit;
+    const int per_cu = std::min(fit, cap_fpc);
     pl.grid = (int)std::min<long long>(B, (long long)ncu * per_cu);
   } else {
     pl.grid = B;
   }
-  if (pl.store_global) pl.scratch_bytes = (size_t)std::max(pl.grid, 1) * c->E * (fixed ? 1 : 4);
+  const size_t msg = fixed ? 1 : 4;
+  if (pl.persistent) pl.scratch_bytes = kQueueBytes;  // work-queue counter, then message slots
+  if (pl.store == STORE_PRE_GLOBAL) pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * c->E * msg;
+  if (pl.store == STORE_ALL_GLOBAL) pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * 2 * c->E * msg;
   return LDPC_OK;
 }
 
@@ -761,11 +788,17 @@ hipError_t enqueue_decode(const ldpc_code* c, DecodePlan& pl, void* scratch, hip
   }
   if (pl.which == 0) return launch_baseline(c->dev, pl.base, pl.fixed, pl.grid, pl.block, st);
   if (pl.which == 2) {
-    pl.me.msg_global = pl.store_global ? scratch : nullptr;
-    return launch_me(c->dev, pl.me, pl.fixed, pl.store_global, pl.topo, pl.grid, pl.block, st);
+    const bool mg = pl.store != STORE_LDS;
+    pl.me.msg_global = mg ? scratch : nullptr;
+    return launch_me(c->dev, pl.me, pl.fixed, mg, pl.topo, pl.grid, pl.block, st);
   }
-  pl.dyn.pre_global = pl.store_global ? scratch : nullptr;
-  return launch_dynamic(c->dev, pl.dyn, pl.fixed, pl.store_global, pl.topo, pl.grid, st);
+  pl.dyn.queue = pl.persistent ? reinterpret_cast<int*>(scratch) : nullptr;
+  pl.dyn.pre_global = pl.store != STORE_LDS ? (char*)scratch + kQueueBytes : nullptr;
+  if (pl.persistent) {
+    hipError_t he = launch_fill_u64(reinterpret_cast<int64_t*>(scratch), 1, 0, st);  // queue = 0
+    if (he != hipSuccess) return he;
+  }
+  return launch_dynamic(c->dev, pl.dyn, pl.fixed, pl.store, pl.topo, pl.grid, st);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -847,7 +880,7 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
     if (!c->h_qc.empty()) tps.push_back(LDPC_TOPO_QC);
     const std::vector<int> blocks = s->kind == LDPC_ME_CIRBP ? std::vector<int>{64, 256, 1024} : std::vector<int>{0};
     for (int b : blocks)
-      for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL})
+      for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL})
         for (int tp : tps)
           for (int fpc : {0, 1, 2, 4, 8, 16})
             cands.push_back(ldpc_tuning{b, fpc, store, tp});
@@ -875,7 +908,7 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
       DecodePlan q;
       if (plan_decode(c, s, llr_in, B, max_updates, nullptr, 0, &out, &cands[j], q) != LDPC_OK) continue;
       dup = q.which == pl.which && q.grid == pl.grid && q.block == pl.block && q.topo == pl.topo &&
-            q.store_global == pl.store_global;
+            q.store == pl.store && q.persistent == pl.persistent;
     }
     if (dup) continue;
     void* scratch = nullptr;
@@ -1002,13 +1035,21 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   for (int i = 0; i < n_codes; ++i) mx.topo_bytes = std::max(mx.topo_bytes, topo_bytes(codes[i], topo));
   const int lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
   const int ncu = device_cu_count(dev);
-  bool pre_global = false;
-  DynLayout Ly = dyn_layout_dims(mx, fixed, false, 0);
-  if (Ly.total > lds_limit) {
-    pre_global = true;
-    Ly = dyn_layout_dims(mx, fixed, true, 0);
-    if (Ly.total > lds_limit) return LDPC_ECAPACITY;
+  // message storage: the mode that keeps the most frames resident per CU (at most 32); ties go to
+  // all messages in global memory (the batch is a large persistent launch)
+  int store = -1, best_fit = 0;
+  DynLayout Ly{};
+  for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL}) {
+    DynLayout cand = dyn_layout_dims(mx, fixed, st, 0);
+    if (cand.total > lds_limit) continue;
+    const int fit = std::min(32, (160 * 1024) / std::max(cand.total, 1));
+    if (store < 0 || fit >= best_fit) {
+      store = st;
+      best_fit = fit;
+      Ly = cand;
+    }
   }
+  if (store < 0) return LDPC_ECAPACITY;
   hipStream_t st = (hipStream_t)stream;
   BatchParams B{};
   DynParams& P = B.P;
@@ -1036,15 +1077,15 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(Ly.total, 1)));
   const int grid = (int)std::min<long long>(F, (long long)ncu * per_cu);
   // scratch: the work-queue counter and pre[] slots if needed
-  const size_t pre_bytes = pre_global ? (size_t)grid * mx.E * (fixed ? 1 : 4) : 0;
+  const size_t pre_bytes = (size_t)grid * mx.E * (fixed ? 1 : 4) * (store == STORE_LDS ? 0 : store == STORE_PRE_GLOBAL ? 1 : 2);
   void* scratch = nullptr;
   hipError_t he = hipMallocAsync(&scratch, 256 + pre_bytes, st);
   if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
   for (int i = 0; i < n_codes; ++i) B.codes[i] = codes[i]->d_self;
   B.queue = reinterpret_cast<int*>(scratch);
-  P.pre_global = pre_global ? (char*)scratch + 256 : nullptr;
+  P.pre_global = store != STORE_LDS ? (char*)scratch + 256 : nullptr;
   he = set_batch_lds_limit(lds_limit);
-  if (he == hipSuccess) he = launch_batch(B, fixed, pre_global, topo, grid, st);
+  if (he == hipSuccess) he = launch_batch(B, fixed, store, topo, grid, st);
   (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
 }

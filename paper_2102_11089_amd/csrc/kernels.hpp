@@ -9,6 +9,8 @@ namespace ldpc {
 
 enum Kind { KIND_FLOODING = 0, KIND_LAYERED = 1, KIND_RBP = 2, KIND_CIRBP = 3, KIND_ME_CIRBP = 4, KIND_REPLAY = 5 };
 enum Topo { TOPO_GLOBAL = 0, TOPO_LDS = 1, TOPO_QC = 2 };
+// single-edge message storage: c2v and pre in LDS; pre in a global slot; both in a global slot
+enum Store { STORE_LDS = 0, STORE_PRE_GLOBAL = 1, STORE_ALL_GLOBAL = 2 };
 
 struct DecOut {
   uint8_t* bits;            // [B][N]
@@ -36,7 +38,9 @@ struct DynParams {
   int qmax;
   float scale;
   const int* lut_global;    // 257 entries (fixed point)
-  void* pre_global;         // grid x E messages when pre[] is not in LDS
+  void* pre_global;         // per-workgroup message slots when messages are not in LDS
+  int* queue;               // persistent launch: next-frame counter (zeroed before launch); null:
+                            // workgroup b decodes frames b, b + grid, ...
   // ME-CIRBP
   int n_p, n_g, fill;
   unsigned long long seed;
@@ -131,7 +135,7 @@ struct TopoSel<TOPO_QC> {
   }
 };
 
-hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, bool pre_global, int topo, int grid,
+hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, int store, int topo, int grid,
                           hipStream_t st);
 hipError_t set_dynamic_lds_limit(int bytes);
 hipError_t launch_baseline(const DevCode& H, const BaseParams& P, bool fixed, int grid, int block,
@@ -207,7 +211,7 @@ hipError_t launch_count_errors(const uint8_t* bits, const uint8_t* cw, int P, in
                                int64_t* counters, hipStream_t st);
 hipError_t launch_fill_u64(int64_t* p, int n, uint64_t v, hipStream_t st);
 
-hipError_t launch_batch(const BatchParams& B, bool fixed, bool pre_global, int topo, int grid, hipStream_t st);
+hipError_t launch_batch(const BatchParams& B, bool fixed, int store, int topo, int grid, hipStream_t st);
 hipError_t set_batch_lds_limit(int bytes);
 
 hipError_t launch_me(const DevCode& H, const MeParams& P, bool fixed, bool msg_global, int topo, int grid,

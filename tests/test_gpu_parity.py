@@ -234,7 +234,7 @@ def test_edge_cases(gpu, c0):
 # ------------------------------------------------------------------------------------------
 # storage variants: every (pre location, topology source) combination is bit-exact
 # ------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("pre", ["lds", "global"])
+@pytest.mark.parametrize("pre", ["lds", "global", "all"])
 @pytest.mark.parametrize("topo", ["global", "lds", "qc"])
 @pytest.mark.parametrize("fpc", [0, 3])
 def test_fixed_storage_variants(gpu, pre, topo, fpc):
@@ -243,7 +243,7 @@ def test_fixed_storage_variants(gpu, pre, topo, fpc):
     cw, llr = S.frames(code, 200, 2.0, 109)
     ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True, dump=True,
                    threads=8)
-    store = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL}[pre]
+    store = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL}[pre]
     tp = {"global": gpu.TOPO_GLOBAL, "lds": gpu.TOPO_LDS, "qc": gpu.TOPO_QC}[topo]
     handles = [gpu.Code(code)] if topo == "qc" else [gpu.Code(code), gpu.Code(code, csr=True)]
     for h in handles:
@@ -376,3 +376,23 @@ def test_batch_rejects_bad_descriptors(gpu):
     u = np_(upd)
     assert list(u[1:5]) == [-1, -1, -1, -1]
     assert u[0] >= 0 and u[5] >= 0
+
+
+@pytest.mark.parametrize("store", ["lds", "global", "all"])
+def test_f32_storage_modes_identical(gpu, store):
+    """FP32 results do not depend on where the messages live (same arithmetic, same order)."""
+    code = S.workload_code("c4")
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 300, 2.0, 111)
+    t = torch.from_numpy(llr).cuda()
+    gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, clear=True)
+    base = gpu.decode(h, t, gpu.CIRBP, gpu.SPA_F32, max_updates=4000, trace=True)
+    st = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL}[store]
+    gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, storage=st, frames_per_cu=2)
+    try:
+        r = gpu.decode(h, t, gpu.CIRBP, gpu.SPA_F32, max_updates=4000, trace=True)
+        torch.cuda.synchronize()
+    finally:
+        gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, clear=True)
+    for a, b in ((base.trace, r.trace), (base.llr_out, r.llr_out), (base.updates_used, r.updates_used)):
+        np.testing.assert_array_equal(np_(a), np_(b))
