@@ -55,6 +55,33 @@ def lds_bytes_per_update_table(code, s_c=4, s_v=4, s_d=4):
     return 2 * s_c * dv[n] + 2 * s_c + 3 * s_v + s_d + per_vn[n] - per_check[rows]
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dynamic_cirbp_bg1shaped_z52_f32_traffic.json")
+
+
+def kernel_sources_digest():
+    """sha256 over the HIP/C++ sources of the library (name + content, sorted by name)."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2102_11089_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic_bytes():
+    """HBM bytes per timed launch (FETCH_SIZE + WRITE_SIZE counters scaled by a plain copy of known
+    size), if they were taken on the current kernel sources; else None."""
+    try:
+        doc = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if doc.get("kernel_sources_sha256") != kernel_sources_digest():
+        return None
+    return float(doc["traffic_bytes_per_launch"])
+
+
 def make_batches(code, nb, B, ebn0, seed, device):
     """nb batches of B frames: random codewords (GF(2) encoding on the GPU) and AWGN LLRs."""
     import torch
@@ -430,6 +457,9 @@ def main():
     bytes_per_update = bytes_traced / max(int(used.sum()), 1)
     kern_s = sum(kms) / 1e3
     achieved_gbs = bytes_per_update * upd / kern_s / 1e9 if kern_s > 0 else 0.0
+    # HBM traffic of the timed launch from the counters taken on this workload (default size only)
+    tb = measured_traffic_bytes() if (args.frames == 8192 and args.ebn0 == 1.25) else None
+    traffic_gbs = round(tb / (float(np.mean(kms)) / 1e3) / 1e9, 2) if tb else None
     del rt, tr, mask
 
     out = {
@@ -455,7 +485,7 @@ def main():
                "edge_updates_per_s": round(upd / wall, 1), "mean_updates_per_frame": upd / nf,
                "fallback_fraction": fall / max(upd, 1), "kernel_ms_per_step": [round(x, 3) for x in kms]},
         "roofline": {"bound": "lds", "achieved": round(achieved_gbs, 2), "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved_gbs / LDS_PEAK_GBS, 6), "traffic": None,
+                     "frac": round(achieved_gbs / LDS_PEAK_GBS, 6), "traffic": traffic_gbs,
                      "kernel": "k_dynamic<ArithF32, STORE_ALL_GLOBAL, TOPO_QC> (2 frames per CU, work queue)",
                      "bytes_per_update": round(bytes_per_update, 2),
                      "kernel_ms_avg": round(float(np.mean(kms)), 3)},
