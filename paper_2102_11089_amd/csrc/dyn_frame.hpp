@@ -223,12 +223,38 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     const int npass = (ncnt + WAVE - 1) / WAVE;
     const int rs_m = uni(G.row_start(mstar));
     const int re_m = rs_m + uni(G.row_deg(mstar));
-    int2 ent0 = make_int2(-1, 0);
-    if (lane < ncnt) ent0 = H.nbr[noff + lane];  // first pass of the two-hop table, early
+    // Inputs of the touched-check passes are loaded ahead of use: table entries two passes ahead,
+    // message pairs and L one pass ahead.  Nothing a pass writes (its own checks' pre, Lt, keys)
+    // is read by a later pass, propagation changes only c2v[e*] and L[n*] (both overridden where
+    // used), so the early loads see the values the passes need.
+    auto load_ent = [&](int ps) -> int2 {
+      const int idx = ps * WAVE + lane;
+      return idx < ncnt ? H.nbr[noff + idx] : make_int2(-1, 0);
+    };
+    struct PassIn {
+      int2 ent;
+      msg_t cm, pm;
+      llr_t lj;
+    };
+    auto load_in = [&](int2 ent) -> PassIn {
+      PassIn q;
+      q.ent = ent;
+      q.cm = (msg_t)0;
+      q.pm = (msg_t)0;
+      q.lj = (llr_t)0;
+      if (ent.x >= 0) {
+        ms.cp(ent.x, q.cm, q.pm);
+        q.lj = L[ent.y & 0xFFFFFF];
+      }
+      return q;
+    };
+    const int2 ent0 = load_ent(0);
+    int2 ent_next = npass > 1 ? load_ent(1) : make_int2(-1, 0);
 
     // ---- propagation (Algorithm 1 line 9) and D_{n*} ----
     msg_t c_star, p_star;
     ms.cp(estar, c_star, p_star);
+    PassIn in_cur = load_in(ent0);
     const val_t newv = (val_t)p_star;
     const val_t oldv = (val_t)c_star;
     const val_t Lold = (val_t)L[nstar];
@@ -260,11 +286,11 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
 
     // ---- touched checks: V2C inputs, whole-row update, residual keys (one pass per 64 lanes) ----
     for (int ps = 0; ps < npass; ++ps) {
-      int2 ent = ent0;
-      if (ps > 0) {
-        const int idx = ps * WAVE + lane;
-        ent = idx < ncnt ? H.nbr[noff + idx] : make_int2(-1, 0);
-      }
+      PassIn in_next{make_int2(-1, 0), (msg_t)0, (msg_t)0, (llr_t)0};
+      int2 ent_after = make_int2(-1, 0);
+      if (ps + 1 < npass) in_next = load_in(ent_next);
+      if (ps + 2 < npass) ent_after = load_ent(ps + 2);
+      const int2 ent = in_cur.ent;
       const int e = ent.x;
       const bool valid = e >= 0;
       const int j = ent.y & 0xFFFFFF;
@@ -274,11 +300,9 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       const bool self = valid && j == nstar;
       val_t cv = 0, po = 0, lv = 0;
       if (valid) {
-        msg_t cm, pm;
-        ms.cp(e, cm, pm);
-        cv = e == estar ? newv : (val_t)cm;  // this update's propagation (its store may be in flight)
-        po = (val_t)pm;
-        lv = self ? Lnew : (val_t)L[j];
+        cv = e == estar ? newv : (val_t)in_cur.cm;  // this update's propagation
+        po = (val_t)in_cur.pm;
+        lv = self ? Lnew : (val_t)in_cur.lj;
       }
       const val_t v = ar.vin(ar.v2c(lv, cv));
       const int maxL2 = uni(L2);  // lane 0 starts the pass's largest block
@@ -319,6 +343,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         if (rk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&cblk[m >> 6]), (unsigned long long)rk);
         else if (rk < ok && cblk[m >> 6] == ok) atomicOr(&cmask[(m >> 6) >> 5], 1u << ((m >> 6) & 31));
       }
+      in_cur = in_next;
+      ent_next = ent_after;
     }
     if constexpr (STORE != STORE_LDS) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // message stores done
     wave_sync();
