@@ -22,7 +22,7 @@ __global__ void k_zero_int(int* p) {
 // lanes of the wave exchange values through the frame's message store (LDS, or global memory)
 template <int STORE>
 __device__ __forceinline__ void store_sync() {
-  if constexpr (STORE == STORE_ALL_GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  if constexpr (STORE >= STORE_ALL_GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   wave_sync();
 }
 
@@ -30,7 +30,7 @@ __device__ __forceinline__ void store_sync() {
 // the frame's message store
 template <class A, int STORE, class Topo>
 __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
-                                                    const MsgStore<typename A::msg_t, STORE>& ms, const FrameJob& J) {
+                                                    const MsgStore<A, STORE>& ms, const FrameJob& J) {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   using val_t = typename A::val_t;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
   const DynParams& P = B.P;
   unsigned char* lds = dyn_lds();
   const int lane = threadIdx.x;
-  const auto ms = make_store<msg_t, STORE>(P, (size_t)B.max_E);
+  const auto ms = make_store<A, STORE>(P, (size_t)B.max_E);
   int* lut = reinterpret_cast<int*>(lds + P.off_lut);
   A ar;
   ar.qmax = P.qmax;
@@ -202,6 +202,7 @@ static hipError_t launch_batch_t(const BatchParams& B, int topo, int grid, hipSt
 
 template <class A>
 static hipError_t launch_batch_s(const BatchParams& B, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_ALL_GLOBAL_LT) return launch_batch_t<A, STORE_ALL_GLOBAL_LT>(B, topo, grid, st);
   if (store == STORE_ALL_GLOBAL) return launch_batch_t<A, STORE_ALL_GLOBAL>(B, topo, grid, st);
   if (store == STORE_PRE_GLOBAL) return launch_batch_t<A, STORE_PRE_GLOBAL>(B, topo, grid, st);
   return launch_batch_t<A, STORE_LDS>(B, topo, grid, st);
@@ -226,9 +227,11 @@ static hipError_t set_batch_store(int bytes) {
 hipError_t set_batch_lds_limit(int bytes) {
   hipError_t e = hipSuccess;
   for (hipError_t r : {set_batch_store<ArithF32, STORE_LDS>(bytes), set_batch_store<ArithF32, STORE_PRE_GLOBAL>(bytes),
-                       set_batch_store<ArithF32, STORE_ALL_GLOBAL>(bytes), set_batch_store<ArithFix, STORE_LDS>(bytes),
+                       set_batch_store<ArithF32, STORE_ALL_GLOBAL>(bytes),
+                       set_batch_store<ArithF32, STORE_ALL_GLOBAL_LT>(bytes), set_batch_store<ArithFix, STORE_LDS>(bytes),
                        set_batch_store<ArithFix, STORE_PRE_GLOBAL>(bytes),
-                       set_batch_store<ArithFix, STORE_ALL_GLOBAL>(bytes)})
+                       set_batch_store<ArithFix, STORE_ALL_GLOBAL>(bytes),
+                       set_batch_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes)})
     if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }

@@ -22,14 +22,17 @@ __device__ __forceinline__ unsigned char* dyn_lds() {
   return lds_dyn;
 }
 
-// Where a frame's C2V messages (c2v) and precomputed messages (pre) live: both in LDS, pre in a
-// global scratch slot, or both in a global slot as interleaved (c2v, pre) pairs so that one load
-// brings the two values of an edge.
-template <class msg_t, int STORE>
+// Where a frame's C2V messages (c2v), precomputed messages (pre) and precomputed totals (Lt)
+// live: all in LDS; pre in a global scratch slot; c2v and pre as interleaved (c2v, pre) pairs (one
+// load brings the two values of an edge) in a global slot per workgroup; or those pairs followed
+// by Lt in the slot.
+template <class A, int STORE, bool PAIRS = (STORE >= STORE_ALL_GLOBAL)>
 struct MsgStore {
+  using msg_t = typename A::msg_t;
+  using llr_t = typename A::llr_t;
   msg_t* c2v;  // LDS
   msg_t* pre;  // LDS (STORE_LDS) or global (STORE_PRE_GLOBAL)
-  static constexpr bool kGlobal = STORE != STORE_LDS;
+  llr_t* Lt;   // LDS
   __device__ __forceinline__ msg_t c(int e) const { return c2v[e]; }
   __device__ __forceinline__ msg_t p(int e) const { return pre[e]; }
   __device__ __forceinline__ void set_c(int e, msg_t v) const { c2v[e] = v; }
@@ -38,6 +41,9 @@ struct MsgStore {
     cv = c2v[e];
     pv = pre[e];
   }
+  __device__ __forceinline__ llr_t lt(int n) const { return Lt[n]; }
+  __device__ __forceinline__ void set_lt(int n, llr_t v) const { Lt[n] = v; }
+  __device__ __forceinline__ void add_lt(int n, llr_t d) const { atomicAdd(&Lt[n], d); }
 };
 
 template <class msg_t>
@@ -45,10 +51,12 @@ struct alignas(2 * sizeof(msg_t)) MsgPair {
   msg_t c, p;
 };
 
-template <class msg_t>
-struct MsgStore<msg_t, STORE_ALL_GLOBAL> {
+template <class A, int STORE>
+struct MsgStore<A, STORE, true> {
+  using msg_t = typename A::msg_t;
+  using llr_t = typename A::llr_t;
   MsgPair<msg_t>* m;  // global, [E]
-  static constexpr bool kGlobal = true;
+  llr_t* Lt;          // LDS (STORE_ALL_GLOBAL) or global (STORE_ALL_GLOBAL_LT), [N]
   __device__ __forceinline__ msg_t c(int e) const { return m[e].c; }
   __device__ __forceinline__ msg_t p(int e) const { return m[e].p; }
   __device__ __forceinline__ void set_c(int e, msg_t v) const { m[e].c = v; }
@@ -58,17 +66,27 @@ struct MsgStore<msg_t, STORE_ALL_GLOBAL> {
     cv = x.c;
     pv = x.p;
   }
+  __device__ __forceinline__ llr_t lt(int n) const { return Lt[n]; }
+  __device__ __forceinline__ void set_lt(int n, llr_t v) const { Lt[n] = v; }
+  __device__ __forceinline__ void add_lt(int n, llr_t d) const { atomicAdd(&Lt[n], d); }
 };
 
-// message store of the workgroup's frame slot (slot_edges = edges reserved per workgroup)
-template <class msg_t, int STORE>
-__device__ __forceinline__ MsgStore<msg_t, STORE> make_store(const DynParams& P, size_t slot_edges) {
+// message store of the workgroup's frame slot (slot_edges = edges reserved per workgroup when
+// only pre is global; the pair-slot layout comes from P.slot_bytes / P.slot_lt_off)
+template <class A, int STORE>
+__device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, size_t slot_edges) {
+  using msg_t = typename A::msg_t;
+  using llr_t = typename A::llr_t;
   unsigned char* lds = dyn_lds();
-  MsgStore<msg_t, STORE> ms;
-  if constexpr (STORE == STORE_ALL_GLOBAL) {
-    ms.m = reinterpret_cast<MsgPair<msg_t>*>(P.pre_global) + (size_t)blockIdx.x * slot_edges;
+  MsgStore<A, STORE> ms;
+  if constexpr (STORE >= STORE_ALL_GLOBAL) {
+    unsigned char* base = reinterpret_cast<unsigned char*>(P.pre_global) + (size_t)blockIdx.x * (size_t)P.slot_bytes;
+    ms.m = reinterpret_cast<MsgPair<msg_t>*>(base);
+    if constexpr (STORE == STORE_ALL_GLOBAL_LT) ms.Lt = reinterpret_cast<llr_t*>(base + P.slot_lt_off);
+    else ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
   } else {
     ms.c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
+    ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
     if constexpr (STORE == STORE_PRE_GLOBAL) ms.pre = reinterpret_cast<msg_t*>(P.pre_global) + (size_t)blockIdx.x * slot_edges;
     else ms.pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
   }
@@ -77,7 +95,7 @@ __device__ __forceinline__ MsgStore<msg_t, STORE> make_store(const DynParams& P,
 
 template <class A, int STORE, class Topo>
 __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
-                                                 const MsgStore<typename A::msg_t, STORE>& ms, const FrameJob& J) {
+                                                 const MsgStore<A, STORE>& ms, const FrameJob& J) {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   using val_t = typename A::val_t;
@@ -85,7 +103,6 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   const int lane = threadIdx.x & (WAVE - 1);
   unsigned char* lds = dyn_lds();
   llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
-  llr_t* Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
   uint32_t* D = reinterpret_cast<uint32_t*>(lds + P.off_D);
   uint64_t* ckey = reinterpret_cast<uint64_t*>(lds + P.off_ckey);
   uint64_t* dblk = reinterpret_cast<uint64_t*>(lds + P.off_dblk);
@@ -139,7 +156,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       G.vn_edge(n, k, m, e);
       lt += (val_t)ms.p(e);
     }
-    Lt[n] = (llr_t)lt;
+    ms.set_lt(n, (llr_t)lt);
     D[n] = with_ci ? ar.ci((val_t)L[n], lt) : 0u;
   }
   wave_sync();
@@ -260,7 +277,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     const val_t Lold = (val_t)L[nstar];
     const val_t Lnew = Lold + (newv - oldv);
     const uint32_t dn_old = D[nstar];
-    const uint32_t dn_new = with_ci ? ar.ci(Lnew, (val_t)Lt[nstar]) : 0u;
+    const uint32_t dn_new = with_ci ? ar.ci(Lnew, (val_t)ms.lt(nstar)) : 0u;
     wave_sync();
     if (lane == 0) {
       ms.set_c(estar, (msg_t)newv);
@@ -332,7 +349,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       }
       if (upd) {
         ms.set_p(e, (msg_t)pv);
-        if (with_ci) atomicAdd(&Lt[j], (llr_t)(pv - po));
+        if (with_ci) ms.add_lt(j, (llr_t)(pv - po));
       }
       tj[ps * WAVE + lane] = upd ? j : -1;
       const uint64_t rk = keymax_all(valid ? mkkey(ar.res(pv, cv), (uint32_t)e) : 0ull, L2, maxL2);
@@ -355,7 +372,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         const int j = tj[ps * WAVE + lane];
         uint32_t nd = 0, od = 0;
         if (j >= 0) {
-          nd = ar.ci((val_t)L[j], (val_t)Lt[j]);
+          nd = ar.ci((val_t)L[j], (val_t)ms.lt(j));
           od = D[j];
         }
         wave_sync();
@@ -416,7 +433,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     J.bits[n] = l < 0 ? 1 : 0;
     if (J.llr_out) J.llr_out[n] = ar.out_llr(l);
     if (J.dump_L) J.dump_L[n] = ar.as_float(l);
-    if (J.dump_Lt) J.dump_Lt[n] = ar.as_float((val_t)Lt[n]);
+    if (J.dump_Lt) J.dump_Lt[n] = ar.as_float((val_t)ms.lt(n));
     if (J.dump_D) J.dump_D[n] = ar.d_float(D[n]);
   }
   for (int e = lane; e < E; e += WAVE) {

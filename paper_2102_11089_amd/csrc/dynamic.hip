@@ -32,7 +32,7 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
   using msg_t = typename A::msg_t;
   unsigned char* lds = dyn_lds();
   const int lane = threadIdx.x;
-  const auto ms = make_store<msg_t, STORE>(P, (size_t)H.E);
+  const auto ms = make_store<A, STORE>(P, (size_t)H.E);
   int* lut = reinterpret_cast<int*>(lds + P.off_lut);
   A ar;
   ar.qmax = P.qmax;
@@ -86,6 +86,7 @@ static hipError_t launch_dyn_t(const DevCode& H, const DynParams& P, int topo, i
 
 template <class A>
 static hipError_t launch_dyn_s(const DevCode& H, const DynParams& P, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_ALL_GLOBAL_LT) return launch_dyn_t<A, STORE_ALL_GLOBAL_LT>(H, P, topo, grid, st);
   if (store == STORE_ALL_GLOBAL) return launch_dyn_t<A, STORE_ALL_GLOBAL>(H, P, topo, grid, st);
   if (store == STORE_PRE_GLOBAL) return launch_dyn_t<A, STORE_PRE_GLOBAL>(H, P, topo, grid, st);
   return launch_dyn_t<A, STORE_LDS>(H, P, topo, grid, st);
@@ -112,8 +113,9 @@ static hipError_t set_store(int bytes) {
 hipError_t set_dynamic_lds_limit(int bytes) {
   hipError_t e = hipSuccess;
   for (hipError_t r : {set_store<ArithF32, STORE_LDS>(bytes), set_store<ArithF32, STORE_PRE_GLOBAL>(bytes),
-                       set_store<ArithF32, STORE_ALL_GLOBAL>(bytes), set_store<ArithFix, STORE_LDS>(bytes),
-                       set_store<ArithFix, STORE_PRE_GLOBAL>(bytes), set_store<ArithFix, STORE_ALL_GLOBAL>(bytes)})
+                       set_store<ArithF32, STORE_ALL_GLOBAL>(bytes), set_store<ArithF32, STORE_ALL_GLOBAL_LT>(bytes),
+                       set_store<ArithFix, STORE_LDS>(bytes), set_store<ArithFix, STORE_PRE_GLOBAL>(bytes),
+                       set_store<ArithFix, STORE_ALL_GLOBAL>(bytes), set_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes)})
     if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }

@@ -111,7 +111,8 @@ struct Dims {
   long long topo_bytes;
 };
 
-// store: STORE_LDS (c2v and pre in LDS), STORE_PRE_GLOBAL (c2v only), STORE_ALL_GLOBAL (neither)
+// store: STORE_LDS (c2v, pre, Lt in LDS), STORE_PRE_GLOBAL (c2v, Lt), STORE_ALL_GLOBAL (Lt),
+// STORE_ALL_GLOBAL_LT (none of them)
 DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int extra_bytes) {
   DynLayout L{};
   const int msg = fixed ? 1 : 4, llr = 4, val = 4;
@@ -120,10 +121,10 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int extra_bytes)
   L.nbd_words = (L.nbd + 31) / 32;
   L.nbc_words = (L.nbc + 31) / 32;
   int o = 0;
-  L.off_c2v = o; if (store != STORE_ALL_GLOBAL) o = align16(o + c.E * msg);
+  L.off_c2v = o; if (store < STORE_ALL_GLOBAL) o = align16(o + c.E * msg);
   L.off_pre = o; if (store == STORE_LDS) o = align16(o + c.E * msg);
   L.off_L = o; o = align16(o + c.N * llr);
-  L.off_Lt = o; o = align16(o + c.N * llr);
+  L.off_Lt = o; if (store != STORE_ALL_GLOBAL_LT) o = align16(o + c.N * llr);
   L.off_D = o; o = align16(o + c.N * 4);
   L.off_ckey = o; o = align16(o + c.M * 8);
   L.off_dblk = o; o = align16(o + L.nbd * 8);
@@ -533,6 +534,14 @@ bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
 
 constexpr size_t kQueueBytes = 256;  // work-queue counter at the front of a persistent launch's scratch
 
+// global slot of one frame when all its messages live in global memory: (c2v, pre) pairs for E
+// edges, then Lt for N VNs, 256-byte aligned
+void all_global_slot(int E, int N, bool fixed, long long& slot_bytes, int& lt_off) {
+  const long long pairs = 2LL * E * (fixed ? 1 : 4);
+  lt_off = (int)((pairs + 255) / 256 * 256);
+  slot_bytes = (lt_off + 4LL * N + 255) / 256 * 256;
+}
+
 // tuning knob -> candidate topologies (empty: the knob does not apply to this code)
 std::vector<int> topo_choices(const ldpc_code* c, int knob) {
   switch (knob) {
@@ -548,7 +557,7 @@ int check_tuning(const ldpc_tuning* t) {
   if (!t) return LDPC_OK;
   if (t->block != 0 && !valid_block(t->block)) return LDPC_EINVAL;
   if (t->frames_per_cu < 0 || t->frames_per_cu > 32) return LDPC_EINVAL;
-  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_ALL) return LDPC_EINVAL;
+  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_LT) return LDPC_EINVAL;
   if (t->topology < LDPC_TOPO_AUTO || t->topology > LDPC_TOPO_QC) return LDPC_EINVAL;
   return LDPC_OK;
 }
@@ -627,10 +636,11 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (c->nbr_max_cnt > NBR_PMAX * WAVE) return LDPC_EUNSUPPORTED;
   const std::vector<int> topos = topo_choices(c, T.topology);
   if (topos.empty()) return LDPC_EUNSUPPORTED;
-  std::vector<int> stores = {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL};
+  std::vector<int> stores = {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL, STORE_ALL_GLOBAL_LT};
   if (T.storage == LDPC_STORE_LDS) stores = {STORE_LDS};
   if (T.storage == LDPC_STORE_GLOBAL) stores = {STORE_PRE_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_ALL) stores = {STORE_ALL_GLOBAL};
+  if (T.storage == LDPC_STORE_GLOBAL_LT) stores = {STORE_ALL_GLOBAL_LT};
   const int lut_off = 257 * (fixed ? s->frac_bits : 0);
 
   if (s->kind == LDPC_ME_CIRBP) {
@@ -651,7 +661,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     MeLayout Ly{};
     std::vector<bool> me_stores = {false, true};
     if (T.storage == LDPC_STORE_LDS) me_stores = {false};
-    if (T.storage == LDPC_STORE_GLOBAL || T.storage == LDPC_STORE_GLOBAL_ALL) me_stores = {true};
+    if (T.storage >= LDPC_STORE_GLOBAL) me_stores = {true};
     for (bool g : me_stores) {
       for (int tp : topos) {
         MeLayout cand = me_layout(c, fixed, g, tp, s->n_p, s->n_g, s->fill);
@@ -727,7 +737,10 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
       if (cand.total > pl.lds_limit) continue;
       const int fit = std::max(1, (160 * 1024) / std::max(cand.total, 1));
       const int eff = (int)std::min<long long>(std::min(fit, cap_fpc), need);
-      const int st_pref = need <= 1 ? 2 - st : st;  // Store values: LDS 0, PRE_GLOBAL 1, ALL_GLOBAL 2
+      // Store preference: one round on the chip: LDS > PRE_GLOBAL > ALL_GLOBAL > ALL_GLOBAL_LT;
+      // larger batches: ALL_GLOBAL > ALL_GLOBAL_LT > PRE_GLOBAL > LDS
+      static const int rank_small[4] = {3, 2, 1, 0}, rank_large[4] = {0, 1, 3, 2};
+      const int st_pref = need <= 1 ? rank_small[st] : rank_large[st];
       const int tp_pref = tp == TOPO_QC ? 2 : (tp == TOPO_LDS ? 1 : 0);
       const int pref = st_pref * 4 + tp_pref;
       if (!found || eff > best_eff || (eff == best_eff && pref > best_pref)) {
@@ -767,7 +780,10 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   const size_t msg = fixed ? 1 : 4;
   if (pl.persistent) pl.scratch_bytes = kQueueBytes;  // work-queue counter, then message slots
   if (pl.store == STORE_PRE_GLOBAL) pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * c->E * msg;
-  if (pl.store == STORE_ALL_GLOBAL) pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * 2 * c->E * msg;
+  if (pl.store >= STORE_ALL_GLOBAL) {
+    all_global_slot(c->E, c->N, fixed, P.slot_bytes, P.slot_lt_off);
+    pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * (size_t)P.slot_bytes;
+  }
   return LDPC_OK;
 }
 
@@ -880,7 +896,7 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
     if (!c->h_qc.empty()) tps.push_back(LDPC_TOPO_QC);
     const std::vector<int> blocks = s->kind == LDPC_ME_CIRBP ? std::vector<int>{64, 256, 1024} : std::vector<int>{0};
     for (int b : blocks)
-      for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL})
+      for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL, LDPC_STORE_GLOBAL_LT})
         for (int tp : tps)
           for (int fpc : {0, 1, 2, 4, 8, 16})
             cands.push_back(ldpc_tuning{b, fpc, store, tp});
@@ -1039,7 +1055,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   // all messages in global memory (the batch is a large persistent launch)
   int store = -1, best_fit = 0;
   DynLayout Ly{};
-  for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL}) {
+  for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL_LT, STORE_ALL_GLOBAL}) {
     DynLayout cand = dyn_layout_dims(mx, fixed, st, 0);
     if (cand.total > lds_limit) continue;
     const int fit = std::min(32, (160 * 1024) / std::max(cand.total, 1));
@@ -1077,7 +1093,12 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(Ly.total, 1)));
   const int grid = (int)std::min<long long>(F, (long long)ncu * per_cu);
   // scratch: the work-queue counter and pre[] slots if needed
-  const size_t pre_bytes = (size_t)grid * mx.E * (fixed ? 1 : 4) * (store == STORE_LDS ? 0 : store == STORE_PRE_GLOBAL ? 1 : 2);
+  size_t pre_bytes = 0;
+  if (store == STORE_PRE_GLOBAL) pre_bytes = (size_t)grid * mx.E * (fixed ? 1 : 4);
+  if (store >= STORE_ALL_GLOBAL) {
+    all_global_slot(mx.E, mx.N, fixed, P.slot_bytes, P.slot_lt_off);
+    pre_bytes = (size_t)grid * (size_t)P.slot_bytes;
+  }
   void* scratch = nullptr;
   hipError_t he = hipMallocAsync(&scratch, 256 + pre_bytes, st);
   if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
