@@ -93,6 +93,13 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
   return ms;
 }
 
+// value of another lane (the lane index is wave-uniform)
+template <class T>
+__device__ __forceinline__ T lane_value(T x, int l) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+  else return (T)__builtin_amdgcn_readlane((int)x, l);
+}
+
 template <class A, int STORE, class Topo>
 __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
                                                  const MsgStore<A, STORE>& ms, const FrameJob& J) {
@@ -104,12 +111,16 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   unsigned char* lds = dyn_lds();
   llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
   uint32_t* D = reinterpret_cast<uint32_t*>(lds + P.off_D);
-  uint64_t* ckey = reinterpret_cast<uint64_t*>(lds + P.off_ckey);
+  // per check: the largest residual of its edges (value bits); block keys pair it with the check
+  // index, and the edge is found again inside the check's row when the check is selected (edge ids
+  // are row-major, so (value, lowest check), then (value, lowest edge) in the row is the global
+  // (value, lowest edge))
+  uint32_t* ckey = reinterpret_cast<uint32_t*>(lds + P.off_ckey);
   uint64_t* dblk = reinterpret_cast<uint64_t*>(lds + P.off_dblk);
   uint64_t* cblk = reinterpret_cast<uint64_t*>(lds + P.off_cblk);
   uint32_t* dmask = reinterpret_cast<uint32_t*>(lds + P.off_dmask);
   uint32_t* cmask = reinterpret_cast<uint32_t*>(lds + P.off_cmask);
-  uint8_t* syn = reinterpret_cast<uint8_t*>(lds + P.off_syn);
+  uint32_t* synw = reinterpret_cast<uint32_t*>(lds + P.off_syn);  // syndrome bits
   int* tj = reinterpret_cast<int*>(lds + P.off_v);  // touched VN of each table lane, per pass
   const int N = H.N, M = H.M, E = H.E;
   const int nbd = (N + WAVE - 1) / WAVE, nbc = (M + WAVE - 1) / WAVE;
@@ -121,6 +132,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   for (int e = lane; e < E; e += WAVE) ms.set_c(e, (msg_t)0);
   for (int w = lane; w < nbd_words; w += WAVE) dmask[w] = 0u;
   for (int w = lane; w < nbc_words; w += WAVE) cmask[w] = 0u;
+  for (int w = lane; w < (M + 31) / 32; w += WAVE) synw[w] = 0u;
   wave_sync();
   // every precomputed C2V message from V2C = channel value: one lane per check row
   int unsat_local = 0;
@@ -141,8 +153,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       ms.set_p(rs + p, (msg_t)o);
       k = umax64(k, mkkey(ar.res(o, (val_t)0), (uint32_t)(rs + p)));
     }
-    ckey[m] = k;
-    syn[m] = (uint8_t)par;
+    ckey[m] = key_val(k);
+    if (par) atomicOr(&synw[m >> 5], 1u << (m & 31));
     unsat_local += par;
   }
   int unsat = wave_sum_i32(unsat_local);
@@ -168,7 +180,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   }
   for (int b = 0; b < nbc; ++b) {
     const int m = b * WAVE + lane;
-    uint64_t k = m < M ? ckey[m] : 0ull;
+    uint64_t k = m < M ? mkkey(ckey[m], (uint32_t)m) : 0ull;
     k = wave_max_u64(k);
     if (lane == 0) cblk[b] = k;
   }
@@ -186,6 +198,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     PROF_MARK(7)
     // ---- selection (Algorithm 1 lines 4-8; RBP eq. (5)) ----
     int estar, mstar = -1, nstar = -1;
+    msg_t c_star = (msg_t)0, p_star = (msg_t)0;  // messages of e*, taken from the selection's loads
+    bool have_star = false;
     if (J.kind == KIND_REPLAY) {
       estar = uni(J.replay[t]);
       if (estar < 0 || estar >= E) break;  // invalid edge id ends the frame's replay
@@ -205,23 +219,40 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       if (global_res) {
         uint64_t k = 0;
         for (int b = lane; b < nbc; b += WAVE) k = umax64(k, cblk[b]);
-        estar = (int)key_idx(wave_max_u64(k));
+        const int mrow = (int)key_idx(wave_max_u64(k));
+        const int rs = uni(G.row_start(mrow)), dc = uni(G.row_deg(mrow));
+        uint64_t ke = 0;
+        msg_t cm = (msg_t)0, pm = (msg_t)0;
+        if (lane < dc) {  // the largest residual of the check's row, lowest edge on ties
+          ms.cp(rs + lane, cm, pm);
+          ke = mkkey(ar.res((val_t)pm, (val_t)cm), (uint32_t)(rs + lane));
+        }
+        estar = (int)key_idx(wave_max_u64(ke));
+        mstar = mrow;
+        nstar = uni(G.row_vn(mrow, rs, estar - rs));
+        c_star = lane_value(cm, estar - rs);
+        p_star = lane_value(pm, estar - rs);
+        have_star = true;
       } else {
         const int dvs = uni(G.vn_deg(nsel));
         uint64_t k = 0;
         int mk = -1;
+        msg_t cm = (msg_t)0, pm = (msg_t)0;
         if (lane < dvs) {
           int e;
           G.vn_edge(nsel, lane, mk, e);
-          msg_t cm, pm;
           ms.cp(e, cm, pm);
           k = mkkey(ar.res((val_t)pm, (val_t)cm), (uint32_t)e);
         }
         const uint64_t kmax = wave_max_u64(k);
         estar = (int)key_idx(kmax);
         const unsigned long long win = __ballot(lane < dvs && k == kmax);
-        mstar = __builtin_amdgcn_readlane(mk, (int)__builtin_ctzll(win));
+        const int wl = (int)__builtin_ctzll(win);
+        mstar = __builtin_amdgcn_readlane(mk, wl);
         nstar = nsel;
+        c_star = lane_value(cm, wl);
+        p_star = lane_value(pm, wl);
+        have_star = true;
       }
     }
     if (mstar < 0) {
@@ -269,8 +300,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     int2 ent_next = npass > 1 ? load_ent(1) : make_int2(-1, 0);
 
     // ---- propagation (Algorithm 1 line 9) and D_{n*} ----
-    msg_t c_star, p_star;
-    ms.cp(estar, c_star, p_star);
+    if (!have_star) ms.cp(estar, c_star, p_star);
     PassIn in_cur = load_in(ent0);
     const val_t newv = (val_t)p_star;
     const val_t oldv = (val_t)c_star;
@@ -292,9 +322,9 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     if ((Lold < 0) != (Lnew < 0)) {  // hard decision flipped: toggle the checks of n*
       int d = 0;
       if (lane < dv) {
-        const int s = syn[my_m];
-        syn[my_m] = (uint8_t)(s ^ 1);
-        d = s ? -1 : 1;
+        const uint32_t bit = 1u << (my_m & 31);
+        const uint32_t old = atomicXor(&synw[my_m >> 5], bit);
+        d = (old & bit) ? -1 : 1;
       }
       unsat += wave_sum_i32(d);
     }
@@ -355,10 +385,11 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       const uint64_t rk = keymax_all(valid ? mkkey(ar.res(pv, cv), (uint32_t)e) : 0ull, L2, maxL2);
       if (leader) {  // one lane per check: new residual key, block maximum
         const int m = G.edge_row(e);
-        const uint64_t ok = ckey[m];
-        ckey[m] = rk;
-        if (rk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&cblk[m >> 6]), (unsigned long long)rk);
-        else if (rk < ok && cblk[m >> 6] == ok) atomicOr(&cmask[(m >> 6) >> 5], 1u << ((m >> 6) & 31));
+        const uint32_t ov = ckey[m];
+        ckey[m] = key_val(rk);
+        const uint64_t nk = mkkey(key_val(rk), (uint32_t)m), ok = mkkey(ov, (uint32_t)m);
+        if (nk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&cblk[m >> 6]), (unsigned long long)nk);
+        else if (nk < ok && cblk[m >> 6] == ok) atomicOr(&cmask[(m >> 6) >> 5], 1u << ((m >> 6) & 31));
       }
       in_cur = in_next;
       ent_next = ent_after;
@@ -393,7 +424,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         const int b = w * 32 + __builtin_ctz(bits);
         bits &= bits - 1;
         const int m = b * WAVE + lane;
-        uint64_t k = m < M ? ckey[m] : 0ull;
+        uint64_t k = m < M ? mkkey(ckey[m], (uint32_t)m) : 0ull;
         k = wave_max_u64(k);
         if (lane == 0) cblk[b] = k;
       }

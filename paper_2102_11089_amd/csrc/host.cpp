@@ -109,6 +109,7 @@ long long topo_bytes(const ldpc_code* c, int topo) {
 struct Dims {
   int E, N, M;
   long long topo_bytes;
+  int nbr_passes;  // largest two-hop table of a VN, in passes of 64 lanes
 };
 
 // store: STORE_LDS (c2v, pre, Lt in LDS), STORE_PRE_GLOBAL (c2v, Lt), STORE_ALL_GLOBAL (Lt),
@@ -126,14 +127,14 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int extra_bytes)
   L.off_L = o; o = align16(o + c.N * llr);
   L.off_Lt = o; if (store != STORE_ALL_GLOBAL_LT) o = align16(o + c.N * llr);
   L.off_D = o; o = align16(o + c.N * 4);
-  L.off_ckey = o; o = align16(o + c.M * 8);
+  L.off_ckey = o; o = align16(o + c.M * 4);
   L.off_dblk = o; o = align16(o + L.nbd * 8);
   L.off_cblk = o; o = align16(o + L.nbc * 8);
   L.off_dmask = o; o = align16(o + L.nbd_words * 4);
   L.off_cmask = o; o = align16(o + L.nbc_words * 4);
-  L.off_syn = o; o = align16(o + c.M);
+  L.off_syn = o; o = align16(o + ((c.M + 31) / 32) * 4);
   (void)val;
-  L.off_v = o; o = align16(o + NBR_PMAX * WAVE * 4);  // touched VN per two-hop table lane
+  L.off_v = o; o = align16(o + std::max(1, std::min(c.nbr_passes, NBR_PMAX)) * WAVE * 4);  // touched VN per table lane
   L.off_pbuf = L.off_jbuf = L.off_kbuf = L.off_slot = L.off_trow = o;
   L.off_lut = o; if (fixed) o = align16(o + 257 * 4);
   L.off_topo = o; o = align16(o + (int)std::max(0LL, c.topo_bytes));
@@ -143,7 +144,8 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int extra_bytes)
 }
 
 DynLayout dyn_layout(const ldpc_code* c, bool fixed, int store, int topo, int extra_bytes) {
-  return dyn_layout_dims(Dims{c->E, c->N, c->M, topo_bytes(c, topo)}, fixed, store, extra_bytes);
+  return dyn_layout_dims(Dims{c->E, c->N, c->M, topo_bytes(c, topo), (c->nbr_max_cnt + WAVE - 1) / WAVE}, fixed,
+                         store, extra_bytes);
 }
 
 
@@ -1037,7 +1039,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return LDPC_EHIP;
   bool all_qc = true;
-  Dims mx{0, 0, 0, 0};
+  Dims mx{0, 0, 0, 0, 0};
   for (int i = 0; i < n_codes; ++i) {
     const ldpc_code* c = codes[i];
     if (!c || c->device != dev) return LDPC_EINVAL;
@@ -1046,6 +1048,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
     mx.E = std::max(mx.E, c->E);
     mx.N = std::max(mx.N, c->N);
     mx.M = std::max(mx.M, c->M);
+    mx.nbr_passes = std::max(mx.nbr_passes, (c->nbr_max_cnt + WAVE - 1) / WAVE);
   }
   const int topo = all_qc ? TOPO_QC : TOPO_GLOBAL;
   for (int i = 0; i < n_codes; ++i) mx.topo_bytes = std::max(mx.topo_bytes, topo_bytes(codes[i], topo));
