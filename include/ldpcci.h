@@ -209,8 +209,10 @@ int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t*
 #define LDPC_STORE_GLOBAL 2      /* precomputed messages in a global scratch slot (ME: all)       */
 #define LDPC_STORE_GLOBAL_ALL 3  /* C2V and precomputed messages as interleaved pairs in a global
                                     slot                                                          */
-#define LDPC_STORE_GLOBAL_LT 4   /* those pairs and the precomputed total LLRs in a global slot:
-                                    the least LDS per frame, so the most frames per CU            */
+#define LDPC_STORE_GLOBAL_LT 4   /* those pairs and the precomputed total LLRs in a global slot   */
+#define LDPC_STORE_GLOBAL_FRAME 5 /* the whole frame (messages, precomputed and total LLRs, CIs)
+                                     in a global slot; only keys and trees stay in LDS: the most
+                                     frames per CU                                                */
 #define LDPC_TOPO_AUTO 0    /* quasi-cyclic tables, else LDS copies, else global arrays       */
 #define LDPC_TOPO_GLOBAL 1
 #define LDPC_TOPO_LDS 2
@@ -236,7 +238,8 @@ int ldpc_get_tuning(const ldpc_code* code, int32_t kind, int32_t arith, ldpc_tun
    caller's frames (llr_in: device [B][N]; best of reps timed runs after one warm-up, HIP events on
    stream), stores the fastest with ldpc_set_tuning and returns it (best, best_ms nullable).
    Blocking: synchronizes stream.  Candidates: block in {64..1024} for flooding / layered;
-   storage (LDS, pre global, all messages global, messages and Lt global) x topology x
+   storage (LDS, pre global, all messages global, messages and Lt global, whole frame global) x
+   topology x
    frames_per_cu in {auto, 1, 2, 4, 8, 16}
    (and block in {64, 256, 1024} for ME-CIRBP) for the dynamic schedules.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),
    LDPC_ECAPACITY (no candidate fits), LDPC_EHIP. */

@@ -36,8 +36,7 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
   using val_t = typename A::val_t;
   using Acc = typename RowAccOf<A>::type;
   const int lane = threadIdx.x & (WAVE - 1);
-  unsigned char* lds = dyn_lds();
-  llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
+  llr_t* L = frame_L(ms, P);
   const int N = H.N, M = H.M, E = H.E;
   for (int n = lane; n < N; n += WAVE) L[n] = (llr_t)ar.channel(J.llr[n]);
   for (int e = lane; e < E; e += WAVE) ms.set_c(e, (msg_t)0);
@@ -79,7 +78,7 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
         }
         L[n] = (llr_t)l;
       }
-      wave_sync();
+      store_sync<STORE>();
     } else {
       for (int l = 0; l < H.n_layers; ++l) {
         const int r0 = H.layer_ptr[l], r1 = H.layer_ptr[l + 1];
@@ -202,6 +201,7 @@ static hipError_t launch_batch_t(const BatchParams& B, int topo, int grid, hipSt
 
 template <class A>
 static hipError_t launch_batch_s(const BatchParams& B, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_FRAME_GLOBAL) return launch_batch_t<A, STORE_FRAME_GLOBAL>(B, topo, grid, st);
   if (store == STORE_ALL_GLOBAL_LT) return launch_batch_t<A, STORE_ALL_GLOBAL_LT>(B, topo, grid, st);
   if (store == STORE_ALL_GLOBAL) return launch_batch_t<A, STORE_ALL_GLOBAL>(B, topo, grid, st);
   if (store == STORE_PRE_GLOBAL) return launch_batch_t<A, STORE_PRE_GLOBAL>(B, topo, grid, st);
@@ -228,10 +228,12 @@ hipError_t set_batch_lds_limit(int bytes) {
   hipError_t e = hipSuccess;
   for (hipError_t r : {set_batch_store<ArithF32, STORE_LDS>(bytes), set_batch_store<ArithF32, STORE_PRE_GLOBAL>(bytes),
                        set_batch_store<ArithF32, STORE_ALL_GLOBAL>(bytes),
-                       set_batch_store<ArithF32, STORE_ALL_GLOBAL_LT>(bytes), set_batch_store<ArithFix, STORE_LDS>(bytes),
+                       set_batch_store<ArithF32, STORE_ALL_GLOBAL_LT>(bytes),
+                       set_batch_store<ArithF32, STORE_FRAME_GLOBAL>(bytes), set_batch_store<ArithFix, STORE_LDS>(bytes),
                        set_batch_store<ArithFix, STORE_PRE_GLOBAL>(bytes),
                        set_batch_store<ArithFix, STORE_ALL_GLOBAL>(bytes),
-                       set_batch_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes)})
+                       set_batch_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes),
+                       set_batch_store<ArithFix, STORE_FRAME_GLOBAL>(bytes)})
     if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }

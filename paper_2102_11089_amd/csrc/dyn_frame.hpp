@@ -56,7 +56,9 @@ struct MsgStore<A, STORE, true> {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   MsgPair<msg_t>* m;  // global, [E]
-  llr_t* Lt;          // LDS (STORE_ALL_GLOBAL) or global (STORE_ALL_GLOBAL_LT), [N]
+  llr_t* Lt;          // LDS (STORE_ALL_GLOBAL) or global, [N]
+  llr_t* Lg;          // STORE_FRAME_GLOBAL: L and D in the slot, [N]
+  uint32_t* Dg;
   __device__ __forceinline__ msg_t c(int e) const { return m[e].c; }
   __device__ __forceinline__ msg_t p(int e) const { return m[e].p; }
   __device__ __forceinline__ void set_c(int e, msg_t v) const { m[e].c = v; }
@@ -72,7 +74,7 @@ struct MsgStore<A, STORE, true> {
 };
 
 // message store of the workgroup's frame slot (slot_edges = edges reserved per workgroup when
-// only pre is global; the pair-slot layout comes from P.slot_bytes / P.slot_lt_off)
+// only pre is global; the pair-slot layout comes from P.slot_bytes and the slot offsets)
 template <class A, int STORE>
 __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, size_t slot_edges) {
   using msg_t = typename A::msg_t;
@@ -82,8 +84,12 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
   if constexpr (STORE >= STORE_ALL_GLOBAL) {
     unsigned char* base = reinterpret_cast<unsigned char*>(P.pre_global) + (size_t)blockIdx.x * (size_t)P.slot_bytes;
     ms.m = reinterpret_cast<MsgPair<msg_t>*>(base);
-    if constexpr (STORE == STORE_ALL_GLOBAL_LT) ms.Lt = reinterpret_cast<llr_t*>(base + P.slot_lt_off);
+    if constexpr (STORE >= STORE_ALL_GLOBAL_LT) ms.Lt = reinterpret_cast<llr_t*>(base + P.slot_lt_off);
     else ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
+    if constexpr (STORE == STORE_FRAME_GLOBAL) {
+      ms.Lg = reinterpret_cast<llr_t*>(base + P.slot_l_off);
+      ms.Dg = reinterpret_cast<uint32_t*>(base + P.slot_d_off);
+    }
   } else {
     ms.c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
     ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
@@ -91,6 +97,25 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
     else ms.pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
   }
   return ms;
+}
+
+// total LLRs L and CIs D of the frame: in LDS, or in the global slot (STORE_FRAME_GLOBAL)
+template <class A, int STORE>
+__device__ __forceinline__ typename A::llr_t* frame_L(const MsgStore<A, STORE>& ms, const DynParams& P) {
+  if constexpr (STORE == STORE_FRAME_GLOBAL) return ms.Lg;
+  else return reinterpret_cast<typename A::llr_t*>(dyn_lds() + P.off_L);
+}
+template <class A, int STORE>
+__device__ __forceinline__ uint32_t* frame_D(const MsgStore<A, STORE>& ms, const DynParams& P) {
+  if constexpr (STORE == STORE_FRAME_GLOBAL) return ms.Dg;
+  else return reinterpret_cast<uint32_t*>(dyn_lds() + P.off_D);
+}
+// ordering point for values exchanged between lanes through the frame store: a workgroup-scope
+// fence (wait for global stores) when the exchanged array lives in global memory
+template <bool GLOBAL>
+__device__ __forceinline__ void frame_sync() {
+  if constexpr (GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  wave_sync();
 }
 
 // value of another lane (the lane index is wave-uniform)
@@ -109,8 +134,9 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   using Acc = typename RowAccOf<A>::type;
   const int lane = threadIdx.x & (WAVE - 1);
   unsigned char* lds = dyn_lds();
-  llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
-  uint32_t* D = reinterpret_cast<uint32_t*>(lds + P.off_D);
+  llr_t* L = frame_L(ms, P);
+  uint32_t* D = frame_D(ms, P);
+  constexpr bool kLDG = STORE == STORE_FRAME_GLOBAL;  // L and D in global memory
   // per check: the largest residual of its edges (value bits); block keys pair it with the check
   // index, and the edge is found again inside the check's row when the check is selected (edge ids
   // are row-major, so (value, lowest check), then (value, lowest edge) in the row is the global
@@ -133,7 +159,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   for (int w = lane; w < nbd_words; w += WAVE) dmask[w] = 0u;
   for (int w = lane; w < nbc_words; w += WAVE) cmask[w] = 0u;
   for (int w = lane; w < (M + 31) / 32; w += WAVE) synw[w] = 0u;
-  wave_sync();
+  frame_sync<kLDG>();
   // every precomputed C2V message from V2C = channel value: one lane per check row
   int unsat_local = 0;
   for (int m = lane; m < M; m += WAVE) {
@@ -171,7 +197,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     ms.set_lt(n, (llr_t)lt);
     D[n] = with_ci ? ar.ci((val_t)L[n], lt) : 0u;
   }
-  wave_sync();
+  frame_sync<kLDG>();
   for (int b = 0; b < nbd; ++b) {
     const int n = b * WAVE + lane;
     uint64_t k = n < N ? mkkey(D[n], (uint32_t)n) : 0ull;
@@ -416,6 +442,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         wave_sync();
       }
     }
+    if constexpr (kLDG) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // D stores done
     PROF_MARK(5)
     // ---- blocks whose maximum leaf decreased ----
     for (int w = 0; w < nbc_words; ++w) {

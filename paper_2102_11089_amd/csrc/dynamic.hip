@@ -86,6 +86,7 @@ static hipError_t launch_dyn_t(const DevCode& H, const DynParams& P, int topo, i
 
 template <class A>
 static hipError_t launch_dyn_s(const DevCode& H, const DynParams& P, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_FRAME_GLOBAL) return launch_dyn_t<A, STORE_FRAME_GLOBAL>(H, P, topo, grid, st);
   if (store == STORE_ALL_GLOBAL_LT) return launch_dyn_t<A, STORE_ALL_GLOBAL_LT>(H, P, topo, grid, st);
   if (store == STORE_ALL_GLOBAL) return launch_dyn_t<A, STORE_ALL_GLOBAL>(H, P, topo, grid, st);
   if (store == STORE_PRE_GLOBAL) return launch_dyn_t<A, STORE_PRE_GLOBAL>(H, P, topo, grid, st);
@@ -114,8 +115,9 @@ hipError_t set_dynamic_lds_limit(int bytes) {
   hipError_t e = hipSuccess;
   for (hipError_t r : {set_store<ArithF32, STORE_LDS>(bytes), set_store<ArithF32, STORE_PRE_GLOBAL>(bytes),
                        set_store<ArithF32, STORE_ALL_GLOBAL>(bytes), set_store<ArithF32, STORE_ALL_GLOBAL_LT>(bytes),
-                       set_store<ArithFix, STORE_LDS>(bytes), set_store<ArithFix, STORE_PRE_GLOBAL>(bytes),
-                       set_store<ArithFix, STORE_ALL_GLOBAL>(bytes), set_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes)})
+                       set_store<ArithF32, STORE_FRAME_GLOBAL>(bytes), set_store<ArithFix, STORE_LDS>(bytes),
+                       set_store<ArithFix, STORE_PRE_GLOBAL>(bytes), set_store<ArithFix, STORE_ALL_GLOBAL>(bytes),
+                       set_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes), set_store<ArithFix, STORE_FRAME_GLOBAL>(bytes)})
     if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }

@@ -112,8 +112,8 @@ struct Dims {
   int nbr_passes;  // largest two-hop table of a VN, in passes of 64 lanes
 };
 
-// store: STORE_LDS (c2v, pre, Lt in LDS), STORE_PRE_GLOBAL (c2v, Lt), STORE_ALL_GLOBAL (Lt),
-// STORE_ALL_GLOBAL_LT (none of them)
+// store: STORE_LDS (c2v, pre, Lt, L, D in LDS), STORE_PRE_GLOBAL (c2v, Lt, L, D), STORE_ALL_GLOBAL
+// (Lt, L, D), STORE_ALL_GLOBAL_LT (L, D), STORE_FRAME_GLOBAL (none of them)
 DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int extra_bytes) {
   DynLayout L{};
   const int msg = fixed ? 1 : 4, llr = 4, val = 4;
@@ -124,9 +124,9 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int extra_bytes)
   int o = 0;
   L.off_c2v = o; if (store < STORE_ALL_GLOBAL) o = align16(o + c.E * msg);
   L.off_pre = o; if (store == STORE_LDS) o = align16(o + c.E * msg);
-  L.off_L = o; o = align16(o + c.N * llr);
-  L.off_Lt = o; if (store != STORE_ALL_GLOBAL_LT) o = align16(o + c.N * llr);
-  L.off_D = o; o = align16(o + c.N * 4);
+  L.off_L = o; if (store != STORE_FRAME_GLOBAL) o = align16(o + c.N * llr);
+  L.off_Lt = o; if (store < STORE_ALL_GLOBAL_LT) o = align16(o + c.N * llr);
+  L.off_D = o; if (store != STORE_FRAME_GLOBAL) o = align16(o + c.N * 4);
   L.off_ckey = o; o = align16(o + c.M * 4);
   L.off_dblk = o; o = align16(o + L.nbd * 8);
   L.off_cblk = o; o = align16(o + L.nbc * 8);
@@ -536,12 +536,15 @@ bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
 
 constexpr size_t kQueueBytes = 256;  // work-queue counter at the front of a persistent launch's scratch
 
-// global slot of one frame when all its messages live in global memory: (c2v, pre) pairs for E
-// edges, then Lt for N VNs, 256-byte aligned
-void all_global_slot(int E, int N, bool fixed, long long& slot_bytes, int& lt_off) {
+// global slot of one frame when its messages live in global memory: (c2v, pre) pairs for E edges,
+// then Lt, L and D for N VNs, each 256-byte aligned
+void all_global_slot(int E, int N, bool fixed, DynParams& P) {
+  auto up = [](long long x) { return (x + 255) / 256 * 256; };
   const long long pairs = 2LL * E * (fixed ? 1 : 4);
-  lt_off = (int)((pairs + 255) / 256 * 256);
-  slot_bytes = (lt_off + 4LL * N + 255) / 256 * 256;
+  P.slot_lt_off = (int)up(pairs);
+  P.slot_l_off = (int)up(P.slot_lt_off + 4LL * N);
+  P.slot_d_off = (int)up(P.slot_l_off + 4LL * N);
+  P.slot_bytes = up(P.slot_d_off + 4LL * N);
 }
 
 // tuning knob -> candidate topologies (empty: the knob does not apply to this code)
@@ -559,7 +562,7 @@ int check_tuning(const ldpc_tuning* t) {
   if (!t) return LDPC_OK;
   if (t->block != 0 && !valid_block(t->block)) return LDPC_EINVAL;
   if (t->frames_per_cu < 0 || t->frames_per_cu > 32) return LDPC_EINVAL;
-  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_LT) return LDPC_EINVAL;
+  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_FRAME) return LDPC_EINVAL;
   if (t->topology < LDPC_TOPO_AUTO || t->topology > LDPC_TOPO_QC) return LDPC_EINVAL;
   return LDPC_OK;
 }
@@ -638,11 +641,12 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (c->nbr_max_cnt > NBR_PMAX * WAVE) return LDPC_EUNSUPPORTED;
   const std::vector<int> topos = topo_choices(c, T.topology);
   if (topos.empty()) return LDPC_EUNSUPPORTED;
-  std::vector<int> stores = {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL, STORE_ALL_GLOBAL_LT};
+  std::vector<int> stores = {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL, STORE_ALL_GLOBAL_LT, STORE_FRAME_GLOBAL};
   if (T.storage == LDPC_STORE_LDS) stores = {STORE_LDS};
   if (T.storage == LDPC_STORE_GLOBAL) stores = {STORE_PRE_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_ALL) stores = {STORE_ALL_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_LT) stores = {STORE_ALL_GLOBAL_LT};
+  if (T.storage == LDPC_STORE_GLOBAL_FRAME) stores = {STORE_FRAME_GLOBAL};
   const int lut_off = 257 * (fixed ? s->frac_bits : 0);
 
   if (s->kind == LDPC_ME_CIRBP) {
@@ -739,9 +743,9 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
       if (cand.total > pl.lds_limit) continue;
       const int fit = std::max(1, (160 * 1024) / std::max(cand.total, 1));
       const int eff = (int)std::min<long long>(std::min(fit, cap_fpc), need);
-      // Store preference: one round on the chip: LDS > PRE_GLOBAL > ALL_GLOBAL > ALL_GLOBAL_LT;
-      // larger batches: ALL_GLOBAL > ALL_GLOBAL_LT > PRE_GLOBAL > LDS
-      static const int rank_small[4] = {3, 2, 1, 0}, rank_large[4] = {0, 1, 3, 2};
+      // Store preference: one round on the chip: LDS > PRE_GLOBAL > ALL_GLOBAL > ALL_GLOBAL_LT >
+      // FRAME_GLOBAL; larger batches: ALL_GLOBAL > ALL_GLOBAL_LT > FRAME_GLOBAL > PRE_GLOBAL > LDS
+      static const int rank_small[5] = {4, 3, 2, 1, 0}, rank_large[5] = {0, 1, 4, 3, 2};
       const int st_pref = need <= 1 ? rank_small[st] : rank_large[st];
       const int tp_pref = tp == TOPO_QC ? 2 : (tp == TOPO_LDS ? 1 : 0);
       const int pref = st_pref * 4 + tp_pref;
@@ -783,7 +787,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (pl.persistent) pl.scratch_bytes = kQueueBytes;  // work-queue counter, then message slots
   if (pl.store == STORE_PRE_GLOBAL) pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * c->E * msg;
   if (pl.store >= STORE_ALL_GLOBAL) {
-    all_global_slot(c->E, c->N, fixed, P.slot_bytes, P.slot_lt_off);
+    all_global_slot(c->E, c->N, fixed, P);
     pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * (size_t)P.slot_bytes;
   }
   return LDPC_OK;
@@ -898,7 +902,8 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
     if (!c->h_qc.empty()) tps.push_back(LDPC_TOPO_QC);
     const std::vector<int> blocks = s->kind == LDPC_ME_CIRBP ? std::vector<int>{64, 256, 1024} : std::vector<int>{0};
     for (int b : blocks)
-      for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL, LDPC_STORE_GLOBAL_LT})
+      for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL, LDPC_STORE_GLOBAL_LT,
+                        LDPC_STORE_GLOBAL_FRAME})
         for (int tp : tps)
           for (int fpc : {0, 1, 2, 4, 8, 16})
             cands.push_back(ldpc_tuning{b, fpc, store, tp});
@@ -1058,7 +1063,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   // all messages in global memory (the batch is a large persistent launch)
   int store = -1, best_fit = 0;
   DynLayout Ly{};
-  for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL_LT, STORE_ALL_GLOBAL}) {
+  for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_FRAME_GLOBAL, STORE_ALL_GLOBAL_LT, STORE_ALL_GLOBAL}) {
     DynLayout cand = dyn_layout_dims(mx, fixed, st, 0);
     if (cand.total > lds_limit) continue;
     const int fit = std::min(32, (160 * 1024) / std::max(cand.total, 1));
@@ -1099,7 +1104,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   size_t pre_bytes = 0;
   if (store == STORE_PRE_GLOBAL) pre_bytes = (size_t)grid * mx.E * (fixed ? 1 : 4);
   if (store >= STORE_ALL_GLOBAL) {
-    all_global_slot(mx.E, mx.N, fixed, P.slot_bytes, P.slot_lt_off);
+    all_global_slot(mx.E, mx.N, fixed, P);
     pre_bytes = (size_t)grid * (size_t)P.slot_bytes;
   }
   void* scratch = nullptr;

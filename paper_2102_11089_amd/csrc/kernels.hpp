@@ -10,8 +10,9 @@ namespace ldpc {
 enum Kind { KIND_FLOODING = 0, KIND_LAYERED = 1, KIND_RBP = 2, KIND_CIRBP = 3, KIND_ME_CIRBP = 4, KIND_REPLAY = 5 };
 enum Topo { TOPO_GLOBAL = 0, TOPO_LDS = 1, TOPO_QC = 2 };
 // single-edge frame storage: c2v and pre in LDS; pre in a global slot; both in a global slot; both
-// and the precomputed totals Lt in a global slot
-enum Store { STORE_LDS = 0, STORE_PRE_GLOBAL = 1, STORE_ALL_GLOBAL = 2, STORE_ALL_GLOBAL_LT = 3 };
+// and the precomputed totals Lt in a global slot; the whole frame (messages, Lt, L, D) in a global
+// slot, leaving only check keys, block maxima, syndrome bits and staging in LDS
+enum Store { STORE_LDS = 0, STORE_PRE_GLOBAL = 1, STORE_ALL_GLOBAL = 2, STORE_ALL_GLOBAL_LT = 3, STORE_FRAME_GLOBAL = 4 };
 
 struct DecOut {
   uint8_t* bits;            // [B][N]
@@ -40,8 +41,10 @@ struct DynParams {
   float scale;
   const int* lut_global;    // 257 entries (fixed point)
   void* pre_global;         // per-workgroup message slots when messages are not in LDS
-  long long slot_bytes;     // STORE_ALL_GLOBAL(_LT): bytes per slot ((c2v, pre) pairs, then Lt)
-  int slot_lt_off;          // STORE_ALL_GLOBAL_LT: byte offset of Lt in a slot
+  long long slot_bytes;     // STORE_ALL_GLOBAL and up: bytes per slot ((c2v, pre) pairs, Lt, L, D)
+  int slot_lt_off;          // STORE_ALL_GLOBAL_LT and up: byte offset of Lt in a slot
+  int slot_l_off;           // STORE_FRAME_GLOBAL: byte offsets of L and D in a slot
+  int slot_d_off;
   int* queue;               // persistent launch: next-frame counter (zeroed before launch); null:
                             // workgroup b decodes frames b, b + grid, ...
   // ME-CIRBP

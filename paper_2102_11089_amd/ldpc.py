@@ -32,7 +32,7 @@ EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_co
            "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
            "ldpc_strerror", "ldpc_last_hip_error")
 UNROLL_MAX_CKPT_EVERY = 128
-STORE_AUTO, STORE_LDS, STORE_GLOBAL, STORE_GLOBAL_ALL, STORE_GLOBAL_LT = 0, 1, 2, 3, 4
+STORE_AUTO, STORE_LDS, STORE_GLOBAL, STORE_GLOBAL_ALL, STORE_GLOBAL_LT, STORE_GLOBAL_FRAME = 0, 1, 2, 3, 4, 5
 TOPO_AUTO, TOPO_GLOBAL, TOPO_LDS, TOPO_QC = 0, 1, 2, 3
 
 # layout of ldpc_frame_desc (40 bytes)

@@ -234,7 +234,7 @@ def test_edge_cases(gpu, c0):
 # ------------------------------------------------------------------------------------------
 # storage variants: every (pre location, topology source) combination is bit-exact
 # ------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("pre", ["lds", "global", "all", "all_lt"])
+@pytest.mark.parametrize("pre", ["lds", "global", "all", "all_lt", "frame"])
 @pytest.mark.parametrize("topo", ["global", "lds", "qc"])
 @pytest.mark.parametrize("fpc", [0, 3])
 def test_fixed_storage_variants(gpu, pre, topo, fpc):
@@ -244,7 +244,7 @@ def test_fixed_storage_variants(gpu, pre, topo, fpc):
     ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True, dump=True,
                    threads=8)
     store = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL,
-             "all_lt": gpu.STORE_GLOBAL_LT}[pre]
+             "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME}[pre]
     tp = {"global": gpu.TOPO_GLOBAL, "lds": gpu.TOPO_LDS, "qc": gpu.TOPO_QC}[topo]
     handles = [gpu.Code(code)] if topo == "qc" else [gpu.Code(code), gpu.Code(code, csr=True)]
     for h in handles:
@@ -379,7 +379,7 @@ def test_batch_rejects_bad_descriptors(gpu):
     assert u[0] >= 0 and u[5] >= 0
 
 
-@pytest.mark.parametrize("store", ["lds", "global", "all", "all_lt"])
+@pytest.mark.parametrize("store", ["lds", "global", "all", "all_lt", "frame"])
 def test_f32_storage_modes_identical(gpu, store):
     """FP32 results do not depend on where the messages live (same arithmetic, same order)."""
     code = S.workload_code("c4")
@@ -389,7 +389,7 @@ def test_f32_storage_modes_identical(gpu, store):
     gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, clear=True)
     base = gpu.decode(h, t, gpu.CIRBP, gpu.SPA_F32, max_updates=4000, trace=True)
     st = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL,
-          "all_lt": gpu.STORE_GLOBAL_LT}[store]
+          "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME}[store]
     gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, storage=st, frames_per_cu=2)
     try:
         r = gpu.decode(h, t, gpu.CIRBP, gpu.SPA_F32, max_updates=4000, trace=True)
