@@ -35,6 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 LDS_PEAK_GBS = 256 * 128 * 2.4  # CUs x bytes/clk/CU x GHz = 78643 GB/s (nominal LDS bandwidth)
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 METRIC = "decoded frames/s & edge-updates/s at FER 1e-3, CI vs flooding BP, one MI355X"
 
 
@@ -484,11 +485,14 @@ def main():
         "ci": {"fer": fe / nf, "frame_errors": fe, "frames": nf, "frames_per_s": round(ci_fps, 3),
                "edge_updates_per_s": round(upd / wall, 1), "mean_updates_per_frame": upd / nf,
                "fallback_fraction": fall / max(upd, 1), "kernel_ms_per_step": [round(x, 3) for x in kms]},
-        "roofline": {"bound": "lds", "achieved": round(achieved_gbs, 2), "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved_gbs / LDS_PEAK_GBS, 6), "traffic": traffic_gbs,
-                     "kernel": "k_dynamic<ArithF32, STORE_ALL_GLOBAL, TOPO_QC> (2 frames per CU, work queue)",
+        # the frame state (messages, totals, CIs) lives in global memory, so the algorithmic bytes of
+        # the update loop (Table 1 operations priced in bytes) are served from L2/MALL/HBM
+        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 6), "traffic": traffic_gbs,
+                     "kernel": "k_dynamic<ArithF32, STORE_FRAME_GLOBAL, TOPO_GLOBAL> (13 frames per CU, work queue)",
                      "bytes_per_update": round(bytes_per_update, 2),
-                     "kernel_ms_avg": round(float(np.mean(kms)), 3)},
+                     "kernel_ms_avg": round(float(np.mean(kms)), 3),
+                     "lds_frac": round(achieved_gbs / LDS_PEAK_GBS, 6)},
     }
 
     if not args.no_baselines:
