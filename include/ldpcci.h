@@ -219,7 +219,9 @@ int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t*
 #define LDPC_TOPO_QC 3
 
 typedef struct {
-  int32_t block;         /* threads per frame: flooding / layered / ME-CIRBP (64..1024, step 64)   */
+  int32_t block;         /* threads per workgroup (64..1024, step 64): per frame for flooding,
+                            layered and ME-CIRBP; for RBP / CIRBP / replay 64 x the frames that
+                            share a workgroup (and its LDS copy of the topology)                   */
   int32_t frames_per_cu; /* single-edge and ME: resident frames per CU of a persistent grid (1..32) */
   int32_t storage;       /* LDPC_STORE_*: where the messages of a frame live                        */
   int32_t topology;      /* LDPC_TOPO_*: where the kernels read H from                              */
@@ -237,9 +239,11 @@ int ldpc_get_tuning(const ldpc_code* code, int32_t kind, int32_t arith, ldpc_tun
 /* Project autotuner: times every distinct launch plan the knobs give for this schedule on the
    caller's frames (llr_in: device [B][N]; best of reps timed runs after one warm-up, HIP events on
    stream), stores the fastest with ldpc_set_tuning and returns it (best, best_ms nullable).
+   Tune on a batch of the size that will be decoded: a small batch cannot use the frame
+   residency that large batches gain from, and favours low-latency plans.
    Blocking: synchronizes stream.  Candidates: block in {64..1024} for flooding / layered;
    storage (LDS, pre global, all messages global, messages and Lt global, whole frame global) x
-   topology x
+   topology x frames per workgroup in {auto, 4, 8} x
    frames_per_cu in {auto, 1, 2, 4, 8, 16}
    (and block in {64, 256, 1024} for ME-CIRBP) for the dynamic schedules.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),
    LDPC_ECAPACITY (no candidate fits), LDPC_EHIP. */

@@ -22,6 +22,17 @@ __device__ __forceinline__ unsigned char* dyn_lds() {
   return lds_dyn;
 }
 
+// A workgroup holds P.wpb frames, one per wavefront: the LDS region of this wavefront's frame, and
+// the index of its frame slot in global scratch
+// (the wavefront index is made scalar so that frame addresses stay wave-uniform)
+__device__ __forceinline__ int wave_in_group() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+__device__ __forceinline__ unsigned char* frame_lds(const DynParams& P) {
+  return dyn_lds() + P.frame_base + wave_in_group() * P.frame_stride;
+}
+__device__ __forceinline__ size_t frame_slot(const DynParams& P) {
+  return (size_t)blockIdx.x * (size_t)P.wpb + (size_t)wave_in_group();
+}
+
 // Where a frame's C2V messages (c2v), precomputed messages (pre) and precomputed totals (Lt)
 // live: all in LDS; pre in a global scratch slot; c2v and pre as interleaved (c2v, pre) pairs (one
 // load brings the two values of an edge) in a global slot per workgroup; or those pairs followed
@@ -79,10 +90,10 @@ template <class A, int STORE>
 __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, size_t slot_edges) {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
-  unsigned char* lds = dyn_lds();
+  unsigned char* lds = frame_lds(P);
   MsgStore<A, STORE> ms;
   if constexpr (STORE >= STORE_ALL_GLOBAL) {
-    unsigned char* base = reinterpret_cast<unsigned char*>(P.pre_global) + (size_t)blockIdx.x * (size_t)P.slot_bytes;
+    unsigned char* base = reinterpret_cast<unsigned char*>(P.pre_global) + frame_slot(P) * (size_t)P.slot_bytes;
     ms.m = reinterpret_cast<MsgPair<msg_t>*>(base);
     if constexpr (STORE >= STORE_ALL_GLOBAL_LT) ms.Lt = reinterpret_cast<llr_t*>(base + P.slot_lt_off);
     else ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
@@ -93,7 +104,7 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
   } else {
     ms.c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
     ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
-    if constexpr (STORE == STORE_PRE_GLOBAL) ms.pre = reinterpret_cast<msg_t*>(P.pre_global) + (size_t)blockIdx.x * slot_edges;
+    if constexpr (STORE == STORE_PRE_GLOBAL) ms.pre = reinterpret_cast<msg_t*>(P.pre_global) + frame_slot(P) * slot_edges;
     else ms.pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
   }
   return ms;
@@ -103,12 +114,12 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
 template <class A, int STORE>
 __device__ __forceinline__ typename A::llr_t* frame_L(const MsgStore<A, STORE>& ms, const DynParams& P) {
   if constexpr (STORE == STORE_FRAME_GLOBAL) return ms.Lg;
-  else return reinterpret_cast<typename A::llr_t*>(dyn_lds() + P.off_L);
+  else return reinterpret_cast<typename A::llr_t*>(frame_lds(P) + P.off_L);
 }
 template <class A, int STORE>
 __device__ __forceinline__ uint32_t* frame_D(const MsgStore<A, STORE>& ms, const DynParams& P) {
   if constexpr (STORE == STORE_FRAME_GLOBAL) return ms.Dg;
-  else return reinterpret_cast<uint32_t*>(dyn_lds() + P.off_D);
+  else return reinterpret_cast<uint32_t*>(frame_lds(P) + P.off_D);
 }
 // ordering point for values exchanged between lanes through the frame store: a workgroup-scope
 // fence (wait for global stores) when the exchanged array lives in global memory
@@ -133,7 +144,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   using val_t = typename A::val_t;
   using Acc = typename RowAccOf<A>::type;
   const int lane = threadIdx.x & (WAVE - 1);
-  unsigned char* lds = dyn_lds();
+  unsigned char* lds = frame_lds(P);
   llr_t* L = frame_L(ms, P);
   uint32_t* D = frame_D(ms, P);
   constexpr bool kLDG = STORE == STORE_FRAME_GLOBAL;  // L and D in global memory

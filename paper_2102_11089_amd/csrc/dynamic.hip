@@ -1,7 +1,8 @@
 // Single-edge dynamic schedules on gfx950: residual BP (RBP, Sec. II-A steps 1-4), CIRBP
 // (Algorithm 1, Sec. III-B) and forced-order replay of a recorded schedule.
 //
-// One wavefront (64 lanes, one workgroup) decodes one codeword at a time.  A persistent grid pulls
+// One wavefront (64 lanes) decodes one codeword at a time; a workgroup holds one or more such
+// frames, which share the workgroup's copy of the topology (and p0 table) in LDS.  A persistent grid pulls
 // frames from a device counter (frames differ widely in length, so fixed striding would leave a
 // long tail); otherwise there is one workgroup per frame.  The frame's state lives in LDS:
 //   c2v[E], pre[E]      current and precomputed C2V messages (pre, or both as interleaved pairs,
@@ -27,23 +28,26 @@ namespace ldpc {
 
 
 
-template <class A, int STORE, int TOPO>
-__global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
+// MF: several frames per workgroup (up to 16 wavefronts); otherwise one wavefront per workgroup,
+// which lets the compiler keep the register count at the level of full occupancy
+template <class A, int STORE, int TOPO, bool MF>
+__global__ __launch_bounds__(MF ? 1024 : WAVE) void k_dynamic(DevCode H, DynParams P) {
   using msg_t = typename A::msg_t;
   unsigned char* lds = dyn_lds();
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (WAVE - 1);
   const auto ms = make_store<A, STORE>(P, (size_t)H.E);
+  // shared by the workgroup's frames: the p0 table and the topology
   int* lut = reinterpret_cast<int*>(lds + P.off_lut);
   A ar;
   ar.qmax = P.qmax;
   ar.scale = P.scale;
   ar.lut = lut;
   if constexpr (A::kFixed) {
-    for (int x = lane; x < 257; x += WAVE) lut[x] = P.lut_global[x];
+    for (int x = threadIdx.x; x < 257; x += blockDim.x) lut[x] = P.lut_global[x];
   }
-  const auto G = TopoSel<TOPO>::make(H, lds + P.off_topo, lane, WAVE);
-  wave_sync();
-  int f = blockIdx.x;
+  const auto G = TopoSel<TOPO>::make(H, lds + P.off_topo, threadIdx.x, blockDim.x);
+  __syncthreads();  // the only workgroup barrier: the frames below run independently
+  int f = (int)frame_slot(P);
   if (P.queue) f = uni(lane == 0 ? atomicAdd(P.queue, 1) : 0);
   while (f < P.B) {
     FrameJob J;
@@ -67,13 +71,19 @@ __global__ __launch_bounds__(WAVE) void k_dynamic(DevCode H, DynParams P) {
     J.dump_D = P.out.dump_D ? P.out.dump_D + (size_t)f * H.N : nullptr;
     dyn_decode_frame<A, STORE>(H, G, ar, P, ms, J);
     if (P.queue) f = uni(lane == 0 ? atomicAdd(P.queue, 1) : 0);
-    else f += gridDim.x;
+    else f += gridDim.x * P.wpb;
   }
 }
 
 template <class A, int ST, int TP>
 static hipError_t launch_dyn(const DevCode& H, const DynParams& P, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_dynamic<A, ST, TP>), dim3(grid), dim3(WAVE), P.lds_bytes, st, H, P);
+  if constexpr (TP != TOPO_GLOBAL) {
+    if (P.wpb > 1) {
+      hipLaunchKernelGGL((k_dynamic<A, ST, TP, true>), dim3(grid), dim3(WAVE * P.wpb), P.lds_bytes, st, H, P);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_dynamic<A, ST, TP, false>), dim3(grid), dim3(WAVE), P.lds_bytes, st, H, P);
   return hipGetLastError();
 }
 
@@ -100,7 +110,12 @@ hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, int 
 
 template <class A, int ST, int TP>
 static hipError_t set_one(int bytes) {
-  return hipFuncSetAttribute((const void*)k_dynamic<A, ST, TP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  hipError_t e = hipFuncSetAttribute((const void*)k_dynamic<A, ST, TP, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if constexpr (TP != TOPO_GLOBAL) {
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_dynamic<A, ST, TP, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  }
+  return e;
 }
 
 template <class A, int ST>

@@ -94,6 +94,7 @@ struct DynLayout {
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_ckey, off_dblk, off_cblk, off_dmask, off_cmask, off_syn;
   int off_v, off_pbuf, off_jbuf, off_kbuf, off_slot, off_trow, off_lut, off_topo, off_extra, total;
   int nbd, nbc, nbd_words, nbc_words;
+  int frame_base, frame_stride, wpb;  // shared region, then wpb frame regions of frame_stride bytes
 };
 
 // LDS bytes of a topology variant
@@ -112,40 +113,45 @@ struct Dims {
   int nbr_passes;  // largest two-hop table of a VN, in passes of 64 lanes
 };
 
-// store: STORE_LDS (c2v, pre, Lt, L, D in LDS), STORE_PRE_GLOBAL (c2v, Lt, L, D), STORE_ALL_GLOBAL
-// (Lt, L, D), STORE_ALL_GLOBAL_LT (L, D), STORE_FRAME_GLOBAL (none of them)
-DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int extra_bytes) {
+// LDS of the single-edge kernels for wpb frames per workgroup: a shared region (p0 table in fixed
+// point, topology tables) followed by wpb frame regions.  Frame arrays by storage mode: STORE_LDS
+// c2v, pre, Lt, L, D; STORE_PRE_GLOBAL c2v, Lt, L, D; STORE_ALL_GLOBAL Lt, L, D; STORE_ALL_GLOBAL_LT
+// L, D; STORE_FRAME_GLOBAL none of them; always the check keys, block maxima, dirty masks,
+// syndrome bits and the two-hop staging.  Frame offsets are relative to the frame's region.
+DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int wpb) {
   DynLayout L{};
-  const int msg = fixed ? 1 : 4, llr = 4, val = 4;
+  const int msg = fixed ? 1 : 4, llr = 4;
   L.nbd = (c.N + WAVE - 1) / WAVE;
   L.nbc = (c.M + WAVE - 1) / WAVE;
   L.nbd_words = (L.nbd + 31) / 32;
   L.nbc_words = (L.nbc + 31) / 32;
   int o = 0;
-  L.off_c2v = o; if (store < STORE_ALL_GLOBAL) o = align16(o + c.E * msg);
-  L.off_pre = o; if (store == STORE_LDS) o = align16(o + c.E * msg);
-  L.off_L = o; if (store != STORE_FRAME_GLOBAL) o = align16(o + c.N * llr);
-  L.off_Lt = o; if (store < STORE_ALL_GLOBAL_LT) o = align16(o + c.N * llr);
-  L.off_D = o; if (store != STORE_FRAME_GLOBAL) o = align16(o + c.N * 4);
-  L.off_ckey = o; o = align16(o + c.M * 4);
-  L.off_dblk = o; o = align16(o + L.nbd * 8);
-  L.off_cblk = o; o = align16(o + L.nbc * 8);
-  L.off_dmask = o; o = align16(o + L.nbd_words * 4);
-  L.off_cmask = o; o = align16(o + L.nbc_words * 4);
-  L.off_syn = o; o = align16(o + ((c.M + 31) / 32) * 4);
-  (void)val;
-  L.off_v = o; o = align16(o + std::max(1, std::min(c.nbr_passes, NBR_PMAX)) * WAVE * 4);  // touched VN per table lane
-  L.off_pbuf = L.off_jbuf = L.off_kbuf = L.off_slot = L.off_trow = o;
   L.off_lut = o; if (fixed) o = align16(o + 257 * 4);
   L.off_topo = o; o = align16(o + (int)std::max(0LL, c.topo_bytes));
-  L.off_extra = o; o = align16(o + extra_bytes);
-  L.total = o;
+  L.frame_base = o;
+  int f = 0;
+  L.off_c2v = f; if (store < STORE_ALL_GLOBAL) f = align16(f + c.E * msg);
+  L.off_pre = f; if (store == STORE_LDS) f = align16(f + c.E * msg);
+  L.off_L = f; if (store != STORE_FRAME_GLOBAL) f = align16(f + c.N * llr);
+  L.off_Lt = f; if (store < STORE_ALL_GLOBAL_LT) f = align16(f + c.N * llr);
+  L.off_D = f; if (store != STORE_FRAME_GLOBAL) f = align16(f + c.N * 4);
+  L.off_ckey = f; f = align16(f + c.M * 4);
+  L.off_dblk = f; f = align16(f + L.nbd * 8);
+  L.off_cblk = f; f = align16(f + L.nbc * 8);
+  L.off_dmask = f; f = align16(f + L.nbd_words * 4);
+  L.off_cmask = f; f = align16(f + L.nbc_words * 4);
+  L.off_syn = f; f = align16(f + ((c.M + 31) / 32) * 4);
+  L.off_v = f; f = align16(f + std::max(1, std::min(c.nbr_passes, NBR_PMAX)) * WAVE * 4);  // touched VN per table lane
+  L.off_pbuf = L.off_jbuf = L.off_kbuf = L.off_slot = L.off_trow = L.off_extra = f;
+  L.frame_stride = f;
+  L.wpb = wpb;
+  L.total = L.frame_base + wpb * f;
   return L;
 }
 
-DynLayout dyn_layout(const ldpc_code* c, bool fixed, int store, int topo, int extra_bytes) {
+DynLayout dyn_layout(const ldpc_code* c, bool fixed, int store, int topo, int wpb) {
   return dyn_layout_dims(Dims{c->E, c->N, c->M, topo_bytes(c, topo), (c->nbr_max_cnt + WAVE - 1) / WAVE}, fixed,
-                         store, extra_bytes);
+                         store, wpb);
 }
 
 
@@ -502,8 +508,8 @@ int ldpc_code_info(const ldpc_code* c, ldpc_code_stats* out) {
   out->n_layers = c->n_layers;
   out->max_touch = c->max_touch;
   const int topo = c->h_qc.empty() ? TOPO_LDS : TOPO_QC;
-  out->lds_bytes_f32 = dyn_layout(c, false, STORE_LDS, topo, 0).total;
-  out->lds_bytes_fix = dyn_layout(c, true, STORE_LDS, topo, 0).total;
+  out->lds_bytes_f32 = dyn_layout(c, false, STORE_LDS, topo, 1).total;
+  out->lds_bytes_fix = dyn_layout(c, true, STORE_LDS, topo, 1).total;
   return LDPC_OK;
 }
 
@@ -732,6 +738,15 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   // in the load round trips the update makes anyway).  Ties: for a batch that fits in one round
   // on the chip, the most state in LDS (lowest latency); otherwise all messages in global memory.
   // Topology ties: quasi-cyclic tables, then LDS copies, then global arrays.
+  // storage plan.  Every (message storage, topology source) pair that fits is scored by the frames
+  // per CU it lets the batch keep resident (at most 32, the wave slots of a CU).  More resident
+  // frames win: one update is a chain of dependent steps, so throughput comes from overlapping
+  // frames, and moving state to global memory adds little latency (both values of an edge come in
+  // the load round trips the update makes anyway).  Ties: for a batch that fits in one round on
+  // the chip, the most state in LDS (lowest latency); otherwise all messages in global memory.
+  // Topology ties: quasi-cyclic tables, then LDS copies, then global arrays.  One frame per
+  // workgroup unless the tuning asks for more (frames of a workgroup share its LDS topology copy;
+  // whether that pays depends on the code, so it is left to the autotuner).
   DynLayout Ly{};
   bool found = false;
   int best_eff = 0, best_pref = -1;
@@ -739,9 +754,11 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   const int cap_fpc = T.frames_per_cu ? T.frames_per_cu : 32;
   for (int st : stores) {
     for (int tp : topos) {
-      DynLayout cand = dyn_layout(c, fixed, st, tp, 0);
+      const int w = T.block && tp != TOPO_GLOBAL ? T.block / WAVE : 1;  // frames share LDS topology only
+      DynLayout cand = dyn_layout(c, fixed, st, tp, w);
       if (cand.total > pl.lds_limit) continue;
-      const int fit = std::max(1, (160 * 1024) / std::max(cand.total, 1));
+      const int wgs = std::max(1, (160 * 1024) / std::max(cand.total, 1));
+      const int fit = std::min(32, w * wgs);  // at most 32 wavefronts per CU
       const int eff = (int)std::min<long long>(std::min(fit, cap_fpc), need);
       // Store preference: one round on the chip: LDS > PRE_GLOBAL > ALL_GLOBAL > ALL_GLOBAL_LT >
       // FRAME_GLOBAL; larger batches: ALL_GLOBAL > ALL_GLOBAL_LT > FRAME_GLOBAL > PRE_GLOBAL > LDS
@@ -758,7 +775,30 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
         found = true;
       }
     }
-  }  if (!found) return LDPC_ECAPACITY;
+  }
+  if (!found) return LDPC_ECAPACITY;
+  // A quasi-cyclic code whose frames left the (small) QC tables for global topology: let several
+  // frames share one LDS copy of the tables if that keeps at least 90% of the residency (measured
+  // on the BG1-shaped codes: 12 frames per CU with shared tables beat 13 with global topology by
+  // 7% at Z=52; 4 against 5 lost 9% at Z=128)
+  if (!T.block && !T.topology && pl.topo == TOPO_GLOBAL && !c->h_qc.empty() && best_eff > 1) {
+    int best_w = 0, best_fit = 0;
+    DynLayout best_ly{};
+    for (int ww = 2; ww <= 16; ++ww) {
+      DynLayout cand = dyn_layout(c, fixed, pl.store, TOPO_QC, ww);
+      if (cand.total > pl.lds_limit) break;
+      const int fit = std::min(32, ww * std::max(1, (160 * 1024) / std::max(cand.total, 1)));
+      if (fit > best_fit) {
+        best_fit = fit;
+        best_w = ww;
+        best_ly = cand;
+      }
+    }
+    if (best_w && 10LL * std::min<long long>(std::min(best_fit, cap_fpc), need) >= 9LL * best_eff) {
+      Ly = best_ly;
+      pl.topo = TOPO_QC;
+    }
+  }
   P.off_c2v = Ly.off_c2v; P.off_pre = Ly.off_pre; P.off_L = Ly.off_L; P.off_Lt = Ly.off_Lt;
   P.off_D = Ly.off_D; P.off_ckey = Ly.off_ckey; P.off_dblk = Ly.off_dblk; P.off_cblk = Ly.off_cblk;
   P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
@@ -766,29 +806,34 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   P.off_pbuf = Ly.off_pbuf; P.off_jbuf = Ly.off_jbuf; P.off_topo = Ly.off_topo;
   P.off_extra = Ly.off_extra;
   P.lds_bytes = Ly.total;
+  P.frame_base = Ly.frame_base;
+  P.frame_stride = Ly.frame_stride;
+  P.wpb = Ly.wpb;
   P.nbd = Ly.nbd; P.nbc = Ly.nbc; P.nbd_words = Ly.nbd_words; P.nbc_words = Ly.nbc_words;
   P.prof = nullptr;
 #ifdef LDPC_PROFILE
   if (const char* pp = std::getenv("LDPCCI_PROF")) P.prof = (long long*)std::strtoull(pp, nullptr, 10);
 #endif
   pl.which = 1;
-  pl.block = WAVE;
+  pl.block = WAVE * P.wpb;
   // persistent grid (workers pull frames from a queue) unless one workgroup per frame fills the
   // chip in a single round and the messages stay in LDS
   pl.persistent = pl.store != STORE_LDS || T.frames_per_cu || need > 1;
+  const long long wg_needed = (B + P.wpb - 1) / P.wpb;
   if (pl.persistent) {
-    const int fit = std::max(1, (160 * 1024) / std::max(P.lds_bytes, 1));
-    const int per_cu = std::min(fit, cap_fpc);
-    pl.grid = (int)std::min<long long>(B, (long long)ncu * per_cu);
+    const int wgs = std::max(1, (160 * 1024) / std::max(P.lds_bytes, 1));
+    const int wg_per_cu = std::max(1, std::min(wgs, std::min(32, cap_fpc) / P.wpb));
+    pl.grid = (int)std::min<long long>(wg_needed, (long long)ncu * wg_per_cu);
   } else {
-    pl.grid = B;
+    pl.grid = (int)wg_needed;
   }
   const size_t msg = fixed ? 1 : 4;
+  const size_t slots = (size_t)std::max(pl.grid, 1) * P.wpb;
   if (pl.persistent) pl.scratch_bytes = kQueueBytes;  // work-queue counter, then message slots
-  if (pl.store == STORE_PRE_GLOBAL) pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * c->E * msg;
+  if (pl.store == STORE_PRE_GLOBAL) pl.scratch_bytes += slots * c->E * msg;
   if (pl.store >= STORE_ALL_GLOBAL) {
     all_global_slot(c->E, c->N, fixed, P);
-    pl.scratch_bytes += (size_t)std::max(pl.grid, 1) * (size_t)P.slot_bytes;
+    pl.scratch_bytes += slots * (size_t)P.slot_bytes;
   }
   return LDPC_OK;
 }
@@ -906,7 +951,8 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
                         LDPC_STORE_GLOBAL_FRAME})
         for (int tp : tps)
           for (int fpc : {0, 1, 2, 4, 8, 16})
-            cands.push_back(ldpc_tuning{b, fpc, store, tp});
+            for (int wb : s->kind == LDPC_ME_CIRBP ? std::vector<int>{0} : std::vector<int>{0, 256, 512})
+              cands.push_back(ldpc_tuning{s->kind == LDPC_ME_CIRBP ? b : wb, fpc, store, tp});
   }
   // outputs for the trial decodes (discarded)
   uint8_t* bits = nullptr;
@@ -1064,7 +1110,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   int store = -1, best_fit = 0;
   DynLayout Ly{};
   for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_FRAME_GLOBAL, STORE_ALL_GLOBAL_LT, STORE_ALL_GLOBAL}) {
-    DynLayout cand = dyn_layout_dims(mx, fixed, st, 0);
+    DynLayout cand = dyn_layout_dims(mx, fixed, st, 1);
     if (cand.total > lds_limit) continue;
     const int fit = std::min(32, (160 * 1024) / std::max(cand.total, 1));
     if (store < 0 || fit >= best_fit) {
@@ -1086,6 +1132,9 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
   P.off_lut = Ly.off_lut; P.off_topo = Ly.off_topo;
   P.lds_bytes = Ly.total;
+  P.frame_base = Ly.frame_base;
+  P.frame_stride = Ly.frame_stride;
+  P.wpb = 1;
   B.n_codes = n_codes;
   B.frames = reinterpret_cast<const BatchFrame*>(frames);
   B.F = F;

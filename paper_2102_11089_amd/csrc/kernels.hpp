@@ -41,6 +41,9 @@ struct DynParams {
   float scale;
   const int* lut_global;    // 257 entries (fixed point)
   void* pre_global;         // per-workgroup message slots when messages are not in LDS
+  int frame_base;           // LDS: the shared region (p0 table, topology) comes first; frame w of a
+  int frame_stride;         // workgroup starts at frame_base + w * frame_stride (frame offsets below
+  int wpb;                  // are relative to it); wpb = frames (wavefronts) per workgroup
   long long slot_bytes;     // STORE_ALL_GLOBAL and up: bytes per slot ((c2v, pre) pairs, Lt, L, D)
   int slot_lt_off;          // STORE_ALL_GLOBAL_LT and up: byte offset of Lt in a slot
   int slot_l_off;           // STORE_FRAME_GLOBAL: byte offsets of L and D in a slot
