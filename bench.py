@@ -61,14 +61,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dynamic_cirbp_bg1shaped_z52_f32
 
 def kernel_sources_digest():
     """sha256 over the HIP/C++ sources of the library (name + content, sorted by name)."""
-    import hashlib
-    csrc = os.path.join(ROOT, "paper_2102_11089_amd", "csrc")
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()
+    from paper_2102_11089_amd.build import sources_digest
+    return sources_digest()
 
 
 def measured_traffic_bytes():
@@ -462,6 +456,10 @@ def main():
     tb = measured_traffic_bytes() if (args.frames == 8192 and args.ebn0 == 1.25) else None
     traffic_gbs = round(tb / (float(np.mean(kms)) / 1e3) / 1e9, 2) if tb else None
     del rt, tr, mask
+    pd = ldpc.describe_plan(h, llr0.shape[0], ldpc.CIRBP, ldpc.SPA_F32, gamma=0.1)
+    kernel_label = (f"k_dynamic<ArithF32, {pd['storage_name']} storage, {pd['topology_name']} topology> "
+                    f"({pd['frames_per_workgroup']} frames per workgroup, {pd['workgroups_per_cu']} workgroups "
+                    f"per CU, grid {pd['grid']}{', work queue' if pd['persistent'] else ''})")
 
     out = {
         "metric": METRIC,
@@ -489,7 +487,7 @@ def main():
         # the update loop (Table 1 operations priced in bytes) are served from L2/MALL/HBM
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved_gbs / HBM_PEAK_GBS, 6), "traffic": traffic_gbs,
-                     "kernel": "k_dynamic<ArithF32, STORE_FRAME_GLOBAL, TOPO_GLOBAL> (13 frames per CU, work queue)",
+                     "kernel": kernel_label,
                      "bytes_per_update": round(bytes_per_update, 2),
                      "kernel_ms_avg": round(float(np.mean(kms)), 3),
                      "lds_frac": round(achieved_gbs / LDS_PEAK_GBS, 6)},

@@ -236,6 +236,27 @@ int ldpc_set_tuning(const ldpc_code* code, int32_t kind, int32_t arith, const ld
 /* The stored tuning (all zero if none): returns 1 if an entry exists, 0 if not, <0 on error. */
 int ldpc_get_tuning(const ldpc_code* code, int32_t kind, int32_t arith, ldpc_tuning* out);
 
+/* The launch ldpc_decode would make for B frames of this code and schedule (with the tuning stored
+   for it, if any), without decoding: for reports and for sizing.  The device must be current, as
+   for ldpc_decode.  Errors: LDPC_EINVAL (null pointer, B < 1, bad schedule), LDPC_ECAPACITY,
+   LDPC_EUNSUPPORTED (as ldpc_decode would return them), LDPC_EHIP. */
+typedef struct {
+  int32_t kernel;               /* 0 flooding / layered, 1 single-edge (RBP, CIRBP, replay), 2 ME-CIRBP */
+  int32_t storage;              /* LDPC_STORE_* chosen (never AUTO); flooding / layered: LDS           */
+  int32_t topology;             /* LDPC_TOPO_* chosen (never AUTO); flooding / layered: GLOBAL         */
+  int32_t block;                /* threads per workgroup                                               */
+  int32_t grid;                 /* workgroups launched                                                 */
+  int32_t frames_per_workgroup; /* frames one workgroup decodes at once (single-edge: its wavefronts) */
+  int32_t workgroups_per_cu;    /* workgroups a CU can hold: min(LDS / lds_bytes, 32 wavefronts)      */
+  int32_t persistent;           /* 1: fewer workgroups than frames, each takes frames in turn (single-
+                                   edge: from a device work queue)                                     */
+  int32_t lds_bytes;            /* dynamic LDS per workgroup                                           */
+  int32_t reserved;
+  int64_t scratch_bytes;        /* stream-ordered device scratch the decode allocates                 */
+} ldpc_plan_info;
+
+int ldpc_describe_plan(const ldpc_code* code, const ldpc_schedule* s, int32_t B, ldpc_plan_info* info);
+
 /* Project autotuner: times every distinct launch plan the knobs give for this schedule on the
    caller's frames (llr_in: device [B][N]; best of reps timed runs after one warm-up, HIP events on
    stream), stores the fastest with ldpc_set_tuning and returns it (best, best_ms nullable).

@@ -23,6 +23,19 @@ FLAGS = [
 ]
 
 
+def sources_digest() -> str:
+    """sha256 over the library's HIP/C++ sources (name + content, sorted by name): ties a stored
+    measurement to the code it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     """Compile every HIP source into one shared library (always recompiles)."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]

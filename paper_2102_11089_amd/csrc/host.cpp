@@ -575,18 +575,21 @@ int check_tuning(const ldpc_tuning* t) {
 
 // Validate a decode request and resolve it to a launch plan.  tune (nullable) overrides the
 // default storage / topology / launch-shape policy.
+// plan_only: shape the launch without the buffers (llr_in, out and replay may be null)
 int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B, int64_t max_updates,
                 const int32_t* replay, int64_t replay_len, const ldpc_outputs* out, const ldpc_tuning* tune,
-                DecodePlan& pl) {
+                DecodePlan& pl, bool plan_only = false) {
+  const ldpc_outputs no_out{};
+  if (plan_only && !out) out = &no_out;
   if (!c || !s || !out || B < 0 || max_updates < 0) return LDPC_EINVAL;
-  if (B > 0 && (!llr_in || !out->bits || !out->updates_used)) return LDPC_EINVAL;
+  if (!plan_only && B > 0 && (!llr_in || !out->bits || !out->updates_used)) return LDPC_EINVAL;
   if (s->kind < LDPC_FLOODING || s->kind > LDPC_REPLAY) return LDPC_EINVAL;
   if (s->arith != LDPC_SPA_F32 && s->arith != LDPC_MS_FIX) return LDPC_EINVAL;
   const bool fixed = s->arith == LDPC_MS_FIX;
   if (fixed && (s->q_bits < 2 || s->q_bits > 8 || s->frac_bits < 0 || s->frac_bits > 6)) return LDPC_EINVAL;
   if (s->check_every < 0) return LDPC_EINVAL;
   if (!(s->gamma >= 0.0f) || !std::isfinite(s->gamma)) return LDPC_EINVAL;
-  if (s->kind == LDPC_REPLAY && (!replay || replay_len < 0)) return LDPC_EINVAL;
+  if (s->kind == LDPC_REPLAY && ((!plan_only && !replay) || replay_len < 0)) return LDPC_EINVAL;
   if (s->kind == LDPC_ME_CIRBP && (s->n_p < 1 || s->n_p > 64 || s->n_g < 1 || s->n_g > 65535 ||
                                    (s->fill != LDPC_FILL_LOWEST && s->fill != LDPC_FILL_HASH)))
     return LDPC_EINVAL;
@@ -731,13 +734,6 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     float g = s->gamma;
     std::memcpy(&P.gamma_bits, &g, 4);
   }
-  // storage plan.  Every (message storage, topology source) pair that fits is scored by the frames
-  // per CU it lets the batch keep resident (at most 32, the wave slots of a CU).  More resident
-  // frames win: one update is a chain of dependent steps, so throughput comes from overlapping
-  // frames, and moving messages to global memory adds little latency (both values of an edge come
-  // in the load round trips the update makes anyway).  Ties: for a batch that fits in one round
-  // on the chip, the most state in LDS (lowest latency); otherwise all messages in global memory.
-  // Topology ties: quasi-cyclic tables, then LDS copies, then global arrays.
   // storage plan.  Every (message storage, topology source) pair that fits is scored by the frames
   // per CU it lets the batch keep resident (at most 32, the wave slots of a CU).  More resident
   // frames win: one update is a chain of dependent steps, so throughput comes from overlapping
@@ -913,6 +909,31 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   hipError_t he = enqueue_decode(c, pl, scratch, st);
   if (scratch) (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+int ldpc_describe_plan(const ldpc_code* c, const ldpc_schedule* s, int32_t B, ldpc_plan_info* info) {
+  if (!c || !s || !info || B < 1) return LDPC_EINVAL;
+  ldpc_tuning t{};
+  const bool tuned = lookup_tuning(c, s->kind, s->arith, t);
+  DecodePlan pl;
+  int rc = plan_decode(c, s, nullptr, B, 0, nullptr, 0, nullptr, tuned ? &t : nullptr, pl, true);
+  if (rc != LDPC_OK) return rc;
+  ldpc_plan_info r{};
+  r.kernel = pl.which;
+  r.storage = pl.which == 0 ? LDPC_STORE_LDS : pl.store + 1;  // Store -> LDPC_STORE_* (shifted by AUTO)
+  r.topology = pl.which == 0 ? LDPC_TOPO_GLOBAL : pl.topo + 1;
+  r.block = pl.block;
+  r.grid = pl.grid;
+  r.frames_per_workgroup = pl.which == 1 ? pl.dyn.wpb : 1;
+  const int lds = pl.which == 0 ? pl.base.lds_bytes : (pl.which == 1 ? pl.dyn.lds_bytes : pl.me.lds_bytes);
+  const int by_lds = std::max(1, (160 * 1024) / std::max(lds, 1));
+  const int by_waves = std::max(1, 32 / std::max(1, pl.block / WAVE));
+  r.workgroups_per_cu = std::min(by_lds, by_waves);
+  r.persistent = pl.which == 1 ? (pl.persistent ? 1 : 0) : (pl.which == 2 && pl.grid < B ? 1 : 0);
+  r.lds_bytes = lds;
+  r.scratch_bytes = (int64_t)pl.scratch_bytes;
+  *info = r;
+  return LDPC_OK;
 }
 
 int ldpc_set_tuning(const ldpc_code* c, int32_t kind, int32_t arith, const ldpc_tuning* t) {

@@ -27,7 +27,7 @@ ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -
           -5: "LDPC_EUNSUPPORTED"}
 
 EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode",
-           "ldpc_decode_batch", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune", "ldpc_tuning_save",
+           "ldpc_decode_batch", "ldpc_describe_plan", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune", "ldpc_tuning_save",
            "ldpc_tuning_load", "ldpc_awgn_frames", "ldpc_sweep_create", "ldpc_sweep_run", "ldpc_sweep_free",
            "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
            "ldpc_strerror", "ldpc_last_hip_error")
@@ -58,6 +58,15 @@ class ldpc_tuning(C.Structure):
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class ldpc_plan_info(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("kernel", "storage", "topology", "block", "grid", "frames_per_workgroup",
+                                          "workgroups_per_cu", "persistent", "lds_bytes", "reserved")] + \
+               [("scratch_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "reserved"}
 
 
 class ldpc_code_stats(C.Structure):
@@ -92,6 +101,8 @@ def load(path: str = LIB_PATH):
     lib.ldpc_decode_batch.argtypes = [P, C.c_int32, C.POINTER(ldpc_schedule), P, C.c_int32, P, C.c_int64, P, P,
                                       C.c_int64, P, P, P, P]
     lib.ldpc_decode_batch.restype = C.c_int
+    lib.ldpc_describe_plan.argtypes = [P, C.POINTER(ldpc_schedule), C.c_int32, C.POINTER(ldpc_plan_info)]
+    lib.ldpc_describe_plan.restype = C.c_int
     lib.ldpc_set_tuning.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(ldpc_tuning)]
     lib.ldpc_set_tuning.restype = C.c_int
     lib.ldpc_get_tuning.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(ldpc_tuning)]
@@ -179,6 +190,12 @@ def ldpc_decode_batch(handles, schedule: ldpc_schedule, frames_ptr: int, F: int,
     rc = load().ldpc_decode_batch(arr, len(handles), C.byref(schedule), frames_ptr, F, llr_ptr, llr_len, bits_ptr,
                                   llr_out_ptr, out_len, upd_ptr, steps_ptr, fall_ptr, stream)
     _check(rc, "ldpc_decode_batch")
+
+
+def ldpc_describe_plan(handle, s: ldpc_schedule, B: int) -> ldpc_plan_info:
+    info = ldpc_plan_info()
+    _check(load().ldpc_describe_plan(handle, C.byref(s), B, C.byref(info)), "ldpc_describe_plan")
+    return info
 
 
 def ldpc_set_tuning(handle, kind: int, arith: int, t: Optional[ldpc_tuning]) -> None:
@@ -449,6 +466,23 @@ def unrolled_decode(code: Code, llr, w, trace, ckpt_every: int = 32):
 def set_tuning(code: Code, kind: int, arith: int, block: int = 0, frames_per_cu: int = 0, storage: int = 0,
                topology: int = 0, clear: bool = False) -> None:
     ldpc_set_tuning(code.handle, kind, arith, None if clear else ldpc_tuning(block, frames_per_cu, storage, topology))
+
+
+STORE_NAMES = {STORE_LDS: "lds", STORE_GLOBAL: "global", STORE_GLOBAL_ALL: "global_all",
+               STORE_GLOBAL_LT: "global_lt", STORE_GLOBAL_FRAME: "global_frame"}
+TOPO_NAMES = {TOPO_GLOBAL: "global", TOPO_LDS: "lds", TOPO_QC: "qc"}
+
+
+def describe_plan(code: Code, B: int, kind: int, arith: int = SPA_F32, gamma: float = 0.1, q_bits: int = 6,
+                  frac_bits: int = 1, n_p: int = 1, n_g: int = 16, fill: int = FILL_LOWEST,
+                  check_every: int = 1) -> dict:
+    """The launch a decode of B frames would use (on the current device), as a dict; storage and
+    topology are also given by name."""
+    s = schedule(kind, arith, gamma, q_bits, frac_bits, n_p, n_g, fill, 0, check_every)
+    d = ldpc_describe_plan(code.handle, s, B).as_dict()
+    d["storage_name"] = STORE_NAMES.get(d["storage"], "?")
+    d["topology_name"] = TOPO_NAMES.get(d["topology"], "?")
+    return d
 
 
 def autotune(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int = 0, gamma: float = 0.1,

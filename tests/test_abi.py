@@ -90,3 +90,11 @@ def test_unrolled_entry_points_reject_bad_arguments():
     assert ldpc.UNROLL_MAX_CKPT_EVERY == 128
     hdr = open(HEADER).read()
     assert "#define LDPC_UNROLL_MAX_CKPT_EVERY 128" in hdr
+
+
+def test_describe_plan_rejects_bad_arguments():
+    lib = ldpc.load()
+    s = ldpc.schedule(ldpc.CIRBP)
+    info = ldpc.ldpc_plan_info()
+    assert C.sizeof(ldpc.ldpc_plan_info) == 48
+    assert lib.ldpc_describe_plan(None, C.byref(s), 8, C.byref(info)) == -1

@@ -99,3 +99,28 @@ def test_tuning_cache_round_trip(gpu, tmp_path):
         gpu.set_tuning(h, gpu.FLOODING, gpu.SPA_F32, block=100)
     with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
         gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, frames_per_cu=33)
+
+
+def test_describe_plan_follows_the_knobs(gpu):
+    code = S.workload_code("c1")  # BG1-shaped Z=52
+    h = gpu.Code(code)
+    k, a = gpu.CIRBP, gpu.SPA_F32
+    gpu.set_tuning(h, k, a, clear=True)
+    d = gpu.describe_plan(h, 8192, k, a)
+    say(f"[plan c1 8192] {d}")
+    assert d["kernel"] == 1 and d["grid"] > 0 and d["block"] == 64 * d["frames_per_workgroup"]
+    assert d["storage"] in gpu.STORE_NAMES and d["topology"] in gpu.TOPO_NAMES
+    assert d["persistent"] == 1 and d["scratch_bytes"] > 0
+    assert d["grid"] <= 256 * d["workgroups_per_cu"]
+    for st in (gpu.STORE_GLOBAL_ALL, gpu.STORE_GLOBAL_FRAME):
+        gpu.set_tuning(h, k, a, storage=st, topology=gpu.TOPO_GLOBAL)
+        e = gpu.describe_plan(h, 8192, k, a)
+        assert e["storage"] == st and e["topology"] == gpu.TOPO_GLOBAL and e["frames_per_workgroup"] == 1
+    gpu.set_tuning(h, k, a, block=256, storage=gpu.STORE_GLOBAL_FRAME, topology=gpu.TOPO_QC)
+    e = gpu.describe_plan(h, 8192, k, a)
+    assert e["frames_per_workgroup"] == 4 and e["block"] == 256 and e["topology"] == gpu.TOPO_QC
+    gpu.set_tuning(h, k, a, clear=True)
+    fl = gpu.describe_plan(h, 100, gpu.FLOODING, a)
+    assert fl["kernel"] == 0 and fl["grid"] == 100 and fl["persistent"] == 0
+    with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+        gpu.describe_plan(h, 0, k, a)
