@@ -213,6 +213,8 @@ int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t*
 #define LDPC_STORE_GLOBAL_FRAME 5 /* the whole frame (messages, precomputed and total LLRs, CIs)
                                      in a global slot; only keys and trees stay in LDS: the most
                                      frames per CU                                                */
+#define LDPC_STORE_GLOBAL_REC 6   /* as GLOBAL_FRAME, with the precomputed total, CI and total of
+                                     a VN in one 16-byte record (single-edge schedules only)      */
 #define LDPC_TOPO_AUTO 0    /* quasi-cyclic tables, else LDS copies, else global arrays       */
 #define LDPC_TOPO_GLOBAL 1
 #define LDPC_TOPO_LDS 2
@@ -263,7 +265,8 @@ int ldpc_describe_plan(const ldpc_code* code, const ldpc_schedule* s, int32_t B,
    Tune on a batch of the size that will be decoded: a small batch cannot use the frame
    residency that large batches gain from, and favours low-latency plans.
    Blocking: synchronizes stream.  Candidates: block in {64..1024} for flooding / layered;
-   storage (LDS, pre global, all messages global, messages and Lt global, whole frame global) x
+   storage (LDS, pre global, all messages global, messages and Lt global, whole frame global as
+   arrays or as VN records) x
    topology x frames per workgroup in {auto, 4, 8} x
    frames_per_cu in {auto, 1, 2, 4, 8, 16}
    (and block in {64, 256, 1024} for ME-CIRBP) for the dynamic schedules.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),

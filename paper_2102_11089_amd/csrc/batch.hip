@@ -121,7 +121,6 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
 
 template <class A, int STORE, int TOPO>
 __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
-  using msg_t = typename A::msg_t;
   const DynParams& P = B.P;
   unsigned char* lds = dyn_lds();
   const int lane = threadIdx.x;

@@ -20,6 +20,10 @@ namespace ldpc {
 
 constexpr int WAVE = 64;
 constexpr int NBR_PMAX = 8;  // two-hop neighbourhood of one VN: at most 8 passes of 64 lanes
+// VNs met twice in one VN's two-hop table (4-cycles) are summed per group: groups 0..kGroups-1 in
+// LDS, the rest (group kGroups) through atomics on Lt
+constexpr int kGroups = 7;
+constexpr int kGroupBytes = 4 * 4 * (kGroups + 1) + 16;  // sums, Lt, L, VN per group; the flag word
 
 // ------------------------------------------------------------------------------------------
 // keys and wave reductions
@@ -187,6 +191,10 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // ------------------------------------------------------------------------------------------
 // FP32 sum-product
 // ------------------------------------------------------------------------------------------
+// reciprocal from the hardware's approximate v_rcp_f32 (about 1 ulp; 1/0 = inf): the sum-product
+// terms need FP32-level relative accuracy, not a correctly rounded quotient
+__device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
+
 __device__ __forceinline__ float softplus_neg(float x) {  // log(1 + e^-x), x >= 0
   return __logf(1.0f + __expf(-x));
 }
@@ -212,7 +220,7 @@ struct ArithF32 {
   }
   __device__ __forceinline__ static float half_tanh(float x) {  // tanh(x/2), odd-exact
     float t = __expf(-fabsf(x));
-    float th = __fdividef(1.0f - t, 1.0f + t);
+    float th = (1.0f - t) * rcp_approx(1.0f + t);
     return x < 0.0f ? -th : th;
   }
   __device__ __forceinline__ uint32_t ci(val_t L, val_t Lt) const {
@@ -287,9 +295,10 @@ __device__ __forceinline__ float phi_f32(float x) {  // -log(tanh(x/2)) = log((1
   // 1 - e^-x: Taylor series below 0.25 (the subtraction would lose the low bits)
   const float ser = x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f)))));
   const float y = x < 0.25f ? ser : 1.0f - t;
-  const float lg = __logf(__fdividef(1.0f + t, y));
+  const float ry = rcp_approx(y);
+  const float lg = __logf((1.0f + t) * ry);
   // above 4 the quotient is 1 + w, w = 2t/(1-t) < 0.04: log(1 + w) by its series
-  const float w = __fdividef(2.0f * t, y);
+  const float w = (2.0f * t) * ry;
   const float lp = w * (1.0f - w * (0.5f - w * (1.0f / 3.0f - w * 0.25f)));
   return x > 4.0f ? lp : lg;
 }
@@ -381,7 +390,8 @@ struct DevCode {
   DevQC qc;              // valid when qc.Z > 0
   // two-hop neighbourhood table: for VN n, nbr[off(n) .. off(n) + cnt(n)) lists every edge of every
   // check of n, each check in an aligned block of 2^L lanes (largest blocks first, padding entries
-  // have e = -1).  Entry = (edge id, VN | L << 24 | leader << 27).
+  // have e = -1).  Entry = (edge id, VN | L << 24 | leader << 27 | twice << 28 | group << 29);
+  // twice marks a VN other than n that lies on more than one check of n, group numbers such VNs.
   const int2* nbr;
   const int2* nbr_idx;   // [N] (off, cnt)
   const int2* nbr_col;   // quasi-cyclic codes: [nb] (off of VN j Z, cnt) -- off(n) = off + (n mod Z) cnt

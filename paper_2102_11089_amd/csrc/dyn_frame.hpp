@@ -33,10 +33,12 @@ __device__ __forceinline__ size_t frame_slot(const DynParams& P) {
   return (size_t)blockIdx.x * (size_t)P.wpb + (size_t)wave_in_group();
 }
 
-// Where a frame's C2V messages (c2v), precomputed messages (pre) and precomputed totals (Lt)
-// live: all in LDS; pre in a global scratch slot; c2v and pre as interleaved (c2v, pre) pairs (one
-// load brings the two values of an edge) in a global slot per workgroup; or those pairs followed
-// by Lt in the slot.
+// Where a frame's state lives.  C2V messages (c2v), precomputed messages (pre), precomputed totals
+// (Lt), totals (L) and CIs (D): all in LDS; pre in a global scratch slot; c2v and pre as
+// interleaved (c2v, pre) pairs (one load brings the two values of an edge) in a global slot; those
+// pairs followed by Lt in the slot; the whole frame in the slot (Lt, L and D as arrays, or as one
+// 16-byte record per VN).  A frame is read and written by its own wavefront only, so lanes
+// exchange values through global memory under the wavefront's program order (wave_sync).
 template <class A, int STORE, bool PAIRS = (STORE >= STORE_ALL_GLOBAL)>
 struct MsgStore {
   using msg_t = typename A::msg_t;
@@ -44,6 +46,8 @@ struct MsgStore {
   msg_t* c2v;  // LDS
   msg_t* pre;  // LDS (STORE_LDS) or global (STORE_PRE_GLOBAL)
   llr_t* Lt;   // LDS
+  llr_t* Lp;   // LDS
+  uint32_t* Dp;
   __device__ __forceinline__ msg_t c(int e) const { return c2v[e]; }
   __device__ __forceinline__ msg_t p(int e) const { return pre[e]; }
   __device__ __forceinline__ void set_c(int e, msg_t v) const { c2v[e] = v; }
@@ -55,6 +59,18 @@ struct MsgStore {
   __device__ __forceinline__ llr_t lt(int n) const { return Lt[n]; }
   __device__ __forceinline__ void set_lt(int n, llr_t v) const { Lt[n] = v; }
   __device__ __forceinline__ void add_lt(int n, llr_t d) const { atomicAdd(&Lt[n], d); }
+  __device__ __forceinline__ llr_t l(int n) const { return Lp[n]; }
+  __device__ __forceinline__ void set_l(int n, llr_t v) const { Lp[n] = v; }
+  __device__ __forceinline__ uint32_t d(int n) const { return Dp[n]; }
+  __device__ __forceinline__ void set_d(int n, uint32_t v) const { Dp[n] = v; }
+  __device__ __forceinline__ void lt_l(int n, llr_t& ltv, llr_t& lv) const {
+    ltv = Lt[n];
+    lv = Lp[n];
+  }
+  __device__ __forceinline__ void set_lt_d(int n, llr_t ltv, uint32_t dv) const {
+    Lt[n] = ltv;
+    Dp[n] = dv;
+  }
 };
 
 template <class msg_t>
@@ -62,14 +78,26 @@ struct alignas(2 * sizeof(msg_t)) MsgPair {
   msg_t c, p;
 };
 
+// per-VN record of STORE_FRAME_REC: (Lt, D) first so that the pair written after a row update is
+// one aligned 8-byte store
+template <class llr_t>
+struct alignas(16) VnRec {
+  llr_t lt;
+  uint32_t d;
+  llr_t l;
+  uint32_t pad;
+};
+
 template <class A, int STORE>
 struct MsgStore<A, STORE, true> {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
+  static constexpr bool kRec = STORE == STORE_FRAME_REC;
   MsgPair<msg_t>* m;  // global, [E]
   llr_t* Lt;          // LDS (STORE_ALL_GLOBAL) or global, [N]
-  llr_t* Lg;          // STORE_FRAME_GLOBAL: L and D in the slot, [N]
-  uint32_t* Dg;
+  llr_t* Lp;          // LDS, or global (STORE_FRAME_GLOBAL), [N]
+  uint32_t* Dp;
+  VnRec<llr_t>* r;    // STORE_FRAME_REC, [N]
   __device__ __forceinline__ msg_t c(int e) const { return m[e].c; }
   __device__ __forceinline__ msg_t p(int e) const { return m[e].p; }
   __device__ __forceinline__ void set_c(int e, msg_t v) const { m[e].c = v; }
@@ -79,9 +107,56 @@ struct MsgStore<A, STORE, true> {
     cv = x.c;
     pv = x.p;
   }
-  __device__ __forceinline__ llr_t lt(int n) const { return Lt[n]; }
-  __device__ __forceinline__ void set_lt(int n, llr_t v) const { Lt[n] = v; }
-  __device__ __forceinline__ void add_lt(int n, llr_t d) const { atomicAdd(&Lt[n], d); }
+  __device__ __forceinline__ llr_t lt(int n) const {
+    if constexpr (kRec) return r[n].lt;
+    else return Lt[n];
+  }
+  __device__ __forceinline__ void set_lt(int n, llr_t v) const {
+    if constexpr (kRec) r[n].lt = v;
+    else Lt[n] = v;
+  }
+  __device__ __forceinline__ void add_lt(int n, llr_t d) const {
+    if constexpr (kRec) atomicAdd(&r[n].lt, d);
+    else atomicAdd(&Lt[n], d);
+  }
+  __device__ __forceinline__ llr_t l(int n) const {
+    if constexpr (kRec) return r[n].l;
+    else return Lp[n];
+  }
+  __device__ __forceinline__ void set_l(int n, llr_t v) const {
+    if constexpr (kRec) r[n].l = v;
+    else Lp[n] = v;
+  }
+  __device__ __forceinline__ uint32_t d(int n) const {
+    if constexpr (kRec) return r[n].d;
+    else return Dp[n];
+  }
+  __device__ __forceinline__ void set_d(int n, uint32_t v) const {
+    if constexpr (kRec) r[n].d = v;
+    else Dp[n] = v;
+  }
+  __device__ __forceinline__ void lt_l(int n, llr_t& ltv, llr_t& lv) const {
+    if constexpr (kRec) {
+      const VnRec<llr_t> x = r[n];  // one 16-byte load
+      ltv = x.lt;
+      lv = x.l;
+    } else {
+      ltv = Lt[n];
+      lv = Lp[n];
+    }
+  }
+  __device__ __forceinline__ void set_lt_d(int n, llr_t ltv, uint32_t dv) const {
+    if constexpr (kRec) {
+      struct alignas(8) LtD {
+        llr_t lt;
+        uint32_t d;
+      };
+      *reinterpret_cast<LtD*>(&r[n]) = LtD{ltv, dv};
+    } else {
+      Lt[n] = ltv;
+      Dp[n] = dv;
+    }
+  }
 };
 
 // message store of the workgroup's frame slot (slot_edges = edges reserved per workgroup when
@@ -92,41 +167,34 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
   using llr_t = typename A::llr_t;
   unsigned char* lds = frame_lds(P);
   MsgStore<A, STORE> ms;
+  ms.Lp = reinterpret_cast<llr_t*>(lds + P.off_L);
+  ms.Dp = reinterpret_cast<uint32_t*>(lds + P.off_D);
+  ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
   if constexpr (STORE >= STORE_ALL_GLOBAL) {
     unsigned char* base = reinterpret_cast<unsigned char*>(P.pre_global) + frame_slot(P) * (size_t)P.slot_bytes;
     ms.m = reinterpret_cast<MsgPair<msg_t>*>(base);
-    if constexpr (STORE >= STORE_ALL_GLOBAL_LT) ms.Lt = reinterpret_cast<llr_t*>(base + P.slot_lt_off);
-    else ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
+    ms.r = nullptr;
+    if constexpr (STORE == STORE_ALL_GLOBAL_LT || STORE == STORE_FRAME_GLOBAL)
+      ms.Lt = reinterpret_cast<llr_t*>(base + P.slot_lt_off);
     if constexpr (STORE == STORE_FRAME_GLOBAL) {
-      ms.Lg = reinterpret_cast<llr_t*>(base + P.slot_l_off);
-      ms.Dg = reinterpret_cast<uint32_t*>(base + P.slot_d_off);
+      ms.Lp = reinterpret_cast<llr_t*>(base + P.slot_l_off);
+      ms.Dp = reinterpret_cast<uint32_t*>(base + P.slot_d_off);
     }
+    if constexpr (STORE == STORE_FRAME_REC) ms.r = reinterpret_cast<VnRec<llr_t>*>(base + P.slot_lt_off);
   } else {
     ms.c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
-    ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
     if constexpr (STORE == STORE_PRE_GLOBAL) ms.pre = reinterpret_cast<msg_t*>(P.pre_global) + frame_slot(P) * slot_edges;
     else ms.pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
   }
   return ms;
 }
 
-// total LLRs L and CIs D of the frame: in LDS, or in the global slot (STORE_FRAME_GLOBAL)
+// total LLRs of the frame as one array (flooding / layered frames of the batched kernel; not
+// available in the record layout)
 template <class A, int STORE>
-__device__ __forceinline__ typename A::llr_t* frame_L(const MsgStore<A, STORE>& ms, const DynParams& P) {
-  if constexpr (STORE == STORE_FRAME_GLOBAL) return ms.Lg;
-  else return reinterpret_cast<typename A::llr_t*>(frame_lds(P) + P.off_L);
-}
-template <class A, int STORE>
-__device__ __forceinline__ uint32_t* frame_D(const MsgStore<A, STORE>& ms, const DynParams& P) {
-  if constexpr (STORE == STORE_FRAME_GLOBAL) return ms.Dg;
-  else return reinterpret_cast<uint32_t*>(frame_lds(P) + P.off_D);
-}
-// ordering point for values exchanged between lanes through the frame store: a workgroup-scope
-// fence (wait for global stores) when the exchanged array lives in global memory
-template <bool GLOBAL>
-__device__ __forceinline__ void frame_sync() {
-  if constexpr (GLOBAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  wave_sync();
+__device__ __forceinline__ typename A::llr_t* frame_L(const MsgStore<A, STORE>& ms, const DynParams&) {
+  static_assert(STORE != STORE_FRAME_REC, "no L array in the record layout");
+  return ms.Lp;
 }
 
 // value of another lane (the lane index is wave-uniform)
@@ -134,6 +202,17 @@ template <class T>
 __device__ __forceinline__ T lane_value(T x, int l) {
   if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
   else return (T)__builtin_amdgcn_readlane((int)x, l);
+}
+
+// Block-maximum maintenance after the leaf key of index i in block b moved from its old value to
+// nk: a larger key raises the block maximum; a smaller one marks the block for recomputation if
+// i held the maximum (a maximum key carries its index, so the old value is not needed).  Lanes
+// racing on one block in one instruction stay correct in either order: a raise by another lane
+// only makes the old maximum irrelevant, and a marked block is recomputed from the leaves.
+__device__ __forceinline__ void leaf_moved(uint64_t* blk, uint32_t* mask, int b, uint32_t i, uint64_t nk) {
+  const uint64_t cur = blk[b];
+  if (nk > cur) atomicMax(reinterpret_cast<unsigned long long*>(&blk[b]), (unsigned long long)nk);
+  else if (nk < cur && key_idx(cur) == i) atomicOr(&mask[b >> 5], 1u << (b & 31));
 }
 
 template <class A, int STORE, class Topo>
@@ -145,9 +224,6 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   using Acc = typename RowAccOf<A>::type;
   const int lane = threadIdx.x & (WAVE - 1);
   unsigned char* lds = frame_lds(P);
-  llr_t* L = frame_L(ms, P);
-  uint32_t* D = frame_D(ms, P);
-  constexpr bool kLDG = STORE == STORE_FRAME_GLOBAL;  // L and D in global memory
   // per check: the largest residual of its edges (value bits); block keys pair it with the check
   // index, and the edge is found again inside the check's row when the check is selected (edge ids
   // are row-major, so (value, lowest check), then (value, lowest edge) in the row is the global
@@ -158,19 +234,28 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   uint32_t* dmask = reinterpret_cast<uint32_t*>(lds + P.off_dmask);
   uint32_t* cmask = reinterpret_cast<uint32_t*>(lds + P.off_cmask);
   uint32_t* synw = reinterpret_cast<uint32_t*>(lds + P.off_syn);  // syndrome bits
-  int* tj = reinterpret_cast<int*>(lds + P.off_v);  // touched VN of each table lane, per pass
+  int* tj = reinterpret_cast<int*>(lds + P.off_v);  // VN of a table lane whose CI is refreshed late
+  // VNs met twice in the two-hop table: per group, the sum of this update's Lt changes, the VN's
+  // Lt and L before the update, the VN; a flag word of the groups changed
+  llr_t* gacc = reinterpret_cast<llr_t*>(lds + P.off_grp);
+  llr_t* glt = gacc + (kGroups + 1);
+  llr_t* gl = glt + (kGroups + 1);
+  int* gj = reinterpret_cast<int*>(gl + (kGroups + 1));
+  uint32_t* gflag = reinterpret_cast<uint32_t*>(gj + (kGroups + 1));
   const int N = H.N, M = H.M, E = H.E;
   const int nbd = (N + WAVE - 1) / WAVE, nbc = (M + WAVE - 1) / WAVE;
   const int nbd_words = (nbd + 31) / 32, nbc_words = (nbc + 31) / 32;
   const bool with_ci = J.kind != KIND_RBP;
   // ---------------- Algorithm 1 lines 1-3: initial state --------------------------------
   const float* llr = J.llr;
-  for (int n = lane; n < N; n += WAVE) L[n] = (llr_t)ar.channel(llr[n]);
+  for (int n = lane; n < N; n += WAVE) ms.set_l(n, (llr_t)ar.channel(llr[n]));
   for (int e = lane; e < E; e += WAVE) ms.set_c(e, (msg_t)0);
   for (int w = lane; w < nbd_words; w += WAVE) dmask[w] = 0u;
   for (int w = lane; w < nbc_words; w += WAVE) cmask[w] = 0u;
   for (int w = lane; w < (M + 31) / 32; w += WAVE) synw[w] = 0u;
-  frame_sync<kLDG>();
+  if (lane <= kGroups) gacc[lane] = (llr_t)0;
+  if (lane == 0) *gflag = 0u;
+  wave_sync();
   // every precomputed C2V message from V2C = channel value: one lane per check row
   int unsat_local = 0;
   for (int m = lane; m < M; m += WAVE) {
@@ -178,14 +263,14 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     Acc acc;
     int par = 0;
     for (int p = 0; p < dc; ++p) {
-      const val_t l = (val_t)L[G.row_vn(m, rs, p)];
+      const val_t l = (val_t)ms.l(G.row_vn(m, rs, p));
       const val_t v = ar.vin(l);
       acc.add(p, v, row_aux(ar, v));
       par ^= l < 0 ? 1 : 0;
     }
     uint64_t k = 0;
     for (int p = 0; p < dc; ++p) {
-      const val_t v = ar.vin((val_t)L[G.row_vn(m, rs, p)]);
+      const val_t v = ar.vin((val_t)ms.l(G.row_vn(m, rs, p)));
       const val_t o = acc.out(p, v, row_aux(ar, v));
       ms.set_p(rs + p, (msg_t)o);
       k = umax64(k, mkkey(ar.res(o, (val_t)0), (uint32_t)(rs + p)));
@@ -195,23 +280,22 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     unsat_local += par;
   }
   int unsat = wave_sum_i32(unsat_local);
-  if constexpr (STORE != STORE_LDS) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // message stores done
   wave_sync();
   for (int n = lane; n < N; n += WAVE) {
-    val_t lt = (val_t)L[n];
+    const val_t l = (val_t)ms.l(n);
+    val_t lt = l;
     const int dv = G.vn_deg(n);
     for (int k = 0; k < dv; ++k) {
       int m, e;
       G.vn_edge(n, k, m, e);
       lt += (val_t)ms.p(e);
     }
-    ms.set_lt(n, (llr_t)lt);
-    D[n] = with_ci ? ar.ci((val_t)L[n], lt) : 0u;
+    ms.set_lt_d(n, (llr_t)lt, with_ci ? ar.ci(l, lt) : 0u);
   }
-  frame_sync<kLDG>();
+  wave_sync();
   for (int b = 0; b < nbd; ++b) {
     const int n = b * WAVE + lane;
-    uint64_t k = n < N ? mkkey(D[n], (uint32_t)n) : 0ull;
+    uint64_t k = n < N ? mkkey(ms.d(n), (uint32_t)n) : 0ull;
     k = wave_max_u64(k);
     if (lane == 0) dblk[b] = k;
   }
@@ -309,9 +393,10 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     const int rs_m = uni(G.row_start(mstar));
     const int re_m = rs_m + uni(G.row_deg(mstar));
     // Inputs of the touched-check passes are loaded ahead of use: table entries two passes ahead,
-    // message pairs and L one pass ahead.  Nothing a pass writes (its own checks' pre, Lt, keys)
-    // is read by a later pass, propagation changes only c2v[e*] and L[n*] (both overridden where
-    // used), so the early loads see the values the passes need.
+    // message pairs, L and Lt one pass ahead.  Nothing a pass writes is read by a later pass
+    // except Lt of a VN listed twice in the two-hop table (such VNs take the atomic path below and
+    // do not use the early value), and propagation changes only c2v[e*] and L[n*] (both
+    // overridden where used), so the early loads see the values the passes need.
     auto load_ent = [&](int ps) -> int2 {
       const int idx = ps * WAVE + lane;
       return idx < ncnt ? H.nbr[noff + idx] : make_int2(-1, 0);
@@ -319,7 +404,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     struct PassIn {
       int2 ent;
       msg_t cm, pm;
-      llr_t lj;
+      llr_t lj, ltj;
     };
     auto load_in = [&](int2 ent) -> PassIn {
       PassIn q;
@@ -327,9 +412,12 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       q.cm = (msg_t)0;
       q.pm = (msg_t)0;
       q.lj = (llr_t)0;
+      q.ltj = (llr_t)0;
       if (ent.x >= 0) {
         ms.cp(ent.x, q.cm, q.pm);
-        q.lj = L[ent.y & 0xFFFFFF];
+        const int j = ent.y & 0xFFFFFF;
+        if (with_ci) ms.lt_l(j, q.ltj, q.lj);
+        else q.lj = ms.l(j);
       }
       return q;
     };
@@ -341,19 +429,19 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     PassIn in_cur = load_in(ent0);
     const val_t newv = (val_t)p_star;
     const val_t oldv = (val_t)c_star;
-    const val_t Lold = (val_t)L[nstar];
+    llr_t lt_n = (llr_t)0, l_n;
+    if (with_ci) ms.lt_l(nstar, lt_n, l_n);
+    else l_n = ms.l(nstar);
+    const val_t Lold = (val_t)l_n;
     const val_t Lnew = Lold + (newv - oldv);
-    const uint32_t dn_old = D[nstar];
-    const uint32_t dn_new = with_ci ? ar.ci(Lnew, (val_t)ms.lt(nstar)) : 0u;
+    const uint32_t dn_new = with_ci ? ar.ci(Lnew, (val_t)lt_n) : 0u;
     wave_sync();
     if (lane == 0) {
       ms.set_c(estar, (msg_t)newv);
-      L[nstar] = (llr_t)Lnew;
+      ms.set_l(nstar, (llr_t)Lnew);
       if (with_ci) {
-        D[nstar] = dn_new;
-        const uint64_t nk = mkkey(dn_new, (uint32_t)nstar), ok = mkkey(dn_old, (uint32_t)nstar);
-        if (nk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&dblk[nstar >> 6]), (unsigned long long)nk);
-        else if (nk < ok && dblk[nstar >> 6] == ok) atomicOr(&dmask[(nstar >> 6) >> 5], 1u << ((nstar >> 6) & 31));
+        ms.set_d(nstar, dn_new);
+        leaf_moved(dblk, dmask, nstar >> 6, (uint32_t)nstar, mkkey(dn_new, (uint32_t)nstar));
       }
     }
     if ((Lold < 0) != (Lnew < 0)) {  // hard decision flipped: toggle the checks of n*
@@ -368,9 +456,11 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     wave_sync();
     PROF_MARK(1)
 
-    // ---- touched checks: V2C inputs, whole-row update, residual keys (one pass per 64 lanes) ----
+    // ---- touched checks: V2C inputs, whole-row update, residual keys, and the CI of every VN
+    //      listed once in the table (Algorithm 1 lines 10-13; one pass per 64 lanes) ----
+    bool late_ci = false;  // a VN of the overflow group was updated: its CI is refreshed after the passes
     for (int ps = 0; ps < npass; ++ps) {
-      PassIn in_next{make_int2(-1, 0), (msg_t)0, (msg_t)0, (llr_t)0};
+      PassIn in_next{make_int2(-1, 0), (msg_t)0, (msg_t)0, (llr_t)0, (llr_t)0};
       int2 ent_after = make_int2(-1, 0);
       if (ps + 1 < npass) in_next = load_in(ent_next);
       if (ps + 2 < npass) ent_after = load_ent(ps + 2);
@@ -380,6 +470,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       const int j = ent.y & 0xFFFFFF;
       const int L2 = (ent.y >> 24) & 7;
       const bool leader = valid && ((ent.y >> 27) & 1);
+      const bool twice = (ent.y >> 28) & 1;
+      const int grp = (ent.y >> 29) & 7;
       const bool in_m = valid && e >= rs_m && e < re_m;
       const bool self = valid && j == nstar;
       val_t cv = 0, po = 0, lv = 0;
@@ -416,44 +508,71 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       }
       if (upd) {
         ms.set_p(e, (msg_t)pv);
-        if (with_ci) ms.add_lt(j, (llr_t)(pv - po));
+        if (with_ci) {
+          const val_t dlt = pv - po;
+          if (!twice) {  // the only change of Lt_j in this update: new Lt_j and D_j right here
+            const val_t ltn = (val_t)in_cur.ltj + dlt;
+            const uint32_t nd = ar.ci(lv, ltn);
+            ms.set_lt_d(j, (llr_t)ltn, nd);
+            leaf_moved(dblk, dmask, j >> 6, (uint32_t)j, mkkey(nd, (uint32_t)j));
+          } else if (grp < kGroups) {  // summed in LDS; Lt_j itself is untouched until the passes end
+            atomicAdd(&gacc[grp], (llr_t)dlt);
+            gj[grp] = j;
+            glt[grp] = in_cur.ltj;
+            gl[grp] = (llr_t)lv;
+            atomicOr(gflag, 1u << grp);
+          } else {
+            ms.add_lt(j, (llr_t)dlt);
+          }
+        }
       }
-      tj[ps * WAVE + lane] = upd ? j : -1;
+      const bool late = with_ci && upd && twice && grp == kGroups;
+      tj[ps * WAVE + lane] = late ? j : -1;
+      late_ci = late_ci || __ballot(late) != 0ull;
       const uint64_t rk = keymax_all(valid ? mkkey(ar.res(pv, cv), (uint32_t)e) : 0ull, L2, maxL2);
       if (leader) {  // one lane per check: new residual key, block maximum
         const int m = G.edge_row(e);
-        const uint32_t ov = ckey[m];
         ckey[m] = key_val(rk);
-        const uint64_t nk = mkkey(key_val(rk), (uint32_t)m), ok = mkkey(ov, (uint32_t)m);
-        if (nk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&cblk[m >> 6]), (unsigned long long)nk);
-        else if (nk < ok && cblk[m >> 6] == ok) atomicOr(&cmask[(m >> 6) >> 5], 1u << ((m >> 6) & 31));
+        leaf_moved(cblk, cmask, m >> 6, (uint32_t)m, mkkey(key_val(rk), (uint32_t)m));
       }
       in_cur = in_next;
       ent_next = ent_after;
     }
-    if constexpr (STORE != STORE_LDS) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // message stores done
     wave_sync();
     PROF_MARK(3)
-    // ---- CI of the VNs of the touched checks (Algorithm 1 line 12) ----
-    if (with_ci) {
+    // ---- VNs listed twice: Lt_j plus the summed changes, then D_j ----
+    const uint32_t gf = (uint32_t)uni((int)*gflag);
+    if (gf) {
+      if (lane < kGroups && ((gf >> lane) & 1u)) {
+        const val_t ltn = (val_t)glt[lane] + (val_t)gacc[lane];
+        const int jg = gj[lane];
+        const uint32_t nd = ar.ci((val_t)gl[lane], ltn);
+        ms.set_lt_d(jg, (llr_t)ltn, nd);
+        leaf_moved(dblk, dmask, jg >> 6, (uint32_t)jg, mkkey(nd, (uint32_t)jg));
+        gacc[lane] = (llr_t)0;
+      }
+      wave_sync();
+      if (lane == 0) *gflag = 0u;
+      wave_sync();
+    }
+    // ---- CI of the VNs of the overflow group (their Lt took several atomic additions) ----
+    if (late_ci) {
       for (int ps = 0; ps < npass; ++ps) {
         const int j = tj[ps * WAVE + lane];
-        uint32_t nd = 0, od = 0;
+        uint32_t nd = 0;
         if (j >= 0) {
-          nd = ar.ci((val_t)L[j], (val_t)ms.lt(j));
-          od = D[j];
+          llr_t ltv, lv;
+          ms.lt_l(j, ltv, lv);
+          nd = ar.ci((val_t)lv, (val_t)ltv);
         }
         wave_sync();
         if (j >= 0) {
-          D[j] = nd;
-          const uint64_t nk = mkkey(nd, (uint32_t)j), ok = mkkey(od, (uint32_t)j);
-          if (nk > ok) atomicMax(reinterpret_cast<unsigned long long*>(&dblk[j >> 6]), (unsigned long long)nk);
-          else if (nk < ok && dblk[j >> 6] == ok) atomicOr(&dmask[(j >> 6) >> 5], 1u << ((j >> 6) & 31));
+          ms.set_d(j, nd);
+          leaf_moved(dblk, dmask, j >> 6, (uint32_t)j, mkkey(nd, (uint32_t)j));
         }
         wave_sync();
       }
     }
-    if constexpr (kLDG) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // D stores done
     PROF_MARK(5)
     // ---- blocks whose maximum leaf decreased ----
     for (int w = 0; w < nbc_words; ++w) {
@@ -475,7 +594,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
           const int b = w * 32 + __builtin_ctz(bits);
           bits &= bits - 1;
           const int n = b * WAVE + lane;
-          uint64_t k = n < N ? mkkey(D[n], (uint32_t)n) : 0ull;
+          uint64_t k = n < N ? mkkey(ms.d(n), (uint32_t)n) : 0ull;
           k = wave_max_u64(k);
           if (lane == 0) dblk[b] = k;
         }
@@ -498,12 +617,12 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
 
   // ---------------- outputs -----------------------------------------------------------
   for (int n = lane; n < N; n += WAVE) {
-    const val_t l = (val_t)L[n];
+    const val_t l = (val_t)ms.l(n);
     J.bits[n] = l < 0 ? 1 : 0;
     if (J.llr_out) J.llr_out[n] = ar.out_llr(l);
     if (J.dump_L) J.dump_L[n] = ar.as_float(l);
     if (J.dump_Lt) J.dump_Lt[n] = ar.as_float((val_t)ms.lt(n));
-    if (J.dump_D) J.dump_D[n] = ar.d_float(D[n]);
+    if (J.dump_D) J.dump_D[n] = ar.d_float(ms.d(n));
   }
   for (int e = lane; e < E; e += WAVE) {
     if (J.dump_c2v) J.dump_c2v[e] = ar.as_float((val_t)ms.c(e));

@@ -32,7 +32,6 @@ namespace ldpc {
 // which lets the compiler keep the register count at the level of full occupancy
 template <class A, int STORE, int TOPO, bool MF>
 __global__ __launch_bounds__(MF ? 1024 : WAVE) void k_dynamic(DevCode H, DynParams P) {
-  using msg_t = typename A::msg_t;
   unsigned char* lds = dyn_lds();
   const int lane = threadIdx.x & (WAVE - 1);
   const auto ms = make_store<A, STORE>(P, (size_t)H.E);
@@ -96,6 +95,7 @@ static hipError_t launch_dyn_t(const DevCode& H, const DynParams& P, int topo, i
 
 template <class A>
 static hipError_t launch_dyn_s(const DevCode& H, const DynParams& P, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_FRAME_REC) return launch_dyn_t<A, STORE_FRAME_REC>(H, P, topo, grid, st);
   if (store == STORE_FRAME_GLOBAL) return launch_dyn_t<A, STORE_FRAME_GLOBAL>(H, P, topo, grid, st);
   if (store == STORE_ALL_GLOBAL_LT) return launch_dyn_t<A, STORE_ALL_GLOBAL_LT>(H, P, topo, grid, st);
   if (store == STORE_ALL_GLOBAL) return launch_dyn_t<A, STORE_ALL_GLOBAL>(H, P, topo, grid, st);
@@ -132,7 +132,8 @@ hipError_t set_dynamic_lds_limit(int bytes) {
                        set_store<ArithF32, STORE_ALL_GLOBAL>(bytes), set_store<ArithF32, STORE_ALL_GLOBAL_LT>(bytes),
                        set_store<ArithF32, STORE_FRAME_GLOBAL>(bytes), set_store<ArithFix, STORE_LDS>(bytes),
                        set_store<ArithFix, STORE_PRE_GLOBAL>(bytes), set_store<ArithFix, STORE_ALL_GLOBAL>(bytes),
-                       set_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes), set_store<ArithFix, STORE_FRAME_GLOBAL>(bytes)})
+                       set_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes), set_store<ArithFix, STORE_FRAME_GLOBAL>(bytes),
+                       set_store<ArithF32, STORE_FRAME_REC>(bytes), set_store<ArithFix, STORE_FRAME_REC>(bytes)})
     if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }

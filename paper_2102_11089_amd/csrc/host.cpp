@@ -92,7 +92,7 @@ double round_half_away(double x) { return x < 0 ? -std::floor(-x + 0.5) : std::f
 // LDS layout of the single-edge / multi-edge dynamic decoders
 struct DynLayout {
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_ckey, off_dblk, off_cblk, off_dmask, off_cmask, off_syn;
-  int off_v, off_pbuf, off_jbuf, off_kbuf, off_slot, off_trow, off_lut, off_topo, off_extra, total;
+  int off_v, off_grp, off_lut, off_topo, total;
   int nbd, nbc, nbd_words, nbc_words;
   int frame_base, frame_stride, wpb;  // shared region, then wpb frame regions of frame_stride bytes
 };
@@ -116,7 +116,7 @@ struct Dims {
 // LDS of the single-edge kernels for wpb frames per workgroup: a shared region (p0 table in fixed
 // point, topology tables) followed by wpb frame regions.  Frame arrays by storage mode: STORE_LDS
 // c2v, pre, Lt, L, D; STORE_PRE_GLOBAL c2v, Lt, L, D; STORE_ALL_GLOBAL Lt, L, D; STORE_ALL_GLOBAL_LT
-// L, D; STORE_FRAME_GLOBAL none of them; always the check keys, block maxima, dirty masks,
+// L, D; STORE_FRAME_GLOBAL and STORE_FRAME_REC none of them; always the check keys, block maxima, dirty masks,
 // syndrome bits and the two-hop staging.  Frame offsets are relative to the frame's region.
 DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int wpb) {
   DynLayout L{};
@@ -132,9 +132,10 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int wpb) {
   int f = 0;
   L.off_c2v = f; if (store < STORE_ALL_GLOBAL) f = align16(f + c.E * msg);
   L.off_pre = f; if (store == STORE_LDS) f = align16(f + c.E * msg);
-  L.off_L = f; if (store != STORE_FRAME_GLOBAL) f = align16(f + c.N * llr);
+  const bool frame = store == STORE_FRAME_GLOBAL || store == STORE_FRAME_REC;
+  L.off_L = f; if (!frame) f = align16(f + c.N * llr);
   L.off_Lt = f; if (store < STORE_ALL_GLOBAL_LT) f = align16(f + c.N * llr);
-  L.off_D = f; if (store != STORE_FRAME_GLOBAL) f = align16(f + c.N * 4);
+  L.off_D = f; if (!frame) f = align16(f + c.N * 4);
   L.off_ckey = f; f = align16(f + c.M * 4);
   L.off_dblk = f; f = align16(f + L.nbd * 8);
   L.off_cblk = f; f = align16(f + L.nbc * 8);
@@ -142,7 +143,7 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int wpb) {
   L.off_cmask = f; f = align16(f + L.nbc_words * 4);
   L.off_syn = f; f = align16(f + ((c.M + 31) / 32) * 4);
   L.off_v = f; f = align16(f + std::max(1, std::min(c.nbr_passes, NBR_PMAX)) * WAVE * 4);  // touched VN per table lane
-  L.off_pbuf = L.off_jbuf = L.off_kbuf = L.off_slot = L.off_trow = L.off_extra = f;
+  L.off_grp = f; f = align16(f + kGroupBytes);  // sums for VNs met twice in a two-hop table
   L.frame_stride = f;
   L.wpb = wpb;
   L.total = L.frame_base + wpb * f;
@@ -302,7 +303,8 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
     c->max_layer_edges = std::max(c->max_layer_edges, row_ptr[lp[l + 1]] - row_ptr[lp[l]]);
   // two-hop neighbourhood table: per VN, every check of the VN as an aligned power-of-two block
   // of lanes (largest first, so every block starts at a multiple of its size), in VN order
-  std::vector<int> nbr, nbr_idx(2 * (size_t)N);
+  std::vector<int> nbr, nbr_idx(2 * (size_t)N), seen(N, 0), group(N, -1);
+  int next_group = 0;
   c->nbr_max_cnt = 0;
   for (int n = 0; n < N; ++n) {
     std::vector<std::pair<int, int>> blocks;  // (log2 size, check)
@@ -314,6 +316,10 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
     }
     std::stable_sort(blocks.begin(), blocks.end(), [](auto& a, auto& b) { return a.first > b.first; });
     const int off = (int)(nbr.size() / 2);
+    // VNs other than n met in more than one check of n (4-cycles through n): flagged, because the
+    // kernels then sum several changes into their Lt
+    for (auto& bk : blocks)
+      for (int x = row_ptr[bk.second]; x < row_ptr[bk.second + 1]; ++x) seen[col_idx[x]] += 1;
     for (auto& bk : blocks) {
       const int l2 = bk.first, m = bk.second, rs = row_ptr[m], dc = row_ptr[m + 1] - rs;
       if (l2 > 5) {
@@ -322,10 +328,23 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
       }
       for (int p = 0; p < (1 << l2); ++p) {
         const bool valid = p < dc;
+        const int j = valid ? col_idx[rs + p] : 0;
+        const bool twice = valid && j != n && seen[j] > 1;
+        int g = 0;
+        if (twice) {  // group id of the VN: first-seen order, the last id shared by any further VNs
+          if (group[j] < 0) group[j] = std::min(next_group++, kGroups);
+          g = group[j];
+        }
         nbr.push_back(valid ? rs + p : -1);
-        nbr.push_back((valid ? col_idx[rs + p] : 0) | (l2 << 24) | ((p == 0 ? 1 : 0) << 27));
+        nbr.push_back(j | (l2 << 24) | ((p == 0 ? 1 : 0) << 27) | ((twice ? 1 : 0) << 28) | (g << 29));
       }
     }
+    for (auto& bk : blocks)
+      for (int x = row_ptr[bk.second]; x < row_ptr[bk.second + 1]; ++x) {
+        seen[col_idx[x]] = 0;
+        group[col_idx[x]] = -1;
+      }
+    next_group = 0;
     const int cnt = (int)(nbr.size() / 2) - off;
     nbr_idx[2 * n] = off;
     nbr_idx[2 * n + 1] = cnt;
@@ -543,11 +562,16 @@ bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
 constexpr size_t kQueueBytes = 256;  // work-queue counter at the front of a persistent launch's scratch
 
 // global slot of one frame when its messages live in global memory: (c2v, pre) pairs for E edges,
-// then Lt, L and D for N VNs, each 256-byte aligned
-void all_global_slot(int E, int N, bool fixed, DynParams& P) {
+// then Lt, L and D for N VNs, each 256-byte aligned (STORE_FRAME_REC: one 16-byte record per VN)
+void all_global_slot(int E, int N, bool fixed, int store, DynParams& P) {
   auto up = [](long long x) { return (x + 255) / 256 * 256; };
   const long long pairs = 2LL * E * (fixed ? 1 : 4);
   P.slot_lt_off = (int)up(pairs);
+  if (store == STORE_FRAME_REC) {
+    P.slot_l_off = P.slot_d_off = P.slot_lt_off;
+    P.slot_bytes = up(P.slot_lt_off + 16LL * N);
+    return;
+  }
   P.slot_l_off = (int)up(P.slot_lt_off + 4LL * N);
   P.slot_d_off = (int)up(P.slot_l_off + 4LL * N);
   P.slot_bytes = up(P.slot_d_off + 4LL * N);
@@ -568,7 +592,7 @@ int check_tuning(const ldpc_tuning* t) {
   if (!t) return LDPC_OK;
   if (t->block != 0 && !valid_block(t->block)) return LDPC_EINVAL;
   if (t->frames_per_cu < 0 || t->frames_per_cu > 32) return LDPC_EINVAL;
-  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_FRAME) return LDPC_EINVAL;
+  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_REC) return LDPC_EINVAL;
   if (t->topology < LDPC_TOPO_AUTO || t->topology > LDPC_TOPO_QC) return LDPC_EINVAL;
   return LDPC_OK;
 }
@@ -650,12 +674,14 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (c->nbr_max_cnt > NBR_PMAX * WAVE) return LDPC_EUNSUPPORTED;
   const std::vector<int> topos = topo_choices(c, T.topology);
   if (topos.empty()) return LDPC_EUNSUPPORTED;
-  std::vector<int> stores = {STORE_LDS, STORE_PRE_GLOBAL, STORE_ALL_GLOBAL, STORE_ALL_GLOBAL_LT, STORE_FRAME_GLOBAL};
+  std::vector<int> stores = {STORE_LDS,           STORE_PRE_GLOBAL,   STORE_ALL_GLOBAL,
+                             STORE_ALL_GLOBAL_LT, STORE_FRAME_GLOBAL, STORE_FRAME_REC};
   if (T.storage == LDPC_STORE_LDS) stores = {STORE_LDS};
   if (T.storage == LDPC_STORE_GLOBAL) stores = {STORE_PRE_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_ALL) stores = {STORE_ALL_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_LT) stores = {STORE_ALL_GLOBAL_LT};
   if (T.storage == LDPC_STORE_GLOBAL_FRAME) stores = {STORE_FRAME_GLOBAL};
+  if (T.storage == LDPC_STORE_GLOBAL_REC) stores = {STORE_FRAME_REC};
   const int lut_off = 257 * (fixed ? s->frac_bits : 0);
 
   if (s->kind == LDPC_ME_CIRBP) {
@@ -757,8 +783,10 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
       const int fit = std::min(32, w * wgs);  // at most 32 wavefronts per CU
       const int eff = (int)std::min<long long>(std::min(fit, cap_fpc), need);
       // Store preference: one round on the chip: LDS > PRE_GLOBAL > ALL_GLOBAL > ALL_GLOBAL_LT >
-      // FRAME_GLOBAL; larger batches: ALL_GLOBAL > ALL_GLOBAL_LT > FRAME_GLOBAL > PRE_GLOBAL > LDS
-      static const int rank_small[5] = {4, 3, 2, 1, 0}, rank_large[5] = {0, 1, 4, 3, 2};
+      // FRAME_REC > FRAME_GLOBAL; larger batches: ALL_GLOBAL > ALL_GLOBAL_LT > FRAME_REC >
+      // FRAME_GLOBAL > PRE_GLOBAL > LDS (the record layout moves one cache line per touched VN
+      // where the split arrays move three)
+      static const int rank_small[6] = {5, 4, 3, 2, 0, 1}, rank_large[6] = {0, 1, 5, 4, 2, 3};
       const int st_pref = need <= 1 ? rank_small[st] : rank_large[st];
       const int tp_pref = tp == TOPO_QC ? 2 : (tp == TOPO_LDS ? 1 : 0);
       const int pref = st_pref * 4 + tp_pref;
@@ -798,9 +826,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   P.off_c2v = Ly.off_c2v; P.off_pre = Ly.off_pre; P.off_L = Ly.off_L; P.off_Lt = Ly.off_Lt;
   P.off_D = Ly.off_D; P.off_ckey = Ly.off_ckey; P.off_dblk = Ly.off_dblk; P.off_cblk = Ly.off_cblk;
   P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
-  P.off_kbuf = Ly.off_kbuf; P.off_slot = Ly.off_slot; P.off_trow = Ly.off_trow; P.off_lut = Ly.off_lut;
-  P.off_pbuf = Ly.off_pbuf; P.off_jbuf = Ly.off_jbuf; P.off_topo = Ly.off_topo;
-  P.off_extra = Ly.off_extra;
+  P.off_grp = Ly.off_grp; P.off_lut = Ly.off_lut; P.off_topo = Ly.off_topo;
   P.lds_bytes = Ly.total;
   P.frame_base = Ly.frame_base;
   P.frame_stride = Ly.frame_stride;
@@ -828,7 +854,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (pl.persistent) pl.scratch_bytes = kQueueBytes;  // work-queue counter, then message slots
   if (pl.store == STORE_PRE_GLOBAL) pl.scratch_bytes += slots * c->E * msg;
   if (pl.store >= STORE_ALL_GLOBAL) {
-    all_global_slot(c->E, c->N, fixed, P);
+    all_global_slot(c->E, c->N, fixed, pl.store, P);
     pl.scratch_bytes += slots * (size_t)P.slot_bytes;
   }
   return LDPC_OK;
@@ -969,7 +995,7 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
     const std::vector<int> blocks = s->kind == LDPC_ME_CIRBP ? std::vector<int>{64, 256, 1024} : std::vector<int>{0};
     for (int b : blocks)
       for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL, LDPC_STORE_GLOBAL_LT,
-                        LDPC_STORE_GLOBAL_FRAME})
+                        LDPC_STORE_GLOBAL_FRAME, LDPC_STORE_GLOBAL_REC})
         for (int tp : tps)
           for (int fpc : {0, 1, 2, 4, 8, 16})
             for (int wb : s->kind == LDPC_ME_CIRBP ? std::vector<int>{0} : std::vector<int>{0, 256, 512})
@@ -1151,7 +1177,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   P.off_c2v = Ly.off_c2v; P.off_pre = Ly.off_pre; P.off_L = Ly.off_L; P.off_Lt = Ly.off_Lt;
   P.off_D = Ly.off_D; P.off_ckey = Ly.off_ckey; P.off_dblk = Ly.off_dblk; P.off_cblk = Ly.off_cblk;
   P.off_dmask = Ly.off_dmask; P.off_cmask = Ly.off_cmask; P.off_syn = Ly.off_syn; P.off_v = Ly.off_v;
-  P.off_lut = Ly.off_lut; P.off_topo = Ly.off_topo;
+  P.off_grp = Ly.off_grp; P.off_lut = Ly.off_lut; P.off_topo = Ly.off_topo;
   P.lds_bytes = Ly.total;
   P.frame_base = Ly.frame_base;
   P.frame_stride = Ly.frame_stride;
@@ -1174,7 +1200,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   size_t pre_bytes = 0;
   if (store == STORE_PRE_GLOBAL) pre_bytes = (size_t)grid * mx.E * (fixed ? 1 : 4);
   if (store >= STORE_ALL_GLOBAL) {
-    all_global_slot(mx.E, mx.N, fixed, P);
+    all_global_slot(mx.E, mx.N, fixed, store, P);
     pre_bytes = (size_t)grid * (size_t)P.slot_bytes;
   }
   void* scratch = nullptr;

@@ -11,8 +11,16 @@ enum Kind { KIND_FLOODING = 0, KIND_LAYERED = 1, KIND_RBP = 2, KIND_CIRBP = 3, K
 enum Topo { TOPO_GLOBAL = 0, TOPO_LDS = 1, TOPO_QC = 2 };
 // single-edge frame storage: c2v and pre in LDS; pre in a global slot; both in a global slot; both
 // and the precomputed totals Lt in a global slot; the whole frame (messages, Lt, L, D) in a global
-// slot, leaving only check keys, block maxima, syndrome bits and staging in LDS
-enum Store { STORE_LDS = 0, STORE_PRE_GLOBAL = 1, STORE_ALL_GLOBAL = 2, STORE_ALL_GLOBAL_LT = 3, STORE_FRAME_GLOBAL = 4 };
+// slot, leaving only check keys, block maxima, syndrome bits and staging in LDS; the same with the
+// three per-VN values of a VN in one 16-byte record (one cache line per touched VN instead of three)
+enum Store {
+  STORE_LDS = 0,
+  STORE_PRE_GLOBAL = 1,
+  STORE_ALL_GLOBAL = 2,
+  STORE_ALL_GLOBAL_LT = 3,
+  STORE_FRAME_GLOBAL = 4,
+  STORE_FRAME_REC = 5
+};
 
 struct DecOut {
   uint8_t* bits;            // [B][N]
@@ -45,7 +53,8 @@ struct DynParams {
   int frame_stride;         // workgroup starts at frame_base + w * frame_stride (frame offsets below
   int wpb;                  // are relative to it); wpb = frames (wavefronts) per workgroup
   long long slot_bytes;     // STORE_ALL_GLOBAL and up: bytes per slot ((c2v, pre) pairs, Lt, L, D)
-  int slot_lt_off;          // STORE_ALL_GLOBAL_LT and up: byte offset of Lt in a slot
+  int slot_lt_off;          // STORE_ALL_GLOBAL_LT and up: byte offset of Lt (STORE_FRAME_REC: of the
+                            // VN records) in a slot
   int slot_l_off;           // STORE_FRAME_GLOBAL: byte offsets of L and D in a slot
   int slot_d_off;
   int* queue;               // persistent launch: next-frame counter (zeroed before launch); null:
@@ -55,7 +64,7 @@ struct DynParams {
   unsigned long long seed;
   // LDS layout (byte offsets)
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_ckey, off_dblk, off_cblk, off_dmask, off_cmask;
-  int off_syn, off_v, off_pbuf, off_jbuf, off_kbuf, off_slot, off_trow, off_lut, off_topo, off_extra;
+  int off_syn, off_v, off_grp, off_lut, off_topo;
   int lds_bytes;
   int nbd, nbc, nbd_words, nbc_words;
   long long* prof;          // development builds only: per-phase cycle sums (null otherwise)

@@ -234,7 +234,7 @@ def test_edge_cases(gpu, c0):
 # ------------------------------------------------------------------------------------------
 # storage variants: every (pre location, topology source) combination is bit-exact
 # ------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("pre", ["lds", "global", "all", "all_lt", "frame"])
+@pytest.mark.parametrize("pre", ["lds", "global", "all", "all_lt", "frame", "rec"])
 @pytest.mark.parametrize("topo", ["global", "lds", "qc"])
 @pytest.mark.parametrize("fpc", [0, 3])
 def test_fixed_storage_variants(gpu, pre, topo, fpc):
@@ -244,7 +244,7 @@ def test_fixed_storage_variants(gpu, pre, topo, fpc):
     ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True, dump=True,
                    threads=8)
     store = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL,
-             "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME}[pre]
+             "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME, "rec": gpu.STORE_GLOBAL_REC}[pre]
     tp = {"global": gpu.TOPO_GLOBAL, "lds": gpu.TOPO_LDS, "qc": gpu.TOPO_QC}[topo]
     handles = [gpu.Code(code)] if topo == "qc" else [gpu.Code(code), gpu.Code(code, csr=True)]
     for h in handles:
@@ -260,6 +260,53 @@ def test_fixed_storage_variants(gpu, pre, topo, fpc):
         np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
         np.testing.assert_array_equal(np_(g.c2v), ref.c2v)
         np.testing.assert_array_equal(np_(g.D), ref.D)
+
+
+def many_four_cycles_code():
+    """Six checks of degree 16 on 32 VNs with heavy overlap: the two-hop table of a VN lists up to
+    27 other VNs more than once (more than the kernels' LDS groups hold), in up to two passes."""
+    rows = [[0, 1, 5, 7, 11, 12, 15, 16, 17, 19, 20, 21, 24, 26, 28, 31],
+            [3, 4, 5, 8, 9, 12, 14, 15, 16, 17, 18, 20, 23, 24, 25, 30],
+            [0, 2, 4, 5, 6, 10, 14, 16, 18, 19, 21, 22, 24, 26, 29, 30],
+            [1, 3, 4, 9, 10, 12, 13, 14, 16, 19, 20, 22, 25, 26, 28, 31],
+            [1, 2, 3, 5, 6, 8, 9, 10, 11, 12, 18, 21, 22, 28, 29, 30],
+            [1, 3, 4, 5, 6, 10, 11, 12, 14, 15, 17, 18, 23, 27, 28, 31]]
+    return S.code_from_rows(6, 32, rows, name="overlap32")
+
+
+@pytest.mark.parametrize("store", ["lds", "rec"])
+def test_fixed_repeated_two_hop_vns_bit_exact(gpu, store):
+    """VNs met on several checks of the updated VN (4-cycles): their precomputed totals take every
+    change of the update, through the LDS groups and through the overflow path."""
+    code = many_four_cycles_code()
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 200, 1.0, 112)
+    st = {"lds": gpu.STORE_LDS, "rec": gpu.STORE_GLOBAL_REC}[store]
+    say(f"[repeated two-hop VNs] overlap32 store={store}")
+    ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=400, check_every=0, q_bits=8, frac_bits=2, trace=True,
+                   dump=True, threads=8)
+    gpu.set_tuning(h, gpu.CIRBP, gpu.MS_FIX, storage=st, frames_per_cu=2)
+    try:
+        g = gpu_decode(gpu, h, llr, "cirbp", gpu.MS_FIX, max_updates=400, check_every=0, q_bits=8, frac_bits=2,
+                       trace=True, dump=True)
+    finally:
+        gpu.set_tuning(h, gpu.CIRBP, gpu.MS_FIX, clear=True)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    np.testing.assert_array_equal(np_(g.Lt), ref.Lt)
+    np.testing.assert_array_equal(np_(g.D), ref.D)
+    # FP32: the oracle's schedule replayed, messages and totals within tolerance
+    rec = O.decode(code, llr, O.CIRBP, O.SPA, max_updates=300, check_every=0, trace=True, threads=8)
+    refr = O.decode(code, llr, O.REPLAY, O.SPA, max_updates=300, replay=rec.trace, dump=True, threads=8)
+    gpu.set_tuning(h, gpu.REPLAY, gpu.SPA_F32, storage=st, frames_per_cu=2)
+    try:
+        gr = gpu_decode(gpu, h, llr, "replay", gpu.SPA_F32, max_updates=300, replay=torch.from_numpy(rec.trace),
+                        dump=True)
+    finally:
+        gpu.set_tuning(h, gpu.REPLAY, gpu.SPA_F32, clear=True)
+    assert_close_msgs(gr.Lt, refr.Lt, "Lt")
+    assert_close_msgs(gr.L, refr.L, "L")
+    assert np.abs(np_(gr.D) - refr.D).max() <= 1e-4
 
 
 # ------------------------------------------------------------------------------------------
@@ -379,7 +426,7 @@ def test_batch_rejects_bad_descriptors(gpu):
     assert u[0] >= 0 and u[5] >= 0
 
 
-@pytest.mark.parametrize("store", ["lds", "global", "all", "all_lt", "frame"])
+@pytest.mark.parametrize("store", ["lds", "global", "all", "all_lt", "frame", "rec"])
 def test_f32_storage_modes_identical(gpu, store):
     """FP32 results do not depend on where the messages live (same arithmetic, same order)."""
     code = S.workload_code("c4")
@@ -389,7 +436,7 @@ def test_f32_storage_modes_identical(gpu, store):
     gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, clear=True)
     base = gpu.decode(h, t, gpu.CIRBP, gpu.SPA_F32, max_updates=4000, trace=True)
     st = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL,
-          "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME}[store]
+          "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME, "rec": gpu.STORE_GLOBAL_REC}[store]
     gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, storage=st, frames_per_cu=2)
     try:
         r = gpu.decode(h, t, gpu.CIRBP, gpu.SPA_F32, max_updates=4000, trace=True)
