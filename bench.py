@@ -7,8 +7,8 @@ channel LLRs generated on the GPU and resident in HBM before timing.  Decoders:
   CIRBP     Algorithm 1, gamma = 0.1, sum-product FP32, at most 3E updates (3 iterations);
   flooding  sum-product FP32, at most 50 iterations;
   layered   sum-product FP32, block-row layers, at most 50 iterations.
-A step decodes one batch of frames; the value is CIRBP decoded frames per second over the timed
-steps.  The same batches are then decoded by flooding and layered BP and reported alongside.
+A step decodes one batch of 65536 frames (the frames of one Eb/N0 point) in one launch; the value
+is CIRBP decoded frames per second over the timed steps.  The same batches are then decoded by flooding and layered BP and reported alongside.
 
 Prints one JSON line.  ``--sweep`` instead prints one JSON line per Eb/N0 point (FER curves).
 ``--workload`` measures the other workloads, one JSON line each:
@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 LDS_PEAK_GBS = 256 * 128 * 2.4  # CUs x bytes/clk/CU x GHz = 78643 GB/s (nominal LDS bandwidth)
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 METRIC = "decoded frames/s & edge-updates/s at FER 1e-3, CI vs flooding BP, one MI355X"
+C1_FRAMES = 65536               # frames per Eb/N0 point of the BG1-shaped workload: one step
 
 
 def lds_bytes_per_update_table(code, s_c=4, s_v=4, s_d=4):
@@ -183,7 +184,7 @@ def ev_time(stream, fn):
 def bench_batched(args, ldpc, S, dev):
     """Workload c2: one persistent launch over uneven codes, schedules and SNRs."""
     import torch
-    F = args.frames if args.frames != 8192 else 262144
+    F = args.frames or 262144
     rng = np.random.default_rng(args.seed)
     codes = [S.qc_24col(Z, mb, seed=1) for Z in (24, 48, 96) for mb in (12, 8, 6, 4)]
     hs = [ldpc.Code(c) for c in codes]
@@ -284,7 +285,7 @@ def bench_multi_edge(args, ldpc, S, dev):
     import torch
     code = S.workload_code("c3")
     h = ldpc.Code(code)
-    B = args.frames if args.frames != 8192 else 2048
+    B = args.frames or 2048
     stream = torch.cuda.Stream(device=dev)
     rows = []
     total_ms = 0.0
@@ -363,9 +364,10 @@ def bench_unrolled(args, ldpc, S, dev):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--frames", type=int, default=8192, help="frames per step")
+    ap.add_argument("--frames", type=int, default=0,
+                    help="frames per step (default: 65536, the frames of one Eb/N0 point of the workload)")
     ap.add_argument("--ebn0", type=float, default=1.25)
     ap.add_argument("--seed", type=int, default=2102)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -392,6 +394,7 @@ def main():
         {"c2": bench_batched, "c3": bench_multi_edge, "c4": bench_unrolled}[args.workload](args, ldpc, S, dev)
         return
 
+    args.frames = args.frames or C1_FRAMES
     code = S.workload_code("c1")
     h = ldpc.Code(code)
     E = code.E
@@ -453,7 +456,7 @@ def main():
     kern_s = sum(kms) / 1e3
     achieved_gbs = bytes_per_update * upd / kern_s / 1e9 if kern_s > 0 else 0.0
     # HBM traffic of the timed launch from the counters taken on this workload (default size only)
-    tb = measured_traffic_bytes() if (args.frames == 8192 and args.ebn0 == 1.25) else None
+    tb = measured_traffic_bytes() if (args.frames == C1_FRAMES and args.ebn0 == 1.25) else None
     traffic_gbs = round(tb / (float(np.mean(kms)) / 1e3) / 1e9, 2) if tb else None
     del rt, tr, mask
     pd = ldpc.describe_plan(h, llr0.shape[0], ldpc.CIRBP, ldpc.SPA_F32, gamma=0.1)

@@ -362,6 +362,24 @@ __device__ __forceinline__ float row_aux(const ArithFix&, int) { return 0.0f; }
 // ------------------------------------------------------------------------------------------
 // code topology as seen by a kernel
 // ------------------------------------------------------------------------------------------
+// Exact quotient n / d for 0 <= n < 2^31 and 1 <= d < 2^31 by a multiply and a shift: with
+// l = ceil(log2 d), sh = 31 + l and mul = ceil(2^sh / d) (below 2^32), n mul / 2^sh exceeds n / d by
+// less than n d / (d 2^sh) < 2^-l <= 1 / d, too little to carry the quotient past the next integer.
+struct FastDiv {
+  uint32_t mul, sh;
+  __host__ __device__ static FastDiv of(uint32_t d) {
+    uint32_t l = 0;
+    while ((1u << l) < d) ++l;
+    FastDiv f;
+    f.sh = 31 + l;
+    f.mul = (uint32_t)(((1ull << f.sh) + d - 1) / d);
+    return f;
+  }
+  __host__ __device__ __forceinline__ int div(int n) const {
+    return (int)(((uint64_t)(uint32_t)n * mul) >> sh);
+  }
+};
+
 // Quasi-cyclic description (Sec. V codes are lifted base graphs): base row i has deg[i] blocks
 // (j, shift) with ascending j; check m = i Z + r meets VN j Z + ((r + shift) mod Z).  Edge ids stay
 // canonical: e = Z bptr[i] + r deg[i] + rank of j in row i.
@@ -373,7 +391,9 @@ struct DevQC {
   const int* bcol_ptr;  // [nb+1]
   const int* bcol;      // [nblk][4]  (i, shift, rank in row i, 0) per column, ascending i
   const int* rowmap;    // [nblk]     base row of edge block e / Z
+  const int* bdiv;      // [mb][2]    FastDiv (mul, sh) of deg[i]
   int words;            // total ints of the tables (for copying into LDS)
+  FastDiv zdiv;         // FastDiv of Z
 };
 
 struct DevCode {
@@ -421,21 +441,28 @@ struct TopoCSR {
   __device__ __forceinline__ int2 nbr(int n) const { return nbr_idx[n]; }
 };
 
-// Topology of a quasi-cyclic code from its base tables (in LDS): no per-edge index arrays
+// Topology of a quasi-cyclic code from its base tables (in LDS): no per-edge index arrays; every
+// division by Z or by a base-row degree is a FastDiv
 struct TopoQC {
   int Z;
+  FastDiv zdiv;
   const int* bdeg;
   const int* bptr;
   const int* brow;
   const int* bcol_ptr;
   const int* bcol;
   const int* rowmap;
+  const int* bdiv;
+  __device__ __forceinline__ int row_div(int i, int x) const {
+    const FastDiv f{(uint32_t)bdiv[2 * i], (uint32_t)bdiv[2 * i + 1]};
+    return f.div(x);
+  }
   __device__ __forceinline__ int vn_deg(int n) const {
-    const int j = n / Z;
+    const int j = zdiv.div(n);
     return bcol_ptr[j + 1] - bcol_ptr[j];
   }
   __device__ __forceinline__ void vn_edge(int n, int k, int& m, int& e) const {
-    const int j = n / Z, c = n - j * Z;
+    const int j = zdiv.div(n), c = n - j * Z;
     const int x = (bcol_ptr[j] + k) * 4;
     const int i = bcol[x], sh = bcol[x + 1], rank = bcol[x + 2];
     int r = c - sh;
@@ -444,26 +471,26 @@ struct TopoQC {
     e = Z * bptr[i] + r * bdeg[i] + rank;
   }
   __device__ __forceinline__ int row_start(int m) const {
-    const int i = m / Z, r = m - i * Z;
+    const int i = zdiv.div(m), r = m - i * Z;
     return Z * bptr[i] + r * bdeg[i];
   }
-  __device__ __forceinline__ int row_deg(int m) const { return bdeg[m / Z]; }
+  __device__ __forceinline__ int row_deg(int m) const { return bdeg[zdiv.div(m)]; }
   __device__ __forceinline__ int row_vn(int m, int, int p) const {
-    const int i = m / Z, r = m - i * Z;
+    const int i = zdiv.div(m), r = m - i * Z;
     const int x = (bptr[i] + p) * 2;
     int c = r + brow[x + 1];
     if (c >= Z) c -= Z;
     return brow[x] * Z + c;
   }
   __device__ __forceinline__ int edge_row(int e) const {
-    const int i = rowmap[e / Z];
-    const int r = (e - Z * bptr[i]) / bdeg[i];
+    const int i = rowmap[zdiv.div(e)];
+    const int r = row_div(i, e - Z * bptr[i]);
     return i * Z + r;
   }
   __device__ __forceinline__ int edge_vn(int e) const {
-    const int i = rowmap[e / Z];
+    const int i = rowmap[zdiv.div(e)];
     const int loc = e - Z * bptr[i];
-    const int r = loc / bdeg[i], p = loc - r * bdeg[i];
+    const int r = row_div(i, loc), p = loc - r * bdeg[i];
     const int x = (bptr[i] + p) * 2;
     int c = r + brow[x + 1];
     if (c >= Z) c -= Z;
@@ -471,7 +498,7 @@ struct TopoQC {
   }
   const int* nbr_col;  // [nb][2] in LDS
   __device__ __forceinline__ int2 nbr(int n) const {
-    const int j = n / Z, c = n - j * Z;
+    const int j = zdiv.div(n), c = n - j * Z;
     const int cnt = nbr_col[2 * j + 1];
     return make_int2(nbr_col[2 * j] + c * cnt, cnt);
   }

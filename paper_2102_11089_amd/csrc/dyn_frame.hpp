@@ -321,6 +321,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     int estar, mstar = -1, nstar = -1;
     msg_t c_star = (msg_t)0, p_star = (msg_t)0;  // messages of e*, taken from the selection's loads
     bool have_star = false;
+    bool have_row = false;                        // lane p holds the pairs of edge row_start(m*) + p
+    msg_t row_cm = (msg_t)0, row_pm = (msg_t)0;
     if (J.kind == KIND_REPLAY) {
       estar = uni(J.replay[t]);
       if (estar < 0 || estar >= E) break;  // invalid edge id ends the frame's replay
@@ -354,6 +356,9 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         c_star = lane_value(cm, estar - rs);
         p_star = lane_value(pm, estar - rs);
         have_star = true;
+        have_row = true;
+        row_cm = cm;
+        row_pm = pm;
       } else {
         const int dvs = uni(G.vn_deg(nsel));
         uint64_t k = 0;
@@ -387,16 +392,24 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       int e;
       G.vn_edge(nstar, lane, my_m, e);
     }
-    const int2 nb = G.nbr(nstar);
-    const int noff = uni(nb.x), ncnt = uni(nb.y);
-    const int npass = (ncnt + WAVE - 1) / WAVE;
     const int rs_m = uni(G.row_start(mstar));
-    const int re_m = rs_m + uni(G.row_deg(mstar));
+    const int dc_m = uni(G.row_deg(mstar));
+    const int re_m = rs_m + dc_m;
+    // n* on no check but m*: nothing is precomputed again, only m*'s residual key changes
+    const bool row_only = dv == 1;
+    int ncnt = 0, npass = 0, noff = 0;
+    if (!row_only) {
+      const int2 nb = G.nbr(nstar);
+      noff = uni(nb.x);
+      ncnt = uni(nb.y);
+      npass = (ncnt + WAVE - 1) / WAVE;
+    }
     // Inputs of the touched-check passes are loaded ahead of use: table entries two passes ahead,
     // message pairs, L and Lt one pass ahead.  Nothing a pass writes is read by a later pass
-    // except Lt of a VN listed twice in the two-hop table (such VNs take the atomic path below and
+    // except Lt of a VN listed twice in the two-hop table (such VNs take the summed paths below and
     // do not use the early value), and propagation changes only c2v[e*] and L[n*] (both
-    // overridden where used), so the early loads see the values the passes need.
+    // overridden where used), so the early loads see the values the passes need.  Lanes of m*'s
+    // row and of n* itself update nothing and load no VN record.
     auto load_ent = [&](int ps) -> int2 {
       const int idx = ps * WAVE + lane;
       return idx < ncnt ? H.nbr[noff + idx] : make_int2(-1, 0);
@@ -416,17 +429,21 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       if (ent.x >= 0) {
         ms.cp(ent.x, q.cm, q.pm);
         const int j = ent.y & 0xFFFFFF;
-        if (with_ci) ms.lt_l(j, q.ltj, q.lj);
-        else q.lj = ms.l(j);
+        if (j != nstar && (ent.x < rs_m || ent.x >= re_m)) {
+          if (with_ci) ms.lt_l(j, q.ltj, q.lj);
+          else q.lj = ms.l(j);
+        }
       }
       return q;
     };
-    const int2 ent0 = load_ent(0);
+    const int2 ent0 = row_only ? make_int2(-1, 0) : load_ent(0);
     int2 ent_next = npass > 1 ? load_ent(1) : make_int2(-1, 0);
 
     // ---- propagation (Algorithm 1 line 9) and D_{n*} ----
     if (!have_star) ms.cp(estar, c_star, p_star);
-    PassIn in_cur = load_in(ent0);
+    PassIn in_cur{make_int2(-1, 0), (msg_t)0, (msg_t)0, (llr_t)0, (llr_t)0};
+    if (!row_only) in_cur = load_in(ent0);
+    else if (!have_row && lane < dc_m) ms.cp(rs_m + lane, row_cm, row_pm);
     const val_t newv = (val_t)p_star;
     const val_t oldv = (val_t)c_star;
     llr_t lt_n = (llr_t)0, l_n;
@@ -456,6 +473,20 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     wave_sync();
     PROF_MARK(1)
 
+    if (row_only) {  // m*'s new residual key: its row with c2v[e*] = pre[e*]
+      uint64_t k = 0;
+      if (lane < dc_m) {
+        const int e = rs_m + lane;
+        const val_t cv = e == estar ? newv : (val_t)row_cm;
+        k = mkkey(ar.res((val_t)row_pm, cv), (uint32_t)e);
+      }
+      const uint32_t kv = key_val(wave_max_u64(k));
+      if (lane == 0) {
+        ckey[mstar] = kv;
+        leaf_moved(cblk, cmask, mstar >> 6, (uint32_t)mstar, mkkey(kv, (uint32_t)mstar));
+      }
+    }
+
     // ---- touched checks: V2C inputs, whole-row update, residual keys, and the CI of every VN
     //      listed once in the table (Algorithm 1 lines 10-13; one pass per 64 lanes) ----
     bool late_ci = false;  // a VN of the overflow group was updated: its CI is refreshed after the passes
@@ -480,31 +511,33 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         po = (val_t)in_cur.pm;
         lv = self ? Lnew : (val_t)in_cur.lj;
       }
-      const val_t v = ar.vin(ar.v2c(lv, cv));
-      const int maxL2 = uni(L2);  // lane 0 starts the pass's largest block
-      RowRed r;
-      r.m1 = valid ? fabsf((float)v) : __builtin_inff();
-      r.m2 = __builtin_inff();
-      r.ap = (valid ? (uint32_t)e : 0x7FFFFFFFu) | (valid && v < 0 ? 0x80000000u : 0u);
       const bool upd = valid && !in_m && !self;
       val_t pv = po;
-      if constexpr (A::kFixed) {
-        rowred_all<false>(r, L2, maxL2);
-        const bool me = (uint32_t)e == (r.ap & 0x7FFFFFFFu);
-        const int mag = (int)(me ? r.m2 : r.m1);
-        const int o = (((r.ap >> 31) ^ (v < 0 ? 1u : 0u)) & 1u) ? -mag : mag;
-        if (upd) pv = o;
-      } else {
-        const float ph = valid ? row_aux(ar, v) : 0.0f;
-        r.S = ph;
-        r.Sx = 0.0f;
-        rowred_all<true>(r, L2, maxL2);
-        const bool me = (uint32_t)e == (r.ap & 0x7FFFFFFFu);
-        const float mo = me ? r.m2 : r.m1;
-        const float Sj = me ? r.Sx : (ph == __builtin_inff() ? __builtin_inff() : r.S - ph);
-        const float mag = fminf(phi_f32(fmaxf(Sj, 0.0f)), mo);
-        const float o = (((r.ap >> 31) ^ (v < 0.0f ? 1u : 0u)) & 1u) ? -mag : mag;
-        if (upd) pv = o;
+      const int maxL2 = uni(L2);  // lane 0 starts the pass's largest block
+      if (__ballot(upd) != 0ull) {  // some row of the pass is precomputed again
+        const val_t v = ar.vin(ar.v2c(lv, cv));
+        RowRed r;
+        r.m1 = valid ? fabsf((float)v) : __builtin_inff();
+        r.m2 = __builtin_inff();
+        r.ap = (valid ? (uint32_t)e : 0x7FFFFFFFu) | (valid && v < 0 ? 0x80000000u : 0u);
+        if constexpr (A::kFixed) {
+          rowred_all<false>(r, L2, maxL2);
+          const bool me = (uint32_t)e == (r.ap & 0x7FFFFFFFu);
+          const int mag = (int)(me ? r.m2 : r.m1);
+          const int o = (((r.ap >> 31) ^ (v < 0 ? 1u : 0u)) & 1u) ? -mag : mag;
+          if (upd) pv = o;
+        } else {
+          const float ph = valid ? row_aux(ar, v) : 0.0f;
+          r.S = ph;
+          r.Sx = 0.0f;
+          rowred_all<true>(r, L2, maxL2);
+          const bool me = (uint32_t)e == (r.ap & 0x7FFFFFFFu);
+          const float mo = me ? r.m2 : r.m1;
+          const float Sj = me ? r.Sx : (ph == __builtin_inff() ? __builtin_inff() : r.S - ph);
+          const float mag = fminf(phi_f32(fmaxf(Sj, 0.0f)), mo);
+          const float o = (((r.ap >> 31) ^ (v < 0.0f ? 1u : 0u)) & 1u) ? -mag : mag;
+          if (upd) pv = o;
+        }
       }
       if (upd) {
         ms.set_p(e, (msg_t)pv);

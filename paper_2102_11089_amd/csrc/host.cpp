@@ -379,6 +379,11 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
       q2.push_back(nbr_idx[2 * ((size_t)j * qZ)]);
       q2.push_back(nbr_idx[2 * ((size_t)j * qZ) + 1]);
     }
+    for (int i = 0; i < qmb; ++i) {  // FastDiv of each base-row degree
+      const FastDiv f = FastDiv::of((uint32_t)(*qc)[i]);
+      q2.push_back((int)f.mul);
+      q2.push_back((int)f.sh);
+    }
     c->h_qc = q2;
     c->qc_Z = qZ;
     c->qc_mb = qmb;
@@ -438,6 +443,8 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
     d.qc.rowmap = d.qc.bcol + 4 * qnblk;
     d.qc.words = (int)c->h_qc.size();
     d.nbr_col = reinterpret_cast<const int2*>(d.qc.rowmap + qnblk);
+    d.qc.bdiv = d.qc.rowmap + qnblk + 2 * qnb;
+    d.qc.zdiv = FastDiv::of((uint32_t)qZ);
   }
   he = hipMalloc((void**)&c->d_self, sizeof(DevCode));
   if (he == hipSuccess) he = hipMemcpy(c->d_self, &c->dev, sizeof(DevCode), hipMemcpyHostToDevice);

@@ -147,7 +147,8 @@ struct TopoSel<TOPO_QC> {
     for (int x = tid; x < q.words; x += nthr) p[x] = q.bdeg[x];  // tables are contiguous from bdeg
     const int o_bptr = (int)(q.bptr - q.bdeg), o_brow = (int)(q.brow - q.bdeg);
     const int o_bcp = (int)(q.bcol_ptr - q.bdeg), o_bcol = (int)(q.bcol - q.bdeg), o_rm = (int)(q.rowmap - q.bdeg);
-    TopoQC t{q.Z, p, p + o_bptr, p + o_brow, p + o_bcp, p + o_bcol, p + o_rm};
+    const int o_bdiv = (int)(q.bdiv - q.bdeg);
+    TopoQC t{q.Z, q.zdiv, p, p + o_bptr, p + o_brow, p + o_bcp, p + o_bcol, p + o_rm, p + o_bdiv};
     t.nbr_col = p + (int)(reinterpret_cast<const int*>(H.nbr_col) - q.bdeg);
     return t;
   }

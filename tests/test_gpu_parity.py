@@ -262,6 +262,38 @@ def test_fixed_storage_variants(gpu, pre, topo, fpc):
         np.testing.assert_array_equal(np_(g.D), ref.D)
 
 
+@pytest.mark.parametrize("store", ["lds", "all", "rec"])
+@pytest.mark.parametrize("kind", ["cirbp", "rbp", "replay"])
+def test_fixed_degree_one_vns(gpu, store, kind):
+    """BG1-shaped base graph lifted by Z = 4 (n = 272): updates of degree-1 VNs (whose only check
+    is the updated edge's check) refresh that check's key without a row pass; bit-exact."""
+    code = S.qc_bg1_shaped(4, seed=3)
+    cw, llr = S.frames(code, 96, 1.0, 113)
+    st = {"lds": gpu.STORE_LDS, "all": gpu.STORE_GLOBAL_ALL, "rec": gpu.STORE_GLOBAL_REC}[store]
+    say(f"[degree-1 VNs] bg1 Z=4 {kind} store={store}")
+    kw = dict(max_updates=2000, q_bits=8, frac_bits=2, trace=True, dump=True)
+    rep = None
+    if kind == "replay":
+        rec = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=1500, q_bits=8, frac_bits=2, check_every=0,
+                       trace=True, threads=8)
+        rep = rec.trace
+        kw["max_updates"] = 1500
+    ref = O.decode(code, llr, KIND[kind][0], O.MSFIX, threads=8, replay=rep, **kw)
+    h = gpu.Code(code)
+    gpu.set_tuning(h, KIND[kind][1], gpu.MS_FIX, storage=st, frames_per_cu=2)
+    try:
+        g = gpu_decode(gpu, h, llr, kind, gpu.MS_FIX, replay=None if rep is None else torch.from_numpy(rep), **kw)
+    finally:
+        gpu.set_tuning(h, KIND[kind][1], gpu.MS_FIX, clear=True)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+    np.testing.assert_array_equal(np_(g.c2v), ref.c2v)
+    np.testing.assert_array_equal(np_(g.pre), ref.pre)
+    if kind != "rbp":  # RBP keeps no CIs
+        np.testing.assert_array_equal(np_(g.D), ref.D)
+
+
 def many_four_cycles_code():
     """Six checks of degree 16 on 32 VNs with heavy overlap: the two-hop table of a VN lists up to
     27 other VNs more than once (more than the kernels' LDS groups hold), in up to two passes."""
