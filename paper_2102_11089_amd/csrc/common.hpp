@@ -55,6 +55,12 @@ template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
 }
+// the same exchange as a plain move: every pattern used here has a valid source lane for every
+// lane, so no fill value is needed (the compiler then emits a single v_mov_b32_dpp)
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, true);
+}
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
   x = max(x, dpp_u32<LDPC_DPP_QXOR1>(x));
@@ -105,10 +111,10 @@ __device__ __forceinline__ int wave_excl_scan(int v, int) {
 // aligned 2^k group.
 template <int LEVEL>
 __device__ __forceinline__ uint32_t bfly(uint32_t x) {
-  if constexpr (LEVEL == 1) return dpp_u32<LDPC_DPP_QXOR1>(x);
-  else if constexpr (LEVEL == 2) return dpp_u32<LDPC_DPP_QXOR2>(x);
-  else if constexpr (LEVEL == 3) return dpp_u32<LDPC_DPP_HALF_MIRROR>(x);
-  else if constexpr (LEVEL == 4) return dpp_u32<LDPC_DPP_MIRROR>(x);
+  if constexpr (LEVEL == 1) return dpp_mov<LDPC_DPP_QXOR1>(x);
+  else if constexpr (LEVEL == 2) return dpp_mov<LDPC_DPP_QXOR2>(x);
+  else if constexpr (LEVEL == 3) return dpp_mov<LDPC_DPP_HALF_MIRROR>(x);
+  else if constexpr (LEVEL == 4) return dpp_mov<LDPC_DPP_MIRROR>(x);
   else return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);
 }
 template <int LEVEL>
@@ -132,21 +138,23 @@ __device__ __forceinline__ void rowred_step(RowRed& r, bool on) {
     pS = bflyf<LEVEL>(r.S);
     pSx = bflyf<LEVEL>(r.Sx);
   }
-  if (on) {
-    const uint32_t par = (r.ap ^ pap) & 0x80000000u;
-    const uint32_t a = r.ap & 0x7FFFFFFFu, pa = pap & 0x7FFFFFFFu;
-    if (pm1 < r.m1 || (pm1 == r.m1 && pa < a)) {
-      r.m2 = fminf(r.m1, pm2);
-      r.m1 = pm1;
-      r.ap = pa | par;
-      if constexpr (SUM) r.Sx = pSx + r.S;
-    } else {
-      r.m2 = fminf(r.m2, pm1);
-      r.ap = a | par;
-      if constexpr (SUM) r.Sx = r.Sx + pS;
-    }
-    if constexpr (SUM) r.S += pS;
+  // straight-line merge (selects, no branches): the partner's minimum wins if smaller, or equal
+  // with a lower edge id
+  const uint32_t par = (r.ap ^ pap) & 0x80000000u;
+  const uint32_t a = r.ap & 0x7FFFFFFFu, pa = pap & 0x7FFFFFFFu;
+  const bool take = pm1 < r.m1 || (pm1 == r.m1 && pa < a);
+  const float m2 = take ? fminf(r.m1, pm2) : fminf(r.m2, pm1);
+  const float m1 = take ? pm1 : r.m1;
+  const uint32_t ap = (take ? pa : a) | par;
+  if constexpr (SUM) {
+    const float Sx = take ? pSx + r.S : r.Sx + pS;
+    const float S = r.S + pS;
+    r.Sx = on ? Sx : r.Sx;
+    r.S = on ? S : r.S;
   }
+  r.m2 = on ? m2 : r.m2;
+  r.m1 = on ? m1 : r.m1;
+  r.ap = on ? ap : r.ap;
 }
 
 // all butterfly levels up to the largest block of the pass (maxL2 is wave-uniform)
@@ -163,10 +171,9 @@ __device__ __forceinline__ void rowred_all(RowRed& r, int L2, int maxL2) {
 template <int LEVEL>
 __device__ __forceinline__ void keymax_step(uint32_t& hi, uint32_t& lo, bool on) {
   const uint32_t ph = bfly<LEVEL>(hi), pl = bfly<LEVEL>(lo);
-  if (on && (ph > hi || (ph == hi && pl > lo))) {
-    hi = ph;
-    lo = pl;
-  }
+  const bool take = on && ((((uint64_t)ph << 32) | pl) > (((uint64_t)hi << 32) | lo));
+  hi = take ? ph : hi;
+  lo = take ? pl : lo;
 }
 __device__ __forceinline__ uint64_t keymax_all(uint64_t k, int L2, int maxL2) {
   uint32_t hi = (uint32_t)(k >> 32), lo = (uint32_t)(k & 0xFFFFFFFFull);
@@ -191,12 +198,14 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // ------------------------------------------------------------------------------------------
 // FP32 sum-product
 // ------------------------------------------------------------------------------------------
-// reciprocal from the hardware's approximate v_rcp_f32 (about 1 ulp; 1/0 = inf): the sum-product
-// terms need FP32-level relative accuracy, not a correctly rounded quotient
+// reciprocal and natural logarithm from the hardware's approximate v_rcp_f32 and v_log_f32 (about
+// 1 ulp; 1/0 = inf, log of inf = inf; no denormal arguments occur here): the sum-product terms
+// need FP32-level relative accuracy, not correctly rounded results
 __device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float log_approx(float x) { return __builtin_amdgcn_logf(x) * 0.69314718056f; }
 
 __device__ __forceinline__ float softplus_neg(float x) {  // log(1 + e^-x), x >= 0
-  return __logf(1.0f + __expf(-x));
+  return log_approx(1.0f + __expf(-x));
 }
 
 struct ArithF32 {
@@ -296,7 +305,7 @@ __device__ __forceinline__ float phi_f32(float x) {  // -log(tanh(x/2)) = log((1
   const float ser = x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f)))));
   const float y = x < 0.25f ? ser : 1.0f - t;
   const float ry = rcp_approx(y);
-  const float lg = __logf((1.0f + t) * ry);
+  const float lg = log_approx((1.0f + t) * ry);
   // above 4 the quotient is 1 + w, w = 2t/(1-t) < 0.04: log(1 + w) by its series
   const float w = (2.0f * t) * ry;
   const float lp = w * (1.0f - w * (0.5f - w * (1.0f / 3.0f - w * 0.25f)));
