@@ -215,6 +215,8 @@ int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t*
                                      frames per CU                                                */
 #define LDPC_STORE_GLOBAL_REC 6   /* as GLOBAL_FRAME, with the precomputed total, CI and total of
                                      a VN in one 16-byte record (single-edge schedules only)      */
+#define LDPC_STORE_GLOBAL_STATE 7 /* as GLOBAL_REC, with the check keys in the slot too: LDS holds
+                                     only block maxima and small bookkeeping (single-edge only)   */
 #define LDPC_TOPO_AUTO 0    /* quasi-cyclic tables, else LDS copies, else global arrays       */
 #define LDPC_TOPO_GLOBAL 1
 #define LDPC_TOPO_LDS 2
@@ -249,7 +251,8 @@ typedef struct {
   int32_t block;                /* threads per workgroup                                               */
   int32_t grid;                 /* workgroups launched                                                 */
   int32_t frames_per_workgroup; /* frames one workgroup decodes at once (single-edge: its wavefronts) */
-  int32_t workgroups_per_cu;    /* workgroups a CU can hold: min(LDS / lds_bytes, 32 wavefronts)      */
+  int32_t workgroups_per_cu;    /* workgroups a CU can hold by LDS and by wavefront slots at the
+                                   kernel's register count                                          */
   int32_t persistent;           /* 1: fewer workgroups than frames, each takes frames in turn (single-
                                    edge: from a device work queue)                                     */
   int32_t lds_bytes;            /* dynamic LDS per workgroup                                           */
@@ -266,7 +269,7 @@ int ldpc_describe_plan(const ldpc_code* code, const ldpc_schedule* s, int32_t B,
    residency that large batches gain from, and favours low-latency plans.
    Blocking: synchronizes stream.  Candidates: block in {64..1024} for flooding / layered;
    storage (LDS, pre global, all messages global, messages and Lt global, whole frame global as
-   arrays or as VN records) x
+   arrays or as VN records, whole frame and check keys global) x
    topology x frames per workgroup in {auto, 4, 8} x
    frames_per_cu in {auto, 1, 2, 4, 8, 16}
    (and block in {64, 256, 1024} for ME-CIRBP) for the dynamic schedules.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),

@@ -92,7 +92,7 @@ template <class A, int STORE>
 struct MsgStore<A, STORE, true> {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
-  static constexpr bool kRec = STORE == STORE_FRAME_REC;
+  static constexpr bool kRec = STORE == STORE_FRAME_REC || STORE == STORE_FRAME_ALL;
   MsgPair<msg_t>* m;  // global, [E]
   llr_t* Lt;          // LDS (STORE_ALL_GLOBAL) or global, [N]
   llr_t* Lp;          // LDS, or global (STORE_FRAME_GLOBAL), [N]
@@ -180,7 +180,8 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
       ms.Lp = reinterpret_cast<llr_t*>(base + P.slot_l_off);
       ms.Dp = reinterpret_cast<uint32_t*>(base + P.slot_d_off);
     }
-    if constexpr (STORE == STORE_FRAME_REC) ms.r = reinterpret_cast<VnRec<llr_t>*>(base + P.slot_lt_off);
+    if constexpr (STORE == STORE_FRAME_REC || STORE == STORE_FRAME_ALL)
+      ms.r = reinterpret_cast<VnRec<llr_t>*>(base + P.slot_lt_off);
   } else {
     ms.c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
     if constexpr (STORE == STORE_PRE_GLOBAL) ms.pre = reinterpret_cast<msg_t*>(P.pre_global) + frame_slot(P) * slot_edges;
@@ -193,7 +194,7 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
 // available in the record layout)
 template <class A, int STORE>
 __device__ __forceinline__ typename A::llr_t* frame_L(const MsgStore<A, STORE>& ms, const DynParams&) {
-  static_assert(STORE != STORE_FRAME_REC, "no L array in the record layout");
+  static_assert(STORE != STORE_FRAME_REC && STORE != STORE_FRAME_ALL, "no L array in the record layout");
   return ms.Lp;
 }
 
@@ -228,13 +229,17 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   // index, and the edge is found again inside the check's row when the check is selected (edge ids
   // are row-major, so (value, lowest check), then (value, lowest edge) in the row is the global
   // (value, lowest edge))
-  uint32_t* ckey = reinterpret_cast<uint32_t*>(lds + P.off_ckey);
+  constexpr bool kKeysG = STORE == STORE_FRAME_ALL;  // check keys and late-CI staging in the slot
+  unsigned char* slot = kKeysG ? reinterpret_cast<unsigned char*>(P.pre_global) + frame_slot(P) * (size_t)P.slot_bytes
+                               : nullptr;
+  uint32_t* ckey = kKeysG ? reinterpret_cast<uint32_t*>(slot + P.slot_ckey_off) : reinterpret_cast<uint32_t*>(lds + P.off_ckey);
   uint64_t* dblk = reinterpret_cast<uint64_t*>(lds + P.off_dblk);
   uint64_t* cblk = reinterpret_cast<uint64_t*>(lds + P.off_cblk);
   uint32_t* dmask = reinterpret_cast<uint32_t*>(lds + P.off_dmask);
   uint32_t* cmask = reinterpret_cast<uint32_t*>(lds + P.off_cmask);
   uint32_t* synw = reinterpret_cast<uint32_t*>(lds + P.off_syn);  // syndrome bits
-  int* tj = reinterpret_cast<int*>(lds + P.off_v);  // VN of a table lane whose CI is refreshed late
+  int* tj = kKeysG ? reinterpret_cast<int*>(slot + P.slot_tj_off)
+                   : reinterpret_cast<int*>(lds + P.off_v);  // VN of a table lane whose CI is refreshed late
   // VNs met twice in the two-hop table: per group, the sum of this update's Lt changes, the VN's
   // Lt and L before the update, the VN; a flag word of the groups changed
   llr_t* gacc = reinterpret_cast<llr_t*>(lds + P.off_grp);
@@ -607,31 +612,48 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       }
     }
     PROF_MARK(5)
-    // ---- blocks whose maximum leaf decreased ----
-    for (int w = 0; w < nbc_words; ++w) {
-      uint32_t bits = (uint32_t)uni((int)cmask[w]);
-      while (bits) {
-        const int b = w * 32 + __builtin_ctz(bits);
-        bits &= bits - 1;
-        const int m = b * WAVE + lane;
-        uint64_t k = m < M ? mkkey(ckey[m], (uint32_t)m) : 0ull;
-        k = wave_max_u64(k);
-        if (lane == 0) cblk[b] = k;
-      }
-      if (lane == 0) cmask[w] = 0u;
-    }
-    if (with_ci) {
-      for (int w = 0; w < nbd_words; ++w) {
-        uint32_t bits = (uint32_t)uni((int)dmask[w]);
-        while (bits) {
-          const int b = w * 32 + __builtin_ctz(bits);
-          bits &= bits - 1;
-          const int n = b * WAVE + lane;
-          uint64_t k = n < N ? mkkey(ms.d(n), (uint32_t)n) : 0ull;
-          k = wave_max_u64(k);
-          if (lane == 0) dblk[b] = k;
+    // ---- blocks whose maximum leaf decreased: one check block and one VN block per round, so
+    //      that their leaf loads share a round trip ----
+    {
+      int cw = 0, dw = 0;
+      uint32_t cbits = nbc_words > 0 ? (uint32_t)uni((int)cmask[0]) : 0u;
+      uint32_t dbits = (with_ci && nbd_words > 0) ? (uint32_t)uni((int)dmask[0]) : 0u;
+      while (true) {
+        while (cbits == 0u && cw + 1 < nbc_words) {
+          if (lane == 0) cmask[cw] = 0u;
+          cw += 1;
+          cbits = (uint32_t)uni((int)cmask[cw]);
         }
-        if (lane == 0) dmask[w] = 0u;
+        while (with_ci && dbits == 0u && dw + 1 < nbd_words) {
+          if (lane == 0) dmask[dw] = 0u;
+          dw += 1;
+          dbits = (uint32_t)uni((int)dmask[dw]);
+        }
+        if (cbits == 0u && dbits == 0u) break;
+        int bc = -1, bd = -1;
+        if (cbits) {
+          bc = cw * 32 + __builtin_ctz(cbits);
+          cbits &= cbits - 1;
+        }
+        if (dbits) {
+          bd = dw * 32 + __builtin_ctz(dbits);
+          dbits &= dbits - 1;
+        }
+        const int m = bc * WAVE + lane, n = bd * WAVE + lane;
+        const uint32_t kc = (bc >= 0 && m < M) ? ckey[m] : 0u;
+        const uint32_t kd = (bd >= 0 && n < N) ? ms.d(n) : 0u;
+        if (bc >= 0) {
+          const uint64_t k = wave_max_u64(m < M ? mkkey(kc, (uint32_t)m) : 0ull);
+          if (lane == 0) cblk[bc] = k;
+        }
+        if (bd >= 0) {
+          const uint64_t k = wave_max_u64(n < N ? mkkey(kd, (uint32_t)n) : 0ull);
+          if (lane == 0) dblk[bd] = k;
+        }
+      }
+      if (lane == 0) {
+        if (nbc_words > 0) cmask[cw] = 0u;
+        if (with_ci && nbd_words > 0) dmask[dw] = 0u;
       }
     }
     wave_sync();

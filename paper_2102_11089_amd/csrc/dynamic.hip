@@ -22,6 +22,9 @@
 //   CI             Lt_j += pre_new - pre_old, then D_j for the VNs of the touched checks,
 //   max trees      block maxima raised with LDS atomic max; a block whose maximum leaf
 //                  decreased is recomputed by one wave reduction.
+#include <map>
+#include <mutex>
+
 #include "dyn_frame.hpp"
 
 namespace ldpc {
@@ -95,6 +98,7 @@ static hipError_t launch_dyn_t(const DevCode& H, const DynParams& P, int topo, i
 
 template <class A>
 static hipError_t launch_dyn_s(const DevCode& H, const DynParams& P, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_FRAME_ALL) return launch_dyn_t<A, STORE_FRAME_ALL>(H, P, topo, grid, st);
   if (store == STORE_FRAME_REC) return launch_dyn_t<A, STORE_FRAME_REC>(H, P, topo, grid, st);
   if (store == STORE_FRAME_GLOBAL) return launch_dyn_t<A, STORE_FRAME_GLOBAL>(H, P, topo, grid, st);
   if (store == STORE_ALL_GLOBAL_LT) return launch_dyn_t<A, STORE_ALL_GLOBAL_LT>(H, P, topo, grid, st);
@@ -126,6 +130,48 @@ static hipError_t set_store(int bytes) {
   return e;
 }
 
+// VGPRs per lane of one kernel variant (0 if the runtime cannot tell), cached per variant
+template <class A, int ST>
+static int vgprs_of(int topo, bool mf) {
+  const void* f = nullptr;
+  if (topo == TOPO_QC) f = mf ? (const void*)k_dynamic<A, ST, TOPO_QC, true> : (const void*)k_dynamic<A, ST, TOPO_QC, false>;
+  else if (topo == TOPO_LDS) f = mf ? (const void*)k_dynamic<A, ST, TOPO_LDS, true> : (const void*)k_dynamic<A, ST, TOPO_LDS, false>;
+  else f = (const void*)k_dynamic<A, ST, TOPO_GLOBAL, false>;
+  hipFuncAttributes at{};
+  if (hipFuncGetAttributes(&at, f) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return at.numRegs;
+}
+
+template <class A>
+static int vgprs_s(int store, int topo, bool mf) {
+  switch (store) {
+    case STORE_LDS: return vgprs_of<A, STORE_LDS>(topo, mf);
+    case STORE_PRE_GLOBAL: return vgprs_of<A, STORE_PRE_GLOBAL>(topo, mf);
+    case STORE_ALL_GLOBAL: return vgprs_of<A, STORE_ALL_GLOBAL>(topo, mf);
+    case STORE_ALL_GLOBAL_LT: return vgprs_of<A, STORE_ALL_GLOBAL_LT>(topo, mf);
+    case STORE_FRAME_GLOBAL: return vgprs_of<A, STORE_FRAME_GLOBAL>(topo, mf);
+    case STORE_FRAME_REC: return vgprs_of<A, STORE_FRAME_REC>(topo, mf);
+    default: return vgprs_of<A, STORE_FRAME_ALL>(topo, mf);
+  }
+}
+
+int dynamic_waves_per_simd(bool fixed, int store, int topo, bool mf) {
+  static std::mutex mu;
+  static std::map<int, int> cache;
+  const int key = ((fixed ? 1 : 0) * kStores + store) * 8 + topo * 2 + (mf ? 1 : 0);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const int regs = fixed ? vgprs_s<ArithFix>(store, topo, mf) : vgprs_s<ArithF32>(store, topo, mf);
+  // 512 VGPRs per SIMD lane, allocated in granules of 8; at most 8 wavefronts per SIMD
+  const int waves = regs > 0 ? std::max(1, std::min(8, 512 / ((regs + 7) / 8 * 8))) : 8;
+  cache[key] = waves;
+  return waves;
+}
+
 hipError_t set_dynamic_lds_limit(int bytes) {
   hipError_t e = hipSuccess;
   for (hipError_t r : {set_store<ArithF32, STORE_LDS>(bytes), set_store<ArithF32, STORE_PRE_GLOBAL>(bytes),
@@ -133,7 +179,8 @@ hipError_t set_dynamic_lds_limit(int bytes) {
                        set_store<ArithF32, STORE_FRAME_GLOBAL>(bytes), set_store<ArithFix, STORE_LDS>(bytes),
                        set_store<ArithFix, STORE_PRE_GLOBAL>(bytes), set_store<ArithFix, STORE_ALL_GLOBAL>(bytes),
                        set_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes), set_store<ArithFix, STORE_FRAME_GLOBAL>(bytes),
-                       set_store<ArithF32, STORE_FRAME_REC>(bytes), set_store<ArithFix, STORE_FRAME_REC>(bytes)})
+                       set_store<ArithF32, STORE_FRAME_REC>(bytes), set_store<ArithFix, STORE_FRAME_REC>(bytes),
+                       set_store<ArithF32, STORE_FRAME_ALL>(bytes), set_store<ArithFix, STORE_FRAME_ALL>(bytes)})
     if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }

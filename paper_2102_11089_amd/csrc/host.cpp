@@ -132,17 +132,18 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int wpb) {
   int f = 0;
   L.off_c2v = f; if (store < STORE_ALL_GLOBAL) f = align16(f + c.E * msg);
   L.off_pre = f; if (store == STORE_LDS) f = align16(f + c.E * msg);
-  const bool frame = store == STORE_FRAME_GLOBAL || store == STORE_FRAME_REC;
+  const bool frame = store == STORE_FRAME_GLOBAL || store == STORE_FRAME_REC || store == STORE_FRAME_ALL;
   L.off_L = f; if (!frame) f = align16(f + c.N * llr);
   L.off_Lt = f; if (store < STORE_ALL_GLOBAL_LT) f = align16(f + c.N * llr);
   L.off_D = f; if (!frame) f = align16(f + c.N * 4);
-  L.off_ckey = f; f = align16(f + c.M * 4);
+  const bool keys_global = store == STORE_FRAME_ALL;
+  L.off_ckey = f; if (!keys_global) f = align16(f + c.M * 4);
   L.off_dblk = f; f = align16(f + L.nbd * 8);
   L.off_cblk = f; f = align16(f + L.nbc * 8);
   L.off_dmask = f; f = align16(f + L.nbd_words * 4);
   L.off_cmask = f; f = align16(f + L.nbc_words * 4);
   L.off_syn = f; f = align16(f + ((c.M + 31) / 32) * 4);
-  L.off_v = f; f = align16(f + std::max(1, std::min(c.nbr_passes, NBR_PMAX)) * WAVE * 4);  // touched VN per table lane
+  L.off_v = f; if (!keys_global) f = align16(f + std::max(1, std::min(c.nbr_passes, NBR_PMAX)) * WAVE * 4);  // late-CI VN per table lane
   L.off_grp = f; f = align16(f + kGroupBytes);  // sums for VNs met twice in a two-hop table
   L.frame_stride = f;
   L.wpb = wpb;
@@ -569,14 +570,21 @@ bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
 constexpr size_t kQueueBytes = 256;  // work-queue counter at the front of a persistent launch's scratch
 
 // global slot of one frame when its messages live in global memory: (c2v, pre) pairs for E edges,
-// then Lt, L and D for N VNs, each 256-byte aligned (STORE_FRAME_REC: one 16-byte record per VN)
-void all_global_slot(int E, int N, bool fixed, int store, DynParams& P) {
+// then Lt, L and D for N VNs, each 256-byte aligned (STORE_FRAME_REC: one 16-byte record per VN;
+// STORE_FRAME_ALL: the records, then M check keys and the late-CI staging)
+void all_global_slot(int E, int N, int M, int nbr_passes, bool fixed, int store, DynParams& P) {
   auto up = [](long long x) { return (x + 255) / 256 * 256; };
   const long long pairs = 2LL * E * (fixed ? 1 : 4);
   P.slot_lt_off = (int)up(pairs);
-  if (store == STORE_FRAME_REC) {
+  P.slot_ckey_off = P.slot_tj_off = 0;
+  if (store == STORE_FRAME_REC || store == STORE_FRAME_ALL) {
     P.slot_l_off = P.slot_d_off = P.slot_lt_off;
     P.slot_bytes = up(P.slot_lt_off + 16LL * N);
+    if (store == STORE_FRAME_ALL) {
+      P.slot_ckey_off = (int)P.slot_bytes;
+      P.slot_tj_off = (int)up(P.slot_ckey_off + 4LL * M);
+      P.slot_bytes = up(P.slot_tj_off + 4LL * WAVE * std::max(1, std::min(nbr_passes, NBR_PMAX)));
+    }
     return;
   }
   P.slot_l_off = (int)up(P.slot_lt_off + 4LL * N);
@@ -599,7 +607,7 @@ int check_tuning(const ldpc_tuning* t) {
   if (!t) return LDPC_OK;
   if (t->block != 0 && !valid_block(t->block)) return LDPC_EINVAL;
   if (t->frames_per_cu < 0 || t->frames_per_cu > 32) return LDPC_EINVAL;
-  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_REC) return LDPC_EINVAL;
+  if (t->storage < LDPC_STORE_AUTO || t->storage > LDPC_STORE_GLOBAL_STATE) return LDPC_EINVAL;
   if (t->topology < LDPC_TOPO_AUTO || t->topology > LDPC_TOPO_QC) return LDPC_EINVAL;
   return LDPC_OK;
 }
@@ -681,14 +689,18 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (c->nbr_max_cnt > NBR_PMAX * WAVE) return LDPC_EUNSUPPORTED;
   const std::vector<int> topos = topo_choices(c, T.topology);
   if (topos.empty()) return LDPC_EUNSUPPORTED;
-  std::vector<int> stores = {STORE_LDS,           STORE_PRE_GLOBAL,   STORE_ALL_GLOBAL,
-                             STORE_ALL_GLOBAL_LT, STORE_FRAME_GLOBAL, STORE_FRAME_REC};
+  // STORE_FRAME_ALL is the capacity fallback only: on the BG1-shaped Z=52 code its 24 resident
+  // frames per CU decoded 2% fewer frames/s than 12 with the check keys in LDS (the update loop
+  // is bound by the memory system there, not by latency)
+  std::vector<int> stores = {STORE_LDS,          STORE_PRE_GLOBAL, STORE_ALL_GLOBAL, STORE_ALL_GLOBAL_LT,
+                             STORE_FRAME_GLOBAL, STORE_FRAME_REC};
   if (T.storage == LDPC_STORE_LDS) stores = {STORE_LDS};
   if (T.storage == LDPC_STORE_GLOBAL) stores = {STORE_PRE_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_ALL) stores = {STORE_ALL_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_LT) stores = {STORE_ALL_GLOBAL_LT};
   if (T.storage == LDPC_STORE_GLOBAL_FRAME) stores = {STORE_FRAME_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_REC) stores = {STORE_FRAME_REC};
+  if (T.storage == LDPC_STORE_GLOBAL_STATE) stores = {STORE_FRAME_ALL};
   const int lut_off = 257 * (fixed ? s->frac_bits : 0);
 
   if (s->kind == LDPC_ME_CIRBP) {
@@ -781,19 +793,27 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   int best_eff = 0, best_pref = -1;
   const long long need = std::max<long long>(1, (B + ncu - 1) / ncu);
   const int cap_fpc = T.frames_per_cu ? T.frames_per_cu : 32;
+  // workgroups of w frames a CU holds: by LDS, and by wavefront slots at the variant's register
+  // count (4 SIMDs per CU)
+  auto wgs_per_cu = [&](const DynLayout& ly, int st, int tp, int w) {
+    const int by_lds = std::max(1, (160 * 1024) / std::max(ly.total, 1));
+    const int wps = dynamic_waves_per_simd(fixed, st, tp, tp != TOPO_GLOBAL && w > 1);
+    const int by_waves = std::max(1, (4 * wps) / w);
+    return std::min(by_lds, by_waves);
+  };
   for (int st : stores) {
     for (int tp : topos) {
       const int w = T.block && tp != TOPO_GLOBAL ? T.block / WAVE : 1;  // frames share LDS topology only
       DynLayout cand = dyn_layout(c, fixed, st, tp, w);
       if (cand.total > pl.lds_limit) continue;
-      const int wgs = std::max(1, (160 * 1024) / std::max(cand.total, 1));
-      const int fit = std::min(32, w * wgs);  // at most 32 wavefronts per CU
+      const int fit = std::min(32, w * wgs_per_cu(cand, st, tp, w));
       const int eff = (int)std::min<long long>(std::min(fit, cap_fpc), need);
       // Store preference: one round on the chip: LDS > PRE_GLOBAL > ALL_GLOBAL > ALL_GLOBAL_LT >
-      // FRAME_REC > FRAME_GLOBAL; larger batches: ALL_GLOBAL > ALL_GLOBAL_LT > FRAME_REC >
-      // FRAME_GLOBAL > PRE_GLOBAL > LDS (the record layout moves one cache line per touched VN
-      // where the split arrays move three)
-      static const int rank_small[6] = {5, 4, 3, 2, 0, 1}, rank_large[6] = {0, 1, 5, 4, 2, 3};
+      // FRAME_REC > FRAME_ALL > FRAME_GLOBAL; larger batches: ALL_GLOBAL > ALL_GLOBAL_LT >
+      // FRAME_REC > FRAME_ALL > FRAME_GLOBAL > PRE_GLOBAL > LDS (the record layout moves one
+      // cache line per touched VN where the split arrays move three; keys in LDS beat keys in
+      // global memory at equal residency)
+      static const int rank_small[kStores] = {6, 5, 4, 3, 0, 2, 1}, rank_large[kStores] = {0, 1, 6, 5, 2, 4, 3};
       const int st_pref = need <= 1 ? rank_small[st] : rank_large[st];
       const int tp_pref = tp == TOPO_QC ? 2 : (tp == TOPO_LDS ? 1 : 0);
       const int pref = st_pref * 4 + tp_pref;
@@ -803,6 +823,22 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
         pl.topo = tp;
         best_eff = eff;
         best_pref = pref;
+        found = true;
+      }
+    }
+  }
+  if (!found && T.storage == LDPC_STORE_AUTO) {  // nothing else fits: check keys to global memory too
+    for (int tp : topos) {
+      const int w = T.block && tp != TOPO_GLOBAL ? T.block / WAVE : 1;
+      DynLayout cand = dyn_layout(c, fixed, STORE_FRAME_ALL, tp, w);
+      if (cand.total > pl.lds_limit) continue;
+      const int eff = (int)std::min<long long>(
+          std::min(std::min(32, w * wgs_per_cu(cand, STORE_FRAME_ALL, tp, w)), cap_fpc), need);
+      if (!found || eff > best_eff) {
+        Ly = cand;
+        pl.store = STORE_FRAME_ALL;
+        pl.topo = tp;
+        best_eff = eff;
         found = true;
       }
     }
@@ -818,7 +854,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     for (int ww = 2; ww <= 16; ++ww) {
       DynLayout cand = dyn_layout(c, fixed, pl.store, TOPO_QC, ww);
       if (cand.total > pl.lds_limit) break;
-      const int fit = std::min(32, ww * std::max(1, (160 * 1024) / std::max(cand.total, 1)));
+      const int fit = std::min(32, ww * wgs_per_cu(cand, pl.store, TOPO_QC, ww));
       if (fit > best_fit) {
         best_fit = fit;
         best_w = ww;
@@ -850,7 +886,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   pl.persistent = pl.store != STORE_LDS || T.frames_per_cu || need > 1;
   const long long wg_needed = (B + P.wpb - 1) / P.wpb;
   if (pl.persistent) {
-    const int wgs = std::max(1, (160 * 1024) / std::max(P.lds_bytes, 1));
+    const int wgs = wgs_per_cu(Ly, pl.store, pl.topo, P.wpb);
     const int wg_per_cu = std::max(1, std::min(wgs, std::min(32, cap_fpc) / P.wpb));
     pl.grid = (int)std::min<long long>(wg_needed, (long long)ncu * wg_per_cu);
   } else {
@@ -861,7 +897,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (pl.persistent) pl.scratch_bytes = kQueueBytes;  // work-queue counter, then message slots
   if (pl.store == STORE_PRE_GLOBAL) pl.scratch_bytes += slots * c->E * msg;
   if (pl.store >= STORE_ALL_GLOBAL) {
-    all_global_slot(c->E, c->N, fixed, pl.store, P);
+    all_global_slot(c->E, c->N, c->M, (c->nbr_max_cnt + WAVE - 1) / WAVE, fixed, pl.store, P);
     pl.scratch_bytes += slots * (size_t)P.slot_bytes;
   }
   return LDPC_OK;
@@ -960,7 +996,9 @@ int ldpc_describe_plan(const ldpc_code* c, const ldpc_schedule* s, int32_t B, ld
   r.frames_per_workgroup = pl.which == 1 ? pl.dyn.wpb : 1;
   const int lds = pl.which == 0 ? pl.base.lds_bytes : (pl.which == 1 ? pl.dyn.lds_bytes : pl.me.lds_bytes);
   const int by_lds = std::max(1, (160 * 1024) / std::max(lds, 1));
-  const int by_waves = std::max(1, 32 / std::max(1, pl.block / WAVE));
+  const int wps = pl.which == 1 ? dynamic_waves_per_simd(pl.fixed, pl.store, pl.topo, pl.topo != TOPO_GLOBAL && pl.dyn.wpb > 1)
+                                : 8;
+  const int by_waves = std::max(1, 4 * wps / std::max(1, pl.block / WAVE));
   r.workgroups_per_cu = std::min(by_lds, by_waves);
   r.persistent = pl.which == 1 ? (pl.persistent ? 1 : 0) : (pl.which == 2 && pl.grid < B ? 1 : 0);
   r.lds_bytes = lds;
@@ -1002,7 +1040,7 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
     const std::vector<int> blocks = s->kind == LDPC_ME_CIRBP ? std::vector<int>{64, 256, 1024} : std::vector<int>{0};
     for (int b : blocks)
       for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL, LDPC_STORE_GLOBAL_LT,
-                        LDPC_STORE_GLOBAL_FRAME, LDPC_STORE_GLOBAL_REC})
+                        LDPC_STORE_GLOBAL_FRAME, LDPC_STORE_GLOBAL_REC, LDPC_STORE_GLOBAL_STATE})
         for (int tp : tps)
           for (int fpc : {0, 1, 2, 4, 8, 16})
             for (int wb : s->kind == LDPC_ME_CIRBP ? std::vector<int>{0} : std::vector<int>{0, 256, 512})
@@ -1207,7 +1245,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   size_t pre_bytes = 0;
   if (store == STORE_PRE_GLOBAL) pre_bytes = (size_t)grid * mx.E * (fixed ? 1 : 4);
   if (store >= STORE_ALL_GLOBAL) {
-    all_global_slot(mx.E, mx.N, fixed, store, P);
+    all_global_slot(mx.E, mx.N, mx.M, mx.nbr_passes, fixed, store, P);
     pre_bytes = (size_t)grid * (size_t)P.slot_bytes;
   }
   void* scratch = nullptr;

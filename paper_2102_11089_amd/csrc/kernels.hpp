@@ -12,15 +12,19 @@ enum Topo { TOPO_GLOBAL = 0, TOPO_LDS = 1, TOPO_QC = 2 };
 // single-edge frame storage: c2v and pre in LDS; pre in a global slot; both in a global slot; both
 // and the precomputed totals Lt in a global slot; the whole frame (messages, Lt, L, D) in a global
 // slot, leaving only check keys, block maxima, syndrome bits and staging in LDS; the same with the
-// three per-VN values of a VN in one 16-byte record (one cache line per touched VN instead of three)
+// three per-VN values of a VN in one 16-byte record (one cache line per touched VN instead of three);
+// and that with the check keys and the late-CI staging in the slot as well (LDS keeps only block
+// maxima, dirty masks, syndrome bits and the repeated-VN groups: the most frames per CU)
 enum Store {
   STORE_LDS = 0,
   STORE_PRE_GLOBAL = 1,
   STORE_ALL_GLOBAL = 2,
   STORE_ALL_GLOBAL_LT = 3,
   STORE_FRAME_GLOBAL = 4,
-  STORE_FRAME_REC = 5
+  STORE_FRAME_REC = 5,
+  STORE_FRAME_ALL = 6
 };
+constexpr int kStores = 7;
 
 struct DecOut {
   uint8_t* bits;            // [B][N]
@@ -57,6 +61,8 @@ struct DynParams {
                             // VN records) in a slot
   int slot_l_off;           // STORE_FRAME_GLOBAL: byte offsets of L and D in a slot
   int slot_d_off;
+  int slot_ckey_off;        // STORE_FRAME_ALL: byte offsets of the check keys and the late-CI
+  int slot_tj_off;          // staging in a slot
   int* queue;               // persistent launch: next-frame counter (zeroed before launch); null:
                             // workgroup b decodes frames b, b + grid, ...
   // ME-CIRBP
@@ -157,6 +163,8 @@ struct TopoSel<TOPO_QC> {
 hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, int store, int topo, int grid,
                           hipStream_t st);
 hipError_t set_dynamic_lds_limit(int bytes);
+// wavefronts of one single-edge kernel variant a SIMD can hold by its register count (1..8)
+int dynamic_waves_per_simd(bool fixed, int store, int topo, bool mf);
 hipError_t launch_baseline(const DevCode& H, const BaseParams& P, bool fixed, int grid, int block,
                            hipStream_t st);
 hipError_t set_baseline_lds_limit(int bytes);

@@ -32,8 +32,8 @@ EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_co
            "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
            "ldpc_strerror", "ldpc_last_hip_error")
 UNROLL_MAX_CKPT_EVERY = 128
-STORE_AUTO, STORE_LDS, STORE_GLOBAL, STORE_GLOBAL_ALL, STORE_GLOBAL_LT, STORE_GLOBAL_FRAME, STORE_GLOBAL_REC = \
-    0, 1, 2, 3, 4, 5, 6
+STORE_AUTO, STORE_LDS, STORE_GLOBAL, STORE_GLOBAL_ALL, STORE_GLOBAL_LT, STORE_GLOBAL_FRAME, STORE_GLOBAL_REC, \
+    STORE_GLOBAL_STATE = 0, 1, 2, 3, 4, 5, 6, 7
 TOPO_AUTO, TOPO_GLOBAL, TOPO_LDS, TOPO_QC = 0, 1, 2, 3
 
 # layout of ldpc_frame_desc (40 bytes)
@@ -470,7 +470,8 @@ def set_tuning(code: Code, kind: int, arith: int, block: int = 0, frames_per_cu:
 
 
 STORE_NAMES = {STORE_LDS: "lds", STORE_GLOBAL: "global", STORE_GLOBAL_ALL: "global_all",
-               STORE_GLOBAL_LT: "global_lt", STORE_GLOBAL_FRAME: "global_frame", STORE_GLOBAL_REC: "global_rec"}
+               STORE_GLOBAL_LT: "global_lt", STORE_GLOBAL_FRAME: "global_frame", STORE_GLOBAL_REC: "global_rec",
+               STORE_GLOBAL_STATE: "global_state"}
 TOPO_NAMES = {TOPO_GLOBAL: "global", TOPO_LDS: "lds", TOPO_QC: "qc"}
 
 

@@ -234,7 +234,7 @@ def test_edge_cases(gpu, c0):
 # ------------------------------------------------------------------------------------------
 # storage variants: every (pre location, topology source) combination is bit-exact
 # ------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("pre", ["lds", "global", "all", "all_lt", "frame", "rec"])
+@pytest.mark.parametrize("pre", ["lds", "global", "all", "all_lt", "frame", "rec", "state"])
 @pytest.mark.parametrize("topo", ["global", "lds", "qc"])
 @pytest.mark.parametrize("fpc", [0, 3])
 def test_fixed_storage_variants(gpu, pre, topo, fpc):
@@ -244,7 +244,8 @@ def test_fixed_storage_variants(gpu, pre, topo, fpc):
     ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=1500, q_bits=8, frac_bits=2, trace=True, dump=True,
                    threads=8)
     store = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL,
-             "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME, "rec": gpu.STORE_GLOBAL_REC}[pre]
+             "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME, "rec": gpu.STORE_GLOBAL_REC,
+             "state": gpu.STORE_GLOBAL_STATE}[pre]
     tp = {"global": gpu.TOPO_GLOBAL, "lds": gpu.TOPO_LDS, "qc": gpu.TOPO_QC}[topo]
     handles = [gpu.Code(code)] if topo == "qc" else [gpu.Code(code), gpu.Code(code, csr=True)]
     for h in handles:
@@ -262,14 +263,15 @@ def test_fixed_storage_variants(gpu, pre, topo, fpc):
         np.testing.assert_array_equal(np_(g.D), ref.D)
 
 
-@pytest.mark.parametrize("store", ["lds", "all", "rec"])
+@pytest.mark.parametrize("store", ["lds", "all", "rec", "state"])
 @pytest.mark.parametrize("kind", ["cirbp", "rbp", "replay"])
 def test_fixed_degree_one_vns(gpu, store, kind):
     """BG1-shaped base graph lifted by Z = 4 (n = 272): updates of degree-1 VNs (whose only check
     is the updated edge's check) refresh that check's key without a row pass; bit-exact."""
     code = S.qc_bg1_shaped(4, seed=3)
     cw, llr = S.frames(code, 96, 1.0, 113)
-    st = {"lds": gpu.STORE_LDS, "all": gpu.STORE_GLOBAL_ALL, "rec": gpu.STORE_GLOBAL_REC}[store]
+    st = {"lds": gpu.STORE_LDS, "all": gpu.STORE_GLOBAL_ALL, "rec": gpu.STORE_GLOBAL_REC,
+          "state": gpu.STORE_GLOBAL_STATE}[store]
     say(f"[degree-1 VNs] bg1 Z=4 {kind} store={store}")
     kw = dict(max_updates=2000, q_bits=8, frac_bits=2, trace=True, dump=True)
     rep = None
@@ -294,6 +296,23 @@ def test_fixed_degree_one_vns(gpu, store, kind):
         np.testing.assert_array_equal(np_(g.D), ref.D)
 
 
+def test_fixed_capacity_fallback_large_code(gpu):
+    """A code whose check keys alone exceed a CU's LDS (BG1-shaped base lifted by Z = 900:
+    m = 41400) decodes with the keys in global memory, bit-exact."""
+    code = S.qc_bg1_shaped(900, seed=3)
+    h = gpu.Code(code)
+    d = gpu.describe_plan(h, 2, gpu.CIRBP, gpu.MS_FIX, q_bits=8, frac_bits=2)
+    say(f"[capacity fallback] bg1 Z=900 plan {d}")
+    assert d["storage"] == gpu.STORE_GLOBAL_STATE
+    cw, llr = S.frames(code, 2, 1.5, 114, zero_codeword=True)
+    kw = dict(max_updates=1500, q_bits=8, frac_bits=2, trace=True)
+    ref = O.decode(code, llr, O.CIRBP, O.MSFIX, threads=2, **kw)
+    g = gpu_decode(gpu, h, llr, "cirbp", gpu.MS_FIX, **kw)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+
+
 def many_four_cycles_code():
     """Six checks of degree 16 on 32 VNs with heavy overlap: the two-hop table of a VN lists up to
     27 other VNs more than once (more than the kernels' LDS groups hold), in up to two passes."""
@@ -306,14 +325,14 @@ def many_four_cycles_code():
     return S.code_from_rows(6, 32, rows, name="overlap32")
 
 
-@pytest.mark.parametrize("store", ["lds", "rec"])
+@pytest.mark.parametrize("store", ["lds", "rec", "state"])
 def test_fixed_repeated_two_hop_vns_bit_exact(gpu, store):
     """VNs met on several checks of the updated VN (4-cycles): their precomputed totals take every
     change of the update, through the LDS groups and through the overflow path."""
     code = many_four_cycles_code()
     h = gpu.Code(code)
     cw, llr = S.frames(code, 200, 1.0, 112)
-    st = {"lds": gpu.STORE_LDS, "rec": gpu.STORE_GLOBAL_REC}[store]
+    st = {"lds": gpu.STORE_LDS, "rec": gpu.STORE_GLOBAL_REC, "state": gpu.STORE_GLOBAL_STATE}[store]
     say(f"[repeated two-hop VNs] overlap32 store={store}")
     ref = O.decode(code, llr, O.CIRBP, O.MSFIX, max_updates=400, check_every=0, q_bits=8, frac_bits=2, trace=True,
                    dump=True, threads=8)
@@ -458,7 +477,7 @@ def test_batch_rejects_bad_descriptors(gpu):
     assert u[0] >= 0 and u[5] >= 0
 
 
-@pytest.mark.parametrize("store", ["lds", "global", "all", "all_lt", "frame", "rec"])
+@pytest.mark.parametrize("store", ["lds", "global", "all", "all_lt", "frame", "rec", "state"])
 def test_f32_storage_modes_identical(gpu, store):
     """FP32 results do not depend on where the messages live (same arithmetic, same order)."""
     code = S.workload_code("c4")
@@ -468,7 +487,8 @@ def test_f32_storage_modes_identical(gpu, store):
     gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, clear=True)
     base = gpu.decode(h, t, gpu.CIRBP, gpu.SPA_F32, max_updates=4000, trace=True)
     st = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL,
-          "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME, "rec": gpu.STORE_GLOBAL_REC}[store]
+          "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME, "rec": gpu.STORE_GLOBAL_REC,
+          "state": gpu.STORE_GLOBAL_STATE}[store]
     gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, storage=st, frames_per_cu=2)
     try:
         r = gpu.decode(h, t, gpu.CIRBP, gpu.SPA_F32, max_updates=4000, trace=True)
