@@ -43,6 +43,7 @@ template <class A, int STORE, bool PAIRS = (STORE >= STORE_ALL_GLOBAL)>
 struct MsgStore {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
+  static constexpr bool kDerivedD = false;
   msg_t* c2v;  // LDS
   msg_t* pre;  // LDS (STORE_LDS) or global (STORE_PRE_GLOBAL)
   llr_t* Lt;   // LDS
@@ -78,14 +79,12 @@ struct alignas(2 * sizeof(msg_t)) MsgPair {
   msg_t c, p;
 };
 
-// per-VN record of STORE_FRAME_REC: (Lt, D) first so that the pair written after a row update is
-// one aligned 8-byte store
+// per-VN record of the record layouts: Lt and L in one aligned 8-byte word.  D is not stored: it
+// is the function ci(L, Lt) of the record and is evaluated where it is needed (kDerivedD).
 template <class llr_t>
-struct alignas(16) VnRec {
+struct alignas(8) VnRec {
   llr_t lt;
-  uint32_t d;
   llr_t l;
-  uint32_t pad;
 };
 
 template <class A, int STORE>
@@ -93,6 +92,7 @@ struct MsgStore<A, STORE, true> {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   static constexpr bool kRec = STORE == STORE_FRAME_REC || STORE == STORE_FRAME_ALL;
+  static constexpr bool kDerivedD = kRec;
   MsgPair<msg_t>* m;  // global, [E]
   llr_t* Lt;          // LDS (STORE_ALL_GLOBAL) or global, [N]
   llr_t* Lp;          // LDS, or global (STORE_FRAME_GLOBAL), [N]
@@ -127,17 +127,16 @@ struct MsgStore<A, STORE, true> {
     if constexpr (kRec) r[n].l = v;
     else Lp[n] = v;
   }
-  __device__ __forceinline__ uint32_t d(int n) const {
-    if constexpr (kRec) return r[n].d;
-    else return Dp[n];
+  __device__ __forceinline__ uint32_t d(int n) const {  // stored CI (not for the record layouts)
+    static_assert(!kRec, "the record layouts derive D from the record");
+    return Dp[n];
   }
   __device__ __forceinline__ void set_d(int n, uint32_t v) const {
-    if constexpr (kRec) r[n].d = v;
-    else Dp[n] = v;
+    if constexpr (!kRec) Dp[n] = v;
   }
   __device__ __forceinline__ void lt_l(int n, llr_t& ltv, llr_t& lv) const {
     if constexpr (kRec) {
-      const VnRec<llr_t> x = r[n];  // one 16-byte load
+      const VnRec<llr_t> x = r[n];  // one 8-byte load
       ltv = x.lt;
       lv = x.l;
     } else {
@@ -147,11 +146,7 @@ struct MsgStore<A, STORE, true> {
   }
   __device__ __forceinline__ void set_lt_d(int n, llr_t ltv, uint32_t dv) const {
     if constexpr (kRec) {
-      struct alignas(8) LtD {
-        llr_t lt;
-        uint32_t d;
-      };
-      *reinterpret_cast<LtD*>(&r[n]) = LtD{ltv, dv};
+      r[n].lt = ltv;  // D follows from the record
     } else {
       Lt[n] = ltv;
       Dp[n] = dv;
@@ -229,17 +224,18 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   // index, and the edge is found again inside the check's row when the check is selected (edge ids
   // are row-major, so (value, lowest check), then (value, lowest edge) in the row is the global
   // (value, lowest edge))
-  constexpr bool kKeysG = STORE == STORE_FRAME_ALL;  // check keys and late-CI staging in the slot
-  unsigned char* slot = kKeysG ? reinterpret_cast<unsigned char*>(P.pre_global) + frame_slot(P) * (size_t)P.slot_bytes
-                               : nullptr;
+  constexpr bool kKeysG = STORE == STORE_FRAME_ALL;  // check keys in the slot
+  constexpr bool kStageG = STORE >= STORE_ALL_GLOBAL;  // late-CI staging in the slot
+  unsigned char* slot = kStageG ? reinterpret_cast<unsigned char*>(P.pre_global) + frame_slot(P) * (size_t)P.slot_bytes
+                                : nullptr;
   uint32_t* ckey = kKeysG ? reinterpret_cast<uint32_t*>(slot + P.slot_ckey_off) : reinterpret_cast<uint32_t*>(lds + P.off_ckey);
   uint64_t* dblk = reinterpret_cast<uint64_t*>(lds + P.off_dblk);
   uint64_t* cblk = reinterpret_cast<uint64_t*>(lds + P.off_cblk);
   uint32_t* dmask = reinterpret_cast<uint32_t*>(lds + P.off_dmask);
   uint32_t* cmask = reinterpret_cast<uint32_t*>(lds + P.off_cmask);
   uint32_t* synw = reinterpret_cast<uint32_t*>(lds + P.off_syn);  // syndrome bits
-  int* tj = kKeysG ? reinterpret_cast<int*>(slot + P.slot_tj_off)
-                   : reinterpret_cast<int*>(lds + P.off_v);  // VN of a table lane whose CI is refreshed late
+  int* tj = kStageG ? reinterpret_cast<int*>(slot + P.slot_tj_off)
+                    : reinterpret_cast<int*>(lds + P.off_v);  // VN of a table lane whose CI is refreshed late
   // VNs met twice in the two-hop table: per group, the sum of this update's Lt changes, the VN's
   // Lt and L before the update, the VN; a flag word of the groups changed
   llr_t* gacc = reinterpret_cast<llr_t*>(lds + P.off_grp);
@@ -251,6 +247,16 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   const int nbd = (N + WAVE - 1) / WAVE, nbc = (M + WAVE - 1) / WAVE;
   const int nbd_words = (nbd + 31) / 32, nbc_words = (nbc + 31) / 32;
   const bool with_ci = J.kind != KIND_RBP;
+  // CI of VN n: stored, or evaluated from the VN's record (record layouts); RBP keeps none
+  auto d_of = [&](int n) -> uint32_t {
+    if constexpr (MsgStore<A, STORE>::kDerivedD) {
+      llr_t ltv, lv;
+      ms.lt_l(n, ltv, lv);
+      return with_ci ? ar.ci((val_t)lv, (val_t)ltv) : 0u;
+    } else {
+      return ms.d(n);
+    }
+  };
   // ---------------- Algorithm 1 lines 1-3: initial state --------------------------------
   const float* llr = J.llr;
   for (int n = lane; n < N; n += WAVE) ms.set_l(n, (llr_t)ar.channel(llr[n]));
@@ -300,7 +306,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   wave_sync();
   for (int b = 0; b < nbd; ++b) {
     const int n = b * WAVE + lane;
-    uint64_t k = n < N ? mkkey(ms.d(n), (uint32_t)n) : 0ull;
+    uint64_t k = n < N ? mkkey(d_of(n), (uint32_t)n) : 0ull;
     k = wave_max_u64(k);
     if (lane == 0) dblk[b] = k;
   }
@@ -641,7 +647,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         }
         const int m = bc * WAVE + lane, n = bd * WAVE + lane;
         const uint32_t kc = (bc >= 0 && m < M) ? ckey[m] : 0u;
-        const uint32_t kd = (bd >= 0 && n < N) ? ms.d(n) : 0u;
+        const uint32_t kd = (bd >= 0 && n < N) ? d_of(n) : 0u;
         if (bc >= 0) {
           const uint64_t k = wave_max_u64(m < M ? mkkey(kc, (uint32_t)m) : 0ull);
           if (lane == 0) cblk[bc] = k;
@@ -677,7 +683,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     if (J.llr_out) J.llr_out[n] = ar.out_llr(l);
     if (J.dump_L) J.dump_L[n] = ar.as_float(l);
     if (J.dump_Lt) J.dump_Lt[n] = ar.as_float((val_t)ms.lt(n));
-    if (J.dump_D) J.dump_D[n] = ar.d_float(ms.d(n));
+    if (J.dump_D) J.dump_D[n] = ar.d_float(d_of(n));
   }
   for (int e = lane; e < E; e += WAVE) {
     if (J.dump_c2v) J.dump_c2v[e] = ar.as_float((val_t)ms.c(e));

@@ -143,7 +143,8 @@ DynLayout dyn_layout_dims(const Dims& c, bool fixed, int store, int wpb) {
   L.off_dmask = f; f = align16(f + L.nbd_words * 4);
   L.off_cmask = f; f = align16(f + L.nbc_words * 4);
   L.off_syn = f; f = align16(f + ((c.M + 31) / 32) * 4);
-  L.off_v = f; if (!keys_global) f = align16(f + std::max(1, std::min(c.nbr_passes, NBR_PMAX)) * WAVE * 4);  // late-CI VN per table lane
+  // late-CI VN per table lane (in the global slot when the frame has one)
+  L.off_v = f; if (store < STORE_ALL_GLOBAL) f = align16(f + std::max(1, std::min(c.nbr_passes, NBR_PMAX)) * WAVE * 4);
   L.off_grp = f; f = align16(f + kGroupBytes);  // sums for VNs met twice in a two-hop table
   L.frame_stride = f;
   L.wpb = wpb;
@@ -569,27 +570,31 @@ bool valid_block(int b) { return b >= 64 && b <= 1024 && b % 64 == 0; }
 
 constexpr size_t kQueueBytes = 256;  // work-queue counter at the front of a persistent launch's scratch
 
-// global slot of one frame when its messages live in global memory: (c2v, pre) pairs for E edges,
-// then Lt, L and D for N VNs, each 256-byte aligned (STORE_FRAME_REC: one 16-byte record per VN;
-// STORE_FRAME_ALL: the records, then M check keys and the late-CI staging)
+// global slot of one frame when its messages live in global memory, each part 256-byte aligned:
+// (c2v, pre) pairs for E edges; Lt (messages + Lt), or Lt, L and D (split arrays), or one 8-byte
+// (Lt, L) record per VN (record layouts); the M check keys (keys global); the late-CI staging
 void all_global_slot(int E, int N, int M, int nbr_passes, bool fixed, int store, DynParams& P) {
   auto up = [](long long x) { return (x + 255) / 256 * 256; };
-  const long long pairs = 2LL * E * (fixed ? 1 : 4);
-  P.slot_lt_off = (int)up(pairs);
-  P.slot_ckey_off = P.slot_tj_off = 0;
+  long long o = up(2LL * E * (fixed ? 1 : 4));
+  P.slot_lt_off = P.slot_l_off = P.slot_d_off = (int)o;
+  P.slot_ckey_off = 0;
   if (store == STORE_FRAME_REC || store == STORE_FRAME_ALL) {
-    P.slot_l_off = P.slot_d_off = P.slot_lt_off;
-    P.slot_bytes = up(P.slot_lt_off + 16LL * N);
-    if (store == STORE_FRAME_ALL) {
-      P.slot_ckey_off = (int)P.slot_bytes;
-      P.slot_tj_off = (int)up(P.slot_ckey_off + 4LL * M);
-      P.slot_bytes = up(P.slot_tj_off + 4LL * WAVE * std::max(1, std::min(nbr_passes, NBR_PMAX)));
+    o = up(o + 8LL * N);
+  } else {
+    if (store >= STORE_ALL_GLOBAL_LT) o = up(o + 4LL * N);
+    if (store == STORE_FRAME_GLOBAL) {
+      P.slot_l_off = (int)o;
+      o = up(o + 4LL * N);
+      P.slot_d_off = (int)o;
+      o = up(o + 4LL * N);
     }
-    return;
   }
-  P.slot_l_off = (int)up(P.slot_lt_off + 4LL * N);
-  P.slot_d_off = (int)up(P.slot_l_off + 4LL * N);
-  P.slot_bytes = up(P.slot_d_off + 4LL * N);
+  if (store == STORE_FRAME_ALL) {
+    P.slot_ckey_off = (int)o;
+    o = up(o + 4LL * M);
+  }
+  P.slot_tj_off = (int)o;
+  P.slot_bytes = up(o + 4LL * WAVE * std::max(1, std::min(nbr_passes, NBR_PMAX)));
 }
 
 // tuning knob -> candidate topologies (empty: the knob does not apply to this code)
