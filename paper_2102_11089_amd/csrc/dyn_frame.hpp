@@ -334,9 +334,36 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     bool have_star = false;
     bool have_row = false;                        // lane p holds the pairs of edge row_start(m*) + p
     msg_t row_cm = (msg_t)0, row_pm = (msg_t)0;
+    // n*'s record and two-hop table entries are requested as soon as n* is known (on the CI path
+    // before the selection's own loads), so that their round trips overlap
+    int dv = 0, ncnt = 0, npass = 0, noff = 0, rs_m = 0, re_m = 0, dc_m = 0;
+    bool row_only = false;  // n* on no check but m*: nothing is precomputed again
+    llr_t lt_n = (llr_t)0, l_n = (llr_t)0;
+    int2 ent0 = make_int2(-1, 0), ent_next = make_int2(-1, 0);
+    auto load_ent = [&](int ps) -> int2 {
+      const int idx = ps * WAVE + lane;
+      return idx < ncnt ? H.nbr[noff + idx] : make_int2(-1, 0);
+    };
+    auto start_nstar = [&](int n) {
+      if (with_ci) ms.lt_l(n, lt_n, l_n);
+      else l_n = ms.l(n);
+      dv = uni(G.vn_deg(n));
+      row_only = dv == 1;
+      if (!row_only) {
+        const int2 nb = G.nbr(n);
+        noff = uni(nb.x);
+        ncnt = uni(nb.y);
+        npass = (ncnt + WAVE - 1) / WAVE;
+        ent0 = load_ent(0);
+        if (npass > 1) ent_next = load_ent(1);
+      }
+    };
     if (J.kind == KIND_REPLAY) {
       estar = uni(J.replay[t]);
       if (estar < 0 || estar >= E) break;  // invalid edge id ends the frame's replay
+      mstar = uni(G.edge_row(estar));
+      nstar = uni(G.edge_vn(estar));
+      start_nstar(nstar);
     } else {
       bool global_res = J.kind == KIND_RBP;
       int nsel = -1;
@@ -364,6 +391,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         estar = (int)key_idx(wave_max_u64(ke));
         mstar = mrow;
         nstar = uni(G.row_vn(mrow, rs, estar - rs));
+        start_nstar(nstar);
         c_star = lane_value(cm, estar - rs);
         p_star = lane_value(pm, estar - rs);
         have_star = true;
@@ -371,11 +399,12 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         row_cm = cm;
         row_pm = pm;
       } else {
-        const int dvs = uni(G.vn_deg(nsel));
+        nstar = nsel;
+        start_nstar(nstar);
         uint64_t k = 0;
         int mk = -1;
         msg_t cm = (msg_t)0, pm = (msg_t)0;
-        if (lane < dvs) {
+        if (lane < dv) {
           int e;
           G.vn_edge(nsel, lane, mk, e);
           ms.cp(e, cm, pm);
@@ -383,48 +412,29 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         }
         const uint64_t kmax = wave_max_u64(k);
         estar = (int)key_idx(kmax);
-        const unsigned long long win = __ballot(lane < dvs && k == kmax);
+        const unsigned long long win = __ballot(lane < dv && k == kmax);
         const int wl = (int)__builtin_ctzll(win);
         mstar = __builtin_amdgcn_readlane(mk, wl);
-        nstar = nsel;
         c_star = lane_value(cm, wl);
         p_star = lane_value(pm, wl);
         have_star = true;
       }
     }
-    if (mstar < 0) {
-      mstar = uni(G.edge_row(estar));
-      nstar = uni(G.edge_vn(estar));
-    }
     PROF_MARK(0)
-    const int dv = uni(G.vn_deg(nstar));
     int my_m = -1;
     if (lane < dv) {
       int e;
       G.vn_edge(nstar, lane, my_m, e);
     }
-    const int rs_m = uni(G.row_start(mstar));
-    const int dc_m = uni(G.row_deg(mstar));
-    const int re_m = rs_m + dc_m;
-    // n* on no check but m*: nothing is precomputed again, only m*'s residual key changes
-    const bool row_only = dv == 1;
-    int ncnt = 0, npass = 0, noff = 0;
-    if (!row_only) {
-      const int2 nb = G.nbr(nstar);
-      noff = uni(nb.x);
-      ncnt = uni(nb.y);
-      npass = (ncnt + WAVE - 1) / WAVE;
-    }
+    rs_m = uni(G.row_start(mstar));
+    dc_m = uni(G.row_deg(mstar));
+    re_m = rs_m + dc_m;
     // Inputs of the touched-check passes are loaded ahead of use: table entries two passes ahead,
     // message pairs, L and Lt one pass ahead.  Nothing a pass writes is read by a later pass
     // except Lt of a VN listed twice in the two-hop table (such VNs take the summed paths below and
     // do not use the early value), and propagation changes only c2v[e*] and L[n*] (both
     // overridden where used), so the early loads see the values the passes need.  Lanes of m*'s
     // row and of n* itself update nothing and load no VN record.
-    auto load_ent = [&](int ps) -> int2 {
-      const int idx = ps * WAVE + lane;
-      return idx < ncnt ? H.nbr[noff + idx] : make_int2(-1, 0);
-    };
     struct PassIn {
       int2 ent;
       msg_t cm, pm;
@@ -447,8 +457,6 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       }
       return q;
     };
-    const int2 ent0 = row_only ? make_int2(-1, 0) : load_ent(0);
-    int2 ent_next = npass > 1 ? load_ent(1) : make_int2(-1, 0);
 
     // ---- propagation (Algorithm 1 line 9) and D_{n*} ----
     if (!have_star) ms.cp(estar, c_star, p_star);
@@ -457,9 +465,6 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     else if (!have_row && lane < dc_m) ms.cp(rs_m + lane, row_cm, row_pm);
     const val_t newv = (val_t)p_star;
     const val_t oldv = (val_t)c_star;
-    llr_t lt_n = (llr_t)0, l_n;
-    if (with_ci) ms.lt_l(nstar, lt_n, l_n);
-    else l_n = ms.l(nstar);
     const val_t Lold = (val_t)l_n;
     const val_t Lnew = Lold + (newv - oldv);
     const uint32_t dn_new = with_ci ? ar.ci(Lnew, (val_t)lt_n) : 0u;
