@@ -195,6 +195,19 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// value of another lane (the lane index is wave-uniform)
+template <class T>
+__device__ __forceinline__ T lane_value(T x, int l) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+  else return (T)__builtin_amdgcn_readlane((int)x, l);
+}
+
+// the C2V message and the precomputed message of one edge, side by side: one load brings both
+template <class msg_t>
+struct alignas(2 * sizeof(msg_t)) MsgPair {
+  msg_t c, p;
+};
+
 // ------------------------------------------------------------------------------------------
 // FP32 sum-product
 // ------------------------------------------------------------------------------------------
@@ -367,6 +380,36 @@ template <> struct RowAccOf<ArithFix> { using type = RowAccFix; };
 // per-input auxiliary value stored next to each V2C (phi for sum-product, unused for min-sum)
 __device__ __forceinline__ float row_aux(const ArithF32&, float v) { return phi_f32(fabsf(v)); }
 __device__ __forceinline__ float row_aux(const ArithFix&, int) { return 0.0f; }
+
+// Whole-row check update (eq. (2)) for the lane's edge, one row per aligned block of 2^L2 lanes:
+// the lane holds input v of edge e (valid) or nothing; every lane of the wavefront must take part
+// (maxL2 wave-uniform, the largest block of the wavefront).  Returns the lane's C2V output: the
+// row's parity and smallest other magnitude (min-sum), or phi of the other inputs' phi-sum clamped
+// by that magnitude (sum-product).
+template <class A>
+__device__ __forceinline__ typename A::val_t row_update_lane(const A& ar, bool valid, uint32_t e,
+                                                             typename A::val_t v, int L2, int maxL2) {
+  RowRed r;
+  r.m1 = valid ? fabsf((float)v) : __builtin_inff();
+  r.m2 = __builtin_inff();
+  r.ap = (valid ? e : 0x7FFFFFFFu) | (valid && v < 0 ? 0x80000000u : 0u);
+  if constexpr (A::kFixed) {
+    rowred_all<false>(r, L2, maxL2);
+    const bool me = e == (r.ap & 0x7FFFFFFFu);
+    const int mag = (int)(me ? r.m2 : r.m1);
+    return (((r.ap >> 31) ^ (v < 0 ? 1u : 0u)) & 1u) ? -mag : mag;
+  } else {
+    const float ph = valid ? row_aux(ar, v) : 0.0f;
+    r.S = ph;
+    r.Sx = 0.0f;
+    rowred_all<true>(r, L2, maxL2);
+    const bool me = e == (r.ap & 0x7FFFFFFFu);
+    const float mo = me ? r.m2 : r.m1;
+    const float Sj = me ? r.Sx : (ph == __builtin_inff() ? __builtin_inff() : r.S - ph);
+    const float mag = fminf(phi_f32(fmaxf(Sj, 0.0f)), mo);
+    return (((r.ap >> 31) ^ (v < 0.0f ? 1u : 0u)) & 1u) ? -mag : mag;
+  }
+}
 
 // ------------------------------------------------------------------------------------------
 // code topology as seen by a kernel

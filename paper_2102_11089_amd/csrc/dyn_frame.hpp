@@ -74,11 +74,6 @@ struct MsgStore {
   }
 };
 
-template <class msg_t>
-struct alignas(2 * sizeof(msg_t)) MsgPair {
-  msg_t c, p;
-};
-
 // per-VN record of the record layouts: Lt and L in one aligned 8-byte word.  D is not stored: it
 // is the function ci(L, Lt) of the record and is evaluated where it is needed (kDerivedD).
 template <class llr_t>
@@ -191,13 +186,6 @@ template <class A, int STORE>
 __device__ __forceinline__ typename A::llr_t* frame_L(const MsgStore<A, STORE>& ms, const DynParams&) {
   static_assert(STORE != STORE_FRAME_REC && STORE != STORE_FRAME_ALL, "no L array in the record layout");
   return ms.Lp;
-}
-
-// value of another lane (the lane index is wave-uniform)
-template <class T>
-__device__ __forceinline__ T lane_value(T x, int l) {
-  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
-  else return (T)__builtin_amdgcn_readlane((int)x, l);
 }
 
 // Block-maximum maintenance after the leaf key of index i in block b moved from its old value to
@@ -532,28 +520,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       const int maxL2 = uni(L2);  // lane 0 starts the pass's largest block
       if (__ballot(upd) != 0ull) {  // some row of the pass is precomputed again
         const val_t v = ar.vin(ar.v2c(lv, cv));
-        RowRed r;
-        r.m1 = valid ? fabsf((float)v) : __builtin_inff();
-        r.m2 = __builtin_inff();
-        r.ap = (valid ? (uint32_t)e : 0x7FFFFFFFu) | (valid && v < 0 ? 0x80000000u : 0u);
-        if constexpr (A::kFixed) {
-          rowred_all<false>(r, L2, maxL2);
-          const bool me = (uint32_t)e == (r.ap & 0x7FFFFFFFu);
-          const int mag = (int)(me ? r.m2 : r.m1);
-          const int o = (((r.ap >> 31) ^ (v < 0 ? 1u : 0u)) & 1u) ? -mag : mag;
-          if (upd) pv = o;
-        } else {
-          const float ph = valid ? row_aux(ar, v) : 0.0f;
-          r.S = ph;
-          r.Sx = 0.0f;
-          rowred_all<true>(r, L2, maxL2);
-          const bool me = (uint32_t)e == (r.ap & 0x7FFFFFFFu);
-          const float mo = me ? r.m2 : r.m1;
-          const float Sj = me ? r.Sx : (ph == __builtin_inff() ? __builtin_inff() : r.S - ph);
-          const float mag = fminf(phi_f32(fmaxf(Sj, 0.0f)), mo);
-          const float o = (((r.ap >> 31) ^ (v < 0.0f ? 1u : 0u)) & 1u) ? -mag : mag;
-          if (upd) pv = o;
-        }
+        const val_t o = row_update_lane(ar, valid, (uint32_t)e, v, L2, maxL2);
+        if (upd) pv = o;
       }
       if (upd) {
         ms.set_p(e, (msg_t)pv);

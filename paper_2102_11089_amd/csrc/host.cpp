@@ -161,7 +161,7 @@ DynLayout dyn_layout(const ldpc_code* c, bool fixed, int store, int topo, int wp
 // LDS layout of the multi-edge decoder; returns the total bytes
 struct MeLayout {
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;
-  int off_cand, off_misc, off_lut, off_topo, total, rows_cap, cand_cap;
+  int off_cand, off_misc, off_lut, off_topo, off_rows2, total, rows_cap, cand_cap;
 };
 
 // LDS of the unrolled kernels: forward (c2v, L); backward adds the adjoints, the weight-gradient
@@ -189,8 +189,7 @@ MeLayout me_layout(const ldpc_code* c, bool fixed, bool msg_global, int topo, in
   L.rows_cap = n_p * c->max_dv;
   L.cand_cap = fill == LDPC_FILL_HASH ? 512 : 0;
   int o = 0;
-  L.off_c2v = o; if (!msg_global) o = align16(o + c->E * msg);
-  L.off_pre = o; if (!msg_global) o = align16(o + c->E * msg);
+  L.off_c2v = L.off_pre = o; if (!msg_global) o = align16(o + 2 * c->E * msg);  // (c2v, pre) pairs
   L.off_L = o; o = align16(o + c->N * 4);
   L.off_Lt = o; o = align16(o + c->N * 4);
   L.off_D = o; o = align16(o + c->N * 4);
@@ -199,6 +198,7 @@ MeLayout me_layout(const ldpc_code* c, bool fixed, bool msg_global, int topo, in
   L.off_rowmark = o; o = align16(o + nsw * 4);
   L.off_vnmark = o; o = align16(o + nvw * 4);
   L.off_rows = o; o = align16(o + L.rows_cap * 4);
+  L.off_rows2 = o; o = align16(o + L.rows_cap * 4);  // the same checks sorted by block size
   L.off_sel = o; o = align16(o + 3 * 64 * 4);
   L.off_cand = o; o = align16(o + L.cand_cap * 12);
   L.off_misc = o; o = align16(o + 32 * 4);
@@ -744,9 +744,13 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     Q.off_c2v = Ly.off_c2v; Q.off_pre = Ly.off_pre; Q.off_L = Ly.off_L; Q.off_Lt = Ly.off_Lt; Q.off_D = Ly.off_D;
     Q.off_hist = Ly.off_hist; Q.off_synw = Ly.off_synw; Q.off_rowmark = Ly.off_rowmark; Q.off_vnmark = Ly.off_vnmark;
     Q.off_rows = Ly.off_rows; Q.off_sel = Ly.off_sel; Q.off_cand = Ly.off_cand; Q.off_misc = Ly.off_misc;
-    Q.off_lut = Ly.off_lut; Q.off_topo = Ly.off_topo; Q.lds_bytes = Ly.total;
+    Q.off_lut = Ly.off_lut; Q.off_topo = Ly.off_topo; Q.off_rows2 = Ly.off_rows2; Q.lds_bytes = Ly.total;
     Q.rows_cap = Ly.rows_cap;
     Q.cand_cap = Ly.cand_cap;
+    Q.prof = nullptr;
+#ifdef LDPC_PROFILE
+    if (const char* pp = std::getenv("LDPCCI_PROF")) Q.prof = (long long*)std::strtoull(pp, nullptr, 10);
+#endif
     pl.which = 2;
     pl.block = T.block ? T.block : (c->N <= 256 ? 64 : (c->N <= 2048 ? 256 : 1024));
     const int lds_per_cu = 160 * 1024;

@@ -180,9 +180,10 @@ struct MeParams {
   unsigned long long seed;
   void* msg_global;         // grid x 2E messages (c2v then pre) when they are not in LDS
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;
-  int off_cand, off_misc, off_lut, off_topo;
+  int off_cand, off_misc, off_lut, off_topo, off_rows2;
   int lds_bytes;
   int rows_cap, cand_cap;
+  long long* prof;          // development builds only: per-phase cycle sums (null otherwise)
 };
 
 // batched launch: one descriptor per frame (layout of ldpc_frame_desc)

@@ -17,11 +17,20 @@
 
 namespace ldpc {
 
-__device__ __forceinline__ uint64_t me_fill_key(uint64_t seed, uint64_t frame, uint64_t step, uint64_t n) {
-  return splitmix64(splitmix64(splitmix64(seed ^ frame) ^ step) ^ n);
-}
+#ifdef LDPC_PROFILE
+// phase timing for development builds only: thread 0's clock64() deltas per phase, summed over steps
+#define ME_PROF_DECL long long mp_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}; long long mp_t = clock64();
+#define ME_PROF_MARK(i) { if (tid == 0) { long long now_ = clock64(); mp_acc[i] += now_ - mp_t; mp_t = now_; } }
+#define ME_PROF_FLUSH { if (tid == 0 && P.prof) for (int i_ = 0; i_ < 8; ++i_) atomicAdd((unsigned long long*)&P.prof[i_], (unsigned long long)mp_acc[i_]); }
+#else
+#define ME_PROF_DECL
+#define ME_PROF_MARK(i)
+#define ME_PROF_FLUSH
+#endif
 
-enum { MS_UNSAT = 0, MS_NROWS, MS_NSEL, MS_BSTAR, MS_FILL, MS_NEED, MS_CNT, MS_NCAND, MS_WAVESUM };
+
+enum { MS_UNSAT = 0, MS_NROWS, MS_NSEL, MS_BSTAR, MS_FILL, MS_NEED, MS_CNT, MS_NCAND, MS_WAVESUM, MS_RBIN, MS_RBELOW,
+       MS_L2 };  // MS_L2 + c - 1: touched checks with blocks of 2^c lanes, c = 1..5
 
 // exclusive prefix sum over the workgroup (lane order); wsum: one int per wave in LDS
 __device__ __forceinline__ int block_excl_scan(int v, int* wsum) {
@@ -46,14 +55,9 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
   const int tid = threadIdx.x, BS = blockDim.x;
   const int N = H.N, M = H.M, E = H.E;
 
-  msg_t *c2v, *pre;
-  if constexpr (MSG_GLOBAL) {
-    c2v = reinterpret_cast<msg_t*>(P.msg_global) + (size_t)blockIdx.x * 2 * (size_t)E;
-    pre = c2v + E;
-  } else {
-    c2v = reinterpret_cast<msg_t*>(lds + P.off_c2v);
-    pre = reinterpret_cast<msg_t*>(lds + P.off_pre);
-  }
+  // (c2v, pre) pairs of the frame: one load brings both values of an edge
+  MsgPair<msg_t>* mp = MSG_GLOBAL ? reinterpret_cast<MsgPair<msg_t>*>(P.msg_global) + (size_t)blockIdx.x * (size_t)E
+                                  : reinterpret_cast<MsgPair<msg_t>*>(lds + P.off_c2v);
   llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
   llr_t* Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
   uint32_t* D = reinterpret_cast<uint32_t*>(lds + P.off_D);
@@ -62,9 +66,9 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
   uint32_t* rowmark = reinterpret_cast<uint32_t*>(lds + P.off_rowmark);
   uint32_t* vnmark = reinterpret_cast<uint32_t*>(lds + P.off_vnmark);
   int* rows = reinterpret_cast<int*>(lds + P.off_rows);
-  int* sel = reinterpret_cast<int*>(lds + P.off_sel);  // [64] unsorted, [64] sorted, [64] edges
+  int* rows2 = reinterpret_cast<int*>(lds + P.off_rows2);
+  int* sel = reinterpret_cast<int*>(lds + P.off_sel);  // [64] unsorted, [64] sorted
   int* sel_s = sel + 64;
-  int* sel_e = sel + 128;
   uint64_t* ckeys = reinterpret_cast<uint64_t*>(lds + P.off_cand);
   int* cidx = reinterpret_cast<int*>(ckeys + P.cand_cap);
   int* misc = reinterpret_cast<int*>(lds + P.off_misc);
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
     // ---------------- Algorithm 5 lines 1-3 --------------------------------------------
     const float* llr = P.llr + (size_t)f * N;
     for (int n = tid; n < N; n += BS) L[n] = (llr_t)ar.channel(llr[n]);
-    for (int e = tid; e < E; e += BS) c2v[e] = (msg_t)0;
+    for (int e = tid; e < E; e += BS) mp[e].c = (msg_t)0;
     for (int b = tid; b < NG; b += BS) hist[b] = 0;
     for (int w = tid; w < nsw; w += BS) synw[w] = 0u, rowmark[w] = 0u;
     for (int w = tid; w < nvw; w += BS) vnmark[w] = 0u;
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       }
       for (int p = 0; p < dc; ++p) {
         const val_t v = ar.vin((val_t)L[G.row_vn(m, rs, p)]);
-        pre[rs + p] = (msg_t)acc.out(p, v, row_aux(ar, v));
+        mp[rs + p].p = (msg_t)acc.out(p, v, row_aux(ar, v));
       }
       if (par) {
         atomicOr(&synw[m >> 5], 1u << (m & 31));
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       for (int k = 0; k < dv; ++k) {
         int m, e;
         G.vn_edge(n, k, m, e);
-        lt += (val_t)pre[e];
+        lt += (val_t)mp[e].p;
       }
       Lt[n] = (llr_t)lt;
       const uint32_t d = ar.ci((val_t)L[n], lt);
@@ -132,7 +136,9 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
     long long t = 0, steps = 0;
     const long long ce = P.check_every;
     bool done = ce > 0 && misc[MS_UNSAT] == 0;
+    ME_PROF_DECL
     while (!done && t + NP <= P.max_updates) {
+      ME_PROF_MARK(7)
       const long long tprev = t;
       // ---- Algorithm 4 line 3: groups taken whole, fill group, number still needed ----
       if (tid == 0) {
@@ -149,18 +155,72 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
         misc[MS_NSEL] = 0;
         misc[MS_CNT] = 0;
         misc[MS_NCAND] = 0;
+        for (int c = 0; c < 5; ++c) {
+          misc[MS_L2 + c] = 0;
+          sel[128 + c] = 0;
+        }
       }
       __syncthreads();
       const int bstar = misc[MS_BSTAR], fill = misc[MS_FILL], need = misc[MS_NEED];
-      // ---- the selected set: groups taken whole ----
+      // keyed fill: the per-step part of the key is uniform, a VN's key is one more splitmix64
+      const bool keyed = P.fill != 0 && need > 0;
+      const uint64_t s2 = splitmix64(splitmix64(P.seed ^ (uint64_t)f) ^ (uint64_t)steps);
+      int* h256 = cidx;  // key-byte histogram of the fill group (before any candidate is stored)
+      if (keyed) {
+        for (int x = tid; x < 256; x += BS) h256[x] = 0;
+        __syncthreads();
+      }
+      // ---- the selected set: groups taken whole; the fill group counted, and for the keyed
+      //      fill its keys' top bytes histogrammed in the same pass.  A thread's VNs are n0..n1;
+      //      up to kKeep of them keep their fill membership and key in registers for the passes
+      //      below (larger codes recompute them) ----
+      constexpr int kKeep = 12;
       const int chunk = (N + BS - 1) / BS;
       const int n0 = tid * chunk, n1 = min(N, n0 + chunk);
+      const bool keep = chunk <= kKeep;
+      uint64_t kk[kKeep];
+      uint32_t kmask = 0u;  // bit i: VN n0 + i is in the fill group
       int nfill = 0;
-      for (int n = n0; n < n1; ++n) {
-        const int b = ar.bin(D[n], NG);
-        if (b >= bstar) sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
-        nfill += b == fill ? 1 : 0;
+      if (keep) {
+#pragma unroll
+        for (int i = 0; i < kKeep; ++i) {
+          kk[i] = 0ull;
+          const int n = n0 + i;
+          if (n < n1) {
+            const int b = ar.bin(D[n], NG);
+            if (b >= bstar) sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
+            if (b == fill) {
+              nfill += 1;
+              kmask |= 1u << i;
+              if (keyed) {
+                kk[i] = splitmix64(s2 ^ (uint64_t)n);
+                atomicAdd(&h256[kk[i] >> 56], 1);
+              }
+            }
+          }
+        }
+      } else {
+        for (int n = n0; n < n1; ++n) {
+          const int b = ar.bin(D[n], NG);
+          if (b >= bstar) sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
+          if (b == fill) {
+            nfill += 1;
+            if (keyed) atomicAdd(&h256[splitmix64(s2 ^ (uint64_t)n) >> 56], 1);
+          }
+        }
       }
+      // every fill member of this thread with its key: f(n, key)
+      auto for_members = [&](auto&& fn) {
+        if (keep) {
+#pragma unroll
+          for (int i = 0; i < kKeep; ++i)
+            if ((kmask >> i) & 1u) fn(n0 + i, kk[i]);
+        } else {
+          for (int n = n0; n < n1; ++n)
+            if (ar.bin(D[n], NG) == fill) fn(n, splitmix64(s2 ^ (uint64_t)n));
+        }
+      };
+      ME_PROF_MARK(0)
       // ---- Algorithm 4 lines 4-6: the fill ----
       if (need > 0) {
         if (P.fill == 0) {  // lowest indices: rank of each fill member in index order
@@ -171,141 +231,250 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
               ++rank;
             }
           }
-        } else {  // smallest keys: shrink a key threshold until few candidates remain, rank them
-          const int members = hist[fill];
-          uint64_t lo = 0, hi = ~0ull, T;
-          {
-            const double frac = fmin(1.0, (2.0 * need + 16.0) / (double)max(members, 1));
-            T = frac >= 1.0 ? ~0ull : (uint64_t)(frac * 18446744073709551615.0);
+        } else {
+          // the `need` smallest keys (ties: lower index) by radix selection: find the key bucket
+          // (a run of leading bytes) that holds the need-th smallest, narrowing it a byte at a
+          // time until it has at most cand_cap members; keys below it are taken, keys inside it
+          // ranked
+          uint64_t lo = 0;
+          int shift = 56, below = 0;
+          while (true) {
+            __syncthreads();  // histogram complete
+            if (tid < WAVE) {
+              const int c0 = h256[4 * tid], c1 = h256[4 * tid + 1], c2 = h256[4 * tid + 2], c3 = h256[4 * tid + 3];
+              const int ex = below + wave_excl_scan(c0 + c1 + c2 + c3, tid);
+              const int cs[4] = {c0, c1, c2, c3};
+              int before = ex;
+              for (int u = 0; u < 4; ++u) {
+                if (cs[u] > 0 && before < need && need <= before + cs[u]) {
+                  misc[MS_RBIN] = 4 * tid + u;
+                  misc[MS_RBELOW] = before;
+                  misc[MS_CNT] = cs[u];
+                }
+                before += cs[u];
+              }
+            }
+            __syncthreads();
+            lo |= (uint64_t)misc[MS_RBIN] << shift;
+            below = misc[MS_RBELOW];
+            const int cnt = misc[MS_CNT];
+            if (cnt <= P.cand_cap || shift == 0) break;
+            shift -= 8;
+            for (int x = tid; x < 256; x += BS) h256[x] = 0;
+            __syncthreads();
+            const uint64_t upper = ~0ull << (shift + 8);  // the bytes fixed so far
+            for_members([&](int, uint64_t k) {
+              if ((k & upper) == lo) atomicAdd(&h256[(k >> shift) & 255], 1);
+            });
           }
-          for (int it = 0; it < 96; ++it) {
-            int cnt = 0;
-            for (int n = n0; n < n1; ++n)
-              if (ar.bin(D[n], NG) == fill && me_fill_key(P.seed, (uint64_t)f, (uint64_t)steps, (uint64_t)n) < T) ++cnt;
-            if (cnt) atomicAdd(&misc[MS_CNT], cnt);
-            __syncthreads();
-            const int total = misc[MS_CNT];
-            __syncthreads();
-            if (tid == 0) misc[MS_CNT] = 0;
-            if (total >= need && total <= P.cand_cap) break;
-            if (T == ~0ull) break;  // every member below the threshold
-            if (total < need) lo = T;
-            else hi = T;
-            T = hi == ~0ull ? (lo > (~0ull >> 1) ? ~0ull : lo * 2 + 1) : lo + (hi - lo) / 2;
-            if (T == lo) T = lo + 1;
-            __syncthreads();
-          }
-          for (int n = n0; n < n1; ++n) {
-            if (ar.bin(D[n], NG) != fill) continue;
-            const uint64_t k = me_fill_key(P.seed, (uint64_t)f, (uint64_t)steps, (uint64_t)n);
-            if (k < T || T == ~0ull) {
+          __syncthreads();  // the histogram's last reader is done before candidates overwrite it
+          const uint64_t hi = lo + ((shift == 0) ? 0ull : ((1ull << shift) - 1ull));
+          for_members([&](int n, uint64_t k) {
+            if (k < lo) {
+              sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
+            } else if (k <= hi) {
               const int i = atomicAdd(&misc[MS_NCAND], 1);
               if (i < P.cand_cap) {
                 ckeys[i] = k;
                 cidx[i] = n;
               }
             }
-          }
+          });
           __syncthreads();
-          const int nc = min(misc[MS_NCAND], P.cand_cap);
-          for (int i = tid; i < nc; i += BS) {
-            const uint64_t ki = ckeys[i];
-            const int ni = cidx[i];
-            int r = 0;
-            for (int j = 0; j < nc; ++j) r += (ckeys[j] < ki || (ckeys[j] == ki && cidx[j] < ni)) ? 1 : 0;
-            if (r < need) sel[atomicAdd(&misc[MS_NSEL], 1)] = ni;
+          const int nc = min(misc[MS_NCAND], P.cand_cap), take = need - below;
+          if (nc <= WAVE) {  // one wavefront: candidate per lane, ranks from register reads
+            if (tid < WAVE) {
+              const uint64_t ki = tid < nc ? ckeys[tid] : ~0ull;
+              const int ni = tid < nc ? cidx[tid] : 0x7FFFFFFF;
+              const uint32_t khi = (uint32_t)(ki >> 32), klo = (uint32_t)ki;
+              int r = 0;
+              for (int j = 0; j < nc; ++j) {
+                const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)khi, j) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readlane((int)klo, j);
+                const int nj = __builtin_amdgcn_readlane(ni, j);
+                r += (kj < ki || (kj == ki && nj < ni)) ? 1 : 0;
+              }
+              if (tid < nc && r < take) sel[atomicAdd(&misc[MS_NSEL], 1)] = ni;
+            }
+          } else {
+            for (int i = tid; i < nc; i += BS) {
+              const uint64_t ki = ckeys[i];
+              const int ni = cidx[i];
+              int r = 0;
+              for (int j = 0; j < nc; ++j) r += (ckeys[j] < ki || (ckeys[j] == ki && cidx[j] < ni)) ? 1 : 0;
+              if (r < take) sel[atomicAdd(&misc[MS_NSEL], 1)] = ni;
+            }
           }
         }
       }
       __syncthreads();
+      ME_PROF_MARK(1)
       const int nsel = misc[MS_NSEL];
-      // ascending order of P (distinct VN indices: rank = number of smaller ones)
-      if (tid < nsel) {
-        const int v = sel[tid];
+      // ascending order of P (distinct VN indices: rank = number of smaller ones; at most 64,
+      // one wavefront, ranks from register reads)
+      if (tid < WAVE) {
+        const int v = tid < nsel ? sel[tid] : 0x7FFFFFFF;
         int r = 0;
-        for (int j = 0; j < nsel; ++j) r += sel[j] < v ? 1 : 0;
-        sel_s[r] = v;
+        for (int j = 0; j < nsel; ++j) r += __builtin_amdgcn_readlane(v, j) < v ? 1 : 0;
+        if (tid < nsel) sel_s[r] = v;
       }
       __syncthreads();
-      // ---- Algorithm 1 line 8 for every p: incoming edge of largest residual (snapshot) ----
-      if (tid < nsel) {
-        const int p = sel_s[tid];
-        const int dv = G.vn_deg(p);
-        uint64_t best = 0;
-        for (int k = 0; k < dv; ++k) {
-          int m, e;
-          G.vn_edge(p, k, m, e);
-          best = umax64(best, mkkey(ar.res((val_t)pre[e], (val_t)c2v[e]), (uint32_t)e));
-        }
-        const int e = (int)key_idx(best);
-        sel_e[tid] = e;
-        if (P.out.trace) P.out.trace[(size_t)f * P.max_updates + tprev + tid] = e;
-      }
-      __syncthreads();
-      // ---- propagations (Algorithm 1 line 9 for every p) ----
-      if (tid < nsel) {
-        const int p = sel_s[tid], e = sel_e[tid];
-        const val_t newv = (val_t)pre[e], oldv = (val_t)c2v[e];
-        c2v[e] = (msg_t)newv;
-        const val_t Lold = (val_t)L[p];
-        const val_t Lnew = Lold + (newv - oldv);
-        L[p] = (llr_t)Lnew;
-        const bool flip = (Lold < 0) != (Lnew < 0);
-        const int dv = G.vn_deg(p);
-        for (int k = 0; k < dv; ++k) {
-          int m, e2;
-          G.vn_edge(p, k, m, e2);
-          const uint32_t bit = 1u << (m & 31);
-          if (flip) {
-            const uint32_t old = atomicXor(&synw[m >> 5], bit);
-            atomicAdd(&misc[MS_UNSAT], (old & bit) ? -1 : 1);
+      const int nwv = BS >> 6, wv = tid >> 6, ln = tid & 63;
+      // ---- Algorithm 1 lines 8-9 for every p: the incoming edge of largest residual, then its
+      //      propagation.  A VN's choice reads only its own edges and a propagation writes only
+      //      its own edge and L, so choosing and propagating VN by VN equals choosing all on the
+      //      snapshot first.  One wavefront per selected VN, one lane per edge (and per check, for
+      //      the syndrome toggles and the list of touched checks); a wavefront requests the edges
+      //      of up to four VNs at once. ----
+      constexpr int kVB = 4;
+      for (int i0 = 0; i0 < nsel; i0 += kVB * nwv) {
+        int pv_[kVB], dv_[kVB], m_[kVB], e_[kVB];
+        MsgPair<msg_t> x_[kVB];
+#pragma unroll
+        for (int u = 0; u < kVB; ++u) {
+          const int i = i0 + u * nwv + wv;
+          pv_[u] = -1;
+          dv_[u] = 0;
+          m_[u] = -1;
+          e_[u] = -1;
+          x_[u] = MsgPair<msg_t>{(msg_t)0, (msg_t)0};
+          if (i < nsel) {
+            pv_[u] = sel_s[i];
+            dv_[u] = G.vn_deg(pv_[u]);
+            if (ln < dv_[u]) {
+              G.vn_edge(pv_[u], ln, m_[u], e_[u]);
+              x_[u] = mp[e_[u]];
+            }
           }
-          const uint32_t om = atomicOr(&rowmark[m >> 5], bit);
-          if (!(om & bit)) rows[atomicAdd(&misc[MS_NROWS], 1)] = m;
+        }
+#pragma unroll
+        for (int u = 0; u < kVB; ++u) {
+          const int i = i0 + u * nwv + wv;
+          if (i >= nsel) break;  // whole wavefronts
+          const int p = pv_[u], dv = dv_[u];
+          const uint64_t k = ln < dv ? mkkey(ar.res((val_t)x_[u].p, (val_t)x_[u].c), (uint32_t)e_[u]) : 0ull;
+          const uint64_t kmax = wave_max_u64(k);
+          const int e = (int)key_idx(kmax);
+          const int wl = (int)__builtin_ctzll(__ballot(ln < dv && k == kmax));
+          const val_t newv = (val_t)lane_value(x_[u].p, wl), oldv = (val_t)lane_value(x_[u].c, wl);
+          const val_t Lold = (val_t)L[p];
+          const val_t Lnew = Lold + (newv - oldv);
+          const bool flip = (Lold < 0) != (Lnew < 0);
+          if (ln < dv) {
+            const int m = m_[u];
+            const uint32_t bit = 1u << (m & 31);
+            if (flip) {
+              const uint32_t old = atomicXor(&synw[m >> 5], bit);
+              atomicAdd(&misc[MS_UNSAT], (old & bit) ? -1 : 1);
+            }
+            const uint32_t om = atomicOr(&rowmark[m >> 5], bit);
+            if (!(om & bit)) {
+              rows[atomicAdd(&misc[MS_NROWS], 1)] = m;
+              atomicAdd(&misc[MS_L2 + 31 - __clz(G.row_deg(m) - 1)], 1);
+            }
+          }
+          wave_sync();
+          if (ln == 0) {
+            if (P.out.trace) P.out.trace[(size_t)f * P.max_updates + tprev + i] = e;
+            mp[e].c = (msg_t)newv;
+            L[p] = (llr_t)Lnew;
+          }
         }
       }
+      ME_PROF_MARK(2)
       if constexpr (MSG_GLOBAL) __threadfence_block();
       __syncthreads();
       const int nrows = misc[MS_NROWS];
-      // ---- every check of every p from the new state (Algorithm 1 lines 10-13) ----
+      // touched checks by block size (2^c lanes for c = ceil(log2 dc)), largest first, so that
+      // every block starts at a multiple of its size: counting sort into rows2
+      int rb[6], lo[6];  // per class c: first row in rows2, first lane
+      rb[5] = 0;
+      lo[5] = 0;
+      for (int c = 5; c > 1; --c) {
+        const int nc_ = misc[MS_L2 + c - 1];
+        rb[c - 1] = rb[c] + nc_;
+        lo[c - 1] = lo[c] + (nc_ << c);
+      }
+      const int total = lo[1] + (misc[MS_L2] << 1);
+      int* placed = sel + 128;  // rows placed so far per class
       for (int r = tid; r < nrows; r += BS) {
         const int m = rows[r];
-        const int rs = G.row_start(m), dc = G.row_deg(m);
-        Acc acc;
-        for (int p = 0; p < dc; ++p) {
-          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)c2v[rs + p]));
-          acc.add(p, v, row_aux(ar, v));
+        const int c = 32 - __clz(G.row_deg(m) - 1);
+        rows2[rb[c] + atomicAdd(&placed[c - 1], 1)] = m;
+      }
+      __syncthreads();
+      ME_PROF_MARK(3)
+      // packed lane gi -> (check, position in its row, log2 block); false beyond the last block
+      auto lane_row = [&](int gi, int& m, int& pos, int& l2) -> bool {
+        if (gi >= total) return false;
+        int c = 5;
+        while (c > 1 && gi >= lo[c - 1]) --c;
+        const int rel = gi - lo[c];
+        m = rows2[rb[c] + (rel >> c)];
+        pos = rel & ((1 << c) - 1);
+        l2 = c;
+        return true;
+      };
+      // ---- every check of every p from the new state (Algorithm 1 lines 10-13): the whole-row
+      //      update by butterflies inside each check's block; the next pass's message pairs are
+      //      requested before this pass computes ----
+      struct RowIn {
+        int e, j, l2;
+        MsgPair<msg_t> x;
+      };
+      auto row_in = [&](int base) -> RowIn {
+        RowIn q{-1, 0, 0, MsgPair<msg_t>{(msg_t)0, (msg_t)0}};
+        int m, pos, l2;
+        if (lane_row(base + tid, m, pos, l2)) {
+          q.l2 = l2;
+          const int rs = G.row_start(m), dc = G.row_deg(m);
+          if (pos < dc) {
+            q.e = rs + pos;
+            q.j = G.row_vn(m, rs, pos);
+            q.x = mp[q.e];
+          }
         }
-        for (int p = 0; p < dc; ++p) {
-          const int j = G.row_vn(m, rs, p);
-          const val_t v = ar.vin(ar.v2c((val_t)L[j], (val_t)c2v[rs + p]));
-          const val_t o = acc.out(p, v, row_aux(ar, v));
-          const val_t old = (val_t)pre[rs + p];
-          pre[rs + p] = (msg_t)o;
-          if (o != old) atomicAdd(&Lt[j], (llr_t)(o - old));
+        return q;
+      };
+      RowIn cur = row_in(0);
+      for (int base = 0; base < total; base += BS) {
+        const RowIn nxt = base + BS < total ? row_in(base + BS) : RowIn{-1, 0, 0, MsgPair<msg_t>{(msg_t)0, (msg_t)0}};
+        const bool valid = cur.e >= 0;
+        const val_t po = (val_t)cur.x.p;
+        const val_t v = valid ? ar.vin(ar.v2c((val_t)L[cur.j], (val_t)cur.x.c)) : (val_t)0;
+        const val_t o = row_update_lane(ar, valid, (uint32_t)cur.e, v, cur.l2, 5);
+        if (valid) {
+          mp[cur.e].p = (msg_t)o;
+          if (o != po) atomicAdd(&Lt[cur.j], (llr_t)(o - po));
         }
+        cur = nxt;
       }
       if constexpr (MSG_GLOBAL) __threadfence_block();
       __syncthreads();
-      // ---- CI and CI group of every VN of those checks ----
-      for (int r = tid; r < nrows; r += BS) {
-        const int m = rows[r];
-        const int rs = G.row_start(m), dc = G.row_deg(m);
-        for (int p = 0; p < dc; ++p) {
-          const int j = G.row_vn(m, rs, p);
-          const uint32_t bit = 1u << (j & 31);
-          if (atomicOr(&vnmark[j >> 5], bit) & bit) continue;
-          const uint32_t nd = ar.ci((val_t)L[j], (val_t)Lt[j]);
-          const uint32_t od = D[j];
-          D[j] = nd;
-          const int ob = ar.bin(od, NG), nb = ar.bin(nd, NG);
-          if (ob != nb) {
-            atomicSub(&hist[ob], 1);
-            atomicAdd(&hist[nb], 1);
+      ME_PROF_MARK(4)
+      // ---- CI and CI group of every VN of those checks (each VN once) ----
+      for (int base = 0; base < total; base += BS) {
+        int m, pos, l2;
+        if (lane_row(base + tid, m, pos, l2)) {
+          const int rs = G.row_start(m), dc = G.row_deg(m);
+          if (pos < dc) {
+            const int j = G.row_vn(m, rs, pos);
+            const uint32_t bit = 1u << (j & 31);
+            if (!(atomicOr(&vnmark[j >> 5], bit) & bit)) {
+              const uint32_t nd = ar.ci((val_t)L[j], (val_t)Lt[j]);
+              const uint32_t od = D[j];
+              D[j] = nd;
+              const int ob = ar.bin(od, NG), nb = ar.bin(nd, NG);
+              if (ob != nb) {
+                atomicSub(&hist[ob], 1);
+                atomicAdd(&hist[nb], 1);
+              }
+            }
           }
         }
       }
       __syncthreads();
+      ME_PROF_MARK(5)
       for (int w = tid; w < nsw; w += BS) rowmark[w] = 0u;
       for (int w = tid; w < nvw; w += BS) vnmark[w] = 0u;
       const int unsat = misc[MS_UNSAT];
@@ -315,7 +484,9 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       steps += 1;
       if (ce > 0 && (t / ce) != (tprev / ce) && unsat == 0) done = true;
       __syncthreads();
+      ME_PROF_MARK(6)
     }
+    ME_PROF_FLUSH
 
     // ---------------- outputs -----------------------------------------------------------
     for (int n = tid; n < N; n += BS) {
@@ -327,8 +498,8 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       if (P.out.dump_D) P.out.dump_D[(size_t)f * N + n] = ar.d_float(D[n]);
     }
     for (int e = tid; e < E; e += BS) {
-      if (P.out.dump_c2v) P.out.dump_c2v[(size_t)f * E + e] = ar.as_float((val_t)c2v[e]);
-      if (P.out.dump_pre) P.out.dump_pre[(size_t)f * E + e] = ar.as_float((val_t)pre[e]);
+      if (P.out.dump_c2v) P.out.dump_c2v[(size_t)f * E + e] = ar.as_float((val_t)mp[e].c);
+      if (P.out.dump_pre) P.out.dump_pre[(size_t)f * E + e] = ar.as_float((val_t)mp[e].p);
     }
     if (tid == 0) {
       P.out.updates_used[f] = t;
