@@ -26,8 +26,8 @@ __device__ __forceinline__ void store_sync() {
   wave_sync();
 }
 
-// flooding / layered for one wavefront: L in the dynamic layout's L region, the C2V messages in
-// the frame's message store
+// flooding / layered for one wavefront: L and the C2V messages in the frame's store (LDS, the
+// global slot, or the VN records)
 template <class A, int STORE, class Topo>
 __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
                                                     const MsgStore<A, STORE>& ms, const FrameJob& J) {
@@ -36,9 +36,8 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
   using val_t = typename A::val_t;
   using Acc = typename RowAccOf<A>::type;
   const int lane = threadIdx.x & (WAVE - 1);
-  llr_t* L = frame_L(ms, P);
   const int N = H.N, M = H.M, E = H.E;
-  for (int n = lane; n < N; n += WAVE) L[n] = (llr_t)ar.channel(J.llr[n]);
+  for (int n = lane; n < N; n += WAVE) ms.set_l(n, (llr_t)ar.channel(J.llr[n]));
   for (int e = lane; e < E; e += WAVE) ms.set_c(e, (msg_t)0);
   store_sync<STORE>();
   auto syndrome = [&]() {
@@ -46,7 +45,7 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
     for (int m = lane; m < M; m += WAVE) {
       const int rs = G.row_start(m), dc = G.row_deg(m);
       int par = 0;
-      for (int p = 0; p < dc; ++p) par ^= (val_t)L[G.row_vn(m, rs, p)] < 0 ? 1 : 0;
+      for (int p = 0; p < dc; ++p) par ^= (val_t)ms.l(G.row_vn(m, rs, p)) < 0 ? 1 : 0;
       u += par;
     }
     return wave_sum_i32(u);
@@ -59,11 +58,11 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
         const int rs = G.row_start(m), dc = G.row_deg(m);
         Acc acc;
         for (int p = 0; p < dc; ++p) {
-          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)ms.c(rs + p)));
+          const val_t v = ar.vin(ar.v2c((val_t)ms.l(G.row_vn(m, rs, p)), (val_t)ms.c(rs + p)));
           acc.add(p, v, row_aux(ar, v));
         }
         for (int p = 0; p < dc; ++p) {
-          const val_t v = ar.vin(ar.v2c((val_t)L[G.row_vn(m, rs, p)], (val_t)ms.c(rs + p)));
+          const val_t v = ar.vin(ar.v2c((val_t)ms.l(G.row_vn(m, rs, p)), (val_t)ms.c(rs + p)));
           ms.set_c(rs + p, (msg_t)acc.out(p, v, row_aux(ar, v)));
         }
       }
@@ -76,7 +75,7 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
           G.vn_edge(n, k, m, e);
           l += (val_t)ms.c(e);
         }
-        L[n] = (llr_t)l;
+        ms.set_l(n, (llr_t)l);
       }
       store_sync<STORE>();
     } else {
@@ -87,16 +86,16 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
           Acc acc;
           for (int p = 0; p < dc; ++p) {
             const int j = G.row_vn(m, rs, p);
-            const val_t v = ar.vin((val_t)L[j] - (val_t)ms.c(rs + p));
+            const val_t v = ar.vin((val_t)ms.l(j) - (val_t)ms.c(rs + p));
             acc.add(p, v, row_aux(ar, v));
           }
           for (int p = 0; p < dc; ++p) {
             const int j = G.row_vn(m, rs, p);
-            const val_t vr = (val_t)L[j] - (val_t)ms.c(rs + p);
+            const val_t vr = (val_t)ms.l(j) - (val_t)ms.c(rs + p);
             const val_t v = ar.vin(vr);
             const val_t o = acc.out(p, v, row_aux(ar, v));
             ms.set_c(rs + p, (msg_t)o);
-            L[j] = (llr_t)(vr + o);
+            ms.set_l(j, (llr_t)(vr + o));
           }
         }
         store_sync<STORE>();
@@ -107,7 +106,7 @@ __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo
     unsat = syndrome();
   }
   for (int n = lane; n < N; n += WAVE) {
-    const val_t l = (val_t)L[n];
+    const val_t l = (val_t)ms.l(n);
     J.bits[n] = l < 0 ? 1 : 0;
     if (J.llr_out) J.llr_out[n] = ar.out_llr(l);
   }
@@ -200,6 +199,7 @@ static hipError_t launch_batch_t(const BatchParams& B, int topo, int grid, hipSt
 
 template <class A>
 static hipError_t launch_batch_s(const BatchParams& B, int store, int topo, int grid, hipStream_t st) {
+  if (store == STORE_FRAME_REC) return launch_batch_t<A, STORE_FRAME_REC>(B, topo, grid, st);
   if (store == STORE_FRAME_GLOBAL) return launch_batch_t<A, STORE_FRAME_GLOBAL>(B, topo, grid, st);
   if (store == STORE_ALL_GLOBAL_LT) return launch_batch_t<A, STORE_ALL_GLOBAL_LT>(B, topo, grid, st);
   if (store == STORE_ALL_GLOBAL) return launch_batch_t<A, STORE_ALL_GLOBAL>(B, topo, grid, st);
@@ -232,7 +232,8 @@ hipError_t set_batch_lds_limit(int bytes) {
                        set_batch_store<ArithFix, STORE_PRE_GLOBAL>(bytes),
                        set_batch_store<ArithFix, STORE_ALL_GLOBAL>(bytes),
                        set_batch_store<ArithFix, STORE_ALL_GLOBAL_LT>(bytes),
-                       set_batch_store<ArithFix, STORE_FRAME_GLOBAL>(bytes)})
+                       set_batch_store<ArithFix, STORE_FRAME_GLOBAL>(bytes),
+                       set_batch_store<ArithF32, STORE_FRAME_REC>(bytes), set_batch_store<ArithFix, STORE_FRAME_REC>(bytes)})
     if (r != hipSuccess && e == hipSuccess) e = r;
   return e;
 }

@@ -180,14 +180,6 @@ __device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, siz
   return ms;
 }
 
-// total LLRs of the frame as one array (flooding / layered frames of the batched kernel; not
-// available in the record layout)
-template <class A, int STORE>
-__device__ __forceinline__ typename A::llr_t* frame_L(const MsgStore<A, STORE>& ms, const DynParams&) {
-  static_assert(STORE != STORE_FRAME_REC && STORE != STORE_FRAME_ALL, "no L array in the record layout");
-  return ms.Lp;
-}
-
 // Block-maximum maintenance after the leaf key of index i in block b moved from its old value to
 // nk: a larger key raises the block maximum; a smaller one marks the block for recomputation if
 // i held the maximum (a maximum key carries its index, so the old value is not needed).  Lanes

@@ -1207,10 +1207,11 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   const int lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
   const int ncu = device_cu_count(dev);
   // message storage: the mode that keeps the most frames resident per CU (at most 32); ties go to
-  // all messages in global memory (the batch is a large persistent launch)
+  // the later mode of the list (the batch is a large persistent launch: messages global, then VN
+  // records over split arrays)
   int store = -1, best_fit = 0;
   DynLayout Ly{};
-  for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_FRAME_GLOBAL, STORE_ALL_GLOBAL_LT, STORE_ALL_GLOBAL}) {
+  for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_FRAME_GLOBAL, STORE_FRAME_REC, STORE_ALL_GLOBAL_LT, STORE_ALL_GLOBAL}) {
     DynLayout cand = dyn_layout_dims(mx, fixed, st, 1);
     if (cand.total > lds_limit) continue;
     const int fit = std::min(32, (160 * 1024) / std::max(cand.total, 1));
