@@ -68,7 +68,7 @@ typedef struct {
   int32_t q_bits;      /* LDPC_MS_FIX: message width, 2..8 (saturation at +-(2^(q-1)-1))         */
   int32_t frac_bits;   /* LDPC_MS_FIX: channel quantisation llr * 2^frac_bits, 0..6              */
   float gamma;         /* CIRBP threshold: fall back to the global residual search if D_{n*} < gamma
-                          (Algorithm 1 line 5); MS_FIX compares D_q with round(gamma * 65534)    */
+                          (Algorithm 1 threshold test); MS_FIX compares D_q with round(gamma * 65534)    */
   int32_t n_p;         /* ME-CIRBP: VNs updated per step (N_P, Sec. VI), 1..64                   */
   int32_t n_g;         /* ME-CIRBP: CI groups (N_G, Algorithm 4), 1..65535                       */
   int32_t fill;        /* ME-CIRBP: LDPC_FILL_LOWEST or LDPC_FILL_HASH                           */

@@ -1,7 +1,8 @@
 /*
  * ldpc_oracle.c -- plain, slow CPU oracle for LDPC belief-propagation decoding with
- * flooding, layered, residual (RBP), conditional-innovation RBP (CIRBP, Algorithm 1) and
- * multi-edge CIRBP (Algorithms 4 and 5) schedules.
+ * flooding, layered, residual (RBP), conditional-innovation RBP (CIRBP, Algorithm 1),
+ * multi-edge CIRBP (Algorithms 4 and 5) and latest-message-driven (LMDRBP and sLMDRBP,
+ * Algorithm 2; LMD-CIRBP, Algorithm 3) schedules.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark may load this file.  It shares no code, header, table or constant generator with the
@@ -41,6 +42,17 @@
  *     either the lowest VN indices of the fill group, or the VNs with the smallest keys
  *     splitmix64(splitmix64(splitmix64(seed ^ frame) ^ step) ^ n) (ties: lower n), a uniform
  *     random subset that is reproducible from (seed, frame, step).
+ *   - LMD schedules (Sec. IV): the first update is chosen globally (Algorithm 2: largest residual;
+ *     Algorithm 3: largest CI, then the incoming edge of largest residual).  After an update of
+ *     e* = (m*, n*) the next one is chosen among the messages just precomputed: LMDRBP takes the
+ *     edge (i, j) of largest residual over i in M(n*) \ m*, j in N(i) \ n*, then n' = j receives
+ *     its incoming edge of largest residual; sLMDRBP sends the edge (i, j) itself; LMD-CIRBP takes
+ *     the VN n' of largest CI over the same VNs, U(m*, n*), and n' then receives its incoming edge
+ *     of largest residual (Algorithm 3 keeps m* implicit after the first update; this reading
+ *     chooses it as for the first one).  When n* has degree 1 the candidates come from m* itself:
+ *     edges (m*, j), VNs j of N(m*) \ n* (Sec. V).  Ties go to the lowest edge id / VN index.  An
+ *     empty candidate set (only with checks of degree 1) sends the next update to the global
+ *     choice again.
  */
 #include <math.h>
 #include <pthread.h>
@@ -48,7 +60,17 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OC_FLOODING = 0, OC_LAYERED = 1, OC_RBP = 2, OC_CIRBP = 3, OC_MECIRBP = 4, OC_REPLAY = 5 };
+enum {
+  OC_FLOODING = 0,
+  OC_LAYERED = 1,
+  OC_RBP = 2,
+  OC_CIRBP = 3,
+  OC_MECIRBP = 4,
+  OC_REPLAY = 5,
+  OC_LMDRBP = 6,
+  OC_SLMDRBP = 7,
+  OC_LMDCIRBP = 8
+};
 enum { ARITH_SPA = 0, ARITH_MSFIX = 1 };
 enum {
   CNT_PROP = 0,   /* C2V propagations (= updates)                                   */
@@ -202,7 +224,7 @@ static void syndrome_rows_of_vn(st_t *S, int32_t n) {
   }
 }
 
-/* Algorithm 1 lines 1-3: c2v = 0, L = channel, all precomputed messages, Lt and D */
+/* Algorithm 1, initialisation: c2v = 0, L = channel, all precomputed messages, Lt and D */
 static void init_dynamic(st_t *S) {
   const oc_code *H = S->H;
   for (int32_t e = 0; e < H->E; ++e) S->c2v[e] = 0.0;
@@ -241,7 +263,7 @@ static int selfcheck(st_t *S) {
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* single-edge update (Algorithm 1 lines 9-13 / RBP steps 3-4)                                 */
+/* single-edge update (Algorithm 1 propagation and precompute loop / RBP steps 3-4)             */
 /* ------------------------------------------------------------------------------------------ */
 static void apply_edge(st_t *S, int32_t estar, int64_t *cnt) {
   const oc_code *H = S->H;
@@ -297,7 +319,7 @@ static int32_t argmax_ci(const st_t *S, int64_t *cnt) {
   return best;
 }
 
-/* edge into VN n with the largest residual (Algorithm 1 line 8); lowest check on ties */
+/* edge into VN n with the largest residual (Algorithm 1 edge choice); lowest check on ties */
 static int32_t argmax_into(const st_t *S, int32_t n, int64_t *cnt) {
   const oc_code *H = S->H;
   int32_t best = H->col_eid[H->col_ptr[n]];
@@ -305,6 +327,61 @@ static int32_t argmax_into(const st_t *S, int32_t n, int64_t *cnt) {
     int32_t e = H->col_eid[k];
     cnt[CNT_CMP] += 1;
     if (residual(S, e) > residual(S, best)) best = e;
+  }
+  return best;
+}
+
+/* Algorithm 2, local edge choice: after the update of e*, the edge (i, j) of largest residual
+   with i a check of n* other than m* (m* itself when n* has degree 1, Sec. V) and j != n*; lowest
+   edge id on ties; -1 when there is no candidate */
+static int32_t lmd_edge(const st_t *S, int32_t estar, int64_t *cnt) {
+  const oc_code *H = S->H;
+  int32_t mstar = S->row_of[estar], nstar = H->col[estar];
+  int deg1 = H->col_ptr[nstar + 1] - H->col_ptr[nstar] == 1;
+  int32_t best = -1;
+  double bv = 0.0;
+  for (int32_t k = H->col_ptr[nstar]; k < H->col_ptr[nstar + 1]; ++k) {
+    int32_t i = H->col_row[k];
+    if (i == mstar && !deg1) continue;
+    for (int32_t e = H->row_ptr[i]; e < H->row_ptr[i + 1]; ++e) {
+      if (H->col[e] == nstar) continue;
+      double r = residual(S, e);
+      if (best < 0) {
+        best = e;
+        bv = r;
+        continue;
+      }
+      cnt[CNT_CMP] += 1;
+      if (r > bv || (r == bv && e < best)) {
+        best = e;
+        bv = r;
+      }
+    }
+  }
+  return best;
+}
+
+/* Algorithm 3, local VN choice: after the update of e*, the VN of largest CI among U(m*, n*), the
+   VNs other than n* of the checks of n* other than m* (of m* itself when n* has degree 1, Sec. V);
+   lowest VN index on ties; -1 when there is no candidate */
+static int32_t lmd_vn(const st_t *S, int32_t estar, int64_t *cnt) {
+  const oc_code *H = S->H;
+  int32_t mstar = S->row_of[estar], nstar = H->col[estar];
+  int deg1 = H->col_ptr[nstar + 1] - H->col_ptr[nstar] == 1;
+  int32_t best = -1;
+  for (int32_t k = H->col_ptr[nstar]; k < H->col_ptr[nstar + 1]; ++k) {
+    int32_t i = H->col_row[k];
+    if (i == mstar && !deg1) continue;
+    for (int32_t e = H->row_ptr[i]; e < H->row_ptr[i + 1]; ++e) {
+      int32_t j = H->col[e];
+      if (j == nstar) continue;
+      if (best < 0) {
+        best = j;
+        continue;
+      }
+      cnt[CNT_CMP] += 1;
+      if (S->D[j] > S->D[best] || (S->D[j] == S->D[best] && j < best)) best = j;
+    }
   }
   return best;
 }
@@ -526,6 +603,8 @@ static int decode_frame(job_t *J, st_t *S, int32_t f) {
     int64_t limit = J->max_updates;
     if (kind == OC_REPLAY && J->replay_len < limit) limit = J->replay_len;
     int64_t ce = kind == OC_REPLAY ? 0 : s->check_every;
+    int lmd = kind == OC_LMDRBP || kind == OC_SLMDRBP || kind == OC_LMDCIRBP;
+    int32_t next_e = -1; /* LMD schedules: the edge chosen by the last update */
     if (!stop_now(S, 0, ce)) {
       while (t < limit) {
         int64_t tprev = t;
@@ -541,8 +620,20 @@ static int decode_frame(job_t *J, st_t *S, int32_t f) {
           int32_t estar;
           if (kind == OC_RBP) estar = argmax_residual(S, cnt);
           else if (kind == OC_CIRBP) estar = select_cirbp(S, cnt);
+          else if (lmd && next_e >= 0) estar = next_e;
+          else if (kind == OC_LMDRBP || kind == OC_SLMDRBP) estar = argmax_residual(S, cnt);
+          else if (kind == OC_LMDCIRBP) estar = argmax_into(S, argmax_ci(S, cnt), cnt);
           else estar = J->replay[(size_t)f * (size_t)J->replay_len + (size_t)t];
           apply_edge(S, estar, cnt);
+          if (kind == OC_SLMDRBP) {
+            next_e = lmd_edge(S, estar, cnt);
+          } else if (kind == OC_LMDRBP) {
+            int32_t e2 = lmd_edge(S, estar, cnt);
+            next_e = e2 < 0 ? -1 : argmax_into(S, H->col[e2], cnt);
+          } else if (kind == OC_LMDCIRBP) {
+            int32_t n2 = lmd_vn(S, estar, cnt);
+            next_e = n2 < 0 ? -1 : argmax_into(S, n2, cnt);
+          }
           cnt[CNT_STEPS] += 1;
           if (tr) tr[t] = estar;
           t += 1;
@@ -617,7 +708,7 @@ int oc_decode(const oc_code *H, const oc_sched *s, int32_t B, const double *llr,
               double *dump_c2v, double *dump_pre, double *dump_L, double *dump_Lt, double *dump_D,
               int32_t nthreads) {
   if (!H || !s || B < 0 || !llr || !bits || !updates_used || max_updates < 0) return OC_EINVAL;
-  if (s->kind < 0 || s->kind > OC_REPLAY || (s->arith != ARITH_SPA && s->arith != ARITH_MSFIX))
+  if (s->kind < 0 || s->kind > OC_LMDCIRBP || (s->arith != ARITH_SPA && s->arith != ARITH_MSFIX))
     return OC_EINVAL;
   if (s->kind == OC_REPLAY && (!replay || replay_len < 0)) return OC_EINVAL;
   if (s->kind == OC_MECIRBP && (s->n_p < 1 || s->n_g < 1)) return OC_EINVAL;

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "ldpc_oracle.c"), os.path.join(_HERE, "unrolled_oracle.c")]
 _LIB = os.path.join(_HERE, "libldpc_oracle.so")
 
-FLOODING, LAYERED, RBP, CIRBP, MECIRBP, REPLAY = range(6)
+FLOODING, LAYERED, RBP, CIRBP, MECIRBP, REPLAY, LMDRBP, SLMDRBP, LMDCIRBP = range(9)
 FILL_LOWEST, FILL_HASH = 0, 1
 SPA, MSFIX = 0, 1
 COUNTERS = ("prop", "v2c", "pre", "ci", "ci_self", "fallback", "cmp", "steps")

@@ -237,7 +237,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       return ms.d(n);
     }
   };
-  // ---------------- Algorithm 1 lines 1-3: initial state --------------------------------
+  // ---------------- Algorithm 1, initialisation: initial state ---------------------------
   const float* llr = J.llr;
   for (int n = lane; n < N; n += WAVE) ms.set_l(n, (llr_t)ar.channel(llr[n]));
   for (int e = lane; e < E; e += WAVE) ms.set_c(e, (msg_t)0);
@@ -308,7 +308,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   PROF_DECL
   while (!done && t < limit) {
     PROF_MARK(7)
-    // ---- selection (Algorithm 1 lines 4-8; RBP eq. (5)) ----
+    // ---- selection (Algorithm 1: CI maximum, threshold test, incoming edge; RBP eq. (5)) ----
     int estar, mstar = -1, nstar = -1;
     msg_t c_star = (msg_t)0, p_star = (msg_t)0;  // messages of e*, taken from the selection's loads
     bool have_star = false;
@@ -438,7 +438,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       return q;
     };
 
-    // ---- propagation (Algorithm 1 line 9) and D_{n*} ----
+    // ---- propagation (Algorithm 1) and D_{n*} ----
     if (!have_star) ms.cp(estar, c_star, p_star);
     PassIn in_cur{make_int2(-1, 0), (msg_t)0, (msg_t)0, (llr_t)0, (llr_t)0};
     if (!row_only) in_cur = load_in(ent0);
@@ -484,7 +484,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     }
 
     // ---- touched checks: V2C inputs, whole-row update, residual keys, and the CI of every VN
-    //      listed once in the table (Algorithm 1 lines 10-13; one pass per 64 lanes) ----
+    //      listed once in the table (Algorithm 1, the loop over M(n*) \ m*; one pass per 64 lanes) ----
     bool late_ci = false;  // a VN of the overflow group was updated: its CI is refreshed after the passes
     for (int ps = 0; ps < npass; ++ps) {
       PassIn in_next{make_int2(-1, 0), (msg_t)0, (msg_t)0, (llr_t)0, (llr_t)0};

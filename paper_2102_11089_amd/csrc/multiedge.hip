@@ -7,7 +7,7 @@
 //   2. the selected set P: every VN of the taken groups, plus the fill -- the lowest VN indices
 //      (block prefix count) or the smallest keys splitmix64(splitmix64(splitmix64(seed ^ frame)
 //      ^ step) ^ n) (a key threshold shrunk until at most CAND candidates remain, then ranked);
-//   3. for each p in P (ascending): the incoming edge of largest residual (Algorithm 1 line 8);
+//   3. for each p in P (ascending): the incoming edge of largest residual (Algorithm 1);
 //   4. all propagations c2v <- pre, L_p += delta, syndrome toggles;
 //   5. every check of every p recomputed from the new state (one lane per check, each check once),
 //      Lt updated by the precompute deltas; then D (and its group) of every VN of those checks.
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
   __syncthreads();
 
   for (int f = blockIdx.x; f < P.B; f += gridDim.x) {
-    // ---------------- Algorithm 5 lines 1-3 --------------------------------------------
+    // ---------------- Algorithm 5, initialisation ---------------------------------------
     const float* llr = P.llr + (size_t)f * N;
     for (int n = tid; n < N; n += BS) L[n] = (llr_t)ar.channel(llr[n]);
     for (int e = tid; e < E; e += BS) mp[e].c = (msg_t)0;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
     while (!done && t + NP <= P.max_updates) {
       ME_PROF_MARK(7)
       const long long tprev = t;
-      // ---- Algorithm 4 line 3: groups taken whole, fill group, number still needed ----
+      // ---- Algorithm 4, group selection: groups taken whole, fill group, number still needed ----
       if (tid == 0) {
         int c = 0, bstar = NG;
         for (int b = NG - 1; b >= 0; --b) {
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
         }
       };
       ME_PROF_MARK(0)
-      // ---- Algorithm 4 lines 4-6: the fill ----
+      // ---- Algorithm 4: the fill ----
       if (need > 0) {
         if (P.fill == 0) {  // lowest indices: rank of each fill member in index order
           int rank = block_excl_scan(nfill, wsum);
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       }
       __syncthreads();
       const int nwv = BS >> 6, wv = tid >> 6, ln = tid & 63;
-      // ---- Algorithm 1 lines 8-9 for every p: the incoming edge of largest residual, then its
+      // ---- Algorithm 1 edge choice and propagation for every p: the incoming edge of largest residual, then its
       //      propagation.  A VN's choice reads only its own edges and a propagation writes only
       //      its own edge and L, so choosing and propagating VN by VN equals choosing all on the
       //      snapshot first.  One wavefront per selected VN, one lane per edge (and per check, for
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
         l2 = c;
         return true;
       };
-      // ---- every check of every p from the new state (Algorithm 1 lines 10-13): the whole-row
+      // ---- every check of every p from the new state (Algorithm 1, the loop over M(n*) \ m*): the whole-row
       //      update by butterflies inside each check's block; the next pass's message pairs are
       //      requested before this pass computes ----
       struct RowIn {

@@ -66,7 +66,7 @@ def test_ci_spa_is_posterior_difference():
 
 
 # ------------------------------------------------------------------------------------------
-# initial precompute and the first selection (Algorithm 1 lines 1-8, RBP step 2)
+# initial precompute and the first selection (Algorithm 1 initialisation and selection, RBP step 2)
 # ------------------------------------------------------------------------------------------
 def test_first_selection_on_spc_matches_bruteforce():
     """On a single check the precomputed C2V into n is the extrinsic MAP LLR, so Lt_n is the
@@ -365,3 +365,188 @@ def test_alg4_keyed_fill_takes_smallest_keys():
     # n_p = 2: two of G3 = {1, 2, 4} with the smallest keys
     top = sorted([1, 2, 4], key=lambda n: (int(keys[n]), n))[:2]
     assert list(O.alg4_select_keyed(bins, g["n_g"], 2, keys)) == sorted(top)
+
+
+# ------------------------------------------------------------------------------------------
+# LMD schedules (Sec. IV, Algorithms 2 and 3; degree-1 rule of Sec. V)
+# ------------------------------------------------------------------------------------------
+LMD_KINDS = (O.LMDRBP, O.SLMDRBP, O.LMDCIRBP)
+
+
+def _spc_extrinsic(x):
+    """C2V messages of one check whose incoming V2C messages are x: the extrinsic part of the
+    exact single-parity-check posterior, by codeword enumeration."""
+    d = len(x)
+    H1 = np.ones((1, d), dtype=np.uint8)
+    return brute.bitwise_map_llr(H1, x) - np.asarray(x, dtype=np.float64)
+
+
+def _lmd_first_two(code, ch, kind):
+    """The first two edges an LMD schedule sends, from the definitions alone: every precomputed
+    C2V message by enumeration on its check, Lt_n = ch_n + sum of precomputed messages into n,
+    D_n = |p0(L_n) - p0(Lt_n)| (eq. (9)).  Returns (e1, e2, margin): margin is the smallest gap
+    between the winning value and the runner-up in the argmaxes taken, so that callers can skip
+    cases that rounding could decide."""
+    rows = code.row_of_edge()
+    E = code.E
+    rp, col = code.row_ptr, code.col
+
+    def precompute(v2c_of):
+        pre = np.zeros(E)
+        for m in range(code.M):
+            sl = slice(rp[m], rp[m + 1])
+            pre[sl] = _spc_extrinsic(v2c_of(m, col[sl]))
+        return pre
+
+    margins = []
+
+    def argmax(vals, ids):
+        # largest value, lowest id on ties (the ids are ascending edge ids or VN indices)
+        vals = np.asarray(vals, dtype=np.float64)
+        order = np.lexsort((np.asarray(ids), -vals))
+        u = np.unique(vals)
+        if len(u) > 1:
+            margins.append(u[-1] - u[-2])
+        return int(np.asarray(ids)[order[0]])
+
+    pre0 = precompute(lambda m, vs: ch[vs])
+    c2v = np.zeros(E)
+    Lt0 = ch + np.bincount(col, weights=pre0, minlength=code.N)
+    D0 = np.abs(sigmoid(ch) - sigmoid(Lt0))
+    res0 = np.abs(pre0 - c2v)
+
+    def into(n, res):
+        es = np.nonzero(col == n)[0]
+        return argmax(res[es], es)
+
+    if kind == O.LMDCIRBP:
+        e1 = into(argmax(D0, np.arange(code.N)), res0)
+    else:
+        e1 = argmax(res0, np.arange(E))
+    ms, ns = int(rows[e1]), int(col[e1])
+    c2v[e1] = pre0[e1]
+    L = ch.copy()
+    L[ns] = ch[ns] + pre0[e1]
+    touched = [int(r) for r in rows[col == ns] if r != ms]
+    pre1 = pre0.copy()
+    for m in touched:
+        sl = slice(rp[m], rp[m + 1])
+        vs = col[sl]
+        pre1[sl] = _spc_extrinsic(np.where(vs == ns, L[ns], ch[vs]))  # c2v into row m is 0
+    res1 = np.abs(pre1 - c2v)
+    Lt1 = ch + np.bincount(col, weights=pre1, minlength=code.N)
+    D1 = np.abs(sigmoid(L) - sigmoid(Lt1))
+    cand_rows = touched if touched else [ms]  # degree-1 n*: search N(m*) \ n* (Sec. V)
+    cand = np.array([e for m in cand_rows for e in range(rp[m], rp[m + 1]) if col[e] != ns])
+    if kind == O.LMDCIRBP:
+        vs = col[cand]
+        e2 = into(argmax(D1[vs], vs), res1)
+    else:
+        e = argmax(res1[cand], cand)
+        e2 = e if kind == O.SLMDRBP else into(int(col[e]), res1)
+    return e1, e2, min(margins) if margins else np.inf
+
+
+def _small_mixed_code():
+    """Four checks of degree 4 on 10 VNs, any two checks sharing one VN: VNs 3, 6, 8 and 9 have
+    degree 1, the others degree 2 (no 4-cycles)."""
+    return S.code_from_rows(4, 10, [[0, 1, 2, 3], [0, 4, 5, 6], [1, 4, 7, 8], [2, 5, 7, 9]])
+
+
+@pytest.mark.parametrize("kind", LMD_KINDS)
+def test_lmd_first_two_choices_match_enumeration(kind):
+    """Algorithms 2 and 3: the global first choice and the local second one (after the latest
+    update, among the messages of the checks that just received new V2C messages; from m* itself
+    when n* has degree 1), recomputed by codeword enumeration on each check."""
+    rng = np.random.default_rng(40 + kind)
+    seen_deg1 = seen_deg2 = 0
+    for code in (_small_mixed_code(), S.workload_code("c0")):
+        deg = np.bincount(code.col, minlength=code.N)
+        for trial in range(25 if code.N < 20 else 8):
+            ch = rng.normal(0.8, 2.0, size=code.N)
+            e1, e2, margin = _lmd_first_two(code, ch, kind)
+            if margin < 1e-9:
+                continue
+            r = O.decode(code, ch, kind, O.SPA, max_updates=2, check_every=0, trace=True)
+            assert list(r.trace[0, :2]) == [e1, e2], (code.name, trial)
+            if deg[code.col[e1]] == 1:
+                seen_deg1 += 1
+            else:
+                seen_deg2 += 1
+    assert seen_deg1 >= 3 and seen_deg2 >= 10
+
+
+@pytest.mark.parametrize("kind", LMD_KINDS)
+@pytest.mark.parametrize("arith", [O.SPA, O.MSFIX])
+def test_lmd_on_a_single_check_follows_the_global_schedule(kind, arith):
+    """On one check every VN has degree 1, so the LMD search covers N(m*) \\ n* (Sec. V); an update
+    changes no other message there and leaves the sent edge with residual 0 and its VN with D = 0.
+    While unsent edges keep positive residuals and CIs, the local maximum is the global one:
+    LMDRBP and sLMDRBP send what RBP sends and LMD-CIRBP what CIRBP with gamma = 0 sends.  In
+    fixed point (small integer channel values, min-sum) most residuals tie, which pins the
+    lowest-index rule for ties."""
+    rng = np.random.default_rng(50 + kind + 10 * arith)
+    for N in (3, 5, 8):
+        code = S.spc_code(N)
+        for _ in range(6):
+            if arith == O.SPA:
+                ch = rng.normal(0.5, 2.0, size=N)
+            else:
+                ch = rng.choice([-3.0, -2.0, -1.0, 1.0, 2.0, 3.0], size=N)
+            ref_kind = O.CIRBP if kind == O.LMDCIRBP else O.RBP
+            a = O.decode(code, ch, kind, arith, max_updates=N, check_every=0, trace=True, frac_bits=0)
+            b = O.decode(code, ch, ref_kind, arith, max_updates=N, check_every=0, trace=True, gamma=0.0,
+                         frac_bits=0)
+            np.testing.assert_array_equal(a.trace, b.trace)
+            assert sorted(a.trace[0]) == list(range(N))  # every edge once
+
+
+@pytest.mark.parametrize("arith", [O.SPA, O.MSFIX])
+def test_table1_counts_lmd_regular_code(arith):
+    """Table 1 on a (3,6)-regular code: after each propagation sLMDRBP makes
+    (d_v - 1)(d_c - 1) - 1 = 9 comparisons, LMDRBP and LMD-CIRBP (d_v - 1) d_c - 1 = 11; the
+    first choice is global (E - 1 residual comparisons, or N - 1 CI comparisons plus d_v - 1)."""
+    code = S.workload_code("c0")
+    cw, llr = S.frames(code, 40, 1.0, 5)
+    first = {O.LMDRBP: code.E - 1, O.SLMDRBP: code.E - 1, O.LMDCIRBP: code.N - 1 + 2}
+    per = {O.LMDRBP: 11, O.SLMDRBP: 9, O.LMDCIRBP: 11}
+    for kind in LMD_KINDS:
+        r = O.decode(code, llr, kind, arith, max_updates=600)
+        u = r.updates_used
+        assert np.all(r.counter("prop") == u)
+        assert np.all(r.counter("pre") == 10 * u)
+        assert np.all(r.counter("cmp") == np.where(u > 0, first[kind], 0) + per[kind] * u)
+        assert np.all(r.counter("fallback") == 0)
+
+
+@pytest.mark.parametrize("kind", LMD_KINDS)
+@pytest.mark.parametrize("arith", [O.SPA, O.MSFIX])
+def test_lmd_incremental_state_equals_definitions(kind, arith):
+    """The state kept by the LMD schedules equals its definitions after every update (the same
+    self-check as the other single-edge schedules), on a code with degree-1 VNs too."""
+    for name in ("c0", "bg"):
+        code = S.workload_code("c0") if name == "c0" else S.qc_bg1_shaped(4, seed=3)
+        cw, llr = S.frames(code, 4, 1.5, 17, zero_codeword=True)
+        O.decode(code, llr, kind, arith, max_updates=300, selfcheck=True)
+
+
+def test_lmd_sign_symmetry_spa():
+    """As for the other schedules: flipping the channel signs on a codeword's support flips the
+    outputs there and leaves the LMD schedule unchanged."""
+    code = S.workload_code("c0")
+    cw, llr = S.frames(code, 20, 2.0, 18)
+    flip = (1.0 - 2.0 * cw)
+    for kind in LMD_KINDS:
+        a = O.decode(code, llr, kind, O.SPA, max_updates=1200, trace=True)
+        b = O.decode(code, llr * flip, kind, O.SPA, max_updates=1200, trace=True)
+        np.testing.assert_array_equal(a.trace, b.trace)
+        np.testing.assert_array_equal(a.llr_out, b.llr_out * flip)
+
+
+def test_lmd_high_snr_decodes_without_errors():
+    code = S.workload_code("c0")
+    cw, llr = S.frames(code, 300, 8.0, 19)
+    for kind in LMD_KINDS:
+        for arith in (O.SPA, O.MSFIX):
+            r = O.decode(code, llr, kind, arith, max_updates=2400, threads=4)
+            assert np.array_equal(r.bits, cw), (kind, arith)
