@@ -7,6 +7,8 @@
  *   - residual BP (RBP): Sec. II-A, steps 1)-4), argmax of eq. (5) over all edges;
  *   - conditional-innovation RBP (CIRBP): Algorithm 1 (Sec. III-B) with the CI metric eq. (9);
  *   - multi-edge CIRBP (ME-CIRBP): Algorithm 5 with the VN selection of Algorithm 4 (Sec. VI);
+ *   - latest-message-driven schedules (Sec. IV): LMDRBP and its simplified form sLMDRBP
+ *     (Algorithm 2), LMD-CIRBP (Algorithm 3), with the degree-1 rule of Sec. V;
  *   - flooding and layered BP baselines (Sec. I);
  *   - replay of a recorded edge order (the schedule held fixed).
  * Messages follow eqs. (1)-(3) (Sec. II-A): V2C, C2V by the tanh rule (sum-product), total LLR
@@ -51,6 +53,19 @@ extern "C" {
 #define LDPC_CIRBP 3
 #define LDPC_ME_CIRBP 4
 #define LDPC_REPLAY 5
+/* LMD schedules: the first update is chosen globally (LMDRBP, sLMDRBP: the edge of largest
+   residual; LMD-CIRBP: the VN of largest CI, then its incoming edge of largest residual).  After an
+   update of (m*, n*) the next one is chosen among the checks of M(n*) \ m*, which have just
+   received n*'s new V2C messages (among m* itself when n* has degree 1, Sec. V):
+     LMDRBP     the edge (i, j), j != n*, of largest residual; then VN j receives its incoming edge
+                of largest residual (Algorithm 2);
+     sLMDRBP    that edge (i, j) itself (Sec. IV-A);
+     LMD-CIRBP  the VN j != n* of largest CI; then its incoming edge of largest residual
+                (Algorithm 3, which leaves that edge choice implicit after the first update).
+   Ties go to the lowest edge id / VN index; there is no gamma threshold. */
+#define LDPC_LMDRBP 6
+#define LDPC_SLMDRBP 7
+#define LDPC_LMD_CIRBP 8
 
 /* arithmetic */
 #define LDPC_SPA_F32 0  /* sum-product, FP32 messages                                          */
@@ -63,7 +78,7 @@ extern "C" {
 typedef struct ldpc_code ldpc_code; /* opaque, library-owned */
 
 typedef struct {
-  int32_t kind;        /* LDPC_FLOODING .. LDPC_REPLAY                                          */
+  int32_t kind;        /* LDPC_FLOODING .. LDPC_LMD_CIRBP                                       */
   int32_t arith;       /* LDPC_SPA_F32 or LDPC_MS_FIX                                            */
   int32_t q_bits;      /* LDPC_MS_FIX: message width, 2..8 (saturation at +-(2^(q-1)-1))         */
   int32_t frac_bits;   /* LDPC_MS_FIX: channel quantisation llr * 2^frac_bits, 0..6              */
@@ -164,9 +179,9 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
                       int64_t* steps_used, int64_t* fallbacks, void* stream);
 
 /* ---- differentiable unrolled decoder ------------------------------------------------------
-   A schedule recorded by a single-edge decode (ldpc_outputs.trace of LDPC_RBP / LDPC_CIRBP with
-   check_every = 0, so that every frame runs exactly T updates) is replayed with a weight w_e per
-   edge.  From c2v = 0 and L = llr, step t on edge e = trace[f][t] (check m, VN n) does
+   A schedule recorded by a single-edge decode (ldpc_outputs.trace of LDPC_RBP, LDPC_CIRBP or an
+   LMD schedule with check_every = 0, so that every frame runs exactly T updates) is replayed with
+   a weight w_e per edge.  From c2v = 0 and L = llr, step t on edge e = trace[f][t] (check m, VN n) does
        c2v_e += w_e (pre_e - c2v_e),   L_n += the same amount,
    where pre_e is the C2V rule of eq. (2) over the V2C messages L_k - c2v_{m->k}, k != n (the
    propagation step of Sec. II-A, steps 3-4, which it equals for w_e = 1).  FP32 sum-product.

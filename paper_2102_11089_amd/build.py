@@ -16,7 +16,7 @@ HEADERS = ["common.hpp", "kernels.hpp", "dyn_frame.hpp"]
 ARCH = os.environ.get("LDPCCI_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions stay off: plain scalar FP32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
@@ -36,15 +36,35 @@ def sources_digest() -> str:
     return h.hexdigest()
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into one shared library (always recompiles)."""
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every HIP source (always recompiles), one compiler process per source in parallel,
+    and link them into one shared library."""
+    import concurrent.futures
+    import shutil
+    import tempfile
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *FLAGS, "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    jobs = jobs or max(1, min(len(srcs), os.cpu_count() or 1, 8))
+    work = tempfile.mkdtemp(prefix="ldpcci_build_")
+    try:
+        objs = [os.path.join(work, os.path.basename(src) + ".o") for src in srcs]
+
+        def compile_one(src, obj):
+            cmd = ["hipcc", *FLAGS, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.check_call(cmd)
+
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+            for f in [ex.submit(compile_one, s, o) for s, o in zip(srcs, objs)]:
+                f.result()
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(work, ignore_errors=True)
     return LIB
 
 

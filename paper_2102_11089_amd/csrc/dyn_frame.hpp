@@ -1,5 +1,6 @@
-// Per-frame body of the single-edge dynamic decoder (RBP, CIRBP, replay) for one wavefront;
-// used by the per-code kernel and by the persistent batched kernel.
+// Per-frame body of the single-edge dynamic decoder (RBP, CIRBP, replay, and the latest-message-
+// driven LMDRBP, sLMDRBP and LMD-CIRBP) for one wavefront; used by the per-code kernel and by the
+// persistent batched kernel.
 #pragma once
 #include "common.hpp"
 #include "kernels.hpp"
@@ -191,7 +192,9 @@ __device__ __forceinline__ void leaf_moved(uint64_t* blk, uint32_t* mask, int b,
   else if (nk < cur && key_idx(cur) == i) atomicOr(&mask[b >> 5], 1u << (b & 31));
 }
 
-template <class A, int STORE, class Topo>
+// LMD: the variant for the LMD schedules (a separate instantiation, so that the others keep their
+// register budget); J.kind must then be one of them
+template <class A, int STORE, class Topo, bool LMD = false>
 __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
                                                  const MsgStore<A, STORE>& ms, const FrameJob& J) {
   using msg_t = typename A::msg_t;
@@ -226,8 +229,13 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   const int N = H.N, M = H.M, E = H.E;
   const int nbd = (N + WAVE - 1) / WAVE, nbc = (M + WAVE - 1) / WAVE;
   const int nbd_words = (nbd + 31) / 32, nbc_words = (nbc + 31) / 32;
-  const bool with_ci = J.kind != KIND_RBP;
-  // CI of VN n: stored, or evaluated from the VN's record (record layouts); RBP keeps none
+  // LMD schedules (Sec. IV): after the first update the next one is chosen among the messages the
+  // update just precomputed, so the global selection keys are used once and then left stale
+  constexpr bool lmd = LMD;
+  const bool lmd_ci = LMD && J.kind == KIND_LMD_CIRBP;
+  const bool with_ci = J.kind == KIND_CIRBP || J.kind == KIND_REPLAY || lmd_ci;
+  // CI of VN n: stored, or evaluated from the VN's record (record layouts); RBP and the residual
+  // LMD schedules keep none
   auto d_of = [&](int n) -> uint32_t {
     if constexpr (MsgStore<A, STORE>::kDerivedD) {
       llr_t ltv, lv;
@@ -300,6 +308,9 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
 
   // ---------------- update loop -------------------------------------------------------
   long long t = 0, nfall = 0;
+  // LMD: the choice the last update made (an edge for sLMDRBP, the VN n' otherwise); -1 before the
+  // first update, whose choice is global
+  int lmd_next = -1;
   long long limit = J.max_updates;
   if (J.kind == KIND_REPLAY && J.replay_len < limit) limit = J.replay_len;
   const long long ce = J.kind == KIND_REPLAY ? 0 : J.check_every;
@@ -344,15 +355,23 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       mstar = uni(G.edge_row(estar));
       nstar = uni(G.edge_vn(estar));
       start_nstar(nstar);
+    } else if (lmd && J.kind == KIND_SLMDRBP && lmd_next >= 0) {  // sLMDRBP: the edge chosen last time
+      estar = lmd_next;
+      mstar = uni(G.edge_row(estar));
+      nstar = uni(G.edge_vn(estar));
+      start_nstar(nstar);
     } else {
-      bool global_res = J.kind == KIND_RBP;
+      // RBP, and the first update of LMDRBP / sLMDRBP: the global residual maximum
+      bool global_res = J.kind == KIND_RBP || (lmd && J.kind != KIND_LMD_CIRBP && lmd_next < 0);
       int nsel = -1;
-      if (!global_res) {
+      if (lmd && !global_res && lmd_next >= 0) {
+        nsel = lmd_next;  // LMDRBP, LMD-CIRBP: n' receives its incoming edge of largest residual
+      } else if (!global_res) {
         uint64_t k = 0;
         for (int b = lane; b < nbd; b += WAVE) k = umax64(k, dblk[b]);
         k = wave_max_u64(k);
         nsel = (int)key_idx(k);
-        if (key_val(k) < J.gamma_bits) {  // D_{n*} < gamma: RBP fallback
+        if (J.kind == KIND_CIRBP && key_val(k) < J.gamma_bits) {  // D_{n*} < gamma: RBP fallback
           global_res = true;
           nfall += 1;
         }
@@ -454,7 +473,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       ms.set_l(nstar, (llr_t)Lnew);
       if (with_ci) {
         ms.set_d(nstar, dn_new);
-        leaf_moved(dblk, dmask, nstar >> 6, (uint32_t)nstar, mkkey(dn_new, (uint32_t)nstar));
+        if (!lmd) leaf_moved(dblk, dmask, nstar >> 6, (uint32_t)nstar, mkkey(dn_new, (uint32_t)nstar));
       }
     }
     if ((Lold < 0) != (Lnew < 0)) {  // hard decision flipped: toggle the checks of n*
@@ -469,7 +488,25 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     wave_sync();
     PROF_MARK(1)
 
-    if (row_only) {  // m*'s new residual key: its row with c2v[e*] = pre[e*]
+    // LMD candidates of this lane: the largest key (residual and edge, or CI and VN) and its VN
+    uint64_t lk = 0;
+    int lkj = -1;
+    auto lmd_offer = [&](uint64_t k, int j) {
+      if (k > lk) {
+        lk = k;
+        lkj = j;
+      }
+    };
+    if (row_only && lmd) {  // n* has degree 1: the candidates are the other edges / VNs of m* (Sec. V)
+      if (lane < dc_m) {
+        const int e = rs_m + lane;
+        const int j = G.row_vn(mstar, rs_m, lane);
+        if (j != nstar) {
+          if (lmd_ci) lmd_offer(mkkey(d_of(j), (uint32_t)j), j);
+          else lmd_offer(mkkey(ar.res((val_t)row_pm, (val_t)row_cm), (uint32_t)e), j);
+        }
+      }
+    } else if (row_only) {  // m*'s new residual key: its row with c2v[e*] = pre[e*]
       uint64_t k = 0;
       if (lane < dc_m) {
         const int e = rs_m + lane;
@@ -523,7 +560,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
             const val_t ltn = (val_t)in_cur.ltj + dlt;
             const uint32_t nd = ar.ci(lv, ltn);
             ms.set_lt_d(j, (llr_t)ltn, nd);
-            leaf_moved(dblk, dmask, j >> 6, (uint32_t)j, mkkey(nd, (uint32_t)j));
+            if (lmd) lmd_offer(mkkey(nd, (uint32_t)j), j);
+            else leaf_moved(dblk, dmask, j >> 6, (uint32_t)j, mkkey(nd, (uint32_t)j));
           } else if (grp < kGroups) {  // summed in LDS; Lt_j itself is untouched until the passes end
             atomicAdd(&gacc[grp], (llr_t)dlt);
             gj[grp] = j;
@@ -538,11 +576,15 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
       const bool late = with_ci && upd && twice && grp == kGroups;
       tj[ps * WAVE + lane] = late ? j : -1;
       late_ci = late_ci || __ballot(late) != 0ull;
-      const uint64_t rk = keymax_all(valid ? mkkey(ar.res(pv, cv), (uint32_t)e) : 0ull, L2, maxL2);
-      if (leader) {  // one lane per check: new residual key, block maximum
-        const int m = G.edge_row(e);
-        ckey[m] = key_val(rk);
-        leaf_moved(cblk, cmask, m >> 6, (uint32_t)m, mkkey(key_val(rk), (uint32_t)m));
+      if (lmd) {
+        if (upd && !lmd_ci) lmd_offer(mkkey(ar.res(pv, cv), (uint32_t)e), j);
+      } else {
+        const uint64_t rk = keymax_all(valid ? mkkey(ar.res(pv, cv), (uint32_t)e) : 0ull, L2, maxL2);
+        if (leader) {  // one lane per check: new residual key, block maximum
+          const int m = G.edge_row(e);
+          ckey[m] = key_val(rk);
+          leaf_moved(cblk, cmask, m >> 6, (uint32_t)m, mkkey(key_val(rk), (uint32_t)m));
+        }
       }
       in_cur = in_next;
       ent_next = ent_after;
@@ -557,7 +599,8 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         const int jg = gj[lane];
         const uint32_t nd = ar.ci((val_t)gl[lane], ltn);
         ms.set_lt_d(jg, (llr_t)ltn, nd);
-        leaf_moved(dblk, dmask, jg >> 6, (uint32_t)jg, mkkey(nd, (uint32_t)jg));
+        if (lmd) lmd_offer(mkkey(nd, (uint32_t)jg), jg);
+        else leaf_moved(dblk, dmask, jg >> 6, (uint32_t)jg, mkkey(nd, (uint32_t)jg));
         gacc[lane] = (llr_t)0;
       }
       wave_sync();
@@ -577,15 +620,25 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         wave_sync();
         if (j >= 0) {
           ms.set_d(j, nd);
-          leaf_moved(dblk, dmask, j >> 6, (uint32_t)j, mkkey(nd, (uint32_t)j));
+          if (lmd) lmd_offer(mkkey(nd, (uint32_t)j), j);
+          else leaf_moved(dblk, dmask, j >> 6, (uint32_t)j, mkkey(nd, (uint32_t)j));
         }
         wave_sync();
       }
     }
     PROF_MARK(5)
+    // ---- LMD: the next choice, the largest candidate key (lowest edge / VN on ties).  The set is
+    //      never empty: every check has degree 2 or more, so m* or a check of M(n*) \ m* has a VN
+    //      other than n* ----
+    if constexpr (LMD) {
+      const uint64_t kmax = wave_max_u64(lk);
+      const unsigned long long win = __ballot(lk == kmax && lk != 0ull);
+      if (J.kind == KIND_SLMDRBP) lmd_next = kmax ? (int)key_idx(kmax) : -1;
+      else lmd_next = win ? __builtin_amdgcn_readlane(lkj, (int)__builtin_ctzll(win)) : -1;
+    }
     // ---- blocks whose maximum leaf decreased: one check block and one VN block per round, so
-    //      that their leaf loads share a round trip ----
-    {
+    //      that their leaf loads share a round trip (nothing to do for the LMD schedules) ----
+    if (!lmd) {
       int cw = 0, dw = 0;
       uint32_t cbits = nbc_words > 0 ? (uint32_t)uni((int)cmask[0]) : 0u;
       uint32_t dbits = (with_ci && nbd_words > 0) ? (uint32_t)uni((int)dmask[0]) : 0u;

@@ -1,5 +1,6 @@
 // Single-edge dynamic schedules on gfx950: residual BP (RBP, Sec. II-A steps 1-4), CIRBP
-// (Algorithm 1, Sec. III-B) and forced-order replay of a recorded schedule.
+// (Algorithm 1, Sec. III-B), forced-order replay of a recorded schedule, and the latest-message-
+// driven LMDRBP, sLMDRBP and LMD-CIRBP (Algorithms 2 and 3, Sec. IV) as separate kernel variants.
 //
 // One wavefront (64 lanes) decodes one codeword at a time; a workgroup holds one or more such
 // frames, which share the workgroup's copy of the topology (and p0 table) in LDS.  A persistent grid pulls
@@ -32,8 +33,9 @@ namespace ldpc {
 
 
 // MF: several frames per workgroup (up to 16 wavefronts); otherwise one wavefront per workgroup,
-// which lets the compiler keep the register count at the level of full occupancy
-template <class A, int STORE, int TOPO, bool MF>
+// which lets the compiler keep the register count at the level of full occupancy.  LMD: the LMD
+// schedules (their local choice keeps a few more values live across the update)
+template <class A, int STORE, int TOPO, bool MF, bool LMD>
 __global__ __launch_bounds__(MF ? 1024 : WAVE) void k_dynamic(DevCode H, DynParams P) {
   unsigned char* lds = dyn_lds();
   const int lane = threadIdx.x & (WAVE - 1);
@@ -71,22 +73,27 @@ __global__ __launch_bounds__(MF ? 1024 : WAVE) void k_dynamic(DevCode H, DynPara
     J.dump_L = P.out.dump_L ? P.out.dump_L + (size_t)f * H.N : nullptr;
     J.dump_Lt = P.out.dump_Lt ? P.out.dump_Lt + (size_t)f * H.N : nullptr;
     J.dump_D = P.out.dump_D ? P.out.dump_D + (size_t)f * H.N : nullptr;
-    dyn_decode_frame<A, STORE>(H, G, ar, P, ms, J);
+    dyn_decode_frame<A, STORE, decltype(G), LMD>(H, G, ar, P, ms, J);
     if (P.queue) f = uni(lane == 0 ? atomicAdd(P.queue, 1) : 0);
     else f += gridDim.x * P.wpb;
   }
 }
 
-template <class A, int ST, int TP>
-static hipError_t launch_dyn(const DevCode& H, const DynParams& P, int grid, hipStream_t st) {
+template <class A, int ST, int TP, bool LMD>
+static hipError_t launch_dyn_l(const DevCode& H, const DynParams& P, int grid, hipStream_t st) {
   if constexpr (TP != TOPO_GLOBAL) {
     if (P.wpb > 1) {
-      hipLaunchKernelGGL((k_dynamic<A, ST, TP, true>), dim3(grid), dim3(WAVE * P.wpb), P.lds_bytes, st, H, P);
+      hipLaunchKernelGGL((k_dynamic<A, ST, TP, true, LMD>), dim3(grid), dim3(WAVE * P.wpb), P.lds_bytes, st, H, P);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_dynamic<A, ST, TP, false>), dim3(grid), dim3(WAVE), P.lds_bytes, st, H, P);
+  hipLaunchKernelGGL((k_dynamic<A, ST, TP, false, LMD>), dim3(grid), dim3(WAVE), P.lds_bytes, st, H, P);
   return hipGetLastError();
+}
+
+template <class A, int ST, int TP>
+static hipError_t launch_dyn(const DevCode& H, const DynParams& P, int grid, hipStream_t st) {
+  return is_lmd(P.kind) ? launch_dyn_l<A, ST, TP, true>(H, P, grid, st) : launch_dyn_l<A, ST, TP, false>(H, P, grid, st);
 }
 
 template <class A, int ST>
@@ -112,13 +119,20 @@ hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, int 
   return fixed ? launch_dyn_s<ArithFix>(H, P, store, topo, grid, st) : launch_dyn_s<ArithF32>(H, P, store, topo, grid, st);
 }
 
-template <class A, int ST, int TP>
-static hipError_t set_one(int bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_dynamic<A, ST, TP, false>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+template <class A, int ST, int TP, bool LMD>
+static hipError_t set_one_l(int bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_dynamic<A, ST, TP, false, LMD>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if constexpr (TP != TOPO_GLOBAL) {
     if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_dynamic<A, ST, TP, true>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+      e = hipFuncSetAttribute((const void*)k_dynamic<A, ST, TP, true, LMD>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   }
+  return e;
+}
+
+template <class A, int ST, int TP>
+static hipError_t set_one(int bytes) {
+  hipError_t e = set_one_l<A, ST, TP, false>(bytes);
+  if (e == hipSuccess) e = set_one_l<A, ST, TP, true>(bytes);
   return e;
 }
 
@@ -131,12 +145,16 @@ static hipError_t set_store(int bytes) {
 }
 
 // VGPRs per lane of one kernel variant (0 if the runtime cannot tell), cached per variant
+template <class A, int ST, bool LMD>
+static const void* kernel_of(int topo, bool mf) {
+  if (topo == TOPO_QC) return mf ? (const void*)k_dynamic<A, ST, TOPO_QC, true, LMD> : (const void*)k_dynamic<A, ST, TOPO_QC, false, LMD>;
+  if (topo == TOPO_LDS) return mf ? (const void*)k_dynamic<A, ST, TOPO_LDS, true, LMD> : (const void*)k_dynamic<A, ST, TOPO_LDS, false, LMD>;
+  return (const void*)k_dynamic<A, ST, TOPO_GLOBAL, false, LMD>;
+}
+
 template <class A, int ST>
-static int vgprs_of(int topo, bool mf) {
-  const void* f = nullptr;
-  if (topo == TOPO_QC) f = mf ? (const void*)k_dynamic<A, ST, TOPO_QC, true> : (const void*)k_dynamic<A, ST, TOPO_QC, false>;
-  else if (topo == TOPO_LDS) f = mf ? (const void*)k_dynamic<A, ST, TOPO_LDS, true> : (const void*)k_dynamic<A, ST, TOPO_LDS, false>;
-  else f = (const void*)k_dynamic<A, ST, TOPO_GLOBAL, false>;
+static int vgprs_of(int topo, bool mf, bool lmd) {
+  const void* f = lmd ? kernel_of<A, ST, true>(topo, mf) : kernel_of<A, ST, false>(topo, mf);
   hipFuncAttributes at{};
   if (hipFuncGetAttributes(&at, f) != hipSuccess) {
     (void)hipGetLastError();
@@ -146,26 +164,26 @@ static int vgprs_of(int topo, bool mf) {
 }
 
 template <class A>
-static int vgprs_s(int store, int topo, bool mf) {
+static int vgprs_s(int store, int topo, bool mf, bool lmd) {
   switch (store) {
-    case STORE_LDS: return vgprs_of<A, STORE_LDS>(topo, mf);
-    case STORE_PRE_GLOBAL: return vgprs_of<A, STORE_PRE_GLOBAL>(topo, mf);
-    case STORE_ALL_GLOBAL: return vgprs_of<A, STORE_ALL_GLOBAL>(topo, mf);
-    case STORE_ALL_GLOBAL_LT: return vgprs_of<A, STORE_ALL_GLOBAL_LT>(topo, mf);
-    case STORE_FRAME_GLOBAL: return vgprs_of<A, STORE_FRAME_GLOBAL>(topo, mf);
-    case STORE_FRAME_REC: return vgprs_of<A, STORE_FRAME_REC>(topo, mf);
-    default: return vgprs_of<A, STORE_FRAME_ALL>(topo, mf);
+    case STORE_LDS: return vgprs_of<A, STORE_LDS>(topo, mf, lmd);
+    case STORE_PRE_GLOBAL: return vgprs_of<A, STORE_PRE_GLOBAL>(topo, mf, lmd);
+    case STORE_ALL_GLOBAL: return vgprs_of<A, STORE_ALL_GLOBAL>(topo, mf, lmd);
+    case STORE_ALL_GLOBAL_LT: return vgprs_of<A, STORE_ALL_GLOBAL_LT>(topo, mf, lmd);
+    case STORE_FRAME_GLOBAL: return vgprs_of<A, STORE_FRAME_GLOBAL>(topo, mf, lmd);
+    case STORE_FRAME_REC: return vgprs_of<A, STORE_FRAME_REC>(topo, mf, lmd);
+    default: return vgprs_of<A, STORE_FRAME_ALL>(topo, mf, lmd);
   }
 }
 
-int dynamic_waves_per_simd(bool fixed, int store, int topo, bool mf) {
+int dynamic_waves_per_simd(bool fixed, int store, int topo, bool mf, bool lmd) {
   static std::mutex mu;
   static std::map<int, int> cache;
-  const int key = ((fixed ? 1 : 0) * kStores + store) * 8 + topo * 2 + (mf ? 1 : 0);
+  const int key = (((fixed ? 1 : 0) * kStores + store) * 8 + topo * 2 + (mf ? 1 : 0)) * 2 + (lmd ? 1 : 0);
   std::lock_guard<std::mutex> lk(mu);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
-  const int regs = fixed ? vgprs_s<ArithFix>(store, topo, mf) : vgprs_s<ArithF32>(store, topo, mf);
+  const int regs = fixed ? vgprs_s<ArithFix>(store, topo, mf, lmd) : vgprs_s<ArithF32>(store, topo, mf, lmd);
   // 512 VGPRs per SIMD lane, allocated in granules of 8; at most 8 wavefronts per SIMD
   const int waves = regs > 0 ? std::max(1, std::min(8, 512 / ((regs + 7) / 8 * 8))) : 8;
   cache[key] = waves;

@@ -627,7 +627,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (plan_only && !out) out = &no_out;
   if (!c || !s || !out || B < 0 || max_updates < 0) return LDPC_EINVAL;
   if (!plan_only && B > 0 && (!llr_in || !out->bits || !out->updates_used)) return LDPC_EINVAL;
-  if (s->kind < LDPC_FLOODING || s->kind > LDPC_REPLAY) return LDPC_EINVAL;
+  if (s->kind < LDPC_FLOODING || s->kind > LDPC_LMD_CIRBP) return LDPC_EINVAL;
   if (s->arith != LDPC_SPA_F32 && s->arith != LDPC_MS_FIX) return LDPC_EINVAL;
   const bool fixed = s->arith == LDPC_MS_FIX;
   if (fixed && (s->q_bits < 2 || s->q_bits > 8 || s->frac_bits < 0 || s->frac_bits > 6)) return LDPC_EINVAL;
@@ -806,7 +806,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   // count (4 SIMDs per CU)
   auto wgs_per_cu = [&](const DynLayout& ly, int st, int tp, int w) {
     const int by_lds = std::max(1, (160 * 1024) / std::max(ly.total, 1));
-    const int wps = dynamic_waves_per_simd(fixed, st, tp, tp != TOPO_GLOBAL && w > 1);
+    const int wps = dynamic_waves_per_simd(fixed, st, tp, tp != TOPO_GLOBAL && w > 1, is_lmd(s->kind));
     const int by_waves = std::max(1, (4 * wps) / w);
     return std::min(by_lds, by_waves);
   };
@@ -1005,7 +1005,8 @@ int ldpc_describe_plan(const ldpc_code* c, const ldpc_schedule* s, int32_t B, ld
   r.frames_per_workgroup = pl.which == 1 ? pl.dyn.wpb : 1;
   const int lds = pl.which == 0 ? pl.base.lds_bytes : (pl.which == 1 ? pl.dyn.lds_bytes : pl.me.lds_bytes);
   const int by_lds = std::max(1, (160 * 1024) / std::max(lds, 1));
-  const int wps = pl.which == 1 ? dynamic_waves_per_simd(pl.fixed, pl.store, pl.topo, pl.topo != TOPO_GLOBAL && pl.dyn.wpb > 1)
+  const int wps = pl.which == 1 ? dynamic_waves_per_simd(pl.fixed, pl.store, pl.topo, pl.topo != TOPO_GLOBAL && pl.dyn.wpb > 1,
+                                                       is_lmd(pl.dyn.kind))
                                 : 8;
   const int by_waves = std::max(1, 4 * wps / std::max(1, pl.block / WAVE));
   r.workgroups_per_cu = std::min(by_lds, by_waves);
@@ -1017,7 +1018,7 @@ int ldpc_describe_plan(const ldpc_code* c, const ldpc_schedule* s, int32_t B, ld
 }
 
 int ldpc_set_tuning(const ldpc_code* c, int32_t kind, int32_t arith, const ldpc_tuning* t) {
-  if (!c || kind < LDPC_FLOODING || kind > LDPC_REPLAY || (arith != LDPC_SPA_F32 && arith != LDPC_MS_FIX))
+  if (!c || kind < LDPC_FLOODING || kind > LDPC_LMD_CIRBP || (arith != LDPC_SPA_F32 && arith != LDPC_MS_FIX))
     return LDPC_EINVAL;
   if (int rc = check_tuning(t)) return rc;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1162,7 +1163,7 @@ int ldpc_tuning_load(const char* path) {
                     "\"storage\": %d, \"topology\": %d}",
                     &sig, &k.kind, &k.arith, &t.block, &t.frames_per_cu, &t.storage, &t.topology) == 7) {
       k.sig = sig;
-      if (check_tuning(&t) != LDPC_OK || k.kind < LDPC_FLOODING || k.kind > LDPC_REPLAY) continue;
+      if (check_tuning(&t) != LDPC_OK || k.kind < LDPC_FLOODING || k.kind > LDPC_LMD_CIRBP) continue;
       rows.push_back({k, t});
     }
   }

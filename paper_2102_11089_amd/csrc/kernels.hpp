@@ -7,7 +7,18 @@
 
 namespace ldpc {
 
-enum Kind { KIND_FLOODING = 0, KIND_LAYERED = 1, KIND_RBP = 2, KIND_CIRBP = 3, KIND_ME_CIRBP = 4, KIND_REPLAY = 5 };
+enum Kind {
+  KIND_FLOODING = 0,
+  KIND_LAYERED = 1,
+  KIND_RBP = 2,
+  KIND_CIRBP = 3,
+  KIND_ME_CIRBP = 4,
+  KIND_REPLAY = 5,
+  KIND_LMDRBP = 6,
+  KIND_SLMDRBP = 7,
+  KIND_LMD_CIRBP = 8
+};
+__host__ __device__ constexpr bool is_lmd(int k) { return k == KIND_LMDRBP || k == KIND_SLMDRBP || k == KIND_LMD_CIRBP; }
 enum Topo { TOPO_GLOBAL = 0, TOPO_LDS = 1, TOPO_QC = 2 };
 // single-edge frame storage: c2v and pre in LDS; pre in a global slot; both in a global slot; both
 // and the precomputed totals Lt in a global slot; the whole frame (messages, Lt, L, D) in a global
@@ -164,7 +175,7 @@ hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, int 
                           hipStream_t st);
 hipError_t set_dynamic_lds_limit(int bytes);
 // wavefronts of one single-edge kernel variant a SIMD can hold by its register count (1..8)
-int dynamic_waves_per_simd(bool fixed, int store, int topo, bool mf);
+int dynamic_waves_per_simd(bool fixed, int store, int topo, bool mf, bool lmd);
 hipError_t launch_baseline(const DevCode& H, const BaseParams& P, bool fixed, int grid, int block,
                            hipStream_t st);
 hipError_t set_baseline_lds_limit(int bytes);

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libldpcci.so")
 
 # schedules / arithmetic / fill (values of include/ldpcci.h)
-FLOODING, LAYERED, RBP, CIRBP, ME_CIRBP, REPLAY = range(6)
+FLOODING, LAYERED, RBP, CIRBP, ME_CIRBP, REPLAY, LMDRBP, SLMDRBP, LMD_CIRBP = range(9)
 SPA_F32, MS_FIX = 0, 1
 FILL_LOWEST, FILL_HASH = 0, 1
 ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -4: "LDPC_ECAPACITY",
@@ -382,7 +382,7 @@ def decode_batch(codes, frames: np.ndarray, llr_pool, out_len: int, arith: int =
 # ----------------------------------------------------------------------------------------------
 def record_schedule(code: Code, llr, T: int, kind: int = CIRBP, gamma: float = 0.1, stream=None):
     """Record T single-edge updates per frame (no early stop): an int32 (B, T) CUDA tensor."""
-    assert kind in (RBP, CIRBP)
+    assert kind in (RBP, CIRBP, LMDRBP, SLMDRBP, LMD_CIRBP)
     return decode(code, llr, kind, SPA_F32, max_updates=T, gamma=gamma, check_every=0, trace=True,
                   stream=stream).trace
 

@@ -1,0 +1,209 @@
+"""GPU parity of the LMD schedules (Sec. IV: LMDRBP, sLMDRBP; Algorithm 3: LMD-CIRBP; the degree-1
+rule of Sec. V) against the CPU oracle, through the C ABI.
+
+* fixed-point min-sum: bit-exact (recorded schedule, updates used, decoded bits, final state);
+* FP32 sum-product: free-running frame error rates within the oracle's 95% Clopper-Pearson
+  interval (the arithmetic itself is pinned by the replay tests of the other schedules: the LMD
+  schedules share the update path and differ only in the choice of the next edge).
+"""
+import numpy as np
+import pytest
+import torch
+from scipy.stats import beta
+
+from oracle import oracle as O
+from paper_2102_11089_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+KINDS = {"lmdrbp": (O.LMDRBP, 6), "slmdrbp": (O.SLMDRBP, 7), "lmdcirbp": (O.LMDCIRBP, 8)}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def np_(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def gpu_decode(ldpc, code_h, llr, kind, arith, **kw):
+    t = torch.from_numpy(np.ascontiguousarray(llr, dtype=np.float32)).cuda()
+    r = ldpc.decode(code_h, t, KINDS[kind][1], arith, **kw)
+    torch.cuda.synchronize()
+    return r
+
+
+def assert_fixed_equal(g, ref, kind, state=True):
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+    np.testing.assert_array_equal(np_(g.fallbacks), 0)
+    if state:
+        np.testing.assert_array_equal(np_(g.c2v), ref.c2v)
+        np.testing.assert_array_equal(np_(g.pre), ref.pre)
+        np.testing.assert_array_equal(np_(g.L), ref.L)
+        if kind == "lmdcirbp":  # the residual LMD schedules keep no CIs
+            np.testing.assert_array_equal(np_(g.Lt), ref.Lt)
+            np.testing.assert_array_equal(np_(g.D), ref.D)
+
+
+def test_constants_match_the_oracle(gpu):
+    assert (gpu.LMDRBP, gpu.SLMDRBP, gpu.LMD_CIRBP) == (O.LMDRBP, O.SLMDRBP, O.LMDCIRBP)
+
+
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_fixed_lmd_bit_exact_c0(gpu, kind):
+    """(3,6)-regular N = 96: every VN has degree 3, so every choice after the first is local."""
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 1000, 2.0, 200)
+    mu = 2400
+    say(f"[fixed {kind}] c0 1000 frames, cap {mu}")
+    kw = dict(max_updates=mu, q_bits=6, frac_bits=1, trace=True, dump=True)
+    ref = O.decode(code, llr, KINDS[kind][0], O.MSFIX, threads=8, **kw)
+    g = gpu_decode(gpu, h, llr, kind, gpu.MS_FIX, **kw)
+    assert_fixed_equal(g, ref, kind)
+    np.testing.assert_array_equal(np_(g.llr_out), ref.llr_out.astype(np.float32))
+
+
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_fixed_lmd_tie_heavy_inputs(gpu, kind):
+    """Integer channel values from a tiny alphabet (exact zeros included) on a ragged N = 200: most
+    local choices are decided by the lowest-index rule."""
+    code = S.peg_regular(200, 3, 6, seed=3)
+    h = gpu.Code(code)
+    rng = np.random.default_rng(6)
+    llr = rng.choice([-1.0, -0.5, 0.0, 0.5, 1.0, 1.5], size=(300, code.N)).astype(np.float32)
+    say(f"[fixed ties {kind}] N=200")
+    kw = dict(max_updates=700, trace=True, dump=True)
+    ref = O.decode(code, llr, KINDS[kind][0], O.MSFIX, threads=8, **kw)
+    g = gpu_decode(gpu, h, llr, kind, gpu.MS_FIX, **kw)
+    assert_fixed_equal(g, ref, kind)
+
+
+@pytest.mark.parametrize("store", ["lds", "all", "rec", "state"])
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_fixed_lmd_degree_one_vns(gpu, store, kind):
+    """BG1-shaped base graph lifted by Z = 4 (n = 272, degree-1 VNs): after an update of a degree-1
+    VN the next choice comes from m* itself (Sec. V); bit-exact in every storage layout."""
+    code = S.qc_bg1_shaped(4, seed=3)
+    cw, llr = S.frames(code, 96, 1.0, 201)
+    st = {"lds": gpu.STORE_LDS, "all": gpu.STORE_GLOBAL_ALL, "rec": gpu.STORE_GLOBAL_REC,
+          "state": gpu.STORE_GLOBAL_STATE}[store]
+    say(f"[degree-1 VNs] bg1 Z=4 {kind} store={store}")
+    kw = dict(max_updates=2000, q_bits=8, frac_bits=2, trace=True, dump=True)
+    ref = O.decode(code, llr, KINDS[kind][0], O.MSFIX, threads=8, **kw)
+    # the rule for degree-1 VNs is exercised
+    deg = np.bincount(code.col, minlength=code.N)
+    tr = ref.trace[ref.trace >= 0]
+    assert np.any(deg[code.col[tr]] == 1)
+    h = gpu.Code(code)
+    gpu.set_tuning(h, KINDS[kind][1], gpu.MS_FIX, storage=st, frames_per_cu=2)
+    try:
+        g = gpu_decode(gpu, h, llr, kind, gpu.MS_FIX, **kw)
+    finally:
+        gpu.set_tuning(h, KINDS[kind][1], gpu.MS_FIX, clear=True)
+    assert_fixed_equal(g, ref, kind)
+
+
+@pytest.mark.parametrize("store", ["lds", "rec", "state"])
+def test_fixed_lmd_repeated_two_hop_vns(gpu, store):
+    """VNs met on several checks of n* (4-cycles) appear more than once among the candidates; their
+    CI is final only after every change of the update (LDS groups and the overflow path)."""
+    from test_gpu_parity import many_four_cycles_code
+    code = many_four_cycles_code()
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 200, 1.0, 202)
+    st = {"lds": gpu.STORE_LDS, "rec": gpu.STORE_GLOBAL_REC, "state": gpu.STORE_GLOBAL_STATE}[store]
+    for kind in ("lmdcirbp", "lmdrbp"):
+        say(f"[repeated two-hop VNs] overlap32 {kind} store={store}")
+        kw = dict(max_updates=400, check_every=0, q_bits=8, frac_bits=2, trace=True, dump=True)
+        ref = O.decode(code, llr, KINDS[kind][0], O.MSFIX, threads=8, **kw)
+        gpu.set_tuning(h, KINDS[kind][1], gpu.MS_FIX, storage=st, frames_per_cu=2)
+        try:
+            g = gpu_decode(gpu, h, llr, kind, gpu.MS_FIX, **kw)
+        finally:
+            gpu.set_tuning(h, KINDS[kind][1], gpu.MS_FIX, clear=True)
+        assert_fixed_equal(g, ref, kind)
+
+
+@pytest.mark.parametrize("pre", ["lds", "global", "all", "all_lt", "frame", "rec", "state"])
+def test_fixed_lmd_storage_variants(gpu, pre):
+    """Every storage layout, several frames per workgroup sharing the quasi-cyclic tables."""
+    code = S.qc_24col(24, 12, seed=4)  # N = 576
+    cw, llr = S.frames(code, 200, 2.0, 203)
+    store = {"lds": gpu.STORE_LDS, "global": gpu.STORE_GLOBAL, "all": gpu.STORE_GLOBAL_ALL,
+             "all_lt": gpu.STORE_GLOBAL_LT, "frame": gpu.STORE_GLOBAL_FRAME, "rec": gpu.STORE_GLOBAL_REC,
+             "state": gpu.STORE_GLOBAL_STATE}[pre]
+    h = gpu.Code(code)
+    for kind in ("lmdcirbp", "slmdrbp"):
+        say(f"[variant {kind} pre={pre}] qc24 Z=24")
+        kw = dict(max_updates=1500, q_bits=8, frac_bits=2, trace=True, dump=True)
+        ref = O.decode(code, llr, KINDS[kind][0], O.MSFIX, threads=8, **kw)
+        gpu.set_tuning(h, KINDS[kind][1], gpu.MS_FIX, frames_per_cu=3, storage=store, topology=gpu.TOPO_QC)
+        try:
+            g = gpu_decode(gpu, h, llr, kind, gpu.MS_FIX, **kw)
+        finally:
+            gpu.set_tuning(h, KINDS[kind][1], gpu.MS_FIX, clear=True)
+        assert_fixed_equal(g, ref, kind)
+
+
+def test_fixed_lmd_bg1_shaped_full_size_sampled(gpu):
+    """The Z = 52 BG1-shaped code at full size in the default plan: a few frames, bit-exact."""
+    code = S.workload_code("c1")
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 4, 1.25, 204)
+    for kind in ("lmdcirbp", "lmdrbp"):
+        say(f"[fixed {kind}] c1 4 frames, cap 3000")
+        kw = dict(max_updates=3000, q_bits=8, frac_bits=2, trace=True)
+        ref = O.decode(code, llr, KINDS[kind][0], O.MSFIX, threads=4, **kw)
+        g = gpu_decode(gpu, h, llr, kind, gpu.MS_FIX, **kw)
+        assert_fixed_equal(g, ref, kind, state=False)
+
+
+def cp_interval(k, n, a=0.05):
+    lo = 0.0 if k == 0 else beta.ppf(a / 2, k, n - k + 1)
+    hi = 1.0 if k == n else beta.ppf(1 - a / 2, k + 1, n - k)
+    return lo, hi
+
+
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_f32_lmd_fer_within_interval_c0(gpu, kind):
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 1000, 2.0, 205)
+    say(f"[f32 FER {kind}] c0 1000 frames")
+    ref = O.decode(code, llr, KINDS[kind][0], O.SPA, max_updates=2400, threads=8)
+    g = gpu_decode(gpu, h, llr, kind, gpu.SPA_F32, max_updates=2400)
+    k_ref = int(np.any(ref.bits != cw, axis=1).sum())
+    k_gpu = int(np.any(np_(g.bits) != cw, axis=1).sum())
+    lo, hi = cp_interval(k_ref, 1000)
+    assert lo <= k_gpu / 1000 <= hi, (k_gpu, k_ref, lo, hi)
+    assert np.mean(np_(g.updates_used) == ref.updates_used) > 0.8
+
+
+def test_lmd_edge_cases(gpu):
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    llr = np.full((3, code.N), 5.0, dtype=np.float32)  # already a codeword: no update
+    for kind in KINDS:
+        g = gpu_decode(gpu, h, llr, kind, gpu.SPA_F32, max_updates=1000)
+        assert np.all(np_(g.updates_used) == 0) and not np_(g.bits).any()
+        g = gpu_decode(gpu, h, -llr, kind, gpu.MS_FIX, max_updates=0)
+        assert np.all(np_(g.updates_used) == 0)
+    # all-zero channel: every value tied
+    llr = np.zeros((4, code.N), dtype=np.float32)
+    for kind in KINDS:
+        ref = O.decode(code, llr, KINDS[kind][0], O.MSFIX, max_updates=200, trace=True)
+        g = gpu_decode(gpu, h, llr, kind, gpu.MS_FIX, max_updates=200, trace=True)
+        np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    # single parity check of length 3: every VN has degree 1 (FP32 against the oracle)
+    spc = S.spc_code(3)
+    sh = gpu.Code(spc)
+    llr = np.array([[1.0, -0.5, 2.0], [0.2, 0.3, -0.1]], dtype=np.float32)
+    for kind in KINDS:
+        ref = O.decode(spc, llr, KINDS[kind][0], O.SPA, max_updates=10, check_every=0, trace=True)
+        g = gpu_decode(gpu, sh, llr, kind, gpu.SPA_F32, max_updates=10, check_every=0, trace=True)
+        np.testing.assert_array_equal(np_(g.trace), ref.trace)
+        np.testing.assert_allclose(np_(g.llr_out), ref.llr_out, rtol=1e-5, atol=1e-5)
