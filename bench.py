@@ -19,7 +19,9 @@ Prints one JSON line.  ``--sweep`` instead prints one JSON line per Eb/N0 point 
       {8, 16, 32, 64}, N_G = 16, random (keyed) fill, Eb/N0 in {1.0, 1.25, 1.5} dB: update steps
       against FER;
   c4  the differentiable unrolled decoder: (3,6)-regular n = 576, 4096 frames, 300 recorded CIRBP
-      updates, damped replay forward with checkpoints every 32 and the adjoint.
+      updates, damped replay forward with checkpoints every 32 and the adjoint;
+  lmd the LMD schedules (LMD-CIRBP, LMDRBP, sLMDRBP; Sec. IV) against CIRBP on the default
+      workload's code and batches.
 """
 from __future__ import annotations
 
@@ -40,21 +42,24 @@ METRIC = "decoded frames/s & edge-updates/s at FER 1e-3, CI vs flooding BP, one 
 C1_FRAMES = 65536               # frames per Eb/N0 point of the BG1-shaped workload: one step
 
 
-def lds_bytes_per_update_table(code, s_c=4, s_v=4, s_d=4):
-    """Algorithmic LDS bytes of one single-edge CIRBP update through edge e (Table 1 operation
-    list): edge choice 2 s_c d_v(n*), propagation 2 s_c + 3 s_v + s_d, and for every touched check
+def lds_bytes_per_update_table(code, s_c=4, s_v=4, s_d=4, ci=True, edge_choice=True):
+    """Algorithmic bytes of one single-edge CIRBP update through edge e (Table 1 operation list):
+    edge choice 2 s_c d_v(n*), propagation 2 s_c + 3 s_v + s_d, and for every touched check
     i in M(n*) \\ m*: d_c(i)(s_c + s_v) V2C reads, 2 s_c (d_c(i) - 1) precompute writes/reads and
-    (d_c(i) - 1)(3 s_v + s_d) CI updates."""
+    (d_c(i) - 1)(3 s_v + s_d) CI updates.  ci=False drops the CI terms (RBP-type schedules:
+    propagation 2 s_c + 2 s_v); edge_choice=False drops the edge choice (sLMDRBP sends the edge
+    its local choice found)."""
     dc = np.diff(code.row_ptr).astype(np.int64)
     col_ptr, col_row, col_eid = code.csc()
     dv = np.diff(col_ptr).astype(np.int64)
     rows = code.row_of_edge()
     # per VN: sum over all its checks of the touched-check bytes; subtract m*'s term per edge
-    per_check = dc * (s_c + s_v) + 2 * s_c * (dc - 1) + (dc - 1) * (3 * s_v + s_d)
+    per_check = dc * (s_c + s_v) + 2 * s_c * (dc - 1) + ((dc - 1) * (3 * s_v + s_d) if ci else 0)
     per_vn = np.zeros(code.N, dtype=np.int64)
     np.add.at(per_vn, code.col, per_check[rows])
     n = code.col
-    return 2 * s_c * dv[n] + 2 * s_c + 3 * s_v + s_d + per_vn[n] - per_check[rows]
+    prop = 2 * s_c + 3 * s_v + s_d if ci else 2 * s_c + 2 * s_v
+    return (2 * s_c * dv[n] if edge_choice else 0) + prop + per_vn[n] - per_check[rows]
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dynamic_cirbp_bg1shaped_z52_f32_traffic.json")
@@ -179,6 +184,79 @@ def ev_time(stream, fn):
     e1.record(stream)
     e1.synchronize()
     return r, e0.elapsed_time(e1), time.perf_counter() - t0
+
+
+def bench_lmd(args, ldpc, S, dev):
+    """The LMD schedules (Sec. IV) on the default workload's code and batches: LMD-CIRBP
+    (Algorithm 3), LMDRBP (Algorithm 2) and sLMDRBP, with CIRBP on the same batches for reference;
+    the value is LMD-CIRBP decoded frames/s."""
+    import torch
+    args.frames = args.frames or C1_FRAMES
+    code = S.workload_code("c1")
+    h = ldpc.Code(code)
+    E = code.E
+    cap = 3 * E
+    stream = torch.cuda.Stream(device=dev)
+    batches = make_batches(code, args.warmup + args.steps, args.frames, args.ebn0, args.seed, dev)
+    check_codewords(code, batches[0][0])
+    timed_batches = batches[args.warmup:]
+    runs = {}
+    for name, kind, ci, ec in (("lmd_cirbp", ldpc.LMD_CIRBP, True, True), ("lmdrbp", ldpc.LMDRBP, False, True),
+                               ("slmdrbp", ldpc.SLMDRBP, False, False), ("cirbp", ldpc.CIRBP, True, True)):
+        one, _ = run_decoder(ldpc, h, batches, kind, cap, stream)
+        for k in range(args.warmup):
+            one(k)
+        torch.cuda.synchronize()
+        one, res = run_decoder(ldpc, h, timed_batches, kind, cap, stream)
+        wall, kms = timed(one, stream, args.steps)
+        fe, nf, upd, fall = summarize(res, code)
+        del res, one
+        # algorithmic bytes per update: the per-edge table over a traced decode of the first batch
+        table = torch.from_numpy(lds_bytes_per_update_table(code, ci=ci, edge_choice=ec)).to(dev)
+        llr0 = timed_batches[0][1][:2048]
+        with torch.cuda.stream(stream):
+            rt = ldpc.decode(h, llr0, kind, ldpc.SPA_F32, max_updates=cap, gamma=0.1, trace=True, stream=stream)
+        torch.cuda.synchronize()
+        mask = torch.arange(rt.trace.shape[1], device=dev)[None, :] < rt.updates_used[:, None]
+        bpu = int(table[rt.trace.clamp(min=0).long()][mask].sum()) / max(int(rt.updates_used.sum()), 1)
+        del rt, mask
+        kern_s = sum(kms) / 1e3
+        gbs = bpu * upd / kern_s / 1e9 if kern_s > 0 else 0.0
+        pd = ldpc.describe_plan(h, args.frames, kind, ldpc.SPA_F32, gamma=0.1)
+        runs[name] = {"fer": fe / nf, "frame_errors": fe, "frames": nf, "frames_per_s": round(nf / wall, 3),
+                      "edge_updates_per_s": round(upd / wall, 1), "mean_updates_per_frame": upd / nf,
+                      "fallback_fraction": fall / max(upd, 1), "kernel_ms_per_step": [round(x, 3) for x in kms],
+                      "wall_s": round(wall, 4), "bytes_per_update": round(bpu, 2), "achieved_gbs": round(gbs, 2),
+                      "plan": f"{pd['storage_name']} storage, {pd['topology_name']} topology, "
+                              f"{pd['frames_per_workgroup']} frames per workgroup, {pd['workgroups_per_cu']} "
+                              f"workgroups per CU"}
+        torch.cuda.empty_cache()
+    lc = runs["lmd_cirbp"]
+    out = {
+        "metric": METRIC,
+        "value": lc["frames_per_s"],
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * lc["wall_s"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "BG1-shaped QC LDPC 46x68, Z=52 (n=3536, m=2392, E=16432), seeded shifts; BPSK/AWGN "
+                               f"Eb/N0 {args.ebn0} dB, random codewords; LMD-CIRBP sum-product FP32, cap 3E; "
+                               "LMDRBP, sLMDRBP and CIRBP (gamma=0.1) on the same batches",
+                   "frames_per_step": args.frames, "ebn0_db": args.ebn0},
+        "schedules": runs,
+        "roofline": {"bound": "hbm", "achieved": lc["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(lc["achieved_gbs"] / HBM_PEAK_GBS, 6), "traffic": None,
+                     "kernel": f"k_dynamic<ArithF32, LMD variant> ({lc['plan']})",
+                     "bytes_per_update": lc["bytes_per_update"],
+                     "kernel_ms_avg": round(float(np.mean(lc["kernel_ms_per_step"])), 3)},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_batched(args, ldpc, S, dev):
@@ -374,7 +452,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--sweep", type=str, default="", help="comma list of Eb/N0 points: FER curves")
-    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4", "lmd"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -391,7 +469,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.workload != "c1":
-        {"c2": bench_batched, "c3": bench_multi_edge, "c4": bench_unrolled}[args.workload](args, ldpc, S, dev)
+        {"c2": bench_batched, "c3": bench_multi_edge, "c4": bench_unrolled,
+         "lmd": bench_lmd}[args.workload](args, ldpc, S, dev)
         return
 
     args.frames = args.frames or C1_FRAMES
