@@ -63,6 +63,7 @@ def lds_bytes_per_update_table(code, s_c=4, s_v=4, s_d=4, ci=True, edge_choice=T
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dynamic_cirbp_bg1shaped_z52_f32_traffic.json")
+TRAFFIC_FILE_LMD = os.path.join(ROOT, "profiles", "k_dynamic_lmdcirbp_bg1shaped_z52_f32_traffic.json")
 
 
 def kernel_sources_digest():
@@ -71,11 +72,11 @@ def kernel_sources_digest():
     return sources_digest()
 
 
-def measured_traffic_bytes():
+def measured_traffic_bytes(path=TRAFFIC_FILE):
     """HBM bytes per timed launch (FETCH_SIZE + WRITE_SIZE counters scaled by a plain copy of known
     size), if they were taken on the current kernel sources; else None."""
     try:
-        doc = json.load(open(TRAFFIC_FILE))
+        doc = json.load(open(path))
     except (OSError, ValueError):
         return None
     if doc.get("kernel_sources_sha256") != kernel_sources_digest():
@@ -232,6 +233,9 @@ def bench_lmd(args, ldpc, S, dev):
                               f"workgroups per CU"}
         torch.cuda.empty_cache()
     lc = runs["lmd_cirbp"]
+    # HBM traffic of the timed LMD-CIRBP launch from the counters taken on this workload (default size)
+    tb = measured_traffic_bytes(TRAFFIC_FILE_LMD) if (args.frames == C1_FRAMES and args.ebn0 == 1.25) else None
+    traffic_gbs = round(tb / (float(np.mean(lc["kernel_ms_per_step"])) / 1e3) / 1e9, 2) if tb else None
     out = {
         "metric": METRIC,
         "value": lc["frames_per_s"],
@@ -251,7 +255,7 @@ def bench_lmd(args, ldpc, S, dev):
                    "frames_per_step": args.frames, "ebn0_db": args.ebn0},
         "schedules": runs,
         "roofline": {"bound": "hbm", "achieved": lc["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(lc["achieved_gbs"] / HBM_PEAK_GBS, 6), "traffic": None,
+                     "frac": round(lc["achieved_gbs"] / HBM_PEAK_GBS, 6), "traffic": traffic_gbs,
                      "kernel": f"k_dynamic<ArithF32, LMD variant> ({lc['plan']})",
                      "bytes_per_update": lc["bytes_per_update"],
                      "kernel_ms_avg": round(float(np.mean(lc["kernel_ms_per_step"])), 3)},
