@@ -1,8 +1,8 @@
 /*
  * ldpc_oracle.c -- plain, slow CPU oracle for LDPC belief-propagation decoding with
  * flooding, layered, residual (RBP), conditional-innovation RBP (CIRBP, Algorithm 1),
- * multi-edge CIRBP (Algorithms 4 and 5) and latest-message-driven (LMDRBP and sLMDRBP,
- * Algorithm 2; LMD-CIRBP, Algorithm 3) schedules.
+ * multi-edge CIRBP (Algorithms 4 and 5), latest-message-driven (LMDRBP and sLMDRBP,
+ * Algorithm 2; LMD-CIRBP, Algorithm 3) and multi-edge LMD-CIRBP (Algorithm 6) schedules.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline leg of the
  * benchmark may load this file.  It shares no code, header, table or constant generator with the
@@ -53,6 +53,12 @@
  *     edges (m*, j), VNs j of N(m*) \ n* (Sec. V).  Ties go to the lowest edge id / VN index.  An
  *     empty candidate set (only with checks of degree 1) sends the next update to the global
  *     choice again.
+ *   - ME-LMD-CIRBP (Algorithm 6): the first step's set P comes from Algorithm 4.  After a step
+ *     (the ME-CIRBP step above), every p in P proposes p', the VN of largest CI among U(m*_p, p)
+ *     on the state after the step (m*_p the check whose message p received; N(m*_p) \ p when p has
+ *     degree 1).  The distinct proposals form P'; if |P'| < N_P, Algorithm 4 adds N_P - |P'| VNs
+ *     chosen among the VNs outside P' (its groups counted without P'), and the union is the next
+ *     step's P.
  */
 #include <math.h>
 #include <pthread.h>
@@ -69,7 +75,8 @@ enum {
   OC_REPLAY = 5,
   OC_LMDRBP = 6,
   OC_SLMDRBP = 7,
-  OC_LMDCIRBP = 8
+  OC_LMDCIRBP = 8,
+  OC_MELMDCIRBP = 9
 };
 enum { ARITH_SPA = 0, ARITH_MSFIX = 1 };
 enum {
@@ -421,13 +428,15 @@ uint64_t oc_fill_key(uint64_t seed, uint64_t frame, uint64_t step, uint64_t n) {
   return oc_splitmix64(oc_splitmix64(oc_splitmix64(seed ^ frame) ^ step) ^ n);
 }
 
-/* Algorithm 4.  keys == NULL: fill with the lowest indices; otherwise with the smallest keys.
-   Fills sel[] in ascending VN order and returns |P|. */
-int32_t oc_alg4_select_keyed(int32_t N, const int32_t *bins, int32_t ng, int32_t np,
-                             const uint64_t *keys, int32_t *sel) {
+/* Algorithm 4 over the VNs n with excl[n] == 0 (excl == NULL: all VNs).  keys == NULL: fill with
+   the lowest indices; otherwise with the smallest keys.  Fills sel[] in ascending VN order and
+   returns |P|. */
+int32_t oc_alg4_select_excl(int32_t N, const int32_t *bins, int32_t ng, int32_t np, const uint64_t *keys,
+                            const uint8_t *excl, int32_t *sel) {
   if (N <= 0 || ng <= 0) return 0;
   int32_t *count = (int32_t *)calloc((size_t)ng, sizeof(int32_t));
-  for (int32_t n = 0; n < N; ++n) count[bins[n]] += 1;
+  for (int32_t n = 0; n < N; ++n)
+    if (!excl || !excl[n]) count[bins[n]] += 1;
   int32_t kstar = 0, q = 0;
   for (int32_t k = 1; k <= ng; ++k) {
     if (q + count[ng - k] > np) break;
@@ -438,12 +447,12 @@ int32_t oc_alg4_select_keyed(int32_t N, const int32_t *bins, int32_t ng, int32_t
   int32_t need = np - q;
   uint8_t *take = (uint8_t *)calloc((size_t)N, 1);
   for (int32_t n = 0; n < N; ++n)
-    if (bins[n] >= ng - kstar) take[n] = 1;
+    if (bins[n] >= ng - kstar && (!excl || !excl[n])) take[n] = 1;
   /* repeatedly take the fill-group member with the smallest (key, index) not yet taken */
   for (int32_t r = 0; r < need && fill_bin >= 0; ++r) {
     int32_t best = -1;
     for (int32_t n = 0; n < N; ++n) {
-      if (bins[n] != fill_bin || take[n]) continue;
+      if (bins[n] != fill_bin || take[n] || (excl && excl[n])) continue;
       if (best < 0) { best = n; continue; }
       if (keys && keys[n] < keys[best]) best = n;
     }
@@ -458,12 +467,20 @@ int32_t oc_alg4_select_keyed(int32_t N, const int32_t *bins, int32_t ng, int32_t
   return out;
 }
 
+int32_t oc_alg4_select_keyed(int32_t N, const int32_t *bins, int32_t ng, int32_t np,
+                             const uint64_t *keys, int32_t *sel) {
+  return oc_alg4_select_excl(N, bins, ng, np, keys, NULL, sel);
+}
+
 /* fills sel[] (ascending VN order) and returns |P| (lowest-index fill) */
 int32_t oc_alg4_select(int32_t N, const int32_t *bins, int32_t ng, int32_t np, int32_t *sel) {
   return oc_alg4_select_keyed(N, bins, ng, np, NULL, sel);
 }
 
-static void me_step(st_t *S, int64_t *cnt, int32_t *trace_out, int64_t *t, int32_t frame) {
+/* One multi-edge step (Algorithm 5; Algorithm 6 when succ != NULL).  succ[0..*nsucc) holds the
+   previous step's proposals P' on entry (empty at the first step) and this step's on return. */
+static void me_step(st_t *S, int64_t *cnt, int32_t *trace_out, int64_t *t, int32_t frame, int32_t *succ,
+                    int32_t *nsucc) {
   const oc_code *H = S->H;
   int32_t N = H->N, ng = S->s->n_g, np = S->s->n_p;
   int32_t *bins = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
@@ -478,7 +495,21 @@ static void me_step(st_t *S, int64_t *cnt, int32_t *trace_out, int64_t *t, int32
     for (int32_t n = 0; n < N; ++n)
       keys[n] = oc_fill_key(S->s->seed, (uint64_t)frame, (uint64_t)cnt[CNT_STEPS], (uint64_t)n);
   }
-  int32_t P = oc_alg4_select_keyed(N, bins, ng, np, keys, sel);
+  int32_t P;
+  if (!succ) {
+    P = oc_alg4_select_keyed(N, bins, ng, np, keys, sel);
+  } else {
+    /* P' first, then Algorithm 4 for the rest among the VNs outside P'; ascending VN order */
+    uint8_t *excl = (uint8_t *)calloc((size_t)N, 1);
+    for (int32_t k = 0; k < *nsucc; ++k) excl[succ[k]] = 1;
+    int32_t need = np - *nsucc;
+    int32_t extra = need > 0 ? oc_alg4_select_excl(N, bins, ng, need, keys, excl, sel) : 0;
+    for (int32_t k = 0; k < extra; ++k) excl[sel[k]] = 1;
+    P = 0;
+    for (int32_t n = 0; n < N; ++n)
+      if (excl[n]) sel[P++] = n;
+    free(excl);
+  }
   free(keys);
   /* edge choice for every selected VN on the snapshot */
   for (int32_t p = 0; p < P; ++p) edge[p] = argmax_into(S, sel[p], cnt);
@@ -503,6 +534,17 @@ static void me_step(st_t *S, int64_t *cnt, int32_t *trace_out, int64_t *t, int32
     S->D[n] = ci(S, S->L[n], S->Lt[n]);
   }
   recompute_syndrome(S);
+  if (succ) { /* Algorithm 6: each p proposes the VN of largest CI among U(m*_p, p); distinct ones */
+    int32_t ns = 0;
+    for (int32_t p = 0; p < P; ++p) {
+      int32_t q = lmd_vn(S, edge[p], cnt);
+      if (q < 0) continue;
+      int dup = 0;
+      for (int32_t k = 0; k < ns; ++k) dup |= succ[k] == q;
+      if (!dup) succ[ns++] = q;
+    }
+    *nsucc = ns;
+  }
   cnt[CNT_PROP] += P;
   cnt[CNT_STEPS] += 1;
   *t += P;
@@ -585,6 +627,7 @@ static int decode_frame(job_t *J, st_t *S, int32_t f) {
   int64_t t = 0;
   int kind = s->kind;
   int rc = OC_OK;
+  int32_t *succ = NULL; /* ME-LMD-CIRBP: the proposals P' of the last step */
   if (kind == OC_FLOODING || kind == OC_LAYERED) {
     for (int32_t e = 0; e < H->E; ++e) S->c2v[e] = 0.0;
     for (int32_t n = 0; n < H->N; ++n) S->L[n] = S->ch[n];
@@ -605,17 +648,20 @@ static int decode_frame(job_t *J, st_t *S, int32_t f) {
     int64_t ce = kind == OC_REPLAY ? 0 : s->check_every;
     int lmd = kind == OC_LMDRBP || kind == OC_SLMDRBP || kind == OC_LMDCIRBP;
     int32_t next_e = -1; /* LMD schedules: the edge chosen by the last update */
+    int32_t nsucc = 0;
+    if (kind == OC_MELMDCIRBP) succ = (int32_t *)malloc(sizeof(int32_t) * (size_t)s->n_p);
     if (!stop_now(S, 0, ce)) {
       while (t < limit) {
         int64_t tprev = t;
-        if (kind == OC_MECIRBP) {
+        if (kind == OC_MECIRBP || kind == OC_MELMDCIRBP) {
           /* whole steps only: a step may propagate up to n_p messages */
           if (t + s->n_p > limit) break;
           int32_t *buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)H->N);
-          me_step(S, cnt, buf, &t, f);
+          me_step(S, cnt, buf, &t, f, kind == OC_MELMDCIRBP ? succ : NULL, &nsucc);
           for (int64_t k = tprev; k < t; ++k)
             if (tr) tr[k] = buf[k - tprev];
           free(buf);
+          if (t == tprev) break; /* an empty set (not reachable with N >= 1) would never end */
         } else {
           int32_t estar;
           if (kind == OC_RBP) estar = argmax_residual(S, cnt);
@@ -645,6 +691,7 @@ static int decode_frame(job_t *J, st_t *S, int32_t f) {
     }
   }
 done:
+  free(succ);
   for (int32_t n = 0; n < H->N; ++n) {
     J->bits[(size_t)f * H->N + n] = (uint8_t)bsgn(S->L[n]);
     if (J->llr_out) J->llr_out[(size_t)f * H->N + n] = S->arith == ARITH_SPA ? S->L[n] : S->L[n] / scale;
@@ -708,10 +755,10 @@ int oc_decode(const oc_code *H, const oc_sched *s, int32_t B, const double *llr,
               double *dump_c2v, double *dump_pre, double *dump_L, double *dump_Lt, double *dump_D,
               int32_t nthreads) {
   if (!H || !s || B < 0 || !llr || !bits || !updates_used || max_updates < 0) return OC_EINVAL;
-  if (s->kind < 0 || s->kind > OC_LMDCIRBP || (s->arith != ARITH_SPA && s->arith != ARITH_MSFIX))
+  if (s->kind < 0 || s->kind > OC_MELMDCIRBP || (s->arith != ARITH_SPA && s->arith != ARITH_MSFIX))
     return OC_EINVAL;
   if (s->kind == OC_REPLAY && (!replay || replay_len < 0)) return OC_EINVAL;
-  if (s->kind == OC_MECIRBP && (s->n_p < 1 || s->n_g < 1)) return OC_EINVAL;
+  if ((s->kind == OC_MECIRBP || s->kind == OC_MELMDCIRBP) && (s->n_p < 1 || s->n_g < 1)) return OC_EINVAL;
   if (nthreads < 1) nthreads = 1;
   if (nthreads > B && B > 0) nthreads = B;
   job_t *jobs = (job_t *)calloc((size_t)nthreads, sizeof(job_t));

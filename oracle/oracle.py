@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "ldpc_oracle.c"), os.path.join(_HERE, "unrolled_oracle.c")]
 _LIB = os.path.join(_HERE, "libldpc_oracle.so")
 
-FLOODING, LAYERED, RBP, CIRBP, MECIRBP, REPLAY, LMDRBP, SLMDRBP, LMDCIRBP = range(9)
+FLOODING, LAYERED, RBP, CIRBP, MECIRBP, REPLAY, LMDRBP, SLMDRBP, LMDCIRBP, MELMDCIRBP = range(10)
 FILL_LOWEST, FILL_HASH = 0, 1
 SPA, MSFIX = 0, 1
 COUNTERS = ("prop", "v2c", "pre", "ci", "ci_self", "fallback", "cmp", "steps")
@@ -81,6 +81,9 @@ def lib():
         _lib.ou_backward.argtypes = [P, C.c_int32, P, P, P, C.c_int32, P, P, P, C.c_int32]
         _lib.ou_boxplus_grad.restype = C.c_double
         _lib.ou_boxplus_grad.argtypes = [C.c_double, C.c_double]
+        _lib.oc_alg4_select_excl.restype = C.c_int32
+        _lib.oc_alg4_select_excl.argtypes = [C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                             C.c_void_p, C.c_void_p]
         _lib.oc_alg4_select.restype = C.c_int32
         _lib.oc_alg4_select.argtypes = [C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
     return _lib
@@ -193,6 +196,17 @@ def alg4_select_keyed(bins, n_g: int, n_p: int, keys) -> np.ndarray:
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
     out = np.zeros(len(bins), dtype=np.int32)
     k = lib().oc_alg4_select_keyed(len(bins), bins.ctypes.data, n_g, n_p, keys.ctypes.data, out.ctypes.data)
+    return out[:k]
+
+
+def alg4_select_excl(bins, n_g: int, n_p: int, excl, keys=None) -> np.ndarray:
+    """Algorithm 4 among the VNs with excl[n] == 0 (Algorithm 6's refill)."""
+    bins = np.ascontiguousarray(bins, dtype=np.int32)
+    excl = np.ascontiguousarray(excl, dtype=np.uint8)
+    kp = None if keys is None else np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.zeros(len(bins), dtype=np.int32)
+    k = lib().oc_alg4_select_excl(len(bins), bins.ctypes.data, n_g, n_p, None if kp is None else kp.ctypes.data,
+                                  excl.ctypes.data, out.ctypes.data)
     return out[:k]
 
 

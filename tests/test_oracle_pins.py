@@ -550,3 +550,97 @@ def test_lmd_high_snr_decodes_without_errors():
         for arith in (O.SPA, O.MSFIX):
             r = O.decode(code, llr, kind, arith, max_updates=2400, threads=4)
             assert np.array_equal(r.bits, cw), (kind, arith)
+
+
+# ------------------------------------------------------------------------------------------
+# ME-LMD-CIRBP (Algorithm 6)
+# ------------------------------------------------------------------------------------------
+def test_alg4_with_excluded_vns_hand_worked():
+    """Algorithm 6 refills P' with Algorithm 4 run on the VNs outside P' (hand-worked cases)."""
+    g = json.load(open(os.path.join(GOLDEN, "alg4_select.json")))
+    D = np.array(g["D"])
+    bins = np.minimum(np.floor(D * g["n_g"]).astype(np.int32), g["n_g"] - 1)
+    for case in g["excl_cases"]:
+        excl = np.zeros(len(D), dtype=np.uint8)
+        excl[case["excl"]] = 1
+        assert list(O.alg4_select_excl(bins, g["n_g"], case["n_p"], excl)) == case["expect"], case["why"]
+
+
+def test_me_lmd_single_vn_equals_lmd_cirbp_fixed_point():
+    """With N_P = 1 and one group per CI level, Algorithm 4 picks the VN of largest CI (lowest index
+    on ties) and every later set is the single proposal p' of Algorithm 3: Algorithm 6 is LMD-CIRBP,
+    bit-exact in fixed point (an ME step's recomputation of m*'s row changes nothing there)."""
+    code = S.workload_code("c0")
+    cw, llr = S.frames(code, 40, 2.0, 21)
+    a = O.decode(code, llr, O.MELMDCIRBP, O.MSFIX, max_updates=900, n_p=1, n_g=65535, trace=True, dump=True)
+    b = O.decode(code, llr, O.LMDCIRBP, O.MSFIX, max_updates=900, trace=True, dump=True)
+    np.testing.assert_array_equal(a.trace, b.trace)
+    np.testing.assert_array_equal(a.updates_used, b.updates_used)
+    np.testing.assert_array_equal(a.llr_out, b.llr_out)
+    np.testing.assert_array_equal(a.D, b.D)
+
+
+def test_me_lmd_disjoint_copies_follow_lmd_cirbp_each():
+    """Two disconnected copies of a code, N_P = 2: when the first set takes one VN per copy, the
+    proposals stay one per copy, so each copy runs LMD-CIRBP on its own (fixed point, exact CI
+    groups).  Ties for the first set are avoided by keeping only trials that split."""
+    base = S.workload_code("c0")
+    rows = []
+    for off in (0, base.N):
+        for m in range(base.M):
+            rows.append(list(base.col[base.row_ptr[m]:base.row_ptr[m + 1]] + off))
+    code = S.code_from_rows(2 * base.M, 2 * base.N, rows)
+    rng = np.random.default_rng(22)
+    T = 120
+    checked = 0
+    for trial in range(30):
+        llr = rng.normal(1.0, 2.0, size=code.N)
+        me = O.decode(code, llr, O.MELMDCIRBP, O.MSFIX, max_updates=T, n_p=2, n_g=65535, check_every=0,
+                      trace=True)
+        e0 = me.trace[0, :2]
+        if not ((code.col[e0[0]] < base.N) and (code.col[e0[1]] >= base.N)):
+            continue
+        a = O.decode(base, llr[:base.N], O.LMDCIRBP, O.MSFIX, max_updates=T // 2, check_every=0, trace=True)
+        b = O.decode(base, llr[base.N:], O.LMDCIRBP, O.MSFIX, max_updates=T // 2, check_every=0, trace=True)
+        np.testing.assert_array_equal(me.trace[0, 0::2], a.trace[0])
+        np.testing.assert_array_equal(me.trace[0, 1::2] - base.E, b.trace[0])
+        checked += 1
+    assert checked >= 5
+
+
+@pytest.mark.parametrize("fill", [O.FILL_LOWEST, O.FILL_HASH])
+def test_me_lmd_every_step_updates_n_p_distinct_vns(fill):
+    """Repeated proposals are merged and Algorithm 4 refills the set, so every step updates exactly
+    N_P distinct VNs."""
+    code = S.workload_code("c0")
+    cw, llr = S.frames(code, 20, 1.5, 23)
+    n_p = 8
+    r = O.decode(code, llr, O.MELMDCIRBP, O.SPA, max_updates=800, n_p=n_p, n_g=16, fill=fill, seed=5,
+                 check_every=0, trace=True)
+    assert np.all(r.updates_used == 800) and np.all(r.steps_used == 100)
+    vn = code.col[r.trace]
+    for f in range(vn.shape[0]):
+        steps = vn[f].reshape(-1, n_p)
+        assert all(len(set(s)) == n_p for s in steps)
+        assert np.all(np.diff(steps, axis=1) > 0)  # ascending VN order within a step
+
+
+@pytest.mark.parametrize("arith", [O.SPA, O.MSFIX])
+def test_me_lmd_incremental_state_equals_definitions(arith):
+    for code in (S.workload_code("c0"), S.qc_bg1_shaped(4, seed=3)):
+        cw, llr = S.frames(code, 4, 1.5, 24, zero_codeword=True)
+        O.decode(code, llr, O.MELMDCIRBP, arith, max_updates=400, selfcheck=True, n_p=4, n_g=8, fill=O.FILL_HASH)
+
+
+def test_me_lmd_sign_symmetry_and_high_snr():
+    code = S.workload_code("c0")
+    cw, llr = S.frames(code, 20, 2.0, 25)
+    flip = (1.0 - 2.0 * cw)
+    a = O.decode(code, llr, O.MELMDCIRBP, O.SPA, max_updates=1200, n_p=4, trace=True)
+    b = O.decode(code, llr * flip, O.MELMDCIRBP, O.SPA, max_updates=1200, n_p=4, trace=True)
+    np.testing.assert_array_equal(a.trace, b.trace)
+    np.testing.assert_array_equal(a.llr_out, b.llr_out * flip)
+    cw, llr = S.frames(code, 200, 8.0, 26)
+    for arith in (O.SPA, O.MSFIX):
+        r = O.decode(code, llr, O.MELMDCIRBP, arith, max_updates=2400, n_p=4, fill=O.FILL_HASH, threads=4)
+        assert np.array_equal(r.bits, cw)
