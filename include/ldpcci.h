@@ -8,7 +8,8 @@
  *   - conditional-innovation RBP (CIRBP): Algorithm 1 (Sec. III-B) with the CI metric eq. (9);
  *   - multi-edge CIRBP (ME-CIRBP): Algorithm 5 with the VN selection of Algorithm 4 (Sec. VI);
  *   - latest-message-driven schedules (Sec. IV): LMDRBP and its simplified form sLMDRBP
- *     (Algorithm 2), LMD-CIRBP (Algorithm 3), with the degree-1 rule of Sec. V;
+ *     (Algorithm 2), LMD-CIRBP (Algorithm 3), with the degree-1 rule of Sec. V, and multi-edge
+ *     LMD-CIRBP (ME-LMD-CIRBP, Algorithm 6);
  *   - flooding and layered BP baselines (Sec. I);
  *   - replay of a recorded edge order (the schedule held fixed).
  * Messages follow eqs. (1)-(3) (Sec. II-A): V2C, C2V by the tanh rule (sum-product), total LLR
@@ -66,6 +67,13 @@ extern "C" {
 #define LDPC_LMDRBP 6
 #define LDPC_SLMDRBP 7
 #define LDPC_LMD_CIRBP 8
+/* multi-edge LMD-CIRBP (Algorithm 6, Sec. VI): the first step's set comes from Algorithm 4 (n_p,
+   n_g, fill as for LDPC_ME_CIRBP).  After a step, every updated VN p proposes the VN of largest CI
+   among U(m*_p, p), where m*_p is the check whose message p received (N(m*_p) \ p when p has degree
+   1); the distinct proposals P' start the next set, and Algorithm 4 run on the VNs outside P' adds
+   the remaining n_p - |P'| (Algorithm 6 names |P| there; this is the count that keeps the set at
+   n_p).  Sets are sent in ascending VN order, as for LDPC_ME_CIRBP. */
+#define LDPC_ME_LMD_CIRBP 9
 
 /* arithmetic */
 #define LDPC_SPA_F32 0  /* sum-product, FP32 messages                                          */
@@ -78,16 +86,16 @@ extern "C" {
 typedef struct ldpc_code ldpc_code; /* opaque, library-owned */
 
 typedef struct {
-  int32_t kind;        /* LDPC_FLOODING .. LDPC_LMD_CIRBP                                       */
+  int32_t kind;        /* LDPC_FLOODING .. LDPC_ME_LMD_CIRBP                                    */
   int32_t arith;       /* LDPC_SPA_F32 or LDPC_MS_FIX                                            */
   int32_t q_bits;      /* LDPC_MS_FIX: message width, 2..8 (saturation at +-(2^(q-1)-1))         */
   int32_t frac_bits;   /* LDPC_MS_FIX: channel quantisation llr * 2^frac_bits, 0..6              */
   float gamma;         /* CIRBP threshold: fall back to the global residual search if D_{n*} < gamma
                           (Algorithm 1 threshold test); MS_FIX compares D_q with round(gamma * 65534)    */
-  int32_t n_p;         /* ME-CIRBP: VNs updated per step (N_P, Sec. VI), 1..64                   */
-  int32_t n_g;         /* ME-CIRBP: CI groups (N_G, Algorithm 4), 1..65535                       */
-  int32_t fill;        /* ME-CIRBP: LDPC_FILL_LOWEST or LDPC_FILL_HASH                           */
-  uint64_t seed;       /* ME-CIRBP: key of the hashed fill                                       */
+  int32_t n_p;         /* ME schedules: VNs updated per step (N_P, Sec. VI), 1..64               */
+  int32_t n_g;         /* ME schedules: CI groups (N_G, Algorithm 4), 1..65535                   */
+  int32_t fill;        /* ME schedules: LDPC_FILL_LOWEST or LDPC_FILL_HASH                       */
+  uint64_t seed;       /* ME schedules: key of the hashed fill                                   */
   int64_t check_every; /* syndrome test at t = 0 and whenever t passes a multiple of check_every
                           (1 = after every update; E = end of each iteration as in Sec. II-A;
                           0 = never stop early).  Flooding/layered test after every iteration. */

@@ -199,9 +199,9 @@ MeLayout me_layout(const ldpc_code* c, bool fixed, bool msg_global, int topo, in
   L.off_vnmark = o; o = align16(o + nvw * 4);
   L.off_rows = o; o = align16(o + L.rows_cap * 4);
   L.off_rows2 = o; o = align16(o + L.rows_cap * 4);  // the same checks sorted by block size
-  L.off_sel = o; o = align16(o + 3 * 64 * 4);
+  L.off_sel = o; o = align16(o + 5 * 64 * 4);  // set, sorted set, class counters, P', m* per VN
   L.off_cand = o; o = align16(o + L.cand_cap * 12);
-  L.off_misc = o; o = align16(o + 32 * 4);
+  L.off_misc = o; o = align16(o + 48 * 4);  // 32 counters, one word per wavefront
   L.off_lut = o; if (fixed) o = align16(o + 257 * 4);
   L.off_topo = o; o = align16(o + (int)std::max(0LL, topo_bytes(c, topo)));
   L.total = o;
@@ -627,14 +627,15 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (plan_only && !out) out = &no_out;
   if (!c || !s || !out || B < 0 || max_updates < 0) return LDPC_EINVAL;
   if (!plan_only && B > 0 && (!llr_in || !out->bits || !out->updates_used)) return LDPC_EINVAL;
-  if (s->kind < LDPC_FLOODING || s->kind > LDPC_LMD_CIRBP) return LDPC_EINVAL;
+  if (s->kind < LDPC_FLOODING || s->kind > LDPC_ME_LMD_CIRBP) return LDPC_EINVAL;
   if (s->arith != LDPC_SPA_F32 && s->arith != LDPC_MS_FIX) return LDPC_EINVAL;
   const bool fixed = s->arith == LDPC_MS_FIX;
   if (fixed && (s->q_bits < 2 || s->q_bits > 8 || s->frac_bits < 0 || s->frac_bits > 6)) return LDPC_EINVAL;
   if (s->check_every < 0) return LDPC_EINVAL;
   if (!(s->gamma >= 0.0f) || !std::isfinite(s->gamma)) return LDPC_EINVAL;
   if (s->kind == LDPC_REPLAY && ((!plan_only && !replay) || replay_len < 0)) return LDPC_EINVAL;
-  if (s->kind == LDPC_ME_CIRBP && (s->n_p < 1 || s->n_p > 64 || s->n_g < 1 || s->n_g > 65535 ||
+  const bool me = s->kind == LDPC_ME_CIRBP || s->kind == LDPC_ME_LMD_CIRBP;
+  if (me && (s->n_p < 1 || s->n_p > 64 || s->n_g < 1 || s->n_g > 65535 ||
                                    (s->fill != LDPC_FILL_LOWEST && s->fill != LDPC_FILL_HASH)))
     return LDPC_EINVAL;
   if (int rc = check_tuning(tune)) return rc;
@@ -708,8 +709,9 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (T.storage == LDPC_STORE_GLOBAL_STATE) stores = {STORE_FRAME_ALL};
   const int lut_off = 257 * (fixed ? s->frac_bits : 0);
 
-  if (s->kind == LDPC_ME_CIRBP) {
+  if (me) {
     MeParams& Q = pl.me;
+    Q.lmd = s->kind == LDPC_ME_LMD_CIRBP ? 1 : 0;
     Q.B = B;
     Q.max_updates = max_updates;
     Q.check_every = s->check_every;
@@ -1018,7 +1020,7 @@ int ldpc_describe_plan(const ldpc_code* c, const ldpc_schedule* s, int32_t B, ld
 }
 
 int ldpc_set_tuning(const ldpc_code* c, int32_t kind, int32_t arith, const ldpc_tuning* t) {
-  if (!c || kind < LDPC_FLOODING || kind > LDPC_LMD_CIRBP || (arith != LDPC_SPA_F32 && arith != LDPC_MS_FIX))
+  if (!c || kind < LDPC_FLOODING || kind > LDPC_ME_LMD_CIRBP || (arith != LDPC_SPA_F32 && arith != LDPC_MS_FIX))
     return LDPC_EINVAL;
   if (int rc = check_tuning(t)) return rc;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1047,14 +1049,15 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
   } else {
     std::vector<int> tps = {LDPC_TOPO_GLOBAL, LDPC_TOPO_LDS};
     if (!c->h_qc.empty()) tps.push_back(LDPC_TOPO_QC);
-    const std::vector<int> blocks = s->kind == LDPC_ME_CIRBP ? std::vector<int>{64, 256, 1024} : std::vector<int>{0};
+    const bool me = s->kind == LDPC_ME_CIRBP || s->kind == LDPC_ME_LMD_CIRBP;
+    const std::vector<int> blocks = me ? std::vector<int>{64, 256, 1024} : std::vector<int>{0};
     for (int b : blocks)
       for (int store : {LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL, LDPC_STORE_GLOBAL_LT,
                         LDPC_STORE_GLOBAL_FRAME, LDPC_STORE_GLOBAL_REC, LDPC_STORE_GLOBAL_STATE})
         for (int tp : tps)
           for (int fpc : {0, 1, 2, 4, 8, 16})
-            for (int wb : s->kind == LDPC_ME_CIRBP ? std::vector<int>{0} : std::vector<int>{0, 256, 512})
-              cands.push_back(ldpc_tuning{s->kind == LDPC_ME_CIRBP ? b : wb, fpc, store, tp});
+            for (int wb : me ? std::vector<int>{0} : std::vector<int>{0, 256, 512})
+              cands.push_back(ldpc_tuning{me ? b : wb, fpc, store, tp});
   }
   // outputs for the trial decodes (discarded)
   uint8_t* bits = nullptr;
@@ -1163,7 +1166,7 @@ int ldpc_tuning_load(const char* path) {
                     "\"storage\": %d, \"topology\": %d}",
                     &sig, &k.kind, &k.arith, &t.block, &t.frames_per_cu, &t.storage, &t.topology) == 7) {
       k.sig = sig;
-      if (check_tuning(&t) != LDPC_OK || k.kind < LDPC_FLOODING || k.kind > LDPC_LMD_CIRBP) continue;
+      if (check_tuning(&t) != LDPC_OK || k.kind < LDPC_FLOODING || k.kind > LDPC_ME_LMD_CIRBP) continue;
       rows.push_back({k, t});
     }
   }

@@ -16,7 +16,8 @@ enum Kind {
   KIND_REPLAY = 5,
   KIND_LMDRBP = 6,
   KIND_SLMDRBP = 7,
-  KIND_LMD_CIRBP = 8
+  KIND_LMD_CIRBP = 8,
+  KIND_ME_LMD_CIRBP = 9
 };
 __host__ __device__ constexpr bool is_lmd(int k) { return k == KIND_LMDRBP || k == KIND_SLMDRBP || k == KIND_LMD_CIRBP; }
 enum Topo { TOPO_GLOBAL = 0, TOPO_LDS = 1, TOPO_QC = 2 };
@@ -188,6 +189,7 @@ struct MeParams {
   float scale;
   const int* lut_global;
   int n_p, n_g, fill;
+  int lmd;                  // ME-LMD-CIRBP (Algorithm 6): the next set starts from the proposals
   unsigned long long seed;
   void* msg_global;         // grid x 2E messages (c2v then pre) when they are not in LDS
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;

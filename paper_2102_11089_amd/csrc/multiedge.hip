@@ -1,5 +1,6 @@
 // Multi-edge CIRBP on gfx950: Algorithm 4 (VN selection by CI groups) and Algorithm 5 (the
-// selected VNs updated together), Sec. VI.
+// selected VNs updated together), Sec. VI; and multi-edge LMD-CIRBP (Algorithm 6), whose next set
+// starts from the VNs the updated ones propose.
 //
 // One workgroup decodes one frame at a time.  Per step, on a snapshot of the state:
 //   1. the CI-group histogram hist[N_G] (kept up to date as D changes) gives the groups taken
@@ -10,7 +11,11 @@
 //   3. for each p in P (ascending): the incoming edge of largest residual (Algorithm 1);
 //   4. all propagations c2v <- pre, L_p += delta, syndrome toggles;
 //   5. every check of every p recomputed from the new state (one lane per check, each check once),
-//      Lt updated by the precompute deltas; then D (and its group) of every VN of those checks.
+//      Lt updated by the precompute deltas; then D (and its group) of every VN of those checks;
+//   6. ME-LMD-CIRBP only: each p proposes the VN of largest CI among U(m*_p, p) (N(m*_p) \ p when p
+//      has degree 1); the distinct proposals P' start the next set, whose remaining N_P - |P'| VNs
+//      come from steps 1-2 run on the VNs outside P' (their histogram counts taken out, their
+//      membership marked in vnmark for the selection).
 // Messages c2v/pre stay in LDS when they fit, otherwise in a global scratch slot per workgroup.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -30,7 +35,9 @@ namespace ldpc {
 
 
 enum { MS_UNSAT = 0, MS_NROWS, MS_NSEL, MS_BSTAR, MS_FILL, MS_NEED, MS_CNT, MS_NCAND, MS_WAVESUM, MS_RBIN, MS_RBELOW,
-       MS_L2 };  // MS_L2 + c - 1: touched checks with blocks of 2^c lanes, c = 1..5
+       MS_L2,                 // MS_L2 + c - 1: touched checks with blocks of 2^c lanes, c = 1..5
+       MS_NSUCC = MS_L2 + 5,  // ME-LMD-CIRBP: |P'|
+       kMiscWords = 32 };     // misc[0, kMiscWords): the counters above; then one word per wavefront
 
 // exclusive prefix sum over the workgroup (lane order); wsum: one int per wave in LDS
 __device__ __forceinline__ int block_excl_scan(int v, int* wsum) {
@@ -69,10 +76,12 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
   int* rows2 = reinterpret_cast<int*>(lds + P.off_rows2);
   int* sel = reinterpret_cast<int*>(lds + P.off_sel);  // [64] unsorted, [64] sorted
   int* sel_s = sel + 64;
+  int* succ = sel + 192;  // ME-LMD-CIRBP: the proposals P' [64]
+  int* selm = sel + 256;  // the check whose message sel_s[i] received [64]
   uint64_t* ckeys = reinterpret_cast<uint64_t*>(lds + P.off_cand);
   int* cidx = reinterpret_cast<int*>(ckeys + P.cand_cap);
   int* misc = reinterpret_cast<int*>(lds + P.off_misc);
-  int* wsum = misc + 16;
+  int* wsum = misc + kMiscWords;
   int* lut = reinterpret_cast<int*>(lds + P.off_lut);
 
   A ar;
@@ -84,6 +93,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
   }
   const auto G = TopoSel<TOPO>::make(H, lds + P.off_topo, tid, BS);
   const int NG = P.n_g, NP = P.n_p;
+  const bool lmd = P.lmd != 0;
   const int nsw = (M + 31) >> 5, nvw = (N + 31) >> 5;
   __syncthreads();
 
@@ -95,7 +105,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
     for (int b = tid; b < NG; b += BS) hist[b] = 0;
     for (int w = tid; w < nsw; w += BS) synw[w] = 0u, rowmark[w] = 0u;
     for (int w = tid; w < nvw; w += BS) vnmark[w] = 0u;
-    if (tid < 16) misc[tid] = 0;
+    if (tid < kMiscWords) misc[tid] = 0;
     __syncthreads();
     for (int m = tid; m < M; m += BS) {
       const int rs = G.row_start(m), dc = G.row_deg(m);
@@ -140,19 +150,34 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
     while (!done && t + NP <= P.max_updates) {
       ME_PROF_MARK(7)
       const long long tprev = t;
+      // ---- ME-LMD-CIRBP: P' goes into the set first and is taken out of Algorithm 4's view ----
+      const int nsucc = lmd ? misc[MS_NSUCC] : 0;
+      if (nsucc > 0) {
+        if (tid < nsucc) {
+          const int v = succ[tid];
+          sel[tid] = v;
+          atomicOr(&vnmark[v >> 5], 1u << (v & 31));
+          atomicSub(&hist[ar.bin(D[v], NG)], 1);
+        }
+        __syncthreads();
+      }
+      const int np_eff = NP - nsucc;
+      // excluded from this step's Algorithm 4: the members of P'
+      auto excluded = [&](int n) -> bool { return nsucc > 0 && ((vnmark[n >> 5] >> (n & 31)) & 1u); };
       // ---- Algorithm 4, group selection: groups taken whole, fill group, number still needed ----
       if (tid == 0) {
         int c = 0, bstar = NG;
         for (int b = NG - 1; b >= 0; --b) {
-          if (c + hist[b] > NP) break;
+          if (c + hist[b] > np_eff) break;
           c += hist[b];
           bstar = b;
         }
         const int fill = bstar > 0 ? bstar - 1 : -1;
         misc[MS_BSTAR] = bstar;
         misc[MS_FILL] = fill;
-        misc[MS_NEED] = fill >= 0 ? NP - c : 0;
-        misc[MS_NSEL] = 0;
+        misc[MS_NEED] = fill >= 0 ? np_eff - c : 0;
+        misc[MS_NSEL] = nsucc;
+        misc[MS_NSUCC] = 0;
         misc[MS_CNT] = 0;
         misc[MS_NCAND] = 0;
         for (int c = 0; c < 5; ++c) {
@@ -186,7 +211,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
         for (int i = 0; i < kKeep; ++i) {
           kk[i] = 0ull;
           const int n = n0 + i;
-          if (n < n1) {
+          if (n < n1 && !excluded(n)) {
             const int b = ar.bin(D[n], NG);
             if (b >= bstar) sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
             if (b == fill) {
@@ -201,6 +226,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
         }
       } else {
         for (int n = n0; n < n1; ++n) {
+          if (excluded(n)) continue;
           const int b = ar.bin(D[n], NG);
           if (b >= bstar) sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
           if (b == fill) {
@@ -217,7 +243,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
             if ((kmask >> i) & 1u) fn(n0 + i, kk[i]);
         } else {
           for (int n = n0; n < n1; ++n)
-            if (ar.bin(D[n], NG) == fill) fn(n, splitmix64(s2 ^ (uint64_t)n));
+            if (ar.bin(D[n], NG) == fill && !excluded(n)) fn(n, splitmix64(s2 ^ (uint64_t)n));
         }
       };
       ME_PROF_MARK(0)
@@ -226,7 +252,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
         if (P.fill == 0) {  // lowest indices: rank of each fill member in index order
           int rank = block_excl_scan(nfill, wsum);
           for (int n = n0; n < n1 && rank < need; ++n) {
-            if (ar.bin(D[n], NG) == fill) {
+            if (ar.bin(D[n], NG) == fill && !excluded(n)) {
               sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
               ++rank;
             }
@@ -310,6 +336,11 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       __syncthreads();
       ME_PROF_MARK(1)
       const int nsel = misc[MS_NSEL];
+      if (nsucc > 0 && tid < nsucc) {  // P' back into Algorithm 4's view (D has not changed)
+        const int v = succ[tid];
+        atomicAnd(&vnmark[v >> 5], ~(1u << (v & 31)));
+        atomicAdd(&hist[ar.bin(D[v], NG)], 1);
+      }
       // ascending order of P (distinct VN indices: rank = number of smaller ones; at most 64,
       // one wavefront, ranks from register reads)
       if (tid < WAVE) {
@@ -373,11 +404,13 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
               atomicAdd(&misc[MS_L2 + 31 - __clz(G.row_deg(m) - 1)], 1);
             }
           }
+          const int mwin = __builtin_amdgcn_readlane(m_[u], wl);
           wave_sync();
           if (ln == 0) {
             if (P.out.trace) P.out.trace[(size_t)f * P.max_updates + tprev + i] = e;
             mp[e].c = (msg_t)newv;
             L[p] = (llr_t)Lnew;
+            selm[i] = mwin;
           }
         }
       }
@@ -479,6 +512,36 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       for (int w = tid; w < nvw; w += BS) vnmark[w] = 0u;
       const int unsat = misc[MS_UNSAT];
       __syncthreads();
+      if (lmd) {
+        // ---- Algorithm 6: each p proposes the VN of largest CI among U(m*_p, p) (lowest index on
+        //      ties), from the state after the step; distinct proposals are kept (marked in vnmark,
+        //      which the next step's selection reads).  One wavefront per p ----
+        for (int i = wv; i < nsel; i += nwv) {
+          const int p = sel_s[i], ms = selm[i];
+          const int rs = G.row_start(ms), dc = G.row_deg(ms);
+          uint64_t best = 0;
+          if (G.vn_deg(p) == 1) {  // Sec. V: the other VNs of m*_p
+            for (int pos = ln; pos < dc; pos += WAVE) {
+              const int j = G.row_vn(ms, rs, pos);
+              if (j != p) best = umax64(best, mkkey(D[j], (uint32_t)j));
+            }
+          } else {  // the VNs other than p of p's checks other than m*_p (two-hop table)
+            const int2 nb = G.nbr(p);
+            for (int idx = ln; idx < nb.y; idx += WAVE) {
+              const int2 ent = H.nbr[nb.x + idx];
+              const int j = ent.y & 0xFFFFFF;
+              if (ent.x >= 0 && j != p && (ent.x < rs || ent.x >= rs + dc)) best = umax64(best, mkkey(D[j], (uint32_t)j));
+            }
+          }
+          best = wave_max_u64(best);
+          if (ln == 0 && best != 0ull) {
+            const int q = (int)key_idx(best);
+            const uint32_t bit = 1u << (q & 31);
+            if (!(atomicOr(&vnmark[q >> 5], bit) & bit)) succ[atomicAdd(&misc[MS_NSUCC], 1)] = q;
+          }
+        }
+        __syncthreads();
+      }
       if (tid == 0) misc[MS_NROWS] = 0;
       t += nsel;
       steps += 1;

@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libldpcci.so")
 
 # schedules / arithmetic / fill (values of include/ldpcci.h)
-FLOODING, LAYERED, RBP, CIRBP, ME_CIRBP, REPLAY, LMDRBP, SLMDRBP, LMD_CIRBP = range(9)
+FLOODING, LAYERED, RBP, CIRBP, ME_CIRBP, REPLAY, LMDRBP, SLMDRBP, LMD_CIRBP, ME_LMD_CIRBP = range(10)
 SPA_F32, MS_FIX = 0, 1
 FILL_LOWEST, FILL_HASH = 0, 1
 ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -4: "LDPC_ECAPACITY",

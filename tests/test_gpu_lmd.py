@@ -1,5 +1,5 @@
 """GPU parity of the LMD schedules (Sec. IV: LMDRBP, sLMDRBP; Algorithm 3: LMD-CIRBP; the degree-1
-rule of Sec. V) against the CPU oracle, through the C ABI.
+rule of Sec. V; Algorithm 6: multi-edge LMD-CIRBP) against the CPU oracle, through the C ABI.
 
 * fixed-point min-sum: bit-exact (recorded schedule, updates used, decoded bits, final state);
 * FP32 sum-product: free-running frame error rates within the oracle's 95% Clopper-Pearson
@@ -17,6 +17,7 @@ from paper_2102_11089_amd import synth as S
 pytestmark = pytest.mark.gpu
 
 KINDS = {"lmdrbp": (O.LMDRBP, 6), "slmdrbp": (O.SLMDRBP, 7), "lmdcirbp": (O.LMDCIRBP, 8)}
+ME_LMD = (O.MELMDCIRBP, 9)
 
 
 def say(*a):
@@ -49,7 +50,8 @@ def assert_fixed_equal(g, ref, kind, state=True):
 
 
 def test_constants_match_the_oracle(gpu):
-    assert (gpu.LMDRBP, gpu.SLMDRBP, gpu.LMD_CIRBP) == (O.LMDRBP, O.SLMDRBP, O.LMDCIRBP)
+    assert (gpu.LMDRBP, gpu.SLMDRBP, gpu.LMD_CIRBP, gpu.ME_LMD_CIRBP) == (O.LMDRBP, O.SLMDRBP, O.LMDCIRBP,
+                                                                          O.MELMDCIRBP)
 
 
 @pytest.mark.parametrize("kind", list(KINDS))
@@ -207,3 +209,64 @@ def test_lmd_edge_cases(gpu):
         g = gpu_decode(gpu, sh, llr, kind, gpu.SPA_F32, max_updates=10, check_every=0, trace=True)
         np.testing.assert_array_equal(np_(g.trace), ref.trace)
         np.testing.assert_allclose(np_(g.llr_out), ref.llr_out, rtol=1e-5, atol=1e-5)
+
+
+# ------------------------------------------------------------------------------------------
+# ME-LMD-CIRBP (Algorithm 6)
+# ------------------------------------------------------------------------------------------
+def me_lmd_gpu(ldpc, code_h, llr, arith, **kw):
+    t = torch.from_numpy(np.ascontiguousarray(llr, dtype=np.float32)).cuda()
+    r = ldpc.decode(code_h, t, ME_LMD[1], arith, **kw)
+    torch.cuda.synchronize()
+    return r
+
+
+@pytest.mark.parametrize("fill", [0, 1])
+@pytest.mark.parametrize("n_p,n_g", [(1, 16), (4, 4), (8, 16), (24, 8), (64, 256)])
+def test_fixed_me_lmd_bit_exact_c0(gpu, n_p, n_g, fill):
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 300, 2.0, 210)
+    say(f"[fixed me-lmd] c0 n_p={n_p} n_g={n_g} fill={fill}")
+    kw = dict(max_updates=2400, n_p=n_p, n_g=n_g, fill=fill, seed=78, trace=True, dump=True, q_bits=6, frac_bits=1)
+    ref = O.decode(code, llr, ME_LMD[0], O.MSFIX, threads=8, **kw)
+    g = me_lmd_gpu(gpu, h, llr, gpu.MS_FIX, **kw)
+    np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+    np.testing.assert_array_equal(np_(g.steps_used), ref.steps_used)
+    np.testing.assert_array_equal(np_(g.trace), ref.trace)
+    np.testing.assert_array_equal(np_(g.bits), ref.bits)
+    np.testing.assert_array_equal(np_(g.c2v), ref.c2v)
+    np.testing.assert_array_equal(np_(g.pre), ref.pre)
+    np.testing.assert_array_equal(np_(g.Lt), ref.Lt)
+    np.testing.assert_array_equal(np_(g.D), ref.D)
+
+
+def test_fixed_me_lmd_degree_one_qc_and_bg1_z128(gpu):
+    """Degree-1 VNs (BG1-shaped, Z = 4), a 24-column QC code and the Z = 128 code (messages in
+    global memory): bit-exact schedules."""
+    for code, B, eb, n_p, mu in ((S.qc_bg1_shaped(4, seed=3), 64, 1.0, 8, 2000),
+                                 (S.qc_24col(24, 8, seed=2), 64, 2.5, 16, 3000),
+                                 (S.workload_code("c3"), 2, 1.25, 32, 4000)):
+        h = gpu.Code(code)
+        cw, llr = S.frames(code, B, eb, 211)
+        say(f"[fixed me-lmd hash] {code.name} n_p={n_p}")
+        kw = dict(max_updates=mu, n_p=n_p, n_g=16, fill=1, seed=6, trace=True, q_bits=8, frac_bits=2)
+        ref = O.decode(code, llr, ME_LMD[0], O.MSFIX, threads=4, **kw)
+        g = me_lmd_gpu(gpu, h, llr, gpu.MS_FIX, **kw)
+        np.testing.assert_array_equal(np_(g.trace), ref.trace)
+        np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+        np.testing.assert_array_equal(np_(g.bits), ref.bits)
+
+
+def test_f32_me_lmd_fer_within_interval_c0(gpu):
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 1000, 2.0, 212)
+    say("[f32 me-lmd] c0 1000 frames n_p=8 hash fill")
+    kw = dict(max_updates=2400, n_p=8, n_g=16, fill=1, seed=10)
+    ref = O.decode(code, llr, ME_LMD[0], O.SPA, threads=8, **kw)
+    g = me_lmd_gpu(gpu, h, llr, gpu.SPA_F32, **kw)
+    k_ref = int(np.any(ref.bits != cw, axis=1).sum())
+    k_gpu = int(np.any(np_(g.bits) != cw, axis=1).sum())
+    lo, hi = cp_interval(k_ref, 1000)
+    assert lo <= k_gpu / 1000 <= hi, (k_gpu, k_ref, lo, hi)
