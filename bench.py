@@ -17,7 +17,7 @@ Prints one JSON line.  ``--sweep`` instead prints one JSON line per Eb/N0 point 
       from {1.0, 1.5, ..., 4.0} dB, FP32 and 8-bit fixed point;
   c3  ME-CIRBP (Algorithms 4-5) on the BG1-shaped code with Z = 128 (n = 8704), N_P in
       {8, 16, 32, 64}, N_G = 16, random (keyed) fill, Eb/N0 in {1.0, 1.25, 1.5} dB: update steps
-      against FER;
+      against FER; ME-LMD-CIRBP (Algorithm 6) on the same batches alongside;
   c4  the differentiable unrolled decoder: (3,6)-regular n = 576, 4096 frames, 300 recorded CIRBP
       updates, damped replay forward with checkpoints every 32 and the adjoint;
   lmd the LMD schedules (LMD-CIRBP, LMDRBP, sLMDRBP; Sec. IV) against CIRBP on the default
@@ -363,7 +363,8 @@ def bench_batched(args, ldpc, S, dev):
 
 
 def bench_multi_edge(args, ldpc, S, dev):
-    """Workload c3: ME-CIRBP, update steps against FER."""
+    """Workload c3: ME-CIRBP, update steps against FER; ME-LMD-CIRBP (Algorithm 6) on the same
+    batches alongside (its points carry "schedule": "me_lmd_cirbp"; value counts ME-CIRBP)."""
     import torch
     code = S.workload_code("c3")
     h = ldpc.Code(code)
@@ -373,31 +374,40 @@ def bench_multi_edge(args, ldpc, S, dev):
     total_ms = 0.0
     total_frames = 0
     total_upd = 0
+    lmd_ms = 0.0
+    lmd_frames = 0
     for eb in (1.0, 1.25, 1.5):
         batch = make_batches(code, 1, B, eb, args.seed + int(eb * 100), dev)[0]
         cw, llr = batch
-        for n_p in (8, 16, 32, 64):
-            def go():
-                with torch.cuda.stream(stream):
-                    return ldpc.decode(h, llr, ldpc.ME_CIRBP, ldpc.SPA_F32, max_updates=3 * code.E, gamma=0.1,
-                                       n_p=n_p, n_g=16, fill=ldpc.FILL_HASH, seed=args.seed, stream=stream)
-            r, ms, _ = ev_time(stream, go)
-            print(f"[c3] Eb/N0 {eb} N_P {n_p}: {ms:.1f} ms", file=sys.stderr, flush=True)
-            fe = int(torch.any(r.bits != cw, dim=1).sum())
-            upd = int(r.updates_used.sum())
-            steps = int(r.steps_used.sum())
-            total_ms += ms
-            total_frames += B
-            total_upd += upd
-            rows.append({"ebn0": eb, "n_p": n_p, "fer": fe / B, "frame_errors": fe, "mean_steps": steps / B,
-                         "mean_updates": upd / B, "frames_per_s": round(B / (ms / 1e3), 2),
-                         "edge_updates_per_s": round(upd / (ms / 1e3), 1), "kernel_ms": round(ms, 3)})
+        for sched, kind in (("me_cirbp", ldpc.ME_CIRBP), ("me_lmd_cirbp", ldpc.ME_LMD_CIRBP)):
+            for n_p in (8, 16, 32, 64):
+                def go():
+                    with torch.cuda.stream(stream):
+                        return ldpc.decode(h, llr, kind, ldpc.SPA_F32, max_updates=3 * code.E, gamma=0.1,
+                                           n_p=n_p, n_g=16, fill=ldpc.FILL_HASH, seed=args.seed, stream=stream)
+                r, ms, _ = ev_time(stream, go)
+                print(f"[c3] {sched} Eb/N0 {eb} N_P {n_p}: {ms:.1f} ms", file=sys.stderr, flush=True)
+                fe = int(torch.any(r.bits != cw, dim=1).sum())
+                upd = int(r.updates_used.sum())
+                steps = int(r.steps_used.sum())
+                if kind == ldpc.ME_CIRBP:
+                    total_ms += ms
+                    total_frames += B
+                    total_upd += upd
+                else:
+                    lmd_ms += ms
+                    lmd_frames += B
+                rows.append({"schedule": sched, "ebn0": eb, "n_p": n_p, "fer": fe / B, "frame_errors": fe,
+                             "mean_steps": steps / B, "mean_updates": upd / B,
+                             "frames_per_s": round(B / (ms / 1e3), 2),
+                             "edge_updates_per_s": round(upd / (ms / 1e3), 1), "kernel_ms": round(ms, 3)})
     out = {"metric": "ME-CIRBP decoded frames/s and update steps vs FER", "value": round(total_frames / (total_ms / 1e3), 3),
            "unit": "frames/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(total_ms, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "BG1-shaped QC 46x68, Z=128 (n=8704, m=5888, E=40448); ME-CIRBP N_G=16, random "
                                   "(keyed) fill, gamma 0.1, cap 3E; Eb/N0 1.0/1.25/1.5 dB", "frames_per_point": B},
-           "edge_updates_per_s": round(total_upd / (total_ms / 1e3), 1), "points": rows}
+           "edge_updates_per_s": round(total_upd / (total_ms / 1e3), 1),
+           "me_lmd_cirbp_frames_per_s": round(lmd_frames / (lmd_ms / 1e3), 3), "points": rows}
     print(json.dumps(out), flush=True)
 
 
