@@ -21,7 +21,9 @@ Prints one JSON line.  ``--sweep`` instead prints one JSON line per Eb/N0 point 
   c4  the differentiable unrolled decoder: (3,6)-regular n = 576, 4096 frames, 300 recorded CIRBP
       updates, damped replay forward with checkpoints every 32 and the adjoint;
   lmd the LMD schedules (LMD-CIRBP, LMDRBP, sLMDRBP; Sec. IV) against CIRBP on the default
-      workload's code and batches.
+      workload's code and batches;
+  ci  the CI-metric analysis: J(gamma) and F(gamma) from GPU flooding decodes beside the GA-DE
+      model (Properties 1-2, Appendix A), and CIRBP's FER against gamma (Fig. 2's sweep).
 """
 from __future__ import annotations
 
@@ -263,6 +265,68 @@ def bench_lmd(args, ldpc, S, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_ci(args, ldpc, S, dev):
+    """CI-metric analysis (Sec. III-A, Properties 1-2, Appendix A; Fig. 2's gamma sweep):
+    J(gamma) and F(gamma) measured from GPU flooding decodes of a girth-6 (4,8)-regular QC code
+    (n = 4000: the flooding kernel keeps the frame's messages in LDS) beside the GA-DE model, and CIRBP's FER against gamma on the BG1-shaped Z=52 code."""
+    import torch
+    from paper_2102_11089_amd import ci_analysis as C
+    stream = torch.cuda.Stream(device=dev)
+    gs = [0.0, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5]
+    code = S.qc_regular(4, 8, 500, seed=1)
+    h = ldpc.Code(code)
+    B = args.frames or 4000
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed)
+    jrows = []
+    t0 = time.perf_counter()
+    for eb in (1.5, 2.0, 2.5):
+        s2 = S.sigma2_from_ebn0(eb, code.design_rate)
+        # all-zero codeword (the analysis' assumption): x = +1
+        llr = (2.0 / s2) * (1.0 + float(np.sqrt(s2)) * torch.randn((B, code.N), generator=g, device=dev))
+        for it in (1, 2, 3):
+            with torch.cuda.stream(stream):
+                L, Lt = C.flooding_states(ldpc, h, llr, it, stream=stream)
+            torch.cuda.synchronize()
+            e = C.empirical(L.cpu().numpy(), Lt.cpu().numpy(), gs)
+            ml, mlt = C.ga_totals(4, 8, C.channel_mean(eb, code.design_rate), it)
+            jrows.append({"ebn0": eb, "iteration": it, "gamma": gs,
+                          "J_decoded": [round(float(x), 5) for x in e["J"]],
+                          "J_ga_de": [round(float(x), 5) for x in C.ga_j(gs, ml, mlt)],
+                          "F_decoded": [round(float(x), 5) for x in e["F"]],
+                          "incorrect_with_D_ge_gamma": [int(x) for x in e["n_incorrect"]]})
+            print(f"[ci] J/F Eb/N0 {eb} iteration {it}", file=sys.stderr, flush=True)
+    t_j = time.perf_counter() - t0
+    code1 = S.workload_code("c1")
+    h1 = ldpc.Code(code1)
+    F1 = 8192
+    srows = []
+    for eb in (1.0, 1.25, 1.5):
+        cw, llr = make_batches(code1, 1, F1, eb, args.seed + int(eb * 100), dev)[0]
+        for cap_it in (1, 3):
+            for gamma in (0.0, 0.05, 0.1, 0.15, 0.2, 0.3):
+                def go():
+                    with torch.cuda.stream(stream):
+                        return ldpc.decode(h1, llr, ldpc.CIRBP, ldpc.SPA_F32, max_updates=cap_it * code1.E,
+                                           gamma=gamma, stream=stream)
+                r, ms, _ = ev_time(stream, go)
+                fe = int(torch.any(r.bits != cw, dim=1).sum())
+                srows.append({"ebn0": eb, "cap_iterations": cap_it, "gamma": gamma, "fer": fe / F1,
+                              "frame_errors": fe, "mean_updates": float(r.updates_used.double().mean()),
+                              "fallback_fraction": float(r.fallbacks.double().sum() / max(int(r.updates_used.sum()), 1)),
+                              "frames_per_s": round(F1 / (ms / 1e3), 2)})
+                print(f"[ci] gamma sweep Eb/N0 {eb} cap {cap_it}E gamma {gamma}: {ms:.1f} ms", file=sys.stderr,
+                      flush=True)
+    out = {"metric": "CI-metric analysis: J(gamma), F(gamma) (decoded vs GA-DE) and CIRBP FER against gamma",
+           "value": None, "unit": None, "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None,
+           "higher_is_better": None, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "J/F: (4,8)-regular girth-6 QC code n=4000 (Z=500), all-zero codeword, "
+                                  f"{B} frames per point, flooding iterations 1-3, Eb/N0 1.5/2.0/2.5 dB; gamma sweep: "
+                                  f"BG1-shaped Z=52, {F1} random codewords per point, CIRBP caps 1E and 3E"},
+           "j_f": jrows, "j_f_seconds": round(t_j, 3), "gamma_sweep": srows}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batched(args, ldpc, S, dev):
     """Workload c2: one persistent launch over uneven codes, schedules and SNRs."""
     import torch
@@ -466,7 +530,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--sweep", type=str, default="", help="comma list of Eb/N0 points: FER curves")
-    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4", "lmd"])
+    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4", "lmd", "ci"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -484,7 +548,7 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload != "c1":
         {"c2": bench_batched, "c3": bench_multi_edge, "c4": bench_unrolled,
-         "lmd": bench_lmd}[args.workload](args, ldpc, S, dev)
+         "lmd": bench_lmd, "ci": bench_ci}[args.workload](args, ldpc, S, dev)
         return
 
     args.frames = args.frames or C1_FRAMES

@@ -181,6 +181,27 @@ def expand_qc(shift: np.ndarray, Z: int, name: str = "", design_rate: float = 0.
     return code
 
 
+def qc_regular(dv: int, dc: int, Z: int, seed: int = 1) -> Code:
+    """(dv, dc)-regular QC code: an all-ones dv x dc base lifted by Z with seeded shifts, redrawn
+    until no 2 x 2 block submatrix closes a 4-cycle (s11 - s12 + s22 - s21 != 0 mod Z), so the
+    Tanner graph has girth at least 6.  n = dc Z, design rate 1 - dv/dc."""
+    rng = np.random.default_rng(seed)
+    for _ in range(10000):
+        shift = rng.integers(0, Z, size=(dv, dc))
+        ok = True
+        for i1 in range(dv):
+            for i2 in range(i1 + 1, dv):
+                d = (shift[i1] - shift[i2]) % Z  # 4-cycle: equal differences in two columns
+                if len(np.unique(d)) < dc:
+                    ok = False
+                    break
+            if not ok:
+                break
+        if ok:
+            return expand_qc(shift.astype(np.int32), Z, name=f"qc{dv}{dc}_Z{Z}s{seed}", design_rate=1 - dv / dc)
+    raise RuntimeError("no 4-cycle-free shifts found")
+
+
 def bg1_shaped_base(seed: int = 1) -> np.ndarray:
     """46 x 68 base pattern (1 = circulant, 0 = zero block) with 316 nonzeros.
 
