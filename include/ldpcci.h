@@ -162,7 +162,8 @@ int ldpc_decode(const ldpc_code* code, const ldpc_schedule* schedule, const floa
 /* One frame of a batched launch (device memory, 40 bytes). */
 typedef struct {
   int32_t code;        /* index into the codes array of ldpc_decode_batch                         */
-  int32_t kind;        /* LDPC_FLOODING, LDPC_LAYERED, LDPC_RBP or LDPC_CIRBP                     */
+  int32_t kind;        /* LDPC_FLOODING, LDPC_LAYERED, LDPC_RBP, LDPC_CIRBP or an LMD schedule    */
+                       /* (LDPC_LMDRBP, LDPC_SLMDRBP, LDPC_LMD_CIRBP)                            */
   float gamma;         /* CIRBP threshold (>= 0)                                                   */
   int32_t reserved;
   int64_t max_updates; /* cap in C2V propagations                                                  */
@@ -171,7 +172,7 @@ typedef struct {
 } ldpc_frame_desc;
 
 /* Decode F frames of uneven codes and schedules in one persistent launch (the batched form of
-   ldpc_decode; the schedules are those of Sec. I, II-A and Algorithm 1).  codes: host array of
+   ldpc_decode; the schedules are those of Sec. I, II-A, Algorithm 1 and Algorithms 2-3).  codes: host array of
    n_codes handles (1..64, all created on the current device).  s supplies the arithmetic (arith,
    q_bits, frac_bits) and check_every for every frame; frames (device [F]) the rest.  Workers pull
    frames from a device work queue in descriptor order (put the longest decodes first for the

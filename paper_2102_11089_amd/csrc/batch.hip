@@ -140,7 +140,8 @@ __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
     f = uni(f);
     if (f >= B.F) break;
     const BatchFrame d = B.frames[f];
-    const bool kind_ok = d.kind == KIND_FLOODING || d.kind == KIND_LAYERED || d.kind == KIND_RBP || d.kind == KIND_CIRBP;
+    const bool kind_ok = d.kind == KIND_FLOODING || d.kind == KIND_LAYERED || d.kind == KIND_RBP || d.kind == KIND_CIRBP ||
+                         is_lmd(d.kind);
     bool ok = d.code >= 0 && d.code < B.n_codes && kind_ok && d.max_updates >= 0 && d.llr_off >= 0 &&
               d.out_off >= 0 && d.gamma >= 0.0f;
     const DevCode& H = *B.codes[ok ? d.code : 0];
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
     J.trace = nullptr;
     J.dump_c2v = J.dump_pre = J.dump_L = J.dump_Lt = J.dump_D = nullptr;
     if (d.kind == KIND_FLOODING || d.kind == KIND_LAYERED) wave_baseline_frame<A, STORE>(H, G, ar, P, ms, J);
+    else if (is_lmd(d.kind)) dyn_decode_frame<A, STORE, decltype(G), true>(H, G, ar, P, ms, J);
     else dyn_decode_frame<A, STORE>(H, G, ar, P, ms, J);
   }
 }

@@ -418,11 +418,11 @@ def _mixed_batch(codes, F, seed, ebn0s=(1.5, 2.5, 3.5)):
     frames = np.zeros(F, dtype=L.FRAME_DESC)
     llrs, cws, per = [], [], []
     off = 0
-    kinds = [L.FLOODING, L.LAYERED, L.RBP, L.CIRBP]
+    kinds = [L.FLOODING, L.LAYERED, L.RBP, L.CIRBP, L.LMDRBP, L.SLMDRBP, L.LMD_CIRBP]
     for f in range(F):
         ci = int(rng.integers(len(codes)))
         c = codes[ci]
-        kind = kinds[int(rng.integers(4))]
+        kind = kinds[int(rng.integers(len(kinds)))]
         cw, llr = S.frames(c, 1, float(rng.choice(ebn0s)), seed * 1000 + f)
         frames[f] = (ci, kind, 0.1, 0, (20 if kind in (L.FLOODING, L.LAYERED) else 3) * c.E, off, off)
         llrs.append(llr[0]); cws.append(cw[0]); per.append((ci, kind, off))
@@ -436,12 +436,13 @@ def test_batch_uneven_codes_and_schedules(gpu, arith):
     hs = [gpu.Code(c) for c in codes]
     frames, pool, cws, per, out_len = _mixed_batch(codes, 240, 3)
     a = gpu.MS_FIX if arith == "fix" else gpu.SPA_F32
-    say(f"[batch {arith}] 240 frames over 3 codes and 4 schedules")
+    say(f"[batch {arith}] 240 frames over 3 codes and 7 schedules")
     bits, llr_out, upd, steps, fall = gpu.decode_batch(hs, frames, torch.from_numpy(pool).cuda(), out_len, arith=a,
                                                        q_bits=8, frac_bits=2)
     torch.cuda.synchronize()
     bits, upd = np_(bits), np_(upd)
-    kmap = {gpu.FLOODING: O.FLOODING, gpu.LAYERED: O.LAYERED, gpu.RBP: O.RBP, gpu.CIRBP: O.CIRBP}
+    kmap = {gpu.FLOODING: O.FLOODING, gpu.LAYERED: O.LAYERED, gpu.RBP: O.RBP, gpu.CIRBP: O.CIRBP,
+            gpu.LMDRBP: O.LMDRBP, gpu.SLMDRBP: O.SLMDRBP, gpu.LMD_CIRBP: O.LMDCIRBP}
     errs_gpu = errs_ref = 0
     for f, (ci, kind, off) in enumerate(per):
         c = codes[ci]
@@ -451,8 +452,9 @@ def test_batch_uneven_codes_and_schedules(gpu, arith):
             ref = O.decode(c, llr, kmap[kind], O.MSFIX, max_updates=mu, q_bits=8, frac_bits=2)
             assert int(upd[f]) == int(ref.updates_used[0]), (f, kind)
             np.testing.assert_array_equal(bits[off:off + c.N], ref.bits[0])
-        elif kind in (gpu.RBP, gpu.CIRBP):  # same per-frame code path as the per-code kernel
-            g = gpu_decode(gpu, hs[ci], llr, "rbp" if kind == gpu.RBP else "cirbp", gpu.SPA_F32, max_updates=mu)
+        elif kind not in (gpu.FLOODING, gpu.LAYERED):  # same per-frame code path as the per-code kernel
+            g = gpu.decode(hs[ci], torch.from_numpy(llr).cuda(), int(kind), gpu.SPA_F32, max_updates=mu)
+            torch.cuda.synchronize()
             assert int(upd[f]) == int(np_(g.updates_used)[0])
             np.testing.assert_array_equal(bits[off:off + c.N], np_(g.bits)[0])
         else:
@@ -467,7 +469,7 @@ def test_batch_rejects_bad_descriptors(gpu):
     hs = [gpu.Code(codes[0])]
     frames, pool, cws, per, out_len = _mixed_batch(codes, 6, 4)
     frames[1]["code"] = 7          # unknown code
-    frames[2]["kind"] = 9          # unknown schedule
+    frames[2]["kind"] = 42         # unknown schedule
     frames[3]["llr_off"] = len(pool) - 10   # LLRs past the end of the pool
     frames[4]["gamma"] = -1.0      # negative threshold
     bits, llr_out, upd, steps, fall = gpu.decode_batch(hs, frames, torch.from_numpy(pool).cuda(), out_len)
