@@ -707,6 +707,12 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   if (T.storage == LDPC_STORE_GLOBAL_FRAME) stores = {STORE_FRAME_GLOBAL};
   if (T.storage == LDPC_STORE_GLOBAL_REC) stores = {STORE_FRAME_REC};
   if (T.storage == LDPC_STORE_GLOBAL_STATE) stores = {STORE_FRAME_ALL};
+  // LMDRBP and sLMDRBP read the check keys for their first choice only and write no CI records:
+  // keys in global memory cost them nothing afterwards, and the LDS they leave holds more resident
+  // frames (BG1-shaped Z=52: 20 frames per CU against 14, +14% and +8% frames/s).  LMD-CIRBP,
+  // which still writes a record per touched VN, lost 3% that way and keeps the keys in LDS.
+  if (T.storage == LDPC_STORE_AUTO && (s->kind == LDPC_LMDRBP || s->kind == LDPC_SLMDRBP))
+    stores.push_back(STORE_FRAME_ALL);
   const int lut_off = 257 * (fixed ? s->frac_bits : 0);
 
   if (me) {
