@@ -270,3 +270,37 @@ def test_f32_me_lmd_fer_within_interval_c0(gpu):
     k_gpu = int(np.any(np_(g.bits) != cw, axis=1).sum())
     lo, hi = cp_interval(k_ref, 1000)
     assert lo <= k_gpu / 1000 <= hi, (k_gpu, k_ref, lo, hi)
+
+
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_f32_lmd_schedule_follows_the_oracle(gpu, kind):
+    """FP32 against the FP64 oracle: the recorded schedules agree update by update until a near-tie
+    is decided differently; most frames agree over their first 200 updates."""
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    cw, llr = S.frames(code, 300, 2.0, 213)
+    say(f"[f32 schedule {kind}] c0 300 frames")
+    kw = dict(max_updates=200, check_every=0, trace=True)
+    ref = O.decode(code, llr, KINDS[kind][0], O.SPA, threads=8, **kw)
+    g = gpu_decode(gpu, h, llr, kind, gpu.SPA_F32, **kw)
+    same = np.all(np_(g.trace) == ref.trace, axis=1)
+    first = np.argmax(np_(g.trace) != ref.trace, axis=1)
+    assert same.mean() > 0.9, (same.mean(), np.median(first[~same]) if (~same).any() else None)
+
+
+def test_me_schedules_with_more_vns_per_step_than_the_code_has(gpu):
+    """N_P larger than N (a single check of 5 VNs, N_P = 8): Algorithm 4 returns every VN, each
+    step updates all five, and the cap counts N_P per step as in the oracle."""
+    code = S.spc_code(5)
+    h = gpu.Code(code)
+    rng = np.random.default_rng(7)
+    llr = rng.normal(0.3, 1.5, size=(16, 5)).astype(np.float32)
+    for kind_o, kind_g in ((O.MECIRBP, 4), (ME_LMD[0], ME_LMD[1])):
+        kw = dict(max_updates=40, n_p=8, n_g=16, check_every=0, trace=True, q_bits=8, frac_bits=2)
+        ref = O.decode(code, llr, kind_o, O.MSFIX, **kw)
+        t = torch.from_numpy(llr).cuda()
+        g = gpu.decode(h, t, kind_g, gpu.MS_FIX, **kw)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(np_(g.trace), ref.trace)
+        np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
+        np.testing.assert_array_equal(np_(g.steps_used), ref.steps_used)
