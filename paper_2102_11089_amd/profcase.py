@@ -78,14 +78,15 @@ def main():
     eb = float(sys.argv[5]) if len(sys.argv) > 5 else 1.0
     code = S.workload_code(name)
     h = ldpc.Code(code)
-    kind = {"cirbp": ldpc.CIRBP, "rbp": ldpc.RBP, "flooding": ldpc.FLOODING, "layered": ldpc.LAYERED}[sched]
+    kind = {"cirbp": ldpc.CIRBP, "rbp": ldpc.RBP, "flooding": ldpc.FLOODING, "layered": ldpc.LAYERED,
+            "lmdcirbp": ldpc.LMD_CIRBP, "lmdrbp": ldpc.LMDRBP, "slmdrbp": ldpc.SLMDRBP}[sched]
     a = ldpc.MS_FIX if arith == "fix" else ldpc.SPA_F32
     cap = 50 * code.E if kind in (ldpc.FLOODING, ldpc.LAYERED) else (2400 if name == "c0" else 3 * code.E)
     cw, llr = S.frames(code, B, eb, 7)
     t = torch.from_numpy(llr).cuda()
     for _ in range(2):
-        r = ldpc.decode(h, t, kind, a, max_updates=cap, check_every=0 if kind in (ldpc.RBP, ldpc.CIRBP) else 1,
-                        q_bits=8, frac_bits=2)
+        dyn = kind not in (ldpc.FLOODING, ldpc.LAYERED)
+        r = ldpc.decode(h, t, kind, a, max_updates=cap, check_every=0 if dyn else 1, q_bits=8, frac_bits=2)
         torch.cuda.synchronize()
     print("updates", int(r.updates_used.sum()), "frames", B, flush=True)
 
