@@ -47,11 +47,13 @@ def eager_counts(gpu, h, t_cw, ebn0s, rate, B, seed, kind, arith, cap, **kw):
     return np.array(rows, dtype=np.int64)
 
 
-@pytest.mark.parametrize("kind,arith", [("cirbp", "f32"), ("flooding", "f32"), ("layered", "fix"), ("me", "fix")])
+@pytest.mark.parametrize("kind,arith", [("cirbp", "f32"), ("flooding", "f32"), ("layered", "fix"), ("me", "fix"),
+                                        ("lmdcirbp", "f32"), ("melmd", "fix")])
 def test_sweep_replays_equal_eager(gpu, kind, arith):
     code = S.qc_24col(24, 12, seed=5)  # N = 576, rate 1/2
     h = gpu.Code(code)
-    k = {"cirbp": gpu.CIRBP, "flooding": gpu.FLOODING, "layered": gpu.LAYERED, "me": gpu.ME_CIRBP}[kind]
+    k = {"cirbp": gpu.CIRBP, "flooding": gpu.FLOODING, "layered": gpu.LAYERED, "me": gpu.ME_CIRBP,
+         "lmdcirbp": gpu.LMD_CIRBP, "melmd": gpu.ME_LMD_CIRBP}[kind]
     a = gpu.SPA_F32 if arith == "f32" else gpu.MS_FIX
     cap = 20 * code.E if kind in ("flooding", "layered") else 2 * code.E
     kw = dict(q_bits=8, frac_bits=2, n_p=8, n_g=16)

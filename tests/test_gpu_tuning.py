@@ -24,12 +24,13 @@ def outputs(gpu, h, llr, kind, arith, **kw):
 
 
 @pytest.mark.parametrize("kind,arith", [("flooding", "f32"), ("layered", "fix"), ("cirbp", "f32"), ("cirbp", "fix"),
-                                        ("rbp", "f32"), ("me", "fix")])
+                                        ("rbp", "f32"), ("me", "fix"), ("lmdcirbp", "fix"), ("slmdrbp", "f32"),
+                                        ("melmd", "fix")])
 def test_autotuned_launch_gives_identical_outputs(gpu, kind, arith):
     code = S.qc_24col(48, 8, seed=2)  # N = 1152, rate 2/3
     h = gpu.Code(code)
     k = {"flooding": gpu.FLOODING, "layered": gpu.LAYERED, "cirbp": gpu.CIRBP, "rbp": gpu.RBP,
-         "me": gpu.ME_CIRBP}[kind]
+         "me": gpu.ME_CIRBP, "lmdcirbp": gpu.LMD_CIRBP, "slmdrbp": gpu.SLMDRBP, "melmd": gpu.ME_LMD_CIRBP}[kind]
     a = gpu.SPA_F32 if arith == "f32" else gpu.MS_FIX
     cw, llr_np = S.frames(code, 384, 3.0, 7)
     llr = torch.from_numpy(llr_np).cuda()
@@ -46,7 +47,8 @@ def test_autotuned_launch_gives_identical_outputs(gpu, kind, arith):
     for x, y in zip(base, tuned):
         np.testing.assert_array_equal(x, y)
     if arith == "fix":  # and both equal the oracle
-        ok = {"flooding": O.FLOODING, "layered": O.LAYERED, "cirbp": O.CIRBP, "rbp": O.RBP, "me": O.MECIRBP}[kind]
+        ok = {"flooding": O.FLOODING, "layered": O.LAYERED, "cirbp": O.CIRBP, "rbp": O.RBP, "me": O.MECIRBP,
+              "lmdcirbp": O.LMDCIRBP, "slmdrbp": O.SLMDRBP, "melmd": O.MELMDCIRBP}[kind]
         ref = O.decode(code, llr_np[:64], ok, O.MSFIX, max_updates=cap, q_bits=8, frac_bits=2, n_p=8, n_g=16,
                        threads=16)
         np.testing.assert_array_equal(tuned[0][:64], ref.bits)
