@@ -164,8 +164,8 @@ struct MeLayout {
   int off_cand, off_misc, off_lut, off_topo, off_rows2, total, rows_cap, cand_cap;
 };
 
-// LDS of the unrolled kernels: forward (c2v, L); backward adds the adjoints, the weight-gradient
-// row and the segment tape
+// LDS of the unrolled kernels: forward (c2v, L); backward adds the adjoints and the segment tape
+// (the weight gradients accumulate in the frame's global scratch row)
 void unroll_layout(const ldpc_code* c, int K, UnrollParams& U) {
   int o = 0;
   U.off_c2v = o; o = align16(o + c->E * 4);
@@ -173,7 +173,6 @@ void unroll_layout(const ldpc_code* c, int K, UnrollParams& U) {
   U.lds_fwd = o;
   U.off_ch = o; o = align16(o + c->E * 4);
   U.off_Lh = o; o = align16(o + c->N * 4);
-  U.off_gw = o; o = align16(o + c->E * 4);
   int ts = 1;
   while (ts < c->max_dc) ts <<= 1;
   U.tstride = ts;

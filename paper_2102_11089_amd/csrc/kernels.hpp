@@ -236,8 +236,8 @@ struct UnrollParams {
   float* c2v_out;          // [B][E] or null
   const float* grad_soft;  // [B][N]
   float* grad_llr;         // [B][N]
-  float* gw_part;          // [B][E] per-frame weight gradients (scratch)
-  int off_c2v, off_L, off_ch, off_Lh, off_gw, off_tape, off_tape_hdr;
+  float* gw_part;          // [B][E] per-frame weight gradients (scratch, accumulated in place)
+  int off_c2v, off_L, off_ch, off_Lh, off_tape, off_tape_hdr;
   int lds_fwd, lds_bwd;
 };
 hipError_t launch_unroll_fwd(const DevCode& H, const UnrollParams& U, int grid, hipStream_t st);

@@ -24,8 +24,11 @@
 //                  Lh_{VN of k} += w_e s g;   ch_{m->k} -= w_e s g.
 // sinh(a [+] b)/sinh(a) is the exact partial derivative of the pairwise rule (it follows from
 // phi being an involution with phi'(x) = -1/sinh(x)); a zero input takes the limit tanh(q/2), q the
-// rule over the remaining inputs.  Per-frame weight gradients go to a scratch row and are summed
-// over frames in a fixed order (frames in fixed chunks, then chunks), so grad_w is deterministic.
+// rule over the remaining inputs.  A step's weight gradient goes into the tape during the reverse
+// sweep; after each segment the contributions to each edge are summed in descending step order and
+// added to the frame's scratch row in global memory (one read-modify-write per distinct edge, so
+// the row leaves LDS for more resident frames).  The rows are summed over frames in a fixed order
+// (frames in fixed chunks, then chunks), so grad_w is deterministic.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -183,11 +186,10 @@ __global__ __launch_bounds__(WAVE) void k_unroll_bwd(DevCode H, UnrollParams U) 
   float* L = reinterpret_cast<float*>(lds + U.off_L);
   float* ch = reinterpret_cast<float*>(lds + U.off_ch);
   float* Lh = reinterpret_cast<float*>(lds + U.off_Lh);
-  float* gw = reinterpret_cast<float*>(lds + U.off_gw);
   const int TS = U.tstride;  // power of two >= largest row degree
   float* tv = reinterpret_cast<float*>(lds + U.off_tape);          // [K][TS] row inputs
   int* tj = reinterpret_cast<int*>(lds + U.off_tape) + U.ckpt_every * TS;  // [K][TS] their VNs
-  float4* th = reinterpret_cast<float4*>(lds + U.off_tape_hdr);      // [K] (p, c_old, w, -)
+  float4* th = reinterpret_cast<float4*>(lds + U.off_tape_hdr);      // [K] (p, c_old, w, dw)
   int4* ts = reinterpret_cast<int4*>(lds + U.off_tape_hdr) + U.ckpt_every;  // [K] (e, rs, dcx, n)
   const int lane = threadIdx.x;
   const int E = H.E, N = H.N, T = U.T, K = U.ckpt_every;
@@ -195,10 +197,11 @@ __global__ __launch_bounds__(WAVE) void k_unroll_bwd(DevCode H, UnrollParams U) 
   for (int f = blockIdx.x; f < U.B; f += gridDim.x) {
     const int* tr = U.trace + (size_t)f * T;
     const float* gs = U.grad_soft + (size_t)f * N;
+    float* gp = U.gw_part + (size_t)f * E;
     for (int i = lane; i < N; i += WAVE) Lh[i] = gs[i];
     for (int i = lane; i < E; i += WAVE) {
       ch[i] = 0.0f;
-      gw[i] = 0.0f;
+      gp[i] = 0.0f;
     }
     wave_sync();
     bool ok = true;
@@ -276,17 +279,40 @@ __global__ __launch_bounds__(WAVE) void k_unroll_bwd(DevCode H, UnrollParams U) 
           ch[si.y + lane] = __fsub_rn(ch[si.y + lane], a);
         }
         if (lane == x) {
-          gw[e] = __fadd_rn(gw[e], __fmul_rn(sadj, __fsub_rn(p, cold)));
+          th[r].w = __fmul_rn(sadj, __fsub_rn(p, cold));  // this step's d loss / d w_e
           ch[e] = __fsub_rn(ch[e], ws);
         }
         wave_sync();
       }
+      // the segment's weight gradients into the frame's row: each lane takes the steps lane and
+      // lane + 64; a step whose edge occurs at no later step of the segment owns that edge and sums
+      // its contributions in descending step order
+      {
+        const int len = t1 - t0;
+        const int ra = lane, rb = lane + WAVE;
+        const int ea = ra < len ? ts[ra].x : -1, eb = rb < len ? ts[rb].x : -1;
+        float sa = 0.0f, sb = 0.0f;
+        bool oa = ea >= 0, ob = eb >= 0;
+        for (int q = len - 1; q >= 0; --q) {
+          const int eq = ts[q].x;
+          const float vq = th[q].w;
+          if (eq == ea) {
+            if (q > ra) oa = false;
+            else sa = __fadd_rn(sa, vq);
+          }
+          if (eq == eb) {
+            if (q > rb) ob = false;
+            else sb = __fadd_rn(sb, vq);
+          }
+        }
+        if (oa) gp[ea] = __fadd_rn(gp[ea], sa);
+        if (ob) gp[eb] = __fadd_rn(gp[eb], sb);
+        wave_sync();
+      }
     }
     float* gl = U.grad_llr + (size_t)f * N;
-    float* gp = U.gw_part + (size_t)f * E;
     if (ok) {
       copy_out(Lh, gl, N);
-      copy_out(gw, gp, E);
     } else {
       fill_row(gl, N, __builtin_nanf(""));
       fill_row(gp, E, __builtin_nanf(""));
