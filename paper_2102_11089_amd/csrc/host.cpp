@@ -173,11 +173,9 @@ void unroll_layout(const ldpc_code* c, int K, UnrollParams& U) {
   U.lds_fwd = o;
   U.off_ch = o; o = align16(o + c->E * 4);
   U.off_Lh = o; o = align16(o + c->N * 4);
-  int ts = 1;
-  while (ts < c->max_dc) ts <<= 1;
-  U.tstride = ts;
-  U.off_tape = o; o = align16(o + K * ts * 8);
-  U.off_tape_hdr = o; o = align16(o + K * 32);
+  U.tstride = c->max_dc;  // tape row: the inputs of one check
+  U.off_tape = o; o = align16(o + K * U.tstride * 8);
+  U.off_tape_hdr = o; o = align16(o + K * 16);  // (p, c_old, dw) per step
   U.lds_bwd = o;
 }
 

@@ -186,11 +186,10 @@ __global__ __launch_bounds__(WAVE) void k_unroll_bwd(DevCode H, UnrollParams U) 
   float* L = reinterpret_cast<float*>(lds + U.off_L);
   float* ch = reinterpret_cast<float*>(lds + U.off_ch);
   float* Lh = reinterpret_cast<float*>(lds + U.off_Lh);
-  const int TS = U.tstride;  // power of two >= largest row degree
+  const int TS = U.tstride;  // largest row degree
   float* tv = reinterpret_cast<float*>(lds + U.off_tape);          // [K][TS] row inputs
   int* tj = reinterpret_cast<int*>(lds + U.off_tape) + U.ckpt_every * TS;  // [K][TS] their VNs
-  float4* th = reinterpret_cast<float4*>(lds + U.off_tape_hdr);      // [K] (p, c_old, w, dw)
-  int4* ts = reinterpret_cast<int4*>(lds + U.off_tape_hdr) + U.ckpt_every;  // [K] (e, rs, dcx, n)
+  float4* th = reinterpret_cast<float4*>(lds + U.off_tape_hdr);      // [K] (p, c_old, dw, -)
   const int lane = threadIdx.x;
   const int E = H.E, N = H.N, T = U.T, K = U.ckpt_every;
   const int nseg = (T + K - 1) / K;
@@ -211,36 +210,33 @@ __global__ __launch_bounds__(WAVE) void k_unroll_bwd(DevCode H, UnrollParams U) 
       for (int i = lane; i < E; i += WAVE) c2v[i] = ck[i];
       for (int i = lane; i < N; i += WAVE) L[i] = ck[E + i];
       wave_sync();
+      // the segment's step descriptors stay in registers for both sweeps: steps t0 + lane and
+      // t0 + 64 + lane (a segment has at most 128 steps)
+      const int len = t1 - t0;
+      StepBlk blka{}, blkb{};
+      ok = load_steps(H, tr, U.w, t0, min(WAVE, len), blka);
+      if (ok && len > WAVE) ok = load_steps(H, tr, U.w, t0 + WAVE, len - WAVE, blkb);
+      if (!ok) break;
+      auto seg_step = [&](int r) -> Step { return r < WAVE ? step_of(blka, r) : step_of(blkb, r - WAVE); };
       // recompute the segment, recording the tape
-      for (int b0 = t0; b0 < t1 && ok; b0 += WAVE) {
-        const int cnt = min(WAVE, t1 - b0);
-        StepBlk blk;
-        ok = load_steps(H, tr, U.w, b0, cnt, blk);
-        if (!ok) break;
-        for (int i = 0; i < cnt; ++i) {
-          const Step s = step_of(blk, i);
-          float v, p, c;
-          int j;
-          fwd_step(H, c2v, L, s, v, j, p, c);
-          const int r = b0 + i - t0;
-          if (lane < TS) {
-            tv[r * TS + lane] = v;
-            tj[r * TS + lane] = j;
-          }
-          if (lane == 0) {
-            th[r] = make_float4(p, c, s.w, 0.0f);
-            ts[r] = make_int4(s.e, s.rs, s.dc | (s.x << 8), s.n);
-          }
+      for (int r = 0; r < len; ++r) {
+        const Step s = seg_step(r);
+        float v, p, c;
+        int j;
+        fwd_step(H, c2v, L, s, v, j, p, c);
+        if (lane < TS) {
+          tv[r * TS + lane] = v;
+          tj[r * TS + lane] = j;
         }
+        if (lane == 0) th[r] = make_float4(p, c, 0.0f, 0.0f);
       }
       wave_sync();
-      if (!ok) break;
       // reverse sweep over the segment
-      for (int r = t1 - t0 - 1; r >= 0; --r) {
+      for (int r = len - 1; r >= 0; --r) {
         const float4 hd = th[r];
-        const int4 si = ts[r];
-        const int e = si.x, dc = si.z & 0xFF, x = si.z >> 8, n = si.w;
-        const float p = hd.x, cold = hd.y, w = hd.z;
+        const Step si = seg_step(r);
+        const int e = si.e, dc = si.dc, x = si.x, n = si.n;
+        const float p = hd.x, cold = hd.y, w = si.w;
         const float sadj = __fadd_rn(ch[e], Lh[n]);
         const float ws = __fmul_rn(w, sadj);
         float v = 0.0f;
@@ -276,10 +272,10 @@ __global__ __launch_bounds__(WAVE) void k_unroll_bwd(DevCode H, UnrollParams U) 
         if (on) {
           const float a = __fmul_rn(ws, g);
           Lh[j] = __fadd_rn(Lh[j], a);
-          ch[si.y + lane] = __fsub_rn(ch[si.y + lane], a);
+          ch[si.rs + lane] = __fsub_rn(ch[si.rs + lane], a);
         }
         if (lane == x) {
-          th[r].w = __fmul_rn(sadj, __fsub_rn(p, cold));  // this step's d loss / d w_e
+          th[r].z = __fmul_rn(sadj, __fsub_rn(p, cold));  // this step's d loss / d w_e
           ch[e] = __fsub_rn(ch[e], ws);
         }
         wave_sync();
@@ -288,14 +284,13 @@ __global__ __launch_bounds__(WAVE) void k_unroll_bwd(DevCode H, UnrollParams U) 
       // lane + 64; a step whose edge occurs at no later step of the segment owns that edge and sums
       // its contributions in descending step order
       {
-        const int len = t1 - t0;
         const int ra = lane, rb = lane + WAVE;
-        const int ea = ra < len ? ts[ra].x : -1, eb = rb < len ? ts[rb].x : -1;
+        const int ea = ra < len ? blka.e : -1, eb = rb < len ? blkb.e : -1;
         float sa = 0.0f, sb = 0.0f;
         bool oa = ea >= 0, ob = eb >= 0;
         for (int q = len - 1; q >= 0; --q) {
-          const int eq = ts[q].x;
-          const float vq = th[q].w;
+          const int eq = seg_step(q).e;
+          const float vq = th[q].z;
           if (eq == ea) {
             if (q > ra) oa = false;
             else sa = __fadd_rn(sa, vq);
