@@ -99,14 +99,20 @@ __device__ __forceinline__ float row_pre(float v, bool on) {
   return neg ? -mag : mag;
 }
 
-// one forward step; returns (for the tape) the lane's row input v, its VN j, and pre_e / c2v_e
-__device__ __forceinline__ void fwd_step(const DevCode& H, float* c2v, float* L, const Step& s, float& v_out,
-                                         int& j_out, float& p_out, float& c_out) {
+// VN of the lane's position in the step's row (0 beyond the row): the one topology read of a step,
+// which depends on the schedule only, so callers request it a step ahead
+__device__ __forceinline__ int row_vn_of(const DevCode& H, const Step& s) {
   const int lane = threadIdx.x & (WAVE - 1);
-  int j = 0;
+  return lane < s.dc ? H.col[s.rs + lane] : 0;
+}
+
+// one forward step, j = row_vn_of(H, s); returns (for the tape) the lane's row input v, its VN j,
+// and pre_e / c2v_e
+__device__ __forceinline__ void fwd_step(float* c2v, float* L, const Step& s, int j, float& v_out, int& j_out,
+                                         float& p_out, float& c_out) {
+  const int lane = threadIdx.x & (WAVE - 1);
   float v = 0.0f, c = 0.0f, lj = 0.0f;
   if (lane < s.dc) {
-    j = H.col[s.rs + lane];
     c = c2v[s.rs + lane];
     lj = L[j];
     v = __fsub_rn(lj, c);
@@ -156,6 +162,8 @@ __global__ __launch_bounds__(WAVE) void k_unroll_fwd(DevCode H, UnrollParams U) 
       StepBlk blk;
       ok = load_steps(H, tr, U.w, t0, cnt, blk);
       if (!ok) break;
+      Step s = step_of(blk, 0);
+      int jn = row_vn_of(H, s);
       for (int i = 0; i < cnt; ++i) {
         const int t = t0 + i;
         if (U.ckpt && t % K == 0) {
@@ -163,9 +171,15 @@ __global__ __launch_bounds__(WAVE) void k_unroll_fwd(DevCode H, UnrollParams U) 
           copy_out(c2v, ck, E);
           copy_out(L, ck + E, N);
         }
+        const Step cur = s;
+        const int jc = jn;
+        if (i + 1 < cnt) {  // the next step's row VNs are requested before this step computes
+          s = step_of(blk, i + 1);
+          jn = row_vn_of(H, s);
+        }
         float v, p, c;
         int j;
-        fwd_step(H, c2v, L, step_of(blk, i), v, j, p, c);
+        fwd_step(c2v, L, cur, jc, v, j, p, c);
       }
     }
     float* out = U.soft_out + (size_t)f * N;
@@ -218,12 +232,15 @@ __global__ __launch_bounds__(WAVE) void k_unroll_bwd(DevCode H, UnrollParams U) 
       if (ok && len > WAVE) ok = load_steps(H, tr, U.w, t0 + WAVE, len - WAVE, blkb);
       if (!ok) break;
       auto seg_step = [&](int r) -> Step { return r < WAVE ? step_of(blka, r) : step_of(blkb, r - WAVE); };
-      // recompute the segment, recording the tape
+      // recompute the segment, recording the tape (each step's row VNs requested a step ahead)
+      int jn = row_vn_of(H, seg_step(0));
       for (int r = 0; r < len; ++r) {
         const Step s = seg_step(r);
+        const int jc = jn;
+        if (r + 1 < len) jn = row_vn_of(H, seg_step(r + 1));
         float v, p, c;
         int j;
-        fwd_step(H, c2v, L, s, v, j, p, c);
+        fwd_step(c2v, L, s, jc, v, j, p, c);
         if (lane < TS) {
           tv[r * TS + lane] = v;
           tj[r * TS + lane] = j;
