@@ -45,6 +45,24 @@ int hip_fail(hipError_t e) {
 
 int align16(int x) { return (x + 15) & ~15; }
 
+// A kernel family's dynamic-LDS limit is raised with one hipFuncSetAttribute per variant (140 for
+// the single-edge family), which costs more host time than a small decode: it is done once per
+// device and family, and again only for a larger limit.
+enum LdsFamily { FAM_BASELINE = 0, FAM_DYNAMIC, FAM_ME, FAM_BATCH, FAM_UNROLL };
+hipError_t raise_lds_limit(int family, int bytes, hipError_t (*set)(int)) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int> raised;  // (device, family) -> limit applied
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set(bytes);
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(dev, family);
+  auto it = raised.find(key);
+  if (it != raised.end() && it->second >= bytes) return hipSuccess;
+  const hipError_t e = set(bytes);
+  if (e == hipSuccess) raised[key] = bytes;
+  return e;
+}
+
 int device_lds_limit(int dev) {
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0) {
@@ -919,9 +937,9 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
 
 // Raise the kernels' dynamic-LDS limit for a plan (not a stream operation: done before capture).
 hipError_t plan_lds_limits(const DecodePlan& pl) {
-  if (pl.which == 0) return set_baseline_lds_limit(pl.lds_limit);
-  if (pl.which == 2) return set_me_lds_limit(pl.lds_limit);
-  return set_dynamic_lds_limit(pl.lds_limit);
+  if (pl.which == 0) return raise_lds_limit(FAM_BASELINE, pl.lds_limit, set_baseline_lds_limit);
+  if (pl.which == 2) return raise_lds_limit(FAM_ME, pl.lds_limit, set_me_lds_limit);
+  return raise_lds_limit(FAM_DYNAMIC, pl.lds_limit, set_dynamic_lds_limit);
 }
 
 // Enqueue a planned decode; scratch must hold pl.scratch_bytes (may be null when that is 0).
@@ -1271,7 +1289,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   for (int i = 0; i < n_codes; ++i) B.codes[i] = codes[i]->d_self;
   B.queue = reinterpret_cast<int*>(scratch);
   P.pre_global = store != STORE_LDS ? (char*)scratch + 256 : nullptr;
-  he = set_batch_lds_limit(lds_limit);
+  he = raise_lds_limit(FAM_BATCH, lds_limit, set_batch_lds_limit);
   if (he == hipSuccess) he = launch_batch(B, fixed, store, topo, grid, st);
   (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
@@ -1309,7 +1327,7 @@ int ldpc_unrolled_forward(const ldpc_code* c, const float* llr, const float* w, 
   U.llr = llr; U.w = w; U.trace = trace; U.ckpt = ckpt; U.soft_out = soft_out; U.c2v_out = c2v_out;
   const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(U.lds_fwd, 1)));
   const int grid = (int)std::min<long long>(B, (long long)device_cu_count(dev) * per_cu);
-  hipError_t he = set_unroll_lds_limit(lds_limit);
+  hipError_t he = raise_lds_limit(FAM_UNROLL, lds_limit, set_unroll_lds_limit);
   if (he == hipSuccess) he = launch_unroll_fwd(c->dev, U, grid, (hipStream_t)stream);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
 }
@@ -1339,7 +1357,7 @@ int ldpc_unrolled_backward(const ldpc_code* c, const float* w, const int32_t* tr
   float* chunks = reinterpret_cast<float*>((char*)scratch + part_bytes);
   const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(U.lds_bwd, 1)));
   const int grid = (int)std::max<long long>(1, std::min<long long>(B, (long long)device_cu_count(dev) * per_cu));
-  he = set_unroll_lds_limit(lds_limit);
+  he = raise_lds_limit(FAM_UNROLL, lds_limit, set_unroll_lds_limit);
   if (he == hipSuccess) he = launch_unroll_bwd(c->dev, U, grid, chunks, nch, chunk, grad_w, st);
   (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
