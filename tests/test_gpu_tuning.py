@@ -126,3 +126,24 @@ def test_describe_plan_follows_the_knobs(gpu):
     assert fl["kernel"] == 0 and fl["grid"] == 100 and fl["persistent"] == 0
     with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
         gpu.describe_plan(h, 0, k, a)
+
+
+def test_describe_plan_lmd_storage_rule(gpu):
+    """The residual LMD schedules read the check keys only for their first choice and keep them in
+    global memory for more resident frames; LMD-CIRBP and CIRBP keep them in LDS (large batch on
+    the BG1-shaped Z=52 code); ME-LMD-CIRBP plans like ME-CIRBP."""
+    code = S.workload_code("c1")
+    h = gpu.Code(code)
+    a = gpu.SPA_F32
+    plans = {k: gpu.describe_plan(h, 65536, k, a) for k in (gpu.CIRBP, gpu.LMD_CIRBP, gpu.LMDRBP, gpu.SLMDRBP)}
+    say(f"[plan c1 65536 lmd] {plans}")
+    assert plans[gpu.LMDRBP]["storage"] == gpu.STORE_GLOBAL_STATE
+    assert plans[gpu.SLMDRBP]["storage"] == gpu.STORE_GLOBAL_STATE
+    assert plans[gpu.LMD_CIRBP]["storage"] != gpu.STORE_GLOBAL_STATE
+    assert plans[gpu.CIRBP]["storage"] != gpu.STORE_GLOBAL_STATE
+    fpc = lambda d: d["frames_per_workgroup"] * d["workgroups_per_cu"]
+    assert fpc(plans[gpu.LMDRBP]) > fpc(plans[gpu.LMD_CIRBP])
+    c3 = gpu.Code(S.workload_code("c3"))
+    me = gpu.describe_plan(c3, 2048, gpu.ME_CIRBP, a, n_p=32, n_g=16)
+    mel = gpu.describe_plan(c3, 2048, gpu.ME_LMD_CIRBP, a, n_p=32, n_g=16)
+    assert me["kernel"] == mel["kernel"] == 2 and me["storage"] == mel["storage"] and me["grid"] == mel["grid"]
