@@ -304,3 +304,23 @@ def test_me_schedules_with_more_vns_per_step_than_the_code_has(gpu):
         np.testing.assert_array_equal(np_(g.trace), ref.trace)
         np.testing.assert_array_equal(np_(g.updates_used), ref.updates_used)
         np.testing.assert_array_equal(np_(g.steps_used), ref.steps_used)
+
+
+def test_schedule_arguments_are_checked(gpu):
+    """Unknown schedules and out-of-range multi-edge parameters are rejected with LDPC_EINVAL before
+    anything is launched; the LMD schedules take no multi-edge parameters."""
+    code = S.workload_code("c0")
+    h = gpu.Code(code)
+    t = torch.zeros((2, code.N), device="cuda")
+    for kind in (-1, 10, 42):
+        with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+            gpu.decode(h, t, kind, gpu.SPA_F32, max_updates=10)
+    for kw in (dict(n_p=0), dict(n_p=65), dict(n_g=0), dict(n_g=65536), dict(fill=2)):
+        with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+            gpu.decode(h, t, gpu.ME_LMD_CIRBP, gpu.SPA_F32, max_updates=10, **kw)
+    for kind in (gpu.LMDRBP, gpu.SLMDRBP, gpu.LMD_CIRBP):  # n_p / n_g are ignored here
+        r = gpu.decode(h, t, kind, gpu.SPA_F32, max_updates=10, n_p=0, n_g=0)
+        torch.cuda.synchronize()
+        assert r.updates_used.shape == (2,)
+    with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
+        gpu.set_tuning(h, 10, gpu.SPA_F32, storage=gpu.STORE_LDS)
