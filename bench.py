@@ -268,7 +268,8 @@ def bench_lmd(args, ldpc, S, dev):
 def bench_ci(args, ldpc, S, dev):
     """CI-metric analysis (Sec. III-A, Properties 1-2, Appendix A; Fig. 2's gamma sweep):
     J(gamma) and F(gamma) measured from GPU flooding decodes of a girth-6 (4,8)-regular QC code
-    (n = 4000: the flooding kernel keeps the frame's messages in LDS) beside the GA-DE model, and CIRBP's FER against gamma on the BG1-shaped Z=52 code."""
+    (n = 4000: the flooding kernel keeps the frame's messages in LDS) and of the BG1-shaped and
+    (3,6) workload codes, beside the GA-DE model (irregular recursion for their degree profiles), and CIRBP's FER against gamma on the BG1-shaped Z=52 code."""
     import torch
     from paper_2102_11089_amd import ci_analysis as C
     stream = torch.cuda.Stream(device=dev)
@@ -290,12 +291,33 @@ def bench_ci(args, ldpc, S, dev):
             torch.cuda.synchronize()
             e = C.empirical(L.cpu().numpy(), Lt.cpu().numpy(), gs)
             ml, mlt = C.ga_totals(4, 8, C.channel_mean(eb, code.design_rate), it)
-            jrows.append({"ebn0": eb, "iteration": it, "gamma": gs,
+            jrows.append({"code": "qc48", "ebn0": eb, "iteration": it, "gamma": gs,
                           "J_decoded": [round(float(x), 5) for x in e["J"]],
                           "J_ga_de": [round(float(x), 5) for x in C.ga_j(gs, ml, mlt)],
                           "F_decoded": [round(float(x), 5) for x in e["F"]],
                           "incorrect_with_D_ge_gamma": [int(x) for x in e["n_incorrect"]]})
             print(f"[ci] J/F Eb/N0 {eb} iteration {it}", file=sys.stderr, flush=True)
+    # the workload codes themselves: decoded J/F beside the GA-DE model of their degree profiles
+    for name, eb, frames in (("c1", 1.25, 4096), ("c0", 2.0, 32768)):
+        cw_code = S.workload_code(name)
+        hw = ldpc.Code(cw_code)
+        node, lam, rho = C.degree_profile(cw_code)
+        s2 = S.sigma2_from_ebn0(eb, cw_code.design_rate)
+        llr = (2.0 / s2) * (1.0 + float(np.sqrt(s2)) * torch.randn((frames, cw_code.N), generator=g, device=dev))
+        mu0 = C.channel_mean(eb, cw_code.design_rate)
+        tmean = np.concatenate([[0.0], C.ga_de_irregular(lam, rho, mu0, 3)])
+        for it in (1, 2, 3):
+            with torch.cuda.stream(stream):
+                L, Lt = C.flooding_states(ldpc, hw, llr, it, stream=stream)
+            torch.cuda.synchronize()
+            e = C.empirical(L.cpu().numpy(), Lt.cpu().numpy(), gs)
+            jrows.append({"code": name, "ebn0": eb, "iteration": it, "gamma": gs,
+                          "J_decoded": [round(float(x), 5) for x in e["J"]],
+                          "J_ga_de": [round(float(x), 5) for x in C.ga_j_mixture(gs, node, mu0, tmean[it - 1],
+                                                                                   tmean[it])],
+                          "F_decoded": [round(float(x), 5) for x in e["F"]],
+                          "incorrect_with_D_ge_gamma": [int(x) for x in e["n_incorrect"]]})
+            print(f"[ci] J/F {name} Eb/N0 {eb} iteration {it}", file=sys.stderr, flush=True)
     t_j = time.perf_counter() - t0
     code1 = S.workload_code("c1")
     h1 = ldpc.Code(code1)
@@ -321,7 +343,9 @@ def bench_ci(args, ldpc, S, dev):
            "value": None, "unit": None, "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None,
            "higher_is_better": None, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "J/F: (4,8)-regular girth-6 QC code n=4000 (Z=500), all-zero codeword, "
-                                  f"{B} frames per point, flooding iterations 1-3, Eb/N0 1.5/2.0/2.5 dB; gamma sweep: "
+                                  f"{B} frames per point, flooding iterations 1-3, Eb/N0 1.5/2.0/2.5 dB (GA-DE of the "
+                                  "ensemble); the BG1-shaped Z=52 code at 1.25 dB (4096 frames) and the (3,6) n=96 code "
+                                  "at 2 dB (32768 frames) beside the GA-DE of their degree profiles; gamma sweep: "
                                   f"BG1-shaped Z=52, {F1} random codewords per point, CIRBP caps 1E and 3E"},
            "j_f": jrows, "j_f_seconds": round(t_j, 3), "gamma_sweep": srows}
     print(json.dumps(out), flush=True)

@@ -100,6 +100,47 @@ def ga_de(dv: int, dc: int, mu0: float, iters: int) -> np.ndarray:
     return np.array(out)
 
 
+def degree_profile(code):
+    """(VN degrees and their node fractions, edge-perspective VN and CN degree distributions
+    lambda_i and rho_j) of a code: lambda_i / rho_j = fraction of edges at VNs / CNs of degree i / j."""
+    dv = np.bincount(code.col, minlength=code.N)
+    dc = np.diff(code.row_ptr)
+    E = float(code.E)
+    vd, vn = np.unique(dv, return_counts=True)
+    lam = {int(d): float(c * d) / E for d, c in zip(vd, vn)}
+    cd, cn = np.unique(dc, return_counts=True)
+    rho = {int(d): float(c * d) / E for d, c in zip(cd, cn)}
+    return {int(d): float(c) / code.N for d, c in zip(vd, vn)}, lam, rho
+
+
+def ga_de_irregular(lam: dict, rho: dict, mu0: float, iters: int) -> np.ndarray:
+    """Mean C2V message t_l after iterations 1..iters for an irregular ensemble (Chung, Richardson,
+    Urbanke 2001): t_l = sum_j rho_j Phi^-1(1 - [1 - sum_i lambda_i Phi(mu_0 + (i - 1) t_{l-1})]^(j-1)),
+    t_0 = 0.  For a single VN and CN degree it is the regular recursion of Appendix A."""
+    t = 0.0
+    out = []
+    for _ in range(iters):
+        inner = sum(l * phi(mu0 + (i - 1) * t) for i, l in lam.items())
+        t = sum(r * phi_inv(-math.expm1((j - 1) * math.log1p(-inner))) for j, r in rho.items())
+        out.append(t)
+    return np.array(out)
+
+
+def ga_j_mixture(gammas: Sequence[float], node_frac: dict, mu0: float, t_prev: float, t_cur: float) -> np.ndarray:
+    """J(gamma) when VNs of degree d (node fraction w_d) have L ~ N(mu_0 + d t_prev, 2 (...)) and
+    Lt - L ~ N(d (t_cur - t_prev), 2 (...)): the correct and incorrect parts are summed over the
+    degrees before the ratio is taken."""
+    num = np.zeros(len(gammas))
+    den = np.zeros(len(gammas))
+    for d, w in node_frac.items():
+        ml, mlt = mu0 + d * t_prev, mu0 + d * t_cur
+        n_d, d_d = _ga_parts(gammas, ml, mlt)
+        num += w * n_d
+        den += w * d_d
+    with np.errstate(divide="ignore"):
+        return num / den
+
+
 def ga_totals(dv: int, dc: int, mu0: float, iteration: int):
     """(mu_L, mu_Lt) at flooding iteration l >= 1: the totals after l - 1 iterations (the current
     ones) and after l (what the iteration's precomputed messages give)."""
@@ -127,22 +168,31 @@ def ga_pr_d_given_l(gamma: float, l, mu_dl: float):
     return 1.0 - _q((a - l - mu_dl) / s) + _q((b - l - mu_dl) / s)
 
 
-def ga_j(gammas: Sequence[float], mu_l: float, mu_lt: float) -> np.ndarray:
-    """J(gamma) of the Gaussian model: the ratio of Pr(correct, D >= gamma) and
-    Pr(incorrect, D >= gamma), each an integral over L ~ N(mu_L, 2 mu_L)."""
+def _ga_parts(gammas: Sequence[float], mu_l: float, mu_lt: float):
+    """Pr(correct, D >= gamma) and Pr(incorrect, D >= gamma) of the Gaussian model, each an
+    integral over L ~ N(mu_L, 2 mu_L)."""
     mu_dl = mu_lt - mu_l
     if not mu_dl > 0.0:
         raise ValueError("the model needs mu_Lt > mu_L")
     sl = math.sqrt(2.0 * mu_l)
     dens = lambda l: math.exp(-((l - mu_l) ** 2) / (4.0 * mu_l)) / math.sqrt(4.0 * math.pi * mu_l)
     lo, hi = mu_l - 14.0 * sl, mu_l + 14.0 * sl
-    out = []
+    num, den = [], []
     for g in gammas:
         f = lambda l: float(ga_pr_d_given_l(g, l, mu_dl)) * dens(l)
-        num, _ = integrate.quad(f, 0.0, max(hi, 1.0), limit=400, epsabs=0.0, epsrel=1e-9)
-        den, _ = integrate.quad(f, min(lo, -1.0), 0.0, limit=400, epsabs=0.0, epsrel=1e-9)
-        out.append(num / den if den > 0 else math.inf)
-    return np.array(out)
+        a, _ = integrate.quad(f, 0.0, max(hi, 1.0), limit=400, epsabs=0.0, epsrel=1e-9)
+        b, _ = integrate.quad(f, min(lo, -1.0), 0.0, limit=400, epsabs=0.0, epsrel=1e-9)
+        num.append(a)
+        den.append(b)
+    return np.array(num), np.array(den)
+
+
+def ga_j(gammas: Sequence[float], mu_l: float, mu_lt: float) -> np.ndarray:
+    """J(gamma) of the Gaussian model: the ratio of Pr(correct, D >= gamma) and
+    Pr(incorrect, D >= gamma), each an integral over L ~ N(mu_L, 2 mu_L)."""
+    num, den = _ga_parts(gammas, mu_l, mu_lt)
+    with np.errstate(divide="ignore"):
+        return np.where(den > 0, num / np.where(den > 0, den, 1.0), np.inf)
 
 
 def ga_f(gammas: Sequence[float], tau: float, mu_dl: float) -> np.ndarray:

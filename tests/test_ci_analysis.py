@@ -113,3 +113,55 @@ def test_decoded_j_follows_the_ga_model():
         ml, mlt = C.ga_totals(4, 8, mu0, it)
         np.testing.assert_allclose(e["J"], C.ga_j(gs, ml, mlt), rtol=tol)
         assert np.all(e["F"] > 1) and np.all(np.diff(e["F"]) > 0)
+
+
+def test_irregular_ga_reduces_to_the_regular_recursion():
+    mu0 = C.channel_mean(2.0, 0.5)
+    np.testing.assert_array_equal(C.ga_de_irregular({4: 1.0}, {8: 1.0}, mu0, 6), C.ga_de(4, 8, mu0, 6))
+    gs = [0.0, 0.1, 0.3]
+    ml, mlt = C.ga_totals(4, 8, mu0, 2)
+    t = C.ga_de(4, 8, mu0, 2)
+    np.testing.assert_allclose(C.ga_j_mixture(gs, {4: 1.0}, mu0, t[0], t[1]), C.ga_j(gs, ml, mlt), rtol=1e-12)
+
+
+def test_degree_mixture_j_matches_monte_carlo():
+    """The degree-mixture J(gamma) equals a Monte Carlo draw of the same model (VN degree drawn by
+    its node fraction, then L and Lt - L from that degree's Gaussians)."""
+    node = {1: 0.5, 3: 0.3, 9: 0.2}
+    mu0, tp, tc = 2.0, 0.4, 0.9
+    gs = [0.0, 0.05, 0.1, 0.2, 0.3]
+    rng = np.random.default_rng(4)
+    n = 3_000_000
+    d = rng.choice(list(node), p=list(node.values()), size=n)
+    ml, md = mu0 + d * tp, d * (tc - tp)
+    L = rng.normal(ml, np.sqrt(2 * ml))
+    Lt = L + rng.normal(md, np.sqrt(2 * md))
+    mc = C.empirical(L, Lt, gs)["J"]
+    np.testing.assert_allclose(C.ga_j_mixture(gs, node, mu0, tp, tc), mc, rtol=0.03)
+
+
+def test_degree_profile_of_a_known_code():
+    code = S.code_from_rows(2, 4, [[0, 1, 2], [1, 2, 3]])
+    node, lam, rho = C.degree_profile(code)
+    assert node == {1: 0.5, 2: 0.5} and lam == {1: 2 / 6, 2: 4 / 6} and rho == {3: 1.0}
+
+
+def test_decoded_j_on_the_workload_codes():
+    """Sec. III-A on the workload codes: on the BG1-shaped Z=52 code at 1.25 dB, J(gamma) measured
+    from the oracle's flooding decodes follows the GA-DE model of its degree profile (Chung et al.'s
+    irregular recursion, J mixed over VN degrees) for the first two iterations; on both c1 and the
+    (3,6) n=96 code J decreases in gamma (Property 1) and F exceeds 1 and grows (Property 2)."""
+    gs = [0.0, 0.05, 0.1, 0.2, 0.3]
+    for name, eb, frames in (("c1", 1.25, 200), ("c0", 2.0, 3000)):
+        code = S.workload_code(name)
+        node, lam, rho = C.degree_profile(code)
+        cw, llr = S.frames(code, frames, eb, 42, zero_codeword=True)
+        mu0 = C.channel_mean(eb, code.design_rate)
+        t = np.concatenate([[0.0], C.ga_de_irregular(lam, rho, mu0, 2)])
+        for it in (1, 2):
+            a = O.decode(code, llr, O.FLOODING, O.SPA, max_updates=(it - 1) * code.E, check_every=0, threads=8)
+            b = O.decode(code, llr, O.FLOODING, O.SPA, max_updates=it * code.E, check_every=0, threads=8)
+            e = C.empirical(a.llr_out, b.llr_out, gs)
+            assert np.all(np.diff(e["J"]) < 0) and np.all(e["F"] > 1) and np.all(np.diff(e["F"]) > 0), (name, it)
+            if name == "c1":
+                np.testing.assert_allclose(e["J"], C.ga_j_mixture(gs, node, mu0, t[it - 1], t[it]), rtol=0.06)
