@@ -237,8 +237,9 @@ int ldpc_unrolled_backward(const ldpc_code* code, const float* w, const int32_t*
 #define LDPC_STORE_GLOBAL_FRAME 5 /* the whole frame (messages, precomputed and total LLRs, CIs)
                                      in a global slot; only keys and trees stay in LDS: the most
                                      frames per CU                                                */
-#define LDPC_STORE_GLOBAL_REC 6   /* as GLOBAL_FRAME, with the precomputed total, CI and total of
-                                     a VN in one 16-byte record (single-edge schedules only)      */
+#define LDPC_STORE_GLOBAL_REC 6   /* as GLOBAL_FRAME, with the precomputed total and the total of
+                                     a VN in one 8-byte record (the CI is evaluated from it;
+                                     single-edge schedules only)                                  */
 #define LDPC_STORE_GLOBAL_STATE 7 /* as GLOBAL_REC, with the check keys in the slot too: LDS holds
                                      only block maxima and small bookkeeping (single-edge only)   */
 #define LDPC_TOPO_AUTO 0    /* quasi-cyclic tables, else LDS copies, else global arrays       */

@@ -37,6 +37,15 @@ def test_header_constants_match_binding():
     assert int(consts["LDPC_CIRBP"]) == ldpc.CIRBP
     assert int(consts["LDPC_ME_CIRBP"]) == ldpc.ME_CIRBP
     assert int(consts["LDPC_REPLAY"]) == ldpc.REPLAY
+    assert int(consts["LDPC_LMDRBP"]) == ldpc.LMDRBP
+    assert int(consts["LDPC_SLMDRBP"]) == ldpc.SLMDRBP
+    assert int(consts["LDPC_LMD_CIRBP"]) == ldpc.LMD_CIRBP
+    assert int(consts["LDPC_ME_LMD_CIRBP"]) == ldpc.ME_LMD_CIRBP
+    for name in ("AUTO", "LDS", "GLOBAL", "GLOBAL_ALL", "GLOBAL_LT", "GLOBAL_FRAME", "GLOBAL_REC", "GLOBAL_STATE"):
+        assert int(consts["LDPC_STORE_" + name]) == getattr(ldpc, "STORE_" + name)
+    for name in ("AUTO", "GLOBAL", "LDS", "QC"):
+        assert int(consts["LDPC_TOPO_" + name]) == getattr(ldpc, "TOPO_" + name)
+    assert int(consts["LDPC_FILL_LOWEST"]) == ldpc.FILL_LOWEST and int(consts["LDPC_FILL_HASH"]) == ldpc.FILL_HASH
     assert int(consts["LDPC_SPA_F32"]) == ldpc.SPA_F32
     assert int(consts["LDPC_MS_FIX"]) == ldpc.MS_FIX
     for k, v in ldpc.ERRORS.items():
