@@ -38,7 +38,8 @@ __device__ __forceinline__ size_t frame_slot(const DynParams& P) {
 // (Lt), totals (L) and CIs (D): all in LDS; pre in a global scratch slot; c2v and pre as
 // interleaved (c2v, pre) pairs (one load brings the two values of an edge) in a global slot; those
 // pairs followed by Lt in the slot; the whole frame in the slot (Lt, L and D as arrays, or as one
-// 16-byte record per VN).  A frame is read and written by its own wavefront only, so lanes
+// 8-byte (Lt, L) record per VN with D evaluated from it).  A frame is read and written by its own
+// wavefront only, so lanes
 // exchange values through global memory under the wavefront's program order (wave_sync).
 template <class A, int STORE, bool PAIRS = (STORE >= STORE_ALL_GLOBAL)>
 struct MsgStore {

@@ -24,7 +24,8 @@ enum Topo { TOPO_GLOBAL = 0, TOPO_LDS = 1, TOPO_QC = 2 };
 // single-edge frame storage: c2v and pre in LDS; pre in a global slot; both in a global slot; both
 // and the precomputed totals Lt in a global slot; the whole frame (messages, Lt, L, D) in a global
 // slot, leaving only check keys, block maxima, syndrome bits and staging in LDS; the same with the
-// three per-VN values of a VN in one 16-byte record (one cache line per touched VN instead of three);
+// per-VN values in one 8-byte (Lt, L) record, D evaluated from it (one cache line per touched VN
+// instead of three);
 // and that with the check keys and the late-CI staging in the slot as well (LDS keeps only block
 // maxima, dirty masks, syndrome bits and the repeated-VN groups: the most frames per CU)
 enum Store {
