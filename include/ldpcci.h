@@ -297,7 +297,8 @@ int ldpc_describe_plan(const ldpc_code* code, const ldpc_schedule* s, int32_t B,
    arrays or as VN records, whole frame and check keys global) x
    topology x frames per workgroup in {auto, 4, 8} x
    frames_per_cu in {auto, 1, 2, 4, 8, 16}
-   (and block in {64, 256, 1024} for ME-CIRBP) for the dynamic schedules.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),
+   (and block in {64, 256, 1024} for ME-CIRBP) for the dynamic schedules.  A candidate whose
+   scratch memory cannot be allocated is skipped.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (replay),
    LDPC_ECAPACITY (no candidate fits), LDPC_EHIP. */
 int ldpc_autotune(const ldpc_code* code, const ldpc_schedule* s, const float* llr_in, int32_t B,
                   int64_t max_updates, int32_t reps, ldpc_tuning* best, float* best_ms, void* stream);

@@ -147,6 +147,26 @@ def _check(rc: int, what: str):
         raise RuntimeError(f"{what}: {ERRORS.get(rc, rc)} ({ldpc_strerror(rc)}), hip={load().ldpc_last_hip_error()}")
 
 
+def _need(cond: bool, msg: str):
+    if not cond:
+        raise ValueError(msg)
+
+
+def _cuda(t, name: str, dtype, cols: Optional[int] = None, rows: Optional[int] = None, device=None):
+    """``t`` as a contiguous CUDA tensor of ``dtype``; with ``cols`` (and ``rows``) given it must be
+    2-D of that width (and height).  The kernels index these buffers by the sizes passed beside
+    them, so a tensor that is smaller, strided or of another type is refused here (ValueError)."""
+    import torch
+    _need(isinstance(t, torch.Tensor) and t.is_cuda, f"{name}: a CUDA tensor is required")
+    _need(t.dtype == dtype, f"{name}: dtype {dtype} is required, got {t.dtype}")
+    if device is not None:
+        _need(t.device == device, f"{name}: must be on {device}, got {t.device}")
+    if cols is not None:
+        _need(t.dim() == 2 and t.shape[1] == cols and (rows is None or t.shape[0] == rows),
+              f"{name}: shape ({'B' if rows is None else rows}, {cols}) is required, got {tuple(t.shape)}")
+    return t.contiguous()
+
+
 def ldpc_code_from_csr(M: int, N: int, row_ptr: np.ndarray, col_idx: np.ndarray,
                        layer_ptr: Optional[np.ndarray] = None) -> int:
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
@@ -325,8 +345,7 @@ def decode(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int = 
            stream=None) -> Decoded:
     """Decode a (B, N) float32 CUDA tensor of channel LLRs; returns device tensors."""
     import torch
-    assert llr.is_cuda and llr.dtype == torch.float32 and llr.dim() == 2 and llr.shape[1] == code.N
-    llr = llr.contiguous()
+    llr = _cuda(llr, "llr", torch.float32, cols=code.N)
     B = llr.shape[0]
     dev = llr.device
     bits = torch.empty((B, code.N), dtype=torch.uint8, device=dev)
@@ -343,7 +362,8 @@ def decode(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int = 
     rep = None
     rep_len = 0
     if replay is not None:
-        rep = replay.to(device=dev, dtype=torch.int32).contiguous()
+        rep = torch.as_tensor(replay).to(device=dev, dtype=torch.int32).contiguous()
+        _need(rep.dim() == 2 and rep.shape[0] == B, f"replay: shape ({B}, T) is required, got {tuple(rep.shape)}")
         rep_len = rep.shape[1]
     ptr = lambda t: None if t is None else t.data_ptr()
     outs = ldpc_outputs(ptr(bits), ptr(llr_out), ptr(upd), ptr(steps), ptr(fall), ptr(tr), ptr(d.get("c2v")),
@@ -361,7 +381,10 @@ def decode_batch(codes, frames: np.ndarray, llr_pool, out_len: int, arith: int =
     ``llr_pool`` a float32 CUDA tensor.  Returns (bits_pool, llr_out_pool, updates_used,
     steps_used, fallbacks) as device tensors."""
     import torch
-    assert frames.dtype == FRAME_DESC
+    _need(isinstance(frames, np.ndarray) and frames.dtype == FRAME_DESC and frames.ndim == 1,
+          "frames: a 1-D numpy array of FRAME_DESC is required")
+    _need(out_len >= 0, "out_len must be >= 0")
+    llr_pool = _cuda(llr_pool, "llr_pool", torch.float32).reshape(-1)
     dev = llr_pool.device
     F = len(frames)
     fr = torch.from_numpy(np.ascontiguousarray(frames).view(np.uint8).copy()).to(dev)
@@ -391,12 +414,13 @@ def unrolled_forward(code: Code, llr, w, trace, ckpt_every: int = 32, checkpoint
                      c2v: bool = False, stream=None):
     """Damped replay of ``trace`` (B, T): returns (soft L (B, N), checkpoints or None, c2v or None)."""
     import torch
-    assert llr.is_cuda and llr.dtype == torch.float32 and llr.dim() == 2 and llr.shape[1] == code.N
-    llr = llr.contiguous()
-    w = w.to(device=llr.device, dtype=torch.float32).contiguous()
-    tr = trace.to(device=llr.device, dtype=torch.int32).contiguous()
+    llr = _cuda(llr, "llr", torch.float32, cols=code.N)
+    w = torch.as_tensor(w).to(device=llr.device, dtype=torch.float32).contiguous()
+    tr = torch.as_tensor(trace).to(device=llr.device, dtype=torch.int32).contiguous()
+    _need(tr.dim() == 2 and tr.shape[0] == llr.shape[0],
+          f"trace: shape ({llr.shape[0]}, T) is required, got {tuple(tr.shape)}")
+    _need(w.numel() == code.E, f"w: {code.E} weights are required, got {w.numel()}")
     B, T = int(tr.shape[0]), int(tr.shape[1])
-    assert B == llr.shape[0] and w.numel() == code.E
     soft = torch.empty((B, code.N), dtype=torch.float32, device=llr.device)
     ck = None
     if checkpoints:
@@ -413,11 +437,18 @@ def unrolled_forward(code: Code, llr, w, trace, ckpt_every: int = 32, checkpoint
 def unrolled_backward(code: Code, w, trace, ckpt, grad_soft, ckpt_every: int = 32, stream=None):
     """Adjoint of ``unrolled_forward``: returns (d/d llr (B, N), d/d w (E,))."""
     import torch
+    _need(isinstance(grad_soft, torch.Tensor) and grad_soft.is_cuda, "grad_soft: a CUDA tensor is required")
     dev = grad_soft.device
-    w = w.to(device=dev, dtype=torch.float32).contiguous()
-    tr = trace.to(device=dev, dtype=torch.int32).contiguous()
-    gs = grad_soft.to(dtype=torch.float32).contiguous()
+    w = torch.as_tensor(w).to(device=dev, dtype=torch.float32).contiguous()
+    tr = torch.as_tensor(trace).to(device=dev, dtype=torch.int32).contiguous()
+    _need(tr.dim() == 2, f"trace: shape (B, T) is required, got {tuple(tr.shape)}")
     B, T = int(tr.shape[0]), int(tr.shape[1])
+    gs = _cuda(grad_soft.to(dtype=torch.float32), "grad_soft", torch.float32, cols=code.N, rows=B)
+    _need(w.numel() == code.E, f"w: {code.E} weights are required, got {w.numel()}")
+    if B > 0 and T > 0:
+        need = B * ldpc_unrolled_ckpt_floats(code.handle, T, ckpt_every)
+        ckpt = _cuda(ckpt, "ckpt", torch.float32, device=dev)
+        _need(ckpt.numel() >= need, f"ckpt: {need} floats are required, got {ckpt.numel()}")
     g_llr = torch.empty((B, code.N), dtype=torch.float32, device=dev)
     g_w = torch.empty(code.E, dtype=torch.float32, device=dev)
     st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
@@ -493,7 +524,7 @@ def autotune(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int 
     """Tune the launch of one schedule on sample frames (a (B, N) float32 CUDA tensor); returns
     (knobs as a dict, best milliseconds).  The result is kept for later decodes of this code."""
     import torch
-    llr = llr.contiguous()
+    llr = _cuda(llr, "llr", torch.float32, cols=code.N)
     s = schedule(kind, arith, gamma, q_bits, frac_bits, n_p, n_g, fill, 0, check_every)
     st = (stream if stream is not None else torch.cuda.current_stream(llr.device)).cuda_stream
     t, ms = ldpc_autotune(code.handle, s, llr.data_ptr(), llr.shape[0], max_updates, reps, st)
@@ -506,7 +537,8 @@ def autotune(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int 
 def awgn_frames(codewords, B: int, sigma2: float, seed: int, point: int = 0, stream=None):
     """(B, N) float32 channel LLRs on the device from a (P, N) uint8 CUDA codeword pool."""
     import torch
-    cw = codewords.contiguous()
+    cw = _cuda(codewords, "codewords", torch.uint8)
+    _need(cw.dim() == 2, f"codewords: shape (P, N) is required, got {tuple(cw.shape)}")
     P, N = cw.shape
     llr = torch.empty((B, N), dtype=torch.float32, device=cw.device)
     st = (stream if stream is not None else torch.cuda.current_stream(cw.device)).cuda_stream
@@ -521,8 +553,9 @@ class Sweep:
     def __init__(self, code: Code, codewords, ebn0_db, rate: float, B: int, kind: int, arith: int = SPA_F32,
                  max_updates: int = 0, gamma: float = 0.1, q_bits: int = 6, frac_bits: int = 1, n_p: int = 1,
                  n_g: int = 16, fill: int = FILL_LOWEST, check_every: int = 1):
+        import torch
         self.code = code
-        self.codewords = codewords.contiguous()  # referenced by the graph
+        self.codewords = _cuda(codewords, "codewords", torch.uint8, cols=code.N)  # referenced by the graph
         self.S = len(ebn0_db)
         s = schedule(kind, arith, gamma, q_bits, frac_bits, n_p, n_g, fill, 0, check_every)
         self.handle = ldpc_sweep_create(code.handle, s, max_updates, self.codewords.data_ptr(),

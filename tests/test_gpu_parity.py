@@ -479,6 +479,42 @@ def test_batch_rejects_bad_descriptors(gpu):
     assert u[0] >= 0 and u[5] >= 0
 
 
+def test_binding_refuses_buffers_that_do_not_match_their_sizes(gpu, c0):
+    """The kernels index each buffer by the sizes passed beside it: the binding refuses, before any
+    launch, a buffer of another shape, type or device (ValueError)."""
+    code, h = c0
+    cw, llr = S.frames(code, 4, 2.0, 5)
+    t = torch.from_numpy(llr).cuda()
+    say("[binding] mismatched buffers refused on the host")
+    with pytest.raises(ValueError, match="replay"):
+        gpu.decode(h, t, gpu.REPLAY, gpu.SPA_F32, max_updates=4, replay=torch.zeros((2, 4), dtype=torch.int32))
+    for bad in (t.double(), t[:, :50], t.cpu(), t[0]):
+        with pytest.raises(ValueError, match="llr"):
+            gpu.decode(h, bad, gpu.CIRBP, gpu.SPA_F32, max_updates=4)
+    frames, pool, _, _, out_len = _mixed_batch([code], 2, 1)
+    with pytest.raises(ValueError, match="llr_pool"):
+        gpu.decode_batch([h], frames, torch.from_numpy(pool.astype(np.float64)).cuda(), out_len)
+    with pytest.raises(ValueError, match="frames"):
+        gpu.decode_batch([h], frames.view(np.uint8), torch.from_numpy(pool).cuda(), out_len)
+    with pytest.raises(ValueError, match="codewords"):
+        gpu.Sweep(h, torch.zeros((2, code.N - 1), dtype=torch.uint8, device="cuda"), [2.0], 0.5, 8, gpu.CIRBP)
+    w = torch.ones(code.E, device="cuda")
+    tr = torch.randint(0, code.E, (4, 40), dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError, match="trace"):
+        gpu.unrolled_forward(h, t, w, tr[:3], 16)
+    with pytest.raises(ValueError, match="w:"):
+        gpu.unrolled_forward(h, t, w[:-1], tr, 16)
+    soft, ck, _ = gpu.unrolled_forward(h, t, w, tr, 16)
+    gs = torch.ones((4, code.N), device="cuda")
+    with pytest.raises(ValueError, match="grad_soft"):
+        gpu.unrolled_backward(h, w, tr, ck, gs[:3], 16)
+    with pytest.raises(ValueError, match="ckpt"):
+        gpu.unrolled_backward(h, w, tr, ck[: ck.numel() // 2], gs, 16)
+    g_llr, g_w = gpu.unrolled_backward(h, w, tr, ck, gs, 16)
+    torch.cuda.synchronize()
+    assert torch.isfinite(soft).all() and torch.isfinite(g_llr).all() and torch.isfinite(g_w).all()
+
+
 @pytest.mark.parametrize("store", ["lds", "global", "all", "all_lt", "frame", "rec", "state"])
 def test_f32_storage_modes_identical(gpu, store):
     """FP32 results do not depend on where the messages live (same arithmetic, same order)."""
