@@ -527,6 +527,10 @@ def bench_unrolled(args, ldpc, S, dev):
         if it >= args.warmup:
             fwd_ms.append(ms_f)
             bwd_ms.append(ms_b)
+        ck_bytes = int(ck.numel() * 4)
+        # a training loop lets go of a step's tensors before the next step: holding the previous
+        # checkpoints (368.6 MB) across the next forward would make every other step allocate anew
+        del soft, ck, gs, g_llr, g_w
     step_ms = float(np.mean(fwd_ms)) + float(np.mean(bwd_ms))
     out = {"metric": "differentiable decoder training steps/s (forward + adjoint)", "value": round(1e3 / step_ms, 3),
            "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -537,7 +541,7 @@ def bench_unrolled(args, ldpc, S, dev):
            "forward_ms": round(float(np.mean(fwd_ms)), 3), "backward_ms": round(float(np.mean(bwd_ms)), 3),
            "replay_steps_per_s_forward": round(B * T / (np.mean(fwd_ms) / 1e3), 1),
            "replay_steps_per_s_backward": round(B * T / (np.mean(bwd_ms) / 1e3), 1),
-           "checkpoint_bytes": int(ck.numel() * 4)}
+           "checkpoint_bytes": ck_bytes}
     print(json.dumps(out), flush=True)
 
 

@@ -25,7 +25,9 @@
  *     synchronised.
  *   - The library owns only ldpc_code handles.  A handle is immutable after creation and may be
  *     shared by concurrent calls on different streams; decode calls are reentrant.  Scratch
- *     memory needed by a call is allocated and freed by the library inside the call.
+ *     memory needed by a call is allocated and freed by the library inside the call, stream-
+ *     ordered, from a memory pool of the library's own per device that keeps up to 2 GiB of
+ *     freed memory for later calls until the process ends.
  *   - Layouts are row-major and frame-contiguous: [B][N] for per-VN arrays, [B][E] for per-edge
  *     arrays, [B] for per-frame scalars.  Edge ids are canonical: the position of the nonzero
  *     (m, n) in the row-major (check-major, VN-ascending) enumeration of H.

@@ -63,6 +63,45 @@ hipError_t raise_lds_limit(int family, int bytes, hipError_t (*set)(int)) {
   return e;
 }
 
+// Stream-ordered scratch memory.  It comes from a pool of the library's own per device that keeps
+// up to kPoolKeepBytes of freed memory for the next call: the device's default pool hands freed
+// memory back to the system at every synchronization, so a caller that decodes, synchronizes and
+// decodes again would map its scratch anew each time (measured: 35 us of a 1.27 ms adjoint call).
+// The pools live until the process ends.  If a pool cannot be made, the default pool is used.
+constexpr uint64_t kPoolKeepBytes = 2ull << 30;
+
+hipMemPool_t scratch_pool(int dev) {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;  // device -> pool (nullptr: creation failed)
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) return it->second;
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof props);
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool = nullptr;
+  if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+    (void)hipGetLastError();
+    pool = nullptr;
+  } else {
+    uint64_t keep = kPoolKeepBytes;
+    if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) (void)hipGetLastError();
+  }
+  pools[dev] = pool;
+  return pool;
+}
+
+hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t st) {
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) return he;
+  hipMemPool_t pool = scratch_pool(dev);
+  return pool ? hipMallocFromPoolAsync(p, bytes, pool, st) : hipMallocAsync(p, bytes, st);
+}
+
 int device_lds_limit(int dev) {
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0) {
@@ -1005,7 +1044,7 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   hipStream_t st = (hipStream_t)stream;
   void* scratch = nullptr;
   if (pl.scratch_bytes) {
-    hipError_t he = hipMallocAsync(&scratch, pl.scratch_bytes, st);
+    hipError_t he = scratch_alloc(&scratch, pl.scratch_bytes, st);
     if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
   }
   hipError_t he = enqueue_decode(c, pl, scratch, st);
@@ -1290,7 +1329,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
     pre_bytes = (size_t)grid * (size_t)P.slot_bytes;
   }
   void* scratch = nullptr;
-  hipError_t he = hipMallocAsync(&scratch, 256 + pre_bytes, st);
+  hipError_t he = scratch_alloc(&scratch, 256 + pre_bytes, st);
   if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
   for (int i = 0; i < n_codes; ++i) B.codes[i] = codes[i]->d_self;
   B.queue = reinterpret_cast<int*>(scratch);
@@ -1357,7 +1396,7 @@ int ldpc_unrolled_backward(const ldpc_code* c, const float* w, const int32_t* tr
   const int chunk = B > 0 ? (B + nch - 1) / nch : 1;
   const size_t part_bytes = (size_t)B * c->E * 4, chunk_bytes = (size_t)nch * c->E * 4;
   void* scratch = nullptr;
-  hipError_t he = hipMallocAsync(&scratch, part_bytes + chunk_bytes, st);
+  hipError_t he = scratch_alloc(&scratch, part_bytes + chunk_bytes, st);
   if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
   U.gw_part = reinterpret_cast<float*>(scratch);
   float* chunks = reinterpret_cast<float*>((char*)scratch + part_bytes);
