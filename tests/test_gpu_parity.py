@@ -194,6 +194,58 @@ def test_f32_bg1_shaped_full_size_replay(gpu):
     assert np.abs(np_(g.D) - ref.D).max() <= 1e-4
 
 
+def _syndrome_weights(code, bits):
+    """Unsatisfied checks per frame of a (B, N) uint8 CUDA tensor (torch index ops)."""
+    col = torch.from_numpy(np.asarray(code.col, dtype=np.int64)).cuda()
+    row_of = torch.from_numpy(np.repeat(np.arange(code.M), np.diff(np.asarray(code.row_ptr)))).cuda()
+    out = []
+    for s0 in range(0, bits.shape[0], 4096):
+        b = bits[s0:s0 + 4096].to(torch.int32)
+        acc = torch.zeros((b.shape[0], code.M), dtype=torch.int32, device=b.device)
+        acc.index_add_(1, row_of, b[:, col])
+        out.append((acc % 2).sum(1))
+    return torch.cat(out).cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", ["cirbp", "lmdcirbp"])
+def test_f32_benchmark_launch_sampled_frames(gpu, kind):
+    """The launch the benchmark times: 65536 frames of the Z=52 BG1-shaped code at 1.25 dB, FP32,
+    cap 3E, default plan.  Sampled frames (and the longest) give the outputs they give when decoded
+    alone, in another plan whose FP32 replay the oracle checks above; every frame that stopped
+    before the cap satisfies all parity checks."""
+    code = S.workload_code("c1")
+    ch = gpu.Code(code)
+    k = gpu.CIRBP if kind == "cirbp" else gpu.LMD_CIRBP
+    B, cap = 65536, 3 * code.E
+    say(f"[benchmark launch {kind}] plan {gpu.describe_plan(ch, B, k)}")
+    say(f"[benchmark launch {kind}] single-frame plan {gpu.describe_plan(ch, 1, k)}")
+    cw = torch.from_numpy(S.random_codewords(code, 256, 11)).cuda().repeat(B // 256, 1)
+    s2 = S.sigma2_from_ebn0(1.25, code.design_rate)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2102)
+    noise = torch.randn(tuple(cw.shape), generator=gen, device="cuda")
+    llr = (2.0 / s2) * ((1.0 - 2.0 * cw.to(torch.float32)) + float(np.sqrt(s2)) * noise)
+    del noise
+    r = gpu.decode(ch, llr, k, gpu.SPA_F32, max_updates=cap, gamma=0.1)
+    torch.cuda.synchronize()
+    upd = np_(r.updates_used)
+    say(f"[benchmark launch {kind}] mean updates {upd.mean():.0f}, at the cap {int((upd >= cap).sum())}")
+    unsat = _syndrome_weights(code, r.bits)
+    stopped = upd < cap
+    assert stopped.mean() > 0.99
+    assert (unsat[stopped] == 0).all()
+    fe = int((r.bits != cw).any(1).sum().item())
+    assert fe < B // 100, fe
+    rng = np.random.default_rng(12)
+    for f in [int(x) for x in rng.choice(B, 6, replace=False)] + [int(np.argmax(upd))]:
+        a = gpu.decode(ch, llr[f:f + 1], k, gpu.SPA_F32, max_updates=cap, gamma=0.1)
+        torch.cuda.synchronize()
+        assert int(np_(a.updates_used)[0]) == int(upd[f]), f
+        assert int(np_(a.fallbacks)[0]) == int(np_(r.fallbacks)[f]), f
+        assert torch.equal(a.bits[0], r.bits[f]), f
+        assert torch.equal(a.llr_out[0], r.llr_out[f]), f
+
+
 # ------------------------------------------------------------------------------------------
 # edge cases
 # ------------------------------------------------------------------------------------------
