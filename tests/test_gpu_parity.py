@@ -246,6 +246,50 @@ def test_f32_benchmark_launch_sampled_frames(gpu, kind):
         assert torch.equal(a.llr_out[0], r.llr_out[f]), f
 
 
+@pytest.fixture(scope="module")
+def c3_launch(gpu):
+    """2048 frames of the Z=128 BG1-shaped code at 1.5 dB (the multi-edge benchmark's batch size):
+    64 random codewords from the CPU generator, noise from torch's seeded device generator."""
+    code = S.workload_code("c3")
+    cw = torch.from_numpy(S.random_codewords(code, 64, 13)).cuda().repeat(32, 1)
+    s2 = S.sigma2_from_ebn0(1.5, code.design_rate)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1500)
+    noise = torch.randn(tuple(cw.shape), generator=gen, device="cuda")
+    llr = (2.0 / s2) * ((1.0 - 2.0 * cw.to(torch.float32)) + float(np.sqrt(s2)) * noise)
+    return code, gpu.Code(code), cw, llr
+
+
+@pytest.mark.parametrize("n_p", [8, 64])
+@pytest.mark.parametrize("kind", ["me", "melmd"])
+def test_f32_me_benchmark_launch_sampled_frames(gpu, c3_launch, kind, n_p):
+    """The multi-edge benchmark's launch (Z=128, 2048 frames, N_G=16, keyed fill, FP32, cap 3E):
+    sampled frames and the longest give the outputs they give when decoded alone (the fill key of
+    frame f is seed ^ f, so a frame decoded alone uses seed ^ f); every frame that stopped before
+    the cap satisfies all parity checks."""
+    code, ch, cw, llr = c3_launch
+    k = gpu.ME_CIRBP if kind == "me" else gpu.ME_LMD_CIRBP
+    B, cap, seed = llr.shape[0], 3 * code.E, 2102
+    kw = dict(max_updates=cap, gamma=0.1, n_p=n_p, n_g=16, fill=gpu.FILL_HASH)
+    say(f"[ME benchmark launch {kind} N_P={n_p}] plan {gpu.describe_plan(ch, B, k, n_p=n_p, fill=gpu.FILL_HASH)}")
+    r = gpu.decode(ch, llr, k, gpu.SPA_F32, seed=seed, **kw)
+    torch.cuda.synchronize()
+    upd, steps = np_(r.updates_used), np_(r.steps_used)
+    say(f"[ME benchmark launch {kind} N_P={n_p}] mean steps {steps.mean():.0f}, at the cap {int((upd >= cap).sum())}")
+    unsat = _syndrome_weights(code, r.bits)
+    stopped = upd < cap
+    assert stopped.mean() > 0.98
+    assert (unsat[stopped] == 0).all()
+    rng = np.random.default_rng(14 + n_p)
+    for f in [int(x) for x in rng.choice(B, 4, replace=False)] + [int(np.argmax(steps))]:
+        a = gpu.decode(ch, llr[f:f + 1], k, gpu.SPA_F32, seed=seed ^ f, **kw)
+        torch.cuda.synchronize()
+        assert int(np_(a.updates_used)[0]) == int(upd[f]), f
+        assert int(np_(a.steps_used)[0]) == int(steps[f]), f
+        assert torch.equal(a.bits[0], r.bits[f]), f
+        assert torch.equal(a.llr_out[0], r.llr_out[f]), f
+
+
 # ------------------------------------------------------------------------------------------
 # edge cases
 # ------------------------------------------------------------------------------------------
