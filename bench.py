@@ -16,14 +16,16 @@ Prints one JSON line.  ``--sweep`` instead prints one JSON line per Eb/N0 point 
       rates 1/2, 2/3, 3/4, 5/6), schedule drawn per frame from {flooding, RBP, CIRBP}, Eb/N0 drawn
       from {1.0, 1.5, ..., 4.0} dB, FP32 and 8-bit fixed point;
   c3  ME-CIRBP (Algorithms 4-5) on the BG1-shaped code with Z = 128 (n = 8704), N_P in
-      {8, 16, 32, 64}, N_G = 16, random (keyed) fill, Eb/N0 in {1.0, 1.25, 1.5} dB: update steps
-      against FER; ME-LMD-CIRBP (Algorithm 6) on the same batches alongside;
+      {8, 16, 32, 64}, N_G = 16, random (keyed) fill, Eb/N0 in {1.0, 1.25, 1.5} dB, 32768 frames
+      per point: update steps against FER; ME-LMD-CIRBP (Algorithm 6) on the same batches alongside;
   c4  the differentiable unrolled decoder: (3,6)-regular n = 576, 4096 frames, 300 recorded CIRBP
       updates, damped replay forward with checkpoints every 32 and the adjoint;
   lmd the LMD schedules (LMD-CIRBP, LMDRBP, sLMDRBP; Sec. IV) against CIRBP on the default
       workload's code and batches;
   ci  the CI-metric analysis: J(gamma) and F(gamma) from GPU flooding decodes beside the GA-DE
-      model (Properties 1-2, Appendix A), and CIRBP's FER against gamma (Fig. 2's sweep).
+      model (Properties 1-2, Appendix A), and CIRBP's FER against gamma (Fig. 2's sweep);
+  sweep  a 13-point SNR sweep (n = 576, 4096 frames per point) captured into one hipGraph, against
+      the same generate / decode / count work launched one call at a time.
 """
 from __future__ import annotations
 
@@ -456,7 +458,7 @@ def bench_multi_edge(args, ldpc, S, dev):
     import torch
     code = S.workload_code("c3")
     h = ldpc.Code(code)
-    B = args.frames or 2048
+    B = args.frames or 32768
     stream = torch.cuda.Stream(device=dev)
     rows = []
     total_ms = 0.0
@@ -497,6 +499,69 @@ def bench_multi_edge(args, ldpc, S, dev):
            "edge_updates_per_s": round(total_upd / (total_ms / 1e3), 1),
            "me_lmd_cirbp_frames_per_s": round(lmd_frames / (lmd_ms / 1e3), 3), "points": rows}
     print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args, ldpc, S, dev):
+    """The SNR sweep captured into one hipGraph (per point: generate frames, decode, count errors)
+    against the same work launched one call at a time, at 4096 frames per point (value: frames/s
+    of the graph) and at 64 frames per point, where launch costs weigh more."""
+    import torch
+    code = S.qc_24col(24, 12, seed=5)  # 24-column QC, Z = 24: N = 576, rate 1/2
+    h = ldpc.Code(code)
+    ebn0 = [1.0 + 0.25 * i for i in range(13)]
+    rate, cap = 0.5, 3 * code.E
+    pool = torch.from_numpy(S.random_codewords(code, 256, args.seed)).to(dev)
+    stream = torch.cuda.Stream(device=dev)
+
+    def measure(B):
+        ref = pool[torch.arange(B, device=dev) % pool.shape[0]]
+        sw = ldpc.Sweep(h, pool, ebn0, rate, B, ldpc.CIRBP, max_updates=cap, gamma=0.1)
+        out = {}
+
+        def graph(k):
+            with torch.cuda.stream(stream):
+                out["graph"] = sw.run(args.seed + k, stream=stream)
+
+        def eager(k):
+            rows = []
+            with torch.cuda.stream(stream):
+                for p, e in enumerate(ebn0):
+                    llr = ldpc.awgn_frames(pool, B, S.sigma2_from_ebn0(e, rate), args.seed + k, p, stream=stream)
+                    r = ldpc.decode(h, llr, ldpc.CIRBP, max_updates=cap, gamma=0.1, stream=stream)
+                    err = (r.bits != ref).sum(dim=1)
+                    rows.append(torch.stack([(err > 0).sum(), err.sum(), r.updates_used.sum()]))
+                out["eager"] = torch.stack(rows)
+
+        for k in range(args.warmup):
+            graph(k)
+            eager(k)
+        _, g_ms = timed(graph, stream, args.steps)
+        _, e_ms = timed(eager, stream, args.steps)
+        g = out["graph"].cpu().numpy()
+        same = bool((out["eager"].cpu().numpy() == g[:, 1:]).all())  # same seed: same frames and counts
+        sw.close()
+        frames = len(ebn0) * B
+        return (frames / (np.mean(g_ms) / 1e3), frames / (np.mean(e_ms) / 1e3), float(np.mean(g_ms)),
+                float(np.mean(e_ms)), same, g)
+
+    gv, ev, gms, ems, same, g = measure(args.frames or 4096)
+    sgv, sev, sgms, sems, ssame, _ = measure(64)
+    print(json.dumps({
+        "metric": "SNR sweep decoded frames/s, one captured hipGraph per sweep", "value": round(gv, 3),
+        "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(gms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "24-column QC Z=24 (n=576, rate 1/2); 13 points Eb/N0 1.0-4.0 dB step 0.25, "
+                               "frames generated on the device per point; CIRBP gamma 0.1 FP32, cap 3E",
+                   "frames_per_point": args.frames or 4096},
+        "eager_frames_per_s": round(ev, 3), "eager_ms_per_step": round(ems, 3),
+        "graph_over_eager": round(gv / ev, 4), "counts_equal_eager": same,
+        "fer": [round(float(x), 6) for x in g[:, 1] / g[:, 0]],
+        "mean_updates": [round(float(x), 1) for x in g[:, 3] / g[:, 0]],
+        "small_batch": {"frames_per_point": 64, "graph_frames_per_s": round(sgv, 3), "graph_ms_per_step": round(sgms, 3),
+                        "eager_frames_per_s": round(sev, 3), "eager_ms_per_step": round(sems, 3),
+                        "graph_over_eager": round(sgv / sev, 4), "counts_equal_eager": ssame}}),
+        flush=True)
 
 
 def bench_unrolled(args, ldpc, S, dev):
@@ -558,7 +623,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--sweep", type=str, default="", help="comma list of Eb/N0 points: FER curves")
-    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4", "lmd", "ci"])
+    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4", "lmd", "ci", "sweep"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -576,7 +641,7 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload != "c1":
         {"c2": bench_batched, "c3": bench_multi_edge, "c4": bench_unrolled,
-         "lmd": bench_lmd, "ci": bench_ci}[args.workload](args, ldpc, S, dev)
+         "lmd": bench_lmd, "ci": bench_ci, "sweep": bench_sweep}[args.workload](args, ldpc, S, dev)
         return
 
     args.frames = args.frames or C1_FRAMES
