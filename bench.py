@@ -400,16 +400,26 @@ def bench_batched(args, ldpc, S, dev):
     frames = frames[np.lexsort((si, -E[ci], -dyn))]
     stream = torch.cuda.Stream(device=dev)
     for name, arith, q, f in (("f32", ldpc.SPA_F32, 6, 1), ("int8", ldpc.MS_FIX, 8, 2)):
-        for _ in range(args.warmup):
+        def go():
             with torch.cuda.stream(stream):
-                ldpc.decode_batch(hs, frames, llr_pool, off, arith=arith, q_bits=q, frac_bits=f, stream=stream)
+                return ldpc.decode_batch(hs, frames, llr_pool, off, arith=arith, q_bits=q, frac_bits=f,
+                                         stream=stream)
+        # the default launch policy, for comparison
+        ldpc.set_batch_tuning(clear=True)
+        for _ in range(args.warmup):
+            go()
+        _, default_ms, _ = ev_time(stream, go)
+        # the launch autotuner on every 8th descriptor (a sample of the same mix), before timing
+        sample = np.ascontiguousarray(frames[::8])
+        knobs, _ = ldpc.autotune_batch(hs, sample, llr_pool, off, arith=arith, q_bits=q, frac_bits=f, reps=1,
+                                       stream=stream)
+        print(f"[c2] {name} default launch {default_ms:.1f} ms; tuned on {len(sample)} frames: {knobs}",
+              file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            go()
         kms = []
         wall = 0.0
         for _ in range(args.steps):
-            def go():
-                with torch.cuda.stream(stream):
-                    return ldpc.decode_batch(hs, frames, llr_pool, off, arith=arith, q_bits=q, frac_bits=f,
-                                             stream=stream)
             res, ms, w = ev_time(stream, go)
             kms.append(ms)
             wall += w
@@ -447,6 +457,8 @@ def bench_batched(args, ldpc, S, dev):
                                       "Eb/N0 1.0..4.0 dB", "frames": F,
                           "arith": "sum-product FP32" if name == "f32" else "min-sum 8-bit (q=8, f=2)"},
                "edge_updates_per_s": round(tot_upd / kern_s, 1), "kernel_ms": [round(x, 3) for x in kms],
+               "launch_tuning": {"autotuned_on_frames": len(sample), "knobs": knobs,
+                                 "default_policy_frames_per_s": round(F / (default_ms / 1e3), 1)},
                "per_schedule": {k: {"frames": v[0], "fer": v[1] / max(v[0], 1), "mean_updates": v[2] / max(v[0], 1)}
                                 for k, v in per_kind.items()}}
         print(json.dumps(out), flush=True)

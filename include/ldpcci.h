@@ -182,8 +182,9 @@ typedef struct {
    llr_out_pool (device, out_len floats, nullable), updates_used / steps_used / fallbacks (device
    [F], the latter two nullable).  A descriptor with an unknown code or schedule, a negative gamma
    or cap, or an offset that does not leave room for N values in its pool is not decoded and gets
-   updates_used = -1.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (a code with VN degree > 63 or a
-   check of degree > 32), LDPC_ECAPACITY, LDPC_ENOMEM, LDPC_EHIP. */
+   updates_used = -1.  The launch shape follows ldpc_set_batch_tuning when a tuning is set.
+   Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED (a code with VN degree > 63 or a check of degree > 32),
+   LDPC_ECAPACITY, LDPC_ENOMEM, LDPC_EHIP. */
 int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
                       const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
                       uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
@@ -304,6 +305,25 @@ int ldpc_describe_plan(const ldpc_code* code, const ldpc_schedule* s, int32_t B,
    LDPC_ECAPACITY (no candidate fits), LDPC_EHIP. */
 int ldpc_autotune(const ldpc_code* code, const ldpc_schedule* s, const float* llr_in, int32_t B,
                   int64_t max_updates, int32_t reps, ldpc_tuning* best, float* best_ms, void* stream);
+
+/* Launch tuning of ldpc_decode_batch, process-wide (one frame per workgroup there, so block and
+   topology must be 0): storage (LDPC_STORE_AUTO .. LDPC_STORE_GLOBAL_REC; LDPC_STORE_GLOBAL_STATE
+   has no batched form: LDPC_EUNSUPPORTED) and a cap on resident frames per CU (0 = as many as
+   LDS allows, at most 32).  NULL restores the default policy.  ldpc_get_batch_tuning returns 1
+   and fills *out if a tuning is set, else 0.  Errors: LDPC_EINVAL. */
+int ldpc_set_batch_tuning(const ldpc_tuning* t);
+int ldpc_get_batch_tuning(ldpc_tuning* out);
+
+/* Project autotuner of the batched launch: decodes the caller's batch (arguments as for
+   ldpc_decode_batch; outputs go to scratch buffers and are discarded) under every storage x
+   frames-per-CU cap in {auto, 4, 8, 12, 16, 24}, takes the best of reps timed launches after one
+   warm-up (HIP events on stream), stores the fastest with ldpc_set_batch_tuning and returns it
+   (best, best_ms nullable).  Candidates whose state does not fit are skipped.  Blocking:
+   synchronizes stream.  Errors: LDPC_EINVAL, LDPC_ECAPACITY (no candidate fits), LDPC_ENOMEM,
+   LDPC_EHIP. */
+int ldpc_autotune_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
+                        const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
+                        int64_t out_len, int32_t reps, ldpc_tuning* best, float* best_ms, void* stream);
 
 /* Write every stored tuning to a JSON file, tagged with the current device's architecture and CU
    count; ldpc_tuning_load reads such a file back (entries of another device are ignored) and

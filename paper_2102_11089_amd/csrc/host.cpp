@@ -1246,12 +1246,31 @@ int ldpc_tuning_load(const char* path) {
   return loaded;
 }
 
-int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
-                      const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
-                      uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
-                      int64_t* steps_used, int64_t* fallbacks, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// process-wide tuning of ldpc_decode_batch (storage and frames per CU; block must be 0)
+std::mutex g_btune_mu;
+bool g_btune_set = false;
+ldpc_tuning g_btune{};
+
+int check_batch_tuning(const ldpc_tuning* t) {
+  if (!t) return LDPC_OK;
+  if (int rc = check_tuning(t)) return rc;
+  if (t->block != 0 || t->topology != LDPC_TOPO_AUTO) return LDPC_EINVAL;
+  if (t->storage == LDPC_STORE_GLOBAL_STATE) return LDPC_EUNSUPPORTED;  // no batched variant
+  return LDPC_OK;
+}
+
+// ldpc_decode_batch with an explicit tuning (nullable: the default policy)
+int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
+                       const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
+                       uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
+                       int64_t* steps_used, int64_t* fallbacks, void* stream, const ldpc_tuning* T) {
   static_assert(sizeof(ldpc_frame_desc) == sizeof(BatchFrame), "descriptor layout");
   if (!codes || n_codes < 1 || n_codes > 64 || !s || F < 0 || llr_len < 0 || out_len < 0) return LDPC_EINVAL;
+  if (int rc = check_batch_tuning(T)) return rc;
   if (F == 0) return LDPC_OK;
   if (!frames || !llr_pool || !bits_pool || !updates_used) return LDPC_EINVAL;
   if (s->arith != LDPC_SPA_F32 && s->arith != LDPC_MS_FIX) return LDPC_EINVAL;
@@ -1282,6 +1301,7 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   int store = -1, best_fit = 0;
   DynLayout Ly{};
   for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_FRAME_GLOBAL, STORE_FRAME_REC, STORE_ALL_GLOBAL_LT, STORE_ALL_GLOBAL}) {
+    if (T && T->storage != LDPC_STORE_AUTO && st != T->storage - 1) continue;  // LDPC_STORE_* = Store + 1
     DynLayout cand = dyn_layout_dims(mx, fixed, st, 1);
     if (cand.total > lds_limit) continue;
     const int fit = std::min(32, (160 * 1024) / std::max(cand.total, 1));
@@ -1319,7 +1339,8 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   B.steps_used = steps_used;
   B.fallbacks = fallbacks;
   B.max_E = mx.E;
-  const int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(Ly.total, 1)));
+  int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(Ly.total, 1)));
+  if (T && T->frames_per_cu) per_cu = std::min(per_cu, T->frames_per_cu);
   const int grid = (int)std::min<long long>(F, (long long)ncu * per_cu);
   // scratch: the work-queue counter and pre[] slots if needed
   size_t pre_bytes = 0;
@@ -1338,6 +1359,106 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   if (he == hipSuccess) he = launch_batch(B, fixed, store, topo, grid, st);
   (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
+                      const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
+                      uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
+                      int64_t* steps_used, int64_t* fallbacks, void* stream) {
+  ldpc_tuning t{};
+  bool tuned = false;
+  {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    tuned = g_btune_set;
+    t = g_btune;
+  }
+  return decode_batch_tuned(codes, n_codes, s, frames, F, llr_pool, llr_len, bits_pool, llr_out_pool, out_len,
+                            updates_used, steps_used, fallbacks, stream, tuned ? &t : nullptr);
+}
+
+int ldpc_set_batch_tuning(const ldpc_tuning* t) {
+  if (int rc = check_batch_tuning(t)) return rc;
+  std::lock_guard<std::mutex> lk(g_btune_mu);
+  g_btune_set = t != nullptr;
+  g_btune = t ? *t : ldpc_tuning{};
+  return LDPC_OK;
+}
+
+int ldpc_get_batch_tuning(ldpc_tuning* out) {
+  if (!out) return LDPC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_btune_mu);
+  *out = g_btune;
+  return g_btune_set ? 1 : 0;
+}
+
+int ldpc_autotune_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
+                        const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
+                        int64_t out_len, int32_t reps, ldpc_tuning* best, float* best_ms, void* stream) {
+  if (F < 1 || out_len < 0 || reps < 1 || reps > 100) return LDPC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  // trial outputs (discarded)
+  uint8_t* bits = nullptr;
+  int64_t* upd = nullptr;
+  hipError_t he = hipMalloc((void**)&bits, (size_t)std::max<int64_t>(out_len, 1));
+  if (he == hipSuccess) he = hipMalloc((void**)&upd, (size_t)F * sizeof(int64_t));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (he == hipSuccess) he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  float best_t = -1.0f;
+  ldpc_tuning best_c{};
+  int rc = LDPC_OK;
+  for (int store : {LDPC_STORE_AUTO, LDPC_STORE_LDS, LDPC_STORE_GLOBAL, LDPC_STORE_GLOBAL_ALL, LDPC_STORE_GLOBAL_LT,
+                    LDPC_STORE_GLOBAL_FRAME, LDPC_STORE_GLOBAL_REC}) {
+    for (int fpc : {0, 4, 8, 12, 16, 24}) {
+      if (he != hipSuccess) break;
+      const ldpc_tuning cand{0, fpc, store, LDPC_TOPO_AUTO};
+      auto run = [&]() {
+        return decode_batch_tuned(codes, n_codes, s, frames, F, llr_pool, llr_len, bits, nullptr, out_len, upd,
+                                  nullptr, nullptr, stream, &cand);
+      };
+      const int r0 = run();  // warm-up; a candidate whose state does not fit is skipped
+      if (r0 == LDPC_ECAPACITY || r0 == LDPC_ENOMEM) continue;
+      if (r0 != LDPC_OK) {
+        rc = r0;
+        break;
+      }
+      float tmin = -1.0f;
+      for (int r = 0; r < reps && he == hipSuccess && rc == LDPC_OK; ++r) {
+        he = hipEventRecord(e0, st);
+        if (he == hipSuccess) rc = run();
+        if (he == hipSuccess && rc == LDPC_OK) he = hipEventRecord(e1, st);
+        if (he == hipSuccess && rc == LDPC_OK) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess && rc == LDPC_OK) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he == hipSuccess && rc == LDPC_OK && (tmin < 0.0f || ms < tmin)) tmin = ms;
+      }
+      if (rc != LDPC_OK) break;
+      if (he == hipSuccess && tmin >= 0.0f && (best_t < 0.0f || tmin < best_t)) {
+        best_t = tmin;
+        best_c = cand;
+      }
+    }
+    if (rc != LDPC_OK || he != hipSuccess) break;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (bits) (void)hipFree(bits);
+  if (upd) (void)hipFree(upd);
+  if (he != hipSuccess) return hip_fail(he);
+  if (rc != LDPC_OK) return rc;
+  if (best_t < 0.0f) return LDPC_ECAPACITY;
+  {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    g_btune_set = true;
+    g_btune = best_c;
+  }
+  if (best) *best = best_c;
+  if (best_ms) *best_ms = best_t;
+  return LDPC_OK;
 }
 
 // ------------------------------------------------------------------------------------------

@@ -27,7 +27,8 @@ ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -
           -5: "LDPC_EUNSUPPORTED"}
 
 EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode",
-           "ldpc_decode_batch", "ldpc_describe_plan", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune", "ldpc_tuning_save",
+           "ldpc_decode_batch", "ldpc_describe_plan", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune",
+           "ldpc_set_batch_tuning", "ldpc_get_batch_tuning", "ldpc_autotune_batch", "ldpc_tuning_save",
            "ldpc_tuning_load", "ldpc_awgn_frames", "ldpc_sweep_create", "ldpc_sweep_run", "ldpc_sweep_free",
            "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
            "ldpc_strerror", "ldpc_last_hip_error")
@@ -111,6 +112,13 @@ def load(path: str = LIB_PATH):
     lib.ldpc_autotune.argtypes = [P, C.POINTER(ldpc_schedule), P, C.c_int32, C.c_int64, C.c_int32,
                                   C.POINTER(ldpc_tuning), C.POINTER(C.c_float), P]
     lib.ldpc_autotune.restype = C.c_int
+    lib.ldpc_set_batch_tuning.argtypes = [C.POINTER(ldpc_tuning)]
+    lib.ldpc_set_batch_tuning.restype = C.c_int
+    lib.ldpc_get_batch_tuning.argtypes = [C.POINTER(ldpc_tuning)]
+    lib.ldpc_get_batch_tuning.restype = C.c_int
+    lib.ldpc_autotune_batch.argtypes = [P, C.c_int32, C.POINTER(ldpc_schedule), P, C.c_int32, P, C.c_int64, C.c_int64,
+                                        C.c_int32, C.POINTER(ldpc_tuning), C.POINTER(C.c_float), P]
+    lib.ldpc_autotune_batch.restype = C.c_int
     lib.ldpc_tuning_save.argtypes = [C.c_char_p]
     lib.ldpc_tuning_save.restype = C.c_int
     lib.ldpc_tuning_load.argtypes = [C.c_char_p]
@@ -236,6 +244,28 @@ def ldpc_autotune(handle, s: ldpc_schedule, llr_ptr: int, B: int, max_updates: i
     ms = C.c_float(0.0)
     _check(load().ldpc_autotune(handle, C.byref(s), llr_ptr, B, max_updates, reps, C.byref(t), C.byref(ms), stream),
            "ldpc_autotune")
+    return t, float(ms.value)
+
+
+def ldpc_set_batch_tuning(t: Optional[ldpc_tuning]) -> None:
+    _check(load().ldpc_set_batch_tuning(None if t is None else C.byref(t)), "ldpc_set_batch_tuning")
+
+
+def ldpc_get_batch_tuning() -> Optional[ldpc_tuning]:
+    t = ldpc_tuning()
+    rc = load().ldpc_get_batch_tuning(C.byref(t))
+    if rc < 0:
+        _check(rc, "ldpc_get_batch_tuning")
+    return t if rc == 1 else None
+
+
+def ldpc_autotune_batch(handles, s: ldpc_schedule, frames_ptr: int, F: int, llr_ptr: int, llr_len: int,
+                        out_len: int, reps: int, stream: int):
+    arr = (C.c_void_p * len(handles))(*handles)
+    t = ldpc_tuning()
+    ms = C.c_float(0.0)
+    _check(load().ldpc_autotune_batch(arr, len(handles), C.byref(s), frames_ptr, F, llr_ptr, llr_len, out_len, reps,
+                                      C.byref(t), C.byref(ms), stream), "ldpc_autotune_batch")
     return t, float(ms.value)
 
 
@@ -398,6 +428,33 @@ def decode_batch(codes, frames: np.ndarray, llr_pool, out_len: int, arith: int =
     ldpc_decode_batch([c.handle for c in codes], s, fr.data_ptr(), F, llr_pool.data_ptr(), llr_pool.numel(),
                       bits.data_ptr(), llr_out.data_ptr(), out_len, upd.data_ptr(), steps.data_ptr(), fall.data_ptr(), st)
     return bits, llr_out, upd, steps, fall
+
+
+def set_batch_tuning(frames_per_cu: int = 0, storage: int = STORE_AUTO, clear: bool = False) -> None:
+    """Launch shape of later ``decode_batch`` calls (process-wide); ``clear`` restores the default."""
+    ldpc_set_batch_tuning(None if clear else ldpc_tuning(0, frames_per_cu, storage, TOPO_AUTO))
+
+
+def get_batch_tuning() -> Optional[dict]:
+    t = ldpc_get_batch_tuning()
+    return None if t is None else t.as_dict()
+
+
+def autotune_batch(codes, frames: np.ndarray, llr_pool, out_len: int, arith: int = SPA_F32, q_bits: int = 6,
+                   frac_bits: int = 1, check_every: int = 1, reps: int = 2, stream=None):
+    """Tune the batched launch on a sample batch (arguments as for ``decode_batch``); returns
+    (knobs as a dict, best milliseconds).  The result applies to later ``decode_batch`` calls."""
+    import torch
+    _need(isinstance(frames, np.ndarray) and frames.dtype == FRAME_DESC and frames.ndim == 1,
+          "frames: a 1-D numpy array of FRAME_DESC is required")
+    llr_pool = _cuda(llr_pool, "llr_pool", torch.float32).reshape(-1)
+    dev = llr_pool.device
+    fr = torch.from_numpy(np.ascontiguousarray(frames).view(np.uint8).copy()).to(dev)
+    s = schedule(0, arith, 0.0, q_bits, frac_bits, 1, 16, 0, 0, check_every)
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    t, ms = ldpc_autotune_batch([c.handle for c in codes], s, fr.data_ptr(), len(frames), llr_pool.data_ptr(),
+                                llr_pool.numel(), out_len, reps, st)
+    return t.as_dict(), ms
 
 
 # ----------------------------------------------------------------------------------------------

@@ -107,3 +107,25 @@ def test_describe_plan_rejects_bad_arguments():
     info = ldpc.ldpc_plan_info()
     assert C.sizeof(ldpc.ldpc_plan_info) == 48
     assert lib.ldpc_describe_plan(None, C.byref(s), 8, C.byref(info)) == -1
+
+
+def test_batch_tuning_validation_and_round_trip():
+    """The batched launch's tuning is validated and kept on the host (no device call)."""
+    lib = ldpc.load()
+    T = ldpc.ldpc_tuning
+    assert lib.ldpc_set_batch_tuning(C.byref(T(64, 0, 0, 0))) == -1    # block: one frame per workgroup
+    assert lib.ldpc_set_batch_tuning(C.byref(T(0, 0, 0, 1))) == -1     # topology is not a batch knob
+    assert lib.ldpc_set_batch_tuning(C.byref(T(0, 33, 0, 0))) == -1    # at most 32 frames per CU
+    assert lib.ldpc_set_batch_tuning(C.byref(T(0, 0, 9, 0))) == -1     # unknown storage
+    assert lib.ldpc_set_batch_tuning(C.byref(T(0, 0, ldpc.STORE_GLOBAL_STATE, 0))) == -5  # no batched form
+    out = T()
+    assert lib.ldpc_get_batch_tuning(None) == -1
+    try:
+        assert lib.ldpc_set_batch_tuning(C.byref(T(0, 12, ldpc.STORE_GLOBAL_REC, 0))) == 0
+        assert lib.ldpc_get_batch_tuning(C.byref(out)) == 1
+        assert (out.block, out.frames_per_cu, out.storage, out.topology) == (0, 12, ldpc.STORE_GLOBAL_REC, 0)
+    finally:
+        assert lib.ldpc_set_batch_tuning(None) == 0
+    assert lib.ldpc_get_batch_tuning(C.byref(out)) == 0
+    s = ldpc.schedule(ldpc.CIRBP)
+    assert lib.ldpc_autotune_batch(None, 1, C.byref(s), None, 0, None, 0, 0, 2, None, None, None) == -1

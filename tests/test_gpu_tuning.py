@@ -147,3 +147,53 @@ def test_describe_plan_lmd_storage_rule(gpu):
     me = gpu.describe_plan(c3, 2048, gpu.ME_CIRBP, a, n_p=32, n_g=16)
     mel = gpu.describe_plan(c3, 2048, gpu.ME_LMD_CIRBP, a, n_p=32, n_g=16)
     assert me["kernel"] == mel["kernel"] == 2 and me["storage"] == mel["storage"] and me["grid"] == mel["grid"]
+
+
+@pytest.mark.parametrize("arith", ["f32", "fix"])
+def test_batch_tuning_and_autotune_give_identical_outputs(gpu, arith):
+    """The batched launch under explicit tunings (storage, frames-per-CU cap) and under the
+    autotuner's choice gives the default launch's outputs, frame by frame."""
+    codes = [S.qc_24col(24, 12, seed=1), S.qc_24col(48, 8, seed=1), S.qc_24col(24, 4, seed=1)]
+    hs = [gpu.Code(c) for c in codes]
+    rng = np.random.default_rng(21)
+    F = 600
+    kinds = [gpu.FLOODING, gpu.LAYERED, gpu.RBP, gpu.CIRBP, gpu.LMDRBP, gpu.SLMDRBP, gpu.LMD_CIRBP]
+    frames = np.zeros(F, dtype=gpu.FRAME_DESC)
+    llrs, off = [], 0
+    for f in range(F):
+        ci = int(rng.integers(len(codes)))
+        c = codes[ci]
+        kind = kinds[int(rng.integers(len(kinds)))]
+        _, llr = S.frames(c, 1, float(rng.choice([1.5, 2.5, 3.5])), 500 + f)
+        frames[f] = (ci, kind, 0.1, 0, (20 if kind in (gpu.FLOODING, gpu.LAYERED) else 3) * c.E, off, off)
+        llrs.append(llr[0])
+        off += c.N
+    pool = torch.from_numpy(np.concatenate(llrs).astype(np.float32)).cuda()
+    a = gpu.SPA_F32 if arith == "f32" else gpu.MS_FIX
+    kw = dict(arith=a, q_bits=8, frac_bits=2)
+
+    def run():
+        bits, llr_out, upd, steps, fall = gpu.decode_batch(hs, frames, pool, off, **kw)
+        torch.cuda.synchronize()
+        return [t.cpu().numpy() for t in (bits, llr_out, upd, steps, fall)]
+
+    gpu.set_batch_tuning(clear=True)
+    base = run()
+    assert (base[2] >= 0).all()
+    try:
+        for fpc, st in ((4, gpu.STORE_AUTO), (0, gpu.STORE_LDS), (8, gpu.STORE_GLOBAL_REC), (0, gpu.STORE_GLOBAL_ALL),
+                        (2, gpu.STORE_GLOBAL_FRAME)):
+            say(f"[batch tuning {arith}] frames_per_cu={fpc} storage={st}")
+            gpu.set_batch_tuning(frames_per_cu=fpc, storage=st)
+            got = run()
+            for x, y in zip(got, base):
+                np.testing.assert_array_equal(x, y)
+        knobs, ms = gpu.autotune_batch(hs, frames, pool, off, reps=1, **kw)
+        say(f"[batch autotune {arith}] {knobs} {ms:.3f} ms")
+        assert ms > 0 and gpu.get_batch_tuning() == knobs
+        got = run()
+        for x, y in zip(got, base):
+            np.testing.assert_array_equal(x, y)
+    finally:
+        gpu.set_batch_tuning(clear=True)
+    assert gpu.get_batch_tuning() is None
