@@ -331,9 +331,10 @@ int ldpc_autotune_batch(const ldpc_code* const* codes, int32_t n_codes, const ld
                         const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
                         int64_t out_len, int32_t reps, ldpc_tuning* best, float* best_ms, void* stream);
 
-/* Write every stored tuning to a JSON file, tagged with the current device's architecture and CU
-   count; ldpc_tuning_load reads such a file back (entries of another device are ignored) and
-   returns the number loaded.  Errors: LDPC_EINVAL (path), LDPC_EHIP. */
+/* Write every stored tuning (per code, and the batched launch's) to a JSON file, tagged with the
+   current device's architecture and CU count; ldpc_tuning_load reads such a file back (entries of
+   another device are ignored) and returns the number loaded.  Errors: LDPC_EINVAL (path),
+   LDPC_EHIP. */
 int ldpc_tuning_save(const char* path);
 int ldpc_tuning_load(const char* path);
 

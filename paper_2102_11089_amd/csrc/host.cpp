@@ -1020,6 +1020,20 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, ldpc_tuning> g_tune;
 
+// process-wide tuning of ldpc_decode_batch (storage and frames per CU; block must be 0)
+std::mutex g_btune_mu;
+bool g_btune_set = false;
+ldpc_tuning g_btune{};
+
+int check_batch_tuning(const ldpc_tuning* t) {
+  if (!t) return LDPC_OK;
+  if (int rc = check_tuning(t)) return rc;
+  if (t->block != 0 || t->topology != LDPC_TOPO_AUTO) return LDPC_EINVAL;
+  if (t->storage == LDPC_STORE_GLOBAL_STATE) return LDPC_EUNSUPPORTED;  // no batched variant
+  return LDPC_OK;
+}
+
+
 bool lookup_tuning(const ldpc_code* c, int kind, int arith, ldpc_tuning& t) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(TuneKey{c->sig, kind, arith});
@@ -1192,8 +1206,16 @@ int ldpc_tuning_save(const char* path) {
   const std::string tag = device_tag(dev);
   FILE* f = std::fopen(path, "w");
   if (!f) return LDPC_EINVAL;
+  ldpc_tuning bt{};
+  bool bset = false;
+  {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    bset = g_btune_set;
+    bt = g_btune;
+  }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   std::fprintf(f, "{\"device\": \"%s\", \"entries\": [\n", tag.c_str());
+  const size_t count = g_tune.size() + (bset ? 1 : 0);
   size_t i = 0;
   for (const auto& kv : g_tune) {
     const ldpc_tuning& t = kv.second;
@@ -1201,8 +1223,10 @@ int ldpc_tuning_save(const char* path) {
                  "{\"sig\": \"%016llx\", \"kind\": %d, \"arith\": %d, \"block\": %d, \"frames_per_cu\": %d, "
                  "\"storage\": %d, \"topology\": %d}%s\n",
                  (unsigned long long)kv.first.sig, kv.first.kind, kv.first.arith, t.block, t.frames_per_cu, t.storage,
-                 t.topology, ++i < g_tune.size() ? "," : "");
+                 t.topology, ++i < count ? "," : "");
   }
+  if (bset)  // the batched launch's tuning (ldpc_set_batch_tuning)
+    std::fprintf(f, "{\"batch\": 1, \"frames_per_cu\": %d, \"storage\": %d}\n", bt.frames_per_cu, bt.storage);
   std::fprintf(f, "]}\n");
   return std::fclose(f) == 0 ? LDPC_OK : LDPC_EINVAL;
 }
@@ -1218,10 +1242,21 @@ int ldpc_tuning_load(const char* path) {
   int loaded = 0;
   bool same_device = false;
   std::vector<std::pair<TuneKey, ldpc_tuning>> rows;
+  ldpc_tuning batch{};
+  bool have_batch = false;
   while (std::fgets(line, sizeof line, f)) {
     char dtag[128];
     if (std::sscanf(line, " {\"device\": \"%127[^\"]\"", dtag) == 1) {
       same_device = tag == dtag;
+      continue;
+    }
+    int bfpc = 0, bst = 0;
+    if (std::sscanf(line, " {\"batch\": 1, \"frames_per_cu\": %d, \"storage\": %d}", &bfpc, &bst) == 2) {
+      const ldpc_tuning bt{0, bfpc, bst, LDPC_TOPO_AUTO};
+      if (check_batch_tuning(&bt) == LDPC_OK) {
+        batch = bt;
+        have_batch = true;
+      }
       continue;
     }
     unsigned long long sig = 0;
@@ -1238,6 +1273,12 @@ int ldpc_tuning_load(const char* path) {
   }
   std::fclose(f);
   if (!same_device) return 0;
+  if (have_batch) {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    g_btune_set = true;
+    g_btune = batch;
+    ++loaded;
+  }
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (auto& r : rows) {
     g_tune[r.first] = r.second;
@@ -1249,19 +1290,6 @@ int ldpc_tuning_load(const char* path) {
 }  // extern "C"
 
 namespace {
-
-// process-wide tuning of ldpc_decode_batch (storage and frames per CU; block must be 0)
-std::mutex g_btune_mu;
-bool g_btune_set = false;
-ldpc_tuning g_btune{};
-
-int check_batch_tuning(const ldpc_tuning* t) {
-  if (!t) return LDPC_OK;
-  if (int rc = check_tuning(t)) return rc;
-  if (t->block != 0 || t->topology != LDPC_TOPO_AUTO) return LDPC_EINVAL;
-  if (t->storage == LDPC_STORE_GLOBAL_STATE) return LDPC_EUNSUPPORTED;  // no batched variant
-  return LDPC_OK;
-}
 
 // ldpc_decode_batch with an explicit tuning (nullable: the default policy)
 int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,

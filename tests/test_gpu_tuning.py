@@ -77,14 +77,22 @@ def test_tuning_cache_round_trip(gpu, tmp_path):
     h = gpu.Code(code)
     gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, frames_per_cu=4, storage=gpu.STORE_GLOBAL, topology=gpu.TOPO_LDS)
     gpu.set_tuning(h, gpu.FLOODING, gpu.MS_FIX, block=128)
+    gpu.set_batch_tuning(frames_per_cu=12, storage=gpu.STORE_GLOBAL_REC)
     path = str(tmp_path / "tune.json")
     gpu.ldpc_tuning_save(path)
     doc = json.load(open(path))
-    assert doc["device"].startswith("gfx") and len(doc["entries"]) >= 2
+    assert doc["device"].startswith("gfx") and len(doc["entries"]) >= 3
+    assert {"batch": 1, "frames_per_cu": 12, "storage": gpu.STORE_GLOBAL_REC} in doc["entries"]
     gpu.set_tuning(h, gpu.CIRBP, gpu.SPA_F32, clear=True)
     gpu.set_tuning(h, gpu.FLOODING, gpu.MS_FIX, clear=True)
+    gpu.set_batch_tuning(clear=True)
     assert gpu.ldpc_get_tuning(h.handle, gpu.CIRBP, gpu.SPA_F32) is None
-    assert gpu.ldpc_tuning_load(path) >= 2
+    try:
+        assert gpu.ldpc_tuning_load(path) >= 3
+        assert gpu.get_batch_tuning() == {"block": 0, "frames_per_cu": 12, "storage": gpu.STORE_GLOBAL_REC,
+                                          "topology": 0}
+    finally:
+        gpu.set_batch_tuning(clear=True)
     t = gpu.ldpc_get_tuning(h.handle, gpu.CIRBP, gpu.SPA_F32)
     assert t.as_dict() == {"block": 0, "frames_per_cu": 4, "storage": gpu.STORE_GLOBAL, "topology": gpu.TOPO_LDS}
     assert gpu.ldpc_get_tuning(h.handle, gpu.FLOODING, gpu.MS_FIX).block == 128
