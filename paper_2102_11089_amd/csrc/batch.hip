@@ -162,8 +162,10 @@ __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
     FrameJob J;
     J.kind = d.kind;
     if constexpr (A::kFixed) {
-      const float g = roundf(d.gamma * 65534.0f);
-      J.gamma_bits = g >= 4294967295.0f ? 0xFFFFFFFFu : (uint32_t)g;
+      // gamma_q = round_half_away(gamma * 65534) in double, as for the per-code launch (the
+      // product of a float and 65534 is exact in double; gamma >= 0 here)
+      const double g = floor((double)d.gamma * 65534.0 + 0.5);
+      J.gamma_bits = g >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)g;
     } else {
       J.gamma_bits = __float_as_uint(d.gamma);
     }

@@ -5,15 +5,19 @@
 // One wavefront (64 lanes) decodes one codeword at a time; a workgroup holds one or more such
 // frames, which share the workgroup's copy of the topology (and p0 table) in LDS.  A persistent grid pulls
 // frames from a device counter (frames differ widely in length, so fixed striding would leave a
-// long tail); otherwise there is one workgroup per frame.  The frame's state lives in LDS:
-//   c2v[E], pre[E]      current and precomputed C2V messages (pre, or both as interleaved pairs,
-//                        may live in a global scratch slot per workgroup instead),
-//   L[N], Lt[N]         total and precomputed total LLRs,
-//   D[N]                CI of every VN as key bits,
+// long tail); otherwise there is one workgroup per frame.  A frame's state is
+//   c2v[E], pre[E]      current and precomputed C2V messages (separate arrays, or interleaved pairs),
+//   L[N], Lt[N]         total and precomputed total LLRs (separate arrays, or one 8-byte (Lt, L)
+//                        record per VN),
+//   D[N]                CI of every VN as key bits (not stored with the records: evaluated from them),
 //   ckey[M]             per check: max over its edges of (residual, lowest edge id),
 //   dblk[], cblk[]      max over blocks of 64 VNs / 64 checks (two-level max trees),
 //   syn[M]              syndrome bits of the current hard decisions,
 //   topology            CSR/CSC copies (small codes) or quasi-cyclic base tables.
+// The storage mode (Store) places it: everything in LDS for small codes, or, from the messages up
+// to the whole frame and the check keys, in a global slot per frame, with the block maxima,
+// masks, syndrome bits and topology left in LDS.  The planner picks the mode that keeps the most
+// frames resident; the large codes (n of a few thousand) keep the whole frame in the slot.
 // Per update (chain of dependent steps kept short; every row computed in registers):
 //   selection      argmax over the block maxima (one wave reduction), or over the checks of n*,
 //   propagation    c2v[e*] <- pre[e*], L_{n*} += delta, D_{n*} refresh, syndrome toggles,
