@@ -130,6 +130,9 @@ typedef struct {
   int32_t max_touch;         /* max over VNs of the summed degrees of its checks               */
   int64_t lds_bytes_f32;     /* LDS bytes per frame of the single-edge decoder, FP32 mode       */
   int64_t lds_bytes_fix;     /* same, fixed-point mode                                          */
+  float mean_dv, mean_dc;    /* E / N and E / M                                                 */
+  int32_t gf2_rank;          /* rank of H over GF(2) once ldpc_code_rank has computed it, else -1 */
+  int32_t reserved;
 } ldpc_code_stats;
 
 /* Create a code handle from H in CSR form (host pointers; Sec. II-A: M x N parity-check matrix,
@@ -151,6 +154,12 @@ int ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t* shift, l
 
 /* Fill *out with the sizes and per-frame on-chip memory needs of a code. */
 int ldpc_code_info(const ldpc_code* code, ldpc_code_stats* out);
+
+/* Rank of H over GF(2) (the code has 2^(N - rank) codewords; the design rate of Sec. V's codes
+   is 1 - M / N only when H has full rank).  Gaussian elimination on bit-packed rows on the host:
+   O(M^2 N / 64) word operations and M N / 8 bytes, done once per handle (thread-safe) and kept;
+   ldpc_code_info reports it afterwards.  Errors: LDPC_EINVAL (null pointer), LDPC_ENOMEM. */
+int ldpc_code_rank(const ldpc_code* code, int32_t* rank);
 
 /* Release a handle (and its device copy).  NULL is ignored. */
 void ldpc_code_free(ldpc_code* code);

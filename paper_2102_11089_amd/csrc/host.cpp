@@ -32,6 +32,8 @@ struct ldpc_code {
   int* d_lut;       // 7 p0 tables (frac_bits 0..6), 257 entries each
   DevCode dev;
   DevCode* d_self;  // device copy of dev (batched launches)
+  std::mutex rank_mu;  // guards gf2_rank, computed on the first ldpc_code_rank call
+  int gf2_rank = -1;
 };
 
 namespace {
@@ -590,9 +592,68 @@ int ldpc_code_info(const ldpc_code* c, ldpc_code_stats* out) {
   out->max_dc = c->max_dc;
   out->n_layers = c->n_layers;
   out->max_touch = c->max_touch;
+  out->mean_dv = (float)((double)c->E / c->N);
+  out->mean_dc = (float)((double)c->E / c->M);
+  {
+    std::lock_guard<std::mutex> g(const_cast<ldpc_code*>(c)->rank_mu);
+    out->gf2_rank = c->gf2_rank;
+  }
+  out->reserved = 0;
   const int topo = c->h_qc.empty() ? TOPO_LDS : TOPO_QC;
   out->lds_bytes_f32 = dyn_layout(c, false, STORE_LDS, topo, 1).total;
   out->lds_bytes_fix = dyn_layout(c, true, STORE_LDS, topo, 1).total;
+  return LDPC_OK;
+}
+
+// Rank of H over GF(2) by Gaussian elimination on bit-packed rows: every row is reduced by the
+// pivots found so far, in column order.  O(M^2 N / 64) word operations, M N / 8 bytes.
+static int gf2_rank_of(const ldpc_code* c) {
+  const int M = c->M, N = c->N, W = (N + 63) / 64;
+  std::vector<uint64_t> A;
+  try {
+    A.assign((size_t)M * W, 0);
+  } catch (const std::bad_alloc&) {
+    return -1;
+  }
+  for (int m = 0; m < M; ++m)
+    for (int e = c->h_row_ptr[m]; e < c->h_row_ptr[m + 1]; ++e) {
+      const int n = c->h_col[e];
+      A[(size_t)m * W + (n >> 6)] |= 1ull << (n & 63);
+    }
+  int rank = 0;
+  for (int col = 0; col < N && rank < M; ++col) {
+    const int w = col >> 6;
+    const uint64_t bit = 1ull << (col & 63);
+    int piv = -1;
+    for (int m = rank; m < M; ++m)
+      if (A[(size_t)m * W + w] & bit) {
+        piv = m;
+        break;
+      }
+    if (piv < 0) continue;
+    if (piv != rank)
+      std::swap_ranges(A.begin() + (size_t)piv * W, A.begin() + (size_t)(piv + 1) * W, A.begin() + (size_t)rank * W);
+    const uint64_t* pr = &A[(size_t)rank * W];
+    for (int m = piv + 1; m < M; ++m) {  // rows between rank and piv have no bit in this column
+      uint64_t* r = &A[(size_t)m * W];
+      if (r[w] & bit)
+        for (int k = w; k < W; ++k) r[k] ^= pr[k];  // the pivot row has no bit before column col
+    }
+    rank += 1;
+  }
+  return rank;
+}
+
+int ldpc_code_rank(const ldpc_code* c, int32_t* rank) {
+  if (!c || !rank) return LDPC_EINVAL;
+  ldpc_code* cc = const_cast<ldpc_code*>(c);
+  std::lock_guard<std::mutex> g(cc->rank_mu);
+  if (cc->gf2_rank < 0) {
+    const int r = gf2_rank_of(c);
+    if (r < 0) return LDPC_ENOMEM;
+    cc->gf2_rank = r;
+  }
+  *rank = cc->gf2_rank;
   return LDPC_OK;
 }
 

@@ -26,7 +26,8 @@ FILL_LOWEST, FILL_HASH = 0, 1
 ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -4: "LDPC_ECAPACITY",
           -5: "LDPC_EUNSUPPORTED"}
 
-EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_free", "ldpc_decode",
+EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_rank", "ldpc_code_free",
+           "ldpc_decode",
            "ldpc_decode_batch", "ldpc_describe_plan", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune",
            "ldpc_set_batch_tuning", "ldpc_get_batch_tuning", "ldpc_autotune_batch", "ldpc_tuning_save",
            "ldpc_tuning_load", "ldpc_awgn_frames", "ldpc_sweep_create", "ldpc_sweep_run", "ldpc_sweep_free",
@@ -74,7 +75,8 @@ class ldpc_plan_info(C.Structure):
 class ldpc_code_stats(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("E", C.c_int32), ("max_dv", C.c_int32),
                 ("max_dc", C.c_int32), ("n_layers", C.c_int32), ("max_touch", C.c_int32),
-                ("lds_bytes_f32", C.c_int64), ("lds_bytes_fix", C.c_int64)]
+                ("lds_bytes_f32", C.c_int64), ("lds_bytes_fix", C.c_int64), ("mean_dv", C.c_float),
+                ("mean_dc", C.c_float), ("gf2_rank", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -95,6 +97,8 @@ def load(path: str = LIB_PATH):
     lib.ldpc_code_from_qc.restype = C.c_int
     lib.ldpc_code_info.argtypes = [P, C.POINTER(ldpc_code_stats)]
     lib.ldpc_code_info.restype = C.c_int
+    lib.ldpc_code_rank.argtypes = [P, C.POINTER(C.c_int32)]
+    lib.ldpc_code_rank.restype = C.c_int
     lib.ldpc_code_free.argtypes = [P]
     lib.ldpc_code_free.restype = None
     lib.ldpc_decode.argtypes = [P, C.POINTER(ldpc_schedule), P, C.c_int32, C.c_int64, P, C.c_int64,
@@ -199,6 +203,12 @@ def ldpc_code_info(handle: int) -> ldpc_code_stats:
     st = ldpc_code_stats()
     _check(load().ldpc_code_info(handle, C.byref(st)), "ldpc_code_info")
     return st
+
+
+def ldpc_code_rank(handle: int) -> int:
+    r = C.c_int32(-1)
+    _check(load().ldpc_code_rank(handle, C.byref(r)), "ldpc_code_rank")
+    return int(r.value)
 
 
 def ldpc_code_free(handle: int) -> None:
@@ -341,6 +351,10 @@ class Code:
             self.handle = ldpc_code_from_csr(self.M, self.N, code.row_ptr, code.col,
                                              getattr(code, "layer_ptr", None))
         self.stats = ldpc_code_info(self.handle)
+
+    def gf2_rank(self) -> int:
+        """Rank of H over GF(2) (computed once by the library and kept in the handle)."""
+        return ldpc_code_rank(self.handle)
 
     def __del__(self):
         h = getattr(self, "handle", None)

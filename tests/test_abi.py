@@ -55,6 +55,7 @@ def test_header_constants_match_binding():
 def test_struct_sizes():
     assert C.sizeof(ldpc.ldpc_schedule) == 48
     assert C.sizeof(ldpc.ldpc_outputs) == 11 * 8
+    assert C.sizeof(ldpc.ldpc_code_stats) == 64
 
 
 def test_strerror():
@@ -82,6 +83,12 @@ def test_code_validation_rejects_malformed(case):
         lp = np.array([0, 2], dtype=np.int32)
     with pytest.raises(RuntimeError, match="LDPC_EINVAL"):
         ldpc.ldpc_code_from_csr(M, N, rp, col, lp)
+
+
+def test_code_rank_rejects_null_arguments():
+    lib = ldpc.load()
+    r = C.c_int32(0)
+    assert lib.ldpc_code_rank(None, C.byref(r)) == -1
 
 
 def test_decode_rejects_null_arguments():
