@@ -176,6 +176,23 @@ int ldpc_decode(const ldpc_code* code, const ldpc_schedule* schedule, const floa
                 int64_t max_updates, const int32_t* replay, int64_t replay_len,
                 const ldpc_outputs* out, void* stream);
 
+/* Allocation-free ldpc_decode, for callers that cannot allocate device memory during the call
+   (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Arguments,
+   outputs, tuning and errors are those of ldpc_decode; the outputs a frame gets are identical.
+   Scratch memory (the work-queue counter and the frame slots of the state that does not stay on
+   chip) comes from one device array of LDPC_NOALLOC_SCRATCH_BYTES that the library holds on each
+   GPU it runs on until the process ends, instead of the memory pool: the call allocates nothing.
+   A decode whose slots would exceed the array runs on fewer persistent workgroups (same outputs,
+   lower throughput); LDPC_ECAPACITY when not even one workgroup's slots fit.  Calls on one GPU share
+   its array: calls that overlap on that GPU (on different streams, or from different threads
+   without ordering) race and corrupt each other's frames.  The queue counter is cleared by a small
+   kernel on the caller's stream at the start of each call.  Errors: as ldpc_decode, and LDPC_EHIP
+   if the array's device address cannot be obtained. */
+#define LDPC_NOALLOC_SCRATCH_BYTES (128ll << 20)
+int ldpc_decode_noalloc(const ldpc_code* code, const ldpc_schedule* schedule, const float* llr_in, int32_t B,
+                        int64_t max_updates, const int32_t* replay, int64_t replay_len,
+                        const ldpc_outputs* out, void* stream);
+
 /* One frame of a batched launch (device memory, 40 bytes). */
 typedef struct {
   int32_t code;        /* index into the codes array of ldpc_decode_batch                         */

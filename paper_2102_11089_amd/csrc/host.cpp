@@ -1127,6 +1127,56 @@ int ldpc_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Shrink a plan's persistent grid until its scratch fits cap bytes.  Workers take frames from a
+// queue (single-edge) or in strides of the grid (ME), so any grid of at least one workgroup decodes
+// every frame, with the same per-frame outputs; fewer workers only lower throughput.
+int fit_plan_to_scratch(const ldpc_code* c, DecodePlan& pl, size_t cap) {
+  if (pl.scratch_bytes <= cap) return LDPC_OK;
+  size_t head = 0, per_wg = 0;
+  if (pl.which == 1) {
+    head = pl.persistent ? kQueueBytes : 0;
+    const size_t msg = pl.fixed ? 1 : 4;
+    if (pl.store == STORE_PRE_GLOBAL) per_wg = (size_t)pl.dyn.wpb * c->E * msg;
+    else if (pl.store >= STORE_ALL_GLOBAL) per_wg = (size_t)pl.dyn.wpb * (size_t)pl.dyn.slot_bytes;
+  } else if (pl.which == 2 && pl.store != STORE_LDS) {
+    per_wg = (size_t)2 * c->E * (pl.fixed ? 1 : 4);
+  }
+  if (per_wg == 0 || cap < head + per_wg) return LDPC_ECAPACITY;
+  const size_t grid = std::min<size_t>((size_t)pl.grid, (cap - head) / per_wg);
+  pl.grid = (int)grid;
+  pl.scratch_bytes = head + grid * per_wg;
+  return LDPC_OK;
+}
+
+}  // namespace
+
+namespace ldpc {
+
+int record_hip_failure(hipError_t e) { return hip_fail(e); }
+
+int decode_in_scratch(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B,
+                      int64_t max_updates, const int32_t* replay, int64_t replay_len, const ldpc_outputs* out,
+                      void* scratch, size_t cap, hipStream_t st) {
+  if (!c || !s || !out || B < 0 || max_updates < 0) return LDPC_EINVAL;
+  if (B == 0) return LDPC_OK;
+  ldpc_tuning t{};
+  const bool tuned = lookup_tuning(c, s->kind, s->arith, t);
+  DecodePlan pl;
+  int rc = plan_decode(c, s, llr_in, B, max_updates, replay, replay_len, out, tuned ? &t : nullptr, pl);
+  if (rc != LDPC_OK) return rc;
+  if ((rc = fit_plan_to_scratch(c, pl, cap)) != LDPC_OK) return rc;
+  const hipError_t he = enqueue_decode(c, pl, pl.scratch_bytes ? scratch : nullptr, st);
+  return he == hipSuccess ? LDPC_OK : hip_fail(he);
+}
+
+}  // namespace ldpc
+
+extern "C" {
+
 int ldpc_describe_plan(const ldpc_code* c, const ldpc_schedule* s, int32_t B, ldpc_plan_info* info) {
   if (!c || !s || !info || B < 1) return LDPC_EINVAL;
   ldpc_tuning t{};

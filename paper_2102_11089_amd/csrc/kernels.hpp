@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/ldpcci.h"
 #include "common.hpp"
 
 namespace ldpc {
@@ -259,5 +260,14 @@ hipError_t set_batch_lds_limit(int bytes);
 hipError_t launch_me(const DevCode& H, const MeParams& P, bool fixed, bool msg_global, int topo, int grid,
                      int block, hipStream_t st);
 hipError_t set_me_lds_limit(int bytes);
+
+// host.cpp: ldpc_decode with the caller's scratch buffer (cap bytes at scratch) in place of an
+// allocation; a persistent grid is lowered until its frame slots fit.  LDPC_ECAPACITY when not
+// even one workgroup's slots fit.  Allocates no device memory.
+int decode_in_scratch(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B,
+                      int64_t max_updates, const int32_t* replay, int64_t replay_len, const ldpc_outputs* out,
+                      void* scratch, size_t cap, hipStream_t st);
+// host.cpp: record a failed HIP call for ldpc_last_hip_error and return LDPC_EHIP
+int record_hip_failure(hipError_t e);
 
 }  // namespace ldpc

@@ -27,7 +27,7 @@ ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -
           -5: "LDPC_EUNSUPPORTED"}
 
 EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_rank", "ldpc_code_free",
-           "ldpc_decode",
+           "ldpc_decode", "ldpc_decode_noalloc",
            "ldpc_decode_batch", "ldpc_describe_plan", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune",
            "ldpc_set_batch_tuning", "ldpc_get_batch_tuning", "ldpc_autotune_batch", "ldpc_tuning_save",
            "ldpc_tuning_load", "ldpc_awgn_frames", "ldpc_sweep_create", "ldpc_sweep_run", "ldpc_sweep_free",
@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH):
     lib.ldpc_decode.argtypes = [P, C.POINTER(ldpc_schedule), P, C.c_int32, C.c_int64, P, C.c_int64,
                                 C.POINTER(ldpc_outputs), P]
     lib.ldpc_decode.restype = C.c_int
+    lib.ldpc_decode_noalloc.argtypes = lib.ldpc_decode.argtypes
+    lib.ldpc_decode_noalloc.restype = C.c_int
     lib.ldpc_decode_batch.argtypes = [P, C.c_int32, C.POINTER(ldpc_schedule), P, C.c_int32, P, C.c_int64, P, P,
                                       C.c_int64, P, P, P, P]
     lib.ldpc_decode_batch.restype = C.c_int
@@ -220,6 +222,13 @@ def ldpc_decode(handle: int, schedule: ldpc_schedule, llr_ptr: int, B: int, max_
     rc = load().ldpc_decode(handle, C.byref(schedule), llr_ptr, B, max_updates, replay_ptr, replay_len,
                             C.byref(outputs), stream)
     _check(rc, "ldpc_decode")
+
+
+def ldpc_decode_noalloc(handle: int, schedule: ldpc_schedule, llr_ptr: int, B: int, max_updates: int,
+                        replay_ptr: Optional[int], replay_len: int, outputs: ldpc_outputs, stream: int) -> None:
+    rc = load().ldpc_decode_noalloc(handle, C.byref(schedule), llr_ptr, B, max_updates, replay_ptr, replay_len,
+                                    C.byref(outputs), stream)
+    _check(rc, "ldpc_decode_noalloc")
 
 
 def ldpc_decode_batch(handles, schedule: ldpc_schedule, frames_ptr: int, F: int, llr_ptr: int, llr_len: int,
@@ -386,8 +395,9 @@ def schedule(kind: int, arith: int = SPA_F32, gamma: float = 0.1, q_bits: int = 
 def decode(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int = 0, gamma: float = 0.1,
            q_bits: int = 6, frac_bits: int = 1, n_p: int = 1, n_g: int = 16, fill: int = FILL_LOWEST,
            seed: int = 0, check_every: int = 1, replay=None, trace: bool = False, dump: bool = False,
-           stream=None) -> Decoded:
-    """Decode a (B, N) float32 CUDA tensor of channel LLRs; returns device tensors."""
+           stream=None, noalloc: bool = False) -> Decoded:
+    """Decode a (B, N) float32 CUDA tensor of channel LLRs; returns device tensors.  noalloc: call
+    ldpc_decode_noalloc (scratch from the library's fixed device array) instead of ldpc_decode."""
     import torch
     llr = _cuda(llr, "llr", torch.float32, cols=code.N)
     B = llr.shape[0]
@@ -414,7 +424,8 @@ def decode(code: Code, llr, kind: int, arith: int = SPA_F32, max_updates: int = 
                         ptr(d.get("pre")), ptr(d.get("L")), ptr(d.get("Lt")), ptr(d.get("D")))
     s = schedule(kind, arith, gamma, q_bits, frac_bits, n_p, n_g, fill, seed, check_every)
     st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
-    ldpc_decode(code.handle, s, llr.data_ptr(), B, max_updates, ptr(rep), rep_len, outs, st)
+    (ldpc_decode_noalloc if noalloc else ldpc_decode)(code.handle, s, llr.data_ptr(), B, max_updates, ptr(rep),
+                                                      rep_len, outs, st)
     return Decoded(bits, llr_out, upd, steps, fall, tr, d.get("c2v"), d.get("pre"), d.get("L"), d.get("Lt"),
                    d.get("D"))
 

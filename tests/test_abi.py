@@ -96,6 +96,13 @@ def test_decode_rejects_null_arguments():
     s = ldpc.schedule(ldpc.CIRBP)
     out = ldpc.ldpc_outputs()
     assert lib.ldpc_decode(None, C.byref(s), None, 1, 10, None, 0, C.byref(out), None) == -1
+    assert lib.ldpc_decode_noalloc(None, C.byref(s), None, 1, 10, None, 0, C.byref(out), None) == -1
+    assert lib.ldpc_decode_noalloc(None, None, None, -1, 10, None, 0, None, None) == -1
+
+
+def test_noalloc_scratch_limit_is_declared():
+    m = re.search(r"#define LDPC_NOALLOC_SCRATCH_BYTES \((\d+)ll << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == 128 << 20
 
 
 def test_unrolled_entry_points_reject_bad_arguments():
