@@ -669,7 +669,11 @@ static int decode_frame(job_t *J, st_t *S, int32_t f) {
           else if (lmd && next_e >= 0) estar = next_e;
           else if (kind == OC_LMDRBP || kind == OC_SLMDRBP) estar = argmax_residual(S, cnt);
           else if (kind == OC_LMDCIRBP) estar = argmax_into(S, argmax_ci(S, cnt), cnt);
-          else estar = J->replay[(size_t)f * (size_t)J->replay_len + (size_t)t];
+          else {
+            /* replay: an edge id outside [0, E) ends the frame's recorded order */
+            estar = J->replay[(size_t)f * (size_t)J->replay_len + (size_t)t];
+            if (estar < 0 || estar >= H->E) break;
+          }
           apply_edge(S, estar, cnt);
           if (kind == OC_SLMDRBP) {
             next_e = lmd_edge(S, estar, cnt);

@@ -244,6 +244,23 @@ def test_replay_reproduces_schedule(arith):
         np.testing.assert_array_equal(rep.c2v[0], a.c2v[f])
 
 
+def test_replay_ends_at_an_invalid_edge_id():
+    """A recorded order padded with -1 after the frame stopped (the layout of a trace row) replays
+    to that point and no further: same updates used, same final state as the recording."""
+    code = S.workload_code("c0")
+    cw, llr = S.frames(code, 12, 2.0, 12)
+    a = O.decode(code, llr, O.CIRBP, O.SPA, max_updates=1000, trace=True, dump=True)
+    assert (a.updates_used < 1000).any()
+    rep = O.decode(code, llr, O.REPLAY, O.SPA, max_updates=1000, replay=a.trace, dump=True)
+    np.testing.assert_array_equal(rep.updates_used, a.updates_used)
+    np.testing.assert_array_equal(rep.llr_out, a.llr_out)
+    np.testing.assert_array_equal(rep.c2v, a.c2v)
+    bad = a.trace.copy()
+    bad[:, 5] = code.E  # out of range from the sixth update on
+    rep = O.decode(code, llr, O.REPLAY, O.SPA, max_updates=1000, replay=bad)
+    np.testing.assert_array_equal(rep.updates_used, np.minimum(a.updates_used, 5))
+
+
 def test_stop_rule_first_valid_codeword():
     """Sec. II-A: decoding stops at the first update after which the hard decisions form a codeword
     (here tested after every update); checked with H from scratch on replayed prefixes."""
