@@ -178,20 +178,85 @@ def test_f32_fer_within_interval_c0(gpu, c0, kind):
     assert np.mean(np_(g.updates_used) == ref.updates_used) > 0.8
 
 
-def test_f32_bg1_shaped_full_size_replay(gpu):
-    """Z=52 BG1-shaped code at full size (pre[] kept outside LDS): replay of 1500 oracle updates."""
+@pytest.fixture(scope="module")
+def c1_full_length_traces():
+    """CIRBP schedules the oracle records on frames of the BG1-shaped Z=52 code at 1.25 dB (cap 3E,
+    stop on a valid codeword): the three longest of 24 frames and a median one, each to the update
+    where it stopped, and the oracle's replay of them with the final state."""
     code = S.workload_code("c1")
+    cw, llr = S.frames(code, 24, 1.25, 106)
+    cap = 3 * code.E
+    say("[f32 replay] c1: oracle CIRBP on 24 frames (full length)")
+    rec = O.decode(code, llr, O.CIRBP, O.SPA, max_updates=cap, gamma=0.1, trace=True, threads=8)
+    order = np.argsort(rec.updates_used, kind="stable")
+    pick = [int(x) for x in order[-3:]] + [int(order[len(order) // 2])]
+    say(f"[f32 replay] c1: frames {pick}, updates {rec.updates_used[pick].tolist()}")
+    tr = rec.trace[pick]
+    ref = O.decode(code, llr[pick], O.REPLAY, O.SPA, max_updates=cap, replay=tr, dump=True, threads=4)
+    assert np.array_equal(ref.updates_used, rec.updates_used[pick])
+    return code, llr[pick], tr, ref
+
+
+@pytest.mark.parametrize("plan", ["default", "benchmark"])
+def test_f32_bg1_shaped_full_length_replay(gpu, c1_full_length_traces, plan):
+    """Z=52 BG1-shaped code: the oracle's CIRBP schedules replayed to their full length (every
+    update the frame made, up to 3E), in the plan a 4-frame decode gets and in the plan the
+    benchmark's 65536-frame launch uses (VN records in global memory, QC tables in LDS, 14 frames
+    per workgroup): every c2v, pre, L and Lt within 1e-4 max(|oracle|, 1), every CI within 1e-4."""
+    code, llr, tr, ref = c1_full_length_traces
     ch = gpu.Code(code)
-    cw, llr = S.frames(code, 3, 1.25, 106)
-    say("[f32 replay] c1 3 frames, 1500 updates")
-    rec = O.decode(code, llr, O.CIRBP, O.SPA, max_updates=1500, check_every=0, trace=True, threads=3)
-    ref = O.decode(code, llr, O.REPLAY, O.SPA, max_updates=1500, replay=rec.trace, dump=True, threads=3)
-    g = gpu_decode(gpu, ch, llr, "replay", gpu.SPA_F32, max_updates=1500, replay=torch.from_numpy(rec.trace),
-                   dump=True)
+    cap = 3 * code.E
+    if plan == "benchmark":
+        gpu.set_tuning(ch, gpu.REPLAY, gpu.SPA_F32, block=14 * 64, storage=gpu.STORE_GLOBAL_REC,
+                       topology=gpu.TOPO_QC)
+    try:
+        pl = gpu.describe_plan(ch, llr.shape[0], gpu.REPLAY)
+        say(f"[f32 replay] c1 {plan} plan {pl}")
+        if plan == "benchmark":
+            bench = gpu.describe_plan(ch, 65536, gpu.CIRBP)
+            for k in ("storage", "topology", "block", "frames_per_workgroup"):
+                assert pl[k] == bench[k], (k, pl, bench)
+        g = gpu_decode(gpu, ch, llr, "replay", gpu.SPA_F32, max_updates=cap, replay=torch.from_numpy(tr),
+                       dump=True)
+    finally:
+        if plan == "benchmark":
+            gpu.set_tuning(ch, gpu.REPLAY, gpu.SPA_F32, clear=True)
+    assert np.array_equal(np_(g.updates_used), ref.updates_used)
     assert_close_msgs(g.c2v, ref.c2v, "c2v")
+    assert_close_msgs(g.pre, ref.pre, "pre")
     assert_close_msgs(g.L, ref.L, "L")
     assert_close_msgs(g.Lt, ref.Lt, "Lt")
     assert np.abs(np_(g.D) - ref.D).max() <= 1e-4
+    sure = np.abs(ref.L) > 1e-3  # hard decisions of totals away from zero
+    assert np.array_equal(np_(g.bits)[sure], ref.bits[sure])
+
+
+def test_f32_c1_fer_within_oracle_interval(gpu):
+    """Free-running FP32 decodes of the BG1-shaped Z=52 code at 0.5 dB (3000 seeded frames):
+    CIRBP (cap 3E), flooding and layered BP (50 iterations) each have frame errors inside the 95%
+    Clopper-Pearson interval of the oracle's on the same frames.  The oracle's counts are stored in
+    tests/golden/c1_fer_0p5db.json by tests/golden/make_c1_fer.py (oracle and input generators
+    only)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c1_fer_0p5db.json")) as fh:
+        gold = json.load(fh)
+    code = S.workload_code("c1")
+    ch = gpu.Code(code)
+    n = gold["frames"]
+    cw, llr = S.frames(code, n, gold["ebn0_db"], gold["seed"])
+    t = torch.from_numpy(llr).cuda()
+    kinds = {"cirbp": gpu.CIRBP, "flooding": gpu.FLOODING, "layered": gpu.LAYERED}
+    for name, d in gold["decoders"].items():
+        r = gpu.decode(ch, t, kinds[name], gpu.SPA_F32, max_updates=d["max_updates"], gamma=d["gamma"])
+        torch.cuda.synchronize()
+        err = np.flatnonzero(np.any(np_(r.bits) != cw, axis=1))
+        k_ref = d["frame_errors"]
+        both = len(set(err.tolist()) & set(d["error_frames"]))
+        lo, hi = cp_interval(k_ref, n)
+        say(f"[c1 FER {name}] gpu {err.size}, oracle {k_ref} of {n} (both {both}); mean updates gpu "
+            f"{np_(r.updates_used).mean():.0f}, oracle {d['mean_updates']:.0f}")
+        assert lo <= err.size / n <= hi, (name, err.size, k_ref, lo, hi)
 
 
 def _syndrome_weights(code, bits):
@@ -542,13 +607,14 @@ def test_f32_me_fer_within_interval_c0(gpu, c0):
 # ------------------------------------------------------------------------------------------
 # persistent batched launch over uneven codes and schedules
 # ------------------------------------------------------------------------------------------
-def _mixed_batch(codes, F, seed, ebn0s=(1.5, 2.5, 3.5)):
+def _mixed_batch(codes, F, seed, ebn0s=(1.5, 2.5, 3.5), kinds=None):
     from paper_2102_11089_amd import ldpc as L
     rng = np.random.default_rng(seed)
     frames = np.zeros(F, dtype=L.FRAME_DESC)
     llrs, cws, per = [], [], []
     off = 0
-    kinds = [L.FLOODING, L.LAYERED, L.RBP, L.CIRBP, L.LMDRBP, L.SLMDRBP, L.LMD_CIRBP]
+    if kinds is None:
+        kinds = [L.FLOODING, L.LAYERED, L.RBP, L.CIRBP, L.LMDRBP, L.SLMDRBP, L.LMD_CIRBP]
     for f in range(F):
         ci = int(rng.integers(len(codes)))
         c = codes[ci]
@@ -592,6 +658,64 @@ def test_batch_uneven_codes_and_schedules(gpu, arith):
             errs_ref += int(np.any(ref.bits[0] != cws[f]))
             errs_gpu += int(np.any(bits[off:off + c.N] != cws[f]))
     assert abs(errs_gpu - errs_ref) <= 2
+
+
+def _oracle_by_group(codes, frames, pool, per, kmap, arith, **kw):
+    """Oracle decodes of a batch's frames, grouped by (code, schedule, cap) so that each group runs
+    as one multi-threaded oracle call: per frame (bits, updates_used)."""
+    groups = {}
+    for f, (ci, kind, off) in enumerate(per):
+        groups.setdefault((ci, kind, int(frames[f]["max_updates"])), []).append(f)
+    out = {}
+    for (ci, kind, mu), fs in groups.items():
+        c = codes[ci]
+        llr = np.stack([pool[per[f][2]:per[f][2] + c.N] for f in fs])
+        r = O.decode(c, llr, kmap[kind], arith, max_updates=mu, gamma=0.1, threads=8, **kw)
+        for x, f in enumerate(fs):
+            out[f] = (r.bits[x], int(r.updates_used[x]))
+    return out
+
+
+@pytest.mark.parametrize("arith", ["fix", "f32"])
+def test_batch_c2_shape_all_codes(gpu, arith):
+    """The batched launch at the shape of the batched workload: all 12 codes of the 24-column
+    family (Z in {24, 48, 96}, base rows 12, 8, 6, 4: rates 1/2, 2/3, 3/4, 5/6) in one launch, the
+    LDS layout sized for the largest (n = 2304), schedules drawn from {flooding (20 iterations), RBP,
+    CIRBP (3E)}.  8-bit fixed point: every frame bit for bit equal to the oracle (decoded bits and
+    updates used).  FP32: each schedule's frame errors inside the 95% Clopper-Pearson interval of
+    the oracle's on the same frames (low Eb/N0, so that errors occur)."""
+    codes = [S.qc_24col(Z, mb, seed=1) for Z in (24, 48, 96) for mb in (12, 8, 6, 4)]
+    hs = [gpu.Code(c) for c in codes]
+    kinds = [gpu.FLOODING, gpu.RBP, gpu.CIRBP]
+    if arith == "fix":
+        F, ebn0s, a, oa = 480, (1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0), gpu.MS_FIX, O.MSFIX
+    else:
+        F, ebn0s, a, oa = 1440, (1.0, 1.5), gpu.SPA_F32, O.SPA
+    frames, pool, cws, per, out_len = _mixed_batch(codes, F, 21, ebn0s=ebn0s, kinds=kinds)
+    say(f"[batch c2 shape {arith}] {F} frames over 12 codes and 3 schedules")
+    bits, llr_out, upd, steps, fall = gpu.decode_batch(hs, frames, torch.from_numpy(pool).cuda(), out_len, arith=a,
+                                                       q_bits=8, frac_bits=2)
+    torch.cuda.synchronize()
+    bits, upd = np_(bits), np_(upd)
+    kmap = {gpu.FLOODING: O.FLOODING, gpu.RBP: O.RBP, gpu.CIRBP: O.CIRBP}
+    ref = _oracle_by_group(codes, frames, pool, per, kmap, oa, q_bits=8, frac_bits=2)
+    say(f"[batch c2 shape {arith}] oracle done")
+    assert {per[f][0] for f in range(F)} == set(range(12))
+    errs = {k: [0, 0, 0] for k in kinds}  # frames, gpu errors, oracle errors
+    for f, (ci, kind, off) in enumerate(per):
+        n = codes[ci].N
+        rb, ru = ref[f]
+        if arith == "fix":
+            assert int(upd[f]) == ru, (f, ci, kind)
+            np.testing.assert_array_equal(bits[off:off + n], rb)
+        e = errs[kind]
+        e[0] += 1
+        e[1] += int(np.any(bits[off:off + n] != cws[f]))
+        e[2] += int(np.any(rb != cws[f]))
+    for kind, (nf, kg, kr) in errs.items():
+        lo, hi = cp_interval(kr, nf)
+        say(f"[batch c2 shape {arith}] schedule {kind}: {nf} frames, frame errors gpu {kg}, oracle {kr}")
+        assert lo <= kg / nf <= hi, (kind, kg, kr, nf, lo, hi)
 
 
 def test_batch_rejects_bad_descriptors(gpu):
