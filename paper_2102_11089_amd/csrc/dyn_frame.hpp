@@ -2,6 +2,8 @@
 // driven LMDRBP, sLMDRBP and LMD-CIRBP) for one wavefront; used by the per-code kernel and by the
 // persistent batched kernel.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -97,10 +99,23 @@ struct MsgStore<A, STORE, true> {
   VnRec<llr_t>* r;    // STORE_FRAME_REC, [N]
   __device__ __forceinline__ msg_t c(int e) const { return m[e].c; }
   __device__ __forceinline__ msg_t p(int e) const { return m[e].p; }
-  __device__ __forceinline__ void set_c(int e, msg_t v) const { m[e].c = v; }
-  __device__ __forceinline__ void set_p(int e, msg_t v) const { m[e].p = v; }
+  // Frames whose whole state lives in global memory exceed the L2 and MALL by far; their message
+  // pairs are read and written with the non-temporal hint, which leaves the caches to the VN
+  // records and the code's tables (c1: 3.6% more frames/s; the same hint on the records cost 12%)
+  static constexpr bool kStream = STORE >= STORE_FRAME_GLOBAL;
+  using pair_bits_t = typename std::conditional<sizeof(MsgPair<msg_t>) == 8, unsigned long long, unsigned short>::type;
+  __device__ __forceinline__ void set_c(int e, msg_t v) const {
+    if constexpr (kStream) __builtin_nontemporal_store(v, &m[e].c);
+    else m[e].c = v;
+  }
+  __device__ __forceinline__ void set_p(int e, msg_t v) const {
+    if constexpr (kStream) __builtin_nontemporal_store(v, &m[e].p);
+    else m[e].p = v;
+  }
   __device__ __forceinline__ void cp(int e, msg_t& cv, msg_t& pv) const {
-    const MsgPair<msg_t> x = m[e];
+    MsgPair<msg_t> x;
+    if constexpr (kStream) x = __builtin_bit_cast(MsgPair<msg_t>, __builtin_nontemporal_load(reinterpret_cast<const pair_bits_t*>(m + e)));
+    else x = m[e];
     cv = x.c;
     pv = x.p;
   }
