@@ -444,6 +444,7 @@ struct DevQC {
   const int* bcol;      // [nblk][4]  (i, shift, rank in row i, 0) per column, ascending i
   const int* rowmap;    // [nblk]     base row of edge block e / Z
   const int* bdiv;      // [mb][2]    FastDiv (mul, sh) of deg[i]
+  const int* border;    // [mb]       base rows by descending degree (ties: ascending index)
   int words;            // total ints of the tables (for copying into LDS)
   FastDiv zdiv;         // FastDiv of Z
 };
@@ -549,6 +550,7 @@ struct TopoQC {
     return brow[x] * Z + c;
   }
   const int* nbr_col;  // [nb][2] in LDS
+  const int* border;   // [mb] base rows by descending degree, in LDS
   __device__ __forceinline__ int2 nbr(int n) const {
     const int j = zdiv.div(n), c = n - j * Z;
     const int cnt = nbr_col[2 * j + 1];

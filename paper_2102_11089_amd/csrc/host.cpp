@@ -442,6 +442,12 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
       q2.push_back((int)f.mul);
       q2.push_back((int)f.sh);
     }
+    // base rows by descending degree (lower index first on ties): the order in which flooding's
+    // wavefronts take rows, so that the longest rows start first
+    std::vector<int> order(qmb);
+    for (int i = 0; i < qmb; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return (*qc)[a] > (*qc)[b]; });
+    q2.insert(q2.end(), order.begin(), order.end());
     c->h_qc = q2;
     c->qc_Z = qZ;
     c->qc_mb = qmb;
@@ -502,6 +508,7 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
     d.qc.words = (int)c->h_qc.size();
     d.nbr_col = reinterpret_cast<const int2*>(d.qc.rowmap + qnblk);
     d.qc.bdiv = d.qc.rowmap + qnblk + 2 * qnb;
+    d.qc.border = d.qc.bdiv + 2 * qmb;
     d.qc.zdiv = FastDiv::of((uint32_t)qZ);
   }
   he = hipMalloc((void**)&c->d_self, sizeof(DevCode));
@@ -790,20 +797,89 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     P.out = o;
     P.qmax = qmax;
     P.scale = scale;
-    const int msg = fixed ? 1 : 4;
-    const int vbuf_n = s->kind == LDPC_FLOODING ? c->E : c->max_layer_edges;
-    int off = 0;
-    P.off_c2v = off; off = align16(off + c->E * msg);
-    P.off_L = off; off = align16(off + c->N * 4);
-    P.off_ch = off; off = align16(off + vbuf_n * 4);
-    P.off_syn = off; off = align16(off + ((c->M + 31) / 32) * 4);
-    P.off_misc = off; off = align16(off + 16);
-    P.lds_bytes = off;
-    if (P.lds_bytes > pl.lds_limit) return LDPC_ECAPACITY;
-    const int work = vbuf_n;
+    P.c2v_global = nullptr;
+    P.queue = nullptr;
+    P.slot_edges = c->E;
     pl.which = 0;
-    pl.block = T.block ? T.block : (work >= 4096 ? 1024 : (work >= 1024 ? 256 : (work >= 256 ? 128 : 64)));
-    pl.grid = B;
+    pl.store = STORE_LDS;
+    const int msg = fixed ? 1 : 4;
+    const int syn = ((c->M + 31) / 32) * 4;
+    // topology: quasi-cyclic base tables, else CSR copies in LDS when they fit, else global arrays
+    std::vector<int> tps = c->h_qc.empty() ? std::vector<int>{TOPO_LDS, TOPO_GLOBAL} : std::vector<int>{TOPO_QC};
+    if (T.topology) {
+      tps = topo_choices(c, T.topology);
+      if (tps.empty()) return LDPC_EUNSUPPORTED;
+    }
+    if (s->kind == LDPC_FLOODING) {
+      // one frame per workgroup, one workgroup per frame (the hardware hands out workgroups as
+      // others finish): c2v, L, channel values, syndrome words, counter, topology copy
+      bool found = false;
+      for (int tp : tps) {
+        int off = 0;
+        P.off_c2v = off; off = align16(off + c->E * msg);
+        P.off_L = off; off = align16(off + c->N * 4);
+        P.off_ch = off; off = align16(off + c->N * 4);
+        P.off_syn = off; off = align16(off + syn);
+        P.off_misc = off; off = align16(off + 16);
+        P.off_topo = off; off = align16(off + (int)topo_bytes(c, tp));
+        P.lds_bytes = off;
+        P.frame_base = 0;
+        P.frame_stride = off;
+        P.wpb = 1;
+        if (off <= pl.lds_limit) {
+          pl.topo = tp;
+          found = true;
+          break;
+        }
+      }
+      if (!found) return LDPC_ECAPACITY;
+      const int work = std::max(c->M, c->N);
+      pl.block = T.block ? T.block : (work >= 2048 ? 1024 : (work >= 512 ? 256 : (work >= 128 ? 128 : 64)));
+      pl.grid = B;
+      return LDPC_OK;
+    }
+    // layered: one frame per wavefront; wpb frames per workgroup share the topology copy.  c2v in
+    // LDS when that keeps at least as many frames per CU as c2v in a global slot would
+    std::vector<bool> c2v_opts = {false, true};
+    if (T.storage == LDPC_STORE_LDS) c2v_opts = {false};
+    else if (T.storage != LDPC_STORE_AUTO) c2v_opts = {true};
+    bool found = false;
+    int best_fpc = 0;
+    for (int tp : tps) {
+      const int topo_b = align16((int)topo_bytes(c, tp));
+      for (bool g : c2v_opts) {
+        const int frame = align16(c->N * 4) + align16(syn) + (g ? 0 : align16(c->E * msg));
+        if (topo_b + frame > pl.lds_limit) continue;
+        int wpb = T.block ? T.block / WAVE : std::min(16, (160 * 1024 - topo_b) / frame);
+        wpb = std::max(1, std::min(wpb, 16));
+        while (wpb > 1 && topo_b + wpb * frame > pl.lds_limit) --wpb;
+        const int lds = topo_b + wpb * frame;
+        const int wgs = std::max(1, std::min((160 * 1024) / lds, 32 / wpb));
+        int fpc = wgs * wpb;
+        if (T.frames_per_cu) fpc = std::min(fpc, std::max(wpb, T.frames_per_cu / wpb * wpb));
+        if (!found || fpc > best_fpc) {
+          found = true;
+          best_fpc = fpc;
+          pl.topo = tp;
+          pl.store = g ? STORE_ALL_GLOBAL : STORE_LDS;
+          P.off_topo = 0;
+          P.frame_base = topo_b;
+          P.frame_stride = frame;
+          P.wpb = wpb;
+          P.off_L = 0;
+          P.off_syn = align16(c->N * 4);
+          P.off_c2v = P.off_syn + align16(syn);
+          P.lds_bytes = lds;
+        }
+      }
+    }
+    if (!found) return LDPC_ECAPACITY;
+    pl.block = WAVE * P.wpb;
+    pl.persistent = true;
+    const long long wg_needed = (B + P.wpb - 1) / P.wpb;
+    pl.grid = (int)std::min<long long>(wg_needed, (long long)ncu * std::max(1, best_fpc / P.wpb));
+    pl.scratch_bytes = kQueueBytes;
+    if (pl.store != STORE_LDS) pl.scratch_bytes += (size_t)pl.grid * P.wpb * c->E * msg;
     return LDPC_OK;
   }
 
@@ -1051,7 +1127,15 @@ hipError_t enqueue_decode(const ldpc_code* c, DecodePlan& pl, void* scratch, hip
     hipError_t he = plan_lds_limits(pl);
     if (he != hipSuccess) return he;
   }
-  if (pl.which == 0) return launch_baseline(c->dev, pl.base, pl.fixed, pl.grid, pl.block, st);
+  if (pl.which == 0) {
+    if (pl.persistent) {
+      pl.base.queue = reinterpret_cast<int*>(scratch);
+      pl.base.c2v_global = pl.store != STORE_LDS ? (char*)scratch + kQueueBytes : nullptr;
+      hipError_t he = launch_fill_u64(reinterpret_cast<int64_t*>(scratch), 1, 0, st);  // queue = 0
+      if (he != hipSuccess) return he;
+    }
+    return launch_baseline(c->dev, pl.base, pl.fixed, pl.topo, pl.grid, pl.block, st);
+  }
   if (pl.which == 2) {
     const bool mg = pl.store != STORE_LDS;
     pl.me.msg_global = mg ? scratch : nullptr;
@@ -1137,7 +1221,10 @@ namespace {
 int fit_plan_to_scratch(const ldpc_code* c, DecodePlan& pl, size_t cap) {
   if (pl.scratch_bytes <= cap) return LDPC_OK;
   size_t head = 0, per_wg = 0;
-  if (pl.which == 1) {
+  if (pl.which == 0 && pl.persistent) {
+    head = kQueueBytes;
+    if (pl.store != STORE_LDS) per_wg = (size_t)pl.base.wpb * c->E * (pl.fixed ? 1 : 4);
+  } else if (pl.which == 1) {
     head = pl.persistent ? kQueueBytes : 0;
     const size_t msg = pl.fixed ? 1 : 4;
     if (pl.store == STORE_PRE_GLOBAL) per_wg = (size_t)pl.dyn.wpb * c->E * msg;
@@ -1186,11 +1273,11 @@ int ldpc_describe_plan(const ldpc_code* c, const ldpc_schedule* s, int32_t B, ld
   if (rc != LDPC_OK) return rc;
   ldpc_plan_info r{};
   r.kernel = pl.which;
-  r.storage = pl.which == 0 ? LDPC_STORE_LDS : pl.store + 1;  // Store -> LDPC_STORE_* (shifted by AUTO)
-  r.topology = pl.which == 0 ? LDPC_TOPO_GLOBAL : pl.topo + 1;
+  r.storage = pl.store + 1;  // Store -> LDPC_STORE_* (shifted by AUTO)
+  r.topology = pl.topo + 1;
   r.block = pl.block;
   r.grid = pl.grid;
-  r.frames_per_workgroup = pl.which == 1 ? pl.dyn.wpb : 1;
+  r.frames_per_workgroup = pl.which == 1 ? pl.dyn.wpb : (pl.which == 0 ? pl.base.wpb : 1);
   const int lds = pl.which == 0 ? pl.base.lds_bytes : (pl.which == 1 ? pl.dyn.lds_bytes : pl.me.lds_bytes);
   const int by_lds = std::max(1, (160 * 1024) / std::max(lds, 1));
   const int wps = pl.which == 1 ? dynamic_waves_per_simd(pl.fixed, pl.store, pl.topo, pl.topo != TOPO_GLOBAL && pl.dyn.wpb > 1,
@@ -1198,7 +1285,7 @@ int ldpc_describe_plan(const ldpc_code* c, const ldpc_schedule* s, int32_t B, ld
                                 : 8;
   const int by_waves = std::max(1, 4 * wps / std::max(1, pl.block / WAVE));
   r.workgroups_per_cu = std::min(by_lds, by_waves);
-  r.persistent = pl.which == 1 ? (pl.persistent ? 1 : 0) : (pl.which == 2 && pl.grid < B ? 1 : 0);
+  r.persistent = pl.which <= 1 ? (pl.persistent ? 1 : 0) : (pl.grid < B ? 1 : 0);
   r.lds_bytes = lds;
   r.scratch_bytes = (int64_t)pl.scratch_bytes;
   *info = r;
@@ -1230,8 +1317,11 @@ int ldpc_autotune(const ldpc_code* c, const ldpc_schedule* s, const float* llr_i
   hipStream_t st = (hipStream_t)stream;
   // candidate knobs of the kernel family this schedule runs on
   std::vector<ldpc_tuning> cands;
-  if (s->kind == LDPC_FLOODING || s->kind == LDPC_LAYERED) {
+  if (s->kind == LDPC_FLOODING) {
     for (int b : {64, 128, 256, 512, 1024}) cands.push_back(ldpc_tuning{b, 0, 0, 0});
+  } else if (s->kind == LDPC_LAYERED) {  // frames per workgroup x c2v in LDS or in a global slot
+    for (int b : {0, 64, 256, 512, 1024})
+      for (int store : {LDPC_STORE_AUTO, LDPC_STORE_LDS, LDPC_STORE_GLOBAL_ALL}) cands.push_back(ldpc_tuning{b, 0, store, 0});
   } else {
     std::vector<int> tps = {LDPC_TOPO_GLOBAL, LDPC_TOPO_LDS};
     if (!c->h_qc.empty()) tps.push_back(LDPC_TOPO_QC);

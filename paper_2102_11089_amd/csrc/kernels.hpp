@@ -115,7 +115,14 @@ struct BaseParams {
   DecOut out;
   int qmax;
   float scale;
-  int off_c2v, off_L, off_ch, off_syn, off_misc;
+  // LDS layout (byte offsets).  Flooding: one frame per workgroup (c2v, L, channel, syndrome
+  // words, counter, topology copy).  Layered: the topology copy at off_topo, then wpb frames of
+  // frame_stride bytes from frame_base, each with L, syndrome words and (unless c2v_global) c2v.
+  int off_c2v, off_L, off_ch, off_syn, off_misc, off_topo;
+  int frame_base, frame_stride, wpb;
+  void* c2v_global;         // layered, large codes: per-wavefront c2v slots of slot_edges messages
+  long long slot_edges;
+  int* queue;               // layered: next-frame counter of the persistent grid (zeroed before launch)
   int lds_bytes;
 };
 
@@ -170,6 +177,7 @@ struct TopoSel<TOPO_QC> {
     const int o_bdiv = (int)(q.bdiv - q.bdeg);
     TopoQC t{q.Z, q.zdiv, p, p + o_bptr, p + o_brow, p + o_bcp, p + o_bcol, p + o_rm, p + o_bdiv};
     t.nbr_col = p + (int)(reinterpret_cast<const int*>(H.nbr_col) - q.bdeg);
+    t.border = p + (int)(q.border - q.bdeg);
     return t;
   }
 };
@@ -179,7 +187,7 @@ hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, int 
 hipError_t set_dynamic_lds_limit(int bytes);
 // wavefronts of one single-edge kernel variant a SIMD can hold by its register count (1..8)
 int dynamic_waves_per_simd(bool fixed, int store, int topo, bool mf, bool lmd);
-hipError_t launch_baseline(const DevCode& H, const BaseParams& P, bool fixed, int grid, int block,
+hipError_t launch_baseline(const DevCode& H, const BaseParams& P, bool fixed, int topo, int grid, int block,
                            hipStream_t st);
 hipError_t set_baseline_lds_limit(int bytes);
 struct MeParams {
