@@ -162,19 +162,93 @@ def summarize(res, code):
     return fe, nf, upd, fall
 
 
-def cpu_baseline(code, llr_host, cw_host, max_updates, seconds, threads):
-    """The oracle (plain C, FP64, linear scans) on the host cores over a bounded sample."""
-    from oracle import oracle as O
+def baseline_roofline(ldpc, h, code, kind, B, updates, kern_s, s_c=4, s_v=4, arith=None):
+    """Roofline of a flooding or layered launch.  Algorithmic bytes per edge-update (one C2V
+    message computed; an iteration is E of them): flooding reads L and the old message and writes
+    the new one (3 s_c + s_v, the V2C formed on the fly) and each VN sums its messages into L once
+    per iteration (2 s_v N / E); layered reads L and the old message and writes both (2 s_c + 2 s_v).
+    Bound: LDS when the messages are in LDS, else HBM for the messages (the L half stays in LDS)."""
+    pd = ldpc.describe_plan(h, B, kind, ldpc.SPA_F32 if arith is None else arith)
+    N, E = code.N, code.E
+    if kind == ldpc.FLOODING:
+        per, msg_bytes = 3 * s_c + s_v + 2 * s_v * N / E, 3 * s_c
+    else:
+        per, msg_bytes = 2 * s_c + 2 * s_v, 2 * s_c
+    if pd["storage_name"] == "lds":
+        achieved = per * updates / kern_s / 1e9
+        return {"bound": "lds", "achieved": round(achieved, 2), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
+                "frac": round(achieved / LDS_PEAK_GBS, 6), "bytes_per_edge_update": round(per, 3),
+                "plan": f"{pd['storage_name']} messages, {pd['topology_name']} topology, block {pd['block']}"}
+    achieved = msg_bytes * updates / kern_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 6), "bytes_per_edge_update": round(msg_bytes, 3),
+            "lds_bytes_per_edge_update": round(per - msg_bytes, 3),
+            "plan": f"{pd['storage_name']} messages, {pd['topology_name']} topology, "
+                    f"{pd['frames_per_workgroup']} frames per workgroup"}
+
+
+def host_cpu():
+    """The host's CPU as this process sees it: logical CPUs, the CPUs it may run on, the model name,
+    and the worker count the oracle uses (the CPU share set by OMP_NUM_THREADS when given, else
+    every CPU of the affinity mask)."""
+    nproc = os.cpu_count() or 1
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = nproc
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    workers = max(1, min(aff, int(share))) if share.isdigit() and int(share) > 0 else aff
+    return {"nproc": nproc, "affinity": aff, "model": model, "workers": workers,
+            "workers_from": "OMP_NUM_THREADS" if share.isdigit() and int(share) > 0 else "affinity"}
+
+
+def oracle_rate(jobs, workers, seconds):
+    """Run oracle jobs (callables returning (frames, updates)) on `workers` threads, in order, until
+    `seconds` have passed (jobs already started finish).  The oracle releases the interpreter while
+    it decodes, so the threads run in parallel.  Returns (frames, updates, wall seconds)."""
+    import concurrent.futures as cf
     t0 = time.perf_counter()
-    done = 0
-    upd = 0
-    while done < len(llr_host) and time.perf_counter() - t0 < seconds:
-        chunk = llr_host[done:done + threads]
-        r = O.decode(code, chunk, O.CIRBP, O.SPA, max_updates=max_updates, gamma=0.1, threads=threads)
-        upd += int(r.updates_used.sum())
-        done += len(chunk)
-    dt = time.perf_counter() - t0
-    return done, upd, dt
+    frames = upd = 0
+    it = iter(jobs)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        running = set()
+        while True:
+            while len(running) < workers and time.perf_counter() - t0 < seconds:
+                job = next(it, None)
+                if job is None:
+                    break
+                running.add(ex.submit(job))
+            if not running:
+                break
+            done, running = cf.wait(running, return_when=cf.FIRST_COMPLETED)
+            for d in done:
+                f, u = d.result()
+                frames += f
+                upd += u
+    return frames, upd, time.perf_counter() - t0
+
+
+def cpu_baseline_entry(jobs_fn, seconds, unit_desc):
+    """The oracle (plain C, FP64, linear scans as in the paper's search) on the host: one thread for
+    a third of the budget, then every worker of the CPU share for the rest.  jobs_fn() yields a fresh
+    job sequence over the same sample."""
+    cpu = host_cpu()
+    f1, u1, t1 = oracle_rate(jobs_fn(), 1, seconds / 3.0)
+    fa, ua, ta = oracle_rate(jobs_fn(), cpu["workers"], seconds * 2.0 / 3.0)
+    return {"value": round(fa / ta, 4), "unit": "frames/s", "cores": cpu["workers"], "kind": "oracle",
+            "sample": f"{unit_desc}; all cores: {fa} frames in {ta:.1f} s on {cpu['workers']} threads; "
+                      f"one thread: {f1} frames in {t1:.1f} s",
+            "edge_updates_per_s": round(ua / ta, 1),
+            "single_thread": {"frames_per_s": round(f1 / t1, 4), "edge_updates_per_s": round(u1 / t1, 1)},
+            "host": {k: cpu[k] for k in ("nproc", "affinity", "model", "workers", "workers_from")}}
 
 
 def ev_time(stream, fn):
@@ -353,6 +427,80 @@ def bench_ci(args, ldpc, S, dev):
     print(json.dumps(out), flush=True)
 
 
+def batched_roofline(ldpc, codes, hs, frames, llr_pool, upd_np, kern_s, arith, q, f, name, stream):
+    """Roofline of the batched launch.  Algorithmic bytes: for the RBP and CIRBP frames of each
+    code, the Table-1 bytes per update averaged over traced decodes of 32 randomly drawn frames of
+    that (code, schedule) (the per-code kernel takes the same schedule), times the updates those
+    frames made in the launch; for the flooding frames 3 s_c + s_v + 2 s_v N / E per edge-update.
+    Bound: the memory the frame state lives in under the launch's plan."""
+    import torch
+    s_c, s_v, s_d = (4, 4, 4) if name == "f32" else (1, 2, 2)
+    rng = np.random.default_rng(7)
+    code_arr, kind_arr = frames["code"], frames["kind"]
+    total = 0.0
+    per = {}
+    for c, code in enumerate(codes):
+        n = code.N
+        for kv, kname in ((ldpc.RBP, "rbp"), (ldpc.CIRBP, "cirbp")):
+            sel = np.flatnonzero((code_arr == c) & (kind_arr == kv))
+            if len(sel) == 0:
+                continue
+            pick = np.sort(rng.choice(sel, min(32, len(sel)), replace=False))
+            llr_s = torch.stack([llr_pool[int(o):int(o) + n] for o in frames["llr_off"][pick]])
+            with torch.cuda.stream(stream):
+                r = ldpc.decode(hs[c], llr_s, kv, arith, max_updates=3 * code.E, gamma=0.1, q_bits=q, frac_bits=f,
+                                trace=True, stream=stream)
+            torch.cuda.synchronize()
+            used = r.updates_used.cpu().numpy()
+            tr = r.trace.cpu().numpy()
+            table = lds_bytes_per_update_table(code, s_c, s_v, s_d, ci=kv == ldpc.CIRBP)
+            b = sum(int(table[tr[x, :used[x]]].sum()) for x in range(len(pick)))
+            mean_b = b / max(int(used.sum()), 1)
+            total += mean_b * float(upd_np[sel].sum())
+            per[f"{kname}_z{code.N // 24}_mb{code.M // (code.N // 24)}"] = round(mean_b, 1)
+        fsel = (code_arr == c) & (kind_arr == ldpc.FLOODING)
+        total += float(upd_np[fsel].sum()) * (3 * s_c + s_v + 2 * s_v * code.N / code.E)
+    pd = ldpc.describe_batch_plan(hs, len(frames), arith, q, f)
+    achieved = total / kern_s / 1e9
+    bound_lds = pd["storage_name"] == "lds"
+    peak = LDS_PEAK_GBS if bound_lds else HBM_PEAK_GBS
+    return {"bound": "lds" if bound_lds else "hbm", "achieved": round(achieved, 2), "peak": round(peak, 1),
+            "unit": "GB/s", "frac": round(achieved / peak, 6), "traffic": None,
+            "kernel": f"k_batch<{'ArithF32' if name == 'f32' else 'ArithFix'}, {pd['storage_name']} storage, "
+                      f"{pd['topology_name']} topology> (one frame per wavefront, {pd['grid']} workgroups, work queue)",
+            "algorithmic_bytes_per_launch": round(total, 1), "kernel_ms_avg": round(kern_s * 1e3, 3),
+            "lds_frac": round(achieved / LDS_PEAK_GBS, 6), "bytes_per_update_sampled": per}
+
+
+def batched_cpu_baseline(codes, frames, llr_pool, arith, q, f, args):
+    """The oracle on a random sample of the batch's descriptors (the batch draws code, schedule and
+    Eb/N0 uniformly, so the sample follows the same mix), one frame per call."""
+    from oracle import oracle as O
+    from paper_2102_11089_amd import ldpc
+    rng = np.random.default_rng(11)
+    pick = rng.choice(len(frames), min(4096, len(frames)), replace=False)
+    okind = {ldpc.FLOODING: O.FLOODING, ldpc.RBP: O.RBP, ldpc.CIRBP: O.CIRBP}
+    oar = O.SPA if arith == ldpc.SPA_F32 else O.MSFIX
+    host = {}
+    for x in pick:
+        d = frames[x]
+        n = codes[int(d["code"])].N
+        host[int(x)] = llr_pool[int(d["llr_off"]):int(d["llr_off"]) + n].cpu().numpy().astype(np.float64)
+
+    def jobs():
+        for x in pick:
+            d = frames[x]
+
+            def one(d=d, x=int(x)):
+                r = O.decode(codes[int(d["code"])], host[x][None], okind[int(d["kind"])], oar,
+                             max_updates=int(d["max_updates"]), gamma=0.1, q_bits=q, frac_bits=f)
+                return 1, int(r.updates_used.sum())
+            yield one
+    return cpu_baseline_entry(jobs, args.cpu_seconds,
+                              "randomly drawn descriptors of the batch (uniform code, schedule, Eb/N0), "
+                              + ("FP64 sum-product" if arith == ldpc.SPA_F32 else f"min-sum q={q} f={f}"))
+
+
 def bench_batched(args, ldpc, S, dev):
     """Workload c2: one persistent launch over uneven codes, schedules and SNRs."""
     import torch
@@ -447,6 +595,7 @@ def bench_batched(args, ldpc, S, dev):
                 d[2] += int(sum(upd_by_off[int(x)] for x in offs[fr][sel]))
         tot_upd = int(upd_np.sum())
         kern_s = float(np.mean(kms)) / 1e3
+        roof = batched_roofline(ldpc, codes, hs, frames, llr_pool, upd_np, kern_s, arith, q, f, name, stream)
         out = {"metric": "decoded frames/s, one persistent launch over uneven codes and schedules",
                "value": round(F / kern_s, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
                "warmup": args.warmup, "ms_per_step": round(1e3 * wall / args.steps, 3), "higher_is_better": True,
@@ -460,7 +609,10 @@ def bench_batched(args, ldpc, S, dev):
                "launch_tuning": {"autotuned_on_frames": len(sample), "knobs": knobs,
                                  "default_policy_frames_per_s": round(F / (default_ms / 1e3), 1)},
                "per_schedule": {k: {"frames": v[0], "fer": v[1] / max(v[0], 1), "mean_updates": v[2] / max(v[0], 1)}
-                                for k, v in per_kind.items()}}
+                                for k, v in per_kind.items()},
+               "roofline": roof}
+        if not args.no_cpu:
+            out["cpu_baseline"] = batched_cpu_baseline(codes, frames, llr_pool, arith, q, f, args)
         print(json.dumps(out), flush=True)
 
 
@@ -765,19 +917,22 @@ def main():
             fe_b, nf_b, upd_b, _ = summarize(res_b, code)
             out[name] = {"fer": fe_b / nf_b, "frame_errors": fe_b, "frames_per_s": round(nf_b / wall_b, 3),
                          "edge_updates_per_s": round(upd_b / wall_b, 1),
-                         "mean_iterations": upd_b / nf_b / E, "cap_iterations": 50}
+                         "mean_iterations": upd_b / nf_b / E, "cap_iterations": 50,
+                         "roofline": baseline_roofline(ldpc, h, code, kind, args.frames, upd_b, sum(kms_b) / 1e3)}
         out["ci_over_flooding_frames_per_s"] = round(ci_fps / out["flooding"]["frames_per_s"], 5)
 
     if not args.no_cpu:
-        threads = max(1, min(16, os.cpu_count() or 1))
-        cw_h = timed_batches[0][0].cpu().numpy()
-        llr_h = timed_batches[0][1][:512].cpu().numpy().astype(np.float64)
-        nf_c, upd_c, dt_c = cpu_baseline(code, llr_h, cw_h, cap_ci, args.cpu_seconds, threads)
-        out["cpu_baseline"] = {"value": round(nf_c / dt_c, 4), "unit": "frames/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"first {nf_c} frames of the first timed batch, CIRBP gamma=0.1 cap 3E, "
-                                         f"FP64, {threads} threads, {dt_c:.1f} s",
-                               "edge_updates_per_s": round(upd_c / dt_c, 1)}
+        from oracle import oracle as O
+        llr_h = timed_batches[0][1][:1024].cpu().numpy().astype(np.float64)
+
+        def jobs():
+            for f in range(len(llr_h)):
+                def one(f=f):
+                    r = O.decode(code, llr_h[f:f + 1], O.CIRBP, O.SPA, max_updates=cap_ci, gamma=0.1)
+                    return 1, int(r.updates_used.sum())
+                yield one
+        out["cpu_baseline"] = cpu_baseline_entry(
+            jobs, args.cpu_seconds, "frames of the first timed batch in order, CIRBP gamma=0.1 cap 3E, FP64")
     print(json.dumps(out), flush=True)
 
 

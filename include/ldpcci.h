@@ -305,7 +305,8 @@ int ldpc_get_tuning(const ldpc_code* code, int32_t kind, int32_t arith, ldpc_tun
    for ldpc_decode.  Errors: LDPC_EINVAL (null pointer, B < 1, bad schedule), LDPC_ECAPACITY,
    LDPC_EUNSUPPORTED (as ldpc_decode would return them), LDPC_EHIP. */
 typedef struct {
-  int32_t kernel;               /* 0 flooding / layered, 1 single-edge (RBP, CIRBP, replay), 2 ME-CIRBP */
+  int32_t kernel;               /* 0 flooding / layered, 1 single-edge (RBP, CIRBP, replay), 2 ME-CIRBP,
+                                   3 batched (ldpc_describe_batch_plan)                                  */
   int32_t storage;              /* LDPC_STORE_* chosen (never AUTO); flooding / layered: LDS           */
   int32_t topology;             /* LDPC_TOPO_* chosen (never AUTO); flooding / layered: GLOBAL         */
   int32_t block;                /* threads per workgroup                                               */
@@ -321,6 +322,14 @@ typedef struct {
 } ldpc_plan_info;
 
 int ldpc_describe_plan(const ldpc_code* code, const ldpc_schedule* s, int32_t B, ldpc_plan_info* info);
+
+/* The launch ldpc_decode_batch would make for F frames over these codes with this schedule's
+   arithmetic (and the tuning of ldpc_set_batch_tuning, if set), without decoding: kernel = 3
+   (batched; one frame per workgroup of one wavefront), the storage mode and topology source chosen
+   for the largest code, the frames per CU the LDS layout allows (workgroups_per_cu), grid, LDS and
+   scratch bytes.  Errors: LDPC_EINVAL, LDPC_EUNSUPPORTED, LDPC_ECAPACITY, LDPC_EHIP. */
+int ldpc_describe_batch_plan(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s, int32_t F,
+                             ldpc_plan_info* info);
 
 /* Project autotuner: times every distinct launch plan the knobs give for this schedule on the
    caller's frames (llr_in: device [B][N]; best of reps timed runs after one warm-up, HIP events on

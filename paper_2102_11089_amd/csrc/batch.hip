@@ -30,7 +30,7 @@ __device__ __forceinline__ void store_sync() {
 // global slot, or the VN records)
 template <class A, int STORE, class Topo>
 __device__ __forceinline__ void wave_baseline_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
-                                                    const MsgStore<A, STORE>& ms, const FrameJob& J) {
+                                                    const FrameStore<A, STORE>& ms, const FrameJob& J) {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   using val_t = typename A::val_t;

@@ -43,7 +43,7 @@ __device__ __forceinline__ size_t frame_slot(const DynParams& P) {
 // 8-byte (Lt, L) record per VN with D evaluated from it).  A frame is read and written by its own
 // wavefront only, so lanes
 // exchange values through global memory under the wavefront's program order (wave_sync).
-template <class A, int STORE, bool PAIRS = (STORE >= STORE_ALL_GLOBAL)>
+template <class A, int STORE, bool PAIRS = (STORE >= STORE_ALL_GLOBAL), bool STREAM = false>
 struct MsgStore {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
@@ -86,8 +86,8 @@ struct alignas(8) VnRec {
   llr_t l;
 };
 
-template <class A, int STORE>
-struct MsgStore<A, STORE, true> {
+template <class A, int STORE, bool STREAM>
+struct MsgStore<A, STORE, true, STREAM> {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   static constexpr bool kRec = STORE == STORE_FRAME_REC || STORE == STORE_FRAME_ALL;
@@ -99,10 +99,12 @@ struct MsgStore<A, STORE, true> {
   VnRec<llr_t>* r;    // STORE_FRAME_REC, [N]
   __device__ __forceinline__ msg_t c(int e) const { return m[e].c; }
   __device__ __forceinline__ msg_t p(int e) const { return m[e].p; }
-  // Frames whose whole state lives in global memory exceed the L2 and MALL by far; their message
-  // pairs are read and written with the non-temporal hint, which leaves the caches to the VN
-  // records and the code's tables (c1: 3.6% more frames/s; the same hint on the records cost 12%)
-  static constexpr bool kStream = STORE >= STORE_FRAME_GLOBAL;
+  // STREAM: the per-code kernel's frames whose whole state lives in global memory exceed the L2
+  // and MALL by far; their message pairs are read and written with the non-temporal hint, which
+  // leaves the caches to the VN records and the code's tables (c1: 3.6% more frames/s; the same
+  // hint on the records cost 12%).  The batched kernel's mix of small codes keeps part of its
+  // pairs in the caches and goes without it (the hint cost it 11-18%).
+  static constexpr bool kStream = STREAM && STORE >= STORE_FRAME_GLOBAL;
   using pair_bits_t = typename std::conditional<sizeof(MsgPair<msg_t>) == 8, unsigned long long, unsigned short>::type;
   __device__ __forceinline__ void set_c(int e, msg_t v) const {
     if constexpr (kStream) __builtin_nontemporal_store(v, &m[e].c);
@@ -168,12 +170,15 @@ struct MsgStore<A, STORE, true> {
 
 // message store of the workgroup's frame slot (slot_edges = edges reserved per workgroup when
 // only pre is global; the pair-slot layout comes from P.slot_bytes and the slot offsets)
-template <class A, int STORE>
-__device__ __forceinline__ MsgStore<A, STORE> make_store(const DynParams& P, size_t slot_edges) {
+template <class A, int STORE, bool STREAM = false>
+using FrameStore = MsgStore<A, STORE, (STORE >= STORE_ALL_GLOBAL), STREAM>;
+
+template <class A, int STORE, bool STREAM = false>
+__device__ __forceinline__ FrameStore<A, STORE, STREAM> make_store(const DynParams& P, size_t slot_edges) {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   unsigned char* lds = frame_lds(P);
-  MsgStore<A, STORE> ms;
+  FrameStore<A, STORE, STREAM> ms;
   ms.Lp = reinterpret_cast<llr_t*>(lds + P.off_L);
   ms.Dp = reinterpret_cast<uint32_t*>(lds + P.off_D);
   ms.Lt = reinterpret_cast<llr_t*>(lds + P.off_Lt);
@@ -210,9 +215,9 @@ __device__ __forceinline__ void leaf_moved(uint64_t* blk, uint32_t* mask, int b,
 
 // LMD: the variant for the LMD schedules (a separate instantiation, so that the others keep their
 // register budget); J.kind must then be one of them
-template <class A, int STORE, class Topo, bool LMD = false>
+template <class A, int STORE, class Topo, bool LMD = false, bool STREAM = false>
 __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G, const A& ar, const DynParams& P,
-                                                 const MsgStore<A, STORE>& ms, const FrameJob& J) {
+                                                 const FrameStore<A, STORE, STREAM>& ms, const FrameJob& J) {
   using msg_t = typename A::msg_t;
   using llr_t = typename A::llr_t;
   using val_t = typename A::val_t;
@@ -253,7 +258,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
   // CI of VN n: stored, or evaluated from the VN's record (record layouts); RBP and the residual
   // LMD schedules keep none
   auto d_of = [&](int n) -> uint32_t {
-    if constexpr (MsgStore<A, STORE>::kDerivedD) {
+    if constexpr (FrameStore<A, STORE, STREAM>::kDerivedD) {
       llr_t ltv, lv;
       ms.lt_l(n, ltv, lv);
       return with_ci ? ar.ci((val_t)lv, (val_t)ltv) : 0u;

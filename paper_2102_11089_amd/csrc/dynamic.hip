@@ -43,7 +43,7 @@ template <class A, int STORE, int TOPO, bool MF, bool LMD>
 __global__ __launch_bounds__(MF ? 1024 : WAVE) void k_dynamic(DevCode H, DynParams P) {
   unsigned char* lds = dyn_lds();
   const int lane = threadIdx.x & (WAVE - 1);
-  const auto ms = make_store<A, STORE>(P, (size_t)H.E);
+  const auto ms = make_store<A, STORE, true>(P, (size_t)H.E);
   // shared by the workgroup's frames: the p0 table and the topology
   int* lut = reinterpret_cast<int*>(lds + P.off_lut);
   A ar;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(MF ? 1024 : WAVE) void k_dynamic(DevCode H, DynPara
     J.dump_L = P.out.dump_L ? P.out.dump_L + (size_t)f * H.N : nullptr;
     J.dump_Lt = P.out.dump_Lt ? P.out.dump_Lt + (size_t)f * H.N : nullptr;
     J.dump_D = P.out.dump_D ? P.out.dump_D + (size_t)f * H.N : nullptr;
-    dyn_decode_frame<A, STORE, decltype(G), LMD>(H, G, ar, P, ms, J);
+    dyn_decode_frame<A, STORE, decltype(G), LMD, true>(H, G, ar, P, ms, J);
     if (P.queue) f = uni(lane == 0 ? atomicAdd(P.queue, 1) : 0);
     else f += gridDim.x * P.wpb;
   }

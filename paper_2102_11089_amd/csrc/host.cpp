@@ -1493,23 +1493,30 @@ int ldpc_tuning_load(const char* path) {
 namespace {
 
 // ldpc_decode_batch with an explicit tuning (nullable: the default policy)
-int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
-                       const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
-                       uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
-                       int64_t* steps_used, int64_t* fallbacks, void* stream, const ldpc_tuning* T) {
-  static_assert(sizeof(ldpc_frame_desc) == sizeof(BatchFrame), "descriptor layout");
-  if (!codes || n_codes < 1 || n_codes > 64 || !s || F < 0 || llr_len < 0 || out_len < 0) return LDPC_EINVAL;
+// A batched launch resolved: storage mode, topology source, LDS layout of the largest code,
+// resident frames per CU, grid and scratch bytes.
+struct BatchPlan {
+  bool fixed = false;
+  int store = -1, topo = TOPO_GLOBAL, per_cu = 0, grid = 0, lds_limit = 0;
+  Dims mx{0, 0, 0, 0, 0};
+  DynLayout Ly{};
+  size_t pre_bytes = 0;
+  DynParams slot{};  // slot offsets when the frame state is global
+};
+
+int plan_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s, int32_t F,
+               const ldpc_tuning* T, BatchPlan& bp) {
+  if (!codes || n_codes < 1 || n_codes > 64 || !s || F < 0) return LDPC_EINVAL;
   if (int rc = check_batch_tuning(T)) return rc;
-  if (F == 0) return LDPC_OK;
-  if (!frames || !llr_pool || !bits_pool || !updates_used) return LDPC_EINVAL;
   if (s->arith != LDPC_SPA_F32 && s->arith != LDPC_MS_FIX) return LDPC_EINVAL;
-  const bool fixed = s->arith == LDPC_MS_FIX;
-  if (fixed && (s->q_bits < 2 || s->q_bits > 8 || s->frac_bits < 0 || s->frac_bits > 6)) return LDPC_EINVAL;
+  bp = BatchPlan{};
+  bp.fixed = s->arith == LDPC_MS_FIX;
+  if (bp.fixed && (s->q_bits < 2 || s->q_bits > 8 || s->frac_bits < 0 || s->frac_bits > 6)) return LDPC_EINVAL;
   if (s->check_every < 0) return LDPC_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return LDPC_EHIP;
   bool all_qc = true;
-  Dims mx{0, 0, 0, 0, 0};
+  Dims& mx = bp.mx;
   for (int i = 0; i < n_codes; ++i) {
     const ldpc_code* c = codes[i];
     if (!c || c->device != dev) return LDPC_EINVAL;
@@ -1520,27 +1527,52 @@ int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldp
     mx.M = std::max(mx.M, c->M);
     mx.nbr_passes = std::max(mx.nbr_passes, (c->nbr_max_cnt + WAVE - 1) / WAVE);
   }
-  const int topo = all_qc ? TOPO_QC : TOPO_GLOBAL;
-  for (int i = 0; i < n_codes; ++i) mx.topo_bytes = std::max(mx.topo_bytes, topo_bytes(codes[i], topo));
-  const int lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
+  bp.topo = all_qc ? TOPO_QC : TOPO_GLOBAL;
+  for (int i = 0; i < n_codes; ++i) mx.topo_bytes = std::max(mx.topo_bytes, topo_bytes(codes[i], bp.topo));
+  bp.lds_limit = std::min(device_lds_limit(dev), 160 * 1024);
   const int ncu = device_cu_count(dev);
   // message storage: the mode that keeps the most frames resident per CU (at most 32); ties go to
   // the later mode of the list (the batch is a large persistent launch: messages global, then VN
   // records over split arrays)
-  int store = -1, best_fit = 0;
-  DynLayout Ly{};
+  int best_fit = 0;
   for (int st : {STORE_LDS, STORE_PRE_GLOBAL, STORE_FRAME_GLOBAL, STORE_FRAME_REC, STORE_ALL_GLOBAL_LT, STORE_ALL_GLOBAL}) {
     if (T && T->storage != LDPC_STORE_AUTO && st != T->storage - 1) continue;  // LDPC_STORE_* = Store + 1
-    DynLayout cand = dyn_layout_dims(mx, fixed, st, 1);
-    if (cand.total > lds_limit) continue;
+    DynLayout cand = dyn_layout_dims(mx, bp.fixed, st, 1);
+    if (cand.total > bp.lds_limit) continue;
     const int fit = std::min(32, (160 * 1024) / std::max(cand.total, 1));
-    if (store < 0 || fit >= best_fit) {
-      store = st;
+    if (bp.store < 0 || fit >= best_fit) {
+      bp.store = st;
       best_fit = fit;
-      Ly = cand;
+      bp.Ly = cand;
     }
   }
-  if (store < 0) return LDPC_ECAPACITY;
+  if (bp.store < 0) return LDPC_ECAPACITY;
+  bp.per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(bp.Ly.total, 1)));
+  if (T && T->frames_per_cu) bp.per_cu = std::min(bp.per_cu, T->frames_per_cu);
+  bp.grid = (int)std::min<long long>(std::max(F, 1), (long long)ncu * bp.per_cu);
+  // scratch: the work-queue counter and the frame slots if needed
+  if (bp.store == STORE_PRE_GLOBAL) bp.pre_bytes = (size_t)bp.grid * mx.E * (bp.fixed ? 1 : 4);
+  if (bp.store >= STORE_ALL_GLOBAL) {
+    all_global_slot(mx.E, mx.N, mx.M, mx.nbr_passes, bp.fixed, bp.store, bp.slot);
+    bp.pre_bytes = (size_t)bp.grid * (size_t)bp.slot.slot_bytes;
+  }
+  return LDPC_OK;
+}
+
+// ldpc_decode_batch with an explicit tuning (nullable: the default policy)
+int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s,
+                       const ldpc_frame_desc* frames, int32_t F, const float* llr_pool, int64_t llr_len,
+                       uint8_t* bits_pool, float* llr_out_pool, int64_t out_len, int64_t* updates_used,
+                       int64_t* steps_used, int64_t* fallbacks, void* stream, const ldpc_tuning* T) {
+  static_assert(sizeof(ldpc_frame_desc) == sizeof(BatchFrame), "descriptor layout");
+  if (!codes || n_codes < 1 || n_codes > 64 || !s || F < 0 || llr_len < 0 || out_len < 0) return LDPC_EINVAL;
+  if (int rc = check_batch_tuning(T)) return rc;
+  if (F == 0) return LDPC_OK;
+  if (!frames || !llr_pool || !bits_pool || !updates_used) return LDPC_EINVAL;
+  BatchPlan bp;
+  if (int rc = plan_batch(codes, n_codes, s, F, T, bp)) return rc;
+  const bool fixed = bp.fixed;
+  const DynLayout& Ly = bp.Ly;
   hipStream_t st = (hipStream_t)stream;
   BatchParams B{};
   DynParams& P = B.P;
@@ -1556,6 +1588,14 @@ int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldp
   P.frame_base = Ly.frame_base;
   P.frame_stride = Ly.frame_stride;
   P.wpb = 1;
+  if (bp.store >= STORE_ALL_GLOBAL) {
+    P.slot_bytes = bp.slot.slot_bytes;
+    P.slot_lt_off = bp.slot.slot_lt_off;
+    P.slot_l_off = bp.slot.slot_l_off;
+    P.slot_d_off = bp.slot.slot_d_off;
+    P.slot_ckey_off = bp.slot.slot_ckey_off;
+    P.slot_tj_off = bp.slot.slot_tj_off;
+  }
   B.n_codes = n_codes;
   B.frames = reinterpret_cast<const BatchFrame*>(frames);
   B.F = F;
@@ -1567,25 +1607,15 @@ int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldp
   B.updates_used = updates_used;
   B.steps_used = steps_used;
   B.fallbacks = fallbacks;
-  B.max_E = mx.E;
-  int per_cu = std::max(1, std::min(32, (160 * 1024) / std::max(Ly.total, 1)));
-  if (T && T->frames_per_cu) per_cu = std::min(per_cu, T->frames_per_cu);
-  const int grid = (int)std::min<long long>(F, (long long)ncu * per_cu);
-  // scratch: the work-queue counter and pre[] slots if needed
-  size_t pre_bytes = 0;
-  if (store == STORE_PRE_GLOBAL) pre_bytes = (size_t)grid * mx.E * (fixed ? 1 : 4);
-  if (store >= STORE_ALL_GLOBAL) {
-    all_global_slot(mx.E, mx.N, mx.M, mx.nbr_passes, fixed, store, P);
-    pre_bytes = (size_t)grid * (size_t)P.slot_bytes;
-  }
+  B.max_E = bp.mx.E;
   void* scratch = nullptr;
-  hipError_t he = scratch_alloc(&scratch, 256 + pre_bytes, st);
+  hipError_t he = scratch_alloc(&scratch, 256 + bp.pre_bytes, st);
   if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
   for (int i = 0; i < n_codes; ++i) B.codes[i] = codes[i]->d_self;
   B.queue = reinterpret_cast<int*>(scratch);
-  P.pre_global = store != STORE_LDS ? (char*)scratch + 256 : nullptr;
-  he = raise_lds_limit(FAM_BATCH, lds_limit, set_batch_lds_limit);
-  if (he == hipSuccess) he = launch_batch(B, fixed, store, topo, grid, st);
+  P.pre_global = bp.store != STORE_LDS ? (char*)scratch + 256 : nullptr;
+  he = raise_lds_limit(FAM_BATCH, bp.lds_limit, set_batch_lds_limit);
+  if (he == hipSuccess) he = launch_batch(B, fixed, bp.store, bp.topo, bp.grid, st);
   (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);
 }
@@ -1607,6 +1637,33 @@ int ldpc_decode_batch(const ldpc_code* const* codes, int32_t n_codes, const ldpc
   }
   return decode_batch_tuned(codes, n_codes, s, frames, F, llr_pool, llr_len, bits_pool, llr_out_pool, out_len,
                             updates_used, steps_used, fallbacks, stream, tuned ? &t : nullptr);
+}
+
+int ldpc_describe_batch_plan(const ldpc_code* const* codes, int32_t n_codes, const ldpc_schedule* s, int32_t F,
+                             ldpc_plan_info* info) {
+  if (!info || F < 1) return LDPC_EINVAL;
+  ldpc_tuning t{};
+  bool tuned = false;
+  {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    tuned = g_btune_set;
+    t = g_btune;
+  }
+  BatchPlan bp;
+  if (int rc = plan_batch(codes, n_codes, s, F, tuned ? &t : nullptr, bp)) return rc;
+  ldpc_plan_info r{};
+  r.kernel = 3;
+  r.storage = bp.store + 1;
+  r.topology = bp.topo + 1;
+  r.block = WAVE;
+  r.grid = bp.grid;
+  r.frames_per_workgroup = 1;
+  r.workgroups_per_cu = bp.per_cu;
+  r.persistent = 1;
+  r.lds_bytes = bp.Ly.total;
+  r.scratch_bytes = (int64_t)(256 + bp.pre_bytes);
+  *info = r;
+  return LDPC_OK;
 }
 
 int ldpc_set_batch_tuning(const ldpc_tuning* t) {

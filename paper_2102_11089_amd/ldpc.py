@@ -28,7 +28,7 @@ ERRORS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_ENOMEM", -3: "LDPC_EHIP", -
 
 EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_code_rank", "ldpc_code_free",
            "ldpc_decode", "ldpc_decode_noalloc",
-           "ldpc_decode_batch", "ldpc_describe_plan", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune",
+           "ldpc_decode_batch", "ldpc_describe_plan", "ldpc_describe_batch_plan", "ldpc_set_tuning", "ldpc_get_tuning", "ldpc_autotune",
            "ldpc_set_batch_tuning", "ldpc_get_batch_tuning", "ldpc_autotune_batch", "ldpc_tuning_save",
            "ldpc_tuning_load", "ldpc_awgn_frames", "ldpc_sweep_create", "ldpc_sweep_run", "ldpc_sweep_free",
            "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
@@ -111,6 +111,9 @@ def load(path: str = LIB_PATH):
     lib.ldpc_decode_batch.restype = C.c_int
     lib.ldpc_describe_plan.argtypes = [P, C.POINTER(ldpc_schedule), C.c_int32, C.POINTER(ldpc_plan_info)]
     lib.ldpc_describe_plan.restype = C.c_int
+    lib.ldpc_describe_batch_plan.argtypes = [P, C.c_int32, C.POINTER(ldpc_schedule), C.c_int32,
+                                             C.POINTER(ldpc_plan_info)]
+    lib.ldpc_describe_batch_plan.restype = C.c_int
     lib.ldpc_set_tuning.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(ldpc_tuning)]
     lib.ldpc_set_tuning.restype = C.c_int
     lib.ldpc_get_tuning.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(ldpc_tuning)]
@@ -243,6 +246,14 @@ def ldpc_decode_batch(handles, schedule: ldpc_schedule, frames_ptr: int, F: int,
 def ldpc_describe_plan(handle, s: ldpc_schedule, B: int) -> ldpc_plan_info:
     info = ldpc_plan_info()
     _check(load().ldpc_describe_plan(handle, C.byref(s), B, C.byref(info)), "ldpc_describe_plan")
+    return info
+
+
+def ldpc_describe_batch_plan(handles, s: ldpc_schedule, F: int) -> ldpc_plan_info:
+    info = ldpc_plan_info()
+    arr = (C.c_void_p * len(handles))(*handles)
+    _check(load().ldpc_describe_batch_plan(arr, len(handles), C.byref(s), F, C.byref(info)),
+           "ldpc_describe_batch_plan")
     return info
 
 
@@ -595,6 +606,16 @@ def describe_plan(code: Code, B: int, kind: int, arith: int = SPA_F32, gamma: fl
     topology are also given by name."""
     s = schedule(kind, arith, gamma, q_bits, frac_bits, n_p, n_g, fill, 0, check_every)
     d = ldpc_describe_plan(code.handle, s, B).as_dict()
+    d["storage_name"] = STORE_NAMES.get(d["storage"], "?")
+    d["topology_name"] = TOPO_NAMES.get(d["topology"], "?")
+    return d
+
+
+def describe_batch_plan(codes, F: int, arith: int = SPA_F32, q_bits: int = 6, frac_bits: int = 1,
+                        check_every: int = 1) -> dict:
+    """The launch ``decode_batch`` would use for F frames over these codes (on the current device)."""
+    s = schedule(0, arith, 0.0, q_bits, frac_bits, 1, 16, 0, 0, check_every)
+    d = ldpc_describe_batch_plan([c.handle for c in codes], s, F).as_dict()
     d["storage_name"] = STORE_NAMES.get(d["storage"], "?")
     d["topology_name"] = TOPO_NAMES.get(d["topology"], "?")
     return d
