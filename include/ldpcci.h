@@ -76,12 +76,10 @@ extern "C" {
    the remaining n_p - |P'| (Algorithm 6 names |P| there; this is the count that keeps the set at
    n_p).  Sets are sent in ascending VN order, as for LDPC_ME_CIRBP. */
 #define LDPC_ME_LMD_CIRBP 9
-/* Reproducibility: the single-edge schedules, flooding, layered and the batched launch give a
-   frame the same outputs on every run and in every launch shape (tested bit for bit).  The two
-   multi-edge schedules do so in LDPC_MS_FIX only.  In LDPC_SPA_F32 several checks updated in one
-   step can change the precomputed total LLR of the same VN, and those float changes are added in
-   the order the checks finish.  A rerun can then differ in the last bits of some values, and at a
-   near-tie of two metrics in the updates chosen after it. */
+/* Reproducibility: every schedule gives a frame the same outputs on every run and in every launch
+   shape (tested bit for bit), in both arithmetics.  In the multi-edge schedules several checks
+   updated in one step can change the precomputed total LLR of the same VN; in LDPC_SPA_F32 those
+   changes are summed per VN in ascending check order. */
 
 /* arithmetic */
 #define LDPC_SPA_F32 0  /* sum-product, FP32 messages                                          */

@@ -220,7 +220,7 @@ DynLayout dyn_layout(const ldpc_code* c, bool fixed, int store, int topo, int wp
 // LDS layout of the multi-edge decoder; returns the total bytes
 struct MeLayout {
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;
-  int off_cand, off_misc, off_lut, off_topo, off_rows2, total, rows_cap, cand_cap;
+  int off_cand, off_misc, off_lut, off_topo, off_rows2, off_vnmulti, total, rows_cap, cand_cap;
 };
 
 // LDS of the unrolled kernels: forward (c2v, L); backward adds the adjoints and the segment tape
@@ -253,6 +253,7 @@ MeLayout me_layout(const ldpc_code* c, bool fixed, bool msg_global, int topo, in
   L.off_synw = o; o = align16(o + nsw * 4);
   L.off_rowmark = o; o = align16(o + nsw * 4);
   L.off_vnmark = o; o = align16(o + nvw * 4);
+  L.off_vnmulti = o; o = align16(o + nvw * 4);  // VNs that two or more checks of a step change
   L.off_rows = o; o = align16(o + L.rows_cap * 4);
   L.off_rows2 = o; o = align16(o + L.rows_cap * 4);  // the same checks sorted by block size
   L.off_sel = o; o = align16(o + 5 * 64 * 4);  // set, sorted set, class counters, P', m* per VN
@@ -944,7 +945,8 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     Q.off_c2v = Ly.off_c2v; Q.off_pre = Ly.off_pre; Q.off_L = Ly.off_L; Q.off_Lt = Ly.off_Lt; Q.off_D = Ly.off_D;
     Q.off_hist = Ly.off_hist; Q.off_synw = Ly.off_synw; Q.off_rowmark = Ly.off_rowmark; Q.off_vnmark = Ly.off_vnmark;
     Q.off_rows = Ly.off_rows; Q.off_sel = Ly.off_sel; Q.off_cand = Ly.off_cand; Q.off_misc = Ly.off_misc;
-    Q.off_lut = Ly.off_lut; Q.off_topo = Ly.off_topo; Q.off_rows2 = Ly.off_rows2; Q.lds_bytes = Ly.total;
+    Q.off_lut = Ly.off_lut; Q.off_topo = Ly.off_topo; Q.off_rows2 = Ly.off_rows2; Q.off_vnmulti = Ly.off_vnmulti;
+    Q.lds_bytes = Ly.total;
     Q.rows_cap = Ly.rows_cap;
     Q.cand_cap = Ly.cand_cap;
     Q.prof = nullptr;
@@ -958,10 +960,18 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
       const int fit = std::max(1, lds_per_cu / std::max(Q.lds_bytes, 1));
       const int per_cu = T.frames_per_cu ? std::min(T.frames_per_cu, fit) : fit;
       pl.grid = (int)std::min<long long>(B, (long long)ncu * per_cu);
+    } else if (!fixed) {
+      // one workgroup per frame, up to four rounds of the workgroups a CU holds (each holds a
+      // global slot for its step changes)
+      const int fit = std::max(1, lds_per_cu / std::max(Q.lds_bytes, 1));
+      pl.grid = (int)std::min<long long>(B, 4LL * ncu * fit);
     } else {
       pl.grid = B;
     }
-    if (pl.store != STORE_LDS) pl.scratch_bytes = (size_t)std::max(pl.grid, 1) * 2 * c->E * (fixed ? 1 : 4);
+    // per workgroup: the (c2v, pre) pairs when they are not in LDS; in FP32 the step's changes of
+    // the precomputed messages, one float per edge (summed per VN in a fixed order)
+    const size_t per_wg = (pl.store != STORE_LDS ? (size_t)2 * c->E * (fixed ? 1 : 4) : 0) + (fixed ? 0 : (size_t)4 * c->E);
+    pl.scratch_bytes = (size_t)std::max(pl.grid, 1) * per_wg;
     return LDPC_OK;
   }
 
@@ -1139,6 +1149,8 @@ hipError_t enqueue_decode(const ldpc_code* c, DecodePlan& pl, void* scratch, hip
   if (pl.which == 2) {
     const bool mg = pl.store != STORE_LDS;
     pl.me.msg_global = mg ? scratch : nullptr;
+    pl.me.dbuf = pl.fixed ? nullptr
+                          : reinterpret_cast<float*>((char*)scratch + (mg ? (size_t)pl.grid * 2 * c->E * 4 : 0));
     return launch_me(c->dev, pl.me, pl.fixed, mg, pl.topo, pl.grid, pl.block, st);
   }
   pl.dyn.queue = pl.persistent ? reinterpret_cast<int*>(scratch) : nullptr;
@@ -1229,8 +1241,8 @@ int fit_plan_to_scratch(const ldpc_code* c, DecodePlan& pl, size_t cap) {
     const size_t msg = pl.fixed ? 1 : 4;
     if (pl.store == STORE_PRE_GLOBAL) per_wg = (size_t)pl.dyn.wpb * c->E * msg;
     else if (pl.store >= STORE_ALL_GLOBAL) per_wg = (size_t)pl.dyn.wpb * (size_t)pl.dyn.slot_bytes;
-  } else if (pl.which == 2 && pl.store != STORE_LDS) {
-    per_wg = (size_t)2 * c->E * (pl.fixed ? 1 : 4);
+  } else if (pl.which == 2) {
+    per_wg = (pl.store != STORE_LDS ? (size_t)2 * c->E * (pl.fixed ? 1 : 4) : 0) + (pl.fixed ? 0 : (size_t)4 * c->E);
   }
   if (per_wg == 0 || cap < head + per_wg) return LDPC_ECAPACITY;
   const size_t grid = std::min<size_t>((size_t)pl.grid, (cap - head) / per_wg);

@@ -202,8 +202,9 @@ struct MeParams {
   int lmd;                  // ME-LMD-CIRBP (Algorithm 6): the next set starts from the proposals
   unsigned long long seed;
   void* msg_global;         // grid x 2E messages (c2v then pre) when they are not in LDS
+  float* dbuf;              // FP32: grid x E changes of the precomputed messages of one step
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;
-  int off_cand, off_misc, off_lut, off_topo, off_rows2;
+  int off_cand, off_misc, off_lut, off_topo, off_rows2, off_vnmulti;
   int lds_bytes;
   int rows_cap, cand_cap;
   long long* prof;          // development builds only: per-phase cycle sums (null otherwise)

@@ -11,7 +11,8 @@
 //   3. for each p in P (ascending): the incoming edge of largest residual (Algorithm 1);
 //   4. all propagations c2v <- pre, L_p += delta, syndrome toggles;
 //   5. every check of every p recomputed from the new state (one lane per check, each check once),
-//      Lt updated by the precompute deltas; then D (and its group) of every VN of those checks;
+//      Lt updated by the precompute deltas (FP32: kept per edge and summed per VN in ascending
+//      check order, so that reruns round alike); then D (and its group) of every VN of those checks;
 //   6. ME-LMD-CIRBP only: each p proposes the VN of largest CI among U(m*_p, p) (N(m*_p) \ p when p
 //      has degree 1); the distinct proposals P' start the next set, whose remaining N_P - |P'| VNs
 //      come from steps 1-2 run on the VNs outside P' (their histogram counts taken out, their
@@ -72,6 +73,10 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
   uint32_t* synw = reinterpret_cast<uint32_t*>(lds + P.off_synw);
   uint32_t* rowmark = reinterpret_cast<uint32_t*>(lds + P.off_rowmark);
   uint32_t* vnmark = reinterpret_cast<uint32_t*>(lds + P.off_vnmark);
+  // FP32: VNs whose precomputed total two or more checks of the step change, and the step's
+  // changes of the precomputed messages (global, one float per edge of this workgroup's frame)
+  uint32_t* vnmulti = reinterpret_cast<uint32_t*>(lds + P.off_vnmulti);
+  float* dbuf = A::kFixed ? nullptr : P.dbuf + (size_t)blockIdx.x * (size_t)E;
   int* rows = reinterpret_cast<int*>(lds + P.off_rows);
   int* rows2 = reinterpret_cast<int*>(lds + P.off_rows2);
   int* sel = reinterpret_cast<int*>(lds + P.off_sel);  // [64] unsorted, [64] sorted
@@ -104,7 +109,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
     for (int e = tid; e < E; e += BS) mp[e].c = (msg_t)0;
     for (int b = tid; b < NG; b += BS) hist[b] = 0;
     for (int w = tid; w < nsw; w += BS) synw[w] = 0u, rowmark[w] = 0u;
-    for (int w = tid; w < nvw; w += BS) vnmark[w] = 0u;
+    for (int w = tid; w < nvw; w += BS) vnmark[w] = 0u, vnmulti[w] = 0u;
     if (tid < kMiscWords) misc[tid] = 0;
     __syncthreads();
     for (int m = tid; m < M; m += BS) {
@@ -478,11 +483,20 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
         const val_t o = row_update_lane(ar, valid, (uint32_t)cur.e, v, cur.l2, 5);
         if (valid) {
           mp[cur.e].p = (msg_t)o;
-          if (o != po) atomicAdd(&Lt[cur.j], (llr_t)(o - po));
+          if constexpr (A::kFixed) {
+            if (o != po) atomicAdd(&Lt[cur.j], (llr_t)(o - po));  // integer sums: any order is exact
+          } else {
+            // FP32: the change is kept per edge and added to Lt after the pass (a VN that several
+            // checks of the step change, marked in vnmulti, takes its changes in ascending check
+            // order), so that a rerun rounds the same way
+            dbuf[cur.e] = o - po;
+            const uint32_t bit = 1u << (cur.j & 31);
+            if (atomicOr(&vnmark[cur.j >> 5], bit) & bit) atomicOr(&vnmulti[cur.j >> 5], bit);
+          }
         }
         cur = nxt;
       }
-      if constexpr (MSG_GLOBAL) __threadfence_block();
+      if constexpr (MSG_GLOBAL || !A::kFixed) __threadfence_block();  // pairs and step changes in global memory
       __syncthreads();
       ME_PROF_MARK(4)
       // ---- CI and CI group of every VN of those checks (each VN once) ----
@@ -493,7 +507,36 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
           if (pos < dc) {
             const int j = G.row_vn(m, rs, pos);
             const uint32_t bit = 1u << (j & 31);
-            if (!(atomicOr(&vnmark[j >> 5], bit) & bit)) {
+            // each VN once: fixed point marks it here; FP32 clears the mark the row pass set
+            bool owner;
+            if constexpr (A::kFixed) owner = !(atomicOr(&vnmark[j >> 5], bit) & bit);
+            else owner = (atomicAnd(&vnmark[j >> 5], ~bit) & bit) != 0;
+            if (owner) {
+              if constexpr (!A::kFixed) {
+                if (vnmulti[j >> 5] & bit) {  // the changes of every check of the step, ascending
+                  val_t lt = (val_t)Lt[j];
+                  const int dvj = G.vn_deg(j);
+                  for (int k0 = 0; k0 < dvj; k0 += 16) {  // 16 loads in flight, then the sums in order
+                    float dd[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                      dd[u] = 0.0f;
+                      if (k0 + u < dvj) {
+                        int mi, ei;
+                        G.vn_edge(j, k0 + u, mi, ei);
+                        if (rowmark[mi >> 5] & (1u << (mi & 31))) dd[u] = dbuf[ei];
+                      }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                      if (dd[u] != 0.0f) lt += dd[u];
+                  }
+                  Lt[j] = (llr_t)lt;
+                } else {  // this lane's check is the only one
+                  const float d = dbuf[rs + pos];
+                  if (d != 0.0f) Lt[j] = (llr_t)((val_t)Lt[j] + d);
+                }
+              }
               const uint32_t nd = ar.ci((val_t)L[j], (val_t)Lt[j]);
               const uint32_t od = D[j];
               D[j] = nd;
@@ -509,7 +552,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       __syncthreads();
       ME_PROF_MARK(5)
       for (int w = tid; w < nsw; w += BS) rowmark[w] = 0u;
-      for (int w = tid; w < nvw; w += BS) vnmark[w] = 0u;
+      for (int w = tid; w < nvw; w += BS) vnmark[w] = 0u, vnmulti[w] = 0u;
       const int unsat = misc[MS_UNSAT];
       __syncthreads();
       if (lmd) {
