@@ -138,7 +138,8 @@ typedef struct {
    at least 2 entries and every column at least 1.  layer_ptr (nullable) lists n_layers + 1 row
    offsets of consecutive layers whose rows share no VN (layered baseline); NULL = one row per
    layer.  The library copies the arrays; the caller keeps ownership of its buffers.
-   Errors: LDPC_EINVAL on a malformed matrix or layer partition, LDPC_ENOMEM, LDPC_EHIP. */
+   Errors: LDPC_EINVAL on a malformed matrix or layer partition, LDPC_EUNSUPPORTED (a check of
+   degree > 32, or N >= 2^24), LDPC_ENOMEM, LDPC_EHIP. */
 int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32_t* col_idx,
                        const int32_t* layer_ptr, int32_t n_layers, ldpc_code** out);
 
@@ -146,7 +147,8 @@ int ldpc_code_from_csr(int32_t M, int32_t N, const int32_t* row_ptr, const int32
    -1 = zero block, s in [0, Z) = circulant): check i Z + r meets VN j Z + ((r + s) mod Z) (the
    lifting used by the paper's Sec. V codes).  The expanded H uses canonical edge ids; the block
    rows form the layers.  Kernels use the base tables instead of per-edge index arrays.
-   Errors: LDPC_EINVAL (shift out of range, a base row with < 2 blocks, an empty base column),
+   Errors: LDPC_EINVAL (shift out of range, a base row with < 2 blocks, an empty base column, more
+   than 2^26 VNs or checks), LDPC_EUNSUPPORTED (a base row of more than 32 blocks, N >= 2^24),
    LDPC_ENOMEM, LDPC_EHIP. */
 int ldpc_code_from_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t* shift, ldpc_code** out);
 

@@ -69,6 +69,61 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     return LIB
 
 
+# Host-side sanitizers: the host code (argument validation, table building, layout sizing) is
+# instrumented with AddressSanitizer and UndefinedBehaviorSanitizer; device code never is.
+SAN_DIR = os.path.join(HERE, "_build")
+SAN_LIB = os.path.join(SAN_DIR, "libldpcci_asan.so")
+SAN_HOST_SOURCES = ("host.cpp", "noalloc.hip")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+             "-Xarch_host", "-shared-libsan"]
+
+
+def asan_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (to be preloaded into the process that loads
+    the sanitized library)."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise RuntimeError("AddressSanitizer runtime not found under /opt/rocm/llvm/lib/clang")
+    return hits[-1]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """Build SAN_LIB (host code sanitized) unless one built from the current sources exists."""
+    import concurrent.futures
+    import shutil
+    import tempfile
+    stamp = os.path.join(SAN_DIR, "sources.sha256")
+    digest = sources_digest()
+    if os.path.exists(SAN_LIB) and os.path.exists(stamp) and open(stamp).read().strip() == digest:
+        return SAN_LIB
+    os.makedirs(SAN_DIR, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    work = tempfile.mkdtemp(prefix="ldpcci_asan_")
+    try:
+        objs = [os.path.join(work, os.path.basename(src) + ".o") for src in srcs]
+
+        def compile_one(src, obj):
+            extra = SAN_FLAGS if os.path.basename(src) in SAN_HOST_SOURCES else []
+            cmd = ["hipcc", *[f for f in FLAGS if f != "-O3"], "-O1", "-g", *extra, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.check_call(cmd)
+
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(srcs), os.cpu_count() or 1, 8)) as ex:
+            for f in [ex.submit(compile_one, s, o) for s, o in zip(srcs, objs)]:
+                f.result()
+        cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Xarch_host", "-shared-libsan", "-o", SAN_LIB,
+               *objs]
+        subprocess.check_call(cmd)
+        with open(stamp, "w") as fh:
+            fh.write(digest + "\n")
+    finally:
+        shutil.rmtree(work, ignore_errors=True)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     build(verbose=True)
     print(LIB)

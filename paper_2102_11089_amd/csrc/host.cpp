@@ -289,6 +289,7 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
   if (!out) return LDPC_EINVAL;
   *out = nullptr;
   if (M <= 0 || N <= 0 || !row_ptr || !col_idx) return LDPC_EINVAL;
+  if (N >= (1 << 24)) return LDPC_EUNSUPPORTED;  // VN indices share a word with 8 flag bits in the two-hop table
   if (row_ptr[0] != 0) return LDPC_EINVAL;
   for (int m = 0; m < M; ++m)
     if (row_ptr[m + 1] - row_ptr[m] < 2) return LDPC_EINVAL;
@@ -408,10 +409,6 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
     nbr_idx[2 * n] = off;
     nbr_idx[2 * n + 1] = cnt;
     c->nbr_max_cnt = std::max(c->nbr_max_cnt, cnt);
-  }
-  if (N >= (1 << 24)) {
-    delete c;
-    return LDPC_EUNSUPPORTED;
   }
   // one device buffer: row_ptr, col, row_of, col_ptr, col_row, col_eid, layer_ptr, 7 LUTs
   std::vector<int> blob;
