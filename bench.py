@@ -12,6 +12,10 @@ is CIRBP decoded frames per second over the timed steps.  The same batches are t
 
 Prints one JSON line.  ``--sweep`` instead prints one JSON line per Eb/N0 point (FER curves).
 ``--workload`` measures the other workloads, one JSON line each:
+  c0  the PEG (3,6) n = 96 code at 2 dB, 1000 frames: flooding, RBP and CIRBP in FP32 and 6-bit
+      min-sum, with the oracle on the same frames;
+  c1sweep  the headline code over 0.5..2.0 dB, 65536 frames per point: CIRBP, layered and flooding,
+      the Eb/N0 at FER 1e-3 per decoder, iso-quality and iso-SNR comparisons;
   c2  one persistent batched launch over 12 quasi-cyclic codes (24-column family, Z in {24, 48, 96},
       rates 1/2, 2/3, 3/4, 5/6), schedule drawn per frame from {flooding, RBP, CIRBP}, Eb/N0 drawn
       from {1.0, 1.5, ..., 4.0} dB, FP32 and 8-bit fixed point;
@@ -665,6 +669,131 @@ def bench_multi_edge(args, ldpc, S, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_c0(args, ldpc, S, dev):
+    """Workload c0: the PEG (3,6)-regular n = 96 code at Eb/N0 2 dB, 1000 frames; flooding (50
+    iterations), RBP and CIRBP (gamma 0.1, cap 2400 updates) in sum-product FP32 and 6-bit min-sum
+    (q = 6, f = 1).  The 1000 frames are decoded as one launch, repeated for timing (HIP events);
+    the oracle decodes the same 1000 frames once per decoder on the host cores.  Value: CIRBP FP32
+    frames/s."""
+    import torch
+    from oracle import oracle as O
+    code = S.workload_code("c0")
+    h = ldpc.Code(code)
+    cw, llr = S.frames(code, 1000, 2.0, args.seed)
+    t = torch.from_numpy(llr).to(dev)
+    stream = torch.cuda.Stream(device=dev)
+    reps = max(1, args.steps) * 20
+    cpu = host_cpu()
+    rows = {}
+    for aname, arith, oa in (("f32", ldpc.SPA_F32, O.SPA), ("fix6", ldpc.MS_FIX, O.MSFIX)):
+        for kname, kind, okind, cap in (("flooding", ldpc.FLOODING, O.FLOODING, 50 * code.E),
+                                        ("rbp", ldpc.RBP, O.RBP, 2400), ("cirbp", ldpc.CIRBP, O.CIRBP, 2400)):
+            def go():
+                with torch.cuda.stream(stream):
+                    return ldpc.decode(h, t, kind, arith, max_updates=cap, gamma=0.1, q_bits=6, frac_bits=1,
+                                       stream=stream)
+            for _ in range(max(1, args.warmup)):
+                go()
+            _, ms, _ = ev_time(stream, lambda: [go() for _ in range(reps)][-1])
+            r = go()
+            torch.cuda.synchronize()
+            fe = int(torch.any(r.bits.cpu() != torch.from_numpy(cw), dim=1).sum())
+            upd = int(r.updates_used.sum())
+            kern_s = ms / 1e3 / reps
+            t0 = time.perf_counter()
+            ref = O.decode(code, llr, okind, oa, max_updates=cap, gamma=0.1, q_bits=6, frac_bits=1,
+                           threads=cpu["workers"])
+            dt = time.perf_counter() - t0
+            fe_o = int(np.any(ref.bits != cw, axis=1).sum())
+            rows[f"{kname}_{aname}"] = {
+                "frames_per_s": round(1000 / kern_s, 1), "edge_updates_per_s": round(upd / kern_s, 1),
+                "fer": fe / 1000, "mean_updates": upd / 1000, "launch_ms": round(kern_s * 1e3, 4),
+                "oracle": {"fer": fe_o / 1000, "mean_updates": float(ref.updates_used.mean()),
+                           "frames_per_s": round(1000 / dt, 1), "threads": cpu["workers"], "seconds": round(dt, 3)}}
+            print(f"[c0] {kname} {aname}: {rows[f'{kname}_{aname}']}", file=sys.stderr, flush=True)
+    v = rows["cirbp_f32"]
+    out = {"metric": "decoded frames/s & edge-updates/s, c0 (PEG (3,6) n=96, 2 dB, 1000 frames)",
+           "value": v["frames_per_s"], "unit": "frames/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+           "ms_per_step": v["launch_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "PEG (3,6)-regular n=96 (seed 2102), BPSK/AWGN Eb/N0 2.0 dB, random codewords, "
+                                  "1000 frames per launch; flooding 50 it, RBP and CIRBP (gamma 0.1) cap 2400 updates; "
+                                  "FP32 sum-product and min-sum q=6 f=1", "frames": 1000},
+           "decoders": rows,
+           "cpu_baseline": {"value": rows["cirbp_f32"]["oracle"]["frames_per_s"], "unit": "frames/s",
+                            "cores": cpu["workers"], "kind": "oracle",
+                            "sample": "all 1000 frames, CIRBP FP64, one call over the CPU share",
+                            "host": {k: cpu[k] for k in ("nproc", "affinity", "model", "workers", "workers_from")}}}
+    print(json.dumps(out), flush=True)
+
+
+def snr_at_fer(points, target=1e-3):
+    """Eb/N0 where the FER crosses target, by log-linear interpolation between the measured points
+    (points: ascending (ebn0, fer)); None when no crossing was measured."""
+    for (e0, f0), (e1, f1) in zip(points, points[1:]):
+        if f0 > target >= f1:
+            if f1 <= 0:
+                return e1
+            return e0 + (np.log10(f0) - np.log10(target)) / (np.log10(f0) - np.log10(f1)) * (e1 - e0)
+    return None
+
+
+def bench_c1_sweep(args, ldpc, S, dev):
+    """The headline code over Eb/N0 0.5..2.0 dB (step 0.25), 65536 frames per point: CIRBP (cap 3E),
+    layered and flooding (cap 50 iterations).  Per decoder the Eb/N0 at FER 1e-3 (log-linear
+    interpolation); iso-quality: each decoder's frames/s and edge-updates/s at its first measured
+    point with FER <= 1e-3; iso-SNR: every decoder at the first point where flooding reaches it.
+    One JSON line per point, then the summary line (value: CIRBP frames/s at its iso-quality point)."""
+    import torch
+    code = S.workload_code("c1")
+    h = ldpc.Code(code)
+    E = code.E
+    B = args.frames or C1_FRAMES
+    stream = torch.cuda.Stream(device=dev)
+    snrs = [0.5 + 0.25 * k for k in range(7)]
+    decs = (("cirbp", ldpc.CIRBP, 3 * E), ("layered", ldpc.LAYERED, 50 * E), ("flooding", ldpc.FLOODING, 50 * E))
+    per = {d[0]: [] for d in decs}
+    for eb in snrs:
+        batches = make_batches(code, 1, B, eb, args.seed + int(eb * 1000), dev)
+        row = {"ebn0": eb, "frames": B}
+        for name, kind, cap in decs:
+            one, res = run_decoder(ldpc, h, batches, kind, cap, stream)
+            one(0)  # warm-up (also decodes: counted below only from the timed run)
+            res.clear()
+            wall, kms = timed(one, stream, 1)
+            fe, nf, upd, fall = summarize(res, code)
+            d = {"fer": fe / nf, "frame_errors": fe, "frames_per_s": nf / (kms[0] / 1e3),
+                 "edge_updates_per_s": upd / (kms[0] / 1e3), "mean_updates": upd / nf}
+            row[name] = d
+            per[name].append((eb, d))
+        print(json.dumps(row), flush=True)
+        del batches
+    summary = {}
+    for name, pts in per.items():
+        s1 = snr_at_fer([(e, d["fer"]) for e, d in pts])
+        first = next(((e, d) for e, d in pts if d["fer"] <= 1e-3), None)
+        summary[name] = {"ebn0_at_fer_1e-3": None if s1 is None else round(float(s1), 4),
+                         "iso_quality_point": None if first is None else
+                         {"ebn0": first[0], "fer": first[1]["fer"], "frames_per_s": round(first[1]["frames_per_s"], 1),
+                          "edge_updates_per_s": round(first[1]["edge_updates_per_s"], 1)}}
+    fl_first = next((e for e, d in per["flooding"] if d["fer"] <= 1e-3), None)
+    iso_snr = None
+    if fl_first is not None:
+        iso_snr = {"ebn0": fl_first}
+        for name, pts in per.items():
+            d = dict(pts)[fl_first]
+            iso_snr[name] = {"fer": d["fer"], "frames_per_s": round(d["frames_per_s"], 1)}
+    ci = summary["cirbp"]["iso_quality_point"]
+    out = {"metric": METRIC, "value": None if ci is None else ci["frames_per_s"], "unit": "frames/s", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "BG1-shaped QC 46x68, Z=52, Eb/N0 0.5..2.0 dB step 0.25, 65536 frames per point; "
+                                  "CIRBP gamma 0.1 cap 3E, layered and flooding cap 50 it; FP32",
+                      "frames_per_point": B},
+           "snr_at_fer_1e-3": summary, "iso_snr": iso_snr}
+    print(json.dumps(out), flush=True)
+
+
 def bench_sweep(args, ldpc, S, dev):
     """The SNR sweep captured into one hipGraph (per point: generate frames, decode, count errors)
     against the same work launched one call at a time, at 4096 frames per point (value: frames/s
@@ -787,7 +916,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true")
     ap.add_argument("--sweep", type=str, default="", help="comma list of Eb/N0 points: FER curves")
-    ap.add_argument("--workload", type=str, default="c1", choices=["c1", "c2", "c3", "c4", "lmd", "ci", "sweep"])
+    ap.add_argument("--workload", type=str, default="c1",
+                    choices=["c1", "c0", "c1sweep", "c2", "c3", "c4", "lmd", "ci", "sweep"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -805,7 +935,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload != "c1":
         {"c2": bench_batched, "c3": bench_multi_edge, "c4": bench_unrolled,
-         "lmd": bench_lmd, "ci": bench_ci, "sweep": bench_sweep}[args.workload](args, ldpc, S, dev)
+         "lmd": bench_lmd, "ci": bench_ci, "sweep": bench_sweep, "c0": bench_c0,
+         "c1sweep": bench_c1_sweep}[args.workload](args, ldpc, S, dev)
         return
 
     args.frames = args.frames or C1_FRAMES
