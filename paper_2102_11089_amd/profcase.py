@@ -2,6 +2,8 @@
 
     python -m paper_2102_11089_amd.profcase <workload> <schedule> <arith> [frames] [ebn0]
     python -m paper_2102_11089_amd.profcase copy <bytes>
+    python -m paper_2102_11089_amd.profcase random <bytes> <accesses>
+    python -m paper_2102_11089_amd.profcase account [frames] [sector bytes]
     python -m paper_2102_11089_amd.profcase traffic <out.json> <kernel> <fetch.csv> <write.csv> \
         <copy_fetch.csv> <copy_write.csv> <copy_bytes> [workload text]
 
@@ -11,6 +13,12 @@ total number of updates so counters can be divided per update.
 
 ``copy`` runs two plain device-to-device copies of a buffer of the given size: the reference for
 scaling the FETCH_SIZE / WRITE_SIZE counters to bytes.
+
+``random`` measures scattered 8-byte gathers and scatters over a buffer of the given size: the
+memory system's rate for the decoder's scattered record accesses.
+
+``account`` counts, per single-edge update of a traced c1 decode, the memory sectors each part of
+the frame state costs in the benchmark's layout (pairs, VN records, two-hop table).
 
 ``traffic`` turns rocprofv3 counter files (``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` runs,
 ``*_counter_collection.csv``) into HBM bytes for the first dispatch whose kernel name contains
@@ -63,9 +71,106 @@ def copy_case(nbytes: int):
     print("copied bytes", src.numel() * 4, "twice", flush=True)
 
 
+def random_case(nbytes: int, accesses: int):
+    """Throughput of scattered 8-byte accesses over a buffer of nbytes in device memory (the access
+    pattern of the decoder's VN records, each in its own 64-byte sector): a gather of `accesses`
+    random elements, a scatter of as many, and a copy of the same index/value volume for
+    comparison.  Prints accesses per second and the 64-byte sector rate of each."""
+    import time
+    import torch
+    n = nbytes // 8
+    buf = torch.zeros(n, dtype=torch.float64, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    idx = torch.randint(0, n, (accesses,), generator=g, device="cuda")
+    vals = torch.ones(accesses, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(vals)
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+    tg = timeit(lambda: torch.index_select(buf, 0, idx, out=out))
+    ts = timeit(lambda: buf.index_copy_(0, idx, vals))
+    tc = timeit(lambda: out.copy_(vals))
+    for name, t in (("gather", tg), ("scatter", ts)):
+        print(f"{name}: {accesses / t / 1e9:.2f} G accesses/s ({accesses * 64 / t / 1e12:.2f} TB/s of 64-byte "
+              f"sectors; plus {accesses * 16 / t / 1e12:.2f} TB/s sequential index and value streams)", flush=True)
+    print(f"copy of the value stream: {accesses * 16 / tc / 1e12:.2f} TB/s", flush=True)
+
+
+def account_case(frames: int, sector: int = 64):
+    """Per-update memory accounting of the single-edge kernel on the BG1-shaped Z=52 code: decode
+    `frames` frames at 1.25 dB with CIRBP (FP32, cap 3E) with the schedule recorded, and for every
+    update count the distinct `sector`-byte sectors of the frame state it touches in the layout of
+    the benchmark's plan (a global slot per frame: (c2v, pre) pairs in row order, then one 8-byte
+    (Lt, L) record per VN): the pairs of every check of n*, the records of n* and of every VN of
+    M(n*) \ m*, and the two-hop table entries of n* (shared by all frames).  Counts assume no reuse
+    between updates; the block recomputations (64 records each) are counted separately."""
+    import numpy as np
+    import torch
+    from . import ldpc
+    from . import synth as S
+    code = S.workload_code("c1")
+    E, N = code.E, code.N
+    rp = np.asarray(code.row_ptr)
+    col = np.asarray(code.col)
+    col_ptr, col_row, _ = code.csc()
+    row_of = np.repeat(np.arange(code.M), np.diff(rp))
+    dc = np.diff(rp)
+    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    rec0 = up(2 * E * 4)
+    p2 = lambda x: 1 << int(np.ceil(np.log2(x)))  # noqa: E731
+    ncnt = np.array([sum(p2(dc[m]) for m in col_row[col_ptr[n]:col_ptr[n + 1]]) for n in range(N)])
+    nbr_off = np.concatenate([[0], np.cumsum(ncnt)])[:-1]
+
+    def secs(lo, hi):
+        return set(range(lo // sector, (hi - 1) // sector + 1))
+    pairs = np.zeros(E)
+    recs = np.zeros(E)
+    vns = np.zeros(E)
+    table = np.zeros(E)
+    for e in range(E):
+        m, n = row_of[e], col[e]
+        checks = col_row[col_ptr[n]:col_ptr[n + 1]]
+        ps, touched = set(), {int(n)}
+        for i in checks:
+            ps |= secs(8 * rp[i], 8 * rp[i + 1])
+            if i != m:
+                touched |= set(col[rp[i]:rp[i + 1]].tolist())
+        rs = set()
+        for j in touched:
+            rs |= secs(rec0 + 8 * j, rec0 + 8 * j + 8)
+        pairs[e], recs[e], vns[e] = len(ps), len(rs), len(touched)
+        table[e] = len(secs(8 * nbr_off[n], 8 * (nbr_off[n] + ncnt[n]))) if len(checks) > 1 else 0
+    h = ldpc.Code(code)
+    _, llr = S.frames(code, frames, 1.25, 7)
+    r = ldpc.decode(h, torch.from_numpy(llr).cuda(), ldpc.CIRBP, ldpc.SPA_F32, max_updates=3 * E, gamma=0.1,
+                    trace=True)
+    torch.cuda.synchronize()
+    used = r.updates_used.cpu().numpy()
+    tr = r.trace.cpu().numpy()
+    t = np.concatenate([tr[f, :used[f]] for f in range(frames)])
+    doc = {"frames": frames, "updates": int(len(t)), "sector_bytes": sector,
+           "pair_sectors": round(float(pairs[t].mean()), 2), "record_sectors": round(float(recs[t].mean()), 2),
+           "touched_vns": round(float(vns[t].mean()), 2), "table_sectors": round(float(table[t].mean()), 2),
+           "rows_of_nstar": round(float(np.diff(col_ptr)[col[t]].mean()), 2),
+           "degree1_nstar_fraction": round(float((np.diff(col_ptr)[col[t]] == 1).mean()), 4)}
+    print(json.dumps(doc), flush=True)
+
+
 def main():
+    if sys.argv[1] == "account":
+        account_case(int(sys.argv[2]) if len(sys.argv) > 2 else 16, int(sys.argv[3]) if len(sys.argv) > 3 else 64)
+        return
     if sys.argv[1] == "copy":
         copy_case(int(sys.argv[2]))
+        return
+    if sys.argv[1] == "random":
+        random_case(int(sys.argv[2]), int(sys.argv[3]))
         return
     if sys.argv[1] == "traffic":
         traffic_case(sys.argv[2:])
