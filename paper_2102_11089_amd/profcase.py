@@ -2,7 +2,7 @@
 
     python -m paper_2102_11089_amd.profcase <workload> <schedule> <arith> [frames] [ebn0]
     python -m paper_2102_11089_amd.profcase copy <bytes>
-    python -m paper_2102_11089_amd.profcase random <bytes> <accesses>
+    python -m paper_2102_11089_amd.profcase random <bytes> <accesses> [width bytes]
     python -m paper_2102_11089_amd.profcase account [frames] [sector bytes]
     python -m paper_2102_11089_amd.profcase traffic <out.json> <kernel> <fetch.csv> <write.csv> \
         <copy_fetch.csv> <copy_write.csv> <copy_bytes> [workload text]
@@ -71,19 +71,21 @@ def copy_case(nbytes: int):
     print("copied bytes", src.numel() * 4, "twice", flush=True)
 
 
-def random_case(nbytes: int, accesses: int):
-    """Throughput of scattered 8-byte accesses over a buffer of nbytes in device memory (the access
-    pattern of the decoder's VN records, each in its own 64-byte sector): a gather of `accesses`
-    random elements, a scatter of as many, and a copy of the same index/value volume for
-    comparison.  Prints accesses per second and the 64-byte sector rate of each."""
+def random_case(nbytes: int, accesses: int, width: int = 8):
+    """Throughput of scattered accesses of `width` bytes (aligned to their size) over a buffer of
+    nbytes in device memory (width 8: the access pattern of the decoder's VN records, each in its
+    own sector): a gather of `accesses` random elements, a scatter of as many, and a copy of the
+    same index/value volume for comparison.  Prints accesses per second and the 64-byte sector
+    rate of each."""
     import time
     import torch
-    n = nbytes // 8
-    buf = torch.zeros(n, dtype=torch.float64, device="cuda")
+    w = max(1, width // 8)
+    n = nbytes // (8 * w)
+    buf = torch.zeros((n, w), dtype=torch.float64, device="cuda")
     g = torch.Generator(device="cuda")
     g.manual_seed(1)
     idx = torch.randint(0, n, (accesses,), generator=g, device="cuda")
-    vals = torch.ones(accesses, dtype=torch.float64, device="cuda")
+    vals = torch.ones((accesses, w), dtype=torch.float64, device="cuda")
     out = torch.empty_like(vals)
 
     def timeit(fn):
@@ -97,9 +99,10 @@ def random_case(nbytes: int, accesses: int):
     ts = timeit(lambda: buf.index_copy_(0, idx, vals))
     tc = timeit(lambda: out.copy_(vals))
     for name, t in (("gather", tg), ("scatter", ts)):
-        print(f"{name}: {accesses / t / 1e9:.2f} G accesses/s ({accesses * 64 / t / 1e12:.2f} TB/s of 64-byte "
-              f"sectors; plus {accesses * 16 / t / 1e12:.2f} TB/s sequential index and value streams)", flush=True)
-    print(f"copy of the value stream: {accesses * 16 / tc / 1e12:.2f} TB/s", flush=True)
+        print(f"{name} of {8 * w} B: {accesses / t / 1e9:.2f} G accesses/s ({accesses * 8 * w / t / 1e12:.2f} TB/s of "
+              f"payload; plus {accesses * (8 + 8 * w) / t / 1e12:.2f} TB/s sequential index and value streams)",
+              flush=True)
+    print(f"copy of the value stream: {accesses * 16 * w / tc / 1e12:.2f} TB/s", flush=True)
 
 
 def account_case(frames: int, sector: int = 64):
@@ -170,7 +173,7 @@ def main():
         copy_case(int(sys.argv[2]))
         return
     if sys.argv[1] == "random":
-        random_case(int(sys.argv[2]), int(sys.argv[3]))
+        random_case(int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]) if len(sys.argv) > 4 else 8)
         return
     if sys.argv[1] == "traffic":
         traffic_case(sys.argv[2:])
