@@ -45,6 +45,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 LDS_PEAK_GBS = 256 * 128 * 2.4  # CUs x bytes/clk/CU x GHz = 78643 GB/s (nominal LDS bandwidth)
+LDS_MEASURED = {}  # LDS read bandwidth of the probe per access width (GB/s), filled by measure_lds
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 METRIC = "decoded frames/s & edge-updates/s at FER 1e-3, CI vs flooding BP, one MI355X"
 C1_FRAMES = 65536               # frames per Eb/N0 point of the BG1-shaped workload: one step
@@ -166,6 +167,23 @@ def summarize(res, code):
     return fe, nf, upd, fall
 
 
+def measure_lds(ldpc):
+    """LDS read bandwidth the chip sustains (``ldpc_probe_lds``: 8 workgroups of 256 lanes per CU,
+    conflict-free reads of 4, 8 and 16 bytes), best of three runs per width, in GB/s."""
+    for w in (4, 8, 16):
+        ldpc.probe_lds(w, iters=256)
+        LDS_MEASURED[f"b{8 * w}"] = round(max(ldpc.probe_lds(w, iters=4096) for _ in range(3)), 1)
+    return dict(LDS_MEASURED)
+
+
+def lds_measured_fields(achieved):
+    """The probe's best LDS bandwidth and the fraction of it achieved, when it was measured."""
+    if not LDS_MEASURED:
+        return {}
+    peak = max(LDS_MEASURED.values())
+    return {"lds_peak_measured": peak, "lds_frac_measured": round(achieved / peak, 6)}
+
+
 def baseline_roofline(ldpc, h, code, kind, B, updates, kern_s, s_c=4, s_v=4, arith=None):
     """Roofline of a flooding or layered launch.  Algorithmic bytes per edge-update (one C2V
     message computed; an iteration is E of them): flooding reads L and the old message and writes
@@ -181,7 +199,8 @@ def baseline_roofline(ldpc, h, code, kind, B, updates, kern_s, s_c=4, s_v=4, ari
     if pd["storage_name"] == "lds":
         achieved = per * updates / kern_s / 1e9
         return {"bound": "lds", "achieved": round(achieved, 2), "peak": round(LDS_PEAK_GBS, 1), "unit": "GB/s",
-                "frac": round(achieved / LDS_PEAK_GBS, 6), "bytes_per_edge_update": round(per, 3),
+                "frac": round(achieved / LDS_PEAK_GBS, 6), **lds_measured_fields(achieved),
+                "bytes_per_edge_update": round(per, 3),
                 "plan": f"{pd['storage_name']} messages, {pd['topology_name']} topology, block {pd['block']}"}
     achieved = msg_bytes * updates / kern_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -620,9 +639,27 @@ def bench_batched(args, ldpc, S, dev):
         print(json.dumps(out), flush=True)
 
 
+def me_bytes_per_update_table(code, lmd):
+    """Algorithmic bytes of one update of a multi-edge step through edge e (FP32): the Table-1
+    bytes of a single-edge update through e (the update rule is the same, Algorithm 5), plus for
+    ME-LMD-CIRBP the CI read of every VN its proposal looks at (Algorithm 6: the VNs of the checks
+    of the updated VN other than e's own check, s_d = 4 bytes each)."""
+    t = lds_bytes_per_update_table(code)
+    if not lmd:
+        return t
+    dc = np.diff(code.row_ptr).astype(np.int64)
+    rows = code.row_of_edge()
+    per_vn = np.zeros(code.N, dtype=np.int64)
+    np.add.at(per_vn, code.col, dc[rows] - 1)
+    return t + 4 * (per_vn[code.col] - (dc[rows] - 1))
+
+
 def bench_multi_edge(args, ldpc, S, dev):
     """Workload c3: ME-CIRBP, update steps against FER; ME-LMD-CIRBP (Algorithm 6) on the same
-    batches alongside (its points carry "schedule": "me_lmd_cirbp"; value counts ME-CIRBP)."""
+    batches alongside (its points carry "schedule": "me_lmd_cirbp"; value counts ME-CIRBP), and
+    an N_G sweep at 1.25 dB.  Roofline of the ME kernel: Table-1 bytes of the updates (averaged
+    over traced decodes of the first 256 frames of each point) plus the N_G histogram words of
+    each step, over kernel time."""
     import torch
     code = S.workload_code("c3")
     h = ldpc.Code(code)
@@ -634,38 +671,81 @@ def bench_multi_edge(args, ldpc, S, dev):
     total_upd = 0
     lmd_ms = 0.0
     lmd_frames = 0
+    acc = {"me_cirbp": [0.0, 0.0, 0.0, 0], "me_lmd_cirbp": [0.0, 0.0, 0.0, 0]}  # bytes, ms, updates, launches
+    tables = {"me_cirbp": me_bytes_per_update_table(code, False), "me_lmd_cirbp": me_bytes_per_update_table(code, True)}
+    ns = min(256, B)
+
+    def point(eb, cw, llr, sched, kind, n_p, n_g):
+        nonlocal total_ms, total_frames, total_upd, lmd_ms, lmd_frames
+
+        def go():
+            with torch.cuda.stream(stream):
+                return ldpc.decode(h, llr, kind, ldpc.SPA_F32, max_updates=3 * code.E, gamma=0.1,
+                                   n_p=n_p, n_g=n_g, fill=ldpc.FILL_HASH, seed=args.seed, stream=stream)
+        r, ms, _ = ev_time(stream, go)
+        print(f"[c3] {sched} Eb/N0 {eb} N_P {n_p} N_G {n_g}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        fe = int(torch.any(r.bits != cw, dim=1).sum())
+        upd = int(r.updates_used.sum())
+        steps = int(r.steps_used.sum())
+        with torch.cuda.stream(stream):  # traced sample for the algorithmic bytes
+            rt = ldpc.decode(h, llr[:ns], kind, ldpc.SPA_F32, max_updates=3 * code.E, gamma=0.1, n_p=n_p,
+                             n_g=n_g, fill=ldpc.FILL_HASH, seed=args.seed, trace=True, stream=stream)
+        torch.cuda.synchronize()
+        used = rt.updates_used.cpu().numpy()
+        tr = rt.trace.cpu().numpy()
+        tab = tables[sched]
+        per_upd = sum(int(tab[tr[x, :used[x]]].sum()) for x in range(ns)) / max(int(used.sum()), 1)
+        a = acc[sched]
+        a[0] += per_upd * upd + 4.0 * n_g * steps
+        a[1] += ms
+        a[2] += upd
+        a[3] += 1
+        if n_g == 16:
+            if kind == ldpc.ME_CIRBP:
+                total_ms += ms
+                total_frames += B
+                total_upd += upd
+            else:
+                lmd_ms += ms
+                lmd_frames += B
+        rows.append({"schedule": sched, "ebn0": eb, "n_p": n_p, "n_g": n_g, "fer": fe / B, "frame_errors": fe,
+                     "mean_steps": steps / B, "mean_updates": upd / B,
+                     "frames_per_s": round(B / (ms / 1e3), 2),
+                     "edge_updates_per_s": round(upd / (ms / 1e3), 1), "kernel_ms": round(ms, 3),
+                     "bytes_per_update": round(per_upd, 1)})
+
     for eb in (1.0, 1.25, 1.5):
-        batch = make_batches(code, 1, B, eb, args.seed + int(eb * 100), dev)[0]
-        cw, llr = batch
+        cw, llr = make_batches(code, 1, B, eb, args.seed + int(eb * 100), dev)[0]
         for sched, kind in (("me_cirbp", ldpc.ME_CIRBP), ("me_lmd_cirbp", ldpc.ME_LMD_CIRBP)):
             for n_p in (8, 16, 32, 64):
-                def go():
-                    with torch.cuda.stream(stream):
-                        return ldpc.decode(h, llr, kind, ldpc.SPA_F32, max_updates=3 * code.E, gamma=0.1,
-                                           n_p=n_p, n_g=16, fill=ldpc.FILL_HASH, seed=args.seed, stream=stream)
-                r, ms, _ = ev_time(stream, go)
-                print(f"[c3] {sched} Eb/N0 {eb} N_P {n_p}: {ms:.1f} ms", file=sys.stderr, flush=True)
-                fe = int(torch.any(r.bits != cw, dim=1).sum())
-                upd = int(r.updates_used.sum())
-                steps = int(r.steps_used.sum())
-                if kind == ldpc.ME_CIRBP:
-                    total_ms += ms
-                    total_frames += B
-                    total_upd += upd
-                else:
-                    lmd_ms += ms
-                    lmd_frames += B
-                rows.append({"schedule": sched, "ebn0": eb, "n_p": n_p, "fer": fe / B, "frame_errors": fe,
-                             "mean_steps": steps / B, "mean_updates": upd / B,
-                             "frames_per_s": round(B / (ms / 1e3), 2),
-                             "edge_updates_per_s": round(upd / (ms / 1e3), 1), "kernel_ms": round(ms, 3)})
+                point(eb, cw, llr, sched, kind, n_p, 16)
+        if eb == 1.25:  # N_G sweep (Algorithm 4's number of CI groups)
+            for sched, kind in (("me_cirbp", ldpc.ME_CIRBP), ("me_lmd_cirbp", ldpc.ME_LMD_CIRBP)):
+                for n_p in (8, 64):
+                    for n_g in (4, 8):
+                        point(eb, cw, llr, sched, kind, n_p, n_g)
+
+    def roof(sched, kind):
+        b, ms, upd, launches = acc[sched]
+        pd = ldpc.describe_plan(h, B, kind, n_p=8, fill=ldpc.FILL_HASH)
+        achieved = b / (ms / 1e3) / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None,
+                "kernel": f"k_me<ArithF32, {pd['storage_name']} messages, {pd['topology_name']} topology"
+                          f"{', lmd' if kind == ldpc.ME_LMD_CIRBP else ''}> ({pd['grid']} workgroups of {pd['block']} "
+                          f"lanes, frame state but the messages in LDS)",
+                "bytes_per_update": round((b - 0.0) / max(upd, 1), 1), "kernel_ms_avg": round(ms / launches, 3),
+                "lds_frac": round(achieved / LDS_PEAK_GBS, 6)}
     out = {"metric": "ME-CIRBP decoded frames/s and update steps vs FER", "value": round(total_frames / (total_ms / 1e3), 3),
            "unit": "frames/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(total_ms, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "BG1-shaped QC 46x68, Z=128 (n=8704, m=5888, E=40448); ME-CIRBP N_G=16, random "
-                                  "(keyed) fill, gamma 0.1, cap 3E; Eb/N0 1.0/1.25/1.5 dB", "frames_per_point": B},
+                                  "(keyed) fill, gamma 0.1, cap 3E; Eb/N0 1.0/1.25/1.5 dB; N_G 4 and 8 at 1.25 dB",
+                      "frames_per_point": B},
            "edge_updates_per_s": round(total_upd / (total_ms / 1e3), 1),
-           "me_lmd_cirbp_frames_per_s": round(lmd_frames / (lmd_ms / 1e3), 3), "points": rows}
+           "me_lmd_cirbp_frames_per_s": round(lmd_frames / (lmd_ms / 1e3), 3),
+           "roofline": roof("me_cirbp", ldpc.ME_CIRBP), "me_lmd_cirbp_roofline": roof("me_lmd_cirbp", ldpc.ME_LMD_CIRBP),
+           "points": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -933,6 +1013,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    measure_lds(ldpc)
+    print(f"[lds probe] GB/s by access width: {LDS_MEASURED}", file=sys.stderr, flush=True)
     if args.workload != "c1":
         {"c2": bench_batched, "c3": bench_multi_edge, "c4": bench_unrolled,
          "lmd": bench_lmd, "ci": bench_ci, "sweep": bench_sweep, "c0": bench_c0,
@@ -1039,6 +1121,7 @@ def main():
                      "bytes_per_update": round(bytes_per_update, 2),
                      "kernel_ms_avg": round(float(np.mean(kms)), 3),
                      "lds_frac": round(achieved_gbs / LDS_PEAK_GBS, 6)},
+        "lds_probe_gbs": dict(LDS_MEASURED),
     }
 
     if not args.no_baselines:

@@ -403,6 +403,17 @@ int ldpc_sweep_run(ldpc_sweep* sweep, uint64_t seed, int64_t* counters, void* st
 /* Destroy a sweep (waits for the device first).  NULL is ignored. */
 void ldpc_sweep_free(ldpc_sweep* sweep);
 
+/* ---- measurement ----------------------------------------------------------------------------
+   The denominator of an LDS roofline, measured: `blocks` workgroups of 256 lanes each fill a
+   16 KiB LDS buffer, then every lane makes iters x 16 aligned reads of `width` bytes (4, 8 or 16:
+   one ds_read_b32 / b64 / b128 each), consecutive lanes at consecutive addresses, folding them
+   into one word that lane 0 writes to sink[workgroup] (device [blocks] uint32, caller-owned).
+   *bytes receives the bytes read, *ms the time between two events recorded on stream around the
+   launch; the call waits for the second event.  Errors: LDPC_EINVAL (width, blocks < 1, iters
+   outside 1..2^24, null pointer), LDPC_EHIP. */
+int ldpc_probe_lds(int32_t width, int32_t blocks, int64_t iters, uint32_t* sink, void* stream, double* bytes,
+                   float* ms);
+
 /* Human-readable name of an error code (static string). */
 const char* ldpc_strerror(int code);
 

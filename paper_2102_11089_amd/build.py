@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libldpcci.so")
 SOURCES = ["host.cpp", "dynamic.hip", "baseline.hip", "multiedge.hip", "batch.hip", "unrolled.hip", "sweep.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "probe.hip"]
 HEADERS = ["common.hpp", "kernels.hpp", "dyn_frame.hpp"]
 ARCH = os.environ.get("LDPCCI_ARCH", "gfx950")
 

@@ -32,7 +32,7 @@ EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_co
            "ldpc_set_batch_tuning", "ldpc_get_batch_tuning", "ldpc_autotune_batch", "ldpc_tuning_save",
            "ldpc_tuning_load", "ldpc_awgn_frames", "ldpc_sweep_create", "ldpc_sweep_run", "ldpc_sweep_free",
            "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
-           "ldpc_strerror", "ldpc_last_hip_error")
+           "ldpc_probe_lds", "ldpc_strerror", "ldpc_last_hip_error")
 UNROLL_MAX_CKPT_EVERY = 128
 STORE_AUTO, STORE_LDS, STORE_GLOBAL, STORE_GLOBAL_ALL, STORE_GLOBAL_LT, STORE_GLOBAL_FRAME, STORE_GLOBAL_REC, \
     STORE_GLOBAL_STATE = 0, 1, 2, 3, 4, 5, 6, 7
@@ -134,6 +134,9 @@ def load(path: str = LIB_PATH):
     lib.ldpc_tuning_load.restype = C.c_int
     lib.ldpc_awgn_frames.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_uint64, C.c_int32, P, P]
     lib.ldpc_awgn_frames.restype = C.c_int
+    lib.ldpc_probe_lds.argtypes = [C.c_int32, C.c_int32, C.c_int64, P, P, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_float)]
+    lib.ldpc_probe_lds.restype = C.c_int
     lib.ldpc_sweep_create.argtypes = [P, C.POINTER(ldpc_schedule), C.c_int64, P, C.c_int32, P, C.c_int32, C.c_float,
                                       C.c_int32, C.POINTER(C.c_void_p)]
     lib.ldpc_sweep_create.restype = C.c_int
@@ -314,6 +317,12 @@ def ldpc_awgn_frames(cw_ptr: int, P: int, N: int, B: int, sigma2: float, seed: i
                      stream: int) -> None:
     _check(load().ldpc_awgn_frames(cw_ptr, P, N, B, sigma2, seed & (2**64 - 1), point, llr_ptr, stream),
            "ldpc_awgn_frames")
+
+
+def ldpc_probe_lds(width: int, blocks: int, iters: int, sink_ptr: int, stream: int):
+    b, t = C.c_double(0.0), C.c_float(0.0)
+    _check(load().ldpc_probe_lds(width, blocks, iters, sink_ptr, stream, C.byref(b), C.byref(t)), "ldpc_probe_lds")
+    return b.value, t.value
 
 
 def ldpc_sweep_create(handle, s: ldpc_schedule, max_updates: int, cw_ptr: int, P: int, ebn0_db, rate: float,
@@ -647,6 +656,19 @@ def awgn_frames(codewords, B: int, sigma2: float, seed: int, point: int = 0, str
     st = (stream if stream is not None else torch.cuda.current_stream(cw.device)).cuda_stream
     ldpc_awgn_frames(cw.data_ptr(), P, N, B, sigma2, seed, point, llr.data_ptr(), st)
     return llr
+
+
+def probe_lds(width: int = 16, blocks: int = 0, iters: int = 2048, stream=None) -> float:
+    """Measured LDS read bandwidth in GB/s (``ldpc_probe_lds``): `blocks` workgroups of 256 lanes
+    (default 8 per CU of device 0), `iters` x 16 reads of `width` bytes per lane."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if blocks <= 0:
+        blocks = 8 * torch.cuda.get_device_properties(dev).multi_processor_count
+    sink = torch.zeros(blocks, dtype=torch.int32, device=dev)
+    st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
+    nbytes, ms = ldpc_probe_lds(width, blocks, iters, sink.data_ptr(), st)
+    return nbytes / (ms * 1e-3) / 1e9
 
 
 class Sweep:

@@ -143,3 +143,13 @@ def test_batch_tuning_validation_and_round_trip():
     assert lib.ldpc_get_batch_tuning(C.byref(out)) == 0
     s = ldpc.schedule(ldpc.CIRBP)
     assert lib.ldpc_autotune_batch(None, 1, C.byref(s), None, 0, None, 0, 0, 2, None, None, None) == -1
+
+
+def test_lds_probe_rejects_bad_arguments():
+    lib = ldpc.load()
+    b, t = C.c_double(0.0), C.c_float(0.0)
+    sink = (C.c_uint32 * 4)()
+    for width, blocks, iters in ((3, 4, 16), (32, 4, 16), (16, 0, 16), (16, 4, 0), (16, 4, (1 << 24) + 1)):
+        assert lib.ldpc_probe_lds(width, blocks, iters, sink, None, C.byref(b), C.byref(t)) == -1
+    assert lib.ldpc_probe_lds(16, 4, 16, None, None, C.byref(b), C.byref(t)) == -1
+    assert lib.ldpc_probe_lds(16, 4, 16, sink, None, None, C.byref(t)) == -1
