@@ -49,6 +49,11 @@ extern "C" {
 #define LDPC_ECAPACITY (-4)    /* the frame state does not fit the device's on-chip memory    */
 #define LDPC_EUNSUPPORTED (-5) /* schedule/arithmetic combination or code shape not supported */
 
+/* Testing hook for the error paths: with the environment variable LDPCCI_FAULT=alloc every
+   scratch allocation of a decode fails (LDPC_ENOMEM); with LDPCCI_FAULT=launch every decode
+   launch fails (LDPC_EHIP, ldpc_last_hip_error() = hipErrorLaunchFailure).  Nothing reaches the
+   device in either case.  Read at each call. */
+
 /* schedules */
 #define LDPC_FLOODING 0
 #define LDPC_LAYERED 1
@@ -402,6 +407,16 @@ int ldpc_sweep_run(ldpc_sweep* sweep, uint64_t seed, int64_t* counters, void* st
 
 /* Destroy a sweep (waits for the device first).  NULL is ignored. */
 void ldpc_sweep_free(ldpc_sweep* sweep);
+
+/* ---- stopping decodes ------------------------------------------------------------------------
+   Process-wide abort flag, for serving loops that must stop work in flight.  While it is set
+   (on != 0), every decode running or launched later on any device starts no further frame: each
+   frame it has not started gets updates_used = -1, its other outputs left as they were (and the
+   counters of an SNR sweep run meanwhile are not meaningful).  Frames already started finish
+   normally.  Clear it (on = 0) before decoding again.  The flag lives in pinned host memory that
+   the kernels read before each frame, so it takes effect without waiting for the decode's stream.
+   Errors: LDPC_EHIP (the flag could not be created). */
+int ldpc_request_abort(int32_t on);
 
 /* ---- measurement ----------------------------------------------------------------------------
    The denominator of an LDS roofline, measured: `blocks` workgroups of 256 lanes each fill a

@@ -136,7 +136,8 @@ __global__ __launch_bounds__(1024) void k_flood(DevCode H, BaseParams P) {
   llr_t* L = reinterpret_cast<llr_t*>(lds + P.off_L);
   val_t* ch = reinterpret_cast<val_t*>(lds + P.off_ch);
   uint32_t* synw = reinterpret_cast<uint32_t*>(lds + P.off_syn);
-  int* misc = reinterpret_cast<int*>(lds + P.off_misc);  // [0] unsatisfied checks, [1] row counter
+  // [0] unsatisfied checks, [1] row counter, [2] the abort flag as read for the workgroup
+  int* misc = reinterpret_cast<int*>(lds + P.off_misc);
   A ar;
   ar.qmax = P.qmax;
   ar.scale = P.scale;
@@ -162,6 +163,12 @@ __global__ __launch_bounds__(1024) void k_flood(DevCode H, BaseParams P) {
   for (int f = blockIdx.x; f < P.B; f += gridDim.x) {
     const float* llr = P.llr + (size_t)f * N;
     __syncthreads();  // the previous frame's outputs are read
+    if (tid == 0) misc[2] = abort_flag_value(P.out.abort);
+    __syncthreads();
+    if (misc[2] != 0) {  // not started: the abort flag was set
+      if (tid == 0) P.out.updates_used[f] = -1;
+      continue;
+    }
     for (int n = tid; n < N; n += BS) {
       const val_t x = ar.channel(llr[n]);
       ch[n] = x;
@@ -286,8 +293,14 @@ __global__ __launch_bounds__(1024) void k_layered(DevCode H, BaseParams P) {
   const int Z = kQC ? H.qc.Z : 1;
   const int nl = kQC ? H.qc.mb : H.n_layers;
 
-  int f = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(P.queue, 1) : 0);
+  int aborted = 0;
+  int f = next_frame(P.queue, P.out.abort, lane, aborted);
   while (f < P.B) {
+    if (aborted) {
+      if (lane == 0) P.out.updates_used[f] = -1;  // not started: the abort flag was set
+      f = next_frame(P.queue, P.out.abort, lane, aborted);
+      continue;
+    }
     const float* llr = P.llr + (size_t)f * N;
     for (int n = lane; n < N; n += WAVE) L[n] = (llr_t)ar.channel(llr[n]);
     for (int e = lane; e < E; e += WAVE) c2v[e] = (msg_t)0;
@@ -389,7 +402,7 @@ __global__ __launch_bounds__(1024) void k_layered(DevCode H, BaseParams P) {
       if (P.out.fallbacks) P.out.fallbacks[f] = 0;
     }
     wave_sync();
-    f = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(P.queue, 1) : 0);
+    f = next_frame(P.queue, P.out.abort, lane, aborted);
   }
 }
 

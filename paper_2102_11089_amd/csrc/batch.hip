@@ -135,9 +135,8 @@ __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
   int cur = -1;
   typename TopoSel<TOPO>::type G{};
   while (true) {
-    int f = 0;
-    if (lane == 0) f = atomicAdd(B.queue, 1);
-    f = uni(f);
+    int aborted = 0;
+    const int f = next_frame(B.queue, B.abort, lane, aborted);
     if (f >= B.F) break;
     const BatchFrame d = B.frames[f];
     const bool kind_ok = d.kind == KIND_FLOODING || d.kind == KIND_LAYERED || d.kind == KIND_RBP || d.kind == KIND_CIRBP ||
@@ -146,7 +145,7 @@ __global__ __launch_bounds__(WAVE) void k_batch(BatchParams B) {
               d.out_off >= 0 && d.gamma >= 0.0f;
     const DevCode& H = *B.codes[ok ? d.code : 0];
     ok = ok && d.llr_off + H.N <= B.llr_len && d.out_off + H.N <= B.out_len;
-    if (!ok) {
+    if (!ok || aborted) {  // malformed, or not started because the abort flag was set
       if (lane == 0) {
         B.updates_used[f] = -1;
         if (B.steps_used) B.steps_used[f] = 0;

@@ -558,6 +558,25 @@ struct TopoQC {
   }
 };
 
+// The process's abort flag (fine-grained host memory, written by ldpc_request_abort): a nonzero
+// value stops decoders from starting further frames.  A system-scope load, so that a host write
+// reaches kernels that are running.
+__device__ __forceinline__ int abort_flag_value(const int* flag) {
+  return flag ? __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0;
+}
+
+// Next frame of a work queue and the abort flag, read by lane 0 with both requests in flight
+// together and made wave-uniform.
+__device__ __forceinline__ int next_frame(int* queue, const int* flag, int lane, int& aborted) {
+  int f = 0, a = 0;
+  if (lane == 0) {
+    f = atomicAdd(queue, 1);
+    a = abort_flag_value(flag);
+  }
+  aborted = __builtin_amdgcn_readfirstlane(a);
+  return __builtin_amdgcn_readfirstlane(f);
+}
+
 // splitmix64 output function (Steele, Lea, Flood, 2014): golden-gamma increment + finaliser
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
   z += 0x9e3779b97f4a7c15ull;

@@ -55,8 +55,9 @@ __global__ __launch_bounds__(MF ? 1024 : WAVE) void k_dynamic(DevCode H, DynPara
   }
   const auto G = TopoSel<TOPO>::make(H, lds + P.off_topo, threadIdx.x, blockDim.x);
   __syncthreads();  // the only workgroup barrier: the frames below run independently
-  int f = (int)frame_slot(P);
-  if (P.queue) f = uni(lane == 0 ? atomicAdd(P.queue, 1) : 0);
+  int f = (int)frame_slot(P), aborted = 0;
+  if (P.queue) f = next_frame(P.queue, P.out.abort, lane, aborted);
+  else aborted = uni(lane == 0 ? abort_flag_value(P.out.abort) : 0);
   while (f < P.B) {
     FrameJob J;
     J.kind = P.kind;
@@ -77,9 +78,16 @@ __global__ __launch_bounds__(MF ? 1024 : WAVE) void k_dynamic(DevCode H, DynPara
     J.dump_L = P.out.dump_L ? P.out.dump_L + (size_t)f * H.N : nullptr;
     J.dump_Lt = P.out.dump_Lt ? P.out.dump_Lt + (size_t)f * H.N : nullptr;
     J.dump_D = P.out.dump_D ? P.out.dump_D + (size_t)f * H.N : nullptr;
-    dyn_decode_frame<A, STORE, decltype(G), LMD, true>(H, G, ar, P, ms, J);
-    if (P.queue) f = uni(lane == 0 ? atomicAdd(P.queue, 1) : 0);
-    else f += gridDim.x * P.wpb;
+    if (!aborted)
+      dyn_decode_frame<A, STORE, decltype(G), LMD, true>(H, G, ar, P, ms, J);
+    else if (lane == 0)
+      *J.updates_used = -1;  // not started: the abort flag was set
+    if (P.queue) {
+      f = next_frame(P.queue, P.out.abort, lane, aborted);
+    } else {
+      f += gridDim.x * P.wpb;
+      aborted = uni(lane == 0 ? abort_flag_value(P.out.abort) : 0);
+    }
   }
 }
 

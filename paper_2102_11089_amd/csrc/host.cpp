@@ -45,6 +45,42 @@ int hip_fail(hipError_t e) {
   return LDPC_EHIP;
 }
 
+// Fault injection for tests of the error paths: LDPCCI_FAULT=alloc fails every scratch allocation
+// as out of memory, LDPCCI_FAULT=launch fails every decode launch; nothing reaches the device.
+enum { FAULT_NONE = 0, FAULT_ALLOC, FAULT_LAUNCH };
+int injected_fault() {
+  const char* v = std::getenv("LDPCCI_FAULT");
+  if (!v) return FAULT_NONE;
+  if (!std::strcmp(v, "alloc")) return FAULT_ALLOC;
+  if (!std::strcmp(v, "launch")) return FAULT_LAUNCH;
+  return FAULT_NONE;
+}
+
+// The process's abort flag: one int of fine-grained pinned host memory, mapped for every device,
+// created with the first code handle (or the first ldpc_request_abort) and kept until the process
+// ends.  Kernels read it before each frame they start.
+std::mutex g_abort_mu;
+int* g_abort_host = nullptr;
+const int* g_abort_dev = nullptr;
+
+int ensure_abort_flag() {
+  std::lock_guard<std::mutex> lk(g_abort_mu);
+  if (g_abort_host) return LDPC_OK;
+  int* p = nullptr;
+  hipError_t he = hipHostMalloc((void**)&p, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable);
+  if (he != hipSuccess) return hip_fail(he);
+  __atomic_store_n(p, 0, __ATOMIC_SEQ_CST);
+  void* d = nullptr;
+  he = hipHostGetDevicePointer(&d, p, 0);
+  if (he != hipSuccess) {
+    (void)hipHostFree(p);
+    return hip_fail(he);
+  }
+  g_abort_dev = static_cast<const int*>(d);
+  g_abort_host = p;
+  return LDPC_OK;
+}
+
 int align16(int x) { return (x + 15) & ~15; }
 
 // A kernel family's dynamic-LDS limit is raised with one hipFuncSetAttribute per variant (140 for
@@ -97,6 +133,7 @@ hipMemPool_t scratch_pool(int dev) {
 }
 
 hipError_t scratch_alloc(void** p, size_t bytes, hipStream_t st) {
+  if (injected_fault() == FAULT_ALLOC) return hipErrorOutOfMemory;
   int dev = 0;
   hipError_t he = hipGetDevice(&dev);
   if (he != hipSuccess) return he;
@@ -283,6 +320,12 @@ const char* ldpc_strerror(int code) {
 
 int ldpc_last_hip_error(void) { return g_last_hip; }
 
+int ldpc_request_abort(int32_t on) {
+  if (int rc = ensure_abort_flag()) return rc;
+  __atomic_store_n(g_abort_host, on ? 1 : 0, __ATOMIC_SEQ_CST);
+  return LDPC_OK;
+}
+
 static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32_t* col_idx,
                        const int32_t* layer_ptr, int32_t n_layers, const std::vector<int>* qc, int qZ, int qmb,
                        int qnb, int qnblk, ldpc_code** out) {
@@ -456,6 +499,10 @@ static int create_code(int32_t M, int32_t N, const int32_t* row_ptr, const int32
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return LDPC_EHIP;
+  }
+  if (int rc = ensure_abort_flag()) {
+    delete c;
+    return rc;
   }
   hipError_t he = hipMalloc((void**)&c->d_buf, blob.size() * sizeof(int));
   if (he != hipSuccess) {
@@ -784,6 +831,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
   o.dump_L = out->dump_L;
   o.dump_Lt = out->dump_Lt;
   o.dump_D = out->dump_D;
+  o.abort = ldpc::abort_flag_address();
 
   if (s->kind == LDPC_FLOODING || s->kind == LDPC_LAYERED) {
     BaseParams& P = pl.base;
@@ -1130,6 +1178,7 @@ hipError_t plan_lds_limits(const DecodePlan& pl) {
 // With set_attr false the caller has applied plan_lds_limits already (stream capture).
 hipError_t enqueue_decode(const ldpc_code* c, DecodePlan& pl, void* scratch, hipStream_t st, bool set_attr = true) {
   if (pl.grid <= 0) return hipSuccess;
+  if (injected_fault() == FAULT_LAUNCH) return hipErrorLaunchFailure;
   if (set_attr) {
     hipError_t he = plan_lds_limits(pl);
     if (he != hipSuccess) return he;
@@ -1253,6 +1302,11 @@ int fit_plan_to_scratch(const ldpc_code* c, DecodePlan& pl, size_t cap) {
 namespace ldpc {
 
 int record_hip_failure(hipError_t e) { return hip_fail(e); }
+
+const int* abort_flag_address() {
+  std::lock_guard<std::mutex> lk(g_abort_mu);
+  return g_abort_dev;
+}
 
 int decode_in_scratch(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in, int32_t B,
                       int64_t max_updates, const int32_t* replay, int64_t replay_len, const ldpc_outputs* out,
@@ -1617,6 +1671,7 @@ int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldp
   B.steps_used = steps_used;
   B.fallbacks = fallbacks;
   B.max_E = bp.mx.E;
+  B.abort = ldpc::abort_flag_address();
   void* scratch = nullptr;
   hipError_t he = scratch_alloc(&scratch, 256 + bp.pre_bytes, st);
   if (he != hipSuccess) return he == hipErrorOutOfMemory ? LDPC_ENOMEM : hip_fail(he);
@@ -1624,6 +1679,7 @@ int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldp
   B.queue = reinterpret_cast<int*>(scratch);
   P.pre_global = bp.store != STORE_LDS ? (char*)scratch + 256 : nullptr;
   he = raise_lds_limit(FAM_BATCH, bp.lds_limit, set_batch_lds_limit);
+  if (he == hipSuccess && injected_fault() == FAULT_LAUNCH) he = hipErrorLaunchFailure;
   if (he == hipSuccess) he = launch_batch(B, fixed, bp.store, bp.topo, bp.grid, st);
   (void)hipFreeAsync(scratch, st);
   return he == hipSuccess ? LDPC_OK : hip_fail(he);

@@ -52,6 +52,7 @@ struct DecOut {
   float* dump_L;            // [B][N] or null
   float* dump_Lt;           // [B][N] or null
   float* dump_D;            // [B][N] or null
+  const int* abort;         // the device's abort flag (nonzero: frames not yet started are skipped)
 };
 
 struct DynParams {
@@ -184,6 +185,8 @@ struct TopoSel<TOPO_QC> {
 
 hipError_t launch_dynamic(const DevCode& H, const DynParams& P, bool fixed, int store, int topo, int grid,
                           hipStream_t st);
+// address of the current device's abort flag (set by ldpc_request_abort), null if it cannot be had
+const int* abort_flag_address();
 hipError_t set_dynamic_lds_limit(int bytes);
 // wavefronts of one single-edge kernel variant a SIMD can hold by its register count (1..8)
 int dynamic_waves_per_simd(bool fixed, int store, int topo, bool mf, bool lmd);
@@ -234,6 +237,7 @@ struct BatchParams {
   int64_t* fallbacks;
   int* queue;               // work-queue counter
   int max_E;
+  const int* abort;         // the device's abort flag
 };
 
 // damped replay of a fixed schedule (forward with checkpoints) and its adjoint

@@ -38,6 +38,7 @@ namespace ldpc {
 enum { MS_UNSAT = 0, MS_NROWS, MS_NSEL, MS_BSTAR, MS_FILL, MS_NEED, MS_CNT, MS_NCAND, MS_WAVESUM, MS_RBIN, MS_RBELOW,
        MS_L2,                 // MS_L2 + c - 1: touched checks with blocks of 2^c lanes, c = 1..5
        MS_NSUCC = MS_L2 + 5,  // ME-LMD-CIRBP: |P'|
+       MS_ABORT,              // the abort flag as read for the workgroup at a frame's start
        kMiscWords = 32 };     // misc[0, kMiscWords): the counters above; then one word per wavefront
 
 // exclusive prefix sum over the workgroup (lane order); wsum: one int per wave in LDS
@@ -103,6 +104,13 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
   __syncthreads();
 
   for (int f = blockIdx.x; f < P.B; f += gridDim.x) {
+    __syncthreads();  // the previous frame is done with the workgroup's LDS
+    if (tid == 0) misc[MS_ABORT] = abort_flag_value(P.out.abort);
+    __syncthreads();
+    if (misc[MS_ABORT] != 0) {  // not started: the abort flag was set
+      if (tid == 0) P.out.updates_used[f] = -1;
+      continue;
+    }
     // ---------------- Algorithm 5, initialisation ---------------------------------------
     const float* llr = P.llr + (size_t)f * N;
     for (int n = tid; n < N; n += BS) L[n] = (llr_t)ar.channel(llr[n]);

@@ -32,7 +32,7 @@ EXPORTS = ("ldpc_code_from_csr", "ldpc_code_from_qc", "ldpc_code_info", "ldpc_co
            "ldpc_set_batch_tuning", "ldpc_get_batch_tuning", "ldpc_autotune_batch", "ldpc_tuning_save",
            "ldpc_tuning_load", "ldpc_awgn_frames", "ldpc_sweep_create", "ldpc_sweep_run", "ldpc_sweep_free",
            "ldpc_unrolled_ckpt_floats", "ldpc_unrolled_forward", "ldpc_unrolled_backward",
-           "ldpc_probe_lds", "ldpc_strerror", "ldpc_last_hip_error")
+           "ldpc_request_abort", "ldpc_probe_lds", "ldpc_strerror", "ldpc_last_hip_error")
 UNROLL_MAX_CKPT_EVERY = 128
 STORE_AUTO, STORE_LDS, STORE_GLOBAL, STORE_GLOBAL_ALL, STORE_GLOBAL_LT, STORE_GLOBAL_FRAME, STORE_GLOBAL_REC, \
     STORE_GLOBAL_STATE = 0, 1, 2, 3, 4, 5, 6, 7
@@ -137,6 +137,8 @@ def load(path: str = LIB_PATH):
     lib.ldpc_probe_lds.argtypes = [C.c_int32, C.c_int32, C.c_int64, P, P, C.POINTER(C.c_double),
                                    C.POINTER(C.c_float)]
     lib.ldpc_probe_lds.restype = C.c_int
+    lib.ldpc_request_abort.argtypes = [C.c_int32]
+    lib.ldpc_request_abort.restype = C.c_int
     lib.ldpc_sweep_create.argtypes = [P, C.POINTER(ldpc_schedule), C.c_int64, P, C.c_int32, P, C.c_int32, C.c_float,
                                       C.c_int32, C.POINTER(C.c_void_p)]
     lib.ldpc_sweep_create.restype = C.c_int
@@ -317,6 +319,12 @@ def ldpc_awgn_frames(cw_ptr: int, P: int, N: int, B: int, sigma2: float, seed: i
                      stream: int) -> None:
     _check(load().ldpc_awgn_frames(cw_ptr, P, N, B, sigma2, seed & (2**64 - 1), point, llr_ptr, stream),
            "ldpc_awgn_frames")
+
+
+def ldpc_request_abort(on: bool) -> None:
+    """Set (True) or clear (False) the process-wide abort flag: decodes start no further frame
+    while it is set, and report updates_used = -1 for the frames they did not start."""
+    _check(load().ldpc_request_abort(1 if on else 0), "ldpc_request_abort")
 
 
 def ldpc_probe_lds(width: int, blocks: int, iters: int, sink_ptr: int, stream: int):
