@@ -37,9 +37,9 @@ def sources_digest() -> str:
     return h.hexdigest()
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
-    """Compile every HIP source (always recompiles), one compiler process per source in parallel,
-    and link them into one shared library."""
+def _compile_link(out: str, extra: list, verbose: bool, jobs: int) -> str:
+    """Compile every HIP source with FLAGS + extra (one compiler process per source, in parallel)
+    and link them into the shared library `out`."""
     import concurrent.futures
     import shutil
     import tempfile
@@ -50,7 +50,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         objs = [os.path.join(work, os.path.basename(src) + ".o") for src in srcs]
 
         def compile_one(src, obj):
-            cmd = ["hipcc", *FLAGS, "-c", "-o", obj, src]
+            cmd = ["hipcc", *FLAGS, *extra, "-c", "-o", obj, src]
             if verbose:
                 print(" ".join(cmd), flush=True)
             subprocess.check_call(cmd)
@@ -58,15 +58,31 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
             for f in [ex.submit(compile_one, s, o) for s, o in zip(srcs, objs)]:
                 f.result()
-        tmp = LIB + ".tmp%d" % os.getpid()
+        tmp = out + ".tmp%d" % os.getpid()
         cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        os.replace(tmp, LIB)
+        os.replace(tmp, out)
     finally:
         shutil.rmtree(work, ignore_errors=True)
-    return LIB
+    return out
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every HIP source (always recompiles) and link them into one shared library."""
+    return _compile_link(LIB, [], verbose, jobs)
+
+
+# Self-checking build for development and tests: after every single-edge update the kernels
+# recompute the touched neighbourhood's derived state from its definition and count mismatches
+# into the buffer whose device address the environment variable LDPCCI_SELFCHECK holds.
+SELFCHECK_LIB = os.path.join(HERE, "libldpcci_selfcheck.so")
+
+
+def build_selfcheck(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile the self-checking variant of the library (always recompiles)."""
+    return _compile_link(SELFCHECK_LIB, ["-DLDPC_SELFCHECK"], verbose, jobs)
 
 
 # Host-side sanitizers: the host code (argument validation, table building, layout sizing) is

@@ -703,6 +703,75 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     }
     wave_sync();
     PROF_MARK(6)
+#ifdef LDPC_SELFCHECK
+    // ---- self-checking builds: the state of the touched neighbourhood against its definition.
+    //      For every VN of the two-hop table, of m*'s row and n* itself: L = channel + sum of
+    //      C2V, Lt = channel + sum of the precomputed messages, a stored D = ci(L, Lt) (exact in
+    //      fixed point; FP32 within 1e-3 of the larger magnitude, the incremental sums having
+    //      rounded in another order); for every check of n*, its key = the largest residual of its
+    //      row; the VN block of n* and the check block of m* = the largest of their leaves (keys
+    //      and blocks not for the LMD schedules, which leave them stale by design).  Mismatches
+    //      are counted per kind; nothing stops the decode. ----
+    if (P.selfcheck) {
+      auto close = [&](val_t a, val_t b) -> bool {
+        if constexpr (A::kFixed) {
+          return a == b;
+        } else {
+          const float x = ar.as_float(a), y = ar.as_float(b);
+          return fabsf(x - y) <= 1e-3f * fmaxf(1.0f, fmaxf(fabsf(x), fabsf(y)));
+        }
+      };
+      auto check_vn = [&](int j) -> int {
+        const val_t ch = ar.channel(J.llr[j]);
+        val_t sl = ch, slt = ch;
+        const int dvj = G.vn_deg(j);
+        for (int k = 0; k < dvj; ++k) {
+          int mm, ee;
+          G.vn_edge(j, k, mm, ee);
+          sl += (val_t)ms.c(ee);
+          slt += (val_t)ms.p(ee);
+        }
+        int bad = close((val_t)ms.l(j), sl) ? 0 : 1;
+        if (with_ci) {
+          if (!close((val_t)ms.lt(j), slt)) bad |= 2;
+          if constexpr (!FrameStore<A, STORE, STREAM>::kDerivedD) {
+            if (ms.d(j) != ar.ci((val_t)ms.l(j), (val_t)ms.lt(j))) bad |= 4;
+          }
+        }
+        return bad;
+      };
+      int bad = 0;
+      for (int ps = 0; ps < npass; ++ps) {
+        const int2 ent = load_ent(ps);
+        if (ent.x >= 0) bad |= check_vn(ent.y & 0xFFFFFF);
+      }
+      if (lane < dc_m) bad |= check_vn(G.row_vn(mstar, rs_m, lane));
+      if (lane == 0) bad |= check_vn(nstar);
+      if (!lmd) {
+        if (lane < dv) {  // the key of every check of n*
+          const int rs = G.row_start(my_m), dc = G.row_deg(my_m);
+          uint32_t kv = 0;
+          for (int p = 0; p < dc; ++p) {
+            msg_t cm, pm;
+            ms.cp(rs + p, cm, pm);
+            kv = max(kv, ar.res((val_t)pm, (val_t)cm));
+          }
+          if (kv != ckey[my_m]) bad |= 8;
+        }
+        const int nb = (nstar >> 6) * WAVE + lane, mb = (mstar >> 6) * WAVE + lane;
+        const uint64_t kd = wave_max_u64((with_ci && nb < N) ? mkkey(d_of(nb), (uint32_t)nb) : 0ull);
+        const uint64_t kc = wave_max_u64(mb < M ? mkkey(ckey[mb], (uint32_t)mb) : 0ull);
+        if (lane == 0 && with_ci && kd != dblk[nstar >> 6]) bad |= 16;
+        if (lane == 0 && kc != cblk[mstar >> 6]) bad |= 32;
+      }
+      for (int kind = 0; kind < 6; ++kind) {
+        const int cnt = wave_sum_i32((bad >> kind) & 1);
+        if (lane == 0 && cnt) atomicAdd(&P.selfcheck[kind], (unsigned long long)cnt);
+      }
+      if (lane == 0) atomicAdd(&P.selfcheck[7], 1ull);
+      wave_sync();
+    }
+#endif
     if (J.trace && lane == 0) J.trace[t] = estar;
     t += 1;
     if (ce > 0) {

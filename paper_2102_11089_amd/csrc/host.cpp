@@ -1143,6 +1143,10 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
 #ifdef LDPC_PROFILE
   if (const char* pp = std::getenv("LDPCCI_PROF")) P.prof = (long long*)std::strtoull(pp, nullptr, 10);
 #endif
+  P.selfcheck = nullptr;
+#ifdef LDPC_SELFCHECK
+  if (const char* sp = std::getenv("LDPCCI_SELFCHECK")) P.selfcheck = (unsigned long long*)std::strtoull(sp, nullptr, 10);
+#endif
   pl.which = 1;
   pl.block = WAVE * P.wpb;
   // persistent grid (workers pull frames from a queue) unless one workgroup per frame fills the
@@ -1639,6 +1643,9 @@ int decode_batch_tuned(const ldpc_code* const* codes, int32_t n_codes, const ldp
   hipStream_t st = (hipStream_t)stream;
   BatchParams B{};
   DynParams& P = B.P;
+#ifdef LDPC_SELFCHECK
+  if (const char* sp = std::getenv("LDPCCI_SELFCHECK")) P.selfcheck = (unsigned long long*)std::strtoull(sp, nullptr, 10);
+#endif
   P.check_every = s->check_every;
   P.qmax = (1 << (std::max(s->q_bits, 2) - 1)) - 1;
   P.scale = std::ldexp(1.0f, fixed ? s->frac_bits : 0);

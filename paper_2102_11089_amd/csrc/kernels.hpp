@@ -89,6 +89,9 @@ struct DynParams {
   int lds_bytes;
   int nbd, nbc, nbd_words, nbc_words;
   long long* prof;          // development builds only: per-phase cycle sums (null otherwise)
+  // self-checking builds only: mismatches per kind (L, Lt, D, check key, VN block, check block;
+  // [7] updates checked), null otherwise
+  unsigned long long* selfcheck;
 };
 
 // one frame of a dynamic-schedule decode: limits and frame-local input/output pointers
