@@ -85,6 +85,16 @@ def build_selfcheck(verbose: bool = False, jobs: int = 0) -> str:
     return _compile_link(SELFCHECK_LIB, ["-DLDPC_SELFCHECK"], verbose, jobs)
 
 
+# Phase-timing build for development: the single-edge and multi-edge kernels sum clock64() deltas
+# per phase into the buffer whose device address LDPCCI_PROF holds (profcase's `phase` case).
+PROFILE_LIB = os.path.join(HERE, "libldpcci_profile.so")
+
+
+def build_profile(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile the phase-timing variant of the library (always recompiles)."""
+    return _compile_link(PROFILE_LIB, ["-DLDPC_PROFILE"], verbose, jobs)
+
+
 # Host-side sanitizers: the host code (argument validation, table building, layout sizing) is
 # instrumented with AddressSanitizer and UndefinedBehaviorSanitizer; device code never is.
 SAN_DIR = os.path.join(HERE, "_build")
@@ -141,6 +151,8 @@ def build_sanitized(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
-    print(LIB)
+    # python -m paper_2102_11089_amd.build [selfcheck|profile]: the library, or one of its variants
+    which = sys.argv[1] if len(sys.argv) > 1 else ""
+    out = {"selfcheck": build_selfcheck, "profile": build_profile}.get(which, build)(verbose=True)
+    print(out)
     sys.exit(0)

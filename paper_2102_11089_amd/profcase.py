@@ -4,6 +4,7 @@
     python -m paper_2102_11089_amd.profcase copy <bytes>
     python -m paper_2102_11089_amd.profcase random <bytes> <accesses> [width bytes]
     python -m paper_2102_11089_amd.profcase account [frames] [sector bytes]
+    python -m paper_2102_11089_amd.profcase phase <profile library> c1|c3
     python -m paper_2102_11089_amd.profcase traffic <out.json> <kernel> <fetch.csv> <write.csv> \
         <copy_fetch.csv> <copy_write.csv> <copy_bytes> [workload text]
 
@@ -19,6 +20,11 @@ memory system's rate for the decoder's scattered record accesses.
 
 ``account`` counts, per single-edge update of a traced c1 decode, the memory sectors each part of
 the frame state costs in the benchmark's layout (pairs, VN records, two-hop table).
+
+``phase`` loads the phase-timing build (``python -m paper_2102_11089_amd.build profile``) and
+prints the cycles per update (c1: FP32 CIRBP, 65536 frames at 1.25 dB, 256 distinct) or per step
+(c3: ME-CIRBP and ME-LMD-CIRBP at N_P 8 and 64, 8192 frames at 1.5 dB, 256 distinct) that each phase takes, summed over the
+wavefronts (c1) or over thread 0 of each workgroup (c3).
 
 ``traffic`` turns rocprofv3 counter files (``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` runs,
 ``*_counter_collection.csv``) into HBM bytes for the first dispatch whose kernel name contains
@@ -165,7 +171,61 @@ def account_case(frames: int, sector: int = 64):
     print(json.dumps(doc), flush=True)
 
 
+def phase_case(lib: str, which: str):
+    """Per-phase cycle sums of the phase-timing build (see the module docstring)."""
+    import os
+    import numpy as np
+    import torch
+    from . import ldpc
+    from . import synth as S
+    ldpc.load(lib)
+    prof = torch.zeros(16, dtype=torch.int64, device="cuda")
+    if which == "c1":
+        code = S.workload_code("c1")
+        h = ldpc.Code(code)
+        _, llr = S.frames(code, 256, 1.25, 7)
+        x = torch.from_numpy(llr).cuda().repeat(256, 1)  # 65536 frames, 256 distinct
+        for it in range(2):
+            prof.zero_()
+            os.environ["LDPCCI_PROF"] = str(prof.data_ptr()) if it == 1 else "0"
+            r = ldpc.decode(h, x, ldpc.CIRBP, ldpc.SPA_F32, max_updates=3 * code.E, gamma=0.1)
+            torch.cuda.synchronize()
+        upd = int(r.updates_used.sum())
+        p = prof.cpu().numpy().astype(np.float64)
+        names = {7: "loop top", 0: "selection", 1: "propagation", 3: "passes", 5: "groups and late CI",
+                 6: "block recomputation"}
+        tot = p[:8].sum()
+        for i in (7, 0, 1, 3, 5, 6):
+            print(f"{names[i]:22s} {p[i] / upd:9.0f} cycles per update {100 * p[i] / tot:5.1f}%", flush=True)
+        print(f"total {tot / upd:.0f} cycles per update per wavefront", flush=True)
+        return
+    code = S.workload_code("c3")
+    h = ldpc.Code(code)
+    B = 8192
+    _, llr = S.frames(code, 256, 1.5, 7)
+    x = torch.from_numpy(llr).cuda().repeat(B // 256, 1)  # 8192 frames, 256 distinct
+    names = {7: "loop top", 0: "P' and group pass", 1: "fill (radix selection)", 2: "edge choice, propagation",
+             3: "sort of touched checks", 4: "touched checks' rows", 5: "CI pass", 6: "Algorithm 6 proposals"}
+    for kind, kn in ((ldpc.ME_CIRBP, "ME-CIRBP"), (ldpc.ME_LMD_CIRBP, "ME-LMD-CIRBP")):
+        for n_p in (8, 64):
+            for it in range(2):
+                prof.zero_()
+                os.environ["LDPCCI_PROF"] = str(prof.data_ptr()) if it == 1 else "0"
+                r = ldpc.decode(h, x, kind, ldpc.SPA_F32, max_updates=3 * code.E, gamma=0.1, n_p=n_p, n_g=16,
+                                fill=ldpc.FILL_HASH, seed=2102)
+                torch.cuda.synchronize()
+            steps = int(r.steps_used.sum())
+            p = prof.cpu().numpy().astype(np.float64)
+            tot = p[:8].sum()
+            print(f"{kn} N_P {n_p}: {steps / B:.0f} steps per frame, {tot / steps:.0f} cycles per step", flush=True)
+            for i in (7, 0, 1, 2, 3, 4, 5, 6):
+                print(f"   {names[i]:26s} {p[i] / steps:8.0f} cycles per step {100 * p[i] / tot:5.1f}%", flush=True)
+
+
 def main():
+    if sys.argv[1] == "phase":
+        phase_case(sys.argv[2], sys.argv[3])
+        return
     if sys.argv[1] == "account":
         account_case(int(sys.argv[2]) if len(sys.argv) > 2 else 16, int(sys.argv[3]) if len(sys.argv) > 3 else 64)
         return
