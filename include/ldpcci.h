@@ -84,7 +84,8 @@ extern "C" {
 /* Reproducibility: every schedule gives a frame the same outputs on every run and in every launch
    shape (tested bit for bit), in both arithmetics.  In the multi-edge schedules several checks
    updated in one step can change the precomputed total LLR of the same VN; in LDPC_SPA_F32 those
-   changes are summed per VN in ascending check order. */
+   changes are summed exactly per VN (each rounded to a multiple of 2^-32, added as 64-bit
+   integers), or, in a step that changes more than 2048 such VNs, in ascending check order. */
 
 /* arithmetic */
 #define LDPC_SPA_F32 0  /* sum-product, FP32 messages                                          */

@@ -257,7 +257,7 @@ DynLayout dyn_layout(const ldpc_code* c, bool fixed, int store, int topo, int wp
 // LDS layout of the multi-edge decoder; returns the total bytes
 struct MeLayout {
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;
-  int off_cand, off_misc, off_lut, off_topo, off_rows2, off_vnmulti, total, rows_cap, cand_cap;
+  int off_cand, off_misc, off_lut, off_topo, off_rows2, off_vnmulti, off_mpref, off_macc, total, rows_cap, cand_cap;
 };
 
 // LDS of the unrolled kernels: forward (c2v, L); backward adds the adjoints and the segment tape
@@ -291,6 +291,8 @@ MeLayout me_layout(const ldpc_code* c, bool fixed, bool msg_global, int topo, in
   L.off_rowmark = o; o = align16(o + nsw * 4);
   L.off_vnmark = o; o = align16(o + nvw * 4);
   L.off_vnmulti = o; o = align16(o + nvw * 4);  // VNs that two or more checks of a step change
+  L.off_mpref = o; if (!fixed) o = align16(o + nvw * 4);             // their rank: prefix counts per word
+  L.off_macc = o; if (!fixed) o = align16(o + kMeAccSlots * 8);      // and their exact 64-bit sums
   L.off_rows = o; o = align16(o + L.rows_cap * 4);
   L.off_rows2 = o; o = align16(o + L.rows_cap * 4);  // the same checks sorted by block size
   L.off_sel = o; o = align16(o + 5 * 64 * 4);  // set, sorted set, class counters, P', m* per VN
@@ -991,6 +993,7 @@ int plan_decode(const ldpc_code* c, const ldpc_schedule* s, const float* llr_in,
     Q.off_hist = Ly.off_hist; Q.off_synw = Ly.off_synw; Q.off_rowmark = Ly.off_rowmark; Q.off_vnmark = Ly.off_vnmark;
     Q.off_rows = Ly.off_rows; Q.off_sel = Ly.off_sel; Q.off_cand = Ly.off_cand; Q.off_misc = Ly.off_misc;
     Q.off_lut = Ly.off_lut; Q.off_topo = Ly.off_topo; Q.off_rows2 = Ly.off_rows2; Q.off_vnmulti = Ly.off_vnmulti;
+    Q.off_mpref = Ly.off_mpref; Q.off_macc = Ly.off_macc;
     Q.lds_bytes = Ly.total;
     Q.rows_cap = Ly.rows_cap;
     Q.cand_cap = Ly.cand_cap;

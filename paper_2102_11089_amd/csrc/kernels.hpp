@@ -211,10 +211,15 @@ struct MeParams {
   float* dbuf;              // FP32: grid x E changes of the precomputed messages of one step
   int off_c2v, off_pre, off_L, off_Lt, off_D, off_hist, off_synw, off_rowmark, off_vnmark, off_rows, off_sel;
   int off_cand, off_misc, off_lut, off_topo, off_rows2, off_vnmulti;
+  int off_mpref, off_macc;  // FP32: prefix counts of vnmulti words, 64-bit sums of multiply-changed VNs
   int lds_bytes;
   int rows_cap, cand_cap;
   long long* prof;          // development builds only: per-phase cycle sums (null otherwise)
 };
+
+// FP32 multi-edge: LDS slots for the exact sums of the VNs that several checks of one step change
+// (a step with more such VNs sums them in check order instead)
+constexpr int kMeAccSlots = 2048;
 
 // batched launch: one descriptor per frame (layout of ldpc_frame_desc)
 struct BatchFrame {

@@ -39,6 +39,7 @@ enum { MS_UNSAT = 0, MS_NROWS, MS_NSEL, MS_BSTAR, MS_FILL, MS_NEED, MS_CNT, MS_N
        MS_L2,                 // MS_L2 + c - 1: touched checks with blocks of 2^c lanes, c = 1..5
        MS_NSUCC = MS_L2 + 5,  // ME-LMD-CIRBP: |P'|
        MS_ABORT,              // the abort flag as read for the workgroup at a frame's start
+       MS_NMULTI,             // FP32: VNs that several checks of the step changed
        kMiscWords = 32 };     // misc[0, kMiscWords): the counters above; then one word per wavefront
 
 // exclusive prefix sum over the workgroup (lane order); wsum: one int per wave in LDS
@@ -77,6 +78,8 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
   // FP32: VNs whose precomputed total two or more checks of the step change, and the step's
   // changes of the precomputed messages (global, one float per edge of this workgroup's frame)
   uint32_t* vnmulti = reinterpret_cast<uint32_t*>(lds + P.off_vnmulti);
+  int* mpref = reinterpret_cast<int*>(lds + P.off_mpref);
+  long long* macc = reinterpret_cast<long long*>(lds + P.off_macc);
   float* dbuf = A::kFixed ? nullptr : P.dbuf + (size_t)blockIdx.x * (size_t)E;
   int* rows = reinterpret_cast<int*>(lds + P.off_rows);
   int* rows2 = reinterpret_cast<int*>(lds + P.off_rows2);
@@ -507,6 +510,47 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       if constexpr (MSG_GLOBAL || !A::kFixed) __threadfence_block();  // pairs and step changes in global memory
       __syncthreads();
       ME_PROF_MARK(4)
+      // ---- FP32: the changes of a VN that several checks of the step changed are summed exactly,
+      //      each rounded to a multiple of 2^-32 and added as a 64-bit integer into the VN's LDS
+      //      slot (its rank among those VNs), so that no order of the adds matters.  With more
+      //      such VNs than slots, the CI pass sums their changes in ascending check order. ----
+      bool use_acc = false;
+      if constexpr (!A::kFixed) {
+        if (tid < WAVE) {  // exclusive prefix of the per-word counts of multiply-changed VNs
+          int run = 0;
+          for (int w0 = 0; w0 < nvw; w0 += WAVE) {
+            const int w = w0 + tid;
+            const int c = w < nvw ? __popc(vnmulti[w]) : 0;
+            const int ex = run + wave_excl_scan(c, tid);
+            if (w < nvw) mpref[w] = ex;
+            run = __builtin_amdgcn_readlane(ex + c, WAVE - 1);
+          }
+          if (tid == 0) misc[MS_NMULTI] = run;
+        }
+        __syncthreads();
+        const int nmulti = misc[MS_NMULTI];
+        use_acc = nmulti <= kMeAccSlots;
+        if (use_acc && nmulti > 0) {
+          for (int x = tid; x < nmulti; x += BS) macc[x] = 0;
+          __syncthreads();
+          for (int base = 0; base < total; base += BS) {
+            int m, pos, l2;
+            if (lane_row(base + tid, m, pos, l2)) {
+              const int rs = G.row_start(m), dc = G.row_deg(m);
+              if (pos < dc) {
+                const int j = G.row_vn(m, rs, pos);
+                const uint32_t w = vnmulti[j >> 5], bit = 1u << (j & 31);
+                if (w & bit) {
+                  const long long q = __float2ll_rn(dbuf[rs + pos] * 4294967296.0f);
+                  atomicAdd(reinterpret_cast<unsigned long long*>(&macc[mpref[j >> 5] + __popc(w & (bit - 1))]),
+                            (unsigned long long)q);
+                }
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
       // ---- CI and CI group of every VN of those checks (each VN once) ----
       for (int base = 0; base < total; base += BS) {
         int m, pos, l2;
@@ -521,7 +565,11 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
             else owner = (atomicAnd(&vnmark[j >> 5], ~bit) & bit) != 0;
             if (owner) {
               if constexpr (!A::kFixed) {
-                if (vnmulti[j >> 5] & bit) {  // the changes of every check of the step, ascending
+                const uint32_t mw = vnmulti[j >> 5];
+                if ((mw & bit) && use_acc) {  // the exact sum of the step's changes
+                  const long long q = macc[mpref[j >> 5] + __popc(mw & (bit - 1))];
+                  Lt[j] = (llr_t)((double)Lt[j] + (double)q * 0x1p-32);
+                } else if (mw & bit) {  // the changes of every check of the step, ascending
                   val_t lt = (val_t)Lt[j];
                   const int dvj = G.vn_deg(j);
                   for (int k0 = 0; k0 < dvj; k0 += 16) {  // 16 loads in flight, then the sums in order
