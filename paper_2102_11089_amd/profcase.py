@@ -6,7 +6,7 @@
     python -m paper_2102_11089_amd.profcase account [frames] [sector bytes]
     python -m paper_2102_11089_amd.profcase phase <profile library> c1|c3
     python -m paper_2102_11089_amd.profcase traffic <out.json> <kernel> <fetch.csv> <write.csv> \
-        <copy_fetch.csv> <copy_write.csv> <copy_bytes> [workload text]
+        <copy_fetch.csv> <copy_write.csv> <copy_bytes> [workload text] [first|last]
 
 workload: c0 (PEG (3,6) n=96), c1 (BG1-shaped Z=52), c4 (PEG (3,6) n=576); schedule: cirbp | rbp |
 flooding | layered; arith: f32 | fix.  One untimed warm-up decode, then one decode; prints the
@@ -27,8 +27,8 @@ prints the cycles per update (c1: FP32 CIRBP, 65536 frames at 1.25 dB, 256 disti
 wavefronts (c1) or over thread 0 of each workgroup (c3).
 
 ``traffic`` turns rocprofv3 counter files (``--pmc FETCH_SIZE`` and ``--pmc WRITE_SIZE`` runs,
-``*_counter_collection.csv``) into HBM bytes for the first dispatch whose kernel name contains
-<kernel>: each counter (KiB per dispatch) is scaled by the ratio of the copy's known bytes to what
+``*_counter_collection.csv``) into HBM bytes for the first (default) or last dispatch whose kernel
+name contains <kernel>: each counter (KiB per dispatch) is scaled by the ratio of the copy's known bytes to what
 the same counter read for the largest dispatch of the copy run.  Writes a JSON document tagged
 with the digest of the library sources it was measured on.
 """
@@ -37,11 +37,12 @@ import json
 import sys
 
 
-def first_counter(path: str, kernel: str) -> float:
-    for r in csv.DictReader(open(path)):
-        if kernel in r["Kernel_Name"]:
-            return float(r["Counter_Value"])
-    raise SystemExit(f"no dispatch of {kernel!r} in {path}")
+def first_counter(path: str, kernel: str, which: str = "first") -> float:
+    """The counter of the first (or last) dispatch whose kernel name contains `kernel`."""
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if kernel in r["Kernel_Name"]]
+    if not vals:
+        raise SystemExit(f"no dispatch of {kernel!r} in {path}")
+    return vals[-1] if which == "last" else vals[0]
 
 
 def max_counter(path: str) -> float:
@@ -52,8 +53,9 @@ def traffic_case(argv):
     from .build import sources_digest
     out, kernel, fcsv, wcsv, cfcsv, cwcsv, cbytes = argv[:7]
     workload = argv[7] if len(argv) > 7 else ""
+    which = argv[8] if len(argv) > 8 else "first"
     cbytes = int(cbytes)
-    f_kib, w_kib = first_counter(fcsv, kernel), first_counter(wcsv, kernel)
+    f_kib, w_kib = first_counter(fcsv, kernel, which), first_counter(wcsv, kernel, which)
     cf_kib, cw_kib = max_counter(cfcsv), max_counter(cwcsv)
     fs, ws = cbytes / (cf_kib * 1024.0), cbytes / (cw_kib * 1024.0)
     doc = {"kernel": kernel, "workload": workload,
