@@ -574,13 +574,15 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         if (upd) pv = o;
       }
       if (upd) {
-        ms.set_p(e, (msg_t)pv);
+        // a value that did not change is not written again: the frame state of the large codes
+        // lives in global memory, where every scattered write costs the memory system a request
+        if (pv != po) ms.set_p(e, (msg_t)pv);
         if (with_ci) {
           const val_t dlt = pv - po;
           if (!twice) {  // the only change of Lt_j in this update: new Lt_j and D_j right here
             const val_t ltn = (val_t)in_cur.ltj + dlt;
             const uint32_t nd = ar.ci(lv, ltn);
-            ms.set_lt_d(j, (llr_t)ltn, nd);
+            if (ltn != (val_t)in_cur.ltj) ms.set_lt_d(j, (llr_t)ltn, nd);  // else Lt_j and D_j stand
             if (lmd) lmd_offer(mkkey(nd, (uint32_t)j), j);
             else leaf_moved(dblk, dmask, j >> 6, (uint32_t)j, mkkey(nd, (uint32_t)j));
           } else if (grp < kGroups) {  // summed in LDS; Lt_j itself is untouched until the passes end
