@@ -544,6 +544,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     // ---- touched checks: V2C inputs, whole-row update, residual keys, and the CI of every VN
     //      listed once in the table (Algorithm 1, the loop over M(n*) \ m*; one pass per 64 lanes) ----
     bool late_ci = false;  // a VN of the overflow group was updated: its CI is refreshed after the passes
+    uint32_t late_passes = 0u;  // passes that staged such VNs (only those write and read the staging)
     for (int ps = 0; ps < npass; ++ps) {
       PassIn in_next{make_int2(-1, 0), (msg_t)0, (msg_t)0, (llr_t)0, (llr_t)0};
       int2 ent_after = make_int2(-1, 0);
@@ -597,8 +598,11 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
         }
       }
       const bool late = with_ci && upd && twice && grp == kGroups;
-      tj[ps * WAVE + lane] = late ? j : -1;
-      late_ci = late_ci || __ballot(late) != 0ull;
+      if (__ballot(late) != 0ull) {  // rare: staging lives in the global slot for the large codes
+        tj[ps * WAVE + lane] = late ? j : -1;
+        late_passes |= 1u << ps;
+        late_ci = true;
+      }
       if (lmd) {
         if (upd && !lmd_ci) lmd_offer(mkkey(ar.res(pv, cv), (uint32_t)e), j);
       } else {
@@ -633,6 +637,7 @@ __device__ __forceinline__ void dyn_decode_frame(const DevCode& H, const Topo& G
     // ---- CI of the VNs of the overflow group (their Lt took several atomic additions) ----
     if (late_ci) {
       for (int ps = 0; ps < npass; ++ps) {
+        if (!((late_passes >> ps) & 1u)) continue;  // nothing staged in this pass
         const int j = tj[ps * WAVE + lane];
         uint32_t nd = 0;
         if (j >= 0) {
