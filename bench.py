@@ -579,6 +579,7 @@ def bench_batched(args, ldpc, S, dev):
                                          stream=stream)
         # the default launch policy, for comparison
         ldpc.set_batch_tuning(clear=True)
+        plan_default = ldpc.describe_batch_plan(hs, F, arith, q, f)
         for _ in range(args.warmup):
             go()
         _, default_ms, _ = ev_time(stream, go)
@@ -624,7 +625,8 @@ def bench_batched(args, ldpc, S, dev):
         # measured HBM bytes of this launch (FETCH_SIZE + WRITE_SIZE of the 262144-frame launch in the
         # default plan, scaled by a copy), while the kernel sources are those it was measured on and
         # the timed launch runs that plan
-        default_plan = not any(int(v) for v in knobs.values())
+        plan_timed = ldpc.describe_batch_plan(hs, F, arith, q, f)
+        default_plan = all(plan_timed[k] == plan_default[k] for k in ("storage", "topology", "block", "grid"))
         tb = (measured_traffic_bytes(TRAFFIC_FILE_C2[name]) if F == 262144 and args.seed == 2102 and default_plan
               else None)
         if tb is not None:
