@@ -726,8 +726,11 @@ def bench_multi_edge(args, ldpc, S, dev):
                      "edge_updates_per_s": round(upd / (ms / 1e3), 1), "kernel_ms": round(ms, 3),
                      "bytes_per_update": round(per_upd, 1)})
 
+    cpu_llr = None
     for eb in (1.0, 1.25, 1.5):
         cw, llr = make_batches(code, 1, B, eb, args.seed + int(eb * 100), dev)[0]
+        if eb == 1.5:
+            cpu_llr = llr[:256].cpu().numpy().astype(np.float64)  # the CPU baseline's sample
         for sched, kind in (("me_cirbp", ldpc.ME_CIRBP), ("me_lmd_cirbp", ldpc.ME_LMD_CIRBP)):
             for n_p in (8, 16, 32, 64):
                 point(eb, cw, llr, sched, kind, n_p, 16)
@@ -758,6 +761,19 @@ def bench_multi_edge(args, ldpc, S, dev):
            "me_lmd_cirbp_frames_per_s": round(lmd_frames / (lmd_ms / 1e3), 3),
            "roofline": roof("me_cirbp", ldpc.ME_CIRBP), "me_lmd_cirbp_roofline": roof("me_lmd_cirbp", ldpc.ME_LMD_CIRBP),
            "points": rows}
+    if not args.no_cpu and cpu_llr is not None:
+        from oracle import oracle as O
+
+        def jobs():  # the oracle's ME-CIRBP (N_P = 8, N_G = 16, keyed fill), one frame per call
+            for x in range(len(cpu_llr)):
+                def one(x=x):
+                    r = O.decode(code, cpu_llr[x][None], O.MECIRBP, O.SPA, max_updates=3 * code.E, gamma=0.1,
+                                 n_p=8, n_g=16, fill=O.FILL_HASH, seed=args.seed)
+                    return 1, int(r.updates_used.sum())
+                yield one
+        out["cpu_baseline"] = cpu_baseline_entry(
+            jobs, args.cpu_seconds, "frames of the 1.5 dB batch in order, ME-CIRBP N_P = 8, N_G = 16, keyed fill, "
+                                    "FP64 (the value compares with the N_P = 8 point at 1.5 dB)")
     print(json.dumps(out), flush=True)
 
 
