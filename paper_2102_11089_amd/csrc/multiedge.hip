@@ -206,15 +206,29 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
       // keyed fill: the per-step part of the key is uniform, a VN's key is one more splitmix64
       const bool keyed = P.fill != 0 && need > 0;
       const uint64_t s2 = splitmix64(splitmix64(P.seed ^ (uint64_t)f) ^ (uint64_t)steps);
-      int* h256 = cidx;  // key-byte histogram of the fill group (before any candidate is stored)
+      int* h256 = cidx;  // key-byte histogram of the fill group (radix selection only)
+      // keyed fill, first try: the keys are uniform, so a threshold below which about
+      // min(3 need, 56) of the fill group's members fall (its size is the histogram's count)
+      // gives, whenever between `need` and 64 keys lie below it, a candidate list that holds the
+      // `need` smallest keys and is ranked inside one wavefront
+      uint64_t thr = 0ull;
       if (keyed) {
-        for (int x = tid; x < 256; x += BS) h256[x] = 0;
-        __syncthreads();
+        const int mf = hist[fill], want = min(3 * need, 56);
+        thr = want >= mf ? ~0ull : (uint64_t)((double)want / (double)mf * 18446744073709551616.0);
       }
+      auto offer = [&](int n, uint64_t k) {  // a fill member whose key is below the threshold
+        if (thr == ~0ull || k < thr) {
+          const int c = atomicAdd(&misc[MS_NCAND], 1);
+          if (c < P.cand_cap) {
+            ckeys[c] = k;
+            cidx[c] = n;
+          }
+        }
+      };
       // ---- the selected set: groups taken whole; the fill group counted, and for the keyed
-      //      fill its keys' top bytes histogrammed in the same pass.  A thread's VNs are n0..n1;
-      //      up to kKeep of them keep their fill membership and key in registers for the passes
-      //      below (larger codes recompute them) ----
+      //      fill its members below the threshold listed in the same pass.  A thread's VNs are
+      //      n0..n1; up to kKeep of them keep their fill membership and key in registers for the
+      //      passes below (larger codes recompute them) ----
       constexpr int kKeep = 12;
       const int chunk = (N + BS - 1) / BS;
       const int n0 = tid * chunk, n1 = min(N, n0 + chunk);
@@ -235,7 +249,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
               kmask |= 1u << i;
               if (keyed) {
                 kk[i] = splitmix64(s2 ^ (uint64_t)n);
-                atomicAdd(&h256[kk[i] >> 56], 1);
+                offer(n, kk[i]);
               }
             }
           }
@@ -247,7 +261,7 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
           if (b >= bstar) sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
           if (b == fill) {
             nfill += 1;
-            if (keyed) atomicAdd(&h256[splitmix64(s2 ^ (uint64_t)n) >> 56], 1);
+            if (keyed) offer(n, splitmix64(s2 ^ (uint64_t)n));
           }
         }
       }
@@ -274,78 +288,109 @@ __global__ __launch_bounds__(1024) void k_me(DevCode H, MeParams P) {
             }
           }
         } else {
-          // the `need` smallest keys (ties: lower index) by radix selection: find the key bucket
-          // (a run of leading bytes) that holds the need-th smallest, narrowing it a byte at a
-          // time until it has at most cand_cap members; keys below it are taken, keys inside it
-          // ranked
-          uint64_t lo = 0;
-          int shift = 56, below = 0;
-          while (true) {
-            __syncthreads();  // histogram complete
-            if (tid < WAVE) {
-              const int c0 = h256[4 * tid], c1 = h256[4 * tid + 1], c2 = h256[4 * tid + 2], c3 = h256[4 * tid + 3];
-              const int ex = below + wave_excl_scan(c0 + c1 + c2 + c3, tid);
-              const int cs[4] = {c0, c1, c2, c3};
-              int before = ex;
-              for (int u = 0; u < 4; ++u) {
-                if (cs[u] > 0 && before < need && need <= before + cs[u]) {
-                  misc[MS_RBIN] = 4 * tid + u;
-                  misc[MS_RBELOW] = before;
-                  misc[MS_CNT] = cs[u];
+          // the `need` smallest keys (ties: lower index) among the nc listed candidates: `take` of
+          // them by rank
+          auto take_smallest = [&](int nc, int take) {
+            if (nc <= WAVE) {  // one wavefront: candidate per lane, ranks from register reads
+              if (tid < WAVE) {
+                const uint64_t ki = tid < nc ? ckeys[tid] : ~0ull;
+                const int ni = tid < nc ? cidx[tid] : 0x7FFFFFFF;
+                const uint32_t khi = (uint32_t)(ki >> 32), klo = (uint32_t)ki;
+                int r = 0;
+                for (int j = 0; j < nc; ++j) {
+                  const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)khi, j) << 32) |
+                                      (uint32_t)__builtin_amdgcn_readlane((int)klo, j);
+                  const int nj = __builtin_amdgcn_readlane(ni, j);
+                  r += (kj < ki || (kj == ki && nj < ni)) ? 1 : 0;
                 }
-                before += cs[u];
+                if (tid < nc && r < take) sel[atomicAdd(&misc[MS_NSEL], 1)] = ni;
+              }
+            } else {  // chunks of 64: a wavefront ranks its chunk against each chunk in turn, one LDS
+                      // load per lane per chunk and then register reads
+              const int nchunk = (nc + WAVE - 1) / WAVE, lw = tid & (WAVE - 1);
+              for (int c0 = tid >> 6; c0 < nchunk; c0 += BS >> 6) {
+                const int i = c0 * WAVE + lw;
+                const uint64_t ki = i < nc ? ckeys[i] : ~0ull;
+                const int ni = i < nc ? cidx[i] : 0x7FFFFFFF;
+                int r = 0;
+                for (int c1 = 0; c1 < nchunk; ++c1) {
+                  const int x = c1 * WAVE + lw;
+                  const uint64_t kx = x < nc ? ckeys[x] : ~0ull;
+                  const int nx = x < nc ? cidx[x] : 0x7FFFFFFF;
+                  const uint32_t xhi = (uint32_t)(kx >> 32), xlo = (uint32_t)kx;
+                  const int cnt = min(WAVE, nc - c1 * WAVE);
+                  for (int j = 0; j < cnt; ++j) {
+                    const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)xhi, j) << 32) |
+                                        (uint32_t)__builtin_amdgcn_readlane((int)xlo, j);
+                    const int nj = __builtin_amdgcn_readlane(nx, j);
+                    r += (kj < ki || (kj == ki && nj < ni)) ? 1 : 0;
+                  }
+                }
+                if (i < nc && r < take) sel[atomicAdd(&misc[MS_NSEL], 1)] = ni;
               }
             }
-            __syncthreads();
-            lo |= (uint64_t)misc[MS_RBIN] << shift;
-            below = misc[MS_RBELOW];
-            const int cnt = misc[MS_CNT];
-            if (cnt <= P.cand_cap || shift == 0) break;
-            shift -= 8;
+          };
+          __syncthreads();  // the threshold's candidates are listed
+          const int ncand = misc[MS_NCAND];
+          if (ncand >= need && ncand <= WAVE) {
+            take_smallest(ncand, need);
+          } else {
+            // fewer keys below the threshold than needed (sets that need many fill members), or
+            // more than one wavefront ranks.
+            // Radix selection over every member: find the key bucket (a run of leading bytes)
+            // that holds the need-th smallest, narrowing it a byte at a time until it has at most
+            // cand_cap members; keys below it are taken, keys inside it ranked
+            __syncthreads();  // every thread has read the count
+            if (tid == 0) misc[MS_NCAND] = 0;
             for (int x = tid; x < 256; x += BS) h256[x] = 0;
             __syncthreads();
-            const uint64_t upper = ~0ull << (shift + 8);  // the bytes fixed so far
-            for_members([&](int, uint64_t k) {
-              if ((k & upper) == lo) atomicAdd(&h256[(k >> shift) & 255], 1);
+            for_members([&](int, uint64_t k) { atomicAdd(&h256[k >> 56], 1); });
+            uint64_t lo = 0;
+            int shift = 56, below = 0;
+            while (true) {
+              __syncthreads();  // histogram complete
+              if (tid < WAVE) {
+                const int c0 = h256[4 * tid], c1 = h256[4 * tid + 1], c2 = h256[4 * tid + 2], c3 = h256[4 * tid + 3];
+                const int ex = below + wave_excl_scan(c0 + c1 + c2 + c3, tid);
+                const int cs[4] = {c0, c1, c2, c3};
+                int before = ex;
+                for (int u = 0; u < 4; ++u) {
+                  if (cs[u] > 0 && before < need && need <= before + cs[u]) {
+                    misc[MS_RBIN] = 4 * tid + u;
+                    misc[MS_RBELOW] = before;
+                    misc[MS_CNT] = cs[u];
+                  }
+                  before += cs[u];
+                }
+              }
+              __syncthreads();
+              lo |= (uint64_t)misc[MS_RBIN] << shift;
+              below = misc[MS_RBELOW];
+              const int cnt = misc[MS_CNT];
+              if (cnt <= P.cand_cap || shift == 0) break;
+              shift -= 8;
+              for (int x = tid; x < 256; x += BS) h256[x] = 0;
+              __syncthreads();
+              const uint64_t upper = ~0ull << (shift + 8);  // the bytes fixed so far
+              for_members([&](int, uint64_t k) {
+                if ((k & upper) == lo) atomicAdd(&h256[(k >> shift) & 255], 1);
+              });
+            }
+            __syncthreads();  // the histogram's last reader is done before candidates overwrite it
+            const uint64_t hi = lo + ((shift == 0) ? 0ull : ((1ull << shift) - 1ull));
+            for_members([&](int n, uint64_t k) {
+              if (k < lo) {
+                sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
+              } else if (k <= hi) {
+                const int i = atomicAdd(&misc[MS_NCAND], 1);
+                if (i < P.cand_cap) {
+                  ckeys[i] = k;
+                  cidx[i] = n;
+                }
+              }
             });
-          }
-          __syncthreads();  // the histogram's last reader is done before candidates overwrite it
-          const uint64_t hi = lo + ((shift == 0) ? 0ull : ((1ull << shift) - 1ull));
-          for_members([&](int n, uint64_t k) {
-            if (k < lo) {
-              sel[atomicAdd(&misc[MS_NSEL], 1)] = n;
-            } else if (k <= hi) {
-              const int i = atomicAdd(&misc[MS_NCAND], 1);
-              if (i < P.cand_cap) {
-                ckeys[i] = k;
-                cidx[i] = n;
-              }
-            }
-          });
-          __syncthreads();
-          const int nc = min(misc[MS_NCAND], P.cand_cap), take = need - below;
-          if (nc <= WAVE) {  // one wavefront: candidate per lane, ranks from register reads
-            if (tid < WAVE) {
-              const uint64_t ki = tid < nc ? ckeys[tid] : ~0ull;
-              const int ni = tid < nc ? cidx[tid] : 0x7FFFFFFF;
-              const uint32_t khi = (uint32_t)(ki >> 32), klo = (uint32_t)ki;
-              int r = 0;
-              for (int j = 0; j < nc; ++j) {
-                const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)khi, j) << 32) |
-                                    (uint32_t)__builtin_amdgcn_readlane((int)klo, j);
-                const int nj = __builtin_amdgcn_readlane(ni, j);
-                r += (kj < ki || (kj == ki && nj < ni)) ? 1 : 0;
-              }
-              if (tid < nc && r < take) sel[atomicAdd(&misc[MS_NSEL], 1)] = ni;
-            }
-          } else {
-            for (int i = tid; i < nc; i += BS) {
-              const uint64_t ki = ckeys[i];
-              const int ni = cidx[i];
-              int r = 0;
-              for (int j = 0; j < nc; ++j) r += (ckeys[j] < ki || (ckeys[j] == ki && cidx[j] < ni)) ? 1 : 0;
-              if (r < take) sel[atomicAdd(&misc[MS_NSEL], 1)] = ni;
-            }
+            __syncthreads();
+            take_smallest(min(misc[MS_NCAND], P.cand_cap), need - below);
           }
         }
       }
