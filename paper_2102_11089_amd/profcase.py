@@ -206,7 +206,7 @@ def phase_case(lib: str, which: str):
     B = 8192
     _, llr = S.frames(code, 256, 1.5, 7)
     x = torch.from_numpy(llr).cuda().repeat(B // 256, 1)  # 8192 frames, 256 distinct
-    names = {7: "loop top", 0: "P' and group pass", 1: "fill (radix selection)", 2: "edge choice, propagation",
+    names = {7: "loop top", 0: "P' and group pass", 1: "fill (list or radix)", 2: "edge choice, propagation",
              3: "sort of touched checks", 4: "touched checks' rows", 5: "CI pass", 6: "Algorithm 6 proposals"}
     for kind, kn in ((ldpc.ME_CIRBP, "ME-CIRBP"), (ldpc.ME_LMD_CIRBP, "ME-LMD-CIRBP")):
         for n_p in (8, 64):
