@@ -579,8 +579,13 @@ def test_fixed_me_bit_exact_c0(gpu, c0, n_p, n_g, fill):
 
 
 def test_fixed_me_qc_and_bg1_z128(gpu):
+    """Keyed fill against the oracle, traced.  On the Z = 128 code a fill group holds hundreds of
+    VNs: at N_P = 8 the fill comes from the short list of keys below the step's threshold, at
+    N_P = 64 often from the radix selection (fills the list cannot hold)."""
+    c3 = S.workload_code("c3")
     for code, B, eb, n_p, mu in ((S.qc_24col(24, 8, seed=2), 64, 2.5, 16, 3000),
-                                 (S.workload_code("c3"), 2, 1.25, 32, 4000)):
+                                 (c3, 2, 1.25, 8, 3000), (c3, 2, 1.25, 32, 4000),
+                                 (c3, 2, 1.25, 64, 6000)):
         h = gpu.Code(code)
         cw, llr = S.frames(code, B, eb, 111)
         say(f"[fixed me hash] {code.name} n_p={n_p}")
